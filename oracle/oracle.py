@@ -1,0 +1,317 @@
+"""ctypes front-end of the serial FP64 CPU oracle (``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product library.  It shares
+no code with the HIP path; it only reads the seeded inputs of
+``paper_2603_21869_amd.cases``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "nfvm_oracle.c")
+
+_dp = C.POINTER(C.c_double)
+
+
+class _Patch(C.Structure):
+    _fields_ = [("face", C.c_int), ("lo", C.c_int * 2), ("hi", C.c_int * 2), ("kind", C.c_int),
+                ("U", C.c_double * 3), ("T", C.c_double), ("k", C.c_double),
+                ("omega", C.c_double), ("T_wall", C.c_double)]
+
+
+class _Case(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("h", C.c_double * 3), ("nu", C.c_double),
+                ("alpha_T", C.c_double), ("Pr_t", C.c_double), ("sigma_k", C.c_double),
+                ("sigma_w", C.c_double), ("dt", C.c_double), ("physics", C.c_int),
+                ("gravity", C.c_double * 3), ("T_ref", C.c_double), ("beta_T", C.c_double),
+                ("T_solid", C.c_double), ("n_patches", C.c_int), ("patches", C.POINTER(_Patch)),
+                ("solid", C.POINTER(C.c_ubyte)), ("n_levels", C.c_int), ("nu1", C.c_int),
+                ("nu2", C.c_int), ("omega_jacobi", C.c_double), ("tol", C.c_double),
+                ("max_cycles", C.c_int)]
+
+
+class _Fields(C.Structure):
+    _fields_ = [(n, _dp) for n in ("u", "v", "w", "p", "T", "k", "omega")]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("cycles", C.c_int), ("status", C.c_int), ("rel_residual", C.c_double),
+                ("max_face_div", C.c_double), ("min_k", C.c_double), ("min_omega", C.c_double)]
+
+
+FIELDS = ("u", "v", "w", "p", "T", "k", "omega")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.orc_mg_create.restype = C.c_void_p
+        L.orc_mg_create.argtypes = [C.POINTER(_Case)]
+        for name in ("orc_mg_free",):
+            getattr(L, name).argtypes = [C.c_void_p]
+        L.orc_mg_levels.argtypes = [C.c_void_p]
+        L.orc_mg_apply.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_mg_smooth.argtypes = [C.c_void_p, C.c_int, _dp, _dp, C.c_int]
+        L.orc_mg_restrict.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_mg_prolong_add.argtypes = [C.c_void_p, C.c_int, _dp, _dp]
+        L.orc_mg_vcycle.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_mg_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, C.c_int,
+                                   C.POINTER(C.c_int), _dp]
+        L.orc_mg_level_shape.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), _dp]
+        L.orc_mg_level_active.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_ubyte)]
+        L.orc_closure_point.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+class OracleCase:
+    """Marshals a ``cases.Case`` into the oracle's C struct (keeps arrays alive)."""
+
+    def __init__(self, case):
+        self.case = case
+        pats = (_Patch * max(1, len(case.patches)))()
+        for q, p in enumerate(case.patches):
+            pats[q].face = p.face
+            pats[q].lo[:] = list(p.lo)
+            pats[q].hi[:] = list(p.hi)
+            pats[q].kind = p.kind
+            pats[q].U[:] = list(p.U)
+            pats[q].T = p.T
+            pats[q].k = p.k
+            pats[q].omega = p.omega
+            pats[q].T_wall = p.T_wall
+        self._pats = pats
+        c = _Case()
+        c.dim = case.dim
+        c.n[:] = list(case.n)
+        c.h[:] = list(case.h)
+        c.nu = case.nu
+        c.alpha_T = case.alpha_T
+        c.Pr_t = case.Pr_t
+        c.sigma_k = case.sigma_k
+        c.sigma_w = case.sigma_w
+        c.dt = case.dt
+        c.physics = case.physics
+        c.gravity[:] = list(case.gravity)
+        c.T_ref = case.T_ref
+        c.beta_T = case.beta_T
+        c.T_solid = case.T_solid
+        c.n_patches = len(case.patches)
+        c.patches = C.cast(pats, C.POINTER(_Patch))
+        if case.solid is not None:
+            self._solid = np.ascontiguousarray(case.solid, dtype=np.uint8)
+            c.solid = self._solid.ctypes.data_as(C.POINTER(C.c_ubyte))
+        else:
+            self._solid = None
+            c.solid = C.POINTER(C.c_ubyte)()
+        c.n_levels = case.n_levels
+        c.nu1 = case.nu1
+        c.nu2 = case.nu2
+        c.omega_jacobi = case.omega_jacobi
+        c.tol = case.tol
+        c.max_cycles = case.max_cycles
+        self.c = c
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+    @property
+    def shape(self):
+        n = self.case.n
+        return (n[2], n[1], n[0])
+
+
+def _fields_struct(f: Dict[str, np.ndarray]):
+    s = _Fields()
+    for n in FIELDS:
+        setattr(s, n, _ptr(f[n]))
+    return s
+
+
+def _fresh(case) -> Dict[str, np.ndarray]:
+    return {n: np.ascontiguousarray(case.fields[n], dtype=np.float64).copy() for n in FIELDS}
+
+
+def step(case, n_steps: Optional[int] = None, forced_cycles: Optional[Sequence[int]] = None,
+         fields: Optional[Dict[str, np.ndarray]] = None):
+    """Run n_steps time steps from the case's initial fields (or ``fields``).
+
+    Returns (fields, stats list, status)."""
+    L = lib()
+    oc = OracleCase(case)
+    n_steps = case.n_steps if n_steps is None else n_steps
+    f = _fresh(case) if fields is None else {k: np.ascontiguousarray(v, dtype=np.float64).copy() for k, v in fields.items()}
+    fs = _fields_struct(f)
+    st = (_Stats * max(1, n_steps))()
+    if forced_cycles is not None:
+        fc = (C.c_int * n_steps)(*[int(x) for x in forced_cycles])
+        fcp = C.cast(fc, C.POINTER(C.c_int))
+    else:
+        fcp = C.POINTER(C.c_int)()
+    status = L.orc_step(oc.ref, C.byref(fs), n_steps, fcp, st)
+    stats = [dict(cycles=st[i].cycles, status=st[i].status, rel_residual=st[i].rel_residual,
+                  max_face_div=st[i].max_face_div, min_k=st[i].min_k, min_omega=st[i].min_omega)
+             for i in range(n_steps)]
+    return f, stats, status
+
+
+def closure_point(nu: float, k: float, omega: float):
+    out = (C.c_double * 4)()
+    lib().orc_closure_point(nu, k, omega, out)
+    return dict(alpha_star=out[0], nu_t=out[1], alpha=out[2], beta_star=out[3])
+
+
+def fixed_omega(case, omega: np.ndarray) -> np.ndarray:
+    oc = OracleCase(case)
+    o = np.ascontiguousarray(omega, dtype=np.float64).copy()
+    lib().orc_fixed_omega(oc.ref, _ptr(o))
+    return o
+
+
+def nut(case, k, omega):
+    oc = OracleCase(case)
+    out = np.zeros(oc.shape)
+    lib().orc_nut(oc.ref, _ptr(np.ascontiguousarray(k, dtype=np.float64)),
+                  _ptr(np.ascontiguousarray(omega, dtype=np.float64)), _ptr(out))
+    return out
+
+
+def explicit_rhs(case, fields: Dict[str, np.ndarray]):
+    oc = OracleCase(case)
+    fin = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
+    out = {k: np.zeros(oc.shape) for k in FIELDS}
+    lib().orc_explicit_rhs(oc.ref, C.byref(_fields_struct(fin)), C.byref(_fields_struct(out)))
+    return out
+
+
+def explicit(case, fields: Dict[str, np.ndarray]):
+    oc = OracleCase(case)
+    fin = {k: np.ascontiguousarray(v, dtype=np.float64) for k, v in fields.items()}
+    out = {k: np.zeros(oc.shape) for k in FIELDS}
+    lib().orc_explicit(oc.ref, C.byref(_fields_struct(fin)), C.byref(_fields_struct(out)))
+    return out
+
+
+def destroy(case, u, v, w, k, omega, tau):
+    oc = OracleCase(case)
+    ko = np.zeros(oc.shape)
+    oo = np.zeros(oc.shape)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (u, v, w, k, omega)]
+    lib().orc_destroy(oc.ref, *[_ptr(x) for x in a], C.c_double(tau), _ptr(ko), _ptr(oo))
+    return ko, oo
+
+
+def rhs_b(case, us, vs, ws):
+    oc = OracleCase(case)
+    b = np.zeros(oc.shape)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (us, vs, ws)]
+    lib().orc_rhs_b(oc.ref, *[_ptr(x) for x in a], _ptr(b))
+    return b
+
+
+def project(case, phi, us, vs, ws, p):
+    oc = OracleCase(case)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (phi, us, vs, ws)]
+    pp = np.ascontiguousarray(p, dtype=np.float64).copy()
+    u = np.zeros(oc.shape)
+    v = np.zeros(oc.shape)
+    w = np.zeros(oc.shape)
+    md = C.c_double(0.0)
+    lib().orc_project(oc.ref, *[_ptr(x) for x in a], _ptr(pp), _ptr(u), _ptr(v), _ptr(w),
+                      C.byref(md))
+    return pp, u, v, w, md.value
+
+
+class MG:
+    """The oracle's multigrid hierarchy for the pressure operator of a case."""
+
+    def __init__(self, case):
+        self.oc = OracleCase(case)
+        self.h = lib().orc_mg_create(self.oc.ref)
+        if not self.h:
+            raise ValueError("oracle multigrid: invalid level count for this grid")
+        self.L = lib().orc_mg_levels(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_mg_free(self.h)
+            self.h = None
+
+    def shape(self, l: int):
+        n = (C.c_int * 3)()
+        h = (C.c_double * 3)()
+        lib().orc_mg_level_shape(self.h, l, n, h)
+        return (n[2], n[1], n[0]), (h[0], h[1], h[2])
+
+    def active(self, l: int) -> np.ndarray:
+        sh, _ = self.shape(l)
+        a = np.zeros(sh, dtype=np.uint8)
+        lib().orc_mg_level_active(self.h, l, a.ctypes.data_as(C.POINTER(C.c_ubyte)))
+        return a
+
+    def apply(self, l: int, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.zeros_like(x)
+        lib().orc_mg_apply(self.h, l, _ptr(x), _ptr(y))
+        return y
+
+    def smooth(self, l: int, x: np.ndarray, b: np.ndarray, sweeps: int) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64).copy()
+        lib().orc_mg_smooth(self.h, l, _ptr(x), _ptr(np.ascontiguousarray(b, dtype=np.float64)), sweeps)
+        return x
+
+    def restrict(self, l: int, r: np.ndarray) -> np.ndarray:
+        sh, _ = self.shape(l + 1)
+        bc = np.zeros(sh)
+        lib().orc_mg_restrict(self.h, l, _ptr(np.ascontiguousarray(r, dtype=np.float64)), _ptr(bc))
+        return bc
+
+    def prolong_add(self, l: int, e: np.ndarray, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64).copy()
+        lib().orc_mg_prolong_add(self.h, l, _ptr(np.ascontiguousarray(e, dtype=np.float64)), _ptr(x))
+        return x
+
+    def vcycle(self, x: np.ndarray, b: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64).copy()
+        lib().orc_mg_vcycle(self.h, _ptr(x), _ptr(np.ascontiguousarray(b, dtype=np.float64)))
+        return x
+
+    def solve(self, b: np.ndarray, x: Optional[np.ndarray] = None, tol: float = 1e-10,
+              max_cycles: int = 100, forced: int = -1):
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros_like(b) if x is None else np.ascontiguousarray(x, dtype=np.float64).copy()
+        cyc = C.c_int(0)
+        rel = C.c_double(0.0)
+        st = lib().orc_mg_solve(self.h, _ptr(b), _ptr(x), tol, max_cycles, forced, C.byref(cyc),
+                                C.byref(rel))
+        return x, cyc.value, rel.value, st

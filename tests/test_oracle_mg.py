@@ -1,0 +1,166 @@
+"""Pins of the oracle's pressure solve (Sec. 2.4, eqs. pc_residual to
+jacobi_pc, Algorithm 1): eigenmodes, manufactured solutions, brute-force
+dense solves, transfer operators and the projection identity."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_21869_amd import cases as C
+from tests.boxcase import box, centres
+
+
+def test_jacobi_sweep_on_dirichlet_eigenmode(oracle):
+    """On a box with zero pressure on every face, v = prod sin(pi m_d (i+1/2)/n_d)
+    is an eigenvector of A with lambda = sum 4/h^2 sin^2(pi m/(2n)); one damped
+    Jacobi sweep with b = 0 gives v (1 - w lambda / D_P) per cell, with the
+    diagonal D_P = sum_d (2 + [first cell] + [last cell]) / h_d^2 (a zero-value
+    face counts twice: its ghost is -x_P)."""
+    n = (8, 6, 5)
+    h = (0.1, 0.13, 0.07)
+    c = box(n, h, kinds=[C.OUTLET] * 6)
+    mg = oracle.MG(c)
+    w = 6.0 / 7.0
+    idx = np.meshgrid(np.arange(5), np.arange(6), np.arange(8), indexing="ij")
+    for m in ((1, 1, 1), (3, 2, 4), (8, 6, 5)):
+        v = np.ones((5, 6, 8))
+        lam = 0.0
+        D = np.zeros((5, 6, 8))
+        for d, (ax, nd) in enumerate(((2, 8), (1, 6), (0, 5))):
+            i = idx[ax]
+            v = v * np.sin(math.pi * m[d] * (i + 0.5) / nd)
+            lam += 4 / h[d] ** 2 * math.sin(math.pi * m[d] / (2 * nd)) ** 2
+            D += (2 + (i == 0) + (i == nd - 1)) / h[d] ** 2
+        assert np.allclose(mg.apply(0, v), lam * v, rtol=0, atol=1e-10 * lam)
+        out = mg.smooth(0, v, np.zeros_like(v), 1)
+        assert np.allclose(out, v * (1 - w * lam / D), rtol=0, atol=1e-12)
+
+
+def _solve_rate(oracle, c, b, cycles=8):
+    mg = oracle.MG(c)
+    x = np.zeros_like(b)
+    r0 = np.linalg.norm(b)
+    facs = []
+    for _ in range(cycles):
+        x = x + mg.vcycle(np.zeros_like(b), b - mg.apply(0, x))
+        r = np.linalg.norm(b - mg.apply(0, x))
+        facs.append(r / r0)
+        r0 = r
+    return max(facs[-3:])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_vcycle_factor_is_textbook_and_mesh_independent(oracle, dim):
+    """Plain V(2,2) cycling on a channel-type box (zero-gradient inlet and walls,
+    zero-value outlet): the convergence factor stays near the local-mode
+    analysis values (mu^4 ~ 0.13 in 2D, 0.26 in 3D) as h halves."""
+    rates = []
+    sizes = [(32, 32), (64, 64), (128, 128)] if dim == 2 else [(16, 16, 16), (32, 32, 32)]
+    for n in sizes:
+        nn = tuple(n) + ((1,) if dim == 2 else ())
+        c = box(nn, tuple(1.0 / s for s in nn), dim=dim,
+                kinds=[C.INLET, C.OUTLET, C.WALL, C.WALL, C.WALL, C.WALL])
+        c.n_levels = C.max_levels(c.n, dim) - 2
+        b = np.random.default_rng(0).standard_normal((c.n[2], c.n[1], c.n[0]))
+        rates.append(_solve_rate(oracle, c, b))
+    bound = 0.2 if dim == 2 else 0.27
+    assert max(rates) < bound
+    assert max(rates) - min(rates) < 0.03
+
+
+def test_manufactured_poisson_second_order(oracle):
+    """phi = cos(pi x/(2Lx)) cos(2 pi y/Ly) cos(2 pi z/Lz) satisfies zero gradient
+    at x = 0 and the side walls and phi = 0 at x = Lx; with b = -lap(phi) at
+    cell centres the discrete solution converges to phi at O(h^2)."""
+    errs = []
+    for N in (8, 16, 32):
+        n = (N, N, N)
+        L = (2.0, 1.0, 1.0)
+        c = box(n, tuple(L[d] / N for d in range(3)),
+                kinds=[C.INLET, C.OUTLET, C.WALL, C.WALL, C.WALL, C.WALL],
+                n_levels=C.max_levels(n, 3) - 2)
+        x, y, z = centres(c)
+        kx, ky, kz = math.pi / (2 * L[0]), 2 * math.pi / L[1], 2 * math.pi / L[2]
+        phi = np.cos(kx * x) * np.cos(ky * y) * np.cos(kz * z)
+        b = (kx ** 2 + ky ** 2 + kz ** 2) * phi
+        mg = oracle.MG(c)
+        sol, cyc, rel, st = mg.solve(b, tol=1e-12)
+        assert st == 0 and rel <= 1e-12
+        errs.append(np.abs(sol - phi).max())
+    assert errs[1] / errs[2] > 3.5 and errs[0] / errs[1] > 3.0
+
+
+def test_mg_solution_equals_dense_solve_with_mask(oracle):
+    """Brute force: assemble A by applying the operator to unit vectors, solve
+    densely with numpy, compare with the multigrid solution (vented box with a
+    solid block, 4 levels)."""
+    n = (16, 8, 8)
+    solid = np.zeros((8, 8, 16), dtype=np.uint8)
+    solid[0:4, 2:5, 5:9] = 1
+    pats = [C.Patch(0, (2, 5), (5, 8), kind=C.INLET, U=(1, 0, 0)),
+            C.Patch(1, (3, 0), (6, 2), kind=C.OUTLET)]
+    c = box(n, (0.1, 0.12, 0.09), patches=pats, solid=solid, n_levels=4)
+    mg = oracle.MG(c)
+    act = mg.active(0).astype(bool)
+    ids = np.flatnonzero(act)
+    A = np.zeros((ids.size, ids.size))
+    for col, q in enumerate(ids):
+        e = np.zeros(act.size)
+        e[q] = 1.0
+        A[:, col] = mg.apply(0, e.reshape(act.shape)).ravel()[ids]
+    assert np.allclose(A, A.T, rtol=0, atol=1e-9)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(act.shape) * act
+    want = np.linalg.solve(A, b.ravel()[ids])
+    sol, cyc, rel, st = mg.solve(b, tol=1e-14, max_cycles=200)
+    assert st == 0
+    assert np.abs(sol.ravel()[ids] - want).max() <= 1e-11 * np.abs(want).max()
+    assert not sol[~act].any()
+
+
+def test_transfer_operators(oracle):
+    """RES (mean of children) and PROL (cell-centred trilinear): prolongation
+    keeps constants everywhere away from zero-value faces and linear functions
+    in the interior; restriction of a linear function is linear, and it keeps
+    the volume integral."""
+    n = (16, 12, 8)
+    h = (0.1, 0.2, 0.3)
+    c = box(n, h, kinds=[C.WALL] * 6, n_levels=2)
+    mg = oracle.MG(c)
+    (nzc, nyc, nxc), hc = mg.shape(1)
+    Z, Y, X = np.meshgrid((np.arange(nzc) + 0.5) * hc[2], (np.arange(nyc) + 0.5) * hc[1],
+                          (np.arange(nxc) + 0.5) * hc[0], indexing="ij")
+    x, y, z = centres(c)
+    e = 2.0 - 0.5 * X + 0.25 * Y + 1.5 * Z
+    out = mg.prolong_add(0, e, np.zeros((8, 12, 16)))
+    lin = 2.0 - 0.5 * x + 0.25 * y + 1.5 * z
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    assert np.allclose(out[inner], lin[inner], rtol=0, atol=1e-13)
+    const = mg.prolong_add(0, np.full(e.shape, 3.0), np.zeros((8, 12, 16)))
+    assert np.allclose(const, 3.0, rtol=0, atol=1e-14)
+    r = mg.restrict(0, lin)
+    assert np.allclose(r, e, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(4)
+    f = rng.standard_normal((8, 12, 16))
+    assert mg.restrict(0, f).sum() * 8 == pytest.approx(f.sum(), rel=1e-12)
+
+
+def test_projection_identity_and_divergence_free(oracle):
+    """Face fluxes after projection satisfy sum_d D_d F_d = -dt (b - A phi) per
+    cell for any phi; with a converged phi the face divergence is round-off
+    (Sec. 2.4, eqs. pc_residual, pc_discretized)."""
+    c = C.room3d(32, 16, 8, seed=3)
+    rng = np.random.default_rng(1)
+    fl = (c.solid == 0)
+    us, vs, ws = (rng.standard_normal(fl.shape) * fl for _ in range(3))
+    b = oracle.rhs_b(c, us, vs, ws)
+    mg = oracle.MG(c)
+    phi1, cyc, rel, st = mg.solve(b, forced=1)
+    _, _, _, _, div1 = oracle.project(c, phi1, us, vs, ws, np.zeros(fl.shape))
+    res = np.abs(b - mg.apply(0, phi1)).max() * c.dt
+    assert div1 == pytest.approx(res, rel=1e-9)
+    phi, cyc, rel, st = mg.solve(b, tol=1e-13, max_cycles=200)
+    assert st == 0
+    p, u, v, w, div = oracle.project(c, phi, us, vs, ws, np.zeros(fl.shape))
+    assert div < 1e-11 * np.abs(b).max() * c.dt
+    assert np.array_equal(p, phi)

@@ -1,0 +1,169 @@
+"""Pins of the oracle's explicit finite-volume operators (Sec. 2.1-2.3, 2.7,
+Algorithms 2 and 4) against closed forms and invariants."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2603_21869_amd import cases as C
+from tests.boxcase import box, centres
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def test_pressure_operator_impulse_is_printed_kernel(oracle):
+    """The operator A applied to a unit impulse reproduces the 3x3x3 kernel
+    printed in Sec. 2.4 (equal spacing), values in units of -1/dx^2."""
+    rows = [l.split() for l in open(f"{GOLDEN}/laplacian_kernel_3d.txt") if l.strip() and not l.startswith("#")]
+    K = np.array(rows, dtype=float).reshape(3, 3, 3)
+    h = 0.25
+    c = box((5, 5, 5), (h, h, h), kinds=[C.OUTLET] * 6)
+    mg = oracle.MG(c)
+    e = np.zeros((5, 5, 5))
+    e[2, 2, 2] = 1.0
+    y = mg.apply(0, e)
+    assert np.array_equal(y[1:4, 1:4, 1:4] * h * h, -K)
+    y[1:4, 1:4, 1:4] = 0.0
+    assert not y.any()
+
+
+def test_upwind_uniform_flow_is_textbook_first_order(oracle):
+    """Uniform u > 0 (or < 0), no diffusion: the scalar right-hand side is
+    -U (T_i - T_{i-1}) / h (or -U (T_{i+1} - T_i) / h), lower cell on the
+    upwind side (eq. upwind_x, Algorithm 2); the inlet ghost is 2 T_in - T_0."""
+    rng = np.random.default_rng(3)
+    for U in (0.7, -0.7):
+        T_in = 300.0
+        if U > 0:
+            pats = [C.Patch(0, (0, 0), (6, 1), kind=C.INLET, U=(U, 0, 0), T=T_in),
+                    C.Patch(1, (0, 0), (6, 1), kind=C.OUTLET)]
+        else:
+            pats = [C.Patch(1, (0, 0), (6, 1), kind=C.INLET, U=(U, 0, 0), T=T_in),
+                    C.Patch(0, (0, 0), (6, 1), kind=C.OUTLET)]
+        c = box((10, 6), (0.1, 0.2), dim=2, patches=pats, physics=C.PHYS_ENERGY, alpha_T=0.0)
+        f = dict(c.fields)
+        f["u"] = np.full(f["u"].shape, U)
+        f["T"] = 290 + rng.random(f["T"].shape)
+        r = oracle.explicit_rhs(c, f)["T"][0]
+        T = f["T"][0]
+        h = 0.1
+        if U > 0:
+            ghost = 2 * T_in - T[:, 0]
+            up = np.concatenate([ghost[:, None], T], axis=1)
+            want = -U * (up[:, 1:] - up[:, :-1]) / h
+        else:
+            ghost = 2 * T_in - T[:, -1]
+            up = np.concatenate([T, ghost[:, None]], axis=1)
+            want = -U * (up[:, 1:] - up[:, :-1]) / h
+        assert np.allclose(r, want, rtol=1e-13, atol=1e-12)
+
+
+def test_flux_form_conserves_scalar_in_closed_box(oracle):
+    """Divergence theorem (eq. divergence_theorem): with adiabatic no-slip walls
+    and internal adiabatic solids, sum(RHS_T * V) = 0 to round-off for any
+    (even divergent) velocity and any eddy viscosity."""
+    rng = np.random.default_rng(5)
+    n = (9, 7, 6)
+    solid = np.zeros((6, 7, 9), dtype=np.uint8)
+    solid[2:4, 3:5, 4:7] = 1
+    c = box(n, (0.1, 0.13, 0.07), solid=solid, physics=C.PHYS_ENERGY | C.PHYS_KOMEGA,
+            alpha_T=2e-3, nu=1e-3)
+    f = {k: rng.random(v.shape) for k, v in c.fields.items()}
+    for k in ("u", "v", "w"):
+        f[k] = f[k] - 0.5
+    f["k"] = 1e-3 + 1e-2 * f["k"]
+    f["omega"] = 0.5 + f["omega"]
+    for k in f:
+        f[k] = f[k] * (1 - solid)
+    r = oracle.explicit_rhs(c, f)
+    s = (r["T"] * (1 - solid)).sum()
+    scale = np.abs(r["T"]).sum()
+    assert abs(s) < 1e-13 * scale
+
+
+def test_diffusion_of_cosine_mode_decays_by_closed_form(oracle):
+    """One explicit step of pure diffusion of cos(pi m (i+1/2)/n) between
+    adiabatic walls multiplies it by 1 - 4 a dt/h^2 sin^2(pi m/(2n)) (central
+    diffusion flux, Sec. 2.3)."""
+    a, dt = 0.05, 0.01
+    for axis, (n, h) in enumerate(((16, 0.1), (12, 0.07), (10, 0.09))):
+        nn = [4, 4, 4]
+        nn[axis] = n
+        hh = [0.1, 0.1, 0.1]
+        hh[axis] = h
+        c = box(tuple(nn), tuple(hh), physics=C.PHYS_ENERGY, alpha_T=a, dt=dt)
+        x, y, z = centres(c)
+        coord = (x, y, z)[axis]
+        L = n * h
+        for m in (1, 3, 7):
+            f = dict(c.fields)
+            f["T"] = np.cos(math.pi * m * coord / L)
+            out = oracle.explicit(c, f)["T"]
+            g = 1 - 4 * a * dt / h ** 2 * math.sin(math.pi * m / (2 * n)) ** 2
+            assert np.allclose(out, g * f["T"], rtol=0, atol=1e-13)
+
+
+def test_buoyancy_and_pressure_free_rest_state(oracle):
+    """Fluid at rest with uniform T: the only momentum source is the Boussinesq
+    term -beta_T (T - T_ref) g (vertical component)."""
+    c = box((6, 6, 6), (0.1, 0.1, 0.1), physics=C.PHYS_ENERGY | C.PHYS_BUOYANCY,
+            kinds=[C.WALL] * 6)
+    f = dict(c.fields)
+    f["T"] = np.full(f["T"].shape, 303.0)
+    r = oracle.explicit_rhs(c, f)
+    want = 9.81 * (303.0 - 293.0) / 293.0
+    assert np.allclose(r["w"], want, rtol=1e-14)
+    assert not r["u"].any() and not r["v"].any()
+
+
+def test_production_terms_in_linear_shear(oracle):
+    """Uniform k, omega in the shear flow u = g y: S^2 = g^2 in interior cells,
+    so RHS_k = nu_t g^2 with nu_t = alpha* k / omega and RHS_omega = alpha
+    (omega / k) G_k (eqs. ko_turb_diff, k_gen, o_gen, a)."""
+    gam, k0, om0, nu = 0.8, 2e-3, 3.0, 1e-5
+    c = box((8, 10, 6), (0.1, 0.05, 0.1), physics=C.PHYS_KOMEGA, nu=nu)
+    x, y, z = centres(c)
+    f = dict(c.fields)
+    f["u"] = gam * y
+    f["k"] = np.full(x.shape, k0)
+    f["omega"] = np.full(x.shape, om0)
+    f["p"] = np.zeros(x.shape)
+    r = oracle.explicit_rhs(c, f)
+    Re_t = k0 / (nu * om0)
+    a_star = (0.072 / 3 + Re_t / 6) / (1 + Re_t / 6)
+    nut = a_star * k0 / om0
+    alpha = 0.52 / a_star * (1 / 9 + Re_t / 2.95) / (1 + Re_t / 2.95)
+    Gk = nut * gam ** 2
+    Gw = alpha * om0 / k0 * Gk
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    assert np.allclose(r["k"][inner], Gk, rtol=1e-12)
+    assert np.allclose(r["omega"][inner], Gw, rtol=1e-12)
+
+
+def test_closure_limits(oracle):
+    """Low-Reynolds damping limits (eqs. a_star, a, beta_star): Re_t -> inf gives
+    alpha* -> 1, alpha -> 0.52, beta* -> 0.09; Re_t -> 0 gives alpha* ->
+    beta_i/3 = 0.024, beta* -> 0.09 * 4/15 = 0.024, alpha -> 0.52/9/0.024."""
+    hi = oracle.closure_point(1e-12, 1.0, 1.0)
+    assert hi["alpha_star"] == pytest.approx(1.0, rel=1e-9)
+    assert hi["alpha"] == pytest.approx(0.52, rel=1e-9)
+    assert hi["beta_star"] == pytest.approx(0.09, rel=1e-12)
+    lo = oracle.closure_point(1.0, 1e-14, 1.0)
+    assert lo["alpha_star"] == pytest.approx(0.024, rel=1e-9)
+    assert lo["beta_star"] == pytest.approx(0.024, rel=1e-9)
+    assert lo["alpha"] == pytest.approx(0.52 / 9 / 0.024, rel=1e-9)
+    assert lo["nu_t"] == pytest.approx(0.024 * 1e-14, rel=1e-9)
+
+
+def test_wall_omega_fixed_value(oracle):
+    """omega in wall cells = 6 nu / (beta_i d^2), d = half the normal cell width
+    (Sec. 2.7); the smaller distance wins in corners."""
+    c = box((6, 5, 4), (0.1, 0.04, 0.2), physics=C.PHYS_KOMEGA, nu=1.5e-5,
+            kinds=[C.INLET, C.OUTLET, C.WALL, C.WALL, C.WALL, C.WALL])
+    om = oracle.fixed_omega(c, np.ones((4, 5, 6)))
+    wy = 6 * 1.5e-5 / (0.072 * 0.02 ** 2)
+    wz = 6 * 1.5e-5 / (0.072 * 0.1 ** 2)
+    assert om[2, 0, 3] == pytest.approx(wy, rel=1e-14)
+    assert om[0, 2, 3] == pytest.approx(wz, rel=1e-14)
+    assert om[0, 0, 3] == pytest.approx(wy, rel=1e-14)
+    assert om[2, 2, 3] == 1.0
