@@ -1,0 +1,180 @@
+"""Benchmark of the NeuralFVM time step on one MI355X.
+
+One benchmark step is one full time step of the hot path (destruction half
+step, explicit update, Poisson right-hand side, multigrid-preconditioned
+pressure solve to the residual target, projection, destruction half step) over
+the whole grid, with all fields resident in device memory.
+
+Default workload: the 3D heated channel, 256 x 64 x 64 cells (2.56 x 0.64 x
+0.64 m, inlet 0.1 m/s, bottom wall 310 K, Boussinesq buoyancy, seeded 1 %
+velocity noise), 7 multigrid levels, mixed precision (FP32 scalars, FP32 /
+BF16 V-cycle, FP64 velocity, pressure, residual and projection), pressure
+solved to a relative residual of 1e-6 every step.
+
+Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+WORKLOADS = {
+    "channel3d": "3D heated channel 256x64x64, 7 levels",
+    "channel2d": "2D turbulent channel 256x64, 6 levels",
+    "room": "3D ventilated room 512x256x128 with seeded blocks, 8 levels",
+    "bigroom": "3D ventilated room 1024x512x256 with seeded blocks, 9 levels",
+}
+
+
+def make_case(name: str, precision: int, tol: float):
+    from paper_2603_21869_amd import cases as C
+    if name == "channel3d":
+        return C.channel3d(precision=precision, tol=tol)
+    if name == "channel2d":
+        return C.channel2d(precision=precision, tol=tol)
+    if name == "room":
+        return C.room3d(precision=precision, tol=tol)
+    if name == "bigroom":
+        return C.room3d(1024, 512, 256, n_levels=9, precision=precision, tol=tol, n_steps=100)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_gpu(case, steps: int, warmup: int, profile: bool, stream: int):
+    import torch
+    from paper_2603_21869_amd import nfvm
+    g = nfvm.Grid(case, stream=stream)
+    if warmup:
+        g.step(warmup, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+    torch.cuda.synchronize()
+    if profile:
+        nfvm.nfvm_profile(g.h, (1 << len(nfvm.KERNELS)) - 1)
+    t0 = time.perf_counter()
+    s, stats = g.step(steps, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {}
+    if profile:
+        for kid, name in enumerate(nfvm.KERNELS):
+            prof[name] = nfvm.nfvm_profile_read(g.h, kid)
+    g.close()
+    return t1 - t0, stats, prof, s
+
+
+def cpu_baseline(case, budget_s: float = 20.0):
+    """The serial FP64 oracle on a bounded number of steps of the same workload."""
+    from oracle import oracle as O
+    O.build()
+    t0 = time.perf_counter()
+    f, st, status = O.step(case, 1)
+    t1 = time.perf_counter()
+    n = 1
+    per = t1 - t0
+    extra = int(max(0, min(3, budget_s / per - 1)))
+    if extra:
+        t2 = time.perf_counter()
+        O.step(case, extra, fields=f)
+        t3 = time.perf_counter()
+        per = (t1 - t0 + t3 - t2) / (1 + extra)
+        n += extra
+    return dict(value=case.ncells / per / 1e6, unit="Mcell-steps/s", cores=1, kind="oracle",
+                sample=f"{n} step(s) of the same workload from its initial state, serial FP64 "
+                       f"oracle, {per:.2f} s/step")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="channel3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2603_21869_amd import cases as C, nfvm
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream().cuda_stream
+    prec = {"fp64": C.PREC_FP64, "fp32": C.PREC_FP32, "mixed": C.PREC_MIXED}[args.precision]
+    case = make_case(args.workload, prec, args.tol)
+
+    sec, stats, prof, status = run_gpu(case, args.steps, args.warmup, True, stream)
+    ms_per_step = sec / args.steps * 1e3
+    value = case.ncells * args.steps / sec / 1e6
+    cycles = [s["cycles"] for s in stats]
+    rel = [s["rel_residual"] for s in stats]
+
+    # dominant kernel: largest summed device time in the timed region
+    dom = max(prof, key=lambda k: prof[k]["seconds"])
+    d = prof[dom]
+    avg = d["seconds"] / max(1, d["launches"])
+    achieved = d["bytes_per_launch"] / avg / 1e9 if avg > 0 else 0.0
+    kernel_table = {k: dict(launches=v["launches"], avg_us=(v["seconds"] / v["launches"] * 1e6)
+                            if v["launches"] else 0.0,
+                            GBs=(v["bytes_per_launch"] / (v["seconds"] / v["launches"]) / 1e9)
+                            if v["launches"] and v["seconds"] > 0 else 0.0,
+                            share=v["seconds"] / sec)
+                    for k, v in prof.items() if v["launches"]}
+
+    variants = {}
+    if not args.no_variants:
+        for pname, pv in (("fp64", C.PREC_FP64), ("fp32", C.PREC_FP32), ("mixed", C.PREC_MIXED)):
+            if pv == prec:
+                continue
+            c2 = make_case(args.workload, pv, args.tol)
+            k2 = max(5, args.steps // 2)
+            s2, st2, _, _ = run_gpu(c2, k2, args.warmup, False, stream)
+            variants[pname] = dict(value=c2.ncells * k2 / s2 / 1e6,
+                                   ms_per_step=s2 / k2 * 1e3,
+                                   mean_cycles=sum(x["cycles"] for x in st2) / len(st2))
+
+    out = {
+        "metric": "Mcell-steps/s at 1e-6 residual",
+        "value": round(value, 3),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "mixed": "f32+bf16 with f64 refinement"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "cells": case.ncells,
+                   "precision": args.precision, "tol": args.tol, "dt": case.dt,
+                   "levels": case.n_levels, "smoothing": "V(2,2) damped Jacobi",
+                   "parallelism": "single GPU"},
+        "solver": {"mean_cycles": sum(cycles) / len(cycles), "max_rel_residual": max(rel)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None, "avg_launch_us": round(avg * 1e6, 2),
+                     "algorithmic_bytes_per_launch": d["bytes_per_launch"]},
+        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kernel_table.items()},
+        "variants": variants,
+        "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
+                         "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(make_case(args.workload, C.PREC_FP64, args.tol))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * nfvm.h -- C ABI of the MI355X NeuralFVM time-step library (libnfvm.so).
+ *
+ * The library advances the incompressible RANS equations with the standard
+ * k-omega model on a uniform structured grid, as formulated in
+ * "NeuralFVM: Neural-physics-based Finite Volume Method for Turbulent Flows
+ * Using the k-omega Model" (Xue et al., arXiv 2603.21869):
+ *   - explicit first-order-upwind finite-volume update of u, v, w, T, k, omega
+ *     (Sec. 2.3; Algorithms 2 and 4; appendix on explicit time stepping),
+ *   - semi-implicit destruction of k and omega in two half steps around it
+ *     (Sec. 2.5, eqs. k_des_step / o_des_step; Sec. 2.6; Algorithm 3),
+ *   - pressure projection with a geometric-multigrid Poisson solve
+ *     (Sec. 2.4, eqs. pc_residual to jacobi_pc; Algorithm 1).
+ * Every step of the time step runs in HIP kernels built for gfx950.
+ *
+ * Conventions shared by all entry points:
+ *   - Every call returns an nfvm_status; nothing throws across the ABI.  On a
+ *     negative status nfvm_last_error() returns a message (thread-local).
+ *   - Host arrays are FP64, cell-centred, C order [nz][ny][nx] (x fastest),
+ *     nz = 1 in 2D.  The caller owns every host pointer; the library only
+ *     reads or writes it during the call.
+ *   - Device arrays (the *_device calls) use the same dense layout, in FP64,
+ *     and must stay valid until the call returns.
+ *   - The library owns all device memory of a grid; nfvm_free_grid releases
+ *     it.  Device memory comes from hipMalloc unless nfvm_set_allocator has
+ *     installed another allocator (for instance PyTorch's caching allocator).
+ *   - Work of a grid is issued on the HIP stream given to nfvm_init_grid
+ *     (NULL: a stream the library creates).  A grid handle must not be used
+ *     from two threads at once; server calls are thread-safe.
+ */
+#ifndef NFVM_H
+#define NFVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NFVM_OK = 0,
+  NFVM_PENDING = 1,       /* nfvm_poll: request not finished yet */
+  NFVM_E_INVAL = -1,      /* bad argument or descriptor */
+  NFVM_E_NOMEM = -2,      /* device allocation failed or request above the HBM budget */
+  NFVM_E_DEVICE = -3,     /* a HIP call failed */
+  NFVM_E_DIVERGED = -4,   /* non-finite residual or field */
+  NFVM_E_NOTCONV = -5,    /* max_cycles reached before tol; fields stay valid */
+  NFVM_E_NOTFOUND = -6    /* unknown ticket */
+} nfvm_status;
+
+typedef enum { NFVM_FP64 = 0, NFVM_FP32 = 1, NFVM_MIXED = 2 } nfvm_precision;
+
+/* boundary patch kinds (Sec. 2.7) */
+enum { NFVM_WALL = 0, NFVM_INLET = 1, NFVM_OUTLET = 2 };
+/* physics switches: k-omega closure, energy equation, Boussinesq buoyancy */
+enum { NFVM_PHYS_KOMEGA = 1, NFVM_PHYS_ENERGY = 2, NFVM_PHYS_BUOYANCY = 4 };
+
+/* A rectangle of boundary faces on one side of the box (Sec. 2.7).
+ * face: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+.  lo/hi: half-open cell ranges
+ * along the two tangential axes (x faces: j, k; y faces: i, k; z faces: i, j).
+ * Faces no patch covers are adiabatic no-slip walls; the first patch that
+ * covers a face wins.
+ *   WALL   no-slip; dk/dn = 0; omega fixed in the wall cell to
+ *          6 nu / (beta_i d^2); T = T_wall (NaN: adiabatic).
+ *   INLET  Dirichlet U, T, k, omega; zero-gradient pressure.
+ *   OUTLET zero-gradient velocity, T, k, omega; zero pressure. */
+typedef struct {
+  int32_t face;
+  int32_t lo[2], hi[2];
+  int32_t kind;
+  double U[3], T, k, omega, T_wall;
+} nfvm_patch;
+
+/* Grid and solver description (the paper's problem statement: uniform
+ * grid, fluid properties, boundary patches, optional solid mask, time step).
+ *   dim           2 or 3; n = cells per axis (n[2] = 1 in 2D); h = spacing [m]
+ *   nu, rho       kinematic viscosity [m^2/s], density (p is kinematic)
+ *   alpha_T       thermal diffusivity; Pr_t turbulent Prandtl number (0.85)
+ *   sigma_k, sigma_w  turbulent Prandtl numbers of k and omega
+ *   dt            time step [s]
+ *   physics       NFVM_PHYS_* bits
+ *   gravity, T_ref, beta_T   Boussinesq source -beta_T (T - T_ref) g
+ *   T_solid       temperature of solid cells (NaN: adiabatic)
+ *   solid_mask    [nz][ny][nx], 1 = solid, may be NULL; fluid pockets must
+ *                 connect to an OUTLET face (else A is singular)
+ *   precision     NFVM_FP64 / NFVM_FP32 / NFVM_MIXED (FP32 fields, BF16
+ *                 coarse levels, FP64 pressure, residual and projection)
+ *   n_levels      multigrid levels; every axis < dim halves exactly per level;
+ *                 the coarsest level holds at most 512 fluid cells
+ *   nu1, nu2      pre/post Jacobi sweeps; omega_jacobi (0: 4/5 in 2D, 6/7 in 3D)
+ *   tol           relative residual target ||b - A phi|| <= tol ||b||
+ *   max_cycles    preconditioner applications per pressure solve */
+typedef struct {
+  int32_t dim, n[3];
+  double h[3];
+  double nu, rho, alpha_T, Pr_t, sigma_k, sigma_w, dt;
+  uint32_t physics;
+  double gravity[3], T_ref, beta_T, T_solid;
+  int32_t n_patches;
+  const nfvm_patch* patches;
+  const uint8_t* solid_mask;
+  int32_t precision;
+  int32_t n_levels, nu1, nu2;
+  double omega_jacobi, tol;
+  int32_t max_cycles;
+} nfvm_grid_desc;
+
+/* Host FP64 fields, [nz][ny][nx].  p is kinematic pressure (Pa / rho). */
+typedef struct { double *u, *v, *w, *p, *T, *k, *omega; } nfvm_fields;
+
+typedef struct {
+  int32_t cycles;         /* preconditioner (V-cycle) applications */
+  int32_t status;         /* nfvm_status of this step */
+  double rel_residual;    /* ||r|| / ||b|| at exit of the pressure solve */
+  double max_face_div;    /* max cell divergence of the corrected face fluxes */
+  double min_k, min_omega;/* over fluid cells after the step */
+  double seconds;         /* device time of the step */
+} nfvm_step_stats;
+
+typedef struct nfvm_grid* nfvm_grid_t;
+typedef struct nfvm_server* nfvm_server_t;
+
+/* Optional device allocator used for all later allocations (NULL, NULL:
+ * back to hipMalloc/hipFree).  alloc(bytes, ctx) returns a device pointer or
+ * NULL; free(ptr, ctx) releases it.  Not thread-safe against running calls. */
+typedef void* (*nfvm_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*nfvm_free_fn)(void* ptr, void* ctx);
+nfvm_status nfvm_set_allocator(nfvm_alloc_fn alloc, nfvm_free_fn free_fn, void* ctx);
+
+/* Create a grid on the current HIP device, classify its cells (patches,
+ * solids, wall-fixed omega cells), build the multigrid hierarchy and upload
+ * init (all seven fields required).  stream: hipStream_t or NULL.
+ * Errors: NFVM_E_INVAL (descriptor), NFVM_E_NOMEM, NFVM_E_DEVICE. */
+nfvm_status nfvm_init_grid(const nfvm_grid_desc* desc, const nfvm_fields* init, void* stream,
+                           nfvm_grid_t* out);
+
+/* Advance n_steps time steps (Sec. 2.6): destruction over dt/2, explicit
+ * step of the rest terms, projection, destruction over dt/2.  stats: NULL or
+ * n_steps entries.  Returns NFVM_E_NOTCONV if a pressure solve hit
+ * max_cycles (the step is still completed) and NFVM_E_DIVERGED on
+ * non-finite residuals (the step stops; fields are undefined). */
+nfvm_status nfvm_step(nfvm_grid_t grid, int32_t n_steps, nfvm_step_stats* stats);
+
+/* Solve A x = b with the grid's pressure operator (eq. pc_discretized:
+ * seven/five-point -laplacian, zero-gradient walls, inlets and solids, zero
+ * value at outlets) by the multigrid-preconditioned iteration.  b, x: host
+ * FP64 [nz][ny][nx]; x is the initial guess on entry and the solution on exit;
+ * solid cells are ignored on entry and 0 on exit.  forced_cycles >= 0 runs
+ * exactly that many cycles (tol ignored).  stats may be NULL. */
+nfvm_status nfvm_mg_solve(nfvm_grid_t grid, const double* b, double* x, double tol,
+                          int32_t max_cycles, int32_t forced_cycles, nfvm_step_stats* stats);
+
+/* As nfvm_mg_solve with device FP64 arrays, on the grid's stream. */
+nfvm_status nfvm_mg_solve_device(nfvm_grid_t grid, const double* b_dev, double* x_dev,
+                                 double tol, int32_t max_cycles, int32_t forced_cycles,
+                                 nfvm_step_stats* stats);
+
+/* Copy the fields to / from host FP64 arrays (all seven pointers required). */
+nfvm_status nfvm_get_fields(nfvm_grid_t grid, nfvm_fields* out);
+nfvm_status nfvm_set_fields(nfvm_grid_t grid, const nfvm_fields* in);
+
+/* Bytes of device memory a grid with this descriptor allocates. */
+nfvm_status nfvm_grid_footprint(const nfvm_grid_desc* desc, size_t* bytes);
+
+nfvm_status nfvm_free_grid(nfvm_grid_t grid);
+
+/* Serving: max_slots host worker threads admit queued solves, first fit in
+ * arrival order, while the summed device footprint of running solves stays
+ * within hbm_budget_bytes.  Every admitted solve runs on its own HIP stream,
+ * so solves of different grid sizes overlap on the device, and a slot takes
+ * the next admissible request as soon as its solve finishes (new work joins
+ * at step boundaries of the running ones).  A finished solve releases its
+ * device memory and keeps its fields on the host until polled.
+ * hbm_budget_bytes <= 0: 90 % of the free device memory. */
+nfvm_status nfvm_server_create(double hbm_budget_bytes, int32_t max_slots, nfvm_server_t* out);
+
+/* Queue a solve of n_steps time steps; the descriptor, patches, mask and
+ * init are copied before return.  NFVM_E_NOMEM if its footprint alone is
+ * above the budget. */
+nfvm_status nfvm_submit(nfvm_server_t server, const nfvm_grid_desc* desc,
+                        const nfvm_fields* init, int32_t n_steps, uint64_t* ticket);
+
+/* NFVM_PENDING while queued or running.  When done, copies the final fields
+ * into out (if non-NULL; all seven pointers) and the last step's stats into
+ * last (if non-NULL), releases the request and returns its status. */
+nfvm_status nfvm_poll(nfvm_server_t server, uint64_t ticket, nfvm_fields* out,
+                      nfvm_step_stats* last);
+
+/* Per-request timestamps in seconds since server creation: submit, admit,
+ * first step meeting tol, done (negative: not yet).  Valid until polled. */
+nfvm_status nfvm_request_times(nfvm_server_t server, uint64_t ticket, double times[4]);
+
+/* Block until every submitted request is done (not yet polled ones stay). */
+nfvm_status nfvm_server_drain(nfvm_server_t server);
+
+nfvm_status nfvm_server_destroy(nfvm_server_t server);
+
+/* Kernel timing.  nfvm_profile(grid, mask) times every later launch of the
+ * kernels whose bit (1 << id) is set with HIP events on the grid's stream and
+ * resets the totals (mask 0: off).  nfvm_profile_read returns, per kernel,
+ * the number of timed launches, their summed device time and the
+ * algorithmic bytes one launch moves (the minimum traffic of its operands:
+ * each input read once, each output written once, at the storage precision;
+ * on level 0 of the multigrid hierarchy). */
+enum {
+  NFVM_K_SMOOTH0 = 0,      /* damped-Jacobi sweep on level 0 */
+  NFVM_K_SMOOTH0_ZERO = 1, /* first sweep from a zero iterate */
+  NFVM_K_RESTRICT0 = 2,    /* residual + restriction, level 0 -> 1 */
+  NFVM_K_PROLONG0 = 3,     /* prolongation + correction, level 1 -> 0 */
+  NFVM_K_EXPLICIT = 4,     /* explicit step of u, v, w, T, k, omega */
+  NFVM_K_DESTROY = 5,      /* semi-implicit destruction half step */
+  NFVM_K_RHS = 6,          /* Poisson right-hand side */
+  NFVM_K_PROJECT = 7,      /* projection */
+  NFVM_K_FCG_DOTS = 8,     /* (z, r), (z, q) */
+  NFVM_K_FCG_DIR = 9,      /* search direction and A p */
+  NFVM_K_FCG_UPDATE = 10,  /* x, r update and ||r|| */
+  NFVM_K_COUNT = 11
+};
+nfvm_status nfvm_profile(nfvm_grid_t grid, uint32_t kernel_mask);
+nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launches,
+                              double* seconds, double* bytes_per_launch);
+
+/* Message for the last non-OK status on this thread. */
+const char* nfvm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

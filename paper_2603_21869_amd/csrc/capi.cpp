@@ -1,0 +1,157 @@
+// C ABI entry points of libnfvm.so (declared in include/nfvm.h): argument
+// checks, conversion of library errors to nfvm_status, thread-local messages.
+#include <string.h>
+
+#include <string>
+
+#include "engine.hpp"
+
+namespace nfvm {
+void set_allocator(nfvm_alloc_fn a, nfvm_free_fn f, void* ctx);
+static thread_local std::string t_err;
+void set_error(const std::string& m) { t_err = m; }
+}  // namespace nfvm
+
+using namespace nfvm;
+
+template <class Fn>
+static nfvm_status guard(Fn&& fn) {
+  try {
+    return fn();
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return NFVM_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return NFVM_E_DEVICE;
+  }
+}
+
+static nfvm_status fail(nfvm_status st, const char* msg) {
+  set_error(msg);
+  return st;
+}
+
+extern "C" {
+
+nfvm_status nfvm_set_allocator(nfvm_alloc_fn alloc, nfvm_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(NFVM_E_INVAL, "allocator and free function must be given together");
+  set_allocator(alloc, free_fn, ctx);
+  return NFVM_OK;
+}
+
+nfvm_status nfvm_init_grid(const nfvm_grid_desc* desc, const nfvm_fields* init, void* stream,
+                           nfvm_grid_t* out) {
+  if (!desc || !out) return fail(NFVM_E_INVAL, "desc and out are required");
+  *out = nullptr;
+  return guard([&] {
+    auto g = make_grid(*desc, init, (hipStream_t)stream);
+    *out = new nfvm_grid{std::move(g)};
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_step(nfvm_grid_t grid, int32_t n_steps, nfvm_step_stats* stats) {
+  if (!grid || n_steps < 0) return fail(NFVM_E_INVAL, "bad grid or step count");
+  return guard([&] {
+    nfvm_status st = NFVM_OK;
+    grid->g->step(n_steps, stats, &st);
+    if (st == NFVM_E_DIVERGED) set_error("non-finite residual or field");
+    if (st == NFVM_E_NOTCONV) set_error("pressure solve reached max_cycles");
+    return st;
+  });
+}
+
+nfvm_status nfvm_mg_solve_device(nfvm_grid_t grid, const double* b_dev, double* x_dev, double tol,
+                                 int32_t max_cycles, int32_t forced_cycles,
+                                 nfvm_step_stats* stats) {
+  if (!grid || !b_dev || !x_dev) return fail(NFVM_E_INVAL, "grid, b and x are required");
+  return guard([&] {
+    nfvm_status st = NFVM_OK;
+    grid->g->mg_solve(b_dev, x_dev, tol, max_cycles, forced_cycles, stats, &st);
+    if (st == NFVM_E_NOTCONV) set_error("pressure solve reached max_cycles");
+    if (st == NFVM_E_DIVERGED) set_error("non-finite residual");
+    return st;
+  });
+}
+
+nfvm_status nfvm_mg_solve(nfvm_grid_t grid, const double* b, double* x, double tol,
+                          int32_t max_cycles, int32_t forced_cycles, nfvm_step_stats* stats) {
+  if (!grid || !b || !x) return fail(NFVM_E_INVAL, "grid, b and x are required");
+  return guard([&] {
+    const size_t bytes = (size_t)grid->g->ncells * sizeof(double);
+    DevBuf bd, xd;
+    hipStream_t s = grid->g->stream;
+    bd.alloc(bytes, s);
+    xd.alloc(bytes, s);
+    NFVM_CK(hipMemcpyAsync(bd.p, b, bytes, hipMemcpyHostToDevice, s));
+    NFVM_CK(hipMemcpyAsync(xd.p, x, bytes, hipMemcpyHostToDevice, s));
+    nfvm_status st = NFVM_OK;
+    grid->g->mg_solve(bd.as<double>(), xd.as<double>(), tol, max_cycles, forced_cycles, stats,
+                      &st);
+    NFVM_CK(hipMemcpyAsync(x, xd.p, bytes, hipMemcpyDeviceToHost, s));
+    NFVM_CK(hipStreamSynchronize(s));
+    if (st == NFVM_E_NOTCONV) set_error("pressure solve reached max_cycles");
+    if (st == NFVM_E_DIVERGED) set_error("non-finite residual");
+    return st;
+  });
+}
+
+nfvm_status nfvm_get_fields(nfvm_grid_t grid, nfvm_fields* out) {
+  if (!grid || !out) return fail(NFVM_E_INVAL, "grid and out are required");
+  return guard([&] {
+    grid->g->get_fields(out);
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_set_fields(nfvm_grid_t grid, const nfvm_fields* in) {
+  if (!grid || !in) return fail(NFVM_E_INVAL, "grid and fields are required");
+  return guard([&] {
+    grid->g->set_fields(in);
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_grid_footprint(const nfvm_grid_desc* desc, size_t* bytes) {
+  if (!desc || !bytes) return fail(NFVM_E_INVAL, "desc and bytes are required");
+  return guard([&] {
+    validate_desc(*desc);
+    *bytes = footprint_bytes(*desc);
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_free_grid(nfvm_grid_t grid) {
+  if (!grid) return fail(NFVM_E_INVAL, "grid is NULL");
+  return guard([&] {
+    delete grid;
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_profile(nfvm_grid_t grid, uint32_t kernel_mask) {
+  if (!grid) return fail(NFVM_E_INVAL, "grid is NULL");
+  return guard([&] {
+    grid->g->prof_reset(kernel_mask & ((1u << NFVM_K_COUNT) - 1));
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launches,
+                              double* seconds, double* bytes_per_launch) {
+  if (!grid || kernel < 0 || kernel >= NFVM_K_COUNT)
+    return fail(NFVM_E_INVAL, "bad grid or kernel id");
+  if (launches) *launches = grid->g->prof_launches[kernel];
+  if (seconds) *seconds = grid->g->prof_seconds[kernel];
+  if (bytes_per_launch) *bytes_per_launch = grid->g->prof_bytes[kernel];
+  return NFVM_OK;
+}
+
+const char* nfvm_last_error(void) { return t_err.c_str(); }
+
+}  // extern "C"

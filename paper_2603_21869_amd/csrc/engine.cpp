@@ -1,0 +1,617 @@
+// Host engine of one grid: device buffers, multigrid hierarchy, and the
+// order of kernels in a time step (Sec. 2.6: destruction over dt/2, explicit
+// step, projection, destruction over dt/2) and in the pressure solve.
+#include "engine.hpp"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+namespace nfvm {
+
+// ---- allocator hook ------------------------------------------------------------
+static nfvm_alloc_fn g_alloc = nullptr;
+static nfvm_free_fn g_free = nullptr;
+static void* g_ctx = nullptr;
+
+void set_allocator(nfvm_alloc_fn a, nfvm_free_fn f, void* ctx) {
+  g_alloc = a;
+  g_free = f;
+  g_ctx = ctx;
+}
+
+void* dev_alloc(size_t bytes) {
+  if (g_alloc) return g_alloc(bytes, g_ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  if (g_free) {
+    g_free(p, g_ctx);
+    return;
+  }
+  (void)hipFree(p);
+}
+
+constexpr int COARSE_MAX = 512;
+
+// ---- descriptor checks ---------------------------------------------------------
+void validate_desc(const nfvm_grid_desc& d) {
+  auto bad = [](const std::string& m) { throw Error{NFVM_E_INVAL, m}; };
+  if (d.dim != 2 && d.dim != 3) bad("dim must be 2 or 3");
+  for (int a = 0; a < d.dim; ++a)
+    if (d.n[a] < 1 || !(d.h[a] > 0)) bad("cell counts and spacings must be positive");
+  if (d.dim == 2 && d.n[2] != 1) bad("2D grids need n[2] == 1");
+  if (d.dim == 3 && d.n[2] < 1) bad("n[2] must be positive");
+  const long long padded = (long long)(d.n[0] + 18) * (d.n[1] + 2) * (d.n[2] + 2);
+  if (padded >= (1LL << 31)) bad("grid too large for 32-bit cell indices");
+  if (!(d.dt > 0) || !(d.nu > 0)) bad("dt and nu must be positive");
+  if (d.precision < NFVM_FP64 || d.precision > NFVM_MIXED) bad("unknown precision");
+  if (d.n_levels < 1 || d.n_levels > 20) bad("n_levels must be in [1, 20]");
+  for (int a = 0; a < d.dim; ++a)
+    if (d.n[a] % (1 << (d.n_levels - 1))) bad("every axis must halve exactly n_levels-1 times");
+  if (d.nu1 < 0 || d.nu2 < 0 || d.nu1 + d.nu2 < 1) bad("need at least one smoothing sweep");
+  if (d.n_patches < 0 || d.n_patches > MAX_PATCHES - PID_USER) bad("too many patches");
+  if (d.n_patches > 0 && !d.patches) bad("patches pointer is NULL");
+  for (int q = 0; q < d.n_patches; ++q) {
+    const nfvm_patch& p = d.patches[q];
+    if (p.face < 0 || p.face >= 2 * d.dim) bad("patch face out of range");
+    if (p.kind < NFVM_WALL || p.kind > NFVM_OUTLET) bad("unknown patch kind");
+  }
+  if (d.max_cycles < 0) bad("max_cycles must be >= 0");
+}
+
+static Geom level_geom(const nfvm_grid_desc& d, int l) {
+  const int f = 1 << l;
+  return make_geom(d.dim, d.n[0] / f, d.n[1] / f, d.dim == 3 ? d.n[2] / f : 1, d.h[0] * f,
+                   d.h[1] * f, d.dim == 3 ? d.h[2] * f : d.h[2]);
+}
+
+static void sizes_of(int prec, size_t& V, size_t& F, size_t& P, size_t& O, size_t& S0,
+                     size_t& SC) {
+  if (prec == NFVM_FP64) { V = F = P = O = S0 = SC = 8; }
+  else if (prec == NFVM_FP32) { V = F = P = O = S0 = SC = 4; }
+  else { V = 8; F = 4; P = 8; O = 8; S0 = 4; SC = 2; }
+}
+
+static int max_blocks_of(const Geom& g) {
+  return ((g.nx + 63) / 64) * ((g.ny + 3) / 4) * g.nz;
+}
+
+size_t footprint_bytes(const nfvm_grid_desc& d) {
+  size_t V, F, P, O, S0, SC;
+  sizes_of(d.precision, V, F, P, O, S0, SC);
+  const Geom g = level_geom(d, 0);
+  const size_t T = (size_t)g.total, N = (size_t)g.cells();
+  size_t b = 0;
+  b += 6 * T * V + 6 * T * F + T * P + T;           // fields (ping-pong), pressure, cell types
+  b += 6 * T * O;                                   // b, phi, r, p (x2), q
+  b += T * O;                                       // initial guess of the solve call
+  b += 8 * N + (d.solid_mask ? N : 0);              // dense staging, mask
+  for (int l = 0; l < d.n_levels; ++l) {
+    const Geom gl = level_geom(d, l);
+    b += (size_t)gl.total * (1 + 4 * d.dim + 3 * (l == 0 ? S0 : SC));
+  }
+  b += (size_t)max_blocks_of(g) * 3 * 8 + 4096;     // reduction partials
+  b += (size_t)2 * COARSE_MAX * COARSE_MAX * 8 + COARSE_MAX * 4;  // dense coarse inverse
+  b += MAX_PATCHES * sizeof(DevPatch) + 5 * 4 * MAX_PATCHES;
+  return b;
+}
+
+// ---- kernel timing ------------------------------------------------------------------
+hipEvent_t GridBase::next_event() {
+  if (ev_used == ev_pool.size()) {
+    hipEvent_t e;
+    NFVM_CK(hipEventCreate(&e));
+    ev_pool.push_back(e);
+  }
+  return ev_pool[ev_used++];
+}
+
+void GridBase::prof_begin(int kid) {
+  if (!(prof_mask & (1u << kid))) return;
+  ProfRec r{kid, next_event(), nullptr};
+  NFVM_CK(hipEventRecord(r.a, stream));
+  prof_pending.push_back(r);
+}
+
+void GridBase::prof_end(int kid) {
+  if (!(prof_mask & (1u << kid))) return;
+  hipEvent_t b = next_event();
+  NFVM_CK(hipEventRecord(b, stream));
+  prof_pending.back().b = b;
+}
+
+void GridBase::prof_collect() {
+  for (const ProfRec& r : prof_pending) {
+    float ms = 0;
+    NFVM_CK(hipEventElapsedTime(&ms, r.a, r.b));
+    prof_launches[r.kid] += 1;
+    prof_seconds[r.kid] += ms * 1e-3;
+  }
+  prof_pending.clear();
+  ev_used = 0;
+}
+
+void GridBase::prof_reset(uint32_t mask) {
+  if (stream) NFVM_CK(hipStreamSynchronize(stream));
+  prof_pending.clear();
+  ev_used = 0;
+  prof_mask = mask;
+  for (int k = 0; k < NFVM_K_COUNT; ++k) {
+    prof_launches[k] = 0;
+    prof_seconds[k] = 0;
+  }
+}
+
+void GridBase::prof_release() {
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  ev_pool.clear();
+}
+
+// ---- the grid ------------------------------------------------------------------
+template <class V, class F, class P, class O, class S0, class SC, class C>
+class GridT : public GridBase {
+ public:
+  Geom g{};
+  Phys ph{};
+  int L = 1, nu1 = 2, nu2 = 2;
+  double wj = 0.8;
+  std::vector<std::unique_ptr<DevBuf>> pool;
+  uint8_t* type = nullptr;
+  DevPatch* patches = nullptr;
+  V* vel[3][2] = {};   // u v w
+  F* sca[3][2] = {};   // T k omega
+  int fcur[6] = {0, 0, 0, 0, 0, 0};
+  P* p = nullptr;
+  std::vector<Level> lv;
+  O *bvec = nullptr, *phi = nullptr, *r = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr,
+    *x0 = nullptr;
+  double* stage = nullptr;
+  RedBuf red{};
+  int* cmap = nullptr;
+  int* ncount = nullptr;
+  double* work = nullptr;
+  double* hs = nullptr;  // pinned host copy of the scalars
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  template <class T>
+  T* alloc(size_t count) {
+    pool.emplace_back(new DevBuf());
+    pool.back()->alloc(count * sizeof(T), stream);
+    return pool.back()->template as<T>();
+  }
+
+  ~GridT() override {
+    if (stream) (void)hipStreamSynchronize(stream);
+    prof_release();
+    pool.clear();
+    if (hs) (void)hipHostFree(hs);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  void init(const nfvm_grid_desc& d, const nfvm_fields* init) {
+    desc = d;
+    desc.patches = nullptr;
+    desc.solid_mask = nullptr;
+    tol = d.tol;
+    max_cycles = d.max_cycles;
+    g = level_geom(d, 0);
+    ncells = g.cells();
+    L = d.n_levels;
+    nu1 = d.nu1;
+    nu2 = d.nu2;
+    wj = d.omega_jacobi > 0 ? d.omega_jacobi : (d.dim == 3 ? 6.0 / 7.0 : 4.0 / 5.0);
+    ph.nu = d.nu;
+    ph.alpha_T = d.alpha_T;
+    ph.inv_Pr_t = 1.0 / d.Pr_t;
+    ph.inv_sigma_k = 1.0 / d.sigma_k;
+    ph.inv_sigma_w = 1.0 / d.sigma_w;
+    ph.dt = d.dt;
+    ph.komega = (d.physics & NFVM_PHYS_KOMEGA) ? 1 : 0;
+    ph.energy = (d.physics & NFVM_PHYS_ENERGY) ? 1 : 0;
+    ph.buoyancy = (d.physics & NFVM_PHYS_BUOYANCY) ? 1 : 0;
+    for (int a = 0; a < 3; ++a) ph.g[a] = d.gravity[a];
+    ph.T_ref = d.T_ref;
+    ph.beta_T = d.beta_T;
+
+    {
+      // algorithmic bytes per launch: operands read once, results written once
+      const double N = (double)ncells, sv = sizeof(V), sf = sizeof(F), sp = sizeof(P),
+                   so = sizeof(O), s0 = sizeof(S0), scs = sizeof(SC);
+      const double nc = L > 1 ? (double)level_geom(d, 1).cells() : 0.0;
+      prof_bytes[NFVM_K_SMOOTH0] = N * (3 * s0 + 1);
+      prof_bytes[NFVM_K_SMOOTH0_ZERO] = N * (2 * s0 + 1);
+      prof_bytes[NFVM_K_RESTRICT0] = N * (2 * s0 + 1) + nc * (scs + 1);
+      prof_bytes[NFVM_K_PROLONG0] = N * (2 * s0 + 1) + nc * (scs + 1);
+      prof_bytes[NFVM_K_EXPLICIT] = N * (6 * sv + 6 * sf + sp + 1);
+      prof_bytes[NFVM_K_DESTROY] = N * (3 * sv + 4 * sf + 1);
+      prof_bytes[NFVM_K_RHS] = N * (3 * sv + so + 1);
+      prof_bytes[NFVM_K_PROJECT] = N * (6 * sv + 2 * sp + so + 1);
+      prof_bytes[NFVM_K_FCG_DOTS] = N * (s0 + 2 * so + 1);
+      prof_bytes[NFVM_K_FCG_DIR] = N * (s0 + 3 * so + 1);
+      prof_bytes[NFVM_K_FCG_UPDATE] = N * (s0 + 6 * so + 1);
+    }
+    NFVM_CK(hipEventCreate(&ev0));
+    NFVM_CK(hipEventCreate(&ev1));
+    NFVM_CK(hipHostMalloc((void**)&hs, S_COUNT * sizeof(double), hipHostMallocDefault));
+
+    // patch table: 0 fluid (unused), 1 solid blocks, 2..7 default walls, then user patches
+    std::vector<DevPatch> tab(MAX_PATCHES);
+    memset(tab.data(), 0, tab.size() * sizeof(DevPatch));
+    for (auto& t : tab) t.kind = K_WALL;
+    // temperatures are held as deviations from T_ref on the device
+    tab[PID_SOLID].T_dirichlet = isnan(d.T_solid) ? 0 : 1;
+    tab[PID_SOLID].T_wall = d.T_solid - d.T_ref;
+    std::vector<int> rect(5 * std::max(1, (int)d.n_patches));
+    for (int qi = 0; qi < d.n_patches; ++qi) {
+      const nfvm_patch& s = d.patches[qi];
+      DevPatch& t = tab[PID_USER + qi];
+      t.kind = s.kind;
+      for (int a = 0; a < 3; ++a) t.U[a] = s.U[a];
+      t.T = s.T - d.T_ref;
+      t.k = s.k;
+      t.omega = s.omega;
+      t.T_wall = s.T_wall - d.T_ref;
+      t.T_dirichlet = (s.kind == NFVM_WALL && !isnan(s.T_wall)) ? 1 : 0;
+      rect[5 * qi + 0] = s.face;
+      rect[5 * qi + 1] = s.lo[0];
+      rect[5 * qi + 2] = s.lo[1];
+      rect[5 * qi + 3] = s.hi[0];
+      rect[5 * qi + 4] = s.hi[1];
+    }
+    patches = alloc<DevPatch>(MAX_PATCHES);
+    NFVM_CK(hipMemcpyAsync(patches, tab.data(), tab.size() * sizeof(DevPatch),
+                           hipMemcpyHostToDevice, stream));
+    int* rect_d = alloc<int>(rect.size());
+    NFVM_CK(hipMemcpyAsync(rect_d, rect.data(), rect.size() * sizeof(int), hipMemcpyHostToDevice,
+                           stream));
+    uint8_t* solid_d = nullptr;
+    if (d.solid_mask) {
+      solid_d = alloc<uint8_t>((size_t)ncells);
+      NFVM_CK(hipMemcpyAsync(solid_d, d.solid_mask, (size_t)ncells, hipMemcpyHostToDevice,
+                             stream));
+    }
+    type = alloc<uint8_t>(g.total);
+    launch_classify(g, solid_d, rect_d, d.n_patches, patches, d.nu, ph.komega, type, stream);
+    if (ph.komega) launch_fix_omega(g, patches, type, stream);
+
+    for (int f = 0; f < 3; ++f)
+      for (int c = 0; c < 2; ++c) {
+        vel[f][c] = alloc<V>(g.total);
+        sca[f][c] = alloc<F>(g.total);
+      }
+    p = alloc<P>(g.total);
+    stage = alloc<double>((size_t)ncells);
+
+    // multigrid hierarchy
+    lv.resize(L);
+    const size_t s0 = sizeof(S0), sc = sizeof(SC);
+    for (int l = 0; l < L; ++l) {
+      Level& v = lv[l];
+      v.g = level_geom(d, l);
+      v.cls = alloc<uint8_t>(v.g.total);
+      for (int a = 0; a < 3; ++a) v.cf[a] = a < d.dim ? alloc<float>(v.g.total) : nullptr;
+      const size_t es = l == 0 ? s0 : sc;
+      for (int c = 0; c < 2; ++c) v.x[c] = alloc<uint8_t>(v.g.total * es);
+      v.b = alloc<uint8_t>(v.g.total * es);
+      v.cur = 0;
+      if (l == 0)
+        launch_level0(v.g, type, patches, v.cls, v.cf[0], v.cf[1], d.dim == 3 ? v.cf[2] : v.cf[0],
+                      stream);
+      else
+        launch_coarsen(lv[l - 1].g, lv[l - 1].cls, lv[l - 1].cf, v.g, v.cls, v.cf, stream);
+    }
+    cmap = alloc<int>(COARSE_MAX);
+    ncount = alloc<int>(1);
+    work = alloc<double>((size_t)2 * COARSE_MAX * COARSE_MAX);
+    launch_coarse_factor(lv[L - 1].g, lv[L - 1].cls, lv[L - 1].cf, cmap, ncount, work, COARSE_MAX,
+                         stream);
+    NFVM_CK(hipGetLastError());
+    int nc = 0;
+    NFVM_CK(hipMemcpyAsync(&nc, ncount, sizeof(int), hipMemcpyDeviceToHost, stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+    if (nc > COARSE_MAX)
+      throw Error{NFVM_E_INVAL, "coarsest level has " + std::to_string(nc) +
+                                    " fluid cells; at most 512 (add levels)"};
+
+    bvec = alloc<O>(g.total);
+    phi = alloc<O>(g.total);
+    r = alloc<O>(g.total);
+    pv[0] = alloc<O>(g.total);
+    pv[1] = alloc<O>(g.total);
+    q = alloc<O>(g.total);
+    x0 = alloc<O>(g.total);
+    red.max_blocks = max_blocks_of(g);
+    red.partial = alloc<double>((size_t)red.max_blocks * 3);
+    red.counter = alloc<unsigned>(16);
+    red.out = alloc<double>(S_COUNT);
+
+    if (init) set_fields(init);
+    NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  // ---- fields -------------------------------------------------------------------
+  V* vcur(int f) { return vel[f][fcur[f]]; }
+  V* valt(int f) { return vel[f][fcur[f] ^ 1]; }
+  F* scur(int f) { return sca[f - 3][fcur[f]]; }
+  F* salt(int f) { return sca[f - 3][fcur[f] ^ 1]; }
+
+  void set_fields(const nfvm_fields* in) override {
+    const double* src[7] = {in->u, in->v, in->w, in->T, in->k, in->omega, in->p};
+    for (int f = 0; f < 7; ++f)
+      if (!src[f]) throw Error{NFVM_E_INVAL, "all seven field pointers are required"};
+    const size_t bytes = (size_t)ncells * sizeof(double);
+    for (int f = 0; f < 6; ++f) {
+      NFVM_CK(hipMemcpyAsync(stage, src[f], bytes, hipMemcpyHostToDevice, stream));
+      if (f < 3)
+        launch_pack<V>(g, stage, vcur(f), 0.0, stream);
+      else
+        launch_pack<F>(g, stage, scur(f), f == 3 ? ph.T_ref : 0.0, stream);
+      NFVM_CK(hipStreamSynchronize(stream));
+    }
+    NFVM_CK(hipMemcpyAsync(stage, src[6], bytes, hipMemcpyHostToDevice, stream));
+    launch_pack<P>(g, stage, p, 0.0, stream);
+    if (ph.komega) launch_set_omega_wall<F>(g, ph, patches, type, scur(5), stream);
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  void get_fields(nfvm_fields* out) override {
+    double* dst[7] = {out->u, out->v, out->w, out->T, out->k, out->omega, out->p};
+    for (int f = 0; f < 7; ++f)
+      if (!dst[f]) throw Error{NFVM_E_INVAL, "all seven field pointers are required"};
+    const size_t bytes = (size_t)ncells * sizeof(double);
+    for (int f = 0; f < 7; ++f) {
+      if (f < 3)
+        launch_unpack<V>(g, vcur(f), stage, 0.0, stream);
+      else if (f < 6)
+        launch_unpack<F>(g, scur(f), stage, f == 3 ? ph.T_ref : 0.0, stream);
+      else
+        launch_unpack<P>(g, p, stage, 0.0, stream);
+      NFVM_CK(hipMemcpyAsync(dst[f], stage, bytes, hipMemcpyDeviceToHost, stream));
+      NFVM_CK(hipStreamSynchronize(stream));
+    }
+  }
+
+  // ---- multigrid ------------------------------------------------------------------
+  void smooth(int l, bool zero) {
+    Level& v = lv[l];
+    const void* xin = zero ? nullptr : v.x[v.cur];
+    void* xout = zero ? v.x[0] : v.x[v.cur ^ 1];
+    const int kid = zero ? NFVM_K_SMOOTH0_ZERO : NFVM_K_SMOOTH0;
+    if (l == 0) {
+      prof_begin(kid);
+      launch_smooth<S0, C>(v, xin, xout, wj, zero, stream);
+      prof_end(kid);
+    } else {
+      launch_smooth<SC, C>(v, xin, xout, wj, zero, stream);
+    }
+    v.cur = zero ? 0 : (v.cur ^ 1);
+  }
+
+  void vcycle(int l) {
+    Level& v = lv[l];
+    if (l == L - 1) {
+      v.cur = 0;
+      if (l == 0)
+        launch_coarse_solve<S0, C>(v, cmap, ncount, work, COARSE_MAX, stream);
+      else
+        launch_coarse_solve<SC, C>(v, cmap, ncount, work, COARSE_MAX, stream);
+      return;
+    }
+    if (nu1 > 0) {
+      smooth(l, true);
+      for (int s = 1; s < nu1; ++s) smooth(l, false);
+    } else {
+      v.cur = 0;
+      if (l == 0)
+        launch_fill_zero<S0>(v, v.x[0], stream);
+      else
+        launch_fill_zero<SC>(v, v.x[0], stream);
+    }
+    if (l == 0) {
+      prof_begin(NFVM_K_RESTRICT0);
+      launch_resid_restrict<S0, C, SC>(lv[0], lv[1], stream);
+      prof_end(NFVM_K_RESTRICT0);
+    } else
+      launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], stream);
+    vcycle(l + 1);
+    if (l == 0) {
+      prof_begin(NFVM_K_PROLONG0);
+      launch_prolong<S0, C, SC>(lv[0], lv[1], stream);
+      prof_end(NFVM_K_PROLONG0);
+    } else
+      launch_prolong<SC, C, SC>(lv[l], lv[l + 1], stream);
+    for (int s = 0; s < nu2; ++s) smooth(l, false);
+  }
+
+  double read_scalar(int slot) {
+    NFVM_CK(hipMemcpyAsync(hs + slot, red.out + slot, sizeof(double), hipMemcpyDeviceToHost,
+                           stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+    return hs[slot];
+  }
+
+  // Flexible CG preconditioned by one V-cycle; b in bvec, result in phi.
+  nfvm_status solve(bool have_x0, double tol_, int maxc, int forced, int* cycles, double* rel) {
+    launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, have_x0, stream);
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipMemcpyAsync(hs, red.out, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+    const double bn = sqrt(hs[S_BB]);
+    double rn = sqrt(hs[S_RR]);
+    int it = 0;
+    nfvm_status st = NFVM_OK;
+    for (;;) {
+      *rel = bn > 0 ? rn / bn : 0.0;
+      if (!isfinite(rn)) { st = NFVM_E_DIVERGED; break; }
+      if (forced >= 0) {
+        if (it >= forced) break;
+      } else {
+        if (bn == 0.0 || rn <= tol_ * bn) break;
+        if (it >= maxc) { st = NFVM_E_NOTCONV; break; }
+      }
+      const int par = it & 1;
+      vcycle(0);
+      prof_begin(NFVM_K_FCG_DOTS);
+      launch_fcg_dots<O, S0>(lv[0], r, q, red, stream);
+      prof_end(NFVM_K_FCG_DOTS);
+      prof_begin(NFVM_K_FCG_DIR);
+      launch_fcg_dir<O, S0>(lv[0], pv[par ^ 1], pv[par], q, red, it == 0, par, stream);
+      prof_end(NFVM_K_FCG_DIR);
+      prof_begin(NFVM_K_FCG_UPDATE);
+      launch_fcg_update<O, S0>(lv[0], phi, r, pv[par], q, red, par, stream);
+      prof_end(NFVM_K_FCG_UPDATE);
+      NFVM_CK(hipGetLastError());
+      rn = sqrt(read_scalar(S_RR));
+      ++it;
+    }
+    *cycles = it;
+    return st;
+  }
+
+  void mg_solve(const double* b_dev, double* x_dev, double tol_, int maxc, int forced,
+                nfvm_step_stats* stt, nfvm_status* status) override {
+    NFVM_CK(hipEventRecord(ev0, stream));
+    launch_pack<O>(g, b_dev, bvec, 0.0, stream);
+    launch_pack<O>(g, x_dev, x0, 0.0, stream);
+    int cyc = 0;
+    double rel = 0;
+    nfvm_status st = solve(true, tol_, maxc, forced, &cyc, &rel);
+    launch_unpack<O>(g, phi, x_dev, 0.0, stream);
+    NFVM_CK(hipEventRecord(ev1, stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+    prof_collect();
+    float ms = 0;
+    NFVM_CK(hipEventElapsedTime(&ms, ev0, ev1));
+    if (stt) {
+      memset(stt, 0, sizeof *stt);
+      stt->cycles = cyc;
+      stt->status = st;
+      stt->rel_residual = rel;
+      stt->seconds = ms * 1e-3;
+      stt->min_k = stt->min_omega = NAN;
+    }
+    *status = st;
+  }
+
+  void swap(int f) { fcur[f] ^= 1; }
+
+  void step(int n, nfvm_step_stats* stt, nfvm_status* status) override {
+    nfvm_status worst = NFVM_OK;
+    for (int s = 0; s < n; ++s) {
+      NFVM_CK(hipEventRecord(ev0, stream));
+      const double half = 0.5 * ph.dt;
+      if (ph.komega) {
+        prof_begin(NFVM_K_DESTROY);
+        launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
+                             half, salt(4), salt(5), nullptr, stream);
+        prof_end(NFVM_K_DESTROY);
+        swap(4);
+        swap(5);
+      }
+      FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
+      FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
+      prof_begin(NFVM_K_EXPLICIT);
+      launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, stream);
+      prof_end(NFVM_K_EXPLICIT);
+      for (int f = 0; f < 6; ++f) swap(f);
+      prof_begin(NFVM_K_RHS);
+      launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red, stream);
+      prof_end(NFVM_K_RHS);
+      NFVM_CK(hipGetLastError());
+      int cyc = 0;
+      double rel = 0;
+      nfvm_status st = solve(false, tol, max_cycles, -1, &cyc, &rel);
+      if (st == NFVM_E_DIVERGED) {
+        if (stt) {
+          memset(&stt[s], 0, sizeof stt[s]);
+          stt[s].status = st;
+          stt[s].cycles = cyc;
+          stt[s].rel_residual = rel;
+        }
+        *status = st;
+        return;
+      }
+      prof_begin(NFVM_K_PROJECT);
+      launch_project<V, P, O>(g, ph, type, patches, phi, vcur(0), vcur(1), vcur(2), p, red,
+                              stream);
+      prof_end(NFVM_K_PROJECT);
+      if (ph.komega) {
+        prof_begin(NFVM_K_DESTROY);
+        launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
+                             half, salt(4), salt(5), &red, stream);
+        prof_end(NFVM_K_DESTROY);
+        swap(4);
+        swap(5);
+      }
+      NFVM_CK(hipGetLastError());
+      NFVM_CK(hipEventRecord(ev1, stream));
+      NFVM_CK(hipMemcpyAsync(hs, red.out, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                             stream));
+      NFVM_CK(hipStreamSynchronize(stream));
+      prof_collect();
+      float ms = 0;
+      NFVM_CK(hipEventElapsedTime(&ms, ev0, ev1));
+      if (!isfinite(hs[S_DIV])) st = NFVM_E_DIVERGED;
+      if (stt) {
+        stt[s].cycles = cyc;
+        stt[s].status = st;
+        stt[s].rel_residual = rel;
+        stt[s].max_face_div = hs[S_DIV];
+        stt[s].min_k = ph.komega ? hs[S_MINK] : NAN;
+        stt[s].min_omega = ph.komega ? hs[S_MINW] : NAN;
+        stt[s].seconds = ms * 1e-3;
+      }
+      if (st == NFVM_E_DIVERGED) {
+        *status = st;
+        return;
+      }
+      if (st != NFVM_OK && worst == NFVM_OK) worst = st;
+    }
+    *status = worst;
+  }
+};
+
+// <velocity, scalars, pressure, outer solve, level-0 storage, coarse storage, V-cycle arithmetic>
+typedef GridT<double, double, double, double, double, double, double> GridFP64;
+typedef GridT<float, float, float, float, float, float, float> GridFP32;
+typedef GridT<double, float, double, double, float, bf16, float> GridMixed;
+
+std::unique_ptr<GridBase> make_grid(const nfvm_grid_desc& d, const nfvm_fields* init,
+                                    hipStream_t stream) {
+  validate_desc(d);
+  std::unique_ptr<GridBase> gb;
+  if (d.precision == NFVM_FP64)
+    gb.reset(new GridFP64());
+  else if (d.precision == NFVM_FP32)
+    gb.reset(new GridFP32());
+  else
+    gb.reset(new GridMixed());
+  if (stream) {
+    gb->stream = stream;
+  } else {
+    NFVM_CK(hipStreamCreateWithFlags(&gb->stream, hipStreamNonBlocking));
+    gb->own_stream = true;
+  }
+  if (d.precision == NFVM_FP64)
+    static_cast<GridFP64*>(gb.get())->init(d, init);
+  else if (d.precision == NFVM_FP32)
+    static_cast<GridFP32*>(gb.get())->init(d, init);
+  else
+    static_cast<GridMixed*>(gb.get())->init(d, init);
+  return gb;
+}
+
+}  // namespace nfvm

@@ -1,0 +1,104 @@
+// Host engine: one grid on the device and the orchestration of a time step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/nfvm.h"
+#include "nfvm_internal.hpp"
+
+namespace nfvm {
+
+// thrown inside the library only; converted to nfvm_status at the C ABI
+struct Error {
+  nfvm_status st;
+  std::string msg;
+};
+
+void set_error(const std::string& m);
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
+#define NFVM_CK(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::nfvm::Error{NFVM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+// Owned device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) dev_free(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t n, hipStream_t s) {
+    release();
+    bytes = n;
+    p = dev_alloc(n ? n : 16);
+    if (!p) throw Error{NFVM_E_NOMEM, "device allocation of " + std::to_string(n) + " bytes failed"};
+    NFVM_CK(hipMemsetAsync(p, 0, n ? n : 16, s));
+  }
+  template <class T>
+  T* as() const {
+    return (T*)p;
+  }
+};
+
+size_t footprint_bytes(const nfvm_grid_desc& d);
+void validate_desc(const nfvm_grid_desc& d);
+
+class GridBase {
+ public:
+  virtual ~GridBase() = default;
+  virtual void step(int n, nfvm_step_stats* st, nfvm_status* status) = 0;
+  virtual void mg_solve(const double* b_dev, double* x_dev, double tol, int max_cycles, int forced,
+                        nfvm_step_stats* st, nfvm_status* status) = 0;
+  virtual void get_fields(nfvm_fields* out) = 0;
+  virtual void set_fields(const nfvm_fields* in) = 0;
+  // kernel timing (nfvm_profile)
+  struct ProfRec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  uint32_t prof_mask = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<ProfRec> prof_pending;
+  long long prof_launches[NFVM_K_COUNT] = {};
+  double prof_seconds[NFVM_K_COUNT] = {};
+  double prof_bytes[NFVM_K_COUNT] = {};
+  int prof_open = -1;
+  hipEvent_t next_event();
+  void prof_begin(int kid);
+  void prof_end(int kid);
+  void prof_collect();  // after a stream synchronisation
+  void prof_reset(uint32_t mask);
+  void prof_release();
+
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  long long ncells = 0;
+  nfvm_grid_desc desc{};
+  double tol = 1e-6;
+  int max_cycles = 100;
+};
+
+std::unique_ptr<GridBase> make_grid(const nfvm_grid_desc& d, const nfvm_fields* init,
+                                    hipStream_t stream);
+
+}  // namespace nfvm
+
+struct nfvm_grid {
+  std::unique_ptr<nfvm::GridBase> g;
+};

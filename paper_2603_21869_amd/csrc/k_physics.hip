@@ -1,0 +1,425 @@
+// Physics kernels of one time step: semi-implicit k-omega destruction
+// (Sec. 2.5, Algorithm 3), the explicit finite-volume update of the rest terms
+// (Sec. 2.3, Algorithms 2 and 4, eqs. ko_mom to ko_temp), the Poisson
+// right-hand side (eq. pc_residual) and the projection (Sec. 2.4).
+//
+// Layout: one thread per cell, 64 x 4 cells per workgroup (x fastest, so a
+// wavefront reads 64 consecutive values of a row), one z plane per grid
+// slice.  Face neighbours come from the padded arrays; a non-fluid neighbour
+// is replaced by the ghost value of its boundary patch.
+#include <hip/hip_runtime.h>
+
+#include "nfvm_device.hpp"
+
+namespace nfvm {
+
+constexpr int BX = 64, BY = 4, BS = BX * BY;
+
+__host__ inline dim3 cell_grid(const Geom& g) {
+  return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz);
+}
+
+// ---- dense <-> padded copies ------------------------------------------------
+// padded = dense - offset (rounded to F) and back
+template <class F>
+__global__ void k_pack(Geom g, const double* __restrict__ d, F* __restrict__ p, double off) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  p[g.idx(i, j, k)] = (F)(d[((size_t)k * g.ny + j) * g.nx + i] - off);
+}
+template <class F>
+__global__ void k_unpack(Geom g, const F* __restrict__ p, double* __restrict__ d, double off) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  d[((size_t)k * g.ny + j) * g.nx + i] = (double)p[g.idx(i, j, k)] + off;
+}
+template <class F>
+void launch_pack(const Geom& g, const double* dense, F* padded, double off, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack<F>, cell_grid(g), dim3(BX, BY), 0, s, g, dense, padded, off);
+}
+template <class F>
+void launch_unpack(const Geom& g, const F* padded, double* dense, double off, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpack<F>, cell_grid(g), dim3(BX, BY), 0, s, g, padded, dense, off);
+}
+template void launch_pack<double>(const Geom&, const double*, double*, double, hipStream_t);
+template void launch_pack<float>(const Geom&, const double*, float*, double, hipStream_t);
+template void launch_unpack<double>(const Geom&, const double*, double*, double, hipStream_t);
+template void launch_unpack<float>(const Geom&, const float*, double*, double, hipStream_t);
+
+// ---- semi-implicit destruction ---------------------------------------------
+// k_new = k / (1 + tau beta* f_beta* omega), omega_new = omega / (1 + tau beta
+// f_beta omega) with cell-centred central gradients (face derivative D, then
+// average L) feeding chi_k and chi_omega; every right-hand side uses the
+// input k and omega.  Fixed wall cells keep omega.
+template <class V, class F, bool RED>
+__global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* __restrict__ type,
+                                                const DevPatch* __restrict__ pt,
+                                                const V* __restrict__ u, const V* __restrict__ v,
+                                                const V* __restrict__ w, const F* __restrict__ kk,
+                                                const F* __restrict__ om, V tau,
+                                                F* __restrict__ k_out, F* __restrict__ om_out,
+                                                RedBuf red) {
+  typedef V R;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  const bool in = i < g.nx && j < g.ny;
+  double mk = INFINITY, mw = INFINITY;
+  if (in) {
+    const int P = g.idx(i, j, k);
+    const uint8_t tp = type[P];
+    const R kP = kk[P], wP = om[P];
+    R kn = kP, wn = wP;
+    if (is_fluid(tp)) {
+      const R vel[3] = {u[P], v[P], w[P]};
+      R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      R gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+      const int st[3] = {1, g.sx, g.sxy};
+      const R ih2[3] = {(R)(0.5 / g.hx), (R)(0.5 / g.hy), (R)(0.5 / g.hz)};
+      for (int d = 0; d < g.dim; ++d)
+        for (int s = -1; s <= 1; s += 2) {
+          const int N = P + s * st[d];
+          const uint8_t tn = type[N];
+          R vn[3], kn_, wn_;
+          if (is_fluid(tn)) {
+            vn[0] = u[N];
+            vn[1] = v[N];
+            vn[2] = w[N];
+            kn_ = kk[N];
+            wn_ = om[N];
+          } else {
+            const DevPatch& pp = pt[tn & 0x7f];
+            for (int a = 0; a < 3; ++a) vn[a] = ghost<R>(pp, G_U + a, vel[a], ph.komega);
+            kn_ = ghost<R>(pp, G_K, kP, ph.komega);
+            wn_ = ghost<R>(pp, G_OM, wP, ph.komega);
+          }
+          const R sc = (R)s * ih2[d];
+          for (int a = 0; a < g.dim; ++a) G[a][d] += sc * vn[a];
+          gk[d] += sc * kn_;
+          gw[d] += sc * wn_;
+        }
+      const R oh = omhat(wP);
+      const R dkdw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
+      const R chik = dkdw / (oh * oh * oh);
+      const R fbs = chik <= (R)0 ? (R)1
+                                 : ((R)1 + (R)680 * chik * chik) / ((R)1 + (R)400 * chik * chik);
+      const R ret = kP / ((R)ph.nu * oh);
+      const R x = ret * (R)(1.0 / C_R_BETA);
+      const R x2 = x * x;
+      const R x4 = x2 * x2;
+      // 0.09 (4/15 + x^4)/(1 + x^4), written so that x^4 = inf gives 0.09
+      const R bst = (R)C_BSTAR * ((R)1 - (R)(11.0 / 15.0) / ((R)1 + x4));
+      kn = kP / ((R)1 + tau * bst * fbs * wP);
+      if (!(tp & FIXED_BIT)) {
+        R S[3][3], W[3][3];
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            S[a][b] = (R)0.5 * (G[a][b] + G[b][a]);
+            W[a][b] = (R)0.5 * (G[a][b] - G[b][a]);
+          }
+        R X = 0;
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b)
+            for (int e = 0; e < 3; ++e) X += W[a][b] * W[b][e] * S[e][a];
+        const R den = (R)C_BSTAR * oh;
+        const R chiw = fabs(X) / (den * den * den);
+        const R fb = ((R)1 + (R)70 * chiw) / ((R)1 + (R)80 * chiw);
+        wn = wP / ((R)1 + tau * (R)C_BETA_I * fb * wP);
+      }
+      mk = (double)kn;
+      mw = (double)wn;
+    }
+    k_out[P] = (F)kn;
+    om_out[P] = (F)wn;
+  }
+  if (RED) {
+    double vv[2] = {mk, mw};
+    block_partial<2, R_MIN, BS>(vv, red);
+  }
+}
+
+template <class V, class F>
+void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                    const V* u, const V* v, const V* w, const F* k, const F* om, double tau,
+                    F* k_out, F* om_out, const RedBuf* red, hipStream_t s) {
+  if (red) {
+    hipLaunchKernelGGL((k_destroy<V, F, true>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt,
+                       u, v, w, k, om, (V)tau, k_out, om_out, *red);
+    const dim3 gr = cell_grid(g);
+    launch_finalize(2, R_MIN, *red, gr.x * gr.y * gr.z, S_MINK, S_MINW, s);
+  } else
+    hipLaunchKernelGGL((k_destroy<V, F, false>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type,
+                       pt, u, v, w, k, om, (V)tau, k_out, om_out, RedBuf{});
+}
+#define INST_DESTROY(V, F)                                                                      \
+  template void launch_destroy<V, F>(const Geom&, const Phys&, const uint8_t*, const DevPatch*, \
+                                     const V*, const V*, const V*, const F*, const F*, double,  \
+                                     F*, F*, const RedBuf*, hipStream_t);
+INST_DESTROY(double, double)
+INST_DESTROY(float, float)
+INST_DESTROY(double, float)
+
+// ---- explicit step of the rest terms -----------------------------------------
+// For each transported field phi: face flux F = -U_f phi_up + Gamma_f D(phi)
+// (upwind value from the lower cell when U_f >= 0), with -(p + 2/3 k)_f on the
+// faces normal to a momentum component; RHS = sum_d (F_+ - F_-)/h_d plus
+// sources (buoyancy, G_k = nu_t S^2, G_omega = alpha_inf (alpha_0 +
+// Re_t/R_w)/(1 + Re_t/R_w) S^2); one forward-Euler step; k, omega >= eps.
+template <class V, class F, class P>
+__global__ __launch_bounds__(BS) void k_explicit(Geom g, Phys ph, const uint8_t* __restrict__ type,
+                                                 const DevPatch* __restrict__ pt,
+                                                 FieldSet<V, F> in, const P* __restrict__ p,
+                                                 FieldSet<V, F> out) {
+  typedef V R;
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int C0 = g.idx(i, j, k);
+  const uint8_t tp = type[C0];
+  // field order: u v w T k omega
+  const V* vin[3] = {in.u, in.v, in.w};
+  const F* sin_[3] = {in.T, in.k, in.om};
+  R vP[6];
+  for (int f = 0; f < 3; ++f) vP[f] = (R)vin[f][C0];
+  for (int f = 0; f < 3; ++f) vP[3 + f] = (R)sin_[f][C0];
+  if (!is_fluid(tp)) {
+    out.u[C0] = in.u[C0];
+    out.v[C0] = in.v[C0];
+    out.w[C0] = in.w[C0];
+    out.T[C0] = in.T[C0];
+    out.k[C0] = in.k[C0];
+    out.om[C0] = in.om[C0];
+    return;
+  }
+  const R nu = (R)ph.nu;
+  const int komega = ph.komega;
+  const R pP = (R)p[C0];
+  const R nutP = komega ? eddy_visc<R>(nu, vP[4], vP[5]) : (R)0;
+  const R gam0[6] = {nu, nu, nu, (R)ph.alpha_T, nu, nu};
+  const R isig[6] = {(R)1, (R)1, (R)1, (R)ph.inv_Pr_t, (R)ph.inv_sigma_k, (R)ph.inv_sigma_w};
+  const int st[3] = {1, g.sx, g.sxy};
+  const R ih[3] = {(R)(1.0 / g.hx), (R)(1.0 / g.hy), (R)(1.0 / g.hz)};
+  R rhs[6] = {0, 0, 0, 0, 0, 0};
+  R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  R divU = 0;
+  for (int d = 0; d < g.dim; ++d)
+    for (int s = -1; s <= 1; s += 2) {
+      const int N = C0 + s * st[d];
+      const uint8_t tn = type[N];
+      R vN[6], pN, nutN;
+      if (is_fluid(tn)) {
+        for (int f = 0; f < 3; ++f) vN[f] = (R)vin[f][N];
+        for (int f = 0; f < 3; ++f) vN[3 + f] = (R)sin_[f][N];
+        pN = (R)p[N];
+        nutN = komega ? eddy_visc<R>(nu, vN[4], vN[5]) : (R)0;
+      } else {
+        const DevPatch& pp = pt[tn & 0x7f];
+        for (int a = 0; a < 3; ++a) vN[a] = ghost<R>(pp, G_U + a, vP[a], komega);
+        vN[3] = ghost<R>(pp, G_T, vP[3], komega);
+        vN[4] = ghost<R>(pp, G_K, vP[4], komega);
+        vN[5] = ghost<R>(pp, G_OM, vP[5], komega);
+        pN = ghost<R>(pp, G_P, pP, komega);
+        nutN = ghost<R>(pp, G_NUT, nutP, komega);
+      }
+      const R Uf = (R)0.5 * (vP[d] + vN[d]);
+      const R nutf = (R)0.5 * (nutP + nutN);
+      const R sc = (R)s * ih[d];
+      divU += sc * Uf;
+      const R hg = (R)s * (R)0.5 * ih[d];
+      for (int a = 0; a < g.dim; ++a) G[a][d] += hg * vN[a];
+      for (int f = 0; f < 6; ++f) {
+        const R lower = s < 0 ? vN[f] : vP[f];
+        const R upper = s < 0 ? vP[f] : vN[f];
+        const R up = Uf >= (R)0 ? lower : upper;
+        const R gam = gam0[f] + nutf * isig[f];
+        R Ff = -Uf * up + gam * (upper - lower) * ih[d];
+        if (f == d) {
+          const R pf = (R)0.5 * (pP + pN);
+          const R kf = komega ? (R)0.5 * (vP[4] + vN[4]) : (R)0;
+          Ff -= pf + (R)(2.0 / 3.0) * kf;
+        }
+        rhs[f] += sc * Ff;
+      }
+    }
+  const R dt = (R)ph.dt;
+  // temperature is stored as theta = T - T_ref: the convective flux of the
+  // constant T_ref adds -T_ref div(U_f), which keeps the update identical to
+  // the one of T itself
+  rhs[3] -= (R)ph.T_ref * divU;
+  R o[6];
+  for (int a = 0; a < 3; ++a) {
+    R src = 0;
+    if (ph.buoyancy) src = -(R)ph.beta_T * vP[3] * (R)ph.g[a];
+    o[a] = a < g.dim ? vP[a] + dt * (rhs[a] + src) : vP[a];
+  }
+  o[3] = ph.energy ? vP[3] + dt * rhs[3] : vP[3];
+  o[4] = vP[4];
+  o[5] = vP[5];
+  if (komega) {
+    R S2 = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const R sab = (R)0.5 * (G[a][b] + G[b][a]);
+        S2 += sab * sab;
+      }
+    S2 *= (R)2;
+    const R ret = vP[4] / (nu * omhat(vP[5]));
+    const R xr = ret * (R)(1.0 / C_R_W);
+    const R Gk = nutP * S2;
+    const R Gw = (R)C_A_INF * ((R)C_A0 + xr) / ((R)1 + xr) * S2;
+    const R kn = vP[4] + dt * (rhs[4] + Gk);
+    o[4] = kn > (R)C_EPS ? kn : (R)C_EPS;
+    if (!(tp & FIXED_BIT)) {
+      const R wn = vP[5] + dt * (rhs[5] + Gw);
+      o[5] = wn > (R)C_EPS ? wn : (R)C_EPS;
+    }
+  }
+  out.u[C0] = (V)o[0];
+  out.v[C0] = (V)o[1];
+  out.w[C0] = (V)o[2];
+  out.T[C0] = (F)o[3];
+  out.k[C0] = (F)o[4];
+  out.om[C0] = (F)o[5];
+}
+
+template <class V, class F, class P>
+void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, hipStream_t s) {
+  hipLaunchKernelGGL((k_explicit<V, F, P>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, in,
+                     p, out);
+}
+#define INST_EXPLICIT(V, F, P)                                                                 \
+  template void launch_explicit<V, F, P>(const Geom&, const Phys&, const uint8_t*,             \
+                                         const DevPatch*, FieldSet<V, F>, const P*,            \
+                                         FieldSet<V, F>, hipStream_t);
+INST_EXPLICIT(double, double, double)
+INST_EXPLICIT(float, float, float)
+INST_EXPLICIT(double, float, double)
+
+// ---- Poisson right-hand side: b = -(1/dt) sum_d D_d L_d BC_d(u*_d) ------------
+template <class F, class O>
+__global__ __launch_bounds__(BS) void k_rhs_b(Geom g, Phys ph, const uint8_t* __restrict__ type,
+                                              const DevPatch* __restrict__ pt,
+                                              const F* __restrict__ u, const F* __restrict__ v,
+                                              const F* __restrict__ w, O* __restrict__ b,
+                                              RedBuf red) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double acc = 0.0;
+  if (i < g.nx && j < g.ny) {
+    const int C0 = g.idx(i, j, k);
+    const uint8_t tp = type[C0];
+    O bv = 0;
+    if (is_fluid(tp)) {
+      const F* vel[3] = {u, v, w};
+      const int st[3] = {1, g.sx, g.sxy};
+      const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
+      O div = 0;
+      for (int d = 0; d < g.dim; ++d) {
+        const O vp = (O)vel[d][C0];
+        O fl[2];
+        for (int s = -1; s <= 1; s += 2) {
+          const int N = C0 + s * st[d];
+          const uint8_t tn = type[N];
+          const O vn = is_fluid(tn) ? (O)vel[d][N] : ghost<O>(pt[tn & 0x7f], G_U + d, vp, ph.komega);
+          fl[s > 0] = (O)0.5 * (vp + vn);
+        }
+        div += (fl[1] - fl[0]) * ih[d];
+      }
+      bv = -div / (O)ph.dt;
+    }
+    b[C0] = bv;
+    acc = (double)bv * (double)bv;
+  }
+  double vv[1] = {acc};
+  block_partial<1, R_SUM, BS>(vv, red);
+}
+
+template <class F, class O>
+void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                  const F* u, const F* v, const F* w, O* b, const RedBuf& red, hipStream_t s) {
+  hipLaunchKernelGGL((k_rhs_b<F, O>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, u, v, w,
+                     b, red);
+  const dim3 gr = cell_grid(g);
+  launch_finalize(1, R_SUM, red, gr.x * gr.y * gr.z, S_BB, S_BB, s);
+}
+template void launch_rhs_b<double, double>(const Geom&, const Phys&, const uint8_t*,
+                                           const DevPatch*, const double*, const double*,
+                                           const double*, double*, const RedBuf&, hipStream_t);
+template void launch_rhs_b<float, float>(const Geom&, const Phys&, const uint8_t*,
+                                         const DevPatch*, const float*, const float*, const float*,
+                                         float*, const RedBuf&, hipStream_t);
+
+
+// ---- projection ----------------------------------------------------------------
+// p += phi; u_d = u*_d - dt (phi_E - phi_W)/(2 h_d) with pressure ghosts;
+// corrected face fluxes F = L(u*) - dt c_f D(phi) give the cell divergence
+// (max reduced into S_DIV).  Arithmetic in the outer precision O.
+template <class F, class P, class O>
+__global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* __restrict__ type,
+                                                const DevPatch* __restrict__ pt,
+                                                const O* __restrict__ phi, F* __restrict__ u,
+                                                F* __restrict__ v, F* __restrict__ w,
+                                                P* __restrict__ p, RedBuf red) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  double mdiv = 0.0;
+  if (i < g.nx && j < g.ny) {
+    const int C0 = g.idx(i, j, k);
+    const uint8_t tp = type[C0];
+    if (is_fluid(tp)) {
+      F* vel[3] = {u, v, w};
+      const int st[3] = {1, g.sx, g.sxy};
+      const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
+      const O dt = (O)ph.dt;
+      const O fP = phi[C0];
+      O div = 0;
+      O unew[3];
+      for (int d = 0; d < g.dim; ++d) {
+        const O vp = (O)vel[d][C0];
+        O grad = 0;
+        O fl[2];
+        for (int s = -1; s <= 1; s += 2) {
+          const int N = C0 + s * st[d];
+          const uint8_t tn = type[N];
+          O vn, fN_ghost, fN_face, c;
+          if (is_fluid(tn)) {
+            vn = (O)vel[d][N];
+            fN_ghost = phi[N];
+            fN_face = fN_ghost;
+            c = 1;
+          } else {
+            const DevPatch& pp = pt[tn & 0x7f];
+            vn = ghost<O>(pp, G_U + d, vp, ph.komega);
+            fN_ghost = ghost<O>(pp, G_P, fP, ph.komega);
+            c = pp.kind == K_OUTLET ? (O)2 : (O)0;
+            fN_face = 0;
+          }
+          grad += (O)s * fN_ghost;
+          const O dphi = s > 0 ? (fN_face - fP) : (fP - fN_face);
+          fl[s > 0] = (O)0.5 * (vp + vn) - dt * c * dphi * ih[d];
+        }
+        unew[d] = vp - dt * grad * (O)0.5 * ih[d];
+        div += (fl[1] - fl[0]) * ih[d];
+      }
+      for (int d = 0; d < g.dim; ++d) vel[d][C0] = (F)unew[d];
+      p[C0] = (P)((O)p[C0] + fP);
+      mdiv = fabs((double)div);
+    }
+  }
+  double vv[1] = {mdiv};
+  block_partial<1, R_MAX, BS>(vv, red);
+}
+
+template <class F, class P, class O>
+void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                    const O* phi, F* u, F* v, F* w, P* p, const RedBuf& red, hipStream_t s) {
+  hipLaunchKernelGGL((k_project<F, P, O>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
+                     u, v, w, p, red);
+  const dim3 gr = cell_grid(g);
+  launch_finalize(1, R_MAX, red, gr.x * gr.y * gr.z, S_DIV, S_DIV, s);
+}
+template void launch_project<double, double, double>(const Geom&, const Phys&, const uint8_t*,
+                                                     const DevPatch*, const double*, double*,
+                                                     double*, double*, double*, const RedBuf&,
+                                                     hipStream_t);
+template void launch_project<float, float, float>(const Geom&, const Phys&, const uint8_t*,
+                                                  const DevPatch*, const float*, float*, float*,
+                                                  float*, float*, const RedBuf&, hipStream_t);
+
+}  // namespace nfvm

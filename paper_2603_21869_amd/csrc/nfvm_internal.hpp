@@ -1,0 +1,169 @@
+// Internal types of the NeuralFVM HIP library: padded device layout, patch
+// table, physics parameters and the launchers every kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nfvm {
+
+// Cell type byte of the fine grid (interior and ghost cells):
+//   low 7 bits: patch id (0 fluid, 1 solid block, 2..7 default wall of face
+//   0..5, 8.. user patches in descriptor order); bit 7: fluid cell whose
+//   omega is held at the wall value (Sec. 2.7).
+constexpr int MAX_PATCHES = 128;
+constexpr int PID_FLUID = 0;
+constexpr int PID_SOLID = 1;
+constexpr int PID_DEFWALL = 2;
+constexpr int PID_USER = 8;
+constexpr uint8_t FIXED_BIT = 0x80;
+
+enum { K_WALL = 0, K_INLET = 1, K_OUTLET = 2 };
+
+// Multigrid cell class per level: 0 inactive (all children solid),
+// 1 regular (active, all faces coefficient 1), 2 irregular (read the face
+// coefficient arrays).
+enum { MG_INACTIVE = 0, MG_REGULAR = 1, MG_IRREGULAR = 2 };
+
+struct bf16 {
+  uint16_t v;
+};
+
+struct DevPatch {
+  int kind;
+  int T_dirichlet;  // wall with a fixed temperature
+  double U[3];
+  double T, k, omega, T_wall;  // temperatures as deviations from T_ref
+  double nut;  // eddy viscosity of the inlet values (filled on the device)
+};
+
+// Padded level layout.  Cell (i, j, k), i in [-1, nx], j in [-1, ny],
+// k in [-gz, nz - 1 + gz], sits at off + k*sxy + j*sx + i; rows are padded to
+// a multiple of 16 elements so interior rows start aligned.
+struct Geom {
+  int nx, ny, nz, dim;
+  int sx, sxy, gz;
+  int off, total;
+  double hx, hy, hz;
+  __host__ __device__ inline int idx(int i, int j, int k) const {
+    return off + k * sxy + j * sx + i;
+  }
+  __host__ __device__ inline long long cells() const {
+    return (long long)nx * ny * nz;
+  }
+};
+
+Geom make_geom(int dim, int nx, int ny, int nz, double hx, double hy, double hz);
+
+struct Phys {
+  double nu, alpha_T, inv_Pr_t, inv_sigma_k, inv_sigma_w, dt;
+  int komega, energy, buoyancy;
+  double g[3], T_ref, beta_T;
+};
+
+// One multigrid level on the device.
+struct Level {
+  Geom g;
+  uint8_t* cls;                 // MG_* per padded cell
+  float* cf[3];                 // face coefficients; face between cell q-1 and q along d at idx(q)
+  void* x[2];                   // iterate, ping-pong (storage type of the level)
+  void* b;                      // right-hand side
+  int cur;                      // which x is current
+};
+
+// Device-wide reduction scratch: per-block partials, a completion counter and
+// the reduced scalars.
+struct RedBuf {
+  double* partial;
+  unsigned* counter;
+  double* out;
+  int max_blocks;
+};
+
+// Scalars of the pressure iteration kept on the device.
+enum {
+  S_BB = 0,        // ||b||^2
+  S_RR = 1,        // ||r||^2
+  S_ZR = 2,        // (z, r)
+  S_ZQ = 3,        // (z, q_prev)
+  S_PQ0 = 4,       // (p, q) of even iterations
+  S_PQ1 = 5,       // (p, q) of odd iterations
+  S_DIV = 7,       // max face divergence
+  S_MINK = 8,
+  S_MINW = 9,
+  S_COUNT = 16
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+// Reduce nblocks partials of nv values (op 0 sum, 1 max, 2 min) into
+// red.out[slot0] (and red.out[slot1] when nv == 2).
+void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, int slot1,
+                     hipStream_t s);
+void launch_classify(const Geom& g, const uint8_t* solid_dense, const int* patch_rect,
+                     int n_patches_user, DevPatch* patches, double nu, int komega,
+                     uint8_t* type, hipStream_t s);
+void launch_fix_omega(const Geom& g, const DevPatch* pt, uint8_t* type, hipStream_t s);
+void launch_level0(const Geom& g, const uint8_t* type, const DevPatch* patches, uint8_t* cls,
+                   float* cx, float* cy, float* cz, hipStream_t s);
+void launch_coarsen(const Geom& fine, const uint8_t* fcls, float* const fcf[3], const Geom& crs,
+                    uint8_t* ccls, float* ccf[3], hipStream_t s);
+void launch_coarse_factor(const Geom& g, const uint8_t* cls, float* const cf[3], int* cmap,
+                          int* ncount, double* work, int max_n, hipStream_t s);
+
+template <class F>
+void launch_set_omega_wall(const Geom& g, const Phys& ph, const DevPatch* pt, const uint8_t* type,
+                           F* om, hipStream_t s);
+template <class F>
+void launch_pack(const Geom& g, const double* dense, F* padded, double offset, hipStream_t s);
+template <class F>
+void launch_unpack(const Geom& g, const F* padded, double* dense, double offset, hipStream_t s);
+
+// Velocity in V, transported scalars (T, k, omega) in F.
+template <class V, class F>
+struct FieldSet {
+  V *u, *v, *w;
+  F *T, *k, *om;
+};
+
+template <class V, class F>
+void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                    const V* u, const V* v, const V* w, const F* k, const F* om, double tau,
+                    F* k_out, F* om_out, const RedBuf* red, hipStream_t s);
+template <class V, class F, class P>
+void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, hipStream_t s);
+template <class V, class O>
+void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                  const V* u, const V* v, const V* w, O* b, const RedBuf& red, hipStream_t s);
+template <class V, class P, class O>
+void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                    const O* phi, V* u, V* v, V* w, P* p, const RedBuf& red, hipStream_t s);
+
+// multigrid (S: storage of the level, C: arithmetic)
+template <class S, class C>
+void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
+                   hipStream_t s);
+template <class S, class C, class SC>
+void launch_resid_restrict(const Level& f, const Level& c, hipStream_t s);
+template <class S, class C, class SC>
+void launch_prolong(const Level& f, const Level& c, hipStream_t s);
+template <class SC, class C>
+void launch_coarse_solve(const Level& c, const int* cmap, const int* ncount, const double* ainv,
+                         int max_n, hipStream_t s);
+template <class S>
+void launch_fill_zero(const Level& l, void* x, hipStream_t s);
+
+// flexible CG on level 0 (O: outer type, S: level-0 storage)
+template <class O, class S>
+void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, const RedBuf& red,
+                      bool have_x0, hipStream_t s);
+template <class O, class S>
+void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s);
+template <class O, class S>
+void launch_fcg_dir(const Level& l0, const O* pold, O* pnew, O* q, const RedBuf& red, bool first,
+                    int parity, hipStream_t s);
+template <class O, class S>
+void launch_fcg_update(const Level& l0, O* x, O* r, const O* pv, const O* q, const RedBuf& red,
+                       int parity, hipStream_t s);
+
+}  // namespace nfvm

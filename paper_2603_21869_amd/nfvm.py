@@ -1,0 +1,309 @@
+"""ctypes binding of libnfvm.so (the C ABI in include/nfvm.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  If the library is missing, loading raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnfvm.so")
+
+NFVM_OK, NFVM_PENDING = 0, 1
+NFVM_E_INVAL, NFVM_E_NOMEM, NFVM_E_DEVICE = -1, -2, -3
+NFVM_E_DIVERGED, NFVM_E_NOTCONV, NFVM_E_NOTFOUND = -4, -5, -6
+NFVM_FP64, NFVM_FP32, NFVM_MIXED = 0, 1, 2
+
+_dp = C.POINTER(C.c_double)
+
+EXPORTS = (
+    "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_mg_solve", "nfvm_mg_solve_device",
+    "nfvm_get_fields", "nfvm_set_fields", "nfvm_grid_footprint", "nfvm_free_grid",
+    "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
+    "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_last_error",
+)
+
+KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "explicit", "destroy", "rhs",
+           "project", "fcg_dots", "fcg_dir", "fcg_update")
+
+
+class nfvm_patch(C.Structure):
+    _fields_ = [("face", C.c_int32), ("lo", C.c_int32 * 2), ("hi", C.c_int32 * 2),
+                ("kind", C.c_int32), ("U", C.c_double * 3), ("T", C.c_double),
+                ("k", C.c_double), ("omega", C.c_double), ("T_wall", C.c_double)]
+
+
+class nfvm_grid_desc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int32 * 3), ("h", C.c_double * 3),
+                ("nu", C.c_double), ("rho", C.c_double), ("alpha_T", C.c_double),
+                ("Pr_t", C.c_double), ("sigma_k", C.c_double), ("sigma_w", C.c_double),
+                ("dt", C.c_double), ("physics", C.c_uint32), ("gravity", C.c_double * 3),
+                ("T_ref", C.c_double), ("beta_T", C.c_double), ("T_solid", C.c_double),
+                ("n_patches", C.c_int32), ("patches", C.POINTER(nfvm_patch)),
+                ("solid_mask", C.POINTER(C.c_uint8)), ("precision", C.c_int32),
+                ("n_levels", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("omega_jacobi", C.c_double), ("tol", C.c_double), ("max_cycles", C.c_int32)]
+
+
+class nfvm_fields(C.Structure):
+    _fields_ = [(n, _dp) for n in ("u", "v", "w", "p", "T", "k", "omega")]
+
+
+class nfvm_step_stats(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("status", C.c_int32), ("rel_residual", C.c_double),
+                ("max_face_div", C.c_double), ("min_k", C.c_double), ("min_omega", C.c_double),
+                ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """Load libnfvm.so; raises OSError when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError(f"{LIB_PATH} is missing: build it with paper_2603_21869_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        L.nfvm_set_allocator.argtypes = [ALLOC_FN, FREE_FN, C.c_void_p]
+        L.nfvm_init_grid.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(nfvm_fields), C.c_void_p,
+                                     C.POINTER(C.c_void_p)]
+        L.nfvm_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(nfvm_step_stats)]
+        L.nfvm_mg_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int32, C.c_int32,
+                                    C.POINTER(nfvm_step_stats)]
+        L.nfvm_mg_solve_device.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                           C.c_int32, C.c_int32, C.POINTER(nfvm_step_stats)]
+        L.nfvm_get_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
+        L.nfvm_set_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
+        L.nfvm_grid_footprint.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(C.c_size_t)]
+        L.nfvm_free_grid.argtypes = [C.c_void_p]
+        L.nfvm_server_create.argtypes = [C.c_double, C.c_int32, C.POINTER(C.c_void_p)]
+        L.nfvm_submit.argtypes = [C.c_void_p, C.POINTER(nfvm_grid_desc), C.POINTER(nfvm_fields),
+                                  C.c_int32, C.POINTER(C.c_uint64)]
+        L.nfvm_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(nfvm_fields),
+                                C.POINTER(nfvm_step_stats)]
+        L.nfvm_request_times.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(C.c_double)]
+        L.nfvm_server_drain.argtypes = [C.c_void_p]
+        L.nfvm_server_destroy.argtypes = [C.c_void_p]
+        L.nfvm_profile.argtypes = [C.c_void_p, C.c_uint32]
+        L.nfvm_profile_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.nfvm_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "nfvm_last_error":
+                getattr(L, name).restype = st
+        _lib = L
+    return _lib
+
+
+class NfvmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"nfvm status {status}: {msg}")
+        self.status = status
+
+
+def _check(st: int, allow=(NFVM_OK,)):
+    if st not in allow:
+        raise NfvmError(st, lib().nfvm_last_error().decode())
+    return st
+
+
+def nfvm_last_error() -> str:
+    return lib().nfvm_last_error().decode()
+
+
+class Desc:
+    """Owns a filled nfvm_grid_desc and the arrays it points at."""
+
+    def __init__(self, case, precision: Optional[int] = None, tol: Optional[float] = None,
+                 max_cycles: Optional[int] = None):
+        d = nfvm_grid_desc()
+        d.dim = case.dim
+        d.n[:] = list(case.n)
+        d.h[:] = list(case.h)
+        d.nu, d.rho, d.alpha_T, d.Pr_t = case.nu, case.rho, case.alpha_T, case.Pr_t
+        d.sigma_k, d.sigma_w, d.dt = case.sigma_k, case.sigma_w, case.dt
+        d.physics = case.physics
+        d.gravity[:] = list(case.gravity)
+        d.T_ref, d.beta_T, d.T_solid = case.T_ref, case.beta_T, case.T_solid
+        pats = (nfvm_patch * max(1, len(case.patches)))()
+        for q, p in enumerate(case.patches):
+            pats[q].face = p.face
+            pats[q].lo[:] = list(p.lo)
+            pats[q].hi[:] = list(p.hi)
+            pats[q].kind = p.kind
+            pats[q].U[:] = list(p.U)
+            pats[q].T, pats[q].k, pats[q].omega, pats[q].T_wall = p.T, p.k, p.omega, p.T_wall
+        self._pats = pats
+        d.n_patches = len(case.patches)
+        d.patches = C.cast(pats, C.POINTER(nfvm_patch))
+        if case.solid is not None:
+            self._mask = np.ascontiguousarray(case.solid, dtype=np.uint8)
+            d.solid_mask = self._mask.ctypes.data_as(C.POINTER(C.c_uint8))
+        else:
+            self._mask = None
+            d.solid_mask = C.POINTER(C.c_uint8)()
+        d.precision = case.precision if precision is None else precision
+        d.n_levels, d.nu1, d.nu2 = case.n_levels, case.nu1, case.nu2
+        d.omega_jacobi = case.omega_jacobi
+        d.tol = case.tol if tol is None else tol
+        d.max_cycles = case.max_cycles if max_cycles is None else max_cycles
+        self.d = d
+
+
+FIELD_ORDER = ("u", "v", "w", "p", "T", "k", "omega")
+
+
+def _fields_struct(arrs: Dict[str, np.ndarray]) -> nfvm_fields:
+    f = nfvm_fields()
+    for n in FIELD_ORDER:
+        a = arrs[n]
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+        setattr(f, n, a.ctypes.data_as(_dp))
+    return f
+
+
+def nfvm_init_grid(desc: Desc, fields: Dict[str, np.ndarray], stream: int = 0) -> C.c_void_p:
+    arrs = {n: np.ascontiguousarray(fields[n], dtype=np.float64) for n in FIELD_ORDER}
+    h = C.c_void_p()
+    _check(lib().nfvm_init_grid(C.byref(desc.d), C.byref(_fields_struct(arrs)),
+                                C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def nfvm_step(grid, n_steps: int, allow=(NFVM_OK,)):
+    st = (nfvm_step_stats * max(1, n_steps))()
+    s = _check(lib().nfvm_step(grid, n_steps, st), allow)
+    return s, [st[i].as_dict() for i in range(n_steps)]
+
+
+def nfvm_mg_solve(grid, b: np.ndarray, x0: Optional[np.ndarray] = None, tol: float = 1e-10,
+                  max_cycles: int = 100, forced_cycles: int = -1, allow=(NFVM_OK,)):
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.ascontiguousarray(x0, dtype=np.float64).copy()
+    st = nfvm_step_stats()
+    s = _check(lib().nfvm_mg_solve(grid, b.ctypes.data_as(_dp), x.ctypes.data_as(_dp), tol,
+                                   max_cycles, forced_cycles, C.byref(st)), allow)
+    return x, st.as_dict(), s
+
+
+def nfvm_mg_solve_device(grid, b_ptr: int, x_ptr: int, tol: float = 1e-10, max_cycles: int = 100,
+                         forced_cycles: int = -1, allow=(NFVM_OK,)):
+    st = nfvm_step_stats()
+    s = _check(lib().nfvm_mg_solve_device(grid, C.c_void_p(b_ptr), C.c_void_p(x_ptr), tol,
+                                          max_cycles, forced_cycles, C.byref(st)), allow)
+    return st.as_dict(), s
+
+
+def nfvm_get_fields(grid, shape) -> Dict[str, np.ndarray]:
+    out = {n: np.zeros(shape) for n in FIELD_ORDER}
+    _check(lib().nfvm_get_fields(grid, C.byref(_fields_struct(out))))
+    return out
+
+
+def nfvm_set_fields(grid, fields: Dict[str, np.ndarray]):
+    arrs = {n: np.ascontiguousarray(fields[n], dtype=np.float64) for n in FIELD_ORDER}
+    _check(lib().nfvm_set_fields(grid, C.byref(_fields_struct(arrs))))
+
+
+def nfvm_grid_footprint(desc: Desc) -> int:
+    b = C.c_size_t(0)
+    _check(lib().nfvm_grid_footprint(C.byref(desc.d), C.byref(b)))
+    return b.value
+
+
+def nfvm_free_grid(grid):
+    _check(lib().nfvm_free_grid(grid))
+
+
+def nfvm_profile(grid, kernel_mask: int):
+    _check(lib().nfvm_profile(grid, kernel_mask))
+
+
+def nfvm_profile_read(grid, kernel: int):
+    n = C.c_int64(0)
+    s = C.c_double(0.0)
+    b = C.c_double(0.0)
+    _check(lib().nfvm_profile_read(grid, kernel, C.byref(n), C.byref(s), C.byref(b)))
+    return dict(launches=n.value, seconds=s.value, bytes_per_launch=b.value)
+
+
+def nfvm_server_create(hbm_budget_bytes: float = 0.0, max_slots: int = 4):
+    h = C.c_void_p()
+    _check(lib().nfvm_server_create(hbm_budget_bytes, max_slots, C.byref(h)))
+    return h
+
+
+def nfvm_submit(server, desc: Desc, fields: Dict[str, np.ndarray], n_steps: int) -> int:
+    arrs = {n: np.ascontiguousarray(fields[n], dtype=np.float64) for n in FIELD_ORDER}
+    t = C.c_uint64(0)
+    _check(lib().nfvm_submit(server, C.byref(desc.d), C.byref(_fields_struct(arrs)), n_steps,
+                             C.byref(t)))
+    return t.value
+
+
+def nfvm_poll(server, ticket: int, shape, allow=(NFVM_OK, NFVM_PENDING)):
+    out = {n: np.zeros(shape) for n in FIELD_ORDER}
+    st = nfvm_step_stats()
+    s = _check(lib().nfvm_poll(server, ticket, C.byref(_fields_struct(out)), C.byref(st)), allow)
+    return s, (out if s != NFVM_PENDING else None), st.as_dict()
+
+
+def nfvm_request_times(server, ticket: int):
+    t = (C.c_double * 4)()
+    _check(lib().nfvm_request_times(server, ticket, t))
+    return list(t)
+
+
+def nfvm_server_drain(server):
+    _check(lib().nfvm_server_drain(server))
+
+
+def nfvm_server_destroy(server):
+    _check(lib().nfvm_server_destroy(server))
+
+
+class Grid:
+    """Convenience owner of one grid handle."""
+
+    def __init__(self, case, precision=None, tol=None, max_cycles=None, stream: int = 0,
+                 fields=None):
+        self.case = case
+        self.desc = Desc(case, precision, tol, max_cycles)
+        self.shape = (case.n[2], case.n[1], case.n[0])
+        self.h = nfvm_init_grid(self.desc, case.fields if fields is None else fields, stream)
+
+    def step(self, n: int, allow=(NFVM_OK,)):
+        return nfvm_step(self.h, n, allow)
+
+    def fields(self):
+        return nfvm_get_fields(self.h, self.shape)
+
+    def set_fields(self, f):
+        nfvm_set_fields(self.h, f)
+
+    def mg_solve(self, b, x0=None, **kw):
+        return nfvm_mg_solve(self.h, b, x0, **kw)
+
+    def close(self):
+        if self.h:
+            nfvm_free_grid(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

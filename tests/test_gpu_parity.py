@@ -1,0 +1,147 @@
+"""Parity of the HIP library (through the C ABI) with the CPU oracle on the
+same seeded inputs.  Bars: FP64 1e-10, FP32 1e-5, mixed 1e-6 relative L2 over
+fluid cells (T relative to its deviation from T_ref); the oracle runs the
+cycle counts the GPU reported, so both take the same iterate."""
+import numpy as np
+import pytest
+
+from paper_2603_21869_amd import cases as C
+from tests.parity import field_errors, fluid
+
+pytestmark = pytest.mark.gpu
+
+TOL = {C.PREC_FP64: 1e-10, C.PREC_FP32: 1e-5, C.PREC_MIXED: 1e-6}
+# FP32 storage floor of p and T: both are driven by differences of stored
+# values a factor delta ~ 1e-2 below their magnitude (the 1 % velocity noise,
+# the T_ref div(U_f) term), so one rounding costs eps32 / delta ~ 1.2e-5 and a
+# few steps accumulate several of them.
+FP32_FLOOR = 1e-4
+
+
+@pytest.fixture(scope="module")
+def nf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2603_21869_amd import nfvm
+    nfvm.lib()
+    return nfvm
+
+
+def small_cases():
+    return [
+        ("ch2d", C.channel2d(96, 18, L=4.0, H=1.0, n_levels=2, n_steps=3)),
+        ("ch3d", C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3, n_steps=3, tol=1e-8)),
+        ("room", C.room3d(64, 24, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4, n_steps=2)),
+    ]
+
+
+@pytest.mark.parametrize("name,case", small_cases(), ids=[c[0] for c in small_cases()])
+def test_mg_solve_fp64_matches_oracle(nf, oracle, name, case):
+    print(f"[mg_solve] {name} n={case.n} L={case.n_levels}", flush=True)
+    g = nf.Grid(case, precision=nf.NFVM_FP64)
+    rng = np.random.default_rng(7)
+    m = fluid(case)
+    b = rng.standard_normal(g.shape) * m
+    x, st, s = g.mg_solve(b, tol=1e-10, max_cycles=60)
+    assert s == 0 and st["rel_residual"] <= 1e-10
+    mg = oracle.MG(case)
+    xr, cyc, rel, sr = mg.solve(b, forced=st["cycles"])
+    err = np.linalg.norm((x - xr)[m]) / np.linalg.norm(xr[m])
+    print(f"   cycles={st['cycles']} rel={st['rel_residual']:.3e} oracle rel={rel:.3e} err={err:.3e}")
+    assert err < 1e-12
+    assert not x[~m].any()
+    # residual of the GPU answer under the oracle's operator
+    assert np.linalg.norm((b - mg.apply(0, x))[m]) <= 2e-10 * np.linalg.norm(b[m])
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [C.PREC_FP64, C.PREC_FP32, C.PREC_MIXED], ids=["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("name,case", small_cases(), ids=[c[0] for c in small_cases()])
+def test_step_matches_oracle(nf, oracle, name, case, prec):
+    # the pressure solve runs to 1e-9 where the precision allows it, so that the
+    # comparison measures arithmetic, not how far each iteration stopped short
+    case = case.copy(precision=prec, tol=1e-9 if prec != C.PREC_FP32 else case.tol)
+    n = case.n_steps
+    print(f"[step] {name} prec={prec} n={case.n} steps={n}", flush=True)
+    g = nf.Grid(case)
+    s, stats = g.step(n, allow=(0, nf.NFVM_E_NOTCONV))
+    out = g.fields()
+    cyc = [x["cycles"] for x in stats]
+    ref, rst, status = oracle.step(case, n, forced_cycles=cyc)
+    errs = field_errors(case, out, ref)
+    print("   cycles", cyc, "errors", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    tol = TOL[prec]
+    for f in ("vel", "k", "omega"):
+        assert errs[f] <= tol, (f, errs[f])
+    tol_pT = FP32_FLOOR if prec == C.PREC_FP32 else tol
+    assert errs["p"] <= tol_pT, ("p", errs["p"])
+    if case.physics & C.PHYS_ENERGY:
+        assert errs["T"] <= tol_pT, ("T", errs["T"])
+    for a, b in zip(stats, rst):
+        assert abs(a["min_k"] - b["min_k"]) <= 1e-6 * b["min_k"] + 1e-30
+    g.close()
+
+
+def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
+    """The 3D heated channel at its full size (256 x 64 x 64, 7 levels, tol
+    1e-8) in the launch configuration the benchmark times: one step, every
+    cell compared."""
+    base = C.channel3d(n_steps=1, tol=1e-8)
+    for prec, tol in ((C.PREC_FP64, 1e-10), (C.PREC_MIXED, 1e-6)):
+        case = base.copy(precision=prec)
+        print(f"[full] channel3d prec={prec}", flush=True)
+        g = nf.Grid(case)
+        s, stats = g.step(1)
+        out = g.fields()
+        g.close()
+        ref, rst, st = oracle.step(case, 1, forced_cycles=[stats[0]["cycles"]])
+        errs = field_errors(case, out, ref)
+        print("   cycles", stats[0]["cycles"], {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for f in ("vel", "p", "k", "omega", "T"):
+            assert errs[f] <= tol, (prec, f, errs[f])
+
+
+def test_deterministic_and_restartable(nf):
+    """Two runs give bitwise equal fields; N + N steps with a get/set of the
+    fields in between equal 2N steps bitwise."""
+    case = C.room3d(64, 24, 16, seed=2, n_levels=4, precision=C.PREC_MIXED)
+    a = nf.Grid(case)
+    a.step(4)
+    fa = a.fields()
+    b = nf.Grid(case)
+    b.step(2)
+    mid = b.fields()
+    b.close()
+    c = nf.Grid(case, fields=mid)
+    c.step(2)
+    fc = c.fields()
+    d = nf.Grid(case)
+    d.step(4)
+    fd = d.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fd[k]), k
+    # restart through FP64 host arrays is exact in FP64 and for the FP64 velocity
+    # and pressure of the mixed mode; FP32 scalars round-trip exactly too
+    for k in fa:
+        assert np.array_equal(fa[k], fc[k]), k
+
+
+def test_error_paths(nf):
+    """Failure handling forced from the host: non-finite input diverges,
+    a tiny cycle budget reports NOTCONV with valid fields, bad descriptors are
+    rejected."""
+    case = C.channel2d(64, 16, n_levels=3)
+    bad = case.copy()
+    bad.fields["u"][0, 5, 7] = np.nan
+    g = nf.Grid(bad)
+    s, st = g.step(1, allow=(nf.NFVM_E_DIVERGED,))
+    assert s == nf.NFVM_E_DIVERGED
+    g.close()
+    g = nf.Grid(case, tol=1e-14, max_cycles=1)
+    s, st = g.step(1, allow=(nf.NFVM_E_NOTCONV,))
+    assert s == nf.NFVM_E_NOTCONV and st[0]["cycles"] == 1
+    f = g.fields()
+    assert np.isfinite(f["u"]).all()
+    g.close()
+    with pytest.raises(nf.NfvmError):
+        nf.Grid(case.copy(n_levels=9))
