@@ -221,6 +221,20 @@ nfvm_status nfvm_profile(nfvm_grid_t grid, uint32_t kernel_mask);
 nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launches,
                               double* seconds, double* bytes_per_launch);
 
+/* Grid options.
+ *   NFVM_OPT_GRAPHS   1 (default): the time step runs as captured HIP graphs
+ *                     (step prefix, one CG iteration replayed, step suffix);
+ *                     0: plain stream launches.  Graphs are not used while
+ *                     nfvm_profile timing is on.
+ *   NFVM_OPT_PREDICT  CG iterations enqueued before the first convergence
+ *                     check (default: the count of the previous solve).
+ *   NFVM_OPT_BOTTOM   1 (default): the coarse levels whose iterates fit in
+ *                     64 KiB of LDS run as one workgroup in one launch;
+ *                     0: one launch per operator and level.
+ * Errors: NFVM_E_INVAL for an unknown option. */
+enum { NFVM_OPT_GRAPHS = 0, NFVM_OPT_PREDICT = 1, NFVM_OPT_BOTTOM = 2 };
+nfvm_status nfvm_set_option(nfvm_grid_t grid, int32_t option, double value);
+
 /* Message for the last non-OK status on this thread. */
 const char* nfvm_last_error(void);
 

@@ -152,6 +152,14 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
   return NFVM_OK;
 }
 
+nfvm_status nfvm_set_option(nfvm_grid_t grid, int32_t option, double value) {
+  if (!grid) return fail(NFVM_E_INVAL, "grid is NULL");
+  return guard([&] {
+    grid->g->set_option(option, value);
+    return NFVM_OK;
+  });
+}
+
 const char* nfvm_last_error(void) { return t_err.c_str(); }
 
 }  // extern "C"

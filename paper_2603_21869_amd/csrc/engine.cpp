@@ -192,6 +192,7 @@ class GridT : public GridBase {
 
   ~GridT() override {
     if (stream) (void)hipStreamSynchronize(stream);
+    drop_graphs();
     prof_release();
     pool.clear();
     if (hs) (void)hipHostFree(hs);
@@ -301,6 +302,7 @@ class GridT : public GridBase {
       Level& v = lv[l];
       v.g = level_geom(d, l);
       v.cls = alloc<uint8_t>(v.g.total);
+      v.full = l > 0 ? alloc<uint8_t>(v.g.total) : nullptr;
       for (int a = 0; a < 3; ++a) v.cf[a] = a < d.dim ? alloc<float>(v.g.total) : nullptr;
       const size_t es = l == 0 ? s0 : sc;
       for (int c = 0; c < 2; ++c) v.x[c] = alloc<uint8_t>(v.g.total * es);
@@ -311,6 +313,7 @@ class GridT : public GridBase {
                       stream);
       else
         launch_coarsen(lv[l - 1].g, lv[l - 1].cls, lv[l - 1].cf, v.g, v.cls, v.cf, stream);
+      if (l > 0) launch_mark_full(v, stream);
     }
     cmap = alloc<int>(COARSE_MAX);
     ncount = alloc<int>(1);
@@ -324,6 +327,8 @@ class GridT : public GridBase {
     if (nc > COARSE_MAX)
       throw Error{NFVM_E_INVAL, "coarsest level has " + std::to_string(nc) +
                                     " fluid cells; at most 512 (add levels)"};
+
+    setup_bottom();
 
     bvec = alloc<O>(g.total);
     phi = alloc<O>(g.total);
@@ -392,22 +397,70 @@ class GridT : public GridBase {
     const int kid = zero ? NFVM_K_SMOOTH0_ZERO : NFVM_K_SMOOTH0;
     if (l == 0) {
       prof_begin(kid);
-      launch_smooth<S0, C>(v, xin, xout, wj, zero, stream);
+      launch_smooth<S0, C>(v, xin, xout, wj, zero, red.out, stream);
       prof_end(kid);
     } else {
-      launch_smooth<SC, C>(v, xin, xout, wj, zero, stream);
+      launch_smooth<SC, C>(v, xin, xout, wj, zero, red.out, stream);
     }
     v.cur = zero ? 0 : (v.cur ^ 1);
   }
 
+  // levels bottom_top .. L-1 run in one LDS-resident workgroup
+  static constexpr size_t LDS_LIMIT = 64 * 1024;
+  int bottom_top = -1;
+  Bottom bot{};
+
+  void setup_bottom() {
+    bottom_top = -1;
+    if (!use_bottom || L < 3) return;
+    size_t bytes = 0;
+    int top = L;
+    for (int l = L - 1; l >= 1; --l) {
+      const size_t need = bytes + 3 * (size_t)lv[l].g.cells() * sizeof(C);
+      if (need > LDS_LIMIT || L - l > BOTTOM_MAX_LEVELS) break;
+      bytes = need;
+      top = l;
+    }
+    if (top > L - 2) return;  // fewer than two levels would fit
+    bottom_top = top;
+    bot.nlev = L - top;
+    bot.nu1 = nu1;
+    bot.nu2 = nu2;
+    bot.wj = wj;
+    size_t off = 0;
+    for (int l = top; l < L; ++l) {
+      BottomLevel& b = bot.lv[l - top];
+      b.g = lv[l].g;
+      b.cls = lv[l].cls;
+      b.cf0 = lv[l].cf[0];
+      b.cf1 = lv[l].cf[1];
+      b.cf2 = desc.dim == 3 ? lv[l].cf[2] : lv[l].cf[0];
+      b.n = (int)lv[l].g.cells();
+      b.ox0 = (int)off;
+      b.ox1 = (int)(off + b.n);
+      b.ob = (int)(off + 2 * b.n);
+      off += 3 * (size_t)b.n;
+    }
+    bot.cmap = cmap;
+    bot.ncount = ncount;
+    bot.ainv = work;
+    bot.max_n = COARSE_MAX;
+    bot.lds_bytes = off * sizeof(C);
+  }
+
   void vcycle(int l) {
     Level& v = lv[l];
+    if (l == bottom_top) {
+      v.cur = 0;
+      launch_bottom<SC, C>(bot, v.b, v.x[0], red.out, stream);
+      return;
+    }
     if (l == L - 1) {
       v.cur = 0;
       if (l == 0)
-        launch_coarse_solve<S0, C>(v, cmap, ncount, work, COARSE_MAX, stream);
+        launch_coarse_solve<S0, C>(v, cmap, ncount, work, COARSE_MAX, red.out, stream);
       else
-        launch_coarse_solve<SC, C>(v, cmap, ncount, work, COARSE_MAX, stream);
+        launch_coarse_solve<SC, C>(v, cmap, ncount, work, COARSE_MAX, red.out, stream);
       return;
     }
     if (nu1 > 0) {
@@ -416,23 +469,23 @@ class GridT : public GridBase {
     } else {
       v.cur = 0;
       if (l == 0)
-        launch_fill_zero<S0>(v, v.x[0], stream);
+        launch_fill_zero<S0>(v, v.x[0], red.out, stream);
       else
-        launch_fill_zero<SC>(v, v.x[0], stream);
+        launch_fill_zero<SC>(v, v.x[0], red.out, stream);
     }
     if (l == 0) {
       prof_begin(NFVM_K_RESTRICT0);
-      launch_resid_restrict<S0, C, SC>(lv[0], lv[1], stream);
+      launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream);
       prof_end(NFVM_K_RESTRICT0);
     } else
-      launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], stream);
+      launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
     vcycle(l + 1);
     if (l == 0) {
       prof_begin(NFVM_K_PROLONG0);
-      launch_prolong<S0, C, SC>(lv[0], lv[1], stream);
+      launch_prolong<S0, C, SC>(lv[0], lv[1], red.out, stream);
       prof_end(NFVM_K_PROLONG0);
     } else
-      launch_prolong<SC, C, SC>(lv[l], lv[l + 1], stream);
+      launch_prolong<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
     for (int s = 0; s < nu2; ++s) smooth(l, false);
   }
 
@@ -443,42 +496,91 @@ class GridT : public GridBase {
     return hs[slot];
   }
 
-  // Flexible CG preconditioned by one V-cycle; b in bvec, result in phi.
-  nfvm_status solve(bool have_x0, double tol_, int maxc, int forced, int* cycles, double* rel) {
-    launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, have_x0, stream);
-    NFVM_CK(hipGetLastError());
-    NFVM_CK(hipMemcpyAsync(hs, red.out, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
-    NFVM_CK(hipStreamSynchronize(stream));
-    const double bn = sqrt(hs[S_BB]);
-    double rn = sqrt(hs[S_RR]);
-    int it = 0;
-    nfvm_status st = NFVM_OK;
-    for (;;) {
-      *rel = bn > 0 ? rn / bn : 0.0;
-      if (!isfinite(rn)) { st = NFVM_E_DIVERGED; break; }
-      if (forced >= 0) {
-        if (it >= forced) break;
-      } else {
-        if (bn == 0.0 || rn <= tol_ * bn) break;
-        if (it >= maxc) { st = NFVM_E_NOTCONV; break; }
-      }
-      const int par = it & 1;
-      vcycle(0);
-      prof_begin(NFVM_K_FCG_DOTS);
-      launch_fcg_dots<O, S0>(lv[0], r, q, red, stream);
-      prof_end(NFVM_K_FCG_DOTS);
-      prof_begin(NFVM_K_FCG_DIR);
-      launch_fcg_dir<O, S0>(lv[0], pv[par ^ 1], pv[par], q, red, it == 0, par, stream);
-      prof_end(NFVM_K_FCG_DIR);
-      prof_begin(NFVM_K_FCG_UPDATE);
-      launch_fcg_update<O, S0>(lv[0], phi, r, pv[par], q, red, par, stream);
-      prof_end(NFVM_K_FCG_UPDATE);
-      NFVM_CK(hipGetLastError());
-      rn = sqrt(read_scalar(S_RR));
-      ++it;
+  // One preconditioned flexible-CG iteration (all kernels are no-ops once
+  // the device-side stopping rule has fired).
+  void fcg_iteration() {
+    vcycle(0);
+    prof_begin(NFVM_K_FCG_DOTS);
+    launch_fcg_dots<O, S0>(lv[0], r, q, red, stream);
+    prof_end(NFVM_K_FCG_DOTS);
+    prof_begin(NFVM_K_FCG_DIR);
+    launch_fcg_dir<O, S0>(lv[0], pv[0], pv[1], q, red, stream);
+    prof_end(NFVM_K_FCG_DIR);
+    prof_begin(NFVM_K_FCG_UPDATE);
+    launch_fcg_update<O, S0>(lv[0], phi, r, pv[0], pv[1], q, red, stream);
+    prof_end(NFVM_K_FCG_UPDATE);
+  }
+
+  int predicted = 8;  // iterations of the last solve: enqueued before the first check
+
+  // ---- graphs: one CG iteration, and the step prefix / suffix for both field
+  // parities (the ping-pong buffers alternate every step) ----
+  struct PartGraph {
+    hipGraphExec_t exec = nullptr;
+    int post[6];
+  };
+  hipGraphExec_t g_iter = nullptr;
+  // keyed by the buffer state (one bit per field) at the start of the part
+  PartGraph g_pre[64], g_suf[64];
+
+  template <class Fn>
+  hipGraphExec_t capture(Fn&& fn) {
+    hipGraph_t gr = nullptr;
+    NFVM_CK(hipStreamSynchronize(stream));  // capture starts on an idle stream
+    NFVM_CK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    fn();
+    NFVM_CK(hipStreamEndCapture(stream, &gr));
+    hipGraphExec_t ex = nullptr;
+    NFVM_CK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+    NFVM_CK(hipGraphDestroy(gr));
+    return ex;
+  }
+
+  void drop_graphs() {
+    if (g_iter) (void)hipGraphExecDestroy(g_iter);
+    g_iter = nullptr;
+    for (int i = 0; i < 64; ++i) {
+      if (g_pre[i].exec) (void)hipGraphExecDestroy(g_pre[i].exec);
+      if (g_suf[i].exec) (void)hipGraphExecDestroy(g_suf[i].exec);
+      g_pre[i].exec = g_suf[i].exec = nullptr;
     }
+  }
+
+  bool graphs_on() const { return use_graphs && prof_mask == 0; }
+
+  void run_iteration() {
+    if (!graphs_on()) {
+      fcg_iteration();
+      return;
+    }
+    if (!g_iter) g_iter = capture([&] { fcg_iteration(); });
+    NFVM_CK(hipGraphLaunch(g_iter, stream));
+  }
+
+  // Flexible CG preconditioned by one V-cycle; b in bvec, result in phi.
+  nfvm_status solve(bool have_x0, double tol_, int maxc, int forced, int* cycles, double* rel,
+                    bool started = false) {
+    if (!started) launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, have_x0, tol_, maxc, forced,
+                                          stream);
+    int ahead = forced >= 0 ? forced : std::min(predicted, maxc);
+    for (int i = 0; i < ahead; ++i) run_iteration();
+    NFVM_CK(hipGetLastError());
+    for (;;) {
+      NFVM_CK(hipMemcpyAsync(hs, red.out, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                             stream));
+      NFVM_CK(hipStreamSynchronize(stream));
+      if (hs[S_DONE] != 0.0) break;
+      run_iteration();
+      NFVM_CK(hipGetLastError());
+    }
+    const int it = (int)hs[S_ITER];
+    const double bn = sqrt(hs[S_BB]), rn = sqrt(hs[S_RR]);
+    *rel = bn > 0 ? rn / bn : 0.0;
     *cycles = it;
-    return st;
+    if (forced < 0) predicted = std::max(1, it);
+    if (!isfinite(rn) || !isfinite(bn)) return NFVM_E_DIVERGED;
+    if (forced < 0 && bn > 0 && rn > tol_ * bn) return NFVM_E_NOTCONV;
+    return NFVM_OK;
   }
 
   void mg_solve(const double* b_dev, double* x_dev, double tol_, int maxc, int forced,
@@ -508,32 +610,76 @@ class GridT : public GridBase {
 
   void swap(int f) { fcur[f] ^= 1; }
 
+  // destruction over dt/2, explicit step, Poisson right-hand side, CG start
+  void step_prefix() {
+    const double half = 0.5 * ph.dt;
+    if (ph.komega) {
+      prof_begin(NFVM_K_DESTROY);
+      launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
+                           half, salt(4), salt(5), nullptr, stream);
+      prof_end(NFVM_K_DESTROY);
+      swap(4);
+      swap(5);
+    }
+    FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
+    FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
+    prof_begin(NFVM_K_EXPLICIT);
+    launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, stream);
+    prof_end(NFVM_K_EXPLICIT);
+    for (int f = 0; f < 6; ++f) swap(f);
+    prof_begin(NFVM_K_RHS);
+    launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red, stream);
+    prof_end(NFVM_K_RHS);
+    launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, false, tol, max_cycles, -1, stream);
+  }
+
+  // projection, destruction over dt/2 (with the min k / omega reduction)
+  void step_suffix() {
+    const double half = 0.5 * ph.dt;
+    prof_begin(NFVM_K_PROJECT);
+    launch_project<V, P, O>(g, ph, type, patches, phi, vcur(0), vcur(1), vcur(2), valt(0),
+                            valt(1), valt(2), p, red, stream);
+    prof_end(NFVM_K_PROJECT);
+    swap(0);
+    swap(1);
+    swap(2);
+    if (ph.komega) {
+      prof_begin(NFVM_K_DESTROY);
+      launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
+                           half, salt(4), salt(5), &red, stream);
+      prof_end(NFVM_K_DESTROY);
+      swap(4);
+      swap(5);
+    }
+  }
+
+  template <class Fn>
+  void run_part(PartGraph* cache, Fn&& fn) {
+    if (!graphs_on()) {
+      fn();
+      return;
+    }
+    int key = 0;
+    for (int f = 0; f < 6; ++f) key |= fcur[f] << f;
+    PartGraph& pg = cache[key];
+    if (!pg.exec) {
+      pg.exec = capture(fn);
+      for (int f = 0; f < 6; ++f) pg.post[f] = fcur[f];
+    } else {
+      for (int f = 0; f < 6; ++f) fcur[f] = pg.post[f];
+    }
+    NFVM_CK(hipGraphLaunch(pg.exec, stream));
+  }
+
   void step(int n, nfvm_step_stats* stt, nfvm_status* status) override {
     nfvm_status worst = NFVM_OK;
     for (int s = 0; s < n; ++s) {
       NFVM_CK(hipEventRecord(ev0, stream));
-      const double half = 0.5 * ph.dt;
-      if (ph.komega) {
-        prof_begin(NFVM_K_DESTROY);
-        launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
-                             half, salt(4), salt(5), nullptr, stream);
-        prof_end(NFVM_K_DESTROY);
-        swap(4);
-        swap(5);
-      }
-      FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
-      FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
-      prof_begin(NFVM_K_EXPLICIT);
-      launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, stream);
-      prof_end(NFVM_K_EXPLICIT);
-      for (int f = 0; f < 6; ++f) swap(f);
-      prof_begin(NFVM_K_RHS);
-      launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red, stream);
-      prof_end(NFVM_K_RHS);
+      run_part(g_pre, [&] { step_prefix(); });
       NFVM_CK(hipGetLastError());
       int cyc = 0;
       double rel = 0;
-      nfvm_status st = solve(false, tol, max_cycles, -1, &cyc, &rel);
+      nfvm_status st = solve(false, tol, max_cycles, -1, &cyc, &rel, true);
       if (st == NFVM_E_DIVERGED) {
         if (stt) {
           memset(&stt[s], 0, sizeof stt[s]);
@@ -544,18 +690,7 @@ class GridT : public GridBase {
         *status = st;
         return;
       }
-      prof_begin(NFVM_K_PROJECT);
-      launch_project<V, P, O>(g, ph, type, patches, phi, vcur(0), vcur(1), vcur(2), p, red,
-                              stream);
-      prof_end(NFVM_K_PROJECT);
-      if (ph.komega) {
-        prof_begin(NFVM_K_DESTROY);
-        launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
-                             half, salt(4), salt(5), &red, stream);
-        prof_end(NFVM_K_DESTROY);
-        swap(4);
-        swap(5);
-      }
+      run_part(g_suf, [&] { step_suffix(); });
       NFVM_CK(hipGetLastError());
       NFVM_CK(hipEventRecord(ev1, stream));
       NFVM_CK(hipMemcpyAsync(hs, red.out, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
@@ -581,6 +716,23 @@ class GridT : public GridBase {
       if (st != NFVM_OK && worst == NFVM_OK) worst = st;
     }
     *status = worst;
+  }
+
+  void set_option(int opt, double v) override {
+    if (opt == NFVM_OPT_GRAPHS) {
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
+      use_graphs = v != 0.0;
+    } else if (opt == NFVM_OPT_PREDICT) {
+      predicted = std::max(1, (int)v);
+    } else if (opt == NFVM_OPT_BOTTOM) {
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
+      use_bottom = v != 0.0;
+      setup_bottom();
+    } else {
+      throw Error{NFVM_E_INVAL, "unknown option"};
+    }
   }
 };
 

@@ -66,6 +66,9 @@ class GridBase {
                         nfvm_step_stats* st, nfvm_status* status) = 0;
   virtual void get_fields(nfvm_fields* out) = 0;
   virtual void set_fields(const nfvm_fields* in) = 0;
+  virtual void set_option(int opt, double v) = 0;
+  bool use_graphs = true;
+  bool use_bottom = true;
   // kernel timing (nfvm_profile)
   struct ProfRec {
     int kid;

@@ -354,16 +354,21 @@ template void launch_rhs_b<float, float>(const Geom&, const Phys&, const uint8_t
 template <class F, class P, class O>
 __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                 const DevPatch* __restrict__ pt,
-                                                const O* __restrict__ phi, F* __restrict__ u,
-                                                F* __restrict__ v, F* __restrict__ w,
-                                                P* __restrict__ p, RedBuf red) {
+                                                const O* __restrict__ phi, const F* __restrict__ u,
+                                                const F* __restrict__ v, const F* __restrict__ w,
+                                                F* __restrict__ uo, F* __restrict__ vo,
+                                                F* __restrict__ wo, P* __restrict__ p,
+                                                RedBuf red) {
   const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
   double mdiv = 0.0;
   if (i < g.nx && j < g.ny) {
     const int C0 = g.idx(i, j, k);
     const uint8_t tp = type[C0];
-    if (is_fluid(tp)) {
-      F* vel[3] = {u, v, w};
+    const F* vel[3] = {u, v, w};
+    F* vout[3] = {uo, vo, wo};
+    if (!is_fluid(tp)) {
+      for (int d = 0; d < 3; ++d) vout[d][C0] = vel[d][C0];
+    } else {
       const int st[3] = {1, g.sx, g.sxy};
       const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
       const O dt = (O)ph.dt;
@@ -397,7 +402,7 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
         unew[d] = vp - dt * grad * (O)0.5 * ih[d];
         div += (fl[1] - fl[0]) * ih[d];
       }
-      for (int d = 0; d < g.dim; ++d) vel[d][C0] = (F)unew[d];
+      for (int d = 0; d < 3; ++d) vout[d][C0] = d < g.dim ? (F)unew[d] : vel[d][C0];
       p[C0] = (P)((O)p[C0] + fP);
       mdiv = fabs((double)div);
     }
@@ -408,18 +413,21 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
 
 template <class F, class P, class O>
 void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                    const O* phi, F* u, F* v, F* w, P* p, const RedBuf& red, hipStream_t s) {
+                    const O* phi, const F* u, const F* v, const F* w, F* uo, F* vo, F* wo, P* p,
+                    const RedBuf& red, hipStream_t s) {
   hipLaunchKernelGGL((k_project<F, P, O>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
-                     u, v, w, p, red);
+                     u, v, w, uo, vo, wo, p, red);
   const dim3 gr = cell_grid(g);
   launch_finalize(1, R_MAX, red, gr.x * gr.y * gr.z, S_DIV, S_DIV, s);
 }
 template void launch_project<double, double, double>(const Geom&, const Phys&, const uint8_t*,
-                                                     const DevPatch*, const double*, double*,
-                                                     double*, double*, double*, const RedBuf&,
-                                                     hipStream_t);
+                                                     const DevPatch*, const double*,
+                                                     const double*, const double*, const double*,
+                                                     double*, double*, double*, double*,
+                                                     const RedBuf&, hipStream_t);
 template void launch_project<float, float, float>(const Geom&, const Phys&, const uint8_t*,
-                                                  const DevPatch*, const float*, float*, float*,
+                                                  const DevPatch*, const float*, const float*,
+                                                  const float*, const float*, float*, float*,
                                                   float*, float*, const RedBuf&, hipStream_t);
 
 }  // namespace nfvm

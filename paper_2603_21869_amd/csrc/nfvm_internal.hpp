@@ -65,6 +65,7 @@ struct Phys {
 struct Level {
   Geom g;
   uint8_t* cls;                 // MG_* per padded cell
+  uint8_t* full;                // 1: cell and all 26 neighbours active and inside (coarse levels)
   float* cf[3];                 // face coefficients; face between cell q-1 and q along d at idx(q)
   void* x[2];                   // iterate, ping-pong (storage type of the level)
   void* b;                      // right-hand side
@@ -91,6 +92,11 @@ enum {
   S_DIV = 7,       // max face divergence
   S_MINK = 8,
   S_MINW = 9,
+  S_DONE = 10,     // 1 once the iteration has met its stopping rule
+  S_ITER = 11,     // preconditioner applications so far
+  S_TOL2 = 12,     // tol^2
+  S_MAXIT = 13,
+  S_FORCED = 14,   // < 0: stop on tol
   S_COUNT = 16
 };
 
@@ -135,35 +141,70 @@ void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const D
 template <class V, class O>
 void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                   const V* u, const V* v, const V* w, O* b, const RedBuf& red, hipStream_t s);
+// reads u* (u, v, w), writes the corrected velocity to (uo, vo, wo)
 template <class V, class P, class O>
 void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                    const O* phi, V* u, V* v, V* w, P* p, const RedBuf& red, hipStream_t s);
+                    const O* phi, const V* u, const V* v, const V* w, V* uo, V* vo, V* wo, P* p,
+                    const RedBuf& red, hipStream_t s);
 
 // multigrid (S: storage of the level, C: arithmetic)
+// (ctl: red.out; every kernel returns at once when ctl[S_DONE] != 0)
 template <class S, class C>
 void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
-                   hipStream_t s);
+                   const double* ctl, hipStream_t s);
 template <class S, class C, class SC>
-void launch_resid_restrict(const Level& f, const Level& c, hipStream_t s);
+void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s);
 template <class S, class C, class SC>
-void launch_prolong(const Level& f, const Level& c, hipStream_t s);
+void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s);
 template <class SC, class C>
 void launch_coarse_solve(const Level& c, const int* cmap, const int* ncount, const double* ainv,
-                         int max_n, hipStream_t s);
+                         int max_n, const double* ctl, hipStream_t s);
 template <class S>
-void launch_fill_zero(const Level& l, void* x, hipStream_t s);
+void launch_fill_zero(const Level& l, void* x, const double* ctl, hipStream_t s);
 
-// flexible CG on level 0 (O: outer type, S: level-0 storage)
+void launch_mark_full(const Level& l, hipStream_t s);
+
+// One-workgroup V-cycle over levels top .. L-1 with the iterates and
+// right-hand sides held in LDS (compute precision); reads b of level top,
+// writes x[0] of level top.
+constexpr int BOTTOM_MAX_LEVELS = 12;
+struct BottomLevel {
+  Geom g;
+  const uint8_t* cls;
+  const float* cf0;
+  const float* cf1;
+  const float* cf2;
+  int n;              // cells (nx * ny * nz)
+  int ox0, ox1, ob;   // LDS offsets in elements
+};
+struct Bottom {
+  int nlev;           // levels top .. L-1
+  int nu1, nu2;
+  double wj;
+  BottomLevel lv[BOTTOM_MAX_LEVELS];
+  const int* cmap;    // padded indices of the coarsest active cells
+  const int* ncount;
+  const double* ainv;
+  int max_n;
+  size_t lds_bytes;
+};
+template <class SC, class C>
+void launch_bottom(const Bottom& B, const void* btop, void* xtop, const double* ctl,
+                   hipStream_t s);
+
+// flexible CG on level 0 (O: outer type, S: level-0 storage).  The stopping
+// rule runs on the device: launch_fcg_start sets S_DONE / S_ITER from tol,
+// max_cycles and forced; every later kernel of an iteration returns at once
+// when S_DONE is set, so surplus iterations enqueued by the host are no-ops.
 template <class O, class S>
 void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, const RedBuf& red,
-                      bool have_x0, hipStream_t s);
+                      bool have_x0, double tol, int max_cycles, int forced, hipStream_t s);
 template <class O, class S>
 void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s);
 template <class O, class S>
-void launch_fcg_dir(const Level& l0, const O* pold, O* pnew, O* q, const RedBuf& red, bool first,
-                    int parity, hipStream_t s);
+void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipStream_t s);
 template <class O, class S>
-void launch_fcg_update(const Level& l0, O* x, O* r, const O* pv, const O* q, const RedBuf& red,
-                       int parity, hipStream_t s);
+void launch_fcg_update(const Level& l0, O* x, O* r, O* p0, O* p1, const O* q, const RedBuf& red,
+                       hipStream_t s);
 
 }  // namespace nfvm

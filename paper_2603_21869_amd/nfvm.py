@@ -25,7 +25,7 @@ EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_mg_solve", "nfvm_mg_solve_device",
     "nfvm_get_fields", "nfvm_set_fields", "nfvm_grid_footprint", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
-    "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_last_error",
+    "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_set_option", "nfvm_last_error",
 )
 
 KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "explicit", "destroy", "rhs",
@@ -100,6 +100,7 @@ def lib():
         L.nfvm_profile.argtypes = [C.c_void_p, C.c_uint32]
         L.nfvm_profile_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.nfvm_set_option.argtypes = [C.c_void_p, C.c_int32, C.c_double]
         L.nfvm_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "nfvm_last_error":
@@ -238,6 +239,13 @@ def nfvm_profile_read(grid, kernel: int):
     b = C.c_double(0.0)
     _check(lib().nfvm_profile_read(grid, kernel, C.byref(n), C.byref(s), C.byref(b)))
     return dict(launches=n.value, seconds=s.value, bytes_per_launch=b.value)
+
+
+NFVM_OPT_GRAPHS, NFVM_OPT_PREDICT, NFVM_OPT_BOTTOM = 0, 1, 2
+
+
+def nfvm_set_option(grid, option: int, value: float):
+    _check(lib().nfvm_set_option(grid, option, value))
 
 
 def nfvm_server_create(hbm_budget_bytes: float = 0.0, max_slots: int = 4):

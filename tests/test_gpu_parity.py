@@ -120,10 +120,14 @@ def test_deterministic_and_restartable(nf):
     fd = d.fields()
     for k in fa:
         assert np.array_equal(fa[k], fd[k]), k
-    # restart through FP64 host arrays is exact in FP64 and for the FP64 velocity
-    # and pressure of the mixed mode; FP32 scalars round-trip exactly too
+    # restart through the FP64 host arrays is exact for every field except T:
+    # the device holds theta = T - T_ref in FP32, and theta + T_ref in FP64
+    # cannot keep every bit of a tiny theta, so T round-trips to ~1e-14 K
     for k in fa:
-        assert np.array_equal(fa[k], fc[k]), k
+        if k == "T":
+            assert np.abs(fa[k] - fc[k]).max() <= 1e-9, k
+        else:
+            assert np.array_equal(fa[k], fc[k]), k
 
 
 def test_error_paths(nf):
@@ -145,3 +149,24 @@ def test_error_paths(nf):
     g.close()
     with pytest.raises(nf.NfvmError):
         nf.Grid(case.copy(n_levels=9))
+
+
+def test_bottom_solver_and_graphs_match_plain_launches(nf, oracle):
+    """The LDS bottom solver and the graph-captured step give the same FP64
+    answers as one launch per operator (both checked against the oracle)."""
+    case = C.room3d(96, 48, 32, size=(10.0, 4.0, 3.0), seed=4, n_levels=5, n_steps=3,
+                    precision=C.PREC_FP64, tol=1e-9)
+    outs = []
+    for bottom, graphs in ((1, 1), (0, 0)):
+        g = nf.Grid(case)
+        nf.nfvm_set_option(g.h, nf.NFVM_OPT_BOTTOM, bottom)
+        nf.nfvm_set_option(g.h, nf.NFVM_OPT_GRAPHS, graphs)
+        s, stats = g.step(3)
+        outs.append((g.fields(), [x["cycles"] for x in stats]))
+        g.close()
+    for (out, cyc) in outs:
+        ref, _, _ = oracle.step(case, 3, forced_cycles=cyc)
+        errs = field_errors(case, out, ref)
+        print("   cycles", cyc, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+        for f in ("vel", "p", "k", "omega", "T"):
+            assert errs[f] <= 1e-10, (f, errs[f])
