@@ -101,7 +101,20 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB five times (for "
+                         "scaling hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration_mb:
+        import torch
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 5}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -174,6 +187,7 @@ def main():
                     for k, v in kernel_table.items()},
         "variants": variants,
         "stream_launch_ms_per_step": round(psec / args.steps * 1e3, 4),
+        "tuning": [list(t) for t in nfvm.nfvm_tuning_table()],
         "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
                          "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",
     }

@@ -231,8 +231,17 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
  *   NFVM_OPT_BOTTOM   1 (default): the coarse levels whose iterates fit in
  *                     64 KiB of LDS run as one workgroup in one launch;
  *                     0: one launch per operator and level.
+ *   NFVM_OPT_AUTOTUNE 1 (default, applied in nfvm_init_grid): the tile shape
+ *                     (workgroups per launch, planes per thread) of every hot
+ *                     kernel is chosen per level by timing candidates on the
+ *                     grid; results are cached per shape and precision for
+ *                     the process.  0: fixed default tiles.
  * Errors: NFVM_E_INVAL for an unknown option. */
-enum { NFVM_OPT_GRAPHS = 0, NFVM_OPT_PREDICT = 1, NFVM_OPT_BOTTOM = 2 };
+enum { NFVM_OPT_GRAPHS = 0, NFVM_OPT_PREDICT = 1, NFVM_OPT_BOTTOM = 2, NFVM_OPT_AUTOTUNE = 3 };
+
+/* The autotuner's choices so far: up to max entries of {kernel id, nx, ny,
+ * nz, dim, precision, tile target}; *count receives the number written. */
+nfvm_status nfvm_tuning_table(int32_t* entries, int32_t max, int32_t* count);
 nfvm_status nfvm_set_option(nfvm_grid_t grid, int32_t option, double value);
 
 /* Message for the last non-OK status on this thread. */

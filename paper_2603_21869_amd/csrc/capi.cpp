@@ -160,6 +160,26 @@ nfvm_status nfvm_set_option(nfvm_grid_t grid, int32_t option, double value) {
   });
 }
 
+nfvm_status nfvm_tuning_table(int32_t* entries, int32_t max, int32_t* count) {
+  if (!count || (max > 0 && !entries)) return fail(NFVM_E_INVAL, "count and entries are required");
+  auto all = tune_entries();
+  int n = 0;
+  for (const auto& kv : all) {
+    if (n >= max) break;
+    int32_t* e = entries + 7 * n;
+    e[0] = kv.first.kid;
+    e[1] = kv.first.nx;
+    e[2] = kv.first.ny;
+    e[3] = kv.first.nz;
+    e[4] = kv.first.dim;
+    e[5] = kv.first.prec;
+    e[6] = kv.second;
+    ++n;
+  }
+  *count = n;
+  return NFVM_OK;
+}
+
 const char* nfvm_last_error(void) { return t_err.c_str(); }
 
 }  // extern "C"

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 
 namespace nfvm {
@@ -104,6 +105,28 @@ size_t footprint_bytes(const nfvm_grid_desc& d) {
   b += (size_t)2 * COARSE_MAX * COARSE_MAX * 8 + COARSE_MAX * 4;  // dense coarse inverse
   b += MAX_PATCHES * sizeof(DevPatch) + 5 * 4 * MAX_PATCHES;
   return b;
+}
+
+// ---- autotuner cache ------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+
+bool tune_lookup(const TuneKey& k, int* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(k);
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void tune_store(const TuneKey& k, int v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[k] = v;
+}
+
+std::vector<std::pair<TuneKey, int>> tune_entries() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return std::vector<std::pair<TuneKey, int>>(g_tune.begin(), g_tune.end());
 }
 
 // ---- kernel timing ------------------------------------------------------------------
@@ -308,6 +331,7 @@ class GridT : public GridBase {
       for (int c = 0; c < 2; ++c) v.x[c] = alloc<uint8_t>(v.g.total * es);
       v.b = alloc<uint8_t>(v.g.total * es);
       v.cur = 0;
+      for (int t = 0; t < TK_LEVEL_COUNT; ++t) v.tt[t] = TILE_DEFAULT;
       if (l == 0)
         launch_level0(v.g, type, patches, v.cls, v.cf[0], v.cf[1], d.dim == 3 ? v.cf[2] : v.cf[0],
                       stream);
@@ -342,7 +366,134 @@ class GridT : public GridBase {
     red.counter = alloc<unsigned>(16);
     red.out = alloc<double>(S_COUNT);
 
+    for (int t = 0; t < TP_COUNT; ++t) tp[t] = TILE_DEFAULT;
+    if (use_autotune) autotune();
     if (init) set_fields(init);
+    NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  // ---- autotuner: for every tunable kernel and level, time a few tile
+  // targets on this grid and keep the fastest (cached per shape and
+  // precision for the process).
+  int tp[TP_COUNT];
+
+  template <class Fn>
+  float time_it(Fn&& fn) {
+    fn();  // warm
+    NFVM_CK(hipEventRecord(ev0, stream));
+    for (int r = 0; r < 3; ++r) fn();
+    NFVM_CK(hipEventRecord(ev1, stream));
+    NFVM_CK(hipEventSynchronize(ev1));
+    float ms = 0;
+    NFVM_CK(hipEventElapsedTime(&ms, ev0, ev1));
+    return ms;
+  }
+
+  template <class Fn>
+  int tune_one(int kid, const Geom& gg, Fn&& launch) {
+    const int cand[] = {512, 2048, 8192, 1 << 30};
+    TuneKey key{kid, gg.nx, gg.ny, gg.nz, desc.dim, desc.precision};
+    int cached;
+    if (tune_lookup(key, &cached)) return cached;
+    int best = TILE_DEFAULT;
+    float bt = 1e30f;
+    for (int c : cand) {
+      const float t = time_it([&] { launch(c); });
+      if (t < bt) {
+        bt = t;
+        best = c;
+      }
+    }
+    tune_store(key, best);
+    return best;
+  }
+
+  void autotune() {
+    NFVM_CK(hipStreamSynchronize(stream));
+    // physics kernels first: phi is still zero, so the projection leaves p alone
+    {
+      FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
+      FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
+      tp[TP_EXPLICIT] = tune_one(100 + TP_EXPLICIT, g, [&](int tt) {
+        launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, tt, stream);
+      });
+      tp[TP_DESTROY] = tune_one(100 + TP_DESTROY, g, [&](int tt) {
+        launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
+                             0.0, salt(4), salt(5), nullptr, tt, stream);
+      });
+      tp[TP_RHS] = tune_one(100 + TP_RHS, g, [&](int tt) {
+        launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red, tt, stream);
+      });
+      tp[TP_PROJECT] = tune_one(100 + TP_PROJECT, g, [&](int tt) {
+        launch_project<V, P, O>(g, ph, type, patches, phi, vcur(0), vcur(1), vcur(2), valt(0),
+                                valt(1), valt(2), p, red, tt, stream);
+      });
+    }
+    const int last = bottom_top >= 0 ? bottom_top : L - 1;  // levels with per-level kernels
+    for (int l = 0; l < last; ++l) {
+      Level& v = lv[l];
+      if (l == 0) {
+        v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH, v.g, [&](int tt) {
+          v.tt[TK_SMOOTH] = tt;
+          launch_smooth<S0, C>(v, v.x[0], v.x[1], wj, false, red.out, stream);
+        });
+        v.tt[TK_SMOOTH_ZERO] = tune_one(TK_SMOOTH_ZERO, v.g, [&](int tt) {
+          v.tt[TK_SMOOTH_ZERO] = tt;
+          launch_smooth<S0, C>(v, nullptr, v.x[0], wj, true, red.out, stream);
+        });
+        v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT, v.g, [&](int tt) {
+          v.tt[TK_RESTRICT] = tt;
+          launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream);
+        });
+        v.tt[TK_PROLONG] = tune_one(TK_PROLONG, v.g, [&](int tt) {
+          v.tt[TK_PROLONG] = tt;
+          launch_prolong<S0, C, SC>(lv[0], lv[1], red.out, stream);
+        });
+        v.tt[TK_START] = tune_one(TK_START, v.g, [&](int tt) {
+          v.tt[TK_START] = tt;
+          launch_fcg_start<O, S0>(v, bvec, x0, r, phi, red, false, 1.0, 1, -1, stream, false);
+        });
+        v.tt[TK_DOTS] = tune_one(TK_DOTS, v.g, [&](int tt) {
+          v.tt[TK_DOTS] = tt;
+          launch_fcg_dots<O, S0>(v, r, q, red, stream, false);
+        });
+        v.tt[TK_DIR] = tune_one(TK_DIR, v.g, [&](int tt) {
+          v.tt[TK_DIR] = tt;
+          launch_fcg_dir<O, S0>(v, pv[0], pv[1], q, red, stream, false);
+        });
+        v.tt[TK_UPDATE] = tune_one(TK_UPDATE, v.g, [&](int tt) {
+          v.tt[TK_UPDATE] = tt;
+          launch_fcg_update<O, S0>(v, phi, r, pv[0], pv[1], q, red, stream, false);
+        });
+      } else {
+        v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + 1000, v.g, [&](int tt) {
+          v.tt[TK_SMOOTH] = tt;
+          launch_smooth<SC, C>(v, v.x[0], v.x[1], wj, false, red.out, stream);
+        });
+        v.tt[TK_SMOOTH_ZERO] = tune_one(TK_SMOOTH_ZERO + 1000, v.g, [&](int tt) {
+          v.tt[TK_SMOOTH_ZERO] = tt;
+          launch_smooth<SC, C>(v, nullptr, v.x[0], wj, true, red.out, stream);
+        });
+        v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT + 1000, v.g, [&](int tt) {
+          v.tt[TK_RESTRICT] = tt;
+          launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
+        });
+        v.tt[TK_PROLONG] = tune_one(TK_PROLONG + 1000, v.g, [&](int tt) {
+          v.tt[TK_PROLONG] = tt;
+          launch_prolong<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
+        });
+      }
+    }
+    NFVM_CK(hipGetLastError());
+    // leave every buffer the tuning touched as a fresh grid has it
+    const size_t ob = (size_t)g.total * sizeof(O);
+    for (O* bufp : {bvec, phi, r, pv[0], pv[1], q, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
+    for (int l = 0; l < L; ++l) {
+      const size_t es = (size_t)lv[l].g.total * (l == 0 ? sizeof(S0) : sizeof(SC));
+      for (int c = 0; c < 2; ++c) NFVM_CK(hipMemsetAsync(lv[l].x[c], 0, es, stream));
+      NFVM_CK(hipMemsetAsync(lv[l].b, 0, es, stream));
+    }
+    NFVM_CK(hipMemsetAsync(red.out, 0, S_COUNT * sizeof(double), stream));
     NFVM_CK(hipStreamSynchronize(stream));
   }
 
@@ -616,7 +767,7 @@ class GridT : public GridBase {
     if (ph.komega) {
       prof_begin(NFVM_K_DESTROY);
       launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
-                           half, salt(4), salt(5), nullptr, stream);
+                           half, salt(4), salt(5), nullptr, tp[TP_DESTROY], stream);
       prof_end(NFVM_K_DESTROY);
       swap(4);
       swap(5);
@@ -624,11 +775,12 @@ class GridT : public GridBase {
     FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
     FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
     prof_begin(NFVM_K_EXPLICIT);
-    launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, stream);
+    launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, tp[TP_EXPLICIT], stream);
     prof_end(NFVM_K_EXPLICIT);
     for (int f = 0; f < 6; ++f) swap(f);
     prof_begin(NFVM_K_RHS);
-    launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red, stream);
+    launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red,
+                       tp[TP_RHS], stream);
     prof_end(NFVM_K_RHS);
     launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, false, tol, max_cycles, -1, stream);
   }
@@ -638,7 +790,7 @@ class GridT : public GridBase {
     const double half = 0.5 * ph.dt;
     prof_begin(NFVM_K_PROJECT);
     launch_project<V, P, O>(g, ph, type, patches, phi, vcur(0), vcur(1), vcur(2), valt(0),
-                            valt(1), valt(2), p, red, stream);
+                            valt(1), valt(2), p, red, tp[TP_PROJECT], stream);
     prof_end(NFVM_K_PROJECT);
     swap(0);
     swap(1);
@@ -646,7 +798,7 @@ class GridT : public GridBase {
     if (ph.komega) {
       prof_begin(NFVM_K_DESTROY);
       launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
-                           half, salt(4), salt(5), &red, stream);
+                           half, salt(4), salt(5), &red, tp[TP_DESTROY], stream);
       prof_end(NFVM_K_DESTROY);
       swap(4);
       swap(5);
@@ -725,6 +877,17 @@ class GridT : public GridBase {
       use_graphs = v != 0.0;
     } else if (opt == NFVM_OPT_PREDICT) {
       predicted = std::max(1, (int)v);
+    } else if (opt == NFVM_OPT_AUTOTUNE) {
+      use_autotune = v != 0.0;
+      if (!use_autotune) {
+        for (auto& lvl : lv)
+          for (int t = 0; t < TK_LEVEL_COUNT; ++t) lvl.tt[t] = TILE_DEFAULT;
+        for (int t = 0; t < TP_COUNT; ++t) tp[t] = TILE_DEFAULT;
+      } else {
+        autotune();
+      }
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
     } else if (opt == NFVM_OPT_BOTTOM) {
       NFVM_CK(hipStreamSynchronize(stream));
       drop_graphs();

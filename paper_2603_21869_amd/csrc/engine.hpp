@@ -5,6 +5,7 @@
 
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/nfvm.h"
@@ -56,6 +57,17 @@ struct DevBuf {
 };
 
 size_t footprint_bytes(const nfvm_grid_desc& d);
+
+// autotuner results, per kernel, level shape, dimension and precision
+struct TuneKey {
+  int kid, nx, ny, nz, dim, prec;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(kid, nx, ny, nz, dim, prec) < std::tie(o.kid, o.nx, o.ny, o.nz, o.dim, o.prec);
+  }
+};
+bool tune_lookup(const TuneKey& k, int* v);
+void tune_store(const TuneKey& k, int v);
+std::vector<std::pair<TuneKey, int>> tune_entries();
 void validate_desc(const nfvm_grid_desc& d);
 
 class GridBase {
@@ -69,6 +81,7 @@ class GridBase {
   virtual void set_option(int opt, double v) = 0;
   bool use_graphs = true;
   bool use_bottom = true;
+  bool use_autotune = true;
   // kernel timing (nfvm_profile)
   struct ProfRec {
     int kid;

@@ -88,73 +88,159 @@ __device__ __forceinline__ void apply_at(const LevelView& L, uint8_t cl, const S
   D = d;
 }
 
+// Tiles of a level for the column-walking kernels below.
+__host__ inline Tiles lvl_tiles(const Level& l, int kid) {
+  return make_tiles(l.g.nx, l.g.ny, l.g.nz, l.tt[kid]);
+}
+
+// A x and the diagonal at cell P, z neighbours given (the walking kernels
+// keep them in registers).
+template <class S, class C>
+__device__ __forceinline__ void apply_z(const LevelView& L, uint8_t cl, const S* __restrict__ x,
+                                        int P, C xP, C xm, C xp, C& Ax, C& D) {
+  const Geom& g = L.g;
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
+  const bool d3 = g.dim == 3;
+  if (cl == MG_REGULAR) {
+    C s = ((C)2 * xP - St<S, C>::ld(x + P - 1) - St<S, C>::ld(x + P + 1)) * ih2x +
+          ((C)2 * xP - St<S, C>::ld(x + P - g.sx) - St<S, C>::ld(x + P + g.sx)) * ih2y;
+    C d = (C)2 * (ih2x + ih2y);
+    if (d3) {
+      s += ((C)2 * xP - xm - xp) * ih2z;
+      d += (C)2 * ih2z;
+    }
+    Ax = s;
+    D = d;
+    return;
+  }
+  const C cxl = (C)L.cf0[P], cxh = (C)L.cf0[P + 1];
+  const C cyl = (C)L.cf1[P], cyh = (C)L.cf1[P + g.sx];
+  C s = (cxl * (xP - St<S, C>::ld(x + P - 1)) + cxh * (xP - St<S, C>::ld(x + P + 1))) * ih2x +
+        (cyl * (xP - St<S, C>::ld(x + P - g.sx)) + cyh * (xP - St<S, C>::ld(x + P + g.sx))) * ih2y;
+  C d = (cxl + cxh) * ih2x + (cyl + cyh) * ih2y;
+  if (d3) {
+    const C czl = (C)L.cf2[P], czh = (C)L.cf2[P + g.sxy];
+    s += (czl * (xP - xm) + czh * (xP - xp)) * ih2z;
+    d += (czl + czh) * ih2z;
+  }
+  Ax = s;
+  D = d;
+}
+
 // ---- damped Jacobi sweep: x_out = x_in + w (b - A x_in) / D -------------------
+// Each thread walks cz planes of one column with x(k-1), x(k), x(k+1) in
+// registers; in-plane neighbours come through the cache.
 template <class S, class C, bool ZERO>
-__global__ __launch_bounds__(MBS) void k_smooth(LevelView L, const S* __restrict__ xin,
+__global__ __launch_bounds__(MBS) void k_smooth(LevelView L, Tiles T, const S* __restrict__ xin,
                                                 S* __restrict__ xout, const S* __restrict__ b,
                                                 C wj, const double* __restrict__ ctl) {
   if (ctl[S_DONE] != 0.0) return;
-  const int i = blockIdx.x * MBX + threadIdx.x, j = blockIdx.y * MBY + threadIdx.y, k = blockIdx.z;
-  if (i >= L.g.nx || j >= L.g.ny) return;
-  const int P = L.g.idx(i, j, k);
-  const uint8_t cl = L.cls[P];
-  if (cl == MG_INACTIVE) return;
-  const C bP = St<S, C>::ld(b + P);
-  C Ax, D;
-  if (ZERO) {
-    // A applied to zero: only the diagonal matters
-    C tmp;
-    apply_at<S, C>(L, cl, b, P, (C)0, tmp, D);
-    St<S, C>::st(xout + P, wj * bP / D);
-  } else {
-    const C xP = St<S, C>::ld(xin + P);
-    apply_at<S, C>(L, cl, xin, P, xP, Ax, D);
-    St<S, C>::st(xout + P, xP + wj * (bP - Ax) / D);
+  int tx, ty, tz;
+  if (!tile_of(T, tx, ty, tz)) return;
+  const Geom& g = L.g;
+  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+  const bool d3 = g.dim == 3;
+  int P = g.idx(i, j, k0);
+  C xm = 0, xc = 0;
+  if (!ZERO) {
+    xc = St<S, C>::ld(xin + P);
+    if (d3) xm = St<S, C>::ld(xin + P - g.sxy);
+  }
+  for (int k = k0; k < k1; ++k, P += g.sxy) {
+    C xp = 0;
+    if (!ZERO && d3) xp = St<S, C>::ld(xin + P + g.sxy);
+    const uint8_t cl = L.cls[P];
+    if (cl != MG_INACTIVE) {
+      const C bP = St<S, C>::ld(b + P);
+      C Ax, D;
+      if (ZERO) {
+        apply_z<S, C>(L, cl, b, P, (C)0, (C)0, (C)0, Ax, D);
+        St<S, C>::st(xout + P, wj * bP / D);
+      } else {
+        apply_z<S, C>(L, cl, xin, P, xc, xm, xp, Ax, D);
+        St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
+      }
+    }
+    xm = xc;
+    xc = xp;
   }
 }
 
 template <class S, class C>
 void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                    const double* ctl, hipStream_t s) {
+  const Tiles T = lvl_tiles(l, from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH);
   if (from_zero)
-    hipLaunchKernelGGL((k_smooth<S, C, true>), lvl_grid(l.g), dim3(MBX, MBY), 0, s, view(l),
+    hipLaunchKernelGGL((k_smooth<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
                        (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
   else
-    hipLaunchKernelGGL((k_smooth<S, C, false>), lvl_grid(l.g), dim3(MBX, MBY), 0, s, view(l),
+    hipLaunchKernelGGL((k_smooth<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
                        (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
 }
 
 // ---- residual and restriction: b_c = mean over the 2^dim children of (b - A x)
+// One thread per fine column (64 x 4 fine columns = 32 x 2 coarse columns per
+// workgroup), walking fine planes in pairs; the 2 x 2 in-plane sum uses a
+// lane exchange (x) and LDS (y).  Tiles count coarse planes along z.
 template <class S, class C, class SC>
-__global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, const S* __restrict__ x,
+__global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, Tiles T,
+                                                        const S* __restrict__ x,
                                                         const S* __restrict__ b, LevelView Cl,
                                                         SC* __restrict__ bc,
                                                         const double* __restrict__ ctl) {
   if (ctl[S_DONE] != 0.0) return;
-  const int I = blockIdx.x * MBX + threadIdx.x, J = blockIdx.y * MBY + threadIdx.y, K = blockIdx.z;
-  if (I >= Cl.g.nx || J >= Cl.g.ny) return;
-  const int PC = Cl.g.idx(I, J, K);
-  if (Cl.cls[PC] == MG_INACTIVE) return;
-  const int kz = Cl.g.dim == 3 ? 2 : 1;
-  C sum = 0;
-  for (int cc = 0; cc < kz; ++cc)
-    for (int bb = 0; bb < 2; ++bb)
-      for (int a = 0; a < 2; ++a) {
-        const int P = F.g.idx(2 * I + a, 2 * J + bb, kz * K + cc);
+  __shared__ C sh[MBY][MBX];
+  int tx, ty, tz;
+  if (!tile_of(T, tx, ty, tz)) return;  // uniform over the workgroup
+  const Geom& g = F.g;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int i = tx * MBX + lx, j = ty * MBY + ly;
+  const bool in = i < g.nx && j < g.ny;
+  const bool d3 = g.dim == 3;
+  const int K0 = tz * T.cz, K1 = min(Cl.g.nz, K0 + T.cz);
+  const int kz = d3 ? 2 : 1;
+  int P = in ? g.idx(i, j, kz * K0) : 0;
+  C xm = 0, xc = 0;
+  if (in) {
+    xc = St<S, C>::ld(x + P);
+    if (d3) xm = St<S, C>::ld(x + P - g.sxy);
+  }
+  for (int K = K0; K < K1; ++K) {
+    C r = 0;
+    for (int c = 0; c < kz; ++c, P += g.sxy) {
+      C xp = 0;
+      if (in) {
+        if (d3) xp = St<S, C>::ld(x + P + g.sxy);
         const uint8_t cl = F.cls[P];
-        if (cl == MG_INACTIVE) continue;
-        const C xP = St<S, C>::ld(x + P);
-        C Ax, D;
-        apply_at<S, C>(F, cl, x, P, xP, Ax, D);
-        sum += St<S, C>::ld(b + P) - Ax;
+        if (cl != MG_INACTIVE) {
+          C Ax, D;
+          apply_z<S, C>(F, cl, x, P, xc, xm, xp, Ax, D);
+          r += St<S, C>::ld(b + P) - Ax;
+        }
       }
-  St<SC, C>::st(bc + PC, sum * (C)(kz == 2 ? 0.125 : 0.25));
+      xm = xc;
+      xc = xp;
+    }
+    r += __shfl_xor(r, 1);
+    sh[ly][lx] = r;
+    __syncthreads();
+    if (in && !(lx & 1) && !(ly & 1)) {
+      const int PC = Cl.g.idx(i >> 1, j >> 1, K);
+      if (Cl.cls[PC] != MG_INACTIVE)
+        St<SC, C>::st(bc + PC, (sh[ly][lx] + sh[ly + 1][lx]) * (C)(d3 ? 0.125 : 0.25));
+    }
+    __syncthreads();
+  }
 }
 
 template <class S, class C, class SC>
 void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_resid_restrict<S, C, SC>), lvl_grid(c.g), dim3(MBX, MBY), 0, s, view(f),
-                     (const S*)f.x[f.cur], (const S*)f.b, view(c), (SC*)c.b, ctl);
+  const Tiles T = make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_RESTRICT]);
+  hipLaunchKernelGGL((k_resid_restrict<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f),
+                     T, (const S*)f.x[f.cur], (const S*)f.b, view(c), (SC*)c.b, ctl);
 }
 
 // ---- prolongation and correction: x_f += PROL(e_c) ------------------------------
@@ -169,14 +255,18 @@ __device__ __forceinline__ bool act_at(const LevelView& L, int i, int j, int k) 
 }
 
 template <class S, class C, class SC>
-__global__ __launch_bounds__(MBS) void k_prolong(LevelView F, S* __restrict__ x, LevelView Cl,
-                                                 const SC* __restrict__ e,
+__global__ __launch_bounds__(MBS) void k_prolong(LevelView F, Tiles T, S* __restrict__ x,
+                                                 LevelView Cl, const SC* __restrict__ e,
                                                  const double* __restrict__ ctl) {
   if (ctl[S_DONE] != 0.0) return;
-  const int i = blockIdx.x * MBX + threadIdx.x, j = blockIdx.y * MBY + threadIdx.y, k = blockIdx.z;
+  int tx, ty, tz;
+  if (!tile_of(T, tx, ty, tz)) return;
+  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
   if (i >= F.g.nx || j >= F.g.ny) return;
+  const int k0 = tz * T.cz, k1 = min(F.g.nz, k0 + T.cz);
+  for (int k = k0; k < k1; ++k) {
   const int P = F.g.idx(i, j, k);
-  if (F.cls[P] == MG_INACTIVE) return;
+  if (F.cls[P] == MG_INACTIVE) continue;
   const Geom& cg = Cl.g;
   const bool d3 = cg.dim == 3;
   const int I = i >> 1, J = j >> 1, K = d3 ? (k >> 1) : 0;
@@ -202,7 +292,7 @@ __global__ __launch_bounds__(MBS) void k_prolong(LevelView F, S* __restrict__ x,
       Z = Y0;
     }
     St<S, C>::st(x + P, St<S, C>::ld(x + P) + Z);
-    return;
+    continue;
   }
   C X[2][2] = {{0, 0}, {0, 0}};
   const int nzc = d3 ? 2 : 1;
@@ -251,11 +341,13 @@ __global__ __launch_bounds__(MBS) void k_prolong(LevelView F, S* __restrict__ x,
     Z = w3 * Y[0] + w1 * zn;
   }
   St<S, C>::st(x + P, St<S, C>::ld(x + P) + Z);
+  }
 }
 
 template <class S, class C, class SC>
 void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_prolong<S, C, SC>), lvl_grid(f.g), dim3(MBX, MBY), 0, s, view(f),
+  const Tiles T = lvl_tiles(f, TK_PROLONG);
+  hipLaunchKernelGGL((k_prolong<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f), T,
                      (S*)f.x[f.cur], view(c), (const SC*)c.x[c.cur], ctl);
 }
 
@@ -305,33 +397,41 @@ void launch_fill_zero(const Level& l, void* x, const double* ctl, hipStream_t s)
 // Vectors x (phi), r, p (two buffers, alternating by iteration parity), q in
 // the outer precision O; z is the V-cycle result in the level-0 storage S; the
 // level-0 right-hand side of the next V-cycle is r rounded to S.  Scalars and
-// the stopping state live in red.out (ctl).
+// the stopping state live in red.out (ctl).  Every kernel walks column tiles
+// and writes one partial per workgroup (tiles outside the grid write zeros).
 
 // r = b - A x0 (x0 = 0 unless given), x = x0 on active cells, 0 elsewhere.
 template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_start(LevelView L, const O* __restrict__ b,
+__global__ __launch_bounds__(MBS) void k_fcg_start(LevelView L, Tiles T, const O* __restrict__ b,
                                                    const O* __restrict__ x0, O* __restrict__ r,
                                                    O* __restrict__ x, S* __restrict__ b0,
                                                    int have_x0, RedBuf red) {
-  const int i = blockIdx.x * MBX + threadIdx.x, j = blockIdx.y * MBY + threadIdx.y, k = blockIdx.z;
+  int tx, ty, tz;
   double bb = 0.0, rr = 0.0;
-  if (i < L.g.nx && j < L.g.ny) {
-    const int P = L.g.idx(i, j, k);
-    const uint8_t cl = L.cls[P];
-    if (cl != MG_INACTIVE) {
-      const O bP = b[P];
-      O rP = bP, xP = 0;
-      if (have_x0) {
-        xP = x0[P];
-        O Ax, D;
-        apply_at<O, O>(L, cl, x0, P, xP, Ax, D);
-        rP = bP - Ax;
+  if (tile_of(T, tx, ty, tz)) {
+    const Geom& g = L.g;
+    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+    if (i < g.nx && j < g.ny) {
+      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+      for (int k = k0; k < k1; ++k) {
+        const int P = g.idx(i, j, k);
+        const uint8_t cl = L.cls[P];
+        if (cl == MG_INACTIVE) continue;
+        const O bP = b[P];
+        O rP = bP, xP = 0;
+        if (have_x0) {
+          xP = x0[P];
+          const O xm = g.dim == 3 ? x0[P - g.sxy] : (O)0, xp = g.dim == 3 ? x0[P + g.sxy] : (O)0;
+          O Ax, D;
+          apply_z<O, O>(L, cl, x0, P, xP, xm, xp, Ax, D);
+          rP = bP - Ax;
+        }
+        r[P] = rP;
+        x[P] = xP;
+        St<S, O>::st(b0 + P, rP);
+        bb += (double)bP * (double)bP;
+        rr += (double)rP * (double)rP;
       }
-      r[P] = rP;
-      x[P] = xP;
-      St<S, O>::st(b0 + P, rP);
-      bb = (double)bP * (double)bP;
-      rr = (double)rP * (double)rP;
     }
   }
   double vv[2] = {bb, rr};
@@ -351,15 +451,21 @@ __device__ __forceinline__ void fcg_judge(double* ctl) {
   ctl[S_DONE] = done ? 1.0 : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_fin_start(RedBuf red, int nb, double tol2, double maxit,
+constexpr int FIN = 1024;  // threads of the finalising workgroup
+
+template <int NV>
+__device__ __forceinline__ void fin_sum(const RedBuf& red, int nb, double (&acc)[NV]) {
+  __shared__ double sh[NV][FIN];
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < nb; i += FIN)
+    for (int q = 0; q < NV; ++q) acc[q] += red.partial[(size_t)i * NV + q];
+  block_tree<NV, R_SUM, FIN>(acc, sh);
+}
+
+__global__ __launch_bounds__(FIN) void k_fin_start(RedBuf red, int nb, double tol2, double maxit,
                                                    double forced) {
-  __shared__ double sh[2][256];
-  double acc[2] = {0.0, 0.0};
-  for (int i = threadIdx.x; i < nb; i += 256) {
-    acc[0] += red.partial[(size_t)i * 2];
-    acc[1] += red.partial[(size_t)i * 2 + 1];
-  }
-  block_tree<2, R_SUM, 256>(acc, sh);
+  double acc[2];
+  fin_sum<2>(red, nb, acc);
   if (threadIdx.x == 0) {
     red.out[S_BB] = acc[0];
     red.out[S_RR] = acc[1];
@@ -373,28 +479,36 @@ __global__ __launch_bounds__(256) void k_fin_start(RedBuf red, int nb, double to
 
 template <class O, class S>
 void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, const RedBuf& red,
-                      bool have_x0, double tol, int max_cycles, int forced, hipStream_t s) {
-  const dim3 gr = lvl_grid(l0.g);
-  hipLaunchKernelGGL((k_fcg_start<O, S>), gr, dim3(MBX, MBY), 0, s, view(l0), b, x0, r, x,
-                     (S*)l0.b, have_x0 ? 1 : 0, red);
-  hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(256), 0, s, red, (int)(gr.x * gr.y * gr.z),
-                     tol * tol, (double)max_cycles, (double)forced);
+                      bool have_x0, double tol, int max_cycles, int forced, hipStream_t s,
+                      bool fin) {
+  const Tiles T = lvl_tiles(l0, TK_START);
+  hipLaunchKernelGGL((k_fcg_start<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, b, x0,
+                     r, x, (S*)l0.b, have_x0 ? 1 : 0, red);
+  if (fin)
+    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(FIN), 0, s, red, T.grid, tol * tol,
+                       (double)max_cycles, (double)forced);
 }
 
 // (z, r) and (z, q_prev)
 template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_dots(LevelView L, const S* __restrict__ z,
+__global__ __launch_bounds__(MBS) void k_fcg_dots(LevelView L, Tiles T, const S* __restrict__ z,
                                                   const O* __restrict__ r, const O* __restrict__ q,
                                                   RedBuf red) {
   if (red.out[S_DONE] != 0.0) return;
-  const int i = blockIdx.x * MBX + threadIdx.x, j = blockIdx.y * MBY + threadIdx.y, k = blockIdx.z;
+  int tx, ty, tz;
   double zr = 0.0, zq = 0.0;
-  if (i < L.g.nx && j < L.g.ny) {
-    const int P = L.g.idx(i, j, k);
-    if (L.cls[P] != MG_INACTIVE) {
-      const double zP = (double)St<S, O>::ld(z + P);
-      zr = zP * (double)r[P];
-      zq = zP * (double)q[P];
+  if (tile_of(T, tx, ty, tz)) {
+    const Geom& g = L.g;
+    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+    if (i < g.nx && j < g.ny) {
+      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+      for (int k = k0; k < k1; ++k) {
+        const int P = g.idx(i, j, k);
+        if (L.cls[P] == MG_INACTIVE) continue;
+        const double zP = (double)St<S, O>::ld(z + P);
+        zr += zP * (double)r[P];
+        zq += zP * (double)q[P];
+      }
     }
   }
   double vv[2] = {zr, zq};
@@ -404,15 +518,11 @@ __global__ __launch_bounds__(MBS) void k_fcg_dots(LevelView L, const S* __restri
 // sums of the last kernel's partials into slots (s0, s1); slot_par adds the
 // iteration parity to both slots
 template <int NV>
-__global__ __launch_bounds__(256) void k_fin_sum(RedBuf red, int nb, int s0, int s1,
+__global__ __launch_bounds__(FIN) void k_fin_sum(RedBuf red, int nb, int s0, int s1,
                                                  int slot_par) {
   if (red.out[S_DONE] != 0.0) return;
-  __shared__ double sh[NV][256];
   double acc[NV];
-  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-  for (int i = threadIdx.x; i < nb; i += 256)
-    for (int q = 0; q < NV; ++q) acc[q] += red.partial[(size_t)i * NV + q];
-  block_tree<NV, R_SUM, 256>(acc, sh);
+  fin_sum<NV>(red, nb, acc);
   if (threadIdx.x == 0) {
     const int par = slot_par ? ((int)red.out[S_ITER] & 1) : 0;
     red.out[s0 + par] = acc[0];
@@ -421,12 +531,12 @@ __global__ __launch_bounds__(256) void k_fin_sum(RedBuf red, int nb, int s0, int
 }
 
 template <class O, class S>
-void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s) {
-  const dim3 gr = lvl_grid(l0.g);
-  hipLaunchKernelGGL((k_fcg_dots<O, S>), gr, dim3(MBX, MBY), 0, s, view(l0),
+void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
+                     bool fin) {
+  const Tiles T = lvl_tiles(l0, TK_DOTS);
+  hipLaunchKernelGGL((k_fcg_dots<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T,
                      (const S*)l0.x[l0.cur], r, q, red);
-  hipLaunchKernelGGL(k_fin_sum<2>, dim3(1), dim3(256), 0, s, red, (int)(gr.x * gr.y * gr.z), S_ZR,
-                     S_ZQ, 0);
+  if (fin) hipLaunchKernelGGL(k_fin_sum<2>, dim3(1), dim3(FIN), 0, s, red, T.grid, S_ZR, S_ZQ, 0);
 }
 
 // p_new = z + beta p_old with beta = -alpha_prev (z, q_prev) / (z_prev, r_prev)
@@ -434,8 +544,8 @@ void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red,
 // computed from z and p_old at the neighbours; (p_new, q) into S_PQ0 + parity.
 // p_new is buffer (iteration parity), p_old the other one.
 template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_dir(LevelView L, const S* __restrict__ z, O* p0,
-                                                 O* p1, O* __restrict__ q, RedBuf red) {
+__global__ __launch_bounds__(MBS) void k_fcg_dir(LevelView L, Tiles T, const S* __restrict__ z,
+                                                 O* p0, O* p1, O* __restrict__ q, RedBuf red) {
   if (red.out[S_DONE] != 0.0) return;
   const int it = (int)red.out[S_ITER];
   const int par = it & 1;
@@ -443,30 +553,46 @@ __global__ __launch_bounds__(MBS) void k_fcg_dir(LevelView L, const S* __restric
   const O* __restrict__ pold = par ? p0 : p1;
   O* __restrict__ pnew = par ? p1 : p0;
   const O beta = first ? (O)0 : (O)(-red.out[S_ZQ] / red.out[par ? S_PQ0 : S_PQ1]);
-  const int i = blockIdx.x * MBX + threadIdx.x, j = blockIdx.y * MBY + threadIdx.y, k = blockIdx.z;
+  int tx, ty, tz;
   double pq = 0.0;
-  if (i < L.g.nx && j < L.g.ny) {
-    const int P = L.g.idx(i, j, k);
-    const uint8_t cl = L.cls[P];
-    if (cl != MG_INACTIVE) {
-      const Geom& g = L.g;
+  if (tile_of(T, tx, ty, tz)) {
+    const Geom& g = L.g;
+    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+    if (i < g.nx && j < g.ny) {
+      const bool d3 = g.dim == 3;
       auto pn = [&](int N) -> O {
         return St<S, O>::ld(z + N) + (first ? (O)0 : beta * pold[N]);
       };
-      const O pP = pn(P);
-      const O ih2[3] = {(O)(1.0 / (g.hx * g.hx)), (O)(1.0 / (g.hy * g.hy)),
-                        (O)(1.0 / (g.hz * g.hz))};
-      const int st[3] = {1, g.sx, g.sxy};
-      const float* cf[3] = {L.cf0, L.cf1, L.cf2};
-      O Ap = 0;
-      for (int d = 0; d < g.dim; ++d) {
-        const O cl_ = cl == MG_REGULAR ? (O)1 : (O)cf[d][P];
-        const O ch_ = cl == MG_REGULAR ? (O)1 : (O)cf[d][P + st[d]];
-        Ap += (cl_ * (pP - pn(P - st[d])) + ch_ * (pP - pn(P + st[d]))) * ih2[d];
+      const O ih2x = (O)(1.0 / (g.hx * g.hx)), ih2y = (O)(1.0 / (g.hy * g.hy)),
+              ih2z = (O)(1.0 / (g.hz * g.hz));
+      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+      int P = g.idx(i, j, k0);
+      O pm = d3 ? pn(P - g.sxy) : (O)0, pc = pn(P);
+      for (int k = k0; k < k1; ++k, P += g.sxy) {
+        const O pp = d3 ? pn(P + g.sxy) : (O)0;
+        const uint8_t cl = L.cls[P];
+        if (cl != MG_INACTIVE) {
+          O cxl = 1, cxh = 1, cyl = 1, cyh = 1, czl = 1, czh = 1;
+          if (cl != MG_REGULAR) {
+            cxl = (O)L.cf0[P];
+            cxh = (O)L.cf0[P + 1];
+            cyl = (O)L.cf1[P];
+            cyh = (O)L.cf1[P + g.sx];
+            if (d3) {
+              czl = (O)L.cf2[P];
+              czh = (O)L.cf2[P + g.sxy];
+            }
+          }
+          O Ap = (cxl * (pc - pn(P - 1)) + cxh * (pc - pn(P + 1))) * ih2x +
+                 (cyl * (pc - pn(P - g.sx)) + cyh * (pc - pn(P + g.sx))) * ih2y;
+          if (d3) Ap += (czl * (pc - pm) + czh * (pc - pp)) * ih2z;
+          pnew[P] = pc;
+          q[P] = Ap;
+          pq += (double)pc * (double)Ap;
+        }
+        pm = pc;
+        pc = pp;
       }
-      pnew[P] = pP;
-      q[P] = Ap;
-      pq = (double)pP * (double)Ap;
     }
   }
   double vv[1] = {pq};
@@ -474,35 +600,41 @@ __global__ __launch_bounds__(MBS) void k_fcg_dir(LevelView L, const S* __restric
 }
 
 template <class O, class S>
-void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipStream_t s) {
-  const dim3 gr = lvl_grid(l0.g);
-  hipLaunchKernelGGL((k_fcg_dir<O, S>), gr, dim3(MBX, MBY), 0, s, view(l0),
+void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipStream_t s,
+                    bool fin) {
+  const Tiles T = lvl_tiles(l0, TK_DIR);
+  hipLaunchKernelGGL((k_fcg_dir<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T,
                      (const S*)l0.x[l0.cur], p0, p1, q, red);
-  hipLaunchKernelGGL(k_fin_sum<1>, dim3(1), dim3(256), 0, s, red, (int)(gr.x * gr.y * gr.z),
-                     S_PQ0, S_PQ0, 1);
+  if (fin)
+    hipLaunchKernelGGL(k_fin_sum<1>, dim3(1), dim3(FIN), 0, s, red, T.grid, S_PQ0, S_PQ0, 1);
 }
 
 // alpha = (z, r)/(p, q); x += alpha p; r -= alpha q; ||r||^2; next V-cycle rhs.
 template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, O* __restrict__ x,
+__global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, Tiles T, O* __restrict__ x,
                                                     O* __restrict__ r, const O* p0, const O* p1,
                                                     const O* __restrict__ q, S* __restrict__ b0,
                                                     RedBuf red) {
   if (red.out[S_DONE] != 0.0) return;
   const int par = (int)red.out[S_ITER] & 1;
   const O* __restrict__ pv = par ? p1 : p0;
-  const double alpha = red.out[S_ZR] / red.out[par ? S_PQ1 : S_PQ0];
-  const int i = blockIdx.x * MBX + threadIdx.x, j = blockIdx.y * MBY + threadIdx.y, k = blockIdx.z;
+  const O a = (O)(red.out[S_ZR] / red.out[par ? S_PQ1 : S_PQ0]);
+  int tx, ty, tz;
   double rr = 0.0;
-  if (i < L.g.nx && j < L.g.ny) {
-    const int P = L.g.idx(i, j, k);
-    if (L.cls[P] != MG_INACTIVE) {
-      const O a = (O)alpha;
-      x[P] += a * pv[P];
-      const O rP = r[P] - a * q[P];
-      r[P] = rP;
-      St<S, O>::st(b0 + P, rP);
-      rr = (double)rP * (double)rP;
+  if (tile_of(T, tx, ty, tz)) {
+    const Geom& g = L.g;
+    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+    if (i < g.nx && j < g.ny) {
+      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+      for (int k = k0; k < k1; ++k) {
+        const int P = g.idx(i, j, k);
+        if (L.cls[P] == MG_INACTIVE) continue;
+        x[P] += a * pv[P];
+        const O rP = r[P] - a * q[P];
+        r[P] = rP;
+        St<S, O>::st(b0 + P, rP);
+        rr += (double)rP * (double)rP;
+      }
     }
   }
   double vv[1] = {rr};
@@ -510,12 +642,10 @@ __global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, O* __restrict__
 }
 
 // ||r||^2, one more iteration done, stopping rule
-__global__ __launch_bounds__(256) void k_fin_update(RedBuf red, int nb) {
+__global__ __launch_bounds__(FIN) void k_fin_update(RedBuf red, int nb) {
   if (red.out[S_DONE] != 0.0) return;
-  __shared__ double sh[1][256];
-  double acc[1] = {0.0};
-  for (int i = threadIdx.x; i < nb; i += 256) acc[0] += red.partial[i];
-  block_tree<1, R_SUM, 256>(acc, sh);
+  double acc[1];
+  fin_sum<1>(red, nb, acc);
   if (threadIdx.x == 0) {
     red.out[S_RR] = acc[0];
     red.out[S_ITER] += 1.0;
@@ -525,11 +655,11 @@ __global__ __launch_bounds__(256) void k_fin_update(RedBuf red, int nb) {
 
 template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p0, O* p1, const O* q, const RedBuf& red,
-                       hipStream_t s) {
-  const dim3 gr = lvl_grid(l0.g);
-  hipLaunchKernelGGL((k_fcg_update<O, S>), gr, dim3(MBX, MBY), 0, s, view(l0), x, r, p0, p1, q,
-                     (S*)l0.b, red);
-  hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(256), 0, s, red, (int)(gr.x * gr.y * gr.z));
+                       hipStream_t s, bool fin) {
+  const Tiles T = lvl_tiles(l0, TK_UPDATE);
+  hipLaunchKernelGGL((k_fcg_update<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, x, r,
+                     p0, p1, q, (S*)l0.b, red);
+  if (fin) hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, red, T.grid);
 }
 
 // ---- deterministic finalisation of block partials ---------------------------------
@@ -821,12 +951,13 @@ template void launch_coarse_solve<bf16, float>(const Level&, const int*, const i
 
 #define INST_FCG(O, S)                                                                          \
   template void launch_fcg_start<O, S>(const Level&, const O*, const O*, O*, O*, const RedBuf&, \
-                                       bool, double, int, int, hipStream_t);                    \
+                                       bool, double, int, int, hipStream_t, bool);              \
   template void launch_fcg_dots<O, S>(const Level&, const O*, const O*, const RedBuf&,          \
-                                      hipStream_t);                                             \
-  template void launch_fcg_dir<O, S>(const Level&, O*, O*, O*, const RedBuf&, hipStream_t);     \
+                                      hipStream_t, bool);                                       \
+  template void launch_fcg_dir<O, S>(const Level&, O*, O*, O*, const RedBuf&, hipStream_t,      \
+                                     bool);                                                     \
   template void launch_fcg_update<O, S>(const Level&, O*, O*, O*, O*, const O*, const RedBuf&,  \
-                                        hipStream_t);
+                                        hipStream_t, bool);
 INST_FCG(double, double)
 INST_FCG(float, float)
 INST_FCG(double, float)

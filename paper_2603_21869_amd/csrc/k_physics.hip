@@ -19,6 +19,10 @@ __host__ inline dim3 cell_grid(const Geom& g) {
   return dim3((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, g.nz);
 }
 
+// column tiles (see Tiles): a few workgroups per compute unit, each thread
+// walking a chunk of planes
+__host__ inline Tiles cell_tiles(const Geom& g, int tt) { return make_tiles(g.nx, g.ny, g.nz, tt); }
+
 // ---- dense <-> padded copies ------------------------------------------------
 // padded = dense - offset (rounded to F) and back
 template <class F>
@@ -58,12 +62,15 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
                                                 const V* __restrict__ w, const F* __restrict__ kk,
                                                 const F* __restrict__ om, V tau,
                                                 F* __restrict__ k_out, F* __restrict__ om_out,
-                                                RedBuf red) {
+                                                RedBuf red, Tiles T) {
   typedef V R;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  const bool in = i < g.nx && j < g.ny;
+  int tx = 0, ty = 0, tz = 0;
+  const bool tile = tile_of(T, tx, ty, tz);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
   double mk = INFINITY, mw = INFINITY;
-  if (in) {
+  if (tile && i < g.nx && j < g.ny)
+  for (int k = kb; k < ke; ++k) {
     const int P = g.idx(i, j, k);
     const uint8_t tp = type[P];
     const R kP = kk[P], wP = om[P];
@@ -124,8 +131,8 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
         const R fb = ((R)1 + (R)70 * chiw) / ((R)1 + (R)80 * chiw);
         wn = wP / ((R)1 + tau * (R)C_BETA_I * fb * wP);
       }
-      mk = (double)kn;
-      mw = (double)wn;
+      mk = fmin(mk, (double)kn);
+      mw = fmin(mw, (double)wn);
     }
     k_out[P] = (F)kn;
     om_out[P] = (F)wn;
@@ -139,20 +146,20 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
 template <class V, class F>
 void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                     const V* u, const V* v, const V* w, const F* k, const F* om, double tau,
-                    F* k_out, F* om_out, const RedBuf* red, hipStream_t s) {
+                    F* k_out, F* om_out, const RedBuf* red, int tt, hipStream_t s) {
+  const Tiles T = cell_tiles(g, tt);
   if (red) {
-    hipLaunchKernelGGL((k_destroy<V, F, true>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt,
-                       u, v, w, k, om, (V)tau, k_out, om_out, *red);
-    const dim3 gr = cell_grid(g);
-    launch_finalize(2, R_MIN, *red, gr.x * gr.y * gr.z, S_MINK, S_MINW, s);
+    hipLaunchKernelGGL((k_destroy<V, F, true>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt,
+                       u, v, w, k, om, (V)tau, k_out, om_out, *red, T);
+    launch_finalize(2, R_MIN, *red, T.grid, S_MINK, S_MINW, s);
   } else
-    hipLaunchKernelGGL((k_destroy<V, F, false>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type,
-                       pt, u, v, w, k, om, (V)tau, k_out, om_out, RedBuf{});
+    hipLaunchKernelGGL((k_destroy<V, F, false>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type,
+                       pt, u, v, w, k, om, (V)tau, k_out, om_out, RedBuf{}, T);
 }
 #define INST_DESTROY(V, F)                                                                      \
   template void launch_destroy<V, F>(const Geom&, const Phys&, const uint8_t*, const DevPatch*, \
                                      const V*, const V*, const V*, const F*, const F*, double,  \
-                                     F*, F*, const RedBuf*, hipStream_t);
+                                     F*, F*, const RedBuf*, int, hipStream_t);
 INST_DESTROY(double, double)
 INST_DESTROY(float, float)
 INST_DESTROY(double, float)
@@ -167,10 +174,14 @@ template <class V, class F, class P>
 __global__ __launch_bounds__(BS) void k_explicit(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                  const DevPatch* __restrict__ pt,
                                                  FieldSet<V, F> in, const P* __restrict__ p,
-                                                 FieldSet<V, F> out) {
+                                                 FieldSet<V, F> out, Tiles T) {
   typedef V R;
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  int tx = 0, ty = 0, tz = 0;
+  const bool tile = tile_of(T, tx, ty, tz);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
+  if (!tile || i >= g.nx || j >= g.ny) return;
+  for (int k = kb; k < ke; ++k) {
   const int C0 = g.idx(i, j, k);
   const uint8_t tp = type[C0];
   // field order: u v w T k omega
@@ -186,7 +197,7 @@ __global__ __launch_bounds__(BS) void k_explicit(Geom g, Phys ph, const uint8_t*
     out.T[C0] = in.T[C0];
     out.k[C0] = in.k[C0];
     out.om[C0] = in.om[C0];
-    return;
+    continue;
   }
   const R nu = (R)ph.nu;
   const int komega = ph.komega;
@@ -277,18 +288,20 @@ __global__ __launch_bounds__(BS) void k_explicit(Geom g, Phys ph, const uint8_t*
   out.T[C0] = (F)o[3];
   out.k[C0] = (F)o[4];
   out.om[C0] = (F)o[5];
+  }
 }
 
 template <class V, class F, class P>
 void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, hipStream_t s) {
-  hipLaunchKernelGGL((k_explicit<V, F, P>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, in,
-                     p, out);
+                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, int tt, hipStream_t s) {
+  const Tiles T = cell_tiles(g, tt);
+  hipLaunchKernelGGL((k_explicit<V, F, P>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, in,
+                     p, out, T);
 }
 #define INST_EXPLICIT(V, F, P)                                                                 \
   template void launch_explicit<V, F, P>(const Geom&, const Phys&, const uint8_t*,             \
                                          const DevPatch*, FieldSet<V, F>, const P*,            \
-                                         FieldSet<V, F>, hipStream_t);
+                                         FieldSet<V, F>, int, hipStream_t);
 INST_EXPLICIT(double, double, double)
 INST_EXPLICIT(float, float, float)
 INST_EXPLICIT(double, float, double)
@@ -299,10 +312,14 @@ __global__ __launch_bounds__(BS) void k_rhs_b(Geom g, Phys ph, const uint8_t* __
                                               const DevPatch* __restrict__ pt,
                                               const F* __restrict__ u, const F* __restrict__ v,
                                               const F* __restrict__ w, O* __restrict__ b,
-                                              RedBuf red) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+                                              RedBuf red, Tiles T) {
+  int tx = 0, ty = 0, tz = 0;
+  const bool tile = tile_of(T, tx, ty, tz);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
   double acc = 0.0;
-  if (i < g.nx && j < g.ny) {
+  if (tile && i < g.nx && j < g.ny)
+  for (int k = kb; k < ke; ++k) {
     const int C0 = g.idx(i, j, k);
     const uint8_t tp = type[C0];
     O bv = 0;
@@ -325,7 +342,7 @@ __global__ __launch_bounds__(BS) void k_rhs_b(Geom g, Phys ph, const uint8_t* __
       bv = -div / (O)ph.dt;
     }
     b[C0] = bv;
-    acc = (double)bv * (double)bv;
+    acc += (double)bv * (double)bv;
   }
   double vv[1] = {acc};
   block_partial<1, R_SUM, BS>(vv, red);
@@ -333,18 +350,19 @@ __global__ __launch_bounds__(BS) void k_rhs_b(Geom g, Phys ph, const uint8_t* __
 
 template <class F, class O>
 void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                  const F* u, const F* v, const F* w, O* b, const RedBuf& red, hipStream_t s) {
-  hipLaunchKernelGGL((k_rhs_b<F, O>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, u, v, w,
-                     b, red);
-  const dim3 gr = cell_grid(g);
-  launch_finalize(1, R_SUM, red, gr.x * gr.y * gr.z, S_BB, S_BB, s);
+                  const F* u, const F* v, const F* w, O* b, const RedBuf& red, int tt,
+                  hipStream_t s) {
+  const Tiles T = cell_tiles(g, tt);
+  hipLaunchKernelGGL((k_rhs_b<F, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, u, v, w,
+                     b, red, T);
+  launch_finalize(1, R_SUM, red, T.grid, S_BB, S_BB, s);
 }
 template void launch_rhs_b<double, double>(const Geom&, const Phys&, const uint8_t*,
                                            const DevPatch*, const double*, const double*,
-                                           const double*, double*, const RedBuf&, hipStream_t);
+                                           const double*, double*, const RedBuf&, int, hipStream_t);
 template void launch_rhs_b<float, float>(const Geom&, const Phys&, const uint8_t*,
                                          const DevPatch*, const float*, const float*, const float*,
-                                         float*, const RedBuf&, hipStream_t);
+                                         float*, const RedBuf&, int, hipStream_t);
 
 
 // ---- projection ----------------------------------------------------------------
@@ -358,10 +376,14 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
                                                 const F* __restrict__ v, const F* __restrict__ w,
                                                 F* __restrict__ uo, F* __restrict__ vo,
                                                 F* __restrict__ wo, P* __restrict__ p,
-                                                RedBuf red) {
-  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+                                                RedBuf red, Tiles T) {
+  int tx = 0, ty = 0, tz = 0;
+  const bool tile = tile_of(T, tx, ty, tz);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
   double mdiv = 0.0;
-  if (i < g.nx && j < g.ny) {
+  if (tile && i < g.nx && j < g.ny)
+  for (int k = kb; k < ke; ++k) {
     const int C0 = g.idx(i, j, k);
     const uint8_t tp = type[C0];
     const F* vel[3] = {u, v, w};
@@ -404,7 +426,7 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
       }
       for (int d = 0; d < 3; ++d) vout[d][C0] = d < g.dim ? (F)unew[d] : vel[d][C0];
       p[C0] = (P)((O)p[C0] + fP);
-      mdiv = fabs((double)div);
+      mdiv = fmax(mdiv, fabs((double)div));
     }
   }
   double vv[1] = {mdiv};
@@ -414,20 +436,20 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
 template <class F, class P, class O>
 void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                     const O* phi, const F* u, const F* v, const F* w, F* uo, F* vo, F* wo, P* p,
-                    const RedBuf& red, hipStream_t s) {
-  hipLaunchKernelGGL((k_project<F, P, O>), cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
-                     u, v, w, uo, vo, wo, p, red);
-  const dim3 gr = cell_grid(g);
-  launch_finalize(1, R_MAX, red, gr.x * gr.y * gr.z, S_DIV, S_DIV, s);
+                    const RedBuf& red, int tt, hipStream_t s) {
+  const Tiles T = cell_tiles(g, tt);
+  hipLaunchKernelGGL((k_project<F, P, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
+                     u, v, w, uo, vo, wo, p, red, T);
+  launch_finalize(1, R_MAX, red, T.grid, S_DIV, S_DIV, s);
 }
 template void launch_project<double, double, double>(const Geom&, const Phys&, const uint8_t*,
                                                      const DevPatch*, const double*,
                                                      const double*, const double*, const double*,
                                                      double*, double*, double*, double*,
-                                                     const RedBuf&, hipStream_t);
+                                                     const RedBuf&, int, hipStream_t);
 template void launch_project<float, float, float>(const Geom&, const Phys&, const uint8_t*,
                                                   const DevPatch*, const float*, const float*,
                                                   const float*, const float*, float*, float*,
-                                                  float*, float*, const RedBuf&, hipStream_t);
+                                                  float*, float*, const RedBuf&, int, hipStream_t);
 
 }  // namespace nfvm

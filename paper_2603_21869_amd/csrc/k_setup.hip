@@ -26,6 +26,21 @@ Geom make_geom(int dim, int nx, int ny, int nz, double hx, double hy, double hz)
   return g;
 }
 
+Tiles make_tiles(int nx, int ny, int nz, int target_blocks) {
+  Tiles t;
+  t.ntx = (nx + 63) / 64;
+  t.nty = (ny + 3) / 4;
+  const int nxy = t.ntx * t.nty;
+  int nzc = (target_blocks + nxy - 1) / nxy;
+  if (nzc < 1) nzc = 1;
+  if (nzc > nz) nzc = nz;
+  t.cz = (nz + nzc - 1) / nzc;
+  t.ntz = (nz + t.cz - 1) / t.cz;
+  t.total = nxy * t.ntz;
+  t.grid = (t.total + 7) / 8 * 8;
+  return t;
+}
+
 // One thread per padded cell.  patch_rect: per user patch {face, lo0, lo1, hi0, hi1}.
 __global__ void k_classify(Geom g, const uint8_t* __restrict__ solid, const int* __restrict__ rect,
                            int npu, DevPatch* patches, double nu, int komega,

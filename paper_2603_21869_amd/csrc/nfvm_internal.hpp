@@ -55,14 +55,50 @@ struct Geom {
 
 Geom make_geom(int dim, int nx, int ny, int nz, double hx, double hy, double hz);
 
+// Column tiling of a level: 64 x 4 columns per workgroup, each thread walks
+// cz consecutive z planes.  Workgroups are dealt to the 8 XCDs round robin
+// (block b runs on XCD b % 8); tile_of gives each XCD one contiguous range of
+// tiles (x fastest), so neighbouring tiles mostly share an L2.
+struct Tiles {
+  int ntx, nty, ntz, cz, total, grid;
+};
+Tiles make_tiles(int nx, int ny, int nz, int target_blocks);
+__device__ __forceinline__ bool tile_of(const Tiles& T, int& tx, int& ty, int& tz) {
+  const int per = T.grid >> 3;
+  const int b = blockIdx.x;
+  const int t = (b & 7) * per + (b >> 3);
+  if (t >= T.total) return false;
+  tx = t % T.ntx;
+  ty = (t / T.ntx) % T.nty;
+  tz = t / (T.ntx * T.nty);
+  return true;
+}
+
 struct Phys {
   double nu, alpha_T, inv_Pr_t, inv_sigma_k, inv_sigma_w, dt;
   int komega, energy, buoyancy;
   double g[3], T_ref, beta_T;
 };
 
+// Tunable kernels: tile targets (workgroups per launch, see Tiles) chosen per
+// level by the autotuner.
+enum {
+  TK_SMOOTH = 0,
+  TK_SMOOTH_ZERO,
+  TK_RESTRICT,  // on the fine level of the pair
+  TK_PROLONG,   // on the fine level of the pair
+  TK_START,
+  TK_DOTS,
+  TK_DIR,
+  TK_UPDATE,
+  TK_LEVEL_COUNT
+};
+enum { TP_EXPLICIT = 0, TP_DESTROY, TP_RHS, TP_PROJECT, TP_COUNT };
+constexpr int TILE_DEFAULT = 4096;
+
 // One multigrid level on the device.
 struct Level {
+  int tt[TK_LEVEL_COUNT];       // tile target per tunable kernel
   Geom g;
   uint8_t* cls;                 // MG_* per padded cell
   uint8_t* full;                // 1: cell and all 26 neighbours active and inside (coarse levels)
@@ -134,18 +170,19 @@ struct FieldSet {
 template <class V, class F>
 void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                     const V* u, const V* v, const V* w, const F* k, const F* om, double tau,
-                    F* k_out, F* om_out, const RedBuf* red, hipStream_t s);
+                    F* k_out, F* om_out, const RedBuf* red, int tt, hipStream_t s);
 template <class V, class F, class P>
 void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, hipStream_t s);
+                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, int tt, hipStream_t s);
 template <class V, class O>
 void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                  const V* u, const V* v, const V* w, O* b, const RedBuf& red, hipStream_t s);
+                  const V* u, const V* v, const V* w, O* b, const RedBuf& red, int tt,
+                  hipStream_t s);
 // reads u* (u, v, w), writes the corrected velocity to (uo, vo, wo)
 template <class V, class P, class O>
 void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                     const O* phi, const V* u, const V* v, const V* w, V* uo, V* vo, V* wo, P* p,
-                    const RedBuf& red, hipStream_t s);
+                    const RedBuf& red, int tt, hipStream_t s);
 
 // multigrid (S: storage of the level, C: arithmetic)
 // (ctl: red.out; every kernel returns at once when ctl[S_DONE] != 0)
@@ -196,15 +233,19 @@ void launch_bottom(const Bottom& B, const void* btop, void* xtop, const double* 
 // rule runs on the device: launch_fcg_start sets S_DONE / S_ITER from tol,
 // max_cycles and forced; every later kernel of an iteration returns at once
 // when S_DONE is set, so surplus iterations enqueued by the host are no-ops.
+// (fin = false: no finalising kernel; used by the autotuner)
 template <class O, class S>
 void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, const RedBuf& red,
-                      bool have_x0, double tol, int max_cycles, int forced, hipStream_t s);
+                      bool have_x0, double tol, int max_cycles, int forced, hipStream_t s,
+                      bool fin = true);
 template <class O, class S>
-void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s);
+void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
+                     bool fin = true);
 template <class O, class S>
-void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipStream_t s);
+void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipStream_t s,
+                    bool fin = true);
 template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p0, O* p1, const O* q, const RedBuf& red,
-                       hipStream_t s);
+                       hipStream_t s, bool fin = true);
 
 }  // namespace nfvm

@@ -25,7 +25,8 @@ EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_mg_solve", "nfvm_mg_solve_device",
     "nfvm_get_fields", "nfvm_set_fields", "nfvm_grid_footprint", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
-    "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_set_option", "nfvm_last_error",
+    "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_set_option", "nfvm_tuning_table",
+    "nfvm_last_error",
 )
 
 KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "explicit", "destroy", "rhs",
@@ -101,6 +102,7 @@ def lib():
         L.nfvm_profile_read.argtypes = [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nfvm_set_option.argtypes = [C.c_void_p, C.c_int32, C.c_double]
+        L.nfvm_tuning_table.argtypes = [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
         L.nfvm_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "nfvm_last_error":
@@ -241,7 +243,14 @@ def nfvm_profile_read(grid, kernel: int):
     return dict(launches=n.value, seconds=s.value, bytes_per_launch=b.value)
 
 
-NFVM_OPT_GRAPHS, NFVM_OPT_PREDICT, NFVM_OPT_BOTTOM = 0, 1, 2
+NFVM_OPT_GRAPHS, NFVM_OPT_PREDICT, NFVM_OPT_BOTTOM, NFVM_OPT_AUTOTUNE = 0, 1, 2, 3
+
+
+def nfvm_tuning_table():
+    buf = (C.c_int32 * (7 * 1024))()
+    cnt = C.c_int32(0)
+    _check(lib().nfvm_tuning_table(buf, 1024, C.byref(cnt)))
+    return [tuple(buf[7 * i: 7 * i + 7]) for i in range(cnt.value)]
 
 
 def nfvm_set_option(grid, option: int, value: float):
