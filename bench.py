@@ -70,6 +70,41 @@ def run_gpu(case, steps: int, warmup: int, profile: bool, stream: int, graphs: b
     return t1 - t0, stats, prof, s
 
 
+def run_serve(n_req: int, slots: int, seed: int = 0):
+    """Replay the first n_req requests of the seeded serving trace (Poisson
+    arrivals, 20/s; edges from {64, 96, 128, 192, 256}; channel or room; 50
+    mixed-precision steps each) against the server in real time."""
+    from paper_2603_21869_amd import cases as C, nfvm
+    trace = C.serve_trace(seed=seed, n_requests=n_req)
+    cases = [C.serve_case(r) for r in trace]
+    descs = [nfvm.Desc(c) for c in cases]
+    srv = nfvm.nfvm_server_create(0.0, slots)
+    t0 = time.perf_counter()
+    tickets = []
+    for r, c, d in zip(trace, cases, descs):
+        wait = t0 + r["arrival"] - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(nfvm.nfvm_submit(srv, d, c.fields, r["n_steps"]))
+    nfvm.nfvm_server_drain(srv)
+    times = [nfvm.nfvm_request_times(srv, t) for t in tickets]
+    status = [nfvm.nfvm_poll(srv, t, None, allow=(0, -4, -5))[0] for t in tickets]
+    nfvm.nfvm_server_destroy(srv)
+    lat = sorted(t[3] - t[0] for t in times)
+    first = sorted(t[2] - t[0] for t in times if t[2] >= 0)
+    span = max(t[3] for t in times) - min(t[0] for t in times)
+    work = sum(c.ncells * r["n_steps"] for c, r in zip(cases, trace))
+    pct = lambda a, q: a[min(len(a) - 1, int(math.ceil(q * len(a))) - 1)]
+    return {"requests": n_req, "slots": slots, "arrival_rate_per_s": 20.0,
+            "ok": sum(1 for s in status if s == 0),
+            "throughput_mcell_steps_s": round(work / span / 1e6, 2),
+            "makespan_s": round(span, 3),
+            "latency_p50_s": round(pct(lat, 0.5), 3), "latency_p99_s": round(pct(lat, 0.99), 3),
+            "first_converged_step_p50_s": round(pct(first, 0.5), 3),
+            "first_converged_step_p99_s": round(pct(first, 0.99), 3),
+            "mean_cells": int(sum(c.ncells for c in cases) / n_req)}
+
+
 def cpu_baseline(case, budget_s: float = 20.0):
     """The serial FP64 oracle on a bounded number of steps of the same workload."""
     from oracle import oracle as O
@@ -101,6 +136,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--serve", type=int, default=24,
+                    help="requests of the serving trace to replay (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (for "
                          "scaling hardware byte counters) and exit")
@@ -191,6 +229,8 @@ def main():
         "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
                          "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",
     }
+    if args.serve:
+        out["serving"] = run_serve(args.serve, args.serve_slots)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(make_case(args.workload, C.PREC_FP64, args.tol))
     print(json.dumps(out))

@@ -100,7 +100,9 @@ size_t footprint_bytes(const nfvm_grid_desc& d) {
   for (int l = 0; l < d.n_levels; ++l) {
     const Geom gl = level_geom(d, l);
     b += (size_t)gl.total * (1 + 4 * d.dim + 3 * (l == 0 ? S0 : SC));
+    b += l == 0 ? (size_t)gl.total * 2 : (size_t)gl.total;  // face codes / full flags
   }
+  b += 160 * 1024;                                  // bottom solver's LDS image
   b += (size_t)max_blocks_of(g) * 3 * 8 + 4096;     // reduction partials
   b += (size_t)2 * COARSE_MAX * COARSE_MAX * 8 + COARSE_MAX * 4;  // dense coarse inverse
   b += MAX_PATCHES * sizeof(DevPatch) + 5 * 4 * MAX_PATCHES;
@@ -331,11 +333,15 @@ class GridT : public GridBase {
       for (int c = 0; c < 2; ++c) v.x[c] = alloc<uint8_t>(v.g.total * es);
       v.b = alloc<uint8_t>(v.g.total * es);
       v.cur = 0;
+      v.code = nullptr;
       for (int t = 0; t < TK_LEVEL_COUNT; ++t) v.tt[t] = TILE_DEFAULT;
-      if (l == 0)
+      if (l == 0) {
         launch_level0(v.g, type, patches, v.cls, v.cf[0], v.cf[1], d.dim == 3 ? v.cf[2] : v.cf[0],
                       stream);
-      else
+        v.code = alloc<uint16_t>(v.g.total);
+        launch_face_codes(v.g, v.cls, v.cf[0], v.cf[1], d.dim == 3 ? v.cf[2] : v.cf[0], v.code,
+                          stream);
+      } else
         launch_coarsen(lv[l - 1].g, lv[l - 1].cls, lv[l - 1].cf, v.g, v.cls, v.cf, stream);
       if (l > 0) launch_mark_full(v, stream);
     }
@@ -389,12 +395,15 @@ class GridT : public GridBase {
     return ms;
   }
 
+  bool tune_cached_only = false;
+
   template <class Fn>
   int tune_one(int kid, const Geom& gg, Fn&& launch) {
     const int cand[] = {512, 2048, 8192, 1 << 30};
     TuneKey key{kid, gg.nx, gg.ny, gg.nz, desc.dim, desc.precision};
     int cached;
     if (tune_lookup(key, &cached)) return cached;
+    if (tune_cached_only) return TILE_DEFAULT;
     int best = TILE_DEFAULT;
     float bt = 1e30f;
     for (int c : cand) {
@@ -451,7 +460,8 @@ class GridT : public GridBase {
         });
         v.tt[TK_START] = tune_one(TK_START, v.g, [&](int tt) {
           v.tt[TK_START] = tt;
-          launch_fcg_start<O, S0>(v, bvec, x0, r, phi, red, false, 1.0, 1, -1, stream, false);
+          launch_fcg_start<O, S0>(v, bvec, x0, r, phi, red, false, 1.0, 1, -1, stream, false,
+                                  zero0(), wj);
         });
         v.tt[TK_DOTS] = tune_one(TK_DOTS, v.g, [&](int tt) {
           v.tt[TK_DOTS] = tt;
@@ -463,7 +473,7 @@ class GridT : public GridBase {
         });
         v.tt[TK_UPDATE] = tune_one(TK_UPDATE, v.g, [&](int tt) {
           v.tt[TK_UPDATE] = tt;
-          launch_fcg_update<O, S0>(v, phi, r, pv[0], pv[1], q, red, stream, false);
+          launch_fcg_update<O, S0>(v, phi, r, pv[0], pv[1], q, red, stream, false, zero0(), wj);
         });
       } else {
         v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + 1000, v.g, [&](int tt) {
@@ -557,18 +567,31 @@ class GridT : public GridBase {
   }
 
   // levels bottom_top .. L-1 run in one LDS-resident workgroup
-  static constexpr size_t LDS_LIMIT = 64 * 1024;
   int bottom_top = -1;
   Bottom bot{};
+
+  // LDS layout of the bottom solver: iterates and right-hand sides of every
+  // level first (cleared per launch), then face coefficients, class bytes and
+  // the compact indices of the coarsest cells.
+  static size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
+  static size_t faces_bytes(const Geom& g) {
+    size_t f = (size_t)(g.nx + 1) * g.ny * g.nz + (size_t)g.nx * (g.ny + 1) * g.nz;
+    if (g.dim == 3) f += (size_t)g.nx * g.ny * (g.nz + 1);
+    return al16(f * sizeof(float));
+  }
+  static size_t bottom_bytes(const Geom& g) {
+    return al16(3 * g.cells() * sizeof(C)) + faces_bytes(g) + al16(g.cells());
+  }
 
   void setup_bottom() {
     bottom_top = -1;
     if (!use_bottom || L < 3) return;
-    size_t bytes = 0;
+    const size_t limit = bottom_lds_limit<SC, C>();
+    size_t bytes = al16(COARSE_MAX * sizeof(int));
     int top = L;
     for (int l = L - 1; l >= 1; --l) {
-      const size_t need = bytes + 3 * (size_t)lv[l].g.cells() * sizeof(C);
-      if (need > LDS_LIMIT || L - l > BOTTOM_MAX_LEVELS) break;
+      const size_t need = bytes + bottom_bytes(lv[l].g);
+      if (need > limit || L - l > BOTTOM_MAX_LEVELS) break;
       bytes = need;
       top = l;
     }
@@ -587,16 +610,45 @@ class GridT : public GridBase {
       b.cf1 = lv[l].cf[1];
       b.cf2 = desc.dim == 3 ? lv[l].cf[2] : lv[l].cf[0];
       b.n = (int)lv[l].g.cells();
-      b.ox0 = (int)off;
-      b.ox1 = (int)(off + b.n);
-      b.ob = (int)(off + 2 * b.n);
-      off += 3 * (size_t)b.n;
+      b.bx0 = (int)off;
+      b.bx1 = (int)(off + b.n * sizeof(C));
+      b.bb = (int)(off + 2 * b.n * sizeof(C));
+      off = al16(off + 3 * b.n * sizeof(C));
     }
+    bot.zero_bytes = (int)off;
+    for (int l = top; l < L; ++l) {
+      BottomLevel& b = bot.lv[l - top];
+      const Geom& g = lv[l].g;
+      b.bfx = (int)off;
+      b.bfy = (int)(off + (size_t)(g.nx + 1) * g.ny * g.nz * sizeof(float));
+      b.bfz = (int)(b.bfy + (size_t)g.nx * (g.ny + 1) * g.nz * sizeof(float));
+      off += faces_bytes(g);
+      b.bcl = (int)off;
+      off += al16(g.cells());
+    }
+    bot.bcidx = (int)off;
+    off += al16(COARSE_MAX * sizeof(int));
     bot.cmap = cmap;
     bot.ncount = ncount;
     bot.ainv = work;
     bot.max_n = COARSE_MAX;
-    bot.lds_bytes = off * sizeof(C);
+    bot.lds_bytes = off;
+    if (off - bot.zero_bytes > bot_img_bytes) {
+      bot_img_bytes = off - bot.zero_bytes;
+      bot_img = alloc<unsigned char>(bot_img_bytes);
+    }
+    bot.img = bot_img;
+    launch_bottom_image(bot, bot_img, stream);
+    NFVM_CK(hipGetLastError());
+  }
+  unsigned char* bot_img = nullptr;
+  size_t bot_img_bytes = 0;
+
+  // Level-0 buffer that the CG start / update kernels fill with the first
+  // pre-smoothing sweep (from zero) of the next V-cycle, or null when level 0
+  // is handled by the bottom solver or the coarsest solve.
+  void* zero0() const {
+    return (nu1 > 0 && bottom_top != 0 && L > 1) ? lv[0].x[0] : nullptr;
   }
 
   void vcycle(int l) {
@@ -615,7 +667,11 @@ class GridT : public GridBase {
       return;
     }
     if (nu1 > 0) {
-      smooth(l, true);
+      if (l == 0 && zero0()) {
+        v.cur = 0;  // first sweep from zero done by the CG start / update kernel
+      } else {
+        smooth(l, true);
+      }
       for (int s = 1; s < nu1; ++s) smooth(l, false);
     } else {
       v.cur = 0;
@@ -658,7 +714,7 @@ class GridT : public GridBase {
     launch_fcg_dir<O, S0>(lv[0], pv[0], pv[1], q, red, stream);
     prof_end(NFVM_K_FCG_DIR);
     prof_begin(NFVM_K_FCG_UPDATE);
-    launch_fcg_update<O, S0>(lv[0], phi, r, pv[0], pv[1], q, red, stream);
+    launch_fcg_update<O, S0>(lv[0], phi, r, pv[0], pv[1], q, red, stream, true, zero0(), wj);
     prof_end(NFVM_K_FCG_UPDATE);
   }
 
@@ -711,8 +767,9 @@ class GridT : public GridBase {
   // Flexible CG preconditioned by one V-cycle; b in bvec, result in phi.
   nfvm_status solve(bool have_x0, double tol_, int maxc, int forced, int* cycles, double* rel,
                     bool started = false) {
-    if (!started) launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, have_x0, tol_, maxc, forced,
-                                          stream);
+    if (!started)
+      launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, have_x0, tol_, maxc, forced, stream,
+                              true, zero0(), wj);
     int ahead = forced >= 0 ? forced : std::min(predicted, maxc);
     for (int i = 0; i < ahead; ++i) run_iteration();
     NFVM_CK(hipGetLastError());
@@ -782,7 +839,8 @@ class GridT : public GridBase {
     launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red,
                        tp[TP_RHS], stream);
     prof_end(NFVM_K_RHS);
-    launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, false, tol, max_cycles, -1, stream);
+    launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, false, tol, max_cycles, -1, stream,
+                            true, zero0(), wj);
   }
 
   // projection, destruction over dt/2 (with the min k / omega reduction)
@@ -905,7 +963,7 @@ typedef GridT<float, float, float, float, float, float, float> GridFP32;
 typedef GridT<double, float, double, double, float, bf16, float> GridMixed;
 
 std::unique_ptr<GridBase> make_grid(const nfvm_grid_desc& d, const nfvm_fields* init,
-                                    hipStream_t stream) {
+                                    hipStream_t stream, int tune_mode) {
   validate_desc(d);
   std::unique_ptr<GridBase> gb;
   if (d.precision == NFVM_FP64)
@@ -914,6 +972,15 @@ std::unique_ptr<GridBase> make_grid(const nfvm_grid_desc& d, const nfvm_fields* 
     gb.reset(new GridFP32());
   else
     gb.reset(new GridMixed());
+  gb->use_autotune = tune_mode != 0;
+  if (tune_mode == 2) {
+    if (d.precision == NFVM_FP64)
+      static_cast<GridFP64*>(gb.get())->tune_cached_only = true;
+    else if (d.precision == NFVM_FP32)
+      static_cast<GridFP32*>(gb.get())->tune_cached_only = true;
+    else
+      static_cast<GridMixed*>(gb.get())->tune_cached_only = true;
+  }
   if (stream) {
     gb->stream = stream;
   } else {

@@ -110,8 +110,9 @@ class GridBase {
   int max_cycles = 100;
 };
 
+// tune_mode: 0 default tiles, 1 autotune (cached per shape), 2 cached choices only
 std::unique_ptr<GridBase> make_grid(const nfvm_grid_desc& d, const nfvm_fields* init,
-                                    hipStream_t stream);
+                                    hipStream_t stream, int tune_mode = 1);
 
 }  // namespace nfvm
 

@@ -27,10 +27,49 @@ struct LevelView {
   const float* cf1;
   const float* cf2;
   const uint8_t* full;
+  const uint16_t* code;  // level 0: face codes (FACE_CODE_INACTIVE for inactive cells)
 };
 
 __host__ inline LevelView view(const Level& l) {
-  return LevelView{l.g, l.cls, l.cf[0], l.cf[1], l.g.dim == 3 ? l.cf[2] : l.cf[0], l.full};
+  return LevelView{l.g,  l.cls,  l.cf[0], l.cf[1], l.g.dim == 3 ? l.cf[2] : l.cf[0],
+                   l.full, l.code};
+}
+
+// Coefficient of face f (0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+) from a face code.
+template <class C>
+__device__ __forceinline__ C face_c(uint32_t cd, int f) {
+  return (C)(int)((cd >> (2 * f)) & 3u);
+}
+
+// A x and the diagonal at cell P from its face code, z neighbours given:
+// sum over faces of c_f (x_P - x_N) / h^2.
+template <class S, class C>
+__device__ __forceinline__ void apply_code(const Geom& g, uint32_t cd, const S* __restrict__ x,
+                                           int P, C xP, C xm, C xp, C& Ax, C& D) {
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
+  const C cxl = face_c<C>(cd, 0), cxh = face_c<C>(cd, 1);
+  const C cyl = face_c<C>(cd, 2), cyh = face_c<C>(cd, 3);
+  C s = (cxl * (xP - St<S, C>::ld(x + P - 1)) + cxh * (xP - St<S, C>::ld(x + P + 1))) * ih2x +
+        (cyl * (xP - St<S, C>::ld(x + P - g.sx)) + cyh * (xP - St<S, C>::ld(x + P + g.sx))) * ih2y;
+  C d = (cxl + cxh) * ih2x + (cyl + cyh) * ih2y;
+  if (g.dim == 3) {
+    const C czl = face_c<C>(cd, 4), czh = face_c<C>(cd, 5);
+    s += (czl * (xP - xm) + czh * (xP - xp)) * ih2z;
+    d += (czl + czh) * ih2z;
+  }
+  Ax = s;
+  D = d;
+}
+
+// Diagonal of A from a face code.
+template <class C>
+__device__ __forceinline__ C diag_code(const Geom& g, uint32_t cd) {
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
+  C d = (face_c<C>(cd, 0) + face_c<C>(cd, 1)) * ih2x + (face_c<C>(cd, 2) + face_c<C>(cd, 3)) * ih2y;
+  if (g.dim == 3) d += (face_c<C>(cd, 4) + face_c<C>(cd, 5)) * ih2z;
+  return d;
 }
 
 // Coarse cells whose 26 neighbours are all active and inside the box: the
@@ -169,10 +208,70 @@ __global__ __launch_bounds__(MBS) void k_smooth(LevelView L, Tiles T, const S* _
   }
 }
 
+// Level-0 sweep from face codes: no branch on the cell kind, and the loads of
+// two planes are issued before their arithmetic.
+template <class S, class C, bool ZERO>
+__global__ __launch_bounds__(MBS) void k_smooth_code(LevelView L, Tiles T,
+                                                     const S* __restrict__ xin,
+                                                     S* __restrict__ xout,
+                                                     const S* __restrict__ b, C wj,
+                                                     const double* __restrict__ ctl) {
+  if (ctl[S_DONE] != 0.0) return;
+  int tx, ty, tz;
+  if (!tile_of(T, tx, ty, tz)) return;
+  const Geom& g = L.g;
+  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+  const bool d3 = g.dim == 3;
+  int P = g.idx(i, j, k0);
+  if (ZERO) {
+    for (int k = k0; k < k1; ++k, P += g.sxy) {
+      const uint32_t cd = L.code[P];
+      const C bP = St<S, C>::ld(b + P);
+      if (cd != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, wj * bP / diag_code<C>(g, cd));
+    }
+    return;
+  }
+  C xc = St<S, C>::ld(xin + P);
+  C xm = d3 ? St<S, C>::ld(xin + P - g.sxy) : (C)0;
+  int k = k0;
+  for (; k + 1 < k1; k += 2, P += 2 * g.sxy) {  // 3D only (a 2D level has one plane)
+    const int Q = P + g.sxy;
+    const uint32_t c0 = L.code[P], c1 = L.code[Q];
+    const C b0 = St<S, C>::ld(b + P), b1 = St<S, C>::ld(b + Q);
+    const C xp = St<S, C>::ld(xin + Q), xpp = St<S, C>::ld(xin + Q + g.sxy);
+    C A0, D0, A1, D1;
+    apply_code<S, C>(g, c0, xin, P, xc, xm, xp, A0, D0);
+    apply_code<S, C>(g, c1, xin, Q, xp, xc, xpp, A1, D1);
+    if (c0 != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, xc + wj * (b0 - A0) / D0);
+    if (c1 != FACE_CODE_INACTIVE) St<S, C>::st(xout + Q, xp + wj * (b1 - A1) / D1);
+    xm = xp;
+    xc = xpp;
+  }
+  if (k < k1) {
+    const uint32_t cd = L.code[P];
+    const C bP = St<S, C>::ld(b + P);
+    const C xp = d3 ? St<S, C>::ld(xin + P + g.sxy) : (C)0;
+    C Ax, D;
+    apply_code<S, C>(g, cd, xin, P, xc, xm, xp, Ax, D);
+    if (cd != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
+  }
+}
+
 template <class S, class C>
 void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                    const double* ctl, hipStream_t s) {
   const Tiles T = lvl_tiles(l, from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH);
+  if (l.code) {
+    if (from_zero)
+      hipLaunchKernelGGL((k_smooth_code<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s,
+                         view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
+    else
+      hipLaunchKernelGGL((k_smooth_code<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s,
+                         view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
+    return;
+  }
   if (from_zero)
     hipLaunchKernelGGL((k_smooth<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
                        (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
@@ -214,11 +313,19 @@ __global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, Tiles T,
       C xp = 0;
       if (in) {
         if (d3) xp = St<S, C>::ld(x + P + g.sxy);
-        const uint8_t cl = F.cls[P];
-        if (cl != MG_INACTIVE) {
+        if (F.code) {
+          const uint32_t cd = F.code[P];
+          const C bP = St<S, C>::ld(b + P);
           C Ax, D;
-          apply_z<S, C>(F, cl, x, P, xc, xm, xp, Ax, D);
-          r += St<S, C>::ld(b + P) - Ax;
+          apply_code<S, C>(g, cd, x, P, xc, xm, xp, Ax, D);
+          if (cd != FACE_CODE_INACTIVE) r += bP - Ax;
+        } else {
+          const uint8_t cl = F.cls[P];
+          if (cl != MG_INACTIVE) {
+            C Ax, D;
+            apply_z<S, C>(F, cl, x, P, xc, xm, xp, Ax, D);
+            r += St<S, C>::ld(b + P) - Ax;
+          }
         }
       }
       xm = xc;
@@ -254,6 +361,67 @@ __device__ __forceinline__ bool act_at(const LevelView& L, int i, int j, int k) 
   return L.cls[L.g.idx(i, j, k)] != MG_INACTIVE;
 }
 
+// Correction at fine cell (i, j, k) with every boundary and mask check.
+// Every value the rules may need is loaded up front (the indices lie in the
+// padded arrays: one ghost layer around the box) and the rules then select
+// among them, so a wave pays one round of loads instead of a chain of
+// dependent ones; the arithmetic is the same, term for term.
+template <class C, class SC>
+__device__ C prolong_checked(const LevelView& Cl, const SC* __restrict__ e, int i, int j, int k) {
+  const Geom& cg = Cl.g;
+  const bool d3 = cg.dim == 3;
+  const int I = i >> 1, J = j >> 1, K = d3 ? (k >> 1) : 0;
+  const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+  const int oy = sy * cg.sx, oz = sz * cg.sxy;
+  const C w3 = (C)0.75, w1 = (C)0.25;
+  const bool inx = (unsigned)(I + sx) < (unsigned)cg.nx;
+  const bool iny = (unsigned)(J + sy) < (unsigned)cg.ny;
+  const bool inz = d3 && (unsigned)(K + sz) < (unsigned)cg.nz;
+  const int nq = d3 ? 4 : 2;
+  // q = 0: (J, K), 1: (J + sy, K), 2: (J, K + sz), 3: (J + sy, K + sz)
+  const int Q0 = cg.idx(I, J, K);
+  int Q[4] = {Q0, Q0 + oy, Q0, Q0};
+  if (d3) {
+    Q[2] = Q0 + oz;
+    Q[3] = Q0 + oz + oy;
+  }
+  C ev[4] = {0, 0, 0, 0}, en[4] = {0, 0, 0, 0}, cfx[4] = {0, 0, 0, 0};
+  bool ac[4] = {false, false, false, false}, an[4] = {false, false, false, false};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q >= nq) break;
+    ev[q] = St<SC, C>::ld(e + Q[q]);
+    en[q] = St<SC, C>::ld(e + Q[q] + sx);
+    ac[q] = Cl.cls[Q[q]] != MG_INACTIVE;
+    an[q] = Cl.cls[Q[q] + sx] != MG_INACTIVE;
+    cfx[q] = (C)Cl.cf0[sx > 0 ? Q[q] + 1 : Q[q]];
+  }
+  const C cfy0 = (C)Cl.cf1[sy > 0 ? Q[0] + cg.sx : Q[0]];
+  const C cfy1 = d3 ? (C)Cl.cf1[sy > 0 ? Q[2] + cg.sx : Q[2]] : (C)0;
+  const C cfz = d3 ? (C)Cl.cf2[sz > 0 ? Q0 + cg.sxy : Q0] : (C)0;
+  const bool act[4] = {ac[0], iny && ac[1], inz && ac[2], iny && inz && ac[3]};
+  C X[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const C nb = inx ? (an[q] ? en[q] : ev[q]) : ((C)1 - cfx[q]) * ev[q];
+    X[q] = act[q] ? w3 * ev[q] + w1 * nb : (C)0;
+  }
+  const C yn0 = iny ? (act[1] ? X[1] : X[0]) : ((C)1 - cfy0) * X[0];
+  const C Y0 = act[0] ? w3 * X[0] + w1 * yn0 : (C)0;
+  if (!d3) return Y0;
+  const C yn1 = iny ? (act[3] ? X[3] : X[2]) : ((C)1 - cfy1) * X[2];
+  const C Y1 = act[2] ? w3 * X[2] + w1 * yn1 : (C)0;
+  const C zn = inz ? (act[2] ? Y1 : Y0) : ((C)1 - cfz) * Y0;
+  return w3 * Y0 + w1 * zn;
+}
+
+// One thread per fine column (i, j) walking the coarse planes K of its tile.
+// The x-then-y interpolated coarse value of planes K-1, K and K+1 stays in
+// registers, so the two fine cells 2K and 2K+1 under a coarse cell whose 26
+// neighbours are all active cost four coarse loads between them; other cells
+// take the checked path.  Planes K-1 and K+1 are read unchecked: they lie in
+// the padded array (one ghost layer) and hold finite values (ghost and
+// inactive cells are 0), and are used only when the cell is marked full.
 template <class S, class C, class SC>
 __global__ __launch_bounds__(MBS) void k_prolong(LevelView F, Tiles T, S* __restrict__ x,
                                                  LevelView Cl, const SC* __restrict__ e,
@@ -263,90 +431,42 @@ __global__ __launch_bounds__(MBS) void k_prolong(LevelView F, Tiles T, S* __rest
   if (!tile_of(T, tx, ty, tz)) return;
   const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
   if (i >= F.g.nx || j >= F.g.ny) return;
-  const int k0 = tz * T.cz, k1 = min(F.g.nz, k0 + T.cz);
-  for (int k = k0; k < k1; ++k) {
-  const int P = F.g.idx(i, j, k);
-  if (F.cls[P] == MG_INACTIVE) continue;
   const Geom& cg = Cl.g;
   const bool d3 = cg.dim == 3;
-  const int I = i >> 1, J = j >> 1, K = d3 ? (k >> 1) : 0;
-  const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
+  const int K0 = tz * T.cz, K1 = min(cg.nz, K0 + T.cz);
+  const int sx = (i & 1) ? 1 : -1, oy = (j & 1) ? cg.sx : -cg.sx;
   const C w3 = (C)0.75, w1 = (C)0.25;
-  const int PC = cg.idx(I, J, K);
-  if (Cl.full[PC]) {
-    // all corners active and inside: same axis-by-axis sums, no checks
-    const int oy = sy * cg.sx, oz = sz * cg.sxy;
-    C Y0, Z;
-    {
-      const C x00 = w3 * St<SC, C>::ld(e + PC) + w1 * St<SC, C>::ld(e + PC + sx);
-      const C x01 = w3 * St<SC, C>::ld(e + PC + oy) + w1 * St<SC, C>::ld(e + PC + oy + sx);
-      Y0 = w3 * x00 + w1 * x01;
+  int PC = cg.idx(i >> 1, j >> 1, K0);
+  auto plane = [&](int Q) -> C {
+    const C x0 = w3 * St<SC, C>::ld(e + Q) + w1 * St<SC, C>::ld(e + Q + sx);
+    const C x1 = w3 * St<SC, C>::ld(e + Q + oy) + w1 * St<SC, C>::ld(e + Q + oy + sx);
+    return w3 * x0 + w1 * x1;
+  };
+  C ym = 0, yc = plane(PC);
+  if (d3) ym = plane(PC - cg.sxy);
+  for (int K = K0; K < K1; ++K, PC += cg.sxy) {
+    const C yp = d3 ? plane(PC + cg.sxy) : (C)0;
+    const bool full = Cl.full[PC] != 0;
+    for (int c = 0; c < (d3 ? 2 : 1); ++c) {
+      const int k = d3 ? 2 * K + c : 0;
+      const int P = F.g.idx(i, j, k);
+      if (F.cls[P] == MG_INACTIVE) continue;
+      C Z;
+      if (full)
+        Z = d3 ? w3 * yc + w1 * (c ? yp : ym) : yc;
+      else
+        Z = prolong_checked<C, SC>(Cl, e, i, j, k);
+      St<S, C>::st(x + P, St<S, C>::ld(x + P) + Z);
     }
-    if (d3) {
-      const C x10 = w3 * St<SC, C>::ld(e + PC + oz) + w1 * St<SC, C>::ld(e + PC + oz + sx);
-      const C x11 =
-          w3 * St<SC, C>::ld(e + PC + oz + oy) + w1 * St<SC, C>::ld(e + PC + oz + oy + sx);
-      const C Y1 = w3 * x10 + w1 * x11;
-      Z = w3 * Y0 + w1 * Y1;
-    } else {
-      Z = Y0;
-    }
-    St<S, C>::st(x + P, St<S, C>::ld(x + P) + Z);
-    continue;
-  }
-  C X[2][2] = {{0, 0}, {0, 0}};
-  const int nzc = d3 ? 2 : 1;
-  for (int cc = 0; cc < nzc; ++cc)
-    for (int b = 0; b < 2; ++b) {
-      const int qj = J + b * sy, qk = K + cc * sz;
-      if (!act_at<SC, C>(Cl, I, qj, qk)) continue;
-      const int Q = cg.idx(I, qj, qk);
-      const C eq = St<SC, C>::ld(e + Q);
-      C en;
-      const int ri = I + sx;
-      if (ri < 0 || ri >= cg.nx) {
-        const C cfb = (C)Cl.cf0[sx > 0 ? Q + 1 : Q];
-        en = ((C)1 - cfb) * eq;
-      } else {
-        en = Cl.cls[Q + sx] != MG_INACTIVE ? St<SC, C>::ld(e + Q + sx) : eq;
-      }
-      X[cc][b] = w3 * eq + w1 * en;
-    }
-  C Y[2] = {0, 0};
-  for (int cc = 0; cc < nzc; ++cc) {
-    const int qk = K + cc * sz;
-    if (!act_at<SC, C>(Cl, I, J, qk)) continue;
-    C yn;
-    const int qj = J + sy;
-    if (qj < 0 || qj >= cg.ny) {
-      const int Q0 = cg.idx(I, J, qk);
-      const C cfb = (C)Cl.cf1[sy > 0 ? Q0 + cg.sx : Q0];
-      yn = ((C)1 - cfb) * X[cc][0];
-    } else {
-      yn = act_at<SC, C>(Cl, I, qj, qk) ? X[cc][1] : X[cc][0];
-    }
-    Y[cc] = w3 * X[cc][0] + w1 * yn;
-  }
-  C Z = Y[0];
-  if (d3) {
-    C zn;
-    const int qk = K + sz;
-    if (qk < 0 || qk >= cg.nz) {
-      const int Q0 = cg.idx(I, J, K);
-      const C cfb = (C)Cl.cf2[sz > 0 ? Q0 + cg.sxy : Q0];
-      zn = ((C)1 - cfb) * Y[0];
-    } else {
-      zn = act_at<SC, C>(Cl, I, J, qk) ? Y[1] : Y[0];
-    }
-    Z = w3 * Y[0] + w1 * zn;
-  }
-  St<S, C>::st(x + P, St<S, C>::ld(x + P) + Z);
+    ym = yc;
+    yc = yp;
   }
 }
 
 template <class S, class C, class SC>
 void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
-  const Tiles T = lvl_tiles(f, TK_PROLONG);
+  // tiles over fine columns and coarse planes
+  const Tiles T = make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_PROLONG]);
   hipLaunchKernelGGL((k_prolong<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f), T,
                      (S*)f.x[f.cur], view(c), (const SC*)c.x[c.cur], ctl);
 }
@@ -401,11 +521,24 @@ void launch_fill_zero(const Level& l, void* x, const double* ctl, hipStream_t s)
 // and writes one partial per workgroup (tiles outside the grid write zeros).
 
 // r = b - A x0 (x0 = 0 unless given), x = x0 on active cells, 0 elsewhere.
+// With z0 set, also the first sweep of the next V-cycle from zero on level 0:
+// z0 = wj b0 / D (C: level-0 arithmetic type).
+// (level-0 arithmetic is done in the level-0 storage type S)
+template <class O, class S>
+__device__ __forceinline__ void zero_sweep(const LevelView& L, int P, uint32_t cd, O rP,
+                                           S* __restrict__ b0, S* __restrict__ z0, S wj) {
+  S bs;
+  St<S, O>::st(&bs, rP);
+  b0[P] = bs;
+  if (z0) z0[P] = wj * bs / diag_code<S>(L.g, cd);
+}
+
 template <class O, class S>
 __global__ __launch_bounds__(MBS) void k_fcg_start(LevelView L, Tiles T, const O* __restrict__ b,
                                                    const O* __restrict__ x0, O* __restrict__ r,
                                                    O* __restrict__ x, S* __restrict__ b0,
-                                                   int have_x0, RedBuf red) {
+                                                   S* __restrict__ z0, S wj, int have_x0,
+                                                   RedBuf red) {
   int tx, ty, tz;
   double bb = 0.0, rr = 0.0;
   if (tile_of(T, tx, ty, tz)) {
@@ -415,20 +548,20 @@ __global__ __launch_bounds__(MBS) void k_fcg_start(LevelView L, Tiles T, const O
       const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
       for (int k = k0; k < k1; ++k) {
         const int P = g.idx(i, j, k);
-        const uint8_t cl = L.cls[P];
-        if (cl == MG_INACTIVE) continue;
+        const uint32_t cd = L.code[P];
+        if (cd == FACE_CODE_INACTIVE) continue;
         const O bP = b[P];
         O rP = bP, xP = 0;
         if (have_x0) {
           xP = x0[P];
           const O xm = g.dim == 3 ? x0[P - g.sxy] : (O)0, xp = g.dim == 3 ? x0[P + g.sxy] : (O)0;
           O Ax, D;
-          apply_z<O, O>(L, cl, x0, P, xP, xm, xp, Ax, D);
+          apply_code<O, O>(g, cd, x0, P, xP, xm, xp, Ax, D);
           rP = bP - Ax;
         }
         r[P] = rP;
         x[P] = xP;
-        St<S, O>::st(b0 + P, rP);
+        zero_sweep<O, S>(L, P, cd, rP, b0, z0, wj);
         bb += (double)bP * (double)bP;
         rr += (double)rP * (double)rP;
       }
@@ -480,10 +613,10 @@ __global__ __launch_bounds__(FIN) void k_fin_start(RedBuf red, int nb, double to
 template <class O, class S>
 void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, const RedBuf& red,
                       bool have_x0, double tol, int max_cycles, int forced, hipStream_t s,
-                      bool fin) {
+                      bool fin, void* z0, double wj) {
   const Tiles T = lvl_tiles(l0, TK_START);
   hipLaunchKernelGGL((k_fcg_start<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, b, x0,
-                     r, x, (S*)l0.b, have_x0 ? 1 : 0, red);
+                     r, x, (S*)l0.b, (S*)z0, (S)wj, have_x0 ? 1 : 0, red);
   if (fin)
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(FIN), 0, s, red, T.grid, tol * tol,
                        (double)max_cycles, (double)forced);
@@ -504,7 +637,7 @@ __global__ __launch_bounds__(MBS) void k_fcg_dots(LevelView L, Tiles T, const S*
       const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
       for (int k = k0; k < k1; ++k) {
         const int P = g.idx(i, j, k);
-        if (L.cls[P] == MG_INACTIVE) continue;
+        if (L.code[P] == FACE_CODE_INACTIVE) continue;
         const double zP = (double)St<S, O>::ld(z + P);
         zr += zP * (double)r[P];
         zq += zP * (double)q[P];
@@ -570,19 +703,10 @@ __global__ __launch_bounds__(MBS) void k_fcg_dir(LevelView L, Tiles T, const S* 
       O pm = d3 ? pn(P - g.sxy) : (O)0, pc = pn(P);
       for (int k = k0; k < k1; ++k, P += g.sxy) {
         const O pp = d3 ? pn(P + g.sxy) : (O)0;
-        const uint8_t cl = L.cls[P];
-        if (cl != MG_INACTIVE) {
-          O cxl = 1, cxh = 1, cyl = 1, cyh = 1, czl = 1, czh = 1;
-          if (cl != MG_REGULAR) {
-            cxl = (O)L.cf0[P];
-            cxh = (O)L.cf0[P + 1];
-            cyl = (O)L.cf1[P];
-            cyh = (O)L.cf1[P + g.sx];
-            if (d3) {
-              czl = (O)L.cf2[P];
-              czh = (O)L.cf2[P + g.sxy];
-            }
-          }
+        const uint32_t cd = L.code[P];
+        if (cd != FACE_CODE_INACTIVE) {
+          const O cxl = face_c<O>(cd, 0), cxh = face_c<O>(cd, 1), cyl = face_c<O>(cd, 2),
+                  cyh = face_c<O>(cd, 3), czl = face_c<O>(cd, 4), czh = face_c<O>(cd, 5);
           O Ap = (cxl * (pc - pn(P - 1)) + cxh * (pc - pn(P + 1))) * ih2x +
                  (cyl * (pc - pn(P - g.sx)) + cyh * (pc - pn(P + g.sx))) * ih2y;
           if (d3) Ap += (czl * (pc - pm) + czh * (pc - pp)) * ih2z;
@@ -614,7 +738,7 @@ template <class O, class S>
 __global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, Tiles T, O* __restrict__ x,
                                                     O* __restrict__ r, const O* p0, const O* p1,
                                                     const O* __restrict__ q, S* __restrict__ b0,
-                                                    RedBuf red) {
+                                                    S* __restrict__ z0, S wj, RedBuf red) {
   if (red.out[S_DONE] != 0.0) return;
   const int par = (int)red.out[S_ITER] & 1;
   const O* __restrict__ pv = par ? p1 : p0;
@@ -628,11 +752,12 @@ __global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, Tiles T, O* __r
       const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
       for (int k = k0; k < k1; ++k) {
         const int P = g.idx(i, j, k);
-        if (L.cls[P] == MG_INACTIVE) continue;
+        const uint32_t cd = L.code[P];
+        if (cd == FACE_CODE_INACTIVE) continue;
         x[P] += a * pv[P];
         const O rP = r[P] - a * q[P];
         r[P] = rP;
-        St<S, O>::st(b0 + P, rP);
+        zero_sweep<O, S>(L, P, cd, rP, b0, z0, wj);
         rr += (double)rP * (double)rP;
       }
     }
@@ -655,10 +780,10 @@ __global__ __launch_bounds__(FIN) void k_fin_update(RedBuf red, int nb) {
 
 template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p0, O* p1, const O* q, const RedBuf& red,
-                       hipStream_t s, bool fin) {
+                       hipStream_t s, bool fin, void* z0, double wj) {
   const Tiles T = lvl_tiles(l0, TK_UPDATE);
   hipLaunchKernelGGL((k_fcg_update<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, x, r,
-                     p0, p1, q, (S*)l0.b, red);
+                     p0, p1, q, (S*)l0.b, (S*)z0, (S)wj, red);
   if (fin) hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, red, T.grid);
 }
 
@@ -690,44 +815,126 @@ void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, 
 }
 
 // ---- LDS bottom solver ----------------------------------------------------------------
-// The same operators as the per-level kernels, on compact LDS arrays
-// (index (k ny + j) nx + i; neighbours outside the box read as 0, inactive
-// cells hold 0); coefficients and classes come from the level arrays.
+// The same operators as the per-level kernels on compact LDS arrays (cell
+// index (k ny + j) nx + i).  Everything a phase reads lives in LDS: iterates,
+// right-hand side, class bytes and the face coefficients (x faces
+// (nx+1) ny nz, y faces nx (ny+1) nz, z faces nx ny (nz+1), low face of cell
+// c at its own index, high face one row/plane further).  Neighbours outside
+// the box read as 0 and inactive cells hold 0, as in global memory.
 template <class C>
-__device__ __forceinline__ C lds_nb(const C* x, const BottomLevel& L, int i, int j, int k, int d,
-                                    int s) {
-  int q[3] = {i, j, k};
-  q[d] += s;
-  const int n3[3] = {L.g.nx, L.g.ny, L.g.nz};
-  if (q[d] < 0 || q[d] >= n3[d]) return (C)0;
-  return x[(q[2] * L.g.ny + q[1]) * L.g.nx + q[0]];
-}
+struct LdsLevel {
+  int nx, ny, nz, d3;
+  C ih2x, ih2y, ih2z;
+  C* x0;
+  C* x1;
+  C* b;
+  float* fx;
+  float* fy;
+  float* fz;
+  uint8_t* cls;
+};
 
 template <class C>
-__device__ __forceinline__ void lds_apply(const BottomLevel& L, const C* x, int i, int j, int k,
-                                          uint8_t cl, C xP, C& Ax, C& D) {
-  const Geom& g = L.g;
-  const C ih2[3] = {(C)(1.0 / (g.hx * g.hx)), (C)(1.0 / (g.hy * g.hy)), (C)(1.0 / (g.hz * g.hz))};
-  const int P = g.idx(i, j, k);
-  const int st[3] = {1, g.sx, g.sxy};
-  const float* cf[3] = {L.cf0, L.cf1, L.cf2};
-  C s = 0, d = 0;
-  for (int a = 0; a < g.dim; ++a) {
-    const C cl_ = cl == MG_REGULAR ? (C)1 : (C)cf[a][P];
-    const C ch_ = cl == MG_REGULAR ? (C)1 : (C)cf[a][P + st[a]];
-    s += (cl_ * (xP - lds_nb(x, L, i, j, k, a, -1)) + ch_ * (xP - lds_nb(x, L, i, j, k, a, 1))) *
-         ih2[a];
-    d += (cl_ + ch_) * ih2[a];
+__device__ __forceinline__ LdsLevel<C> lds_level(const BottomLevel& L, unsigned char* base) {
+  LdsLevel<C> v;
+  v.nx = L.g.nx;
+  v.ny = L.g.ny;
+  v.nz = L.g.nz;
+  v.d3 = L.g.dim == 3;
+  v.ih2x = (C)(1.0 / (L.g.hx * L.g.hx));
+  v.ih2y = (C)(1.0 / (L.g.hy * L.g.hy));
+  v.ih2z = (C)(1.0 / (L.g.hz * L.g.hz));
+  v.x0 = (C*)(base + L.bx0);
+  v.x1 = (C*)(base + L.bx1);
+  v.b = (C*)(base + L.bb);
+  v.fx = (float*)(base + L.bfx);
+  v.fy = (float*)(base + L.bfy);
+  v.fz = (float*)(base + L.bfz);
+  v.cls = base + L.bcl;
+  return v;
+}
+
+// A x and the diagonal at compact cell c = (i, j, k).
+template <class C>
+__device__ __forceinline__ void lds_apply(const LdsLevel<C>& L, const C* x, int c, int i, int j,
+                                          int k, C xP, C& Ax, C& D) {
+  const int nxy = L.nx * L.ny;
+  const int fxl = (k * L.ny + j) * (L.nx + 1) + i;
+  const C cxl = (C)L.fx[fxl], cxh = (C)L.fx[fxl + 1];
+  const C xw = i > 0 ? x[c - 1] : (C)0, xe = i < L.nx - 1 ? x[c + 1] : (C)0;
+  C s = (cxl * (xP - xw) + cxh * (xP - xe)) * L.ih2x;
+  C d = (cxl + cxh) * L.ih2x;
+  const int fyl = (k * (L.ny + 1) + j) * L.nx + i;
+  const C cyl = (C)L.fy[fyl], cyh = (C)L.fy[fyl + L.nx];
+  const C xs = j > 0 ? x[c - L.nx] : (C)0, xn = j < L.ny - 1 ? x[c + L.nx] : (C)0;
+  s += (cyl * (xP - xs) + cyh * (xP - xn)) * L.ih2y;
+  d += (cyl + cyh) * L.ih2y;
+  if (L.d3) {
+    const C czl = (C)L.fz[c], czh = (C)L.fz[c + nxy];
+    const C xb = k > 0 ? x[c - nxy] : (C)0, xt = k < L.nz - 1 ? x[c + nxy] : (C)0;
+    s += (czl * (xP - xb) + czh * (xP - xt)) * L.ih2z;
+    d += (czl + czh) * L.ih2z;
   }
   Ax = s;
   D = d;
 }
 
-template <class C>
-__device__ __forceinline__ void lds_cell(const BottomLevel& L, int c, int& i, int& j, int& k) {
-  i = c % L.g.nx;
-  j = (c / L.g.nx) % L.g.ny;
-  k = c / (L.g.nx * L.g.ny);
+__device__ __forceinline__ void lds_cell(int nx, int ny, int c, int& i, int& j, int& k) {
+  i = c % nx;
+  j = (c / nx) % ny;
+  k = c / (nx * ny);
+}
+
+// Builds the constant part of the bottom solver's LDS image (everything
+// from byte zero_bytes on) in global memory, once per grid.
+__global__ __launch_bounds__(1024) void k_bottom_image(Bottom B, unsigned char* __restrict__ img) {
+  const int t = threadIdx.x, NT = blockDim.x;
+  unsigned char* base = img - B.zero_bytes;  // LDS byte offsets index img + (off - zero_bytes)
+  const int nl = B.nlev;
+  for (int l = 0; l < nl; ++l) {
+    const BottomLevel& G = B.lv[l];
+    const Geom& g = G.g;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    uint8_t* cls = base + G.bcl;
+    float* fx = (float*)(base + G.bfx);
+    float* fy = (float*)(base + G.bfy);
+    float* fz = (float*)(base + G.bfz);
+    for (int c = t; c < G.n; c += NT) {
+      int i, j, k;
+      lds_cell(nx, ny, c, i, j, k);
+      cls[c] = G.cls[g.idx(i, j, k)];
+    }
+    const int nfx = (nx + 1) * ny * nz;
+    for (int e = t; e < nfx; e += NT) {
+      const int i = e % (nx + 1), j = (e / (nx + 1)) % ny, k = e / ((nx + 1) * ny);
+      fx[e] = G.cf0[g.idx(i, j, k)];
+    }
+    const int nfy = nx * (ny + 1) * nz;
+    for (int e = t; e < nfy; e += NT) {
+      const int i = e % nx, j = (e / nx) % (ny + 1), k = e / (nx * (ny + 1));
+      fy[e] = G.cf1[g.idx(i, j, k)];
+    }
+    if (g.dim == 3) {
+      const int nfz = nx * ny * (nz + 1);
+      for (int e = t; e < nfz; e += NT) {
+        const int i = e % nx, j = (e / nx) % ny, k = e / (nx * ny);
+        fz[e] = G.cf2[g.idx(i, j, k)];
+      }
+    }
+  }
+  int* cidx = (int*)(base + B.bcidx);
+  const int nco = *B.ncount;
+  const BottomLevel& G = B.lv[nl - 1];
+  if (nco <= B.max_n)
+    for (int a = t; a < nco; a += NT) {
+      const int P = B.cmap[a] - G.g.off;
+      const int kk = P / G.g.sxy, jj = (P % G.g.sxy) / G.g.sx, ii = P % G.g.sx;
+      cidx[a] = (kk * G.g.ny + jj) * G.g.nx + ii;
+    }
+}
+
+void launch_bottom_image(const Bottom& B, void* img, hipStream_t s) {
+  hipLaunchKernelGGL(k_bottom_image, dim3(1), dim3(1024), 0, s, B, (unsigned char*)img);
 }
 
 template <class SC, class C>
@@ -735,145 +942,181 @@ __global__ __launch_bounds__(1024) void k_bottom(Bottom B, const SC* __restrict_
                                                  SC* __restrict__ xtop,
                                                  const double* __restrict__ ctl) {
   if (ctl[S_DONE] != 0.0) return;
-  extern __shared__ unsigned char lds_raw[];
-  C* lds = (C*)lds_raw;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
   const int t = threadIdx.x, NT = blockDim.x;
   const C wj = (C)B.wj;
   const int nl = B.nlev;
-  for (int e = t; e < (int)(B.lds_bytes / sizeof(C)); e += NT) lds[e] = (C)0;
+  // iterates and right-hand sides start at zero
+  for (int e = t; e < B.zero_bytes / 4; e += NT) ((float*)lds_raw)[e] = 0.f;
+  // constant part (classes, face coefficients, coarsest-cell indices): one
+  // copy of the image built at set-up, 16 bytes per load, four loads in
+  // flight per thread
+  {
+    const uint4* __restrict__ src = (const uint4*)B.img;
+    uint4* dst = (uint4*)(lds_raw + B.zero_bytes);
+    const int n16 = (int)((B.lds_bytes - (size_t)B.zero_bytes) / 16);
+    for (int e0 = t; e0 < n16; e0 += 4 * NT) {
+      uint4 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q * NT < n16) v[q] = src[e0 + q * NT];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (e0 + q * NT < n16) dst[e0 + q * NT] = v[q];
+    }
+  }
+  int* cidx = (int*)(lds_raw + B.bcidx);
+  const int nco = *B.ncount;
   __syncthreads();
   {
-    const BottomLevel& L = B.lv[0];
-    for (int c = t; c < L.n; c += NT) {
-      int i, j, k;
-      lds_cell<C>(L, c, i, j, k);
-      lds[L.ob + c] = St<SC, C>::ld(btop + L.g.idx(i, j, k));
+    const BottomLevel& G = B.lv[0];
+    const LdsLevel<C> L = lds_level<C>(G, lds_raw);
+    for (int c0 = t; c0 < G.n; c0 += 4 * NT) {
+      C v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = c0 + q * NT;
+        if (c < G.n) {
+          int i, j, k;
+          lds_cell(L.nx, L.ny, c, i, j, k);
+          v[q] = St<SC, C>::ld(btop + G.g.idx(i, j, k));
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (c0 + q * NT < G.n) L.b[c0 + q * NT] = v[q];
     }
   }
   __syncthreads();
-  int cur[BOTTOM_MAX_LEVELS];
+  // current iterate buffer of every level, one bit per level (a bit mask
+  // rather than an array keeps it in a register)
+  unsigned curm = 0;
+  auto cur_of = [&](int l) -> int { return (int)((curm >> l) & 1u); };
+  auto set_cur = [&](int l, int v) { curm = (curm & ~(1u << l)) | ((unsigned)v << l); };
   // one damped-Jacobi sweep on level l from buffer cur (or from zero)
   auto sweep = [&](int l, bool zero) {
-    const BottomLevel& L = B.lv[l];
-    const C* xin = lds + (cur[l] ? L.ox1 : L.ox0);
-    C* xout = lds + (zero ? L.ox0 : (cur[l] ? L.ox0 : L.ox1));
-    const C* b = lds + L.ob;
-    for (int c = t; c < L.n; c += NT) {
+    const LdsLevel<C> L = lds_level<C>(B.lv[l], lds_raw);
+    const C* xin = cur_of(l) ? L.x1 : L.x0;
+    C* xout = zero ? L.x0 : (cur_of(l) ? L.x0 : L.x1);
+    const int n = B.lv[l].n;
+    for (int c = t; c < n; c += NT) {
+      if (L.cls[c] == MG_INACTIVE) continue;
       int i, j, k;
-      lds_cell<C>(L, c, i, j, k);
-      const uint8_t cl = L.cls[L.g.idx(i, j, k)];
-      if (cl == MG_INACTIVE) continue;
+      lds_cell(L.nx, L.ny, c, i, j, k);
       C Ax, D;
-      const C xP = zero ? (C)0 : xin[c];
-      lds_apply<C>(L, zero ? b : xin, i, j, k, cl, xP, Ax, D);
-      xout[c] = zero ? wj * b[c] / D : xP + wj * (b[c] - Ax) / D;
+      if (zero) {
+        lds_apply<C>(L, L.b, c, i, j, k, (C)0, Ax, D);
+        xout[c] = wj * L.b[c] / D;
+      } else {
+        const C xP = xin[c];
+        lds_apply<C>(L, xin, c, i, j, k, xP, Ax, D);
+        xout[c] = xP + wj * (L.b[c] - Ax) / D;
+      }
     }
-    cur[l] = zero ? 0 : (cur[l] ^ 1);
+    set_cur(l, zero ? 0 : (cur_of(l) ^ 1));
     __syncthreads();
   };
   for (int l = 0; l < nl - 1; ++l) {
-    cur[l] = 0;
+    set_cur(l, 0);
     if (B.nu1 > 0) {
       sweep(l, true);
       for (int s = 1; s < B.nu1; ++s) sweep(l, false);
-    } else {
-      const BottomLevel& L = B.lv[l];
-      for (int c = t; c < L.n; c += NT) lds[L.ox0 + c] = (C)0;
-      __syncthreads();
-    }
+    }  // else x0 is still zero
     // residual and restriction into level l + 1
-    const BottomLevel& F = B.lv[l];
-    const BottomLevel& Cc = B.lv[l + 1];
-    const C* x = lds + (cur[l] ? F.ox1 : F.ox0);
-    const int kz = Cc.g.dim == 3 ? 2 : 1;
-    for (int c = t; c < Cc.n; c += NT) {
+    const LdsLevel<C> F = lds_level<C>(B.lv[l], lds_raw);
+    const LdsLevel<C> Cc = lds_level<C>(B.lv[l + 1], lds_raw);
+    const C* x = cur_of(l) ? F.x1 : F.x0;
+    const int kz = Cc.d3 ? 2 : 1;
+    const int ncl = B.lv[l + 1].n;
+    for (int c = t; c < ncl; c += NT) {
+      if (Cc.cls[c] == MG_INACTIVE) continue;
       int I, J, K;
-      lds_cell<C>(Cc, c, I, J, K);
-      if (Cc.cls[Cc.g.idx(I, J, K)] == MG_INACTIVE) continue;
+      lds_cell(Cc.nx, Cc.ny, c, I, J, K);
       C sum = 0;
-      for (int cc = 0; cc < kz; ++cc)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
         for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
           for (int a = 0; a < 2; ++a) {
+            if (cc >= kz) continue;
             const int i = 2 * I + a, j = 2 * J + bb, k = kz * K + cc;
-            const uint8_t cl = F.cls[F.g.idx(i, j, k)];
-            if (cl == MG_INACTIVE) continue;
-            const int fc = (k * F.g.ny + j) * F.g.nx + i;
+            const int fc = (k * F.ny + j) * F.nx + i;
+            if (F.cls[fc] == MG_INACTIVE) continue;
             C Ax, D;
-            lds_apply<C>(F, x, i, j, k, cl, x[fc], Ax, D);
-            sum += lds[F.ob + fc] - Ax;
+            lds_apply<C>(F, x, fc, i, j, k, x[fc], Ax, D);
+            sum += F.b[fc] - Ax;
           }
-      lds[Cc.ob + c] = sum * (C)(kz == 2 ? 0.125 : 0.25);
+      Cc.b[c] = sum * (C)(kz == 2 ? 0.125 : 0.25);
     }
     __syncthreads();
   }
   // coarsest level: dense inverse
   {
     const int l = nl - 1;
-    const BottomLevel& L = B.lv[l];
-    const int n = *B.ncount;
-    cur[l] = 0;
-    if (n <= B.max_n) {
-      for (int a = t; a < n; a += NT) {
+    const LdsLevel<C> L = lds_level<C>(B.lv[l], lds_raw);
+    set_cur(l, 0);
+    if (nco <= B.max_n) {
+      for (int a = t; a < nco; a += NT) {
         C s = 0;
-        const double* row = B.ainv + (size_t)a * n;
-        for (int q = 0; q < n; ++q) {
-          const int P = B.cmap[q] - L.g.off;
-          const int kk = P / L.g.sxy, jj = (P % L.g.sxy) / L.g.sx, ii = P % L.g.sx;
-          s += (C)row[q] * lds[L.ob + (kk * L.g.ny + jj) * L.g.nx + ii];
-        }
-        const int P = B.cmap[a] - L.g.off;
-        const int kk = P / L.g.sxy, jj = (P % L.g.sxy) / L.g.sx, ii = P % L.g.sx;
-        lds[L.ox0 + (kk * L.g.ny + jj) * L.g.nx + ii] = s;
+        const double* row = B.ainv + (size_t)a * nco;
+        for (int q = 0; q < nco; ++q) s += (C)row[q] * L.b[cidx[q]];
+        L.x0[cidx[a]] = s;
       }
     }
     __syncthreads();
   }
   // up the hierarchy: prolongation and post-smoothing
   for (int l = nl - 2; l >= 0; --l) {
-    const BottomLevel& F = B.lv[l];
-    const BottomLevel& Cc = B.lv[l + 1];
-    C* x = lds + (cur[l] ? F.ox1 : F.ox0);
-    const C* e = lds + (cur[l + 1] ? Cc.ox1 : Cc.ox0);
-    const Geom& cg = Cc.g;
-    const bool d3 = cg.dim == 3;
+    const LdsLevel<C> F = lds_level<C>(B.lv[l], lds_raw);
+    const LdsLevel<C> Cc = lds_level<C>(B.lv[l + 1], lds_raw);
+    C* x = cur_of(l) ? F.x1 : F.x0;
+    const C* e = cur_of(l + 1) ? Cc.x1 : Cc.x0;
+    const bool d3 = Cc.d3;
+    const int cnx = Cc.nx, cny = Cc.ny, cnz = Cc.nz;
+    auto cc_of = [&](int I, int J, int K) { return (K * cny + J) * cnx + I; };
     auto act = [&](int I, int J, int K) -> bool {
-      if (I < 0 || J < 0 || K < 0 || I >= cg.nx || J >= cg.ny || K >= cg.nz) return false;
-      return Cc.cls[cg.idx(I, J, K)] != MG_INACTIVE;
+      if (I < 0 || J < 0 || K < 0 || I >= cnx || J >= cny || K >= cnz) return false;
+      return Cc.cls[cc_of(I, J, K)] != MG_INACTIVE;
     };
-    auto ev = [&](int I, int J, int K) -> C { return e[(K * cg.ny + J) * cg.nx + I]; };
-    for (int c = t; c < F.n; c += NT) {
+    const int nf = B.lv[l].n;
+    for (int c = t; c < nf; c += NT) {
+      if (F.cls[c] == MG_INACTIVE) continue;
       int i, j, k;
-      lds_cell<C>(F, c, i, j, k);
-      if (F.cls[F.g.idx(i, j, k)] == MG_INACTIVE) continue;
+      lds_cell(F.nx, F.ny, c, i, j, k);
       const int I = i >> 1, J = j >> 1, K = d3 ? (k >> 1) : 0;
       const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
       const C w3 = (C)0.75, w1 = (C)0.25;
       C X[2][2] = {{0, 0}, {0, 0}};
       const int nzc = d3 ? 2 : 1;
-      for (int cc = 0; cc < nzc; ++cc)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
         for (int b = 0; b < 2; ++b) {
           const int qj = J + b * sy, qk = K + cc * sz;
-          if (!act(I, qj, qk)) continue;
-          const C eq = ev(I, qj, qk);
+          if (cc >= nzc || !act(I, qj, qk)) continue;
+          const C eq = e[cc_of(I, qj, qk)];
           C en;
           const int ri = I + sx;
-          if (ri < 0 || ri >= cg.nx) {
-            const int Q = cg.idx(I, qj, qk);
-            en = ((C)1 - (C)Cc.cf0[sx > 0 ? Q + 1 : Q]) * eq;
+          if (ri < 0 || ri >= cnx) {
+            // boundary x face of coarse cell (I, qj, qk)
+            const int f = (qk * cny + qj) * (cnx + 1) + I + (sx > 0 ? 1 : 0);
+            en = ((C)1 - (C)Cc.fx[f]) * eq;
           } else {
-            en = act(ri, qj, qk) ? ev(ri, qj, qk) : eq;
+            en = act(ri, qj, qk) ? e[cc_of(ri, qj, qk)] : eq;
           }
           X[cc][b] = w3 * eq + w1 * en;
         }
       C Y[2] = {0, 0};
-      for (int cc = 0; cc < nzc; ++cc) {
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc) {
         const int qk = K + cc * sz;
-        if (!act(I, J, qk)) continue;
+        if (cc >= nzc || !act(I, J, qk)) continue;
         C yn;
         const int qj = J + sy;
-        if (qj < 0 || qj >= cg.ny) {
-          const int Q0 = cg.idx(I, J, qk);
-          yn = ((C)1 - (C)Cc.cf1[sy > 0 ? Q0 + cg.sx : Q0]) * X[cc][0];
+        if (qj < 0 || qj >= cny) {
+          const int f = (qk * (cny + 1) + J + (sy > 0 ? 1 : 0)) * cnx + I;
+          yn = ((C)1 - (C)Cc.fy[f]) * X[cc][0];
         } else {
           yn = act(I, qj, qk) ? X[cc][1] : X[cc][0];
         }
@@ -883,9 +1126,9 @@ __global__ __launch_bounds__(1024) void k_bottom(Bottom B, const SC* __restrict_
       if (d3) {
         C zn;
         const int qk = K + sz;
-        if (qk < 0 || qk >= cg.nz) {
-          const int Q0 = cg.idx(I, J, K);
-          zn = ((C)1 - (C)Cc.cf2[sz > 0 ? Q0 + cg.sxy : Q0]) * Y[0];
+        if (qk < 0 || qk >= cnz) {
+          const int f = ((K + (sz > 0 ? 1 : 0)) * cny + J) * cnx + I;
+          zn = ((C)1 - (C)Cc.fz[f]) * Y[0];
         } else {
           zn = act(I, J, qk) ? Y[1] : Y[0];
         }
@@ -897,16 +1140,37 @@ __global__ __launch_bounds__(1024) void k_bottom(Bottom B, const SC* __restrict_
     for (int s = 0; s < B.nu2; ++s) sweep(l, false);
   }
   {
-    const BottomLevel& L = B.lv[0];
-    const C* x = lds + (cur[0] ? L.ox1 : L.ox0);
-    for (int c = t; c < L.n; c += NT) {
+    const BottomLevel& G = B.lv[0];
+    const LdsLevel<C> L = lds_level<C>(G, lds_raw);
+    const C* x = cur_of(0) ? L.x1 : L.x0;
+    for (int c = t; c < G.n; c += NT) {
+      if (L.cls[c] == MG_INACTIVE) continue;
       int i, j, k;
-      lds_cell<C>(L, c, i, j, k);
-      const int P = L.g.idx(i, j, k);
-      if (L.cls[P] != MG_INACTIVE) St<SC, C>::st(xtop + P, x[c]);
+      lds_cell(L.nx, L.ny, c, i, j, k);
+      St<SC, C>::st(xtop + G.g.idx(i, j, k), x[c]);
     }
   }
 }
+
+// LDS bytes one bottom workgroup may use on the current device (dynamic
+// shared memory above 64 KiB is enabled per kernel where the device has it).
+template <class SC, class C>
+size_t bottom_lds_limit() {
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      lim <= 64 * 1024)
+    return 64 * 1024;
+  if (hipFuncSetAttribute((const void*)k_bottom<SC, C>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return (size_t)lim;
+}
+template size_t bottom_lds_limit<double, double>();
+template size_t bottom_lds_limit<float, float>();
+template size_t bottom_lds_limit<bf16, float>();
 
 template <class SC, class C>
 void launch_bottom(const Bottom& B, const void* btop, void* xtop, const double* ctl,
@@ -951,13 +1215,13 @@ template void launch_coarse_solve<bf16, float>(const Level&, const int*, const i
 
 #define INST_FCG(O, S)                                                                          \
   template void launch_fcg_start<O, S>(const Level&, const O*, const O*, O*, O*, const RedBuf&, \
-                                       bool, double, int, int, hipStream_t, bool);              \
+                                       bool, double, int, int, hipStream_t, bool, void*, double); \
   template void launch_fcg_dots<O, S>(const Level&, const O*, const O*, const RedBuf&,          \
                                       hipStream_t, bool);                                       \
   template void launch_fcg_dir<O, S>(const Level&, O*, O*, O*, const RedBuf&, hipStream_t,      \
                                      bool);                                                     \
   template void launch_fcg_update<O, S>(const Level&, O*, O*, O*, O*, const O*, const RedBuf&,  \
-                                        hipStream_t, bool);
+                                        hipStream_t, bool, void*, double);
 INST_FCG(double, double)
 INST_FCG(float, float)
 INST_FCG(double, float)

@@ -81,8 +81,12 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
       R gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
       const int st[3] = {1, g.sx, g.sxy};
       const R ih2[3] = {(R)(0.5 / g.hx), (R)(0.5 / g.hy), (R)(0.5 / g.hz)};
-      for (int d = 0; d < g.dim; ++d)
+      // constant trip counts keep G, gk and gw in registers
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
         for (int s = -1; s <= 1; s += 2) {
+          if (d >= g.dim) continue;
           const int N = P + s * st[d];
           const uint8_t tn = type[N];
           R vn[3], kn_, wn_;
@@ -99,7 +103,9 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
             wn_ = ghost<R>(pp, G_OM, wP, ph.komega);
           }
           const R sc = (R)s * ih2[d];
-          for (int a = 0; a < g.dim; ++a) G[a][d] += sc * vn[a];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            if (a < g.dim) G[a][d] += sc * vn[a];
           gk[d] += sc * kn_;
           gw[d] += sc * wn_;
         }
@@ -396,11 +402,14 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
       const O dt = (O)ph.dt;
       const O fP = phi[C0];
       O div = 0;
-      O unew[3];
-      for (int d = 0; d < g.dim; ++d) {
+      O unew[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d >= g.dim) continue;
         const O vp = (O)vel[d][C0];
         O grad = 0;
         O fl[2];
+#pragma unroll
         for (int s = -1; s <= 1; s += 2) {
           const int N = C0 + s * st[d];
           const uint8_t tn = type[N];
@@ -424,6 +433,7 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
         unew[d] = vp - dt * grad * (O)0.5 * ih[d];
         div += (fl[1] - fl[0]) * ih[d];
       }
+#pragma unroll
       for (int d = 0; d < 3; ++d) vout[d][C0] = d < g.dim ? (F)unew[d] : vel[d][C0];
       p[C0] = (P)((O)p[C0] + fP);
       mdiv = fmax(mdiv, fabs((double)div));

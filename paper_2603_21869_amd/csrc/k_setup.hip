@@ -184,6 +184,31 @@ void launch_level0(const Geom& g, const uint8_t* type, const DevPatch* pt, uint8
                      g, type, pt, cls, cx, cy, cz);
 }
 
+// Level-0 face codes from the class bytes and face coefficients (which are
+// 0, 1 or 2 on level 0).
+__global__ void k_face_codes(Geom g, const uint8_t* __restrict__ cls, const float* __restrict__ cx,
+                             const float* __restrict__ cy, const float* __restrict__ cz,
+                             uint16_t* __restrict__ code) {
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int P = g.idx(i, j, k);
+  if (cls[P] == MG_INACTIVE) {
+    code[P] = (uint16_t)FACE_CODE_INACTIVE;
+    return;
+  }
+  const float f[6] = {cx[P], cx[P + 1], cy[P], cy[P + g.sx], g.dim == 3 ? cz[P] : 0.f,
+                      g.dim == 3 ? cz[P + g.sxy] : 0.f};
+  uint32_t c = 0;
+  for (int q = 0; q < 6; ++q) c |= ((uint32_t)f[q] & 3u) << (2 * q);
+  code[P] = (uint16_t)c;
+}
+
+void launch_face_codes(const Geom& g, const uint8_t* cls, const float* cx, const float* cy,
+                       const float* cz, uint16_t* code, hipStream_t s) {
+  hipLaunchKernelGGL(k_face_codes, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), dim3(64, 4), 0, s,
+                     g, cls, cx, cy, cz, code);
+}
+
 // Coarse level: a cell is active when any child is; a face coefficient is the
 // mean of the fine sub-face coefficients it covers.
 __global__ void k_coarsen(Geom f, const uint8_t* __restrict__ fcls, const float* __restrict__ fx,

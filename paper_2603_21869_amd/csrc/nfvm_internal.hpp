@@ -106,7 +106,15 @@ struct Level {
   void* x[2];                   // iterate, ping-pong (storage type of the level)
   void* b;                      // right-hand side
   int cur;                      // which x is current
+  uint16_t* code;               // level 0 only: face codes (else null)
 };
+
+// Level-0 face code of a cell: 2 bits per face (x-, x+, y-, y+, z-, z+ from
+// bit 0), each the face coefficient c_f in {0, 1, 2}; inactive cells hold
+// FACE_CODE_INACTIVE.
+constexpr uint32_t FACE_CODE_INACTIVE = 0xFFFFu;
+void launch_face_codes(const Geom& g, const uint8_t* cls, const float* cx, const float* cy,
+                       const float* cz, uint16_t* code, hipStream_t s);
 
 // Device-wide reduction scratch: per-block partials, a completion counter and
 // the reduced scalars.
@@ -211,20 +219,28 @@ struct BottomLevel {
   const float* cf0;
   const float* cf1;
   const float* cf2;
-  int n;              // cells (nx * ny * nz)
-  int ox0, ox1, ob;   // LDS offsets in elements
+  int n;  // cells (nx * ny * nz)
+  // LDS byte offsets: iterates, right-hand side, x / y / z face
+  // coefficients, class bytes
+  int bx0, bx1, bb, bfx, bfy, bfz, bcl;
 };
 struct Bottom {
-  int nlev;           // levels top .. L-1
+  int nlev;  // levels top .. L-1
   int nu1, nu2;
   double wj;
   BottomLevel lv[BOTTOM_MAX_LEVELS];
-  const int* cmap;    // padded indices of the coarsest active cells
+  const int* cmap;  // padded indices of the coarsest active cells
   const int* ncount;
   const double* ainv;
   int max_n;
+  int bcidx;       // LDS byte offset of the coarsest cells' compact indices
+  int zero_bytes;  // leading LDS bytes (iterates, right-hand sides) cleared per launch
   size_t lds_bytes;
+  const void* img;  // LDS bytes [zero_bytes, lds_bytes) as built by launch_bottom_image
 };
+void launch_bottom_image(const Bottom& B, void* img, hipStream_t s);
+template <class SC, class C>
+size_t bottom_lds_limit();
 template <class SC, class C>
 void launch_bottom(const Bottom& B, const void* btop, void* xtop, const double* ctl,
                    hipStream_t s);
@@ -237,7 +253,7 @@ void launch_bottom(const Bottom& B, const void* btop, void* xtop, const double* 
 template <class O, class S>
 void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, const RedBuf& red,
                       bool have_x0, double tol, int max_cycles, int forced, hipStream_t s,
-                      bool fin = true);
+                      bool fin = true, void* z0 = nullptr, double wj = 0.0);
 template <class O, class S>
 void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
                      bool fin = true);
@@ -246,6 +262,6 @@ void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipS
                     bool fin = true);
 template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p0, O* p1, const O* q, const RedBuf& red,
-                       hipStream_t s, bool fin = true);
+                       hipStream_t s, bool fin = true, void* z0 = nullptr, double wj = 0.0);
 
 }  // namespace nfvm

@@ -84,7 +84,9 @@ struct nfvm_server {
     d.solid_mask = r->mask.empty() ? nullptr : r->mask.data();
     nfvm_status st = NFVM_OK;
     try {
-      std::unique_ptr<GridBase> g = make_grid(d, &init, nullptr);
+      // tiles: the autotuner's cached choices, never a tuning run on the
+      // request's critical path
+      std::unique_ptr<GridBase> g = make_grid(d, &init, nullptr, 2);
       for (int s = 0; s < r->n_steps; ++s) {
         nfvm_step_stats ss{};
         nfvm_status one = NFVM_OK;

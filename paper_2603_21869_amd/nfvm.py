@@ -271,9 +271,13 @@ def nfvm_submit(server, desc: Desc, fields: Dict[str, np.ndarray], n_steps: int)
     return t.value
 
 
-def nfvm_poll(server, ticket: int, shape, allow=(NFVM_OK, NFVM_PENDING)):
-    out = {n: np.zeros(shape) for n in FIELD_ORDER}
+def nfvm_poll(server, ticket: int, shape=None, allow=(NFVM_OK, NFVM_PENDING)):
+    """Poll a request; with shape None the fields are not copied back."""
     st = nfvm_step_stats()
+    if shape is None:
+        s = _check(lib().nfvm_poll(server, ticket, None, C.byref(st)), allow)
+        return s, None, st.as_dict()
+    out = {n: np.zeros(shape) for n in FIELD_ORDER}
     s = _check(lib().nfvm_poll(server, ticket, C.byref(_fields_struct(out)), C.byref(st)), allow)
     return s, (out if s != NFVM_PENDING else None), st.as_dict()
 
