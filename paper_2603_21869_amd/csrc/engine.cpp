@@ -452,7 +452,7 @@ class GridT : public GridBase {
         });
         v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT, v.g, [&](int tt) {
           v.tt[TK_RESTRICT] = tt;
-          launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream);
+          launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream, zero_of(1), wj);
         });
         v.tt[TK_PROLONG] = tune_one(TK_PROLONG, v.g, [&](int tt) {
           v.tt[TK_PROLONG] = tt;
@@ -486,7 +486,8 @@ class GridT : public GridBase {
         });
         v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT + 1000, v.g, [&](int tt) {
           v.tt[TK_RESTRICT] = tt;
-          launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
+          launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream, zero_of(l + 1),
+                                           wj);
         });
         v.tt[TK_PROLONG] = tune_one(TK_PROLONG + 1000, v.g, [&](int tt) {
           v.tt[TK_PROLONG] = tt;
@@ -580,7 +581,8 @@ class GridT : public GridBase {
     return al16(f * sizeof(float));
   }
   static size_t bottom_bytes(const Geom& g) {
-    return al16(3 * g.cells() * sizeof(C)) + faces_bytes(g) + al16(g.cells());
+    return al16(3 * g.cells() * sizeof(C)) + faces_bytes(g) + al16(g.cells() * sizeof(C)) +
+           al16(g.cells());
   }
 
   void setup_bottom() {
@@ -623,7 +625,11 @@ class GridT : public GridBase {
       b.bfy = (int)(off + (size_t)(g.nx + 1) * g.ny * g.nz * sizeof(float));
       b.bfz = (int)(b.bfy + (size_t)g.nx * (g.ny + 1) * g.nz * sizeof(float));
       off += faces_bytes(g);
+      b.bwd = (int)off;
+      off += al16(g.cells() * sizeof(C));
       b.bcl = (int)off;
+      b.inx = 1.0f / (float)g.nx;
+      b.inxy = 1.0f / ((float)g.nx * (float)g.ny);
       off += al16(g.cells());
     }
     bot.bcidx = (int)off;
@@ -638,7 +644,7 @@ class GridT : public GridBase {
       bot_img = alloc<unsigned char>(bot_img_bytes);
     }
     bot.img = bot_img;
-    launch_bottom_image(bot, bot_img, stream);
+    launch_bottom_image<C>(bot, bot_img, stream);
     NFVM_CK(hipGetLastError());
   }
   unsigned char* bot_img = nullptr;
@@ -647,9 +653,13 @@ class GridT : public GridBase {
   // Level-0 buffer that the CG start / update kernels fill with the first
   // pre-smoothing sweep (from zero) of the next V-cycle, or null when level 0
   // is handled by the bottom solver or the coarsest solve.
-  void* zero0() const {
-    return (nu1 > 0 && bottom_top != 0 && L > 1) ? lv[0].x[0] : nullptr;
-  }
+  void* zero0() const { return fused_zero(0) ? lv[0].x[0] : nullptr; }
+  // Whether level l gets its first pre-smoothing sweep from the kernel that
+  // writes its right-hand side (CG start / update for level 0, the
+  // restriction from level l - 1 otherwise): levels that run a regular
+  // V-cycle step with pre-smoothing.
+  bool fused_zero(int l) const { return nu1 > 0 && l != bottom_top && l < L - 1; }
+  void* zero_of(int l) const { return fused_zero(l) ? lv[l].x[0] : nullptr; }
 
   void vcycle(int l) {
     Level& v = lv[l];
@@ -667,8 +677,8 @@ class GridT : public GridBase {
       return;
     }
     if (nu1 > 0) {
-      if (l == 0 && zero0()) {
-        v.cur = 0;  // first sweep from zero done by the CG start / update kernel
+      if (fused_zero(l)) {
+        v.cur = 0;  // first sweep from zero done by the kernel that wrote v.b
       } else {
         smooth(l, true);
       }
@@ -682,10 +692,10 @@ class GridT : public GridBase {
     }
     if (l == 0) {
       prof_begin(NFVM_K_RESTRICT0);
-      launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream);
+      launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream, zero_of(1), wj);
       prof_end(NFVM_K_RESTRICT0);
     } else
-      launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
+      launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream, zero_of(l + 1), wj);
     vcycle(l + 1);
     if (l == 0) {
       prof_begin(NFVM_K_PROLONG0);

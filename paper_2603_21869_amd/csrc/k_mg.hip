@@ -167,6 +167,22 @@ __device__ __forceinline__ void apply_z(const LevelView& L, uint8_t cl, const S*
   D = d;
 }
 
+// Diagonal of A at cell P (active), formed as apply_z forms it.
+template <class C>
+__device__ __forceinline__ C diag_at(const LevelView& L, uint8_t cl, int P) {
+  const Geom& g = L.g;
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
+  if (cl == MG_REGULAR) {
+    C d = (C)2 * (ih2x + ih2y);
+    if (g.dim == 3) d += (C)2 * ih2z;
+    return d;
+  }
+  C d = ((C)L.cf0[P] + (C)L.cf0[P + 1]) * ih2x + ((C)L.cf1[P] + (C)L.cf1[P + g.sx]) * ih2y;
+  if (g.dim == 3) d += ((C)L.cf2[P] + (C)L.cf2[P + g.sxy]) * ih2z;
+  return d;
+}
+
 // ---- damped Jacobi sweep: x_out = x_in + w (b - A x_in) / D -------------------
 // Each thread walks cz planes of one column with x(k-1), x(k), x(k+1) in
 // registers; in-plane neighbours come through the cache.
@@ -196,8 +212,7 @@ __global__ __launch_bounds__(MBS) void k_smooth(LevelView L, Tiles T, const S* _
       const C bP = St<S, C>::ld(b + P);
       C Ax, D;
       if (ZERO) {
-        apply_z<S, C>(L, cl, b, P, (C)0, (C)0, (C)0, Ax, D);
-        St<S, C>::st(xout + P, wj * bP / D);
+        St<S, C>::st(xout + P, wj * bP / diag_at<C>(L, cl, P));
       } else {
         apply_z<S, C>(L, cl, xin, P, xc, xm, xp, Ax, D);
         St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
@@ -289,6 +304,7 @@ __global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, Tiles T,
                                                         const S* __restrict__ x,
                                                         const S* __restrict__ b, LevelView Cl,
                                                         SC* __restrict__ bc,
+                                                        SC* __restrict__ zc, C wj,
                                                         const double* __restrict__ ctl) {
   if (ctl[S_DONE] != 0.0) return;
   __shared__ C sh[MBY][MBX];
@@ -336,18 +352,25 @@ __global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, Tiles T,
     __syncthreads();
     if (in && !(lx & 1) && !(ly & 1)) {
       const int PC = Cl.g.idx(i >> 1, j >> 1, K);
-      if (Cl.cls[PC] != MG_INACTIVE)
-        St<SC, C>::st(bc + PC, (sh[ly][lx] + sh[ly + 1][lx]) * (C)(d3 ? 0.125 : 0.25));
+      const uint8_t ccl = Cl.cls[PC];
+      if (ccl != MG_INACTIVE) {
+        SC* dst = bc + PC;
+        St<SC, C>::st(dst, (sh[ly][lx] + sh[ly + 1][lx]) * (C)(d3 ? 0.125 : 0.25));
+        // first pre-smoothing sweep (from zero) of the coarse level
+        if (zc) St<SC, C>::st(zc + PC, wj * St<SC, C>::ld(dst) / diag_at<C>(Cl, ccl, PC));
+      }
     }
     __syncthreads();
   }
 }
 
 template <class S, class C, class SC>
-void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
+void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s,
+                           void* zc, double wj) {
   const Tiles T = make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_RESTRICT]);
   hipLaunchKernelGGL((k_resid_restrict<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f),
-                     T, (const S*)f.x[f.cur], (const S*)f.b, view(c), (SC*)c.b, ctl);
+                     T, (const S*)f.x[f.cur], (const S*)f.b, view(c), (SC*)c.b, (SC*)zc, (C)wj,
+                     ctl);
 }
 
 // ---- prolongation and correction: x_f += PROL(e_c) ------------------------------
@@ -821,22 +844,31 @@ void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, 
 // (nx+1) ny nz, y faces nx (ny+1) nz, z faces nx ny (nz+1), low face of cell
 // c at its own index, high face one row/plane further).  Neighbours outside
 // the box read as 0 and inactive cells hold 0, as in global memory.
+// The workgroup's dynamic LDS.  Level arrays are addressed as byte offsets
+// from it (pointers kept in memory would lose the LDS address space and
+// turn every access into a flat one).
+extern __shared__ __align__(16) unsigned char bot_lds[];
+
 template <class C>
 struct LdsLevel {
-  int nx, ny, nz, d3;
+  int n, nx, ny, nz, d3;
+  float inx, inxy;
   C ih2x, ih2y, ih2z;
-  C* x0;
-  C* x1;
-  C* b;
-  float* fx;
-  float* fy;
-  float* fz;
-  uint8_t* cls;
+  int ox0, ox1, ob, ofx, ofy, ofz, owd, ocl;  // byte offsets in bot_lds
+  __device__ C* x0() const { return (C*)(bot_lds + ox0); }
+  __device__ C* x1() const { return (C*)(bot_lds + ox1); }
+  __device__ C* b() const { return (C*)(bot_lds + ob); }
+  __device__ const float* fx() const { return (const float*)(bot_lds + ofx); }
+  __device__ const float* fy() const { return (const float*)(bot_lds + ofy); }
+  __device__ const float* fz() const { return (const float*)(bot_lds + ofz); }
+  __device__ const C* wd() const { return (const C*)(bot_lds + owd); }
+  __device__ const uint8_t* cls() const { return bot_lds + ocl; }
 };
 
 template <class C>
-__device__ __forceinline__ LdsLevel<C> lds_level(const BottomLevel& L, unsigned char* base) {
+__device__ __forceinline__ LdsLevel<C> lds_level(const BottomLevel& L) {
   LdsLevel<C> v;
+  v.n = L.n;
   v.nx = L.g.nx;
   v.ny = L.g.ny;
   v.nz = L.g.nz;
@@ -844,39 +876,58 @@ __device__ __forceinline__ LdsLevel<C> lds_level(const BottomLevel& L, unsigned 
   v.ih2x = (C)(1.0 / (L.g.hx * L.g.hx));
   v.ih2y = (C)(1.0 / (L.g.hy * L.g.hy));
   v.ih2z = (C)(1.0 / (L.g.hz * L.g.hz));
-  v.x0 = (C*)(base + L.bx0);
-  v.x1 = (C*)(base + L.bx1);
-  v.b = (C*)(base + L.bb);
-  v.fx = (float*)(base + L.bfx);
-  v.fy = (float*)(base + L.bfy);
-  v.fz = (float*)(base + L.bfz);
-  v.cls = base + L.bcl;
+  v.ox0 = L.bx0;
+  v.ox1 = L.bx1;
+  v.ob = L.bb;
+  v.ofx = L.bfx;
+  v.ofy = L.bfy;
+  v.ofz = L.bfz;
+  v.owd = L.bwd;
+  v.ocl = L.bcl;
+  v.inx = L.inx;
+  v.inxy = L.inxy;
   return v;
 }
 
-// A x and the diagonal at compact cell c = (i, j, k).
+// A x at compact cell c = (i, j, k).
 template <class C>
-__device__ __forceinline__ void lds_apply(const LdsLevel<C>& L, const C* x, int c, int i, int j,
-                                          int k, C xP, C& Ax, C& D) {
+__device__ __forceinline__ C lds_apply(const LdsLevel<C>& L, const C* x, int c, int i, int j,
+                                       int k, C xP) {
   const int nxy = L.nx * L.ny;
   const int fxl = (k * L.ny + j) * (L.nx + 1) + i;
-  const C cxl = (C)L.fx[fxl], cxh = (C)L.fx[fxl + 1];
+  const float* fx = L.fx();
+  const C cxl = (C)fx[fxl], cxh = (C)fx[fxl + 1];
   const C xw = i > 0 ? x[c - 1] : (C)0, xe = i < L.nx - 1 ? x[c + 1] : (C)0;
   C s = (cxl * (xP - xw) + cxh * (xP - xe)) * L.ih2x;
-  C d = (cxl + cxh) * L.ih2x;
   const int fyl = (k * (L.ny + 1) + j) * L.nx + i;
-  const C cyl = (C)L.fy[fyl], cyh = (C)L.fy[fyl + L.nx];
+  const float* fy = L.fy();
+  const C cyl = (C)fy[fyl], cyh = (C)fy[fyl + L.nx];
   const C xs = j > 0 ? x[c - L.nx] : (C)0, xn = j < L.ny - 1 ? x[c + L.nx] : (C)0;
   s += (cyl * (xP - xs) + cyh * (xP - xn)) * L.ih2y;
-  d += (cyl + cyh) * L.ih2y;
   if (L.d3) {
-    const C czl = (C)L.fz[c], czh = (C)L.fz[c + nxy];
+    const float* fz = L.fz();
+    const C czl = (C)fz[c], czh = (C)fz[c + nxy];
     const C xb = k > 0 ? x[c - nxy] : (C)0, xt = k < L.nz - 1 ? x[c + nxy] : (C)0;
     s += (czl * (xP - xb) + czh * (xP - xt)) * L.ih2z;
-    d += (czl + czh) * L.ih2z;
   }
-  Ax = s;
-  D = d;
+  return s;
+}
+
+// q = n / d for 0 <= n < 2^22 from a float reciprocal of d, corrected to the
+// exact integer quotient.
+__device__ __forceinline__ int qdiv(int n, int d, float inv) {
+  int q = (int)((float)n * inv);
+  const int r = n - q * d;
+  q += (r >= d) - (r < 0);
+  return q;
+}
+
+template <class C>
+__device__ __forceinline__ void lds_ijk(const LdsLevel<C>& L, int c, int& i, int& j, int& k) {
+  k = qdiv(c, L.nx * L.ny, L.inxy);
+  const int r = c - k * L.nx * L.ny;
+  j = qdiv(r, L.nx, L.inx);
+  i = r - j * L.nx;
 }
 
 __device__ __forceinline__ void lds_cell(int nx, int ny, int c, int& i, int& j, int& k) {
@@ -887,6 +938,7 @@ __device__ __forceinline__ void lds_cell(int nx, int ny, int c, int& i, int& j, 
 
 // Builds the constant part of the bottom solver's LDS image (everything
 // from byte zero_bytes on) in global memory, once per grid.
+template <class C>
 __global__ __launch_bounds__(1024) void k_bottom_image(Bottom B, unsigned char* __restrict__ img) {
   const int t = threadIdx.x, NT = blockDim.x;
   unsigned char* base = img - B.zero_bytes;  // LDS byte offsets index img + (off - zero_bytes)
@@ -899,10 +951,18 @@ __global__ __launch_bounds__(1024) void k_bottom_image(Bottom B, unsigned char* 
     float* fx = (float*)(base + G.bfx);
     float* fy = (float*)(base + G.bfy);
     float* fz = (float*)(base + G.bfz);
+    C* wd = (C*)(base + G.bwd);
+    const double ih2x = 1.0 / (g.hx * g.hx), ih2y = 1.0 / (g.hy * g.hy),
+                 ih2z = 1.0 / (g.hz * g.hz);
     for (int c = t; c < G.n; c += NT) {
       int i, j, k;
       lds_cell(nx, ny, c, i, j, k);
-      cls[c] = G.cls[g.idx(i, j, k)];
+      const int P = g.idx(i, j, k);
+      cls[c] = G.cls[P];
+      // the diagonal in the level's arithmetic type, as the sweep kernels form it
+      C d = ((C)G.cf0[P] + (C)G.cf0[P + 1]) * (C)ih2x + ((C)G.cf1[P] + (C)G.cf1[P + g.sx]) * (C)ih2y;
+      if (g.dim == 3) d += ((C)G.cf2[P] + (C)G.cf2[P + g.sxy]) * (C)ih2z;
+      wd[c] = G.cls[P] == MG_INACTIVE ? (C)0 : (C)B.wj / d;
     }
     const int nfx = (nx + 1) * ny * nz;
     for (int e = t; e < nfx; e += NT) {
@@ -933,240 +993,237 @@ __global__ __launch_bounds__(1024) void k_bottom_image(Bottom B, unsigned char* 
     }
 }
 
+template <class C>
 void launch_bottom_image(const Bottom& B, void* img, hipStream_t s) {
-  hipLaunchKernelGGL(k_bottom_image, dim3(1), dim3(1024), 0, s, B, (unsigned char*)img);
+  hipLaunchKernelGGL(k_bottom_image<C>, dim3(1), dim3(1024), 0, s, B, (unsigned char*)img);
 }
+template void launch_bottom_image<double>(const Bottom&, void*, hipStream_t);
+template void launch_bottom_image<float>(const Bottom&, void*, hipStream_t);
 
 template <class SC, class C>
 __global__ __launch_bounds__(1024) void k_bottom(Bottom B, const SC* __restrict__ btop,
                                                  SC* __restrict__ xtop,
                                                  const double* __restrict__ ctl) {
   if (ctl[S_DONE] != 0.0) return;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
   const int t = threadIdx.x, NT = blockDim.x;
-  const C wj = (C)B.wj;
   const int nl = B.nlev;
-  // iterates and right-hand sides start at zero
-  for (int e = t; e < B.zero_bytes / 4; e += NT) ((float*)lds_raw)[e] = 0.f;
-  // constant part (classes, face coefficients, coarsest-cell indices): one
-  // copy of the image built at set-up, 16 bytes per load, four loads in
-  // flight per thread
+  const bool pre = B.nu1 > 0;
+  // level descriptors, read from LDS by every phase (not from the kernel
+  // arguments, whose scalar loads would stall each phase)
+  __shared__ LdsLevel<C> lvs[BOTTOM_MAX_LEVELS];
+  if (t < nl) lvs[t] = lds_level<C>(B.lv[t]);
+  // ---- phase 0: constant image, cleared iterates, the top level's
+  // right-hand side and its first sweep from zero (disjoint LDS ranges)
   {
     const uint4* __restrict__ src = (const uint4*)B.img;
-    uint4* dst = (uint4*)(lds_raw + B.zero_bytes);
+    uint4* dst = (uint4*)(bot_lds + B.zero_bytes);
     const int n16 = (int)((B.lds_bytes - (size_t)B.zero_bytes) / 16);
     for (int e0 = t; e0 < n16; e0 += 4 * NT) {
-      uint4 v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (e0 + q * NT < n16) v[q] = src[e0 + q * NT];
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (e0 + q * NT < n16) dst[e0 + q * NT] = v[q];
+      // indices past the end re-read the last element (kept in registers)
+      const uint4 v0 = src[e0], v1 = src[min(e0 + NT, n16 - 1)];
+      const uint4 v2 = src[min(e0 + 2 * NT, n16 - 1)], v3 = src[min(e0 + 3 * NT, n16 - 1)];
+      dst[e0] = v0;
+      if (e0 + NT < n16) dst[e0 + NT] = v1;
+      if (e0 + 2 * NT < n16) dst[e0 + 2 * NT] = v2;
+      if (e0 + 3 * NT < n16) dst[e0 + 3 * NT] = v3;
+    }
+    const BottomLevel& G = B.lv[0];
+    // top level: x0 [bx0, bx1), x1 [bx1, bb), b [bb, ...): clear x1 and
+    // every later level's iterates and right-hand side
+    for (int e = G.bx1 / 4 + t; e < G.bb / 4; e += NT) ((float*)bot_lds)[e] = 0.f;
+    const int z1 = (int)((G.bb + (size_t)G.n * sizeof(C) + 15) & ~(size_t)15);
+    for (int e = z1 / 4 + t; e < B.zero_bytes / 4; e += NT) ((float*)bot_lds)[e] = 0.f;
+    // class bytes and wj / D of the top level straight from the image in
+    // global memory (the LDS copy is not complete before the barrier)
+    const uint8_t* gcl = (const uint8_t*)B.img + (G.bcl - B.zero_bytes);
+    const C* gwd = (const C*)((const uint8_t*)B.img + (G.bwd - B.zero_bytes));
+    C* x0 = (C*)(bot_lds + G.bx0);
+    C* bt = (C*)(bot_lds + G.bb);
+    const LdsLevel<C> L = lds_level<C>(G);
+    for (int c = t; c < G.n; c += NT) {
+      int i, j, k;
+      lds_ijk(L, c, i, j, k);
+      const C v = St<SC, C>::ld(btop + G.g.idx(i, j, k));
+      const bool act = gcl[c] != MG_INACTIVE;
+      bt[c] = v;
+      x0[c] = (pre && act) ? v * gwd[c] : (C)0;
     }
   }
-  int* cidx = (int*)(lds_raw + B.bcidx);
+  int* cidx = (int*)(bot_lds + B.bcidx);
   const int nco = *B.ncount;
   __syncthreads();
-  {
-    const BottomLevel& G = B.lv[0];
-    const LdsLevel<C> L = lds_level<C>(G, lds_raw);
-    for (int c0 = t; c0 < G.n; c0 += 4 * NT) {
-      C v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int c = c0 + q * NT;
-        if (c < G.n) {
-          int i, j, k;
-          lds_cell(L.nx, L.ny, c, i, j, k);
-          v[q] = St<SC, C>::ld(btop + G.g.idx(i, j, k));
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (c0 + q * NT < G.n) L.b[c0 + q * NT] = v[q];
-    }
-  }
-  __syncthreads();
   // current iterate buffer of every level, one bit per level (a bit mask
-  // rather than an array keeps it in a register)
+  // rather than an array keeps it in a register); x0 holds the first sweep
   unsigned curm = 0;
   auto cur_of = [&](int l) -> int { return (int)((curm >> l) & 1u); };
-  auto set_cur = [&](int l, int v) { curm = (curm & ~(1u << l)) | ((unsigned)v << l); };
-  // one damped-Jacobi sweep on level l from buffer cur (or from zero)
-  auto sweep = [&](int l, bool zero) {
-    const LdsLevel<C> L = lds_level<C>(B.lv[l], lds_raw);
-    const C* xin = cur_of(l) ? L.x1 : L.x0;
-    C* xout = zero ? L.x0 : (cur_of(l) ? L.x0 : L.x1);
-    const int n = B.lv[l].n;
-    for (int c = t; c < n; c += NT) {
-      if (L.cls[c] == MG_INACTIVE) continue;
+  // one damped-Jacobi sweep on level l (to global memory: the last sweep of
+  // the top level)
+  auto sweep = [&](int l, bool to_global) {
+    const LdsLevel<C> L = lvs[l];
+    const C* xin = cur_of(l) ? L.x1() : L.x0();
+    C* xout = cur_of(l) ? L.x0() : L.x1();
+    const uint8_t* cls = L.cls();
+    const C* bb = L.b();
+    const C* wd = L.wd();
+    for (int c = t; c < L.n; c += NT) {
+      if (cls[c] == MG_INACTIVE) continue;
       int i, j, k;
-      lds_cell(L.nx, L.ny, c, i, j, k);
-      C Ax, D;
-      if (zero) {
-        lds_apply<C>(L, L.b, c, i, j, k, (C)0, Ax, D);
-        xout[c] = wj * L.b[c] / D;
-      } else {
-        const C xP = xin[c];
-        lds_apply<C>(L, xin, c, i, j, k, xP, Ax, D);
-        xout[c] = xP + wj * (L.b[c] - Ax) / D;
-      }
+      lds_ijk(L, c, i, j, k);
+      const C xP = xin[c];
+      const C v = xP + (bb[c] - lds_apply<C>(L, xin, c, i, j, k, xP)) * wd[c];
+      if (to_global)
+        St<SC, C>::st(xtop + B.lv[0].g.idx(i, j, k), v);
+      else
+        xout[c] = v;
     }
-    set_cur(l, zero ? 0 : (cur_of(l) ^ 1));
+    curm ^= 1u << l;
     __syncthreads();
   };
+  // ---- down the hierarchy
   for (int l = 0; l < nl - 1; ++l) {
-    set_cur(l, 0);
-    if (B.nu1 > 0) {
-      sweep(l, true);
-      for (int s = 1; s < B.nu1; ++s) sweep(l, false);
-    }  // else x0 is still zero
-    // residual and restriction into level l + 1
-    const LdsLevel<C> F = lds_level<C>(B.lv[l], lds_raw);
-    const LdsLevel<C> Cc = lds_level<C>(B.lv[l + 1], lds_raw);
-    const C* x = cur_of(l) ? F.x1 : F.x0;
+    for (int s = 1; s < B.nu1; ++s) sweep(l, false);
+    // residual and restriction in one phase: 8 consecutive lanes take the 8
+    // children of one coarse cell and sum their residuals by lane exchange;
+    // the coarse level's first sweep from zero follows at once
+    const LdsLevel<C> F = lvs[l];
+    const LdsLevel<C> Cc = lvs[l + 1];
+    const C* x = cur_of(l) ? F.x1() : F.x0();
+    const uint8_t* fcls = F.cls();
+    const uint8_t* ccls = Cc.cls();
     const int kz = Cc.d3 ? 2 : 1;
-    const int ncl = B.lv[l + 1].n;
-    for (int c = t; c < ncl; c += NT) {
-      if (Cc.cls[c] == MG_INACTIVE) continue;
-      int I, J, K;
-      lds_cell(Cc.nx, Cc.ny, c, I, J, K);
-      C sum = 0;
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            if (cc >= kz) continue;
-            const int i = 2 * I + a, j = 2 * J + bb, k = kz * K + cc;
-            const int fc = (k * F.ny + j) * F.nx + i;
-            if (F.cls[fc] == MG_INACTIVE) continue;
-            C Ax, D;
-            lds_apply<C>(F, x, fc, i, j, k, x[fc], Ax, D);
-            sum += F.b[fc] - Ax;
-          }
-      Cc.b[c] = sum * (C)(kz == 2 ? 0.125 : 0.25);
+    const int ncl8 = Cc.n * 8;
+    for (int base = 0; base < ncl8; base += NT) {  // uniform trip count
+      const int q = base + t;
+      const int c = q >> 3, ch = q & 7;
+      C r = 0;
+      const bool cact = q < ncl8 && ccls[c] != MG_INACTIVE;
+      int I = 0, J = 0, K = 0;
+      if (cact) lds_ijk(Cc, c, I, J, K);
+      const int a = ch & 1, bj = (ch >> 1) & 1, cc = ch >> 2;
+      if (cact && cc < kz) {
+        const int i = 2 * I + a, j = 2 * J + bj, k = kz * K + cc;
+        const int fc = (k * F.ny + j) * F.nx + i;
+        if (fcls[fc] != MG_INACTIVE) r = F.b()[fc] - lds_apply<C>(F, x, fc, i, j, k, x[fc]);
+      }
+      r += __shfl_xor(r, 1);
+      r += __shfl_xor(r, 2);
+      r += __shfl_xor(r, 4);
+      if (cact && ch == 0) {
+        const C bc = r * (C)(kz == 2 ? 0.125 : 0.25);
+        Cc.b()[c] = bc;
+        Cc.x0()[c] = pre ? bc * Cc.wd()[c] : (C)0;
+      }
     }
     __syncthreads();
   }
-  // coarsest level: dense inverse
+  // ---- coarsest level: dense inverse
   {
-    const int l = nl - 1;
-    const LdsLevel<C> L = lds_level<C>(B.lv[l], lds_raw);
-    set_cur(l, 0);
+    const LdsLevel<C> L = lvs[nl - 1];
+    curm &= ~(1u << (nl - 1));
     if (nco <= B.max_n) {
       for (int a = t; a < nco; a += NT) {
         C s = 0;
         const double* row = B.ainv + (size_t)a * nco;
-        for (int q = 0; q < nco; ++q) s += (C)row[q] * L.b[cidx[q]];
-        L.x0[cidx[a]] = s;
+        for (int q = 0; q < nco; ++q) s += (C)row[q] * L.b()[cidx[q]];
+        L.x0()[cidx[a]] = s;
       }
     }
     __syncthreads();
   }
-  // up the hierarchy: prolongation and post-smoothing
+  // ---- up the hierarchy: prolongation and post-smoothing
   for (int l = nl - 2; l >= 0; --l) {
-    const LdsLevel<C> F = lds_level<C>(B.lv[l], lds_raw);
-    const LdsLevel<C> Cc = lds_level<C>(B.lv[l + 1], lds_raw);
-    C* x = cur_of(l) ? F.x1 : F.x0;
-    const C* e = cur_of(l + 1) ? Cc.x1 : Cc.x0;
+    const LdsLevel<C> F = lvs[l];
+    const LdsLevel<C> Cc = lvs[l + 1];
+    C* x = cur_of(l) ? F.x1() : F.x0();
+    const C* e = cur_of(l + 1) ? Cc.x1() : Cc.x0();
     const bool d3 = Cc.d3;
     const int cnx = Cc.nx, cny = Cc.ny, cnz = Cc.nz;
+    const uint8_t* ccls = Cc.cls();
+    const float* cfxa = Cc.fx();
+    const float* cfya = Cc.fy();
+    const float* cfza = Cc.fz();
     auto cc_of = [&](int I, int J, int K) { return (K * cny + J) * cnx + I; };
-    auto act = [&](int I, int J, int K) -> bool {
-      if (I < 0 || J < 0 || K < 0 || I >= cnx || J >= cny || K >= cnz) return false;
-      return Cc.cls[cc_of(I, J, K)] != MG_INACTIVE;
-    };
-    const int nf = B.lv[l].n;
+    const int nf = F.n;
+    const uint8_t* fcls = F.cls();
+    const bool direct = l == 0 && B.nu2 == 0;  // no post-sweep: write out here
     for (int c = t; c < nf; c += NT) {
-      if (F.cls[c] == MG_INACTIVE) continue;
+      if (fcls[c] == MG_INACTIVE) continue;
       int i, j, k;
-      lds_cell(F.nx, F.ny, c, i, j, k);
+      lds_ijk(F, c, i, j, k);
+      // the rules of prolong_checked on the compact arrays: indices outside
+      // the box are clamped to the cell itself and their values masked
       const int I = i >> 1, J = j >> 1, K = d3 ? (k >> 1) : 0;
       const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
       const C w3 = (C)0.75, w1 = (C)0.25;
-      C X[2][2] = {{0, 0}, {0, 0}};
-      const int nzc = d3 ? 2 : 1;
+      const bool inx = (unsigned)(I + sx) < (unsigned)cnx;
+      const bool iny = (unsigned)(J + sy) < (unsigned)cny;
+      const bool inz = d3 && (unsigned)(K + sz) < (unsigned)cnz;
+      const int In = inx ? I + sx : I, Jn = iny ? J + sy : J, Kn = inz ? K + sz : K;
+      const int Jq[4] = {J, Jn, J, Jn}, Kq[4] = {K, K, Kn, Kn};
+      C ev[4], en[4], cfx[4];
+      bool ac[4], an[4];
 #pragma unroll
-      for (int cc = 0; cc < 2; ++cc)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int qj = J + b * sy, qk = K + cc * sz;
-          if (cc >= nzc || !act(I, qj, qk)) continue;
-          const C eq = e[cc_of(I, qj, qk)];
-          C en;
-          const int ri = I + sx;
-          if (ri < 0 || ri >= cnx) {
-            // boundary x face of coarse cell (I, qj, qk)
-            const int f = (qk * cny + qj) * (cnx + 1) + I + (sx > 0 ? 1 : 0);
-            en = ((C)1 - (C)Cc.fx[f]) * eq;
-          } else {
-            en = act(ri, qj, qk) ? e[cc_of(ri, qj, qk)] : eq;
-          }
-          X[cc][b] = w3 * eq + w1 * en;
-        }
-      C Y[2] = {0, 0};
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        const int qk = K + cc * sz;
-        if (cc >= nzc || !act(I, J, qk)) continue;
-        C yn;
-        const int qj = J + sy;
-        if (qj < 0 || qj >= cny) {
-          const int f = (qk * (cny + 1) + J + (sy > 0 ? 1 : 0)) * cnx + I;
-          yn = ((C)1 - (C)Cc.fy[f]) * X[cc][0];
-        } else {
-          yn = act(I, qj, qk) ? X[cc][1] : X[cc][0];
-        }
-        Y[cc] = w3 * X[cc][0] + w1 * yn;
+      for (int q = 0; q < 4; ++q) {
+        const int Q = cc_of(I, Jq[q], Kq[q]), Qn = cc_of(In, Jq[q], Kq[q]);
+        ev[q] = e[Q];
+        en[q] = e[Qn];
+        ac[q] = ccls[Q] != MG_INACTIVE;
+        an[q] = ccls[Qn] != MG_INACTIVE;
+        cfx[q] = (C)cfxa[(Kq[q] * cny + Jq[q]) * (cnx + 1) + I + (sx > 0 ? 1 : 0)];
       }
-      C Z = Y[0];
+      const C cfy0 = (C)cfya[(K * (cny + 1) + J + (sy > 0 ? 1 : 0)) * cnx + I];
+      const C cfy1 = (C)cfya[(Kn * (cny + 1) + J + (sy > 0 ? 1 : 0)) * cnx + I];
+      const C cfz = d3 ? (C)cfza[((K + (sz > 0 ? 1 : 0)) * cny + J) * cnx + I] : (C)0;
+      const bool act[4] = {ac[0], iny && ac[1], inz && ac[2], iny && inz && ac[3]};
+      C X[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const C nb = inx ? (an[q] ? en[q] : ev[q]) : ((C)1 - cfx[q]) * ev[q];
+        X[q] = act[q] ? w3 * ev[q] + w1 * nb : (C)0;
+      }
+      const C yn0 = iny ? (act[1] ? X[1] : X[0]) : ((C)1 - cfy0) * X[0];
+      const C Y0 = act[0] ? w3 * X[0] + w1 * yn0 : (C)0;
+      C Z = Y0;
       if (d3) {
-        C zn;
-        const int qk = K + sz;
-        if (qk < 0 || qk >= cnz) {
-          const int f = ((K + (sz > 0 ? 1 : 0)) * cny + J) * cnx + I;
-          zn = ((C)1 - (C)Cc.fz[f]) * Y[0];
-        } else {
-          zn = act(I, J, qk) ? Y[1] : Y[0];
-        }
-        Z = w3 * Y[0] + w1 * zn;
+        const C yn1 = iny ? (act[3] ? X[3] : X[2]) : ((C)1 - cfy1) * X[2];
+        const C Y1 = act[2] ? w3 * X[2] + w1 * yn1 : (C)0;
+        const C zn = inz ? (act[2] ? Y1 : Y0) : ((C)1 - cfz) * Y0;
+        Z = w3 * Y0 + w1 * zn;
       }
-      x[c] += Z;
+      const C v = x[c] + Z;
+      if (direct)
+        St<SC, C>::st(xtop + B.lv[0].g.idx(i, j, k), v);
+      else
+        x[c] = v;
     }
     __syncthreads();
-    for (int s = 0; s < B.nu2; ++s) sweep(l, false);
-  }
-  {
-    const BottomLevel& G = B.lv[0];
-    const LdsLevel<C> L = lds_level<C>(G, lds_raw);
-    const C* x = cur_of(0) ? L.x1 : L.x0;
-    for (int c = t; c < G.n; c += NT) {
-      if (L.cls[c] == MG_INACTIVE) continue;
-      int i, j, k;
-      lds_cell(L.nx, L.ny, c, i, j, k);
-      St<SC, C>::st(xtop + G.g.idx(i, j, k), x[c]);
-    }
+    for (int s = 0; s < B.nu2; ++s) sweep(l, l == 0 && s == B.nu2 - 1);
   }
 }
 
-// LDS bytes one bottom workgroup may use on the current device (dynamic
-// shared memory above 64 KiB is enabled per kernel where the device has it).
+// Dynamic LDS bytes one bottom workgroup may use on the current device: the
+// device's LDS per workgroup less the kernel's static LDS (its level table);
+// dynamic LDS above 64 KiB is enabled per kernel where the device has it.
 template <class SC, class C>
 size_t bottom_lds_limit() {
   int dev = 0, lim = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
-  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-      lim <= 64 * 1024)
-    return 64 * 1024;
-  if (hipFuncSetAttribute((const void*)k_bottom<SC, C>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) {
+  hipFuncAttributes fa;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+      hipFuncGetAttributes(&fa, (const void*)k_bottom<SC, C>) != hipSuccess) {
     (void)hipGetLastError();
-    return 64 * 1024;
+    return 0;
   }
-  return (size_t)lim;
+  const int stat = (int)fa.sharedSizeBytes;
+  const int dyn = lim - stat;
+  if (dyn <= 0) return 0;
+  if (lim > 64 * 1024 &&
+      hipFuncSetAttribute((const void*)k_bottom<SC, C>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
+    (void)hipGetLastError();
+    return (size_t)(64 * 1024 - stat);
+  }
+  return (size_t)dyn;
 }
 template size_t bottom_lds_limit<double, double>();
 template size_t bottom_lds_limit<float, float>();
@@ -1198,7 +1255,7 @@ template void launch_fill_zero<bf16>(const Level&, void*, const double*, hipStre
 
 #define INST_PAIR(S, C, SC)                                                                 \
   template void launch_resid_restrict<S, C, SC>(const Level&, const Level&, const double*,   \
-                                                hipStream_t);                                 \
+                                                hipStream_t, void*, double);                  \
   template void launch_prolong<S, C, SC>(const Level&, const Level&, const double*,          \
                                          hipStream_t);
 INST_PAIR(double, double, double)

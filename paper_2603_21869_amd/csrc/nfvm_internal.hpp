@@ -198,7 +198,8 @@ template <class S, class C>
 void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                    const double* ctl, hipStream_t s);
 template <class S, class C, class SC>
-void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s);
+void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s,
+                           void* zc = nullptr, double wj = 0.0);
 template <class S, class C, class SC>
 void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s);
 template <class SC, class C>
@@ -221,8 +222,9 @@ struct BottomLevel {
   const float* cf2;
   int n;  // cells (nx * ny * nz)
   // LDS byte offsets: iterates, right-hand side, x / y / z face
-  // coefficients, class bytes
-  int bx0, bx1, bb, bfx, bfy, bfz, bcl;
+  // coefficients, damping over diagonal (wj / D), class bytes
+  int bx0, bx1, bb, bfx, bfy, bfz, bwd, bcl;
+  float inx, inxy;  // 1 / nx and 1 / (nx ny) for division-free cell indices
 };
 struct Bottom {
   int nlev;  // levels top .. L-1
@@ -238,6 +240,7 @@ struct Bottom {
   size_t lds_bytes;
   const void* img;  // LDS bytes [zero_bytes, lds_bytes) as built by launch_bottom_image
 };
+template <class C>
 void launch_bottom_image(const Bottom& B, void* img, hipStream_t s);
 template <class SC, class C>
 size_t bottom_lds_limit();
