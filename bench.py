@@ -16,6 +16,7 @@ Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -33,6 +34,44 @@ WORKLOADS = {
     "room": "3D ventilated room 512x256x128 with seeded blocks, 8 levels",
     "bigroom": "3D ventilated room 1024x512x256 with seeded blocks, 9 levels",
 }
+
+
+# kernel sources whose hash identifies the build the committed counter
+# summaries were taken with
+KERNEL_SOURCES = ("k_mg.hip", "k_physics.hip", "nfvm_device.hpp", "nfvm_internal.hpp")
+PROFILE_FILES = {
+    ("channel3d", "mixed"): "kernels_channel3d_256x64x64_mixed.md",
+    ("room", "mixed"): "kernels_room_512x256x128_mixed.md",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2603_21869_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, precision: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload; None when there is none or when the kernel
+    sources changed since the counters were taken."""
+    name = PROFILE_FILES.get((workload, precision))
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None, None
+    traffic, sha = {}, None
+    with open(path) as fh:
+        for line in fh:
+            parts = line.split()
+            if len(parts) == 3 and parts[0] == "traffic":
+                traffic[parts[1]] = float(parts[2])
+            elif len(parts) == 2 and parts[0] == "source_sha256":
+                sha = parts[1]
+    if sha != kernel_source_hash():
+        return None, name + " (stale: kernel sources changed)"
+    return traffic.get(kernel), name
 
 
 def make_case(name: str, precision: int, tol: float):
@@ -68,6 +107,24 @@ def run_gpu(case, steps: int, warmup: int, profile: bool, stream: int, graphs: b
             prof[name] = nfvm.nfvm_profile_read(g.h, kid)
     g.close()
     return t1 - t0, stats, prof, s
+
+
+def run_pcie(case, steps: int, stream: int):
+    """Throughput with the fields handed over in host memory: upload, the
+    steps, download (the grid and its tile choices exist already)."""
+    import torch
+    from paper_2603_21869_amd import nfvm
+    g = nfvm.Grid(case, stream=stream)
+    g.step(1, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.set_fields(case.fields)
+    g.step(steps, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+    g.fields()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    g.close()
+    return case.ncells * steps / sec / 1e6
 
 
 def run_serve(n_req: int, slots: int, seed: int = 0):
@@ -199,6 +256,8 @@ def main():
                                    ms_per_step=s2 / k2 * 1e3,
                                    mean_cycles=sum(x["cycles"] for x in st2) / len(st2))
 
+    pcie = run_pcie(case, args.steps, stream)
+    traffic, traffic_src = measured_traffic(args.workload, args.precision, dom)
     out = {
         "metric": "Mcell-steps/s at 1e-6 residual",
         "value": round(value, 3),
@@ -219,12 +278,14 @@ def main():
         "solver": {"mean_cycles": sum(cycles) / len(cycles), "max_rel_residual": max(rel)},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(avg * 1e6, 2),
+                     "traffic": traffic, "traffic_source": traffic_src,
+                     "avg_launch_us": round(avg * 1e6, 2),
                      "algorithmic_bytes_per_launch": d["bytes_per_launch"]},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernel_table.items()},
         "variants": variants,
         "stream_launch_ms_per_step": round(psec / args.steps * 1e3, 4),
+        "pcie_inclusive_mcell_steps_s": round(pcie, 2),
         "tuning": [list(t) for t in nfvm.nfvm_tuning_table()],
         "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
                          "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",

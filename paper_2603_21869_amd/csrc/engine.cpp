@@ -256,17 +256,19 @@ class GridT : public GridBase {
       const double N = (double)ncells, sv = sizeof(V), sf = sizeof(F), sp = sizeof(P),
                    so = sizeof(O), s0 = sizeof(S0), scs = sizeof(SC);
       const double nc = L > 1 ? (double)level_geom(d, 1).cells() : 0.0;
-      prof_bytes[NFVM_K_SMOOTH0] = N * (3 * s0 + 1);
-      prof_bytes[NFVM_K_SMOOTH0_ZERO] = N * (2 * s0 + 1);
-      prof_bytes[NFVM_K_RESTRICT0] = N * (2 * s0 + 1) + nc * (scs + 1);
+      // level 0 reads a 2-byte face code per cell; the restriction also
+      // writes the coarse level's first sweep, the CG update the level-0 one
+      prof_bytes[NFVM_K_SMOOTH0] = N * (3 * s0 + 2);
+      prof_bytes[NFVM_K_SMOOTH0_ZERO] = N * (2 * s0 + 2);
+      prof_bytes[NFVM_K_RESTRICT0] = N * (2 * s0 + 2) + nc * (2 * scs + 1);
       prof_bytes[NFVM_K_PROLONG0] = N * (2 * s0 + 1) + nc * (scs + 1);
       prof_bytes[NFVM_K_EXPLICIT] = N * (6 * sv + 6 * sf + sp + 1);
       prof_bytes[NFVM_K_DESTROY] = N * (3 * sv + 4 * sf + 1);
       prof_bytes[NFVM_K_RHS] = N * (3 * sv + so + 1);
       prof_bytes[NFVM_K_PROJECT] = N * (6 * sv + 2 * sp + so + 1);
-      prof_bytes[NFVM_K_FCG_DOTS] = N * (s0 + 2 * so + 1);
-      prof_bytes[NFVM_K_FCG_DIR] = N * (s0 + 3 * so + 1);
-      prof_bytes[NFVM_K_FCG_UPDATE] = N * (s0 + 6 * so + 1);
+      prof_bytes[NFVM_K_FCG_DOTS] = N * (s0 + 2 * so + 2);
+      prof_bytes[NFVM_K_FCG_DIR] = N * (s0 + 3 * so + 2);
+      prof_bytes[NFVM_K_FCG_UPDATE] = N * (2 * s0 + 6 * so + 2);
     }
     NFVM_CK(hipEventCreate(&ev0));
     NFVM_CK(hipEventCreate(&ev1));
