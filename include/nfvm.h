@@ -212,10 +212,9 @@ enum {
   NFVM_K_DESTROY = 5,      /* semi-implicit destruction half step */
   NFVM_K_RHS = 6,          /* Poisson right-hand side */
   NFVM_K_PROJECT = 7,      /* projection */
-  NFVM_K_FCG_DOTS = 8,     /* (z, r), (z, q) */
-  NFVM_K_FCG_DIR = 9,      /* search direction and A p */
-  NFVM_K_FCG_UPDATE = 10,  /* x, r update and ||r|| */
-  NFVM_K_COUNT = 11
+  NFVM_K_FCG_APPLY = 8,    /* w = A z and (z, r), (z, q), (z, w) */
+  NFVM_K_FCG_UPDATE = 9,   /* p, q, x, r update and ||r|| */
+  NFVM_K_COUNT = 10
 };
 nfvm_status nfvm_profile(nfvm_grid_t grid, uint32_t kernel_mask);
 nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launches,

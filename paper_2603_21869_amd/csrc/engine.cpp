@@ -141,18 +141,23 @@ hipEvent_t GridBase::next_event() {
   return ev_pool[ev_used++];
 }
 
+thread_local LaunchEvents t_launch_ev;
+
+// The main kernel launched between prof_begin and prof_end records the pair
+// of events at its own start and end.
 void GridBase::prof_begin(int kid) {
   if (!(prof_mask & (1u << kid))) return;
-  ProfRec r{kid, next_event(), nullptr};
-  NFVM_CK(hipEventRecord(r.a, stream));
+  ProfRec r{kid, next_event(), next_event()};
+  t_launch_ev = LaunchEvents{r.a, r.b};
   prof_pending.push_back(r);
 }
 
 void GridBase::prof_end(int kid) {
   if (!(prof_mask & (1u << kid))) return;
-  hipEvent_t b = next_event();
-  NFVM_CK(hipEventRecord(b, stream));
-  prof_pending.back().b = b;
+  if (t_launch_ev.start) {  // nothing was launched: drop the record
+    t_launch_ev = LaunchEvents{};
+    prof_pending.pop_back();
+  }
 }
 
 void GridBase::prof_collect() {
@@ -198,7 +203,7 @@ class GridT : public GridBase {
   int fcur[6] = {0, 0, 0, 0, 0, 0};
   P* p = nullptr;
   std::vector<Level> lv;
-  O *bvec = nullptr, *phi = nullptr, *r = nullptr, *pv[2] = {nullptr, nullptr}, *q = nullptr,
+  O *bvec = nullptr, *phi = nullptr, *r = nullptr, *pv = nullptr, *q = nullptr, *wv = nullptr,
     *x0 = nullptr;
   double* stage = nullptr;
   RedBuf red{};
@@ -266,9 +271,8 @@ class GridT : public GridBase {
       prof_bytes[NFVM_K_DESTROY] = N * (3 * sv + 4 * sf + 1);
       prof_bytes[NFVM_K_RHS] = N * (3 * sv + so + 1);
       prof_bytes[NFVM_K_PROJECT] = N * (6 * sv + 2 * sp + so + 1);
-      prof_bytes[NFVM_K_FCG_DOTS] = N * (s0 + 2 * so + 2);
-      prof_bytes[NFVM_K_FCG_DIR] = N * (s0 + 3 * so + 2);
-      prof_bytes[NFVM_K_FCG_UPDATE] = N * (2 * s0 + 6 * so + 2);
+      prof_bytes[NFVM_K_FCG_APPLY] = N * (s0 + 3 * so + 2);
+      prof_bytes[NFVM_K_FCG_UPDATE] = N * (3 * s0 + 9 * so + 2);
     }
     NFVM_CK(hipEventCreate(&ev0));
     NFVM_CK(hipEventCreate(&ev1));
@@ -365,8 +369,8 @@ class GridT : public GridBase {
     bvec = alloc<O>(g.total);
     phi = alloc<O>(g.total);
     r = alloc<O>(g.total);
-    pv[0] = alloc<O>(g.total);
-    pv[1] = alloc<O>(g.total);
+    pv = alloc<O>(g.total);
+    wv = alloc<O>(g.total);
     q = alloc<O>(g.total);
     x0 = alloc<O>(g.total);
     red.max_blocks = max_blocks_of(g);
@@ -465,17 +469,13 @@ class GridT : public GridBase {
           launch_fcg_start<O, S0>(v, bvec, x0, r, phi, red, false, 1.0, 1, -1, stream, false,
                                   zero0(), wj);
         });
-        v.tt[TK_DOTS] = tune_one(TK_DOTS, v.g, [&](int tt) {
-          v.tt[TK_DOTS] = tt;
-          launch_fcg_dots<O, S0>(v, r, q, red, stream, false);
-        });
-        v.tt[TK_DIR] = tune_one(TK_DIR, v.g, [&](int tt) {
-          v.tt[TK_DIR] = tt;
-          launch_fcg_dir<O, S0>(v, pv[0], pv[1], q, red, stream, false);
+        v.tt[TK_APPLY] = tune_one(TK_APPLY, v.g, [&](int tt) {
+          v.tt[TK_APPLY] = tt;
+          launch_fcg_apply<O, S0>(v, r, q, wv, red, stream, false);
         });
         v.tt[TK_UPDATE] = tune_one(TK_UPDATE, v.g, [&](int tt) {
           v.tt[TK_UPDATE] = tt;
-          launch_fcg_update<O, S0>(v, phi, r, pv[0], pv[1], q, red, stream, false, zero0(), wj);
+          launch_fcg_update<O, S0>(v, phi, r, pv, q, wv, red, stream, false, zero0(), wj);
         });
       } else {
         v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + 1000, v.g, [&](int tt) {
@@ -500,7 +500,7 @@ class GridT : public GridBase {
     NFVM_CK(hipGetLastError());
     // leave every buffer the tuning touched as a fresh grid has it
     const size_t ob = (size_t)g.total * sizeof(O);
-    for (O* bufp : {bvec, phi, r, pv[0], pv[1], q, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
+    for (O* bufp : {bvec, phi, r, pv, q, wv, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
     for (int l = 0; l < L; ++l) {
       const size_t es = (size_t)lv[l].g.total * (l == 0 ? sizeof(S0) : sizeof(SC));
       for (int c = 0; c < 2; ++c) NFVM_CK(hipMemsetAsync(lv[l].x[c], 0, es, stream));
@@ -719,14 +719,11 @@ class GridT : public GridBase {
   // the device-side stopping rule has fired).
   void fcg_iteration() {
     vcycle(0);
-    prof_begin(NFVM_K_FCG_DOTS);
-    launch_fcg_dots<O, S0>(lv[0], r, q, red, stream);
-    prof_end(NFVM_K_FCG_DOTS);
-    prof_begin(NFVM_K_FCG_DIR);
-    launch_fcg_dir<O, S0>(lv[0], pv[0], pv[1], q, red, stream);
-    prof_end(NFVM_K_FCG_DIR);
+    prof_begin(NFVM_K_FCG_APPLY);
+    launch_fcg_apply<O, S0>(lv[0], r, q, wv, red, stream);
+    prof_end(NFVM_K_FCG_APPLY);
     prof_begin(NFVM_K_FCG_UPDATE);
-    launch_fcg_update<O, S0>(lv[0], phi, r, pv[0], pv[1], q, red, stream, true, zero0(), wj);
+    launch_fcg_update<O, S0>(lv[0], phi, r, pv, q, wv, red, stream, true, zero0(), wj);
     prof_end(NFVM_K_FCG_UPDATE);
   }
 

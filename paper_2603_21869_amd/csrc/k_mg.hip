@@ -280,18 +280,18 @@ void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool 
   const Tiles T = lvl_tiles(l, from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH);
   if (l.code) {
     if (from_zero)
-      hipLaunchKernelGGL((k_smooth_code<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s,
+      NFVM_LAUNCH((k_smooth_code<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s,
                          view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
     else
-      hipLaunchKernelGGL((k_smooth_code<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s,
+      NFVM_LAUNCH((k_smooth_code<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s,
                          view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
     return;
   }
   if (from_zero)
-    hipLaunchKernelGGL((k_smooth<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
+    NFVM_LAUNCH((k_smooth<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
                        (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
   else
-    hipLaunchKernelGGL((k_smooth<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
+    NFVM_LAUNCH((k_smooth<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
                        (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
 }
 
@@ -368,7 +368,7 @@ template <class S, class C, class SC>
 void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s,
                            void* zc, double wj) {
   const Tiles T = make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_RESTRICT]);
-  hipLaunchKernelGGL((k_resid_restrict<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f),
+  NFVM_LAUNCH((k_resid_restrict<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f),
                      T, (const S*)f.x[f.cur], (const S*)f.b, view(c), (SC*)c.b, (SC*)zc, (C)wj,
                      ctl);
 }
@@ -490,7 +490,7 @@ template <class S, class C, class SC>
 void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
   // tiles over fine columns and coarse planes
   const Tiles T = make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_PROLONG]);
-  hipLaunchKernelGGL((k_prolong<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f), T,
+  NFVM_LAUNCH((k_prolong<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f), T,
                      (S*)f.x[f.cur], view(c), (const SC*)c.x[c.cur], ctl);
 }
 
@@ -645,127 +645,89 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                        (double)max_cycles, (double)forced);
 }
 
-// (z, r) and (z, q_prev)
+// w = A z and the dot products (z, r), (z, q_prev), (z, w).  With
+// beta = -(z, q_prev) / (p_prev, q_prev), the new direction p = z + beta p_prev
+// has A p = w + beta q_prev and (p, A p) = (z, w) + 2 beta (z, q_prev) +
+// beta^2 (p_prev, q_prev), so one stencil pass per iteration serves both the
+// direction and the step length.
 template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_dots(LevelView L, Tiles T, const S* __restrict__ z,
-                                                  const O* __restrict__ r, const O* __restrict__ q,
-                                                  RedBuf red) {
+__global__ __launch_bounds__(MBS) void k_fcg_apply(LevelView L, Tiles T, const S* __restrict__ z,
+                                                   const O* __restrict__ r,
+                                                   const O* __restrict__ q, O* __restrict__ w,
+                                                   RedBuf red) {
   if (red.out[S_DONE] != 0.0) return;
   int tx, ty, tz;
-  double zr = 0.0, zq = 0.0;
-  if (tile_of(T, tx, ty, tz)) {
-    const Geom& g = L.g;
-    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
-    if (i < g.nx && j < g.ny) {
-      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
-      for (int k = k0; k < k1; ++k) {
-        const int P = g.idx(i, j, k);
-        if (L.code[P] == FACE_CODE_INACTIVE) continue;
-        const double zP = (double)St<S, O>::ld(z + P);
-        zr += zP * (double)r[P];
-        zq += zP * (double)q[P];
-      }
-    }
-  }
-  double vv[2] = {zr, zq};
-  block_partial<2, R_SUM, MBS>(vv, red);
-}
-
-// sums of the last kernel's partials into slots (s0, s1); slot_par adds the
-// iteration parity to both slots
-template <int NV>
-__global__ __launch_bounds__(FIN) void k_fin_sum(RedBuf red, int nb, int s0, int s1,
-                                                 int slot_par) {
-  if (red.out[S_DONE] != 0.0) return;
-  double acc[NV];
-  fin_sum<NV>(red, nb, acc);
-  if (threadIdx.x == 0) {
-    const int par = slot_par ? ((int)red.out[S_ITER] & 1) : 0;
-    red.out[s0 + par] = acc[0];
-    if (NV > 1) red.out[s1 + par] = acc[NV - 1];
-  }
-}
-
-template <class O, class S>
-void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
-                     bool fin) {
-  const Tiles T = lvl_tiles(l0, TK_DOTS);
-  hipLaunchKernelGGL((k_fcg_dots<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T,
-                     (const S*)l0.x[l0.cur], r, q, red);
-  if (fin) hipLaunchKernelGGL(k_fin_sum<2>, dim3(1), dim3(FIN), 0, s, red, T.grid, S_ZR, S_ZQ, 0);
-}
-
-// p_new = z + beta p_old with beta = -alpha_prev (z, q_prev) / (z_prev, r_prev)
-// = -(z, q_prev) / (p_prev, q_prev) (0 on the first iteration); q = A p_new,
-// computed from z and p_old at the neighbours; (p_new, q) into S_PQ0 + parity.
-// p_new is buffer (iteration parity), p_old the other one.
-template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_dir(LevelView L, Tiles T, const S* __restrict__ z,
-                                                 O* p0, O* p1, O* __restrict__ q, RedBuf red) {
-  if (red.out[S_DONE] != 0.0) return;
-  const int it = (int)red.out[S_ITER];
-  const int par = it & 1;
-  const bool first = it == 0;
-  const O* __restrict__ pold = par ? p0 : p1;
-  O* __restrict__ pnew = par ? p1 : p0;
-  const O beta = first ? (O)0 : (O)(-red.out[S_ZQ] / red.out[par ? S_PQ0 : S_PQ1]);
-  int tx, ty, tz;
-  double pq = 0.0;
+  double zr = 0.0, zq = 0.0, zw = 0.0;
   if (tile_of(T, tx, ty, tz)) {
     const Geom& g = L.g;
     const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
     if (i < g.nx && j < g.ny) {
       const bool d3 = g.dim == 3;
-      auto pn = [&](int N) -> O {
-        return St<S, O>::ld(z + N) + (first ? (O)0 : beta * pold[N]);
-      };
-      const O ih2x = (O)(1.0 / (g.hx * g.hx)), ih2y = (O)(1.0 / (g.hy * g.hy)),
-              ih2z = (O)(1.0 / (g.hz * g.hz));
       const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
       int P = g.idx(i, j, k0);
-      O pm = d3 ? pn(P - g.sxy) : (O)0, pc = pn(P);
+      O zm = d3 ? St<S, O>::ld(z + P - g.sxy) : (O)0, zc = St<S, O>::ld(z + P);
       for (int k = k0; k < k1; ++k, P += g.sxy) {
-        const O pp = d3 ? pn(P + g.sxy) : (O)0;
+        const O zp = d3 ? St<S, O>::ld(z + P + g.sxy) : (O)0;
         const uint32_t cd = L.code[P];
         if (cd != FACE_CODE_INACTIVE) {
-          const O cxl = face_c<O>(cd, 0), cxh = face_c<O>(cd, 1), cyl = face_c<O>(cd, 2),
-                  cyh = face_c<O>(cd, 3), czl = face_c<O>(cd, 4), czh = face_c<O>(cd, 5);
-          O Ap = (cxl * (pc - pn(P - 1)) + cxh * (pc - pn(P + 1))) * ih2x +
-                 (cyl * (pc - pn(P - g.sx)) + cyh * (pc - pn(P + g.sx))) * ih2y;
-          if (d3) Ap += (czl * (pc - pm) + czh * (pc - pp)) * ih2z;
-          pnew[P] = pc;
-          q[P] = Ap;
-          pq += (double)pc * (double)Ap;
+          O Az, D;
+          apply_code<S, O>(g, cd, z, P, zc, zm, zp, Az, D);
+          w[P] = Az;
+          zr += (double)zc * (double)r[P];
+          zq += (double)zc * (double)q[P];
+          zw += (double)zc * (double)Az;
         }
-        pm = pc;
-        pc = pp;
+        zm = zc;
+        zc = zp;
       }
     }
   }
-  double vv[1] = {pq};
-  block_partial<1, R_SUM, MBS>(vv, red);
+  double vv[3] = {zr, zq, zw};
+  block_partial<3, R_SUM, MBS>(vv, red);
+}
+
+constexpr int FIN_NV3 = 3;
+
+// (z, r), (z, q_prev), (z, w); beta, (p, q) and alpha of this iteration.
+__global__ __launch_bounds__(FIN) void k_fin_apply(RedBuf red, int nb) {
+  if (red.out[S_DONE] != 0.0) return;
+  double acc[FIN_NV3];
+  fin_sum<FIN_NV3>(red, nb, acc);
+  if (threadIdx.x == 0) {
+    const double zr = acc[0], zq = acc[1], zw = acc[2];
+    const bool first = red.out[S_ITER] == 0.0;
+    const double pq_prev = red.out[S_PQ];
+    const double beta = first ? 0.0 : -zq / pq_prev;
+    const double pq = first ? zw : zw + 2.0 * beta * zq + beta * beta * pq_prev;
+    red.out[S_ZR] = zr;
+    red.out[S_ZQ] = zq;
+    red.out[S_ZW] = zw;
+    red.out[S_BETA] = beta;
+    red.out[S_PQ] = pq;
+    red.out[S_ALPHA] = zr / pq;
+  }
 }
 
 template <class O, class S>
-void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipStream_t s,
-                    bool fin) {
-  const Tiles T = lvl_tiles(l0, TK_DIR);
-  hipLaunchKernelGGL((k_fcg_dir<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T,
-                     (const S*)l0.x[l0.cur], p0, p1, q, red);
-  if (fin)
-    hipLaunchKernelGGL(k_fin_sum<1>, dim3(1), dim3(FIN), 0, s, red, T.grid, S_PQ0, S_PQ0, 1);
+void launch_fcg_apply(const Level& l0, const O* r, const O* q, O* w, const RedBuf& red,
+                      hipStream_t s, bool fin) {
+  const Tiles T = lvl_tiles(l0, TK_APPLY);
+  NFVM_LAUNCH((k_fcg_apply<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T,
+              (const S*)l0.x[l0.cur], r, q, w, red);
+  if (fin) hipLaunchKernelGGL(k_fin_apply, dim3(1), dim3(FIN), 0, s, red, T.grid);
 }
 
-// alpha = (z, r)/(p, q); x += alpha p; r -= alpha q; ||r||^2; next V-cycle rhs.
+// p = z + beta p, q = w + beta q, x += alpha p, r -= alpha q, ||r||^2, the
+// next V-cycle's right-hand side (and first level-0 sweep).
 template <class O, class S>
 __global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, Tiles T, O* __restrict__ x,
-                                                    O* __restrict__ r, const O* p0, const O* p1,
-                                                    const O* __restrict__ q, S* __restrict__ b0,
+                                                    O* __restrict__ r, O* __restrict__ p,
+                                                    O* __restrict__ q, const O* __restrict__ w,
+                                                    const S* __restrict__ z, S* __restrict__ b0,
                                                     S* __restrict__ z0, S wj, RedBuf red) {
   if (red.out[S_DONE] != 0.0) return;
-  const int par = (int)red.out[S_ITER] & 1;
-  const O* __restrict__ pv = par ? p1 : p0;
-  const O a = (O)(red.out[S_ZR] / red.out[par ? S_PQ1 : S_PQ0]);
+  const bool first = red.out[S_ITER] == 0.0;
+  const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA];
   int tx, ty, tz;
   double rr = 0.0;
   if (tile_of(T, tx, ty, tz)) {
@@ -777,8 +739,13 @@ __global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, Tiles T, O* __r
         const int P = g.idx(i, j, k);
         const uint32_t cd = L.code[P];
         if (cd == FACE_CODE_INACTIVE) continue;
-        x[P] += a * pv[P];
-        const O rP = r[P] - a * q[P];
+        const O zP = St<S, O>::ld(z + P);
+        const O pP = first ? zP : zP + be * p[P];
+        const O qP = first ? w[P] : w[P] + be * q[P];
+        p[P] = pP;
+        q[P] = qP;
+        x[P] += a * pP;
+        const O rP = r[P] - a * qP;
         r[P] = rP;
         zero_sweep<O, S>(L, P, cd, rP, b0, z0, wj);
         rr += (double)rP * (double)rP;
@@ -802,11 +769,11 @@ __global__ __launch_bounds__(FIN) void k_fin_update(RedBuf red, int nb) {
 }
 
 template <class O, class S>
-void launch_fcg_update(const Level& l0, O* x, O* r, O* p0, O* p1, const O* q, const RedBuf& red,
+void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const O* w, const RedBuf& red,
                        hipStream_t s, bool fin, void* z0, double wj) {
   const Tiles T = lvl_tiles(l0, TK_UPDATE);
-  hipLaunchKernelGGL((k_fcg_update<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, x, r,
-                     p0, p1, q, (S*)l0.b, (S*)z0, (S)wj, red);
+  NFVM_LAUNCH((k_fcg_update<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, x, r, p, q,
+              w, (const S*)l0.x[l0.cur], (S*)l0.b, (S*)z0, (S)wj, red);
   if (fin) hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, red, T.grid);
 }
 
@@ -1273,10 +1240,8 @@ template void launch_coarse_solve<bf16, float>(const Level&, const int*, const i
 #define INST_FCG(O, S)                                                                          \
   template void launch_fcg_start<O, S>(const Level&, const O*, const O*, O*, O*, const RedBuf&, \
                                        bool, double, int, int, hipStream_t, bool, void*, double); \
-  template void launch_fcg_dots<O, S>(const Level&, const O*, const O*, const RedBuf&,          \
-                                      hipStream_t, bool);                                       \
-  template void launch_fcg_dir<O, S>(const Level&, O*, O*, O*, const RedBuf&, hipStream_t,      \
-                                     bool);                                                     \
+  template void launch_fcg_apply<O, S>(const Level&, const O*, const O*, O*, const RedBuf&,     \
+                                       hipStream_t, bool);                                      \
   template void launch_fcg_update<O, S>(const Level&, O*, O*, O*, O*, const O*, const RedBuf&,  \
                                         hipStream_t, bool, void*, double);
 INST_FCG(double, double)

@@ -155,11 +155,11 @@ void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const De
                     F* k_out, F* om_out, const RedBuf* red, int tt, hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
   if (red) {
-    hipLaunchKernelGGL((k_destroy<V, F, true>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt,
+    NFVM_LAUNCH((k_destroy<V, F, true>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt,
                        u, v, w, k, om, (V)tau, k_out, om_out, *red, T);
     launch_finalize(2, R_MIN, *red, T.grid, S_MINK, S_MINW, s);
   } else
-    hipLaunchKernelGGL((k_destroy<V, F, false>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type,
+    NFVM_LAUNCH((k_destroy<V, F, false>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type,
                        pt, u, v, w, k, om, (V)tau, k_out, om_out, RedBuf{}, T);
 }
 #define INST_DESTROY(V, F)                                                                      \
@@ -301,7 +301,7 @@ template <class V, class F, class P>
 void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                      FieldSet<V, F> in, const P* p, FieldSet<V, F> out, int tt, hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
-  hipLaunchKernelGGL((k_explicit<V, F, P>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, in,
+  NFVM_LAUNCH((k_explicit<V, F, P>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, in,
                      p, out, T);
 }
 #define INST_EXPLICIT(V, F, P)                                                                 \
@@ -359,7 +359,7 @@ void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevP
                   const F* u, const F* v, const F* w, O* b, const RedBuf& red, int tt,
                   hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
-  hipLaunchKernelGGL((k_rhs_b<F, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, u, v, w,
+  NFVM_LAUNCH((k_rhs_b<F, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, u, v, w,
                      b, red, T);
   launch_finalize(1, R_SUM, red, T.grid, S_BB, S_BB, s);
 }
@@ -448,7 +448,7 @@ void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const De
                     const O* phi, const F* u, const F* v, const F* w, F* uo, F* vo, F* wo, P* p,
                     const RedBuf& red, int tt, hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
-  hipLaunchKernelGGL((k_project<F, P, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
+  NFVM_LAUNCH((k_project<F, P, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
                      u, v, w, uo, vo, wo, p, red, T);
   launch_finalize(1, R_MAX, red, T.grid, S_DIV, S_DIV, s);
 }

@@ -2,10 +2,33 @@
 // table, physics parameters and the launchers every kernel file provides.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace nfvm {
+
+// Kernel-timing events for the next main-kernel launch of the calling thread
+// (set by the grid's profiler; null when not timing).  The launch records
+// them itself at the kernel's start and end (hipExtLaunchKernelGGL), so
+// the interval is the kernel's own run time, and clears them, so the
+// finalising kernels that follow are not timed.
+struct LaunchEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents t_launch_ev;
+
+#define NFVM_LAUNCH(K, G, B, SH, S, ...)                                                     \
+  do {                                                                                       \
+    if (::nfvm::t_launch_ev.start) {                                                         \
+      hipExtLaunchKernelGGL(K, G, B, SH, S, ::nfvm::t_launch_ev.start,                       \
+                            ::nfvm::t_launch_ev.stop, 0, __VA_ARGS__);                       \
+      ::nfvm::t_launch_ev = ::nfvm::LaunchEvents{};                                          \
+    } else {                                                                                 \
+      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                       \
+    }                                                                                        \
+  } while (0)
+
 
 // Cell type byte of the fine grid (interior and ghost cells):
 //   low 7 bits: patch id (0 fluid, 1 solid block, 2..7 default wall of face
@@ -88,8 +111,7 @@ enum {
   TK_RESTRICT,  // on the fine level of the pair
   TK_PROLONG,   // on the fine level of the pair
   TK_START,
-  TK_DOTS,
-  TK_DIR,
+  TK_APPLY,
   TK_UPDATE,
   TK_LEVEL_COUNT
 };
@@ -131,8 +153,9 @@ enum {
   S_RR = 1,        // ||r||^2
   S_ZR = 2,        // (z, r)
   S_ZQ = 3,        // (z, q_prev)
-  S_PQ0 = 4,       // (p, q) of even iterations
-  S_PQ1 = 5,       // (p, q) of odd iterations
+  S_PQ = 4,        // (p, q) of the current iteration (the previous one while it is formed)
+  S_ZW = 5,        // (z, A z)
+  S_ALPHA = 6,     // step length of the current iteration
   S_DIV = 7,       // max face divergence
   S_MINK = 8,
   S_MINW = 9,
@@ -141,6 +164,7 @@ enum {
   S_TOL2 = 12,     // tol^2
   S_MAXIT = 13,
   S_FORCED = 14,   // < 0: stop on tol
+  S_BETA = 15,     // direction coefficient of the current iteration
   S_COUNT = 16
 };
 
@@ -258,13 +282,10 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                       bool have_x0, double tol, int max_cycles, int forced, hipStream_t s,
                       bool fin = true, void* z0 = nullptr, double wj = 0.0);
 template <class O, class S>
-void launch_fcg_dots(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
-                     bool fin = true);
+void launch_fcg_apply(const Level& l0, const O* r, const O* q, O* w, const RedBuf& red,
+                      hipStream_t s, bool fin = true);
 template <class O, class S>
-void launch_fcg_dir(const Level& l0, O* p0, O* p1, O* q, const RedBuf& red, hipStream_t s,
-                    bool fin = true);
-template <class O, class S>
-void launch_fcg_update(const Level& l0, O* x, O* r, O* p0, O* p1, const O* q, const RedBuf& red,
+void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const O* w, const RedBuf& red,
                        hipStream_t s, bool fin = true, void* z0 = nullptr, double wj = 0.0);
 
 }  // namespace nfvm

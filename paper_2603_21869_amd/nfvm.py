@@ -30,7 +30,7 @@ EXPORTS = (
 )
 
 KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "explicit", "destroy", "rhs",
-           "project", "fcg_dots", "fcg_dir", "fcg_update")
+           "project", "fcg_apply", "fcg_update")
 
 
 class nfvm_patch(C.Structure):
