@@ -93,7 +93,7 @@ size_t footprint_bytes(const nfvm_grid_desc& d) {
   const Geom g = level_geom(d, 0);
   const size_t T = (size_t)g.total, N = (size_t)g.cells();
   size_t b = 0;
-  b += 6 * T * V + 6 * T * F + T * P + T;           // fields (ping-pong), pressure, cell types
+  b += 6 * T * V + 7 * T * F + T * P + T;           // fields (ping-pong), nu_t, pressure, types
   b += 6 * T * O;                                   // b, phi, r, p (x2), q
   b += T * O;                                       // initial guess of the solve call
   b += 8 * N + (d.solid_mask ? N : 0);              // dense staging, mask
@@ -202,6 +202,7 @@ class GridT : public GridBase {
   F* sca[3][2] = {};   // T k omega
   int fcur[6] = {0, 0, 0, 0, 0, 0};
   P* p = nullptr;
+  F* nut = nullptr;  // eddy viscosity of the stored k, omega (written by the first half step)
   std::vector<Level> lv;
   O *bvec = nullptr, *phi = nullptr, *r = nullptr, *pv = nullptr, *q = nullptr, *wv = nullptr,
     *x0 = nullptr;
@@ -267,8 +268,8 @@ class GridT : public GridBase {
       prof_bytes[NFVM_K_SMOOTH0_ZERO] = N * (2 * s0 + 2);
       prof_bytes[NFVM_K_RESTRICT0] = N * (2 * s0 + 2) + nc * (2 * scs + 1);
       prof_bytes[NFVM_K_PROLONG0] = N * (2 * s0 + 1) + nc * (scs + 1);
-      prof_bytes[NFVM_K_EXPLICIT] = N * (6 * sv + 6 * sf + sp + 1);
-      prof_bytes[NFVM_K_DESTROY] = N * (3 * sv + 4 * sf + 1);
+      prof_bytes[NFVM_K_EXPLICIT] = N * (6 * sv + 7 * sf + sp + 1);
+      prof_bytes[NFVM_K_DESTROY] = N * (3 * sv + 5 * sf + 1);  // (the first half step)
       prof_bytes[NFVM_K_RHS] = N * (3 * sv + so + 1);
       prof_bytes[NFVM_K_PROJECT] = N * (6 * sv + 2 * sp + so + 1);
       prof_bytes[NFVM_K_FCG_APPLY] = N * (s0 + 3 * so + 2);
@@ -324,6 +325,7 @@ class GridT : public GridBase {
         sca[f][c] = alloc<F>(g.total);
       }
     p = alloc<P>(g.total);
+    nut = alloc<F>(g.total);
     stage = alloc<double>((size_t)ncells);
 
     // multigrid hierarchy
@@ -430,11 +432,11 @@ class GridT : public GridBase {
       FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
       FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
       tp[TP_EXPLICIT] = tune_one(100 + TP_EXPLICIT, g, [&](int tt) {
-        launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, tt, stream);
+        launch_explicit<V, F, P>(g, ph, type, patches, in, p, nut, out, tt, stream);
       });
       tp[TP_DESTROY] = tune_one(100 + TP_DESTROY, g, [&](int tt) {
         launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
-                             0.0, salt(4), salt(5), nullptr, tt, stream);
+                             0.0, salt(4), salt(5), nut, nullptr, tt, stream);
       });
       tp[TP_RHS] = tune_one(100 + TP_RHS, g, [&](int tt) {
         launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red, tt, stream);
@@ -833,7 +835,7 @@ class GridT : public GridBase {
     if (ph.komega) {
       prof_begin(NFVM_K_DESTROY);
       launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
-                           half, salt(4), salt(5), nullptr, tp[TP_DESTROY], stream);
+                           half, salt(4), salt(5), nut, nullptr, tp[TP_DESTROY], stream);
       prof_end(NFVM_K_DESTROY);
       swap(4);
       swap(5);
@@ -841,7 +843,7 @@ class GridT : public GridBase {
     FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
     FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
     prof_begin(NFVM_K_EXPLICIT);
-    launch_explicit<V, F, P>(g, ph, type, patches, in, p, out, tp[TP_EXPLICIT], stream);
+    launch_explicit<V, F, P>(g, ph, type, patches, in, p, nut, out, tp[TP_EXPLICIT], stream);
     prof_end(NFVM_K_EXPLICIT);
     for (int f = 0; f < 6; ++f) swap(f);
     prof_begin(NFVM_K_RHS);
@@ -865,7 +867,7 @@ class GridT : public GridBase {
     if (ph.komega) {
       prof_begin(NFVM_K_DESTROY);
       launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
-                           half, salt(4), salt(5), &red, tp[TP_DESTROY], stream);
+                           half, salt(4), salt(5), nullptr, &red, tp[TP_DESTROY], stream);
       prof_end(NFVM_K_DESTROY);
       swap(4);
       swap(5);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
                                                 const V* __restrict__ w, const F* __restrict__ kk,
                                                 const F* __restrict__ om, V tau,
                                                 F* __restrict__ k_out, F* __restrict__ om_out,
-                                                RedBuf red, Tiles T) {
+                                                F* __restrict__ nut_out, RedBuf red, Tiles T) {
   typedef V R;
   int tx = 0, ty = 0, tz = 0;
   const bool tile = tile_of(T, tx, ty, tz);
@@ -139,6 +139,8 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
       }
       mk = fmin(mk, (double)kn);
       mw = fmin(mw, (double)wn);
+      // eddy viscosity of the stored k, omega, for the explicit step
+      if (nut_out) nut_out[P] = (F)eddy_visc<R>((R)ph.nu, (R)(F)kn, (R)(F)wn);
     }
     k_out[P] = (F)kn;
     om_out[P] = (F)wn;
@@ -152,20 +154,20 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
 template <class V, class F>
 void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                     const V* u, const V* v, const V* w, const F* k, const F* om, double tau,
-                    F* k_out, F* om_out, const RedBuf* red, int tt, hipStream_t s) {
+                    F* k_out, F* om_out, F* nut_out, const RedBuf* red, int tt, hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
   if (red) {
     NFVM_LAUNCH((k_destroy<V, F, true>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt,
-                       u, v, w, k, om, (V)tau, k_out, om_out, *red, T);
+                       u, v, w, k, om, (V)tau, k_out, om_out, nut_out, *red, T);
     launch_finalize(2, R_MIN, *red, T.grid, S_MINK, S_MINW, s);
   } else
     NFVM_LAUNCH((k_destroy<V, F, false>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type,
-                       pt, u, v, w, k, om, (V)tau, k_out, om_out, RedBuf{}, T);
+                       pt, u, v, w, k, om, (V)tau, k_out, om_out, nut_out, RedBuf{}, T);
 }
 #define INST_DESTROY(V, F)                                                                      \
   template void launch_destroy<V, F>(const Geom&, const Phys&, const uint8_t*, const DevPatch*, \
                                      const V*, const V*, const V*, const F*, const F*, double,  \
-                                     F*, F*, const RedBuf*, int, hipStream_t);
+                                     F*, F*, F*, const RedBuf*, int, hipStream_t);
 INST_DESTROY(double, double)
 INST_DESTROY(float, float)
 INST_DESTROY(double, float)
@@ -176,137 +178,227 @@ INST_DESTROY(double, float)
 // faces normal to a momentum component; RHS = sum_d (F_+ - F_-)/h_d plus
 // sources (buoyancy, G_k = nu_t S^2, G_omega = alpha_inf (alpha_0 +
 // Re_t/R_w)/(1 + Re_t/R_w) S^2); one forward-Euler step; k, omega >= eps.
+// Values of one cell that the face fluxes need.
+template <class R>
+struct CellVals {
+  R v[6];  // u v w T k omega
+  R p, nut;
+};
+
+template <class V, class F, class P, class R>
+__device__ __forceinline__ void load_cell(const FieldSet<V, F>& in, const P* __restrict__ p,
+                                          const F* __restrict__ nut, int N, int komega,
+                                          CellVals<R>& c) {
+  c.v[0] = (R)in.u[N];
+  c.v[1] = (R)in.v[N];
+  c.v[2] = (R)in.w[N];
+  c.v[3] = (R)in.T[N];
+  c.v[4] = (R)in.k[N];
+  c.v[5] = (R)in.om[N];
+  c.p = (R)p[N];
+  c.nut = komega ? (R)nut[N] : (R)0;
+}
+
+// Ghost values across a face to a non-fluid neighbour of cell P.
+template <class R>
+__device__ __forceinline__ void ghost_cell(const DevPatch& pp, const CellVals<R>& P, int komega,
+                                           CellVals<R>& c) {
+  for (int a = 0; a < 3; ++a) c.v[a] = ghost<R>(pp, G_U + a, P.v[a], komega);
+  c.v[3] = ghost<R>(pp, G_T, P.v[3], komega);
+  c.v[4] = ghost<R>(pp, G_K, P.v[4], komega);
+  c.v[5] = ghost<R>(pp, G_OM, P.v[5], komega);
+  c.p = ghost<R>(pp, G_P, P.p, komega);
+  c.nut = ghost<R>(pp, G_NUT, P.nut, komega);
+}
+
+// Fluxes of the six fields through the face between P and N along axis d
+// (s = -1: N below, +1: N above) and the face velocity.  The value depends
+// only on the lower and upper cell, so the two cells of a face get the same
+// numbers.
+template <class R>
+__device__ __forceinline__ void face_flux(const Phys& ph, const CellVals<R>& P,
+                                          const CellVals<R>& N, int d, int s, R ihd,
+                                          R (&Ff)[6], R& Uf) {
+  const int komega = ph.komega;
+  const R nu = (R)ph.nu;
+  const R gam0[6] = {nu, nu, nu, (R)ph.alpha_T, nu, nu};
+  const R isig[6] = {(R)1, (R)1, (R)1, (R)ph.inv_Pr_t, (R)ph.inv_sigma_k, (R)ph.inv_sigma_w};
+  Uf = (R)0.5 * (P.v[d] + N.v[d]);
+  const R nutf = (R)0.5 * (P.nut + N.nut);
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const R lower = s < 0 ? N.v[f] : P.v[f];
+    const R upper = s < 0 ? P.v[f] : N.v[f];
+    const R up = Uf >= (R)0 ? lower : upper;
+    const R gam = gam0[f] + nutf * isig[f];
+    R F_ = -Uf * up + gam * (upper - lower) * ihd;
+    if (f == d) {
+      const R pf = (R)0.5 * (P.p + N.p);
+      const R kf = komega ? (R)0.5 * (P.v[4] + N.v[4]) : (R)0;
+      F_ -= pf + (R)(2.0 / 3.0) * kf;
+    }
+    Ff[f] = F_;
+  }
+}
+
+// Each thread walks cz planes of one column.  The cell above becomes the
+// next centre and the flux through the face between them is kept, so a cell
+// loads only its four in-plane neighbours and the cell above, and computes
+// five face fluxes instead of six; the sums are formed in the same order as
+// face by face.
 template <class V, class F, class P>
-__global__ __launch_bounds__(BS) void k_explicit(Geom g, Phys ph, const uint8_t* __restrict__ type,
+__global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                  const DevPatch* __restrict__ pt,
                                                  FieldSet<V, F> in, const P* __restrict__ p,
-                                                 FieldSet<V, F> out, Tiles T) {
+                                                 const F* __restrict__ nut, FieldSet<V, F> out,
+                                                 Tiles T) {
   typedef V R;
   int tx = 0, ty = 0, tz = 0;
   const bool tile = tile_of(T, tx, ty, tz);
   const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
   const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
   if (!tile || i >= g.nx || j >= g.ny) return;
-  for (int k = kb; k < ke; ++k) {
-  const int C0 = g.idx(i, j, k);
-  const uint8_t tp = type[C0];
-  // field order: u v w T k omega
-  const V* vin[3] = {in.u, in.v, in.w};
-  const F* sin_[3] = {in.T, in.k, in.om};
-  R vP[6];
-  for (int f = 0; f < 3; ++f) vP[f] = (R)vin[f][C0];
-  for (int f = 0; f < 3; ++f) vP[3 + f] = (R)sin_[f][C0];
-  if (!is_fluid(tp)) {
-    out.u[C0] = in.u[C0];
-    out.v[C0] = in.v[C0];
-    out.w[C0] = in.w[C0];
-    out.T[C0] = in.T[C0];
-    out.k[C0] = in.k[C0];
-    out.om[C0] = in.om[C0];
-    continue;
-  }
   const R nu = (R)ph.nu;
   const int komega = ph.komega;
-  const R pP = (R)p[C0];
-  const R nutP = komega ? eddy_visc<R>(nu, vP[4], vP[5]) : (R)0;
-  const R gam0[6] = {nu, nu, nu, (R)ph.alpha_T, nu, nu};
-  const R isig[6] = {(R)1, (R)1, (R)1, (R)ph.inv_Pr_t, (R)ph.inv_sigma_k, (R)ph.inv_sigma_w};
+  const bool d3 = g.dim == 3;
   const int st[3] = {1, g.sx, g.sxy};
   const R ih[3] = {(R)(1.0 / g.hx), (R)(1.0 / g.hy), (R)(1.0 / g.hz)};
-  R rhs[6] = {0, 0, 0, 0, 0, 0};
-  R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  R divU = 0;
-  for (int d = 0; d < g.dim; ++d)
-    for (int s = -1; s <= 1; s += 2) {
-      const int N = C0 + s * st[d];
-      const uint8_t tn = type[N];
-      R vN[6], pN, nutN;
-      if (is_fluid(tn)) {
-        for (int f = 0; f < 3; ++f) vN[f] = (R)vin[f][N];
-        for (int f = 0; f < 3; ++f) vN[3 + f] = (R)sin_[f][N];
-        pN = (R)p[N];
-        nutN = komega ? eddy_visc<R>(nu, vN[4], vN[5]) : (R)0;
-      } else {
-        const DevPatch& pp = pt[tn & 0x7f];
-        for (int a = 0; a < 3; ++a) vN[a] = ghost<R>(pp, G_U + a, vP[a], komega);
-        vN[3] = ghost<R>(pp, G_T, vP[3], komega);
-        vN[4] = ghost<R>(pp, G_K, vP[4], komega);
-        vN[5] = ghost<R>(pp, G_OM, vP[5], komega);
-        pN = ghost<R>(pp, G_P, pP, komega);
-        nutN = ghost<R>(pp, G_NUT, nutP, komega);
-      }
-      const R Uf = (R)0.5 * (vP[d] + vN[d]);
-      const R nutf = (R)0.5 * (nutP + nutN);
-      const R sc = (R)s * ih[d];
-      divU += sc * Uf;
-      const R hg = (R)s * (R)0.5 * ih[d];
-      for (int a = 0; a < g.dim; ++a) G[a][d] += hg * vN[a];
-      for (int f = 0; f < 6; ++f) {
-        const R lower = s < 0 ? vN[f] : vP[f];
-        const R upper = s < 0 ? vP[f] : vN[f];
-        const R up = Uf >= (R)0 ? lower : upper;
-        const R gam = gam0[f] + nutf * isig[f];
-        R Ff = -Uf * up + gam * (upper - lower) * ih[d];
-        if (f == d) {
-          const R pf = (R)0.5 * (pP + pN);
-          const R kf = komega ? (R)0.5 * (vP[4] + vN[4]) : (R)0;
-          Ff -= pf + (R)(2.0 / 3.0) * kf;
-        }
-        rhs[f] += sc * Ff;
-      }
-    }
   const R dt = (R)ph.dt;
-  // temperature is stored as theta = T - T_ref: the convective flux of the
-  // constant T_ref adds -T_ref div(U_f), which keeps the update identical to
-  // the one of T itself
-  rhs[3] -= (R)ph.T_ref * divU;
-  R o[6];
-  for (int a = 0; a < 3; ++a) {
-    R src = 0;
-    if (ph.buoyancy) src = -(R)ph.beta_T * vP[3] * (R)ph.g[a];
-    o[a] = a < g.dim ? vP[a] + dt * (rhs[a] + src) : vP[a];
-  }
-  o[3] = ph.energy ? vP[3] + dt * rhs[3] : vP[3];
-  o[4] = vP[4];
-  o[5] = vP[5];
-  if (komega) {
-    R S2 = 0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        const R sab = (R)0.5 * (G[a][b] + G[b][a]);
-        S2 += sab * sab;
+  int C0 = g.idx(i, j, kb);
+  // centre of the first plane
+  uint8_t tp = type[C0];
+  CellVals<R> cP;
+  load_cell<V, F, P, R>(in, p, nut, C0, komega, cP);
+  // the face below the centre: its flux when the cell below was a fluid
+  // centre of this walk
+  bool have_lo = false;
+  R Flo[6], Ulo = 0;
+  R vlo[3] = {0, 0, 0};  // velocities of the fluid cell below
+  for (int k = kb; k < ke; ++k, C0 += g.sxy) {
+    // the cell above: loaded once, the next centre
+    const int Nz = C0 + g.sxy;
+    const uint8_t tz_ = d3 ? type[Nz] : (uint8_t)1;
+    CellVals<R> cU;
+    if (d3 && is_fluid(tz_)) load_cell<V, F, P, R>(in, p, nut, Nz, komega, cU);
+    bool next_have = false;
+    R Fhi[6], Uhi = 0;
+    if (!is_fluid(tp)) {
+      out.u[C0] = in.u[C0];
+      out.v[C0] = in.v[C0];
+      out.w[C0] = in.w[C0];
+      out.T[C0] = in.T[C0];
+      out.k[C0] = in.k[C0];
+      out.om[C0] = in.om[C0];
+    } else {
+      R rhs[6] = {0, 0, 0, 0, 0, 0};
+      R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      R divU = 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+#pragma unroll
+        for (int s = -1; s <= 1; s += 2) {
+          if (d >= g.dim) continue;
+          R Ff[6], Uf;
+          R vN[3];
+          if (d == 2 && s < 0 && have_lo) {
+            for (int f = 0; f < 6; ++f) Ff[f] = Flo[f];
+            Uf = Ulo;
+            for (int a = 0; a < 3; ++a) vN[a] = vlo[a];
+          } else {
+            CellVals<R> cN;
+            const int N = C0 + s * st[d];
+            const uint8_t tn = (d == 2 && s > 0) ? tz_ : type[N];
+            if (is_fluid(tn)) {
+              if (d == 2 && s > 0)
+                cN = cU;
+              else
+                load_cell<V, F, P, R>(in, p, nut, N, komega, cN);
+            } else {
+              ghost_cell<R>(pt[tn & 0x7f], cP, komega, cN);
+            }
+            face_flux<R>(ph, cP, cN, d, s, ih[d], Ff, Uf);
+            for (int a = 0; a < 3; ++a) vN[a] = cN.v[a];
+            if (d == 2 && s > 0 && is_fluid(tn)) {
+              next_have = true;
+              for (int f = 0; f < 6; ++f) Fhi[f] = Ff[f];
+              Uhi = Uf;
+            }
+          }
+          const R sc = (R)s * ih[d];
+          divU += sc * Uf;
+          const R hg = (R)s * (R)0.5 * ih[d];
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            if (a < g.dim) G[a][d] += hg * vN[a];
+#pragma unroll
+          for (int f = 0; f < 6; ++f) rhs[f] += sc * Ff[f];
+        }
       }
-    S2 *= (R)2;
-    const R ret = vP[4] / (nu * omhat(vP[5]));
-    const R xr = ret * (R)(1.0 / C_R_W);
-    const R Gk = nutP * S2;
-    const R Gw = (R)C_A_INF * ((R)C_A0 + xr) / ((R)1 + xr) * S2;
-    const R kn = vP[4] + dt * (rhs[4] + Gk);
-    o[4] = kn > (R)C_EPS ? kn : (R)C_EPS;
-    if (!(tp & FIXED_BIT)) {
-      const R wn = vP[5] + dt * (rhs[5] + Gw);
-      o[5] = wn > (R)C_EPS ? wn : (R)C_EPS;
+      // temperature is stored as theta = T - T_ref: the convective flux of the
+      // constant T_ref adds -T_ref div(U_f), which keeps the update identical to
+      // the one of T itself
+      rhs[3] -= (R)ph.T_ref * divU;
+      R o[6];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R src = 0;
+        if (ph.buoyancy) src = -(R)ph.beta_T * cP.v[3] * (R)ph.g[a];
+        o[a] = a < g.dim ? cP.v[a] + dt * (rhs[a] + src) : cP.v[a];
+      }
+      o[3] = ph.energy ? cP.v[3] + dt * rhs[3] : cP.v[3];
+      o[4] = cP.v[4];
+      o[5] = cP.v[5];
+      if (komega) {
+        R S2 = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b2 = 0; b2 < 3; ++b2) {
+            const R sab = (R)0.5 * (G[a][b2] + G[b2][a]);
+            S2 += sab * sab;
+          }
+        S2 *= (R)2;
+        const R ret = cP.v[4] / (nu * omhat(cP.v[5]));
+        const R xr = ret * (R)(1.0 / C_R_W);
+        const R Gk = cP.nut * S2;
+        const R Gw = (R)C_A_INF * ((R)C_A0 + xr) / ((R)1 + xr) * S2;
+        const R kn = cP.v[4] + dt * (rhs[4] + Gk);
+        o[4] = kn > (R)C_EPS ? kn : (R)C_EPS;
+        if (!(tp & FIXED_BIT)) {
+          const R wn = cP.v[5] + dt * (rhs[5] + Gw);
+          o[5] = wn > (R)C_EPS ? wn : (R)C_EPS;
+        }
+      }
+      out.u[C0] = (V)o[0];
+      out.v[C0] = (V)o[1];
+      out.w[C0] = (V)o[2];
+      out.T[C0] = (F)o[3];
+      out.k[C0] = (F)o[4];
+      out.om[C0] = (F)o[5];
     }
-  }
-  out.u[C0] = (V)o[0];
-  out.v[C0] = (V)o[1];
-  out.w[C0] = (V)o[2];
-  out.T[C0] = (F)o[3];
-  out.k[C0] = (F)o[4];
-  out.om[C0] = (F)o[5];
+    // shift: the cell above becomes the centre
+    have_lo = next_have;
+    if (next_have) {
+      for (int f = 0; f < 6; ++f) Flo[f] = Fhi[f];
+      Ulo = Uhi;
+      for (int a = 0; a < 3; ++a) vlo[a] = cP.v[a];
+    }
+    tp = tz_;
+    if (d3 && is_fluid(tz_)) cP = cU;  // (a non-fluid centre only copies its values)
   }
 }
 
 template <class V, class F, class P>
 void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, int tt, hipStream_t s) {
+                     FieldSet<V, F> in, const P* p, const F* nut, FieldSet<V, F> out, int tt,
+                     hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
   NFVM_LAUNCH((k_explicit<V, F, P>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, in,
-                     p, out, T);
+                     p, nut, out, T);
 }
 #define INST_EXPLICIT(V, F, P)                                                                 \
   template void launch_explicit<V, F, P>(const Geom&, const Phys&, const uint8_t*,             \
-                                         const DevPatch*, FieldSet<V, F>, const P*,            \
+                                         const DevPatch*, FieldSet<V, F>, const P*, const F*,  \
                                          FieldSet<V, F>, int, hipStream_t);
 INST_EXPLICIT(double, double, double)
 INST_EXPLICIT(float, float, float)

@@ -202,10 +202,13 @@ struct FieldSet {
 template <class V, class F>
 void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                     const V* u, const V* v, const V* w, const F* k, const F* om, double tau,
-                    F* k_out, F* om_out, const RedBuf* red, int tt, hipStream_t s);
+                    F* k_out, F* om_out, F* nut_out, const RedBuf* red, int tt, hipStream_t s);
+// (nut: eddy viscosity per cell, written by the destruction half step that
+// precedes the explicit step)
 template <class V, class F, class P>
 void launch_explicit(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                     FieldSet<V, F> in, const P* p, FieldSet<V, F> out, int tt, hipStream_t s);
+                     FieldSet<V, F> in, const P* p, const F* nut, FieldSet<V, F> out, int tt,
+                     hipStream_t s);
 template <class V, class O>
 void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                   const V* u, const V* v, const V* w, O* b, const RedBuf& red, int tt,
