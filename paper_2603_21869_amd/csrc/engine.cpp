@@ -211,7 +211,8 @@ class GridT : public GridBase {
   int* cmap = nullptr;
   int* ncount = nullptr;
   double* work = nullptr;
-  double* hs = nullptr;  // pinned host copy of the scalars
+  double* hs = nullptr;  // host-coherent mirror of the scalars (written by the device)
+  hipEvent_t ev_step[2][2] = {};  // start / end of the last two steps
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   template <class T>
@@ -227,6 +228,9 @@ class GridT : public GridBase {
     prof_release();
     pool.clear();
     if (hs) (void)hipHostFree(hs);
+    for (auto& pr : ev_step)
+      for (hipEvent_t e : pr)
+        if (e) (void)hipEventDestroy(e);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -277,7 +281,11 @@ class GridT : public GridBase {
     }
     NFVM_CK(hipEventCreate(&ev0));
     NFVM_CK(hipEventCreate(&ev1));
-    NFVM_CK(hipHostMalloc((void**)&hs, S_COUNT * sizeof(double), hipHostMallocDefault));
+    for (auto& pr : ev_step)
+      for (hipEvent_t& e : pr) NFVM_CK(hipEventCreate(&e));
+    NFVM_CK(hipHostMalloc((void**)&hs, S_COUNT * sizeof(double),
+                          hipHostMallocMapped | hipHostMallocCoherent));
+    memset(hs, 0, S_COUNT * sizeof(double));
 
     // patch table: 0 fluid (unused), 1 solid blocks, 2..7 default walls, then user patches
     std::vector<DevPatch> tab(MAX_PATCHES);
@@ -379,6 +387,7 @@ class GridT : public GridBase {
     red.partial = alloc<double>((size_t)red.max_blocks * 3);
     red.counter = alloc<unsigned>(16);
     red.out = alloc<double>(S_COUNT);
+    NFVM_CK(hipHostGetDevicePointer((void**)&red.mirror, hs, 0));
 
     for (int t = 0; t < TP_COUNT; ++t) tp[t] = TILE_DEFAULT;
     if (use_autotune) autotune();
@@ -710,13 +719,6 @@ class GridT : public GridBase {
     for (int s = 0; s < nu2; ++s) smooth(l, false);
   }
 
-  double read_scalar(int slot) {
-    NFVM_CK(hipMemcpyAsync(hs + slot, red.out + slot, sizeof(double), hipMemcpyDeviceToHost,
-                           stream));
-    NFVM_CK(hipStreamSynchronize(stream));
-    return hs[slot];
-  }
-
   // One preconditioned flexible-CG iteration (all kernels are no-ops once
   // the device-side stopping rule has fired).
   void fcg_iteration() {
@@ -784,11 +786,13 @@ class GridT : public GridBase {
     int ahead = forced >= 0 ? forced : std::min(predicted, maxc);
     for (int i = 0; i < ahead; ++i) run_iteration();
     NFVM_CK(hipGetLastError());
-    for (;;) {
-      NFVM_CK(hipMemcpyAsync(hs, red.out, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                             stream));
+    const int limit = std::max(maxc, forced) + 2;  // the device stops at max_cycles
+    for (int enq = ahead;; ++enq) {
+      // the finalising kernels mirror the stopping state into hs
       NFVM_CK(hipStreamSynchronize(stream));
+      prof_collect();
       if (hs[S_DONE] != 0.0) break;
+      if (enq >= limit) throw Error{NFVM_E_DEVICE, "stopping state of the solve not observed"};
       run_iteration();
       NFVM_CK(hipGetLastError());
     }
@@ -892,15 +896,46 @@ class GridT : public GridBase {
     NFVM_CK(hipGraphLaunch(pg.exec, stream));
   }
 
+  // Steps run back to back with one host synchronisation each (the solve's
+  // convergence check); the statistics of a step (face divergence, min k,
+  // min omega, run time) are read at the next synchronisation, when the
+  // mirror still holds them, and after the last step.
   void step(int n, nfvm_step_stats* stt, nfvm_status* status) override {
     nfvm_status worst = NFVM_OK;
+    int pend = -1, pend_cyc = 0;
+    double pend_rel = 0;
+    nfvm_status pend_st = NFVM_OK;
+    auto collect = [&]() -> bool {  // after a synchronisation
+      if (pend < 0) return true;
+      nfvm_status st = pend_st;
+      if (!isfinite(hs[S_DIV])) st = NFVM_E_DIVERGED;
+      if (stt) {
+        float ms = 0;
+        NFVM_CK(hipEventElapsedTime(&ms, ev_step[pend & 1][0], ev_step[pend & 1][1]));
+        stt[pend].cycles = pend_cyc;
+        stt[pend].status = st;
+        stt[pend].rel_residual = pend_rel;
+        stt[pend].max_face_div = hs[S_DIV];
+        stt[pend].min_k = ph.komega ? hs[S_MINK] : NAN;
+        stt[pend].min_omega = ph.komega ? hs[S_MINW] : NAN;
+        stt[pend].seconds = ms * 1e-3;
+      }
+      pend = -1;
+      if (st == NFVM_E_DIVERGED) {
+        *status = st;
+        return false;
+      }
+      if (st != NFVM_OK && worst == NFVM_OK) worst = st;
+      return true;
+    };
     for (int s = 0; s < n; ++s) {
-      NFVM_CK(hipEventRecord(ev0, stream));
+      NFVM_CK(hipEventRecord(ev_step[s & 1][0], stream));
       run_part(g_pre, [&] { step_prefix(); });
       NFVM_CK(hipGetLastError());
       int cyc = 0;
       double rel = 0;
       nfvm_status st = solve(false, tol, max_cycles, -1, &cyc, &rel, true);
+      if (!collect()) return;  // the previous step, read at the solve's synchronisation
       if (st == NFVM_E_DIVERGED) {
         if (stt) {
           memset(&stt[s], 0, sizeof stt[s]);
@@ -913,31 +948,18 @@ class GridT : public GridBase {
       }
       run_part(g_suf, [&] { step_suffix(); });
       NFVM_CK(hipGetLastError());
-      NFVM_CK(hipEventRecord(ev1, stream));
-      NFVM_CK(hipMemcpyAsync(hs, red.out, S_COUNT * sizeof(double), hipMemcpyDeviceToHost,
-                             stream));
-      NFVM_CK(hipStreamSynchronize(stream));
-      prof_collect();
-      float ms = 0;
-      NFVM_CK(hipEventElapsedTime(&ms, ev0, ev1));
-      if (!isfinite(hs[S_DIV])) st = NFVM_E_DIVERGED;
-      if (stt) {
-        stt[s].cycles = cyc;
-        stt[s].status = st;
-        stt[s].rel_residual = rel;
-        stt[s].max_face_div = hs[S_DIV];
-        stt[s].min_k = ph.komega ? hs[S_MINK] : NAN;
-        stt[s].min_omega = ph.komega ? hs[S_MINW] : NAN;
-        stt[s].seconds = ms * 1e-3;
-      }
-      if (st == NFVM_E_DIVERGED) {
-        *status = st;
-        return;
-      }
-      if (st != NFVM_OK && worst == NFVM_OK) worst = st;
+      NFVM_CK(hipEventRecord(ev_step[s & 1][1], stream));
+      pend = s;
+      pend_cyc = cyc;
+      pend_rel = rel;
+      pend_st = st;
     }
+    NFVM_CK(hipStreamSynchronize(stream));
+    prof_collect();
+    if (!collect()) return;
     *status = worst;
   }
+
 
   void set_option(int opt, double v) override {
     if (opt == NFVM_OPT_GRAPHS) {

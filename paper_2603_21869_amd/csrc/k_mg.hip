@@ -594,6 +594,18 @@ __global__ __launch_bounds__(MBS) void k_fcg_start(LevelView L, Tiles T, const O
   block_partial<2, R_SUM, MBS>(vv, red);
 }
 
+// Copy slots of red.out to the host-coherent mirror (one thread) and make
+// the stores visible to the host before the kernel ends.
+__device__ __forceinline__ void publish(const RedBuf& red, int s0, int s1 = -1, int s2 = -1,
+                                        int s3 = -1) {
+  if (!red.mirror) return;
+  red.mirror[s0] = red.out[s0];
+  if (s1 >= 0) red.mirror[s1] = red.out[s1];
+  if (s2 >= 0) red.mirror[s2] = red.out[s2];
+  if (s3 >= 0) red.mirror[s3] = red.out[s3];
+  __threadfence_system();
+}
+
 // Stopping rule, evaluated by one thread after ||r||^2 is known.
 __device__ __forceinline__ void fcg_judge(double* ctl) {
   const double bb = ctl[S_BB], rr = ctl[S_RR], it = ctl[S_ITER];
@@ -630,6 +642,7 @@ __global__ __launch_bounds__(FIN) void k_fin_start(RedBuf red, int nb, double to
     red.out[S_MAXIT] = maxit;
     red.out[S_FORCED] = forced;
     fcg_judge(red.out);
+    publish(red, S_BB, S_RR, S_ITER, S_DONE);
   }
 }
 
@@ -765,6 +778,7 @@ __global__ __launch_bounds__(FIN) void k_fin_update(RedBuf red, int nb) {
     red.out[S_RR] = acc[0];
     red.out[S_ITER] += 1.0;
     fcg_judge(red.out);
+    publish(red, S_RR, S_ITER, S_DONE);
   }
 }
 
@@ -789,6 +803,7 @@ __global__ __launch_bounds__(256) void k_finalize(RedBuf red, int nb, int s0, in
   if (threadIdx.x == 0) {
     red.out[s0] = acc[0];
     if (NV > 1) red.out[s1] = acc[NV - 1];
+    publish(red, s0, NV > 1 ? s1 : -1);
   }
 }
 

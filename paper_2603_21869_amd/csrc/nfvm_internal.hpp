@@ -145,6 +145,9 @@ struct RedBuf {
   unsigned* counter;
   double* out;
   int max_blocks;
+  // host-coherent copy of the scalars the host reads (stopping state,
+  // norms, step statistics), written by the finalising kernels; may be null
+  double* mirror;
 };
 
 // Scalars of the pressure iteration kept on the device.
