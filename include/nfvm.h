@@ -142,6 +142,19 @@ nfvm_status nfvm_init_grid(const nfvm_grid_desc* desc, const nfvm_fields* init, 
  * non-finite residuals (the step stops; fields are undefined). */
 nfvm_status nfvm_step(nfvm_grid_t grid, int32_t n_steps, nfvm_step_stats* stats);
 
+/* Advance n_steps time steps (Sec. 2.6) of several grids together, a
+ * batching the paper does not treat: each multigrid level's kernels run as one launch
+ * over the tiles of every grid of a precision, the bottom solvers and the
+ * CG finalisers as one workgroup per grid, all on grids[0]'s stream (the
+ * other grids' streams are joined before and after).  A grid whose pressure
+ * solve converges goes on to its next step while the others iterate.
+ * Results are bitwise those of nfvm_step on each grid alone.  All grids on
+ * the current device, no grid twice.  stats: NULL or n_grids * n_steps
+ * entries, grid-major; statuses: NULL or n_grids entries (each as
+ * nfvm_step would return).  Returns the first non-OK status in grid order. */
+nfvm_status nfvm_step_batch(nfvm_grid_t* grids, int32_t n_grids, int32_t n_steps,
+                            nfvm_step_stats* stats, nfvm_status* statuses);
+
 /* Solve A x = b with the grid's pressure operator (eq. pc_discretized:
  * seven/five-point -laplacian, zero-gradient walls, inlets and solids, zero
  * value at outlets) by the multigrid-preconditioned iteration.  b, x: host
@@ -165,13 +178,16 @@ nfvm_status nfvm_grid_footprint(const nfvm_grid_desc* desc, size_t* bytes);
 
 nfvm_status nfvm_free_grid(nfvm_grid_t grid);
 
-/* Serving: max_slots host worker threads admit queued solves, first fit in
- * arrival order, while the summed device footprint of running solves stays
- * within hbm_budget_bytes.  Every admitted solve runs on its own HIP stream,
- * so solves of different grid sizes overlap on the device, and a slot takes
- * the next admissible request as soon as its solve finishes (new work joins
- * at step boundaries of the running ones).  A finished solve releases its
- * device memory and keeps its fields on the host until polled.
+/* Serving: at most max_slots solves run at once; queued solves are admitted
+ * first fit in arrival order while the summed device footprint of running
+ * solves stays within hbm_budget_bytes.  Running solves are spread over
+ * min(max_slots, 3) lanes, each a host thread with its own HIP stream that
+ * advances its solves together as in nfvm_step_batch (at most
+ * ceil(max_slots / lanes) per lane); lanes overlap on the device.  A lane
+ * admits the next request as soon as it has room (new work joins at the next
+ * round of its lane).  A finished solve releases its device memory and keeps
+ * its fields on the host until polled.  Every request's fields are bitwise
+ * those of nfvm_step on a grid of its own.
  * hbm_budget_bytes <= 0: 90 % of the free device memory. */
 nfvm_status nfvm_server_create(double hbm_budget_bytes, int32_t max_slots, nfvm_server_t* out);
 

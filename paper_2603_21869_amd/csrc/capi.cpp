@@ -3,6 +3,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "engine.hpp"
 
@@ -63,6 +64,68 @@ nfvm_status nfvm_step(nfvm_grid_t grid, int32_t n_steps, nfvm_step_stats* stats)
     if (st == NFVM_E_DIVERGED) set_error("non-finite residual or field");
     if (st == NFVM_E_NOTCONV) set_error("pressure solve reached max_cycles");
     return st;
+  });
+}
+
+// The grids' own streams wait for the work enqueued before the call; the
+// batch runs on the first grid's stream, and the others wait for it after.
+struct StreamJoin {
+  std::vector<GridBase*> gs;
+  std::vector<hipStream_t> own;
+  std::vector<hipEvent_t> evs;
+  hipStream_t s = nullptr;
+  explicit StreamJoin(const std::vector<GridBase*>& g) : gs(g) {
+    s = gs[0]->stream;
+    for (GridBase* x : gs) {
+      own.push_back(x->stream);
+      if (x->stream == s) continue;
+      hipEvent_t e = nullptr;
+      NFVM_CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      evs.push_back(e);
+      NFVM_CK(hipEventRecord(e, x->stream));
+      NFVM_CK(hipStreamWaitEvent(s, e, 0));
+      x->stream = s;
+    }
+  }
+  ~StreamJoin() {
+    hipEvent_t e = nullptr;
+    const bool ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess &&
+                    hipEventRecord(e, s) == hipSuccess;
+    for (size_t i = 0; i < gs.size(); ++i) {
+      gs[i]->stream = own[i];
+      if (own[i] != s && ok) (void)hipStreamWaitEvent(own[i], e, 0);
+    }
+    if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t x : evs) (void)hipEventDestroy(x);
+  }
+};
+
+nfvm_status nfvm_step_batch(nfvm_grid_t* grids, int32_t n_grids, int32_t n_steps,
+                            nfvm_step_stats* stats, nfvm_status* statuses) {
+  if (!grids || n_grids < 1 || n_steps < 0)
+    return fail(NFVM_E_INVAL, "grids, n_grids >= 1 and n_steps >= 0 are required");
+  std::vector<GridBase*> gs;
+  for (int i = 0; i < n_grids; ++i) {
+    if (!grids[i]) return fail(NFVM_E_INVAL, "grid is NULL");
+    for (GridBase* o : gs)
+      if (o == grids[i]->g.get()) return fail(NFVM_E_INVAL, "a grid appears twice");
+    gs.push_back(grids[i]->g.get());
+  }
+  return guard([&] {
+    StreamJoin join(gs);
+    BatchRunner br(join.s);
+    for (int i = 0; i < n_grids; ++i)
+      br.add(gs[i], n_steps, stats ? stats + (size_t)i * n_steps : nullptr);
+    while (br.size()) br.advance();
+    nfvm_status first = NFVM_OK;
+    for (int i = 0; i < n_grids; ++i) {
+      const nfvm_status st = gs[i]->run_status();
+      if (statuses) statuses[i] = st;
+      if (st != NFVM_OK && first == NFVM_OK) first = st;
+    }
+    if (first == NFVM_E_DIVERGED) set_error("non-finite residual or field");
+    if (first == NFVM_E_NOTCONV) set_error("pressure solve reached max_cycles");
+    return first;
   });
 }
 

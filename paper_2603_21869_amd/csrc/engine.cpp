@@ -56,7 +56,7 @@ void validate_desc(const nfvm_grid_desc& d) {
   if (padded >= (1LL << 31)) bad("grid too large for 32-bit cell indices");
   if (!(d.dt > 0) || !(d.nu > 0)) bad("dt and nu must be positive");
   if (d.precision < NFVM_FP64 || d.precision > NFVM_MIXED) bad("unknown precision");
-  if (d.n_levels < 1 || d.n_levels > 20) bad("n_levels must be in [1, 20]");
+  if (d.n_levels < 1 || d.n_levels > MAX_LEVELS) bad("n_levels must be in [1, 20]");
   for (int a = 0; a < d.dim; ++a)
     if (d.n[a] % (1 << (d.n_levels - 1))) bad("every axis must halve exactly n_levels-1 times");
   if (d.nu1 < 0 || d.nu2 < 0 || d.nu1 + d.nu2 < 1) bad("need at least one smoothing sweep");
@@ -796,6 +796,11 @@ class GridT : public GridBase {
       run_iteration();
       NFVM_CK(hipGetLastError());
     }
+    return solve_result(forced, tol_, cycles, rel);
+  }
+
+  // Outcome of a finished solve from the mirrored scalars.
+  nfvm_status solve_result(int forced, double tol_, int* cycles, double* rel) {
     const int it = (int)hs[S_ITER];
     const double bn = sqrt(hs[S_BB]), rn = sqrt(hs[S_RR]);
     *rel = bn > 0 ? rn / bn : 0.0;
@@ -896,70 +901,178 @@ class GridT : public GridBase {
     NFVM_CK(hipGraphLaunch(pg.exec, stream));
   }
 
+  // ---- time steps (the GridBase state machine) ----
   // Steps run back to back with one host synchronisation each (the solve's
   // convergence check); the statistics of a step (face divergence, min k,
   // min omega, run time) are read at the next synchronisation, when the
   // mirror still holds them, and after the last step.
-  void step(int n, nfvm_step_stats* stt, nfvm_status* status) override {
-    nfvm_status worst = NFVM_OK;
-    int pend = -1, pend_cyc = 0;
+  struct Run {
+    int n = 0, s = 0;  // steps asked / started
+    nfvm_step_stats* stt = nullptr;
+    nfvm_status worst = NFVM_OK, final_st = NFVM_OK;
+    bool solving = false;
+    int enq = 0;        // iterations enqueued for the running solve
+    int converged = 0;  // steps whose solve met tol
+    int pend = -1, pend_cyc = 0;  // step whose statistics are read at the next synchronisation
     double pend_rel = 0;
     nfvm_status pend_st = NFVM_OK;
-    auto collect = [&]() -> bool {  // after a synchronisation
-      if (pend < 0) return true;
-      nfvm_status st = pend_st;
-      if (!isfinite(hs[S_DIV])) st = NFVM_E_DIVERGED;
-      if (stt) {
-        float ms = 0;
-        NFVM_CK(hipEventElapsedTime(&ms, ev_step[pend & 1][0], ev_step[pend & 1][1]));
-        stt[pend].cycles = pend_cyc;
-        stt[pend].status = st;
-        stt[pend].rel_residual = pend_rel;
-        stt[pend].max_face_div = hs[S_DIV];
-        stt[pend].min_k = ph.komega ? hs[S_MINK] : NAN;
-        stt[pend].min_omega = ph.komega ? hs[S_MINW] : NAN;
-        stt[pend].seconds = ms * 1e-3;
-      }
-      pend = -1;
-      if (st == NFVM_E_DIVERGED) {
-        *status = st;
-        return false;
-      }
-      if (st != NFVM_OK && worst == NFVM_OK) worst = st;
-      return true;
-    };
-    for (int s = 0; s < n; ++s) {
-      NFVM_CK(hipEventRecord(ev_step[s & 1][0], stream));
-      run_part(g_pre, [&] { step_prefix(); });
-      NFVM_CK(hipGetLastError());
-      int cyc = 0;
-      double rel = 0;
-      nfvm_status st = solve(false, tol, max_cycles, -1, &cyc, &rel, true);
-      if (!collect()) return;  // the previous step, read at the solve's synchronisation
-      if (st == NFVM_E_DIVERGED) {
-        if (stt) {
-          memset(&stt[s], 0, sizeof stt[s]);
-          stt[s].status = st;
-          stt[s].cycles = cyc;
-          stt[s].rel_residual = rel;
-        }
-        *status = st;
-        return;
-      }
-      run_part(g_suf, [&] { step_suffix(); });
-      NFVM_CK(hipGetLastError());
-      NFVM_CK(hipEventRecord(ev_step[s & 1][1], stream));
-      pend = s;
-      pend_cyc = cyc;
-      pend_rel = rel;
-      pend_st = st;
-    }
-    NFVM_CK(hipStreamSynchronize(stream));
-    prof_collect();
-    if (!collect()) return;
-    *status = worst;
+  } run;
+
+  void run_start_step() {
+    NFVM_CK(hipEventRecord(ev_step[run.s & 1][0], stream));
+    run_part(g_pre, [&] { step_prefix(); });
+    NFVM_CK(hipGetLastError());
+    run.solving = true;
+    run.enq = 0;
   }
 
+  void run_begin(int n, nfvm_step_stats* stt) override {
+    run = Run{};
+    run.n = n;
+    run.stt = stt;
+    if (n > 0) run_start_step();
+  }
+
+  int run_ahead() const override {
+    if (!run.solving) return -1;
+    return std::max(0, std::min(predicted, max_cycles) - run.enq);
+  }
+
+  void run_enqueued(int k) override { run.enq += k; }
+
+  nfvm_status run_status() const override { return run.final_st; }
+  int run_converged() const override { return run.converged; }
+
+  // the previous step's statistics; false if it diverged
+  bool run_collect() {
+    if (run.pend < 0) return true;
+    nfvm_status st = run.pend_st;
+    if (!isfinite(hs[S_DIV])) st = NFVM_E_DIVERGED;
+    if (run.stt) {
+      float ms = 0;
+      NFVM_CK(hipEventElapsedTime(&ms, ev_step[run.pend & 1][0], ev_step[run.pend & 1][1]));
+      nfvm_step_stats& o = run.stt[run.pend];
+      o.cycles = run.pend_cyc;
+      o.status = st;
+      o.rel_residual = run.pend_rel;
+      o.max_face_div = hs[S_DIV];
+      o.min_k = ph.komega ? hs[S_MINK] : NAN;
+      o.min_omega = ph.komega ? hs[S_MINW] : NAN;
+      o.seconds = ms * 1e-3;
+    }
+    run.pend = -1;
+    if (st == NFVM_E_DIVERGED) return false;
+    if (st != NFVM_OK && run.worst == NFVM_OK) run.worst = st;
+    return true;
+  }
+
+  bool run_after_sync() override {
+    prof_collect();
+    if (!run_collect()) {
+      run.final_st = NFVM_E_DIVERGED;
+      run.solving = false;
+      return true;
+    }
+    if (run.solving) {
+      if (hs[S_DONE] == 0.0) {
+        // the device stops at max_cycles
+        if (run.enq >= max_cycles + 2)
+          throw Error{NFVM_E_DEVICE, "stopping state of the solve not observed"};
+        return false;
+      }
+      run.solving = false;
+      int cyc = 0;
+      double rel = 0;
+      const nfvm_status st = solve_result(-1, tol, &cyc, &rel);
+      if (st == NFVM_E_DIVERGED) {
+        if (run.stt) {
+          memset(&run.stt[run.s], 0, sizeof run.stt[run.s]);
+          run.stt[run.s].status = st;
+          run.stt[run.s].cycles = cyc;
+          run.stt[run.s].rel_residual = rel;
+        }
+        run.final_st = st;
+        return true;
+      }
+      if (st == NFVM_OK) ++run.converged;
+      run_part(g_suf, [&] { step_suffix(); });
+      NFVM_CK(hipGetLastError());
+      NFVM_CK(hipEventRecord(ev_step[run.s & 1][1], stream));
+      run.pend = run.s;
+      run.pend_cyc = cyc;
+      run.pend_rel = rel;
+      run.pend_st = st;
+      if (++run.s < run.n) run_start_step();
+      return false;
+    }
+    if (run.s >= run.n) {  // the last step's statistics are read above
+      run.final_st = run.worst;
+      return true;
+    }
+    return false;
+  }
+
+  void step(int n, nfvm_step_stats* stt, nfvm_status* status) override {
+    run_begin(n, stt);
+    for (;;) {
+      const int ahead = run_ahead();
+      if (ahead >= 0) {
+        const int k = std::max(1, ahead);
+        for (int i = 0; i < k; ++i) run_iteration();
+        run_enqueued(k);
+        NFVM_CK(hipGetLastError());
+      }
+      NFVM_CK(hipStreamSynchronize(stream));
+      if (run_after_sync()) break;
+    }
+    *status = run_status();
+  }
+
+  // ---- batched iterations ----
+  int type_id() const override { return desc.precision; }
+
+  void mg_desc(MgGridDesc& d) {
+    memset(&d, 0, sizeof d);
+    d.lv = lv.data();
+    d.L = L;
+    d.bottom_top = bottom_top;
+    d.nu1 = nu1;
+    d.nu2 = nu2;
+    d.wj = wj;
+    d.bot = &bot;
+    d.cmap = cmap;
+    d.ncount = ncount;
+    d.ainv = work;
+    d.coarse_max = COARSE_MAX;
+    for (int l = 0; l < L; ++l) d.zero[l] = zero_of(l);
+    d.red = red;
+    d.x = phi;
+    d.r = r;
+    d.p = pv;
+    d.q = q;
+    d.w = wv;
+  }
+
+  std::unique_ptr<IterPlan> make_plan(const std::vector<GridBase*>& same) override {
+    std::vector<MgGridDesc> ds(same.size());
+    for (size_t i = 0; i < same.size(); ++i) {
+      if (same[i]->type_id() != type_id() || same[i]->stream != stream)
+        throw Error{NFVM_E_INVAL, "batched grids must share precision and stream"};
+      static_cast<GridT*>(same[i])->mg_desc(ds[i]);
+    }
+    std::unique_ptr<IterPlan> pl(new IterPlan());
+    plan_fcg_iteration<O, S0, SC, C>(ds.data(), (int)ds.size(), pl->ops);
+    pl->blob.alloc(pl->ops.blob.size(), stream);
+    NFVM_CK(hipMemcpyAsync(pl->blob.p, pl->ops.blob.data(), pl->ops.blob.size(),
+                           hipMemcpyHostToDevice, stream));
+    bool graphs = true;
+    for (GridBase* g : same) graphs = graphs && g->use_graphs && g->prof_mask == 0;
+    if (graphs) pl->exec = capture([&] {
+      for (auto& op : pl->ops.ops) op((const unsigned char*)pl->blob.p, stream);
+    });
+    NFVM_CK(hipStreamSynchronize(stream));
+    return pl;
+  }
 
   void set_option(int opt, double v) override {
     if (opt == NFVM_OPT_GRAPHS) {
@@ -1027,6 +1140,69 @@ std::unique_ptr<GridBase> make_grid(const nfvm_grid_desc& d, const nfvm_fields* 
   else
     static_cast<GridMixed*>(gb.get())->init(d, init);
   return gb;
+}
+
+IterPlan::~IterPlan() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+}
+
+void IterPlan::launch(hipStream_t s) {
+  if (exec) {
+    NFVM_CK(hipGraphLaunch(exec, s));
+    return;
+  }
+  for (auto& op : ops.ops) op((const unsigned char*)blob.p, s);
+}
+
+void BatchRunner::add(GridBase* g, int n_steps, nfvm_step_stats* stt) {
+  if (g->stream != stream) throw Error{NFVM_E_INVAL, "grid is not on the runner's stream"};
+  for (GridBase* o : gs)
+    if (o == g) throw Error{NFVM_E_INVAL, "grid added twice"};
+  g->run_begin(n_steps, stt);
+  gs.push_back(g);
+  dirty = true;
+}
+
+std::vector<GridBase*> BatchRunner::advance() {
+  std::vector<GridBase*> over;
+  if (gs.empty()) return over;
+  if (dirty) {
+    plans.clear();
+    std::vector<int> types;
+    for (GridBase* g : gs)
+      if (std::find(types.begin(), types.end(), g->type_id()) == types.end())
+        types.push_back(g->type_id());
+    for (int t : types) {
+      std::vector<GridBase*> same;
+      for (GridBase* g : gs)
+        if (g->type_id() == t) same.push_back(g);
+      plans.push_back(same[0]->make_plan(same));
+    }
+    dirty = false;
+  }
+  // as many iterations as the grid closest to its stopping rule is
+  // predicted to need (grids already stopped skip them on the device)
+  int k = -1;
+  for (GridBase* g : gs) {
+    const int a = g->run_ahead();
+    if (a >= 0) k = k < 0 ? a : std::min(k, a);
+  }
+  if (k >= 0) {
+    k = std::max(1, k);
+    for (int i = 0; i < k; ++i)
+      for (auto& pl : plans) pl->launch(stream);
+    for (GridBase* g : gs)
+      if (g->run_ahead() >= 0) g->run_enqueued(k);
+    NFVM_CK(hipGetLastError());
+  }
+  NFVM_CK(hipStreamSynchronize(stream));
+  std::vector<GridBase*> keep;
+  for (GridBase* g : gs) (g->run_after_sync() ? over : keep).push_back(g);
+  if (!over.empty()) {
+    gs.swap(keep);
+    dirty = true;
+  }
+  return over;
 }
 
 }  // namespace nfvm

@@ -70,10 +70,45 @@ void tune_store(const TuneKey& k, int v);
 std::vector<std::pair<TuneKey, int>> tune_entries();
 void validate_desc(const nfvm_grid_desc& d);
 
+// One CG iteration of several grids of one precision: the batched launches
+// of plan_fcg_iteration, their arguments in device memory, replayed as one
+// graph when graphs are on.
+struct IterPlan {
+  DevBuf blob;
+  BatchOps ops;
+  hipGraphExec_t exec = nullptr;
+  IterPlan() = default;
+  IterPlan(const IterPlan&) = delete;
+  IterPlan& operator=(const IterPlan&) = delete;
+  ~IterPlan();
+  void launch(hipStream_t s);
+};
+
 class GridBase {
  public:
   virtual ~GridBase() = default;
   virtual void step(int n, nfvm_step_stats* st, nfvm_status* status) = 0;
+
+  // ---- time steps as a state machine.  step() drives it for one grid; a
+  // BatchRunner drives several grids on one stream, enqueuing the CG
+  // iterations of all of them as batched launches.
+  // Start n steps (enqueues the first step's prefix); stt: NULL or n entries.
+  virtual void run_begin(int n, nfvm_step_stats* stt) = 0;
+  // -1 while no pressure solve is under way, else the iterations still
+  // predicted before its stopping rule fires (0: check after each one).
+  virtual int run_ahead() const = 0;
+  virtual void run_enqueued(int k) = 0;
+  // After a synchronisation of the grid's stream: read what the device
+  // mirrored, finish a converged solve (suffix, next prefix); true once all
+  // steps are over or one failed.
+  virtual bool run_after_sync() = 0;
+  virtual nfvm_status run_status() const = 0;
+  // time steps whose pressure solve met its tolerance so far
+  virtual int run_converged() const = 0;
+  // grids of one type_id share batched launches
+  virtual int type_id() const = 0;
+  virtual std::unique_ptr<IterPlan> make_plan(const std::vector<GridBase*>& same_type) = 0;
+
   virtual void mg_solve(const double* b_dev, double* x_dev, double tol, int max_cycles, int forced,
                         nfvm_step_stats* st, nfvm_status* status) = 0;
   virtual void get_fields(nfvm_fields* out) = 0;
@@ -108,6 +143,26 @@ class GridBase {
   nfvm_grid_desc desc{};
   double tol = 1e-6;
   int max_cycles = 100;
+};
+
+// Several grids advanced together on one stream: per round, the next CG
+// iterations of every grid whose pressure solve is under way as batched
+// launches (one plan per precision), then one synchronisation, after which
+// each grid finishes a converged solve and starts its next step.  Grids may
+// join (add) at any round; a grid leaves when advance() returns it.
+class BatchRunner {
+ public:
+  explicit BatchRunner(hipStream_t s) : stream(s) {}
+  // g must run on this runner's stream
+  void add(GridBase* g, int n_steps, nfvm_step_stats* stt);
+  std::vector<GridBase*> advance();
+  size_t size() const { return gs.size(); }
+
+ private:
+  hipStream_t stream;
+  std::vector<GridBase*> gs;
+  std::vector<std::unique_ptr<IterPlan>> plans;
+  bool dirty = true;
 };
 
 // tune_mode: 0 default tiles, 1 autotune (cached per shape), 2 cached choices only

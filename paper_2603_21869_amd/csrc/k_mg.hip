@@ -8,7 +8,18 @@
 // same formula covers zero-value outlet faces (c_f = 2 there) and closed faces
 // (c_f = 0).  Regular cells (all c_f = 1, neighbours inside the box) skip the
 // coefficient loads.
+// Multiply-adds are fused only where one source expression holds both
+// (a * b + c), never across statements: the rounding of every result then
+// follows from the source alone, so a single launch and a batched launch of
+// the same body give bitwise the same values however the compiler unrolls or
+// schedules each.
+#pragma clang fp contract(on)
+
 #include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "nfvm_device.hpp"
 
@@ -132,6 +143,82 @@ __host__ inline Tiles lvl_tiles(const Level& l, int kid) {
   return make_tiles(l.g.nx, l.g.ny, l.g.nz, l.tt[kid]);
 }
 
+// ---- single and batched launches ----------------------------------------------------
+// Every level kernel is a body taking its arguments as one struct and the tile
+// it works on.  A single launch covers one grid (block b takes tile
+// tile_of(b)); a batched launch covers the tiles of up to MAXB grids, one
+// after the other.  `pb` is the block index the tile has in a single launch of its grid, where
+// a reduction kernel stores its partial: batched and single launches then sum
+// the same partials in the same order.
+struct TileCtx {
+  int tx, ty, tz, pb;
+};
+
+__device__ __forceinline__ bool tile_single(const Tiles& T, TileCtx& c) {
+  c.pb = blockIdx.x;
+  return tile_of(T, c.tx, c.ty, c.tz);
+}
+
+__device__ __forceinline__ bool tile_of_index(const Tiles& T, int t, TileCtx& c) {
+  const int per = T.grid >> 3;
+  c.pb = (t % per) * 8 + t / per;
+  c.tx = t % T.ntx;
+  c.ty = (t / T.ntx) % T.nty;
+  c.tz = t / (T.ntx * T.nty);
+  return t < T.total;
+}
+
+// Arguments of a batched launch over up to MAXB grids, passed by value (in
+// the kernel-argument segment, read with scalar loads like a single
+// launch's): grid i owns the blocks [start[i], start[i + 1]).
+constexpr int MAXB = 8;
+template <class A>
+struct Pack {
+  A a[MAXB];
+  int start[MAXB + 1];
+  int n;
+};
+
+// Grid and tile index of this block in a batched launch (false past the
+// end); block b takes entry (b mod 8) * (blocks / 8) + b / 8, so that each
+// XCD gets a contiguous range of entries.
+template <class A>
+__device__ __forceinline__ bool pack_entry(const Pack<A>& p, int& g, int& t) {
+  const int per = gridDim.x >> 3;
+  const int b = blockIdx.x;
+  const int q = (b & 7) * per + (b >> 3);
+  if (q >= p.start[p.n]) return false;
+  int i = 0;
+  while (q >= p.start[i + 1]) ++i;
+  g = i;
+  t = q - p.start[i];
+  return true;
+}
+
+// Defines the single kernel NAME(ARGS a) and the batched kernel
+// NAME_batch(Pack<ARGS> p) around BODY(const ARGS&, const TileCtx&, bool
+// valid); TPL / TPLA are the parenthesised template parameters / arguments of
+// the kernels and ARGA the argument struct's template arguments; with PAD,
+// blocks of tiles past the end still run the body (reductions store a zero
+// partial there).
+#define NFVM_PASS(...) __VA_ARGS__
+#define NFVM_TILE_KERNELS(NAME, BODY, ARGS, ARGA, TPL, TPLA, THREADS, PAD)                    \
+  template <NFVM_PASS TPL>                                                                    \
+  __global__ __launch_bounds__(THREADS) void NAME(ARGS<NFVM_PASS ARGA> a) {                   \
+    TileCtx c;                                                                                \
+    const bool v = tile_single(a.T, c);                                                       \
+    if (v || PAD) BODY<NFVM_PASS TPLA>(a, c, v);                                              \
+  }                                                                                           \
+  template <NFVM_PASS TPL>                                                                    \
+  __global__ __launch_bounds__(THREADS) void NAME##_batch(Pack<ARGS<NFVM_PASS ARGA>> p) {     \
+    int gi, t;                                                                                \
+    if (!pack_entry(p, gi, t)) return;                                                        \
+    const ARGS<NFVM_PASS ARGA>& a = p.a[gi];                                                  \
+    TileCtx c;                                                                                \
+    const bool v = tile_of_index(a.T, t, c);                                                  \
+    if (v || PAD) BODY<NFVM_PASS TPLA>(a, c, v);                                              \
+  }
+
 // A x and the diagonal at cell P, z neighbours given (the walking kernels
 // keep them in registers).
 template <class S, class C>
@@ -184,19 +271,31 @@ __device__ __forceinline__ C diag_at(const LevelView& L, uint8_t cl, int P) {
 }
 
 // ---- damped Jacobi sweep: x_out = x_in + w (b - A x_in) / D -------------------
+template <class S, class C>
+struct SmoothArgs {
+  LevelView L;
+  Tiles T;
+  const S* xin;
+  S* xout;
+  const S* b;
+  C wj;
+  const double* ctl;
+};
+
 // Each thread walks cz planes of one column with x(k-1), x(k), x(k+1) in
 // registers; in-plane neighbours come through the cache.
 template <class S, class C, bool ZERO>
-__global__ __launch_bounds__(MBS) void k_smooth(LevelView L, Tiles T, const S* __restrict__ xin,
-                                                S* __restrict__ xout, const S* __restrict__ b,
-                                                C wj, const double* __restrict__ ctl) {
-  if (ctl[S_DONE] != 0.0) return;
-  int tx, ty, tz;
-  if (!tile_of(T, tx, ty, tz)) return;
+__device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const TileCtx& c, bool) {
+  if (a.ctl[S_DONE] != 0.0) return;
+  const LevelView& L = a.L;
+  const S* __restrict__ xin = a.xin;
+  S* __restrict__ xout = a.xout;
+  const S* __restrict__ b = a.b;
+  const C wj = a.wj;
   const Geom& g = L.g;
-  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+  const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
-  const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+  const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
   const bool d3 = g.dim == 3;
   int P = g.idx(i, j, k0);
   C xm = 0, xc = 0;
@@ -222,22 +321,24 @@ __global__ __launch_bounds__(MBS) void k_smooth(LevelView L, Tiles T, const S* _
     xc = xp;
   }
 }
+NFVM_TILE_KERNELS(k_smooth, smooth_body, SmoothArgs, (S, C), (class S, class C, bool ZERO),
+                  (S, C, ZERO), MBS, false)
 
 // Level-0 sweep from face codes: no branch on the cell kind, and the loads of
 // two planes are issued before their arithmetic.
 template <class S, class C, bool ZERO>
-__global__ __launch_bounds__(MBS) void k_smooth_code(LevelView L, Tiles T,
-                                                     const S* __restrict__ xin,
-                                                     S* __restrict__ xout,
-                                                     const S* __restrict__ b, C wj,
-                                                     const double* __restrict__ ctl) {
-  if (ctl[S_DONE] != 0.0) return;
-  int tx, ty, tz;
-  if (!tile_of(T, tx, ty, tz)) return;
+__device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, const TileCtx& c,
+                                                 bool) {
+  if (a.ctl[S_DONE] != 0.0) return;
+  const LevelView& L = a.L;
+  const S* __restrict__ xin = a.xin;
+  S* __restrict__ xout = a.xout;
+  const S* __restrict__ b = a.b;
+  const C wj = a.wj;
   const Geom& g = L.g;
-  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+  const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
-  const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+  const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
   const bool d3 = g.dim == 3;
   int P = g.idx(i, j, k0);
   if (ZERO) {
@@ -273,26 +374,31 @@ __global__ __launch_bounds__(MBS) void k_smooth_code(LevelView L, Tiles T,
     if (cd != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
   }
 }
+NFVM_TILE_KERNELS(k_smooth_code, smooth_code_body, SmoothArgs, (S, C),
+                  (class S, class C, bool ZERO), (S, C, ZERO), MBS, false)
+
+template <class S, class C>
+SmoothArgs<S, C> smooth_args(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
+                             const double* ctl) {
+  return SmoothArgs<S, C>{view(l),      lvl_tiles(l, from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH),
+                          (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl};
+}
 
 template <class S, class C>
 void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                    const double* ctl, hipStream_t s) {
-  const Tiles T = lvl_tiles(l, from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH);
+  const SmoothArgs<S, C> a = smooth_args<S, C>(l, xin, xout, wj, from_zero, ctl);
+  const dim3 G(a.T.grid), B(MBX, MBY);
   if (l.code) {
     if (from_zero)
-      NFVM_LAUNCH((k_smooth_code<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s,
-                         view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
+      NFVM_LAUNCH((k_smooth_code<S, C, true>), G, B, 0, s, a);
     else
-      NFVM_LAUNCH((k_smooth_code<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s,
-                         view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
-    return;
+      NFVM_LAUNCH((k_smooth_code<S, C, false>), G, B, 0, s, a);
+  } else if (from_zero) {
+    NFVM_LAUNCH((k_smooth<S, C, true>), G, B, 0, s, a);
+  } else {
+    NFVM_LAUNCH((k_smooth<S, C, false>), G, B, 0, s, a);
   }
-  if (from_zero)
-    NFVM_LAUNCH((k_smooth<S, C, true>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
-                       (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
-  else
-    NFVM_LAUNCH((k_smooth<S, C, false>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l), T,
-                       (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl);
 }
 
 // ---- residual and restriction: b_c = mean over the 2^dim children of (b - A x)
@@ -300,22 +406,33 @@ void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool 
 // workgroup), walking fine planes in pairs; the 2 x 2 in-plane sum uses a
 // lane exchange (x) and LDS (y).  Tiles count coarse planes along z.
 template <class S, class C, class SC>
-__global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, Tiles T,
-                                                        const S* __restrict__ x,
-                                                        const S* __restrict__ b, LevelView Cl,
-                                                        SC* __restrict__ bc,
-                                                        SC* __restrict__ zc, C wj,
-                                                        const double* __restrict__ ctl) {
-  if (ctl[S_DONE] != 0.0) return;
+struct RestrictArgs {
+  LevelView F;
+  Tiles T;  // fine columns, coarse planes
+  const S* x;
+  const S* b;
+  LevelView Cl;
+  SC* bc;
+  SC* zc;  // coarse level's first sweep from zero (null: not fused)
+  C wj;
+  const double* ctl;
+};
+
+template <class S, class C, class SC>
+__device__ __forceinline__ void restrict_body(const RestrictArgs<S, C, SC>& a, const TileCtx& c,
+                                              bool) {
+  if (a.ctl[S_DONE] != 0.0) return;  // uniform over the workgroup
   __shared__ C sh[MBY][MBX];
-  int tx, ty, tz;
-  if (!tile_of(T, tx, ty, tz)) return;  // uniform over the workgroup
+  const LevelView& F = a.F;
+  const LevelView& Cl = a.Cl;
+  const S* __restrict__ x = a.x;
+  const S* __restrict__ b = a.b;
   const Geom& g = F.g;
   const int lx = threadIdx.x, ly = threadIdx.y;
-  const int i = tx * MBX + lx, j = ty * MBY + ly;
+  const int i = c.tx * MBX + lx, j = c.ty * MBY + ly;
   const bool in = i < g.nx && j < g.ny;
   const bool d3 = g.dim == 3;
-  const int K0 = tz * T.cz, K1 = min(Cl.g.nz, K0 + T.cz);
+  const int K0 = c.tz * a.T.cz, K1 = min(Cl.g.nz, K0 + a.T.cz);
   const int kz = d3 ? 2 : 1;
   int P = in ? g.idx(i, j, kz * K0) : 0;
   C xm = 0, xc = 0;
@@ -325,7 +442,7 @@ __global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, Tiles T,
   }
   for (int K = K0; K < K1; ++K) {
     C r = 0;
-    for (int c = 0; c < kz; ++c, P += g.sxy) {
+    for (int cc = 0; cc < kz; ++cc, P += g.sxy) {
       C xp = 0;
       if (in) {
         if (d3) xp = St<S, C>::ld(x + P + g.sxy);
@@ -354,23 +471,38 @@ __global__ __launch_bounds__(MBS) void k_resid_restrict(LevelView F, Tiles T,
       const int PC = Cl.g.idx(i >> 1, j >> 1, K);
       const uint8_t ccl = Cl.cls[PC];
       if (ccl != MG_INACTIVE) {
-        SC* dst = bc + PC;
+        SC* dst = a.bc + PC;
         St<SC, C>::st(dst, (sh[ly][lx] + sh[ly + 1][lx]) * (C)(d3 ? 0.125 : 0.25));
         // first pre-smoothing sweep (from zero) of the coarse level
-        if (zc) St<SC, C>::st(zc + PC, wj * St<SC, C>::ld(dst) / diag_at<C>(Cl, ccl, PC));
+        if (a.zc)
+          St<SC, C>::st(a.zc + PC, a.wj * St<SC, C>::ld(dst) / diag_at<C>(Cl, ccl, PC));
       }
     }
     __syncthreads();
   }
 }
+NFVM_TILE_KERNELS(k_resid_restrict, restrict_body, RestrictArgs, (S, C, SC),
+                  (class S, class C, class SC), (S, C, SC), MBS, false)
+
+template <class S, class C, class SC>
+RestrictArgs<S, C, SC> restrict_args(const Level& f, const Level& c, const double* ctl, void* zc,
+                                     double wj) {
+  return RestrictArgs<S, C, SC>{view(f),
+                                make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_RESTRICT]),
+                                (const S*)f.x[f.cur],
+                                (const S*)f.b,
+                                view(c),
+                                (SC*)c.b,
+                                (SC*)zc,
+                                (C)wj,
+                                ctl};
+}
 
 template <class S, class C, class SC>
 void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s,
                            void* zc, double wj) {
-  const Tiles T = make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_RESTRICT]);
-  NFVM_LAUNCH((k_resid_restrict<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f),
-                     T, (const S*)f.x[f.cur], (const S*)f.b, view(c), (SC*)c.b, (SC*)zc, (C)wj,
-                     ctl);
+  const RestrictArgs<S, C, SC> a = restrict_args<S, C, SC>(f, c, ctl, zc, wj);
+  NFVM_LAUNCH((k_resid_restrict<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
 }
 
 // ---- prolongation and correction: x_f += PROL(e_c) ------------------------------
@@ -446,17 +578,28 @@ __device__ C prolong_checked(const LevelView& Cl, const SC* __restrict__ e, int 
 // the padded array (one ghost layer) and hold finite values (ghost and
 // inactive cells are 0), and are used only when the cell is marked full.
 template <class S, class C, class SC>
-__global__ __launch_bounds__(MBS) void k_prolong(LevelView F, Tiles T, S* __restrict__ x,
-                                                 LevelView Cl, const SC* __restrict__ e,
-                                                 const double* __restrict__ ctl) {
-  if (ctl[S_DONE] != 0.0) return;
-  int tx, ty, tz;
-  if (!tile_of(T, tx, ty, tz)) return;
-  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+struct ProlongArgs {
+  LevelView F;
+  Tiles T;  // fine columns, coarse planes
+  S* x;
+  LevelView Cl;
+  const SC* e;
+  const double* ctl;
+};
+
+template <class S, class C, class SC>
+__device__ __forceinline__ void prolong_body(const ProlongArgs<S, C, SC>& a, const TileCtx& c,
+                                             bool) {
+  if (a.ctl[S_DONE] != 0.0) return;
+  const LevelView& F = a.F;
+  const LevelView& Cl = a.Cl;
+  S* __restrict__ x = a.x;
+  const SC* __restrict__ e = a.e;
+  const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
   if (i >= F.g.nx || j >= F.g.ny) return;
   const Geom& cg = Cl.g;
   const bool d3 = cg.dim == 3;
-  const int K0 = tz * T.cz, K1 = min(cg.nz, K0 + T.cz);
+  const int K0 = c.tz * a.T.cz, K1 = min(cg.nz, K0 + a.T.cz);
   const int sx = (i & 1) ? 1 : -1, oy = (j & 1) ? cg.sx : -cg.sx;
   const C w3 = (C)0.75, w1 = (C)0.25;
   int PC = cg.idx(i >> 1, j >> 1, K0);
@@ -470,13 +613,13 @@ __global__ __launch_bounds__(MBS) void k_prolong(LevelView F, Tiles T, S* __rest
   for (int K = K0; K < K1; ++K, PC += cg.sxy) {
     const C yp = d3 ? plane(PC + cg.sxy) : (C)0;
     const bool full = Cl.full[PC] != 0;
-    for (int c = 0; c < (d3 ? 2 : 1); ++c) {
-      const int k = d3 ? 2 * K + c : 0;
+    for (int cc = 0; cc < (d3 ? 2 : 1); ++cc) {
+      const int k = d3 ? 2 * K + cc : 0;
       const int P = F.g.idx(i, j, k);
       if (F.cls[P] == MG_INACTIVE) continue;
       C Z;
       if (full)
-        Z = d3 ? w3 * yc + w1 * (c ? yp : ym) : yc;
+        Z = d3 ? w3 * yc + w1 * (cc ? yp : ym) : yc;
       else
         Z = prolong_checked<C, SC>(Cl, e, i, j, k);
       St<S, C>::st(x + P, St<S, C>::ld(x + P) + Z);
@@ -485,41 +628,69 @@ __global__ __launch_bounds__(MBS) void k_prolong(LevelView F, Tiles T, S* __rest
     yc = yp;
   }
 }
+NFVM_TILE_KERNELS(k_prolong, prolong_body, ProlongArgs, (S, C, SC), (class S, class C, class SC),
+                  (S, C, SC), MBS, false)
+
+template <class S, class C, class SC>
+ProlongArgs<S, C, SC> prolong_args(const Level& f, const Level& c, const double* ctl) {
+  // tiles over fine columns and coarse planes
+  return ProlongArgs<S, C, SC>{view(f), make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_PROLONG]),
+                               (S*)f.x[f.cur], view(c), (const SC*)c.x[c.cur], ctl};
+}
 
 template <class S, class C, class SC>
 void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
-  // tiles over fine columns and coarse planes
-  const Tiles T = make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_PROLONG]);
-  NFVM_LAUNCH((k_prolong<S, C, SC>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(f), T,
-                     (S*)f.x[f.cur], view(c), (const SC*)c.x[c.cur], ctl);
+  const ProlongArgs<S, C, SC> a = prolong_args<S, C, SC>(f, c, ctl);
+  NFVM_LAUNCH((k_prolong<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
 }
 
 // ---- coarsest level: x = A^-1 b with the dense inverse, one workgroup -------------
 template <class SC, class C>
-__global__ __launch_bounds__(256) void k_coarse_solve(const SC* __restrict__ b, SC* __restrict__ x,
-                                                      const int* __restrict__ cmap,
-                                                      const int* __restrict__ ncount,
-                                                      const double* __restrict__ ainv, int max_n,
-                                                      const double* __restrict__ ctl) {
-  if (ctl[S_DONE] != 0.0) return;
+struct CoarseArgs {
+  const SC* b;
+  SC* x;
+  const int* cmap;
+  const int* ncount;
+  const double* ainv;
+  int max_n;
+  const double* ctl;
+};
+
+template <class SC, class C>
+__device__ __forceinline__ void coarse_body(const CoarseArgs<SC, C>& A) {
+  if (A.ctl[S_DONE] != 0.0) return;
   __shared__ C bs[512];
-  const int n = *ncount;
-  if (n > max_n) return;
-  for (int a = threadIdx.x; a < n; a += blockDim.x) bs[a] = St<SC, C>::ld(b + cmap[a]);
+  const int n = *A.ncount;
+  if (n > A.max_n) return;
+  for (int a = threadIdx.x; a < n; a += blockDim.x) bs[a] = St<SC, C>::ld(A.b + A.cmap[a]);
   __syncthreads();
   for (int a = threadIdx.x; a < n; a += blockDim.x) {
     C s = 0;
-    const double* row = ainv + (size_t)a * n;
+    const double* row = A.ainv + (size_t)a * n;
     for (int q = 0; q < n; ++q) s += (C)row[q] * bs[q];
-    St<SC, C>::st(x + cmap[a], s);
+    St<SC, C>::st(A.x + A.cmap[a], s);
   }
+}
+template <class SC, class C>
+__global__ __launch_bounds__(256) void k_coarse_solve(CoarseArgs<SC, C> a) {
+  coarse_body<SC, C>(a);
+}
+template <class SC, class C>
+__global__ __launch_bounds__(256) void k_coarse_solve_batch(Pack<CoarseArgs<SC, C>> p) {
+  coarse_body<SC, C>(p.a[blockIdx.x]);
+}
+
+template <class SC, class C>
+CoarseArgs<SC, C> coarse_args(const Level& c, const int* cmap, const int* ncount,
+                              const double* ainv, int max_n, const double* ctl) {
+  return CoarseArgs<SC, C>{(const SC*)c.b, (SC*)c.x[c.cur], cmap, ncount, ainv, max_n, ctl};
 }
 
 template <class SC, class C>
 void launch_coarse_solve(const Level& c, const int* cmap, const int* ncount, const double* ainv,
                          int max_n, const double* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_solve<SC, C>), dim3(1), dim3(256), 0, s, (const SC*)c.b,
-                     (SC*)c.x[c.cur], cmap, ncount, ainv, max_n, ctl);
+  hipLaunchKernelGGL((k_coarse_solve<SC, C>), dim3(1), dim3(256), 0, s,
+                     coarse_args<SC, C>(c, cmap, ncount, ainv, max_n, ctl));
 }
 
 template <class S>
@@ -664,19 +835,33 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
 // beta^2 (p_prev, q_prev), so one stencil pass per iteration serves both the
 // direction and the step length.
 template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_apply(LevelView L, Tiles T, const S* __restrict__ z,
-                                                   const O* __restrict__ r,
-                                                   const O* __restrict__ q, O* __restrict__ w,
-                                                   RedBuf red) {
+struct ApplyArgs {
+  LevelView L;
+  Tiles T;
+  const S* z;
+  const O* r;
+  const O* q;
+  O* w;
+  RedBuf red;
+};
+
+template <class O, class S>
+__device__ __forceinline__ void apply_body(const ApplyArgs<O, S>& a, const TileCtx& c,
+                                           bool valid) {
+  const RedBuf& red = a.red;
   if (red.out[S_DONE] != 0.0) return;
-  int tx, ty, tz;
+  const LevelView& L = a.L;
+  const S* __restrict__ z = a.z;
+  const O* __restrict__ r = a.r;
+  const O* __restrict__ q = a.q;
+  O* __restrict__ w = a.w;
   double zr = 0.0, zq = 0.0, zw = 0.0;
-  if (tile_of(T, tx, ty, tz)) {
+  if (valid) {
     const Geom& g = L.g;
-    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+    const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
     if (i < g.nx && j < g.ny) {
       const bool d3 = g.dim == 3;
-      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+      const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
       int P = g.idx(i, j, k0);
       O zm = d3 ? St<S, O>::ld(z + P - g.sxy) : (O)0, zc = St<S, O>::ld(z + P);
       for (int k = k0; k < k1; ++k, P += g.sxy) {
@@ -696,16 +881,26 @@ __global__ __launch_bounds__(MBS) void k_fcg_apply(LevelView L, Tiles T, const S
     }
   }
   double vv[3] = {zr, zq, zw};
-  block_partial<3, R_SUM, MBS>(vv, red);
+  block_partial<3, R_SUM, MBS>(vv, red, c.pb);
 }
+NFVM_TILE_KERNELS(k_fcg_apply, apply_body, ApplyArgs, (O, S), (class O, class S), (O, S), MBS,
+                  true)
 
 constexpr int FIN_NV3 = 3;
 
+// Arguments of the one-workgroup finalising kernels (one workgroup per grid
+// in a batched launch).
+struct FinArgs {
+  RedBuf red;
+  int nb;
+};
+
 // (z, r), (z, q_prev), (z, w); beta, (p, q) and alpha of this iteration.
-__global__ __launch_bounds__(FIN) void k_fin_apply(RedBuf red, int nb) {
+__device__ __forceinline__ void fin_apply_body(const FinArgs& f) {
+  const RedBuf& red = f.red;
   if (red.out[S_DONE] != 0.0) return;
   double acc[FIN_NV3];
-  fin_sum<FIN_NV3>(red, nb, acc);
+  fin_sum<FIN_NV3>(red, f.nb, acc);
   if (threadIdx.x == 0) {
     const double zr = acc[0], zq = acc[1], zw = acc[2];
     const bool first = red.out[S_ITER] == 0.0;
@@ -720,34 +915,62 @@ __global__ __launch_bounds__(FIN) void k_fin_apply(RedBuf red, int nb) {
     red.out[S_ALPHA] = zr / pq;
   }
 }
+__global__ __launch_bounds__(FIN) void k_fin_apply(FinArgs f) { fin_apply_body(f); }
+__global__ __launch_bounds__(FIN) void k_fin_apply_batch(Pack<FinArgs> f) {
+  fin_apply_body(f.a[blockIdx.x]);
+}
+
+template <class O, class S>
+ApplyArgs<O, S> apply_args(const Level& l0, const O* r, const O* q, O* w, const RedBuf& red) {
+  return ApplyArgs<O, S>{view(l0), lvl_tiles(l0, TK_APPLY), (const S*)l0.x[l0.cur], r, q, w, red};
+}
 
 template <class O, class S>
 void launch_fcg_apply(const Level& l0, const O* r, const O* q, O* w, const RedBuf& red,
                       hipStream_t s, bool fin) {
-  const Tiles T = lvl_tiles(l0, TK_APPLY);
-  NFVM_LAUNCH((k_fcg_apply<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T,
-              (const S*)l0.x[l0.cur], r, q, w, red);
-  if (fin) hipLaunchKernelGGL(k_fin_apply, dim3(1), dim3(FIN), 0, s, red, T.grid);
+  const ApplyArgs<O, S> a = apply_args<O, S>(l0, r, q, w, red);
+  NFVM_LAUNCH((k_fcg_apply<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  if (fin) hipLaunchKernelGGL(k_fin_apply, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
 
 // p = z + beta p, q = w + beta q, x += alpha p, r -= alpha q, ||r||^2, the
 // next V-cycle's right-hand side (and first level-0 sweep).
 template <class O, class S>
-__global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, Tiles T, O* __restrict__ x,
-                                                    O* __restrict__ r, O* __restrict__ p,
-                                                    O* __restrict__ q, const O* __restrict__ w,
-                                                    const S* __restrict__ z, S* __restrict__ b0,
-                                                    S* __restrict__ z0, S wj, RedBuf red) {
+struct UpdateArgs {
+  LevelView L;
+  Tiles T;
+  O* x;
+  O* r;
+  O* p;
+  O* q;
+  const O* w;
+  const S* z;
+  S* b0;
+  S* z0;
+  S wj;
+  RedBuf red;
+};
+
+template <class O, class S>
+__device__ __forceinline__ void update_body(const UpdateArgs<O, S>& A, const TileCtx& c,
+                                            bool valid) {
+  const RedBuf& red = A.red;
   if (red.out[S_DONE] != 0.0) return;
+  const LevelView& L = A.L;
+  O* __restrict__ x = A.x;
+  O* __restrict__ r = A.r;
+  O* __restrict__ p = A.p;
+  O* __restrict__ q = A.q;
+  const O* __restrict__ w = A.w;
+  const S* __restrict__ z = A.z;
   const bool first = red.out[S_ITER] == 0.0;
   const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA];
-  int tx, ty, tz;
   double rr = 0.0;
-  if (tile_of(T, tx, ty, tz)) {
+  if (valid) {
     const Geom& g = L.g;
-    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+    const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
     if (i < g.nx && j < g.ny) {
-      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+      const int k0 = c.tz * A.T.cz, k1 = min(g.nz, k0 + A.T.cz);
       for (int k = k0; k < k1; ++k) {
         const int P = g.idx(i, j, k);
         const uint32_t cd = L.code[P];
@@ -760,20 +983,23 @@ __global__ __launch_bounds__(MBS) void k_fcg_update(LevelView L, Tiles T, O* __r
         x[P] += a * pP;
         const O rP = r[P] - a * qP;
         r[P] = rP;
-        zero_sweep<O, S>(L, P, cd, rP, b0, z0, wj);
+        zero_sweep<O, S>(L, P, cd, rP, A.b0, A.z0, A.wj);
         rr += (double)rP * (double)rP;
       }
     }
   }
   double vv[1] = {rr};
-  block_partial<1, R_SUM, MBS>(vv, red);
+  block_partial<1, R_SUM, MBS>(vv, red, c.pb);
 }
+NFVM_TILE_KERNELS(k_fcg_update, update_body, UpdateArgs, (O, S), (class O, class S), (O, S), MBS,
+                  true)
 
 // ||r||^2, one more iteration done, stopping rule
-__global__ __launch_bounds__(FIN) void k_fin_update(RedBuf red, int nb) {
+__device__ __forceinline__ void fin_update_body(const FinArgs& f) {
+  const RedBuf& red = f.red;
   if (red.out[S_DONE] != 0.0) return;
   double acc[1];
-  fin_sum<1>(red, nb, acc);
+  fin_sum<1>(red, f.nb, acc);
   if (threadIdx.x == 0) {
     red.out[S_RR] = acc[0];
     red.out[S_ITER] += 1.0;
@@ -781,14 +1007,24 @@ __global__ __launch_bounds__(FIN) void k_fin_update(RedBuf red, int nb) {
     publish(red, S_RR, S_ITER, S_DONE);
   }
 }
+__global__ __launch_bounds__(FIN) void k_fin_update(FinArgs f) { fin_update_body(f); }
+__global__ __launch_bounds__(FIN) void k_fin_update_batch(Pack<FinArgs> f) {
+  fin_update_body(f.a[blockIdx.x]);
+}
+
+template <class O, class S>
+UpdateArgs<O, S> update_args(const Level& l0, O* x, O* r, O* p, O* q, const O* w,
+                             const RedBuf& red, void* z0, double wj) {
+  return UpdateArgs<O, S>{view(l0), lvl_tiles(l0, TK_UPDATE), x, r, p, q, w,
+                          (const S*)l0.x[l0.cur], (S*)l0.b, (S*)z0, (S)wj, red};
+}
 
 template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const O* w, const RedBuf& red,
                        hipStream_t s, bool fin, void* z0, double wj) {
-  const Tiles T = lvl_tiles(l0, TK_UPDATE);
-  NFVM_LAUNCH((k_fcg_update<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, x, r, p, q,
-              w, (const S*)l0.x[l0.cur], (S*)l0.b, (S*)z0, (S)wj, red);
-  if (fin) hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, red, T.grid);
+  const UpdateArgs<O, S> a = update_args<O, S>(l0, x, r, p, q, w, red, z0, wj);
+  NFVM_LAUNCH((k_fcg_update<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  if (fin) hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
 
 // ---- deterministic finalisation of block partials ---------------------------------
@@ -983,9 +1219,9 @@ template void launch_bottom_image<double>(const Bottom&, void*, hipStream_t);
 template void launch_bottom_image<float>(const Bottom&, void*, hipStream_t);
 
 template <class SC, class C>
-__global__ __launch_bounds__(1024) void k_bottom(Bottom B, const SC* __restrict__ btop,
-                                                 SC* __restrict__ xtop,
-                                                 const double* __restrict__ ctl) {
+__device__ __forceinline__ void bottom_body(const Bottom& B, const SC* __restrict__ btop,
+                                            SC* __restrict__ xtop,
+                                            const double* __restrict__ ctl) {
   if (ctl[S_DONE] != 0.0) return;
   const int t = threadIdx.x, NT = blockDim.x;
   const int nl = B.nlev;
@@ -1183,6 +1419,28 @@ __global__ __launch_bounds__(1024) void k_bottom(Bottom B, const SC* __restrict_
   }
 }
 
+// One bottom solve per workgroup: the single launch takes the descriptor as a
+// kernel argument, the batched launch one descriptor per workgroup.
+struct BottomArgsBase {
+  Bottom B;
+  const void* btop;
+  void* xtop;
+  const double* ctl;
+};
+
+template <class SC, class C>
+__global__ __launch_bounds__(1024) void k_bottom(Bottom B, const SC* __restrict__ btop,
+                                                 SC* __restrict__ xtop,
+                                                 const double* __restrict__ ctl) {
+  bottom_body<SC, C>(B, btop, xtop, ctl);
+}
+
+template <class SC, class C>
+__global__ __launch_bounds__(1024) void k_bottom_batch(const BottomArgsBase* __restrict__ a) {
+  const BottomArgsBase& e = a[blockIdx.x];
+  bottom_body<SC, C>(e.B, (const SC*)e.btop, (SC*)e.xtop, e.ctl);
+}
+
 // Dynamic LDS bytes one bottom workgroup may use on the current device: the
 // device's LDS per workgroup less the kernel's static LDS (its level table);
 // dynamic LDS above 64 KiB is enabled per kernel where the device has it.
@@ -1200,8 +1458,10 @@ size_t bottom_lds_limit() {
   const int dyn = lim - stat;
   if (dyn <= 0) return 0;
   if (lim > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_bottom<SC, C>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) {
+      (hipFuncSetAttribute((const void*)k_bottom<SC, C>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess ||
+       hipFuncSetAttribute((const void*)k_bottom_batch<SC, C>,
+                           hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess)) {
     (void)hipGetLastError();
     return (size_t)(64 * 1024 - stat);
   }
@@ -1223,6 +1483,282 @@ template void launch_bottom<float, float>(const Bottom&, const void*, void*, con
                                           hipStream_t);
 template void launch_bottom<bf16, float>(const Bottom&, const void*, void*, const double*,
                                          hipStream_t);
+
+// ---- batched iteration plan ---------------------------------------------------------
+namespace {
+
+size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// Argument structs of one kernel for the grids of one batched launch.
+template <class A>
+using Group = std::vector<A>;
+
+template <class V>
+size_t put(BatchOps& o, const std::vector<V>& v) {
+  const size_t off = al16(o.blob.size());
+  o.blob.resize(off + v.size() * sizeof(V));
+  if (!v.empty()) memcpy(o.blob.data() + off, v.data(), v.size() * sizeof(V));
+  return off;
+}
+
+// Tile kernels: one grid takes the single kernel (T.grid blocks); more grids
+// take the batched kernel, MAXB grids per launch, ceil(blocks / 8) * 8
+// workgroups.  With pad, a grid's padding tiles are part of its range (its
+// reduction partials are all written).
+template <class A, class K1, class KB>
+void emit_tiles(BatchOps& o, const Group<A>& g, K1 single, KB batched, bool pad) {
+  if (g.size() == 1) {
+    const A a = g[0];
+    o.ops.push_back([=](const unsigned char*, hipStream_t s) {
+      hipLaunchKernelGGL(single, dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+    });
+    return;
+  }
+  for (size_t i0 = 0; i0 < g.size(); i0 += MAXB) {
+    Pack<A> p;
+    memset(&p, 0, sizeof p);
+    p.n = (int)std::min(g.size() - i0, (size_t)MAXB);
+    p.start[0] = 0;
+    for (int i = 0; i < p.n; ++i) {
+      p.a[i] = g[i0 + i];
+      p.start[i + 1] = p.start[i] + (pad ? p.a[i].T.grid : p.a[i].T.total);
+    }
+    const int blocks = (p.start[p.n] + 7) / 8 * 8;
+    o.ops.push_back([=](const unsigned char*, hipStream_t s) {
+      hipLaunchKernelGGL(batched, dim3(blocks), dim3(MBX, MBY), 0, s, p);
+    });
+  }
+}
+
+// One workgroup per grid, arguments by value (MAXB grids per launch).
+template <class A, class KB>
+void emit_packed_blocks(BatchOps& o, const Group<A>& g, KB kern, int threads) {
+  for (size_t i0 = 0; i0 < g.size(); i0 += MAXB) {
+    Pack<A> p;
+    memset(&p, 0, sizeof p);
+    p.n = (int)std::min(g.size() - i0, (size_t)MAXB);
+    for (int i = 0; i < p.n; ++i) p.a[i] = g[i0 + i];
+    const int n = p.n;
+    o.ops.push_back([=](const unsigned char*, hipStream_t s) {
+      hipLaunchKernelGGL(kern, dim3(n), dim3(threads), 0, s, p);
+    });
+  }
+}
+
+// One workgroup per grid, arguments in the plan's device memory (the bottom
+// solver's descriptors are too large for the kernel-argument segment).
+template <class A, class K>
+void emit_blocks(BatchOps& o, const std::vector<A>& args, K kern, int threads, size_t lds) {
+  if (args.empty()) return;
+  const size_t ao = put(o, args);
+  const int n = (int)args.size();
+  o.ops.push_back([=](const unsigned char* base, hipStream_t s) {
+    hipLaunchKernelGGL(kern, dim3(n), dim3(threads), lds, s, (const A*)(base + ao));
+  });
+}
+
+// Sweep groups of one level, by kernel: face-code or class-byte sweep, from
+// zero or not.
+template <class S, class C>
+struct SweepGroups {
+  Group<SmoothArgs<S, C>> g[2][2];  // [code][zero]
+  void add(const Level& l, double wj, bool zero, const double* ctl) {
+    const void* xin = zero ? nullptr : l.x[l.cur];
+    void* xout = zero ? l.x[0] : l.x[l.cur ^ 1];
+    g[l.code != nullptr][zero].push_back(smooth_args<S, C>(l, xin, xout, wj, zero, ctl));
+  }
+  void emit(BatchOps& o) const {
+    emit_tiles(o, g[0][0], k_smooth<S, C, false>, k_smooth_batch<S, C, false>, false);
+    emit_tiles(o, g[0][1], k_smooth<S, C, true>, k_smooth_batch<S, C, true>, false);
+    emit_tiles(o, g[1][0], k_smooth_code<S, C, false>, k_smooth_code_batch<S, C, false>, false);
+    emit_tiles(o, g[1][1], k_smooth_code<S, C, true>, k_smooth_code_batch<S, C, true>, false);
+  }
+};
+
+// Levels below the top whose V-cycle step is a regular one (not the
+// bottom solver's or the coarsest solve's).
+int stop_level(const MgGridDesc& d) { return d.bottom_top >= 0 ? d.bottom_top : d.L - 1; }
+
+// Sweep number s on level l of grid d (the same order as one grid's
+// recursive V-cycle): pre-smoothing when `pre`.
+template <class S, class C>
+void add_sweep(SweepGroups<S, C>& sg, MgGridDesc& d, int l, int s, bool pre) {
+  Level& v = d.lv[l];
+  const double* ctl = d.red.out;
+  if (pre) {
+    if (d.nu1 == 0) return;
+    if (s == 0) {
+      if (d.zero[l]) {
+        v.cur = 0;  // written by the kernel that formed this level's right-hand side
+      } else {
+        sg.add(v, d.wj, true, ctl);
+        v.cur = 0;
+      }
+      return;
+    }
+    if (s >= d.nu1) return;
+  } else if (s >= d.nu2) {
+    return;
+  }
+  sg.add(v, d.wj, false, ctl);
+  v.cur ^= 1;
+}
+
+}  // namespace
+
+template <class O, class S0, class SC, class C>
+void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
+  int top = 0, nu1 = 0, nu2 = 0;
+  for (int i = 0; i < n; ++i) {
+    top = std::max(top, stop_level(G[i]));
+    nu1 = std::max(nu1, G[i].nu1);
+    nu2 = std::max(nu2, G[i].nu2);
+  }
+  // zero-filled levels (no pre-smoothing): one launch per grid, not batched
+  auto fill = [&](MgGridDesc& d, int l) {
+    Level& v = d.lv[l];
+    v.cur = 0;
+    const Level lv = v;
+    const double* ctl = d.red.out;
+    o.ops.push_back([=](const unsigned char*, hipStream_t s) {
+      if (l == 0)
+        launch_fill_zero<S0>(lv, lv.x[0], ctl, s);
+      else
+        launch_fill_zero<SC>(lv, lv.x[0], ctl, s);
+    });
+  };
+  // down: pre-smoothing and restriction, level by level
+  for (int l = 0; l < top; ++l) {
+    for (int s = 0; s < std::max(nu1, 1); ++s) {
+      SweepGroups<S0, C> g0;
+      SweepGroups<SC, C> gc;
+      for (int i = 0; i < n; ++i) {
+        if (l >= stop_level(G[i])) continue;
+        if (G[i].nu1 == 0) {
+          if (s == 0) fill(G[i], l);
+          continue;
+        }
+        if (l == 0)
+          add_sweep(g0, G[i], l, s, true);
+        else
+          add_sweep(gc, G[i], l, s, true);
+      }
+      g0.emit(o);
+      gc.emit(o);
+    }
+    Group<RestrictArgs<S0, C, SC>> r0;
+    Group<RestrictArgs<SC, C, SC>> rc;
+    for (int i = 0; i < n; ++i) {
+      MgGridDesc& d = G[i];
+      if (l >= stop_level(d)) continue;
+      if (l == 0) {
+        r0.push_back(restrict_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out, d.zero[1], d.wj));
+      } else {
+        rc.push_back(
+            restrict_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out, d.zero[l + 1], d.wj));
+      }
+    }
+    emit_tiles(o, r0, k_resid_restrict<S0, C, SC>, k_resid_restrict_batch<S0, C, SC>, false);
+    emit_tiles(o, rc, k_resid_restrict<SC, C, SC>, k_resid_restrict_batch<SC, C, SC>, false);
+  }
+  // bottom solver or coarsest solve of every grid
+  {
+    std::vector<BottomArgsBase> bo;
+    Group<CoarseArgs<S0, C>> c0;
+    Group<CoarseArgs<SC, C>> cc;
+    size_t lds = 0;
+    for (int i = 0; i < n; ++i) {
+      MgGridDesc& d = G[i];
+      if (d.bottom_top >= 0) {
+        Level& v = d.lv[d.bottom_top];
+        v.cur = 0;
+        bo.push_back(BottomArgsBase{*d.bot, v.b, v.x[0], d.red.out});
+        lds = std::max(lds, d.bot->lds_bytes);
+      } else {
+        Level& v = d.lv[d.L - 1];
+        v.cur = 0;
+        if (d.L == 1)
+          c0.push_back(coarse_args<S0, C>(v, d.cmap, d.ncount, d.ainv, d.coarse_max, d.red.out));
+        else
+          cc.push_back(coarse_args<SC, C>(v, d.cmap, d.ncount, d.ainv, d.coarse_max, d.red.out));
+      }
+    }
+    if (bo.size() == 1) {
+      const BottomArgsBase e = bo[0];
+      o.ops.push_back([=](const unsigned char*, hipStream_t s) {
+        hipLaunchKernelGGL((k_bottom<SC, C>), dim3(1), dim3(1024), e.B.lds_bytes, s, e.B,
+                           (const SC*)e.btop, (SC*)e.xtop, e.ctl);
+      });
+    } else {
+      emit_blocks(o, bo, k_bottom_batch<SC, C>, 1024, lds);
+    }
+    emit_packed_blocks(o, c0, k_coarse_solve_batch<S0, C>, 256);
+    emit_packed_blocks(o, cc, k_coarse_solve_batch<SC, C>, 256);
+  }
+  // up: prolongation and post-smoothing
+  for (int l = top - 1; l >= 0; --l) {
+    Group<ProlongArgs<S0, C, SC>> p0;
+    Group<ProlongArgs<SC, C, SC>> pc;
+    for (int i = 0; i < n; ++i) {
+      MgGridDesc& d = G[i];
+      if (l >= stop_level(d)) continue;
+      if (l == 0) {
+        p0.push_back(prolong_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out));
+      } else {
+        pc.push_back(prolong_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out));
+      }
+    }
+    emit_tiles(o, p0, k_prolong<S0, C, SC>, k_prolong_batch<S0, C, SC>, false);
+    emit_tiles(o, pc, k_prolong<SC, C, SC>, k_prolong_batch<SC, C, SC>, false);
+    for (int s = 0; s < nu2; ++s) {
+      SweepGroups<S0, C> g0;
+      SweepGroups<SC, C> gc;
+      for (int i = 0; i < n; ++i) {
+        if (l >= stop_level(G[i])) continue;
+        if (l == 0)
+          add_sweep(g0, G[i], l, s, false);
+        else
+          add_sweep(gc, G[i], l, s, false);
+      }
+      g0.emit(o);
+      gc.emit(o);
+    }
+  }
+  // CG: w = A z with its dot products, then the vector update
+  Group<ApplyArgs<O, S0>> ap;
+  Group<UpdateArgs<O, S0>> up;
+  Group<FinArgs> fa, fu;
+  for (int i = 0; i < n; ++i) {
+    MgGridDesc& d = G[i];
+    const auto a = apply_args<O, S0>(d.lv[0], (const O*)d.r, (const O*)d.q, (O*)d.w, d.red);
+    ap.push_back(a);
+    fa.push_back(FinArgs{d.red, a.T.grid});
+  }
+  for (int i = 0; i < n; ++i) {
+    MgGridDesc& d = G[i];
+    const auto a = update_args<O, S0>(d.lv[0], (O*)d.x, (O*)d.r, (O*)d.p, (O*)d.q,
+                                      (const O*)d.w, d.red, d.zero[0], d.wj);
+    up.push_back(a);
+    fu.push_back(FinArgs{d.red, a.T.grid});
+  }
+  emit_tiles(o, ap, k_fcg_apply<O, S0>, k_fcg_apply_batch<O, S0>, true);
+  if (n == 1)
+    o.ops.push_back([f = fa[0]](const unsigned char*, hipStream_t s) {
+      hipLaunchKernelGGL(k_fin_apply, dim3(1), dim3(FIN), 0, s, f);
+    });
+  else
+    emit_packed_blocks(o, fa, k_fin_apply_batch, FIN);
+  emit_tiles(o, up, k_fcg_update<O, S0>, k_fcg_update_batch<O, S0>, true);
+  if (n == 1)
+    o.ops.push_back([f = fu[0]](const unsigned char*, hipStream_t s) {
+      hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, f);
+    });
+  else
+    emit_packed_blocks(o, fu, k_fin_update_batch, FIN);
+}
+template void plan_fcg_iteration<double, double, double, double>(MgGridDesc*, int, BatchOps&);
+template void plan_fcg_iteration<float, float, float, float>(MgGridDesc*, int, BatchOps&);
+template void plan_fcg_iteration<double, float, bf16, float>(MgGridDesc*, int, BatchOps&);
 
 // ---- instantiations ------------------------------------------------------------
 #define INST_LEVEL(S, C)                                                                     \

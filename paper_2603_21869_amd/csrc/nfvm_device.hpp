@@ -79,11 +79,12 @@ __device__ __forceinline__ void block_tree(double (&v)[NV], double (*sh)[BS]) {
 // one-workgroup kernel (launch_finalize) then reduces the partials in a fixed
 // order, so the result does not depend on block scheduling.  Must be called
 // by every thread of every block.
+// (pb: the partial's index; by default the block's index in its launch)
 template <int NV, int OP, int BS>
-__device__ __forceinline__ void block_partial(double (&v)[NV], const RedBuf& red) {
+__device__ __forceinline__ void block_partial(double (&v)[NV], const RedBuf& red, int pb = -1) {
   __shared__ double sh[NV][BS];
   const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-  const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int b = pb >= 0 ? pb : blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   block_tree<NV, OP, BS>(v, sh);
   if (t == 0)
     for (int q = 0; q < NV; ++q) red.partial[(size_t)b * NV + q] = v[q];

@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 namespace nfvm {
 
 // Kernel-timing events for the next main-kernel launch of the calling thread
@@ -293,5 +296,36 @@ void launch_fcg_apply(const Level& l0, const O* r, const O* q, O* w, const RedBu
 template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const O* w, const RedBuf& red,
                        hipStream_t s, bool fin = true, void* z0 = nullptr, double wj = 0.0);
+
+// ---- batched iterations of several grids ----------------------------------------
+constexpr int MAX_LEVELS = 20;
+
+// What the batched CG iteration needs of one grid: its levels and V-cycle
+// settings, the coarsest solve, and the level-0 CG vectors (outer type O).
+struct MgGridDesc {
+  Level* lv;  // levels 0 .. L-1; cur is advanced as the iteration is laid out
+  int L, bottom_top, nu1, nu2;
+  double wj;
+  const Bottom* bot;  // when bottom_top >= 0
+  const int* cmap;
+  const int* ncount;
+  const double* ainv;
+  int coarse_max;
+  void* zero[MAX_LEVELS];  // buffer of level l's fused first sweep, or null
+  RedBuf red;
+  void *x, *r, *p, *q, *w;
+};
+
+// One flexible-CG iteration of several grids as a list of launches: per
+// level, one batched launch covers the tiles of every grid (one workgroup
+// per grid for the bottom solves and finalisers).  `blob` holds the argument
+// structs and tile lists; each op is called with the device address the
+// blob was copied to.
+struct BatchOps {
+  std::vector<unsigned char> blob;
+  std::vector<std::function<void(const unsigned char*, hipStream_t)>> ops;
+};
+template <class O, class S0, class SC, class C>
+void plan_fcg_iteration(MgGridDesc* grids, int n, BatchOps& out);
 
 }  // namespace nfvm

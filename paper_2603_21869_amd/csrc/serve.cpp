@@ -1,15 +1,22 @@
-// Serving loop: requests of different grid sizes are queued, admitted while
-// their summed device footprint stays inside the HBM budget and a slot is
-// free, and run on their own HIP streams so that admitted solves overlap on
-// the device.  A slot picks up the next admissible request as soon as its
-// previous one finishes (continuous admission at step boundaries); a finished
-// solve releases its device memory at once and keeps its fields on the host
-// until polled.
+// Serving loop: requests of different grid sizes are queued and admitted,
+// first fit in arrival order, while their summed device footprint stays
+// inside the HBM budget and fewer than max_slots grids run.  Admitted grids
+// run in up to three lanes, each a host thread with its own HIP stream and a
+// BatchRunner: per round, the CG iterations of all the lane's grids whose
+// pressure solve is under way run as batched launches (one launch per
+// multigrid kernel and level over the tiles of every grid), then one
+// synchronisation.  Lanes overlap on the device, so one lane's host work
+// (a synchronisation, a grid's creation or the download of its fields) does
+// not leave the device idle.  A grid whose solve converged goes on to its
+// next step at once; a request joins its lane at the next round after its
+// admission (continuous batching); a finished request releases its device
+// memory at once and keeps its fields on the host until polled.
 #include <math.h>
 #include <string.h>
 
 #include <chrono>
 #include <condition_variable>
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -70,48 +77,44 @@ struct nfvm_server {
     return nullptr;
   }
 
-  void run(Request* r) {
+  // One admitted request: its grid and per-step statistics.
+  struct Active {
+    Request* r;
+    std::unique_ptr<GridBase> g;
+    std::vector<nfvm_step_stats> stats;
+  };
+
+  std::unique_ptr<GridBase> make(Request* r, hipStream_t s) {
     nfvm_fields init;
-    init.u = r->f[0].data();
-    init.v = r->f[1].data();
-    init.w = r->f[2].data();
-    init.p = r->f[3].data();
-    init.T = r->f[4].data();
-    init.k = r->f[5].data();
-    init.omega = r->f[6].data();
+    double** dst[7] = {&init.u, &init.v, &init.w, &init.p, &init.T, &init.k, &init.omega};
+    for (int f = 0; f < 7; ++f) *dst[f] = r->f[f].data();
     nfvm_grid_desc d = r->desc;
     d.patches = r->patches.empty() ? nullptr : r->patches.data();
     d.solid_mask = r->mask.empty() ? nullptr : r->mask.data();
-    nfvm_status st = NFVM_OK;
-    try {
-      // tiles: the autotuner's cached choices, never a tuning run on the
-      // request's critical path
-      std::unique_ptr<GridBase> g = make_grid(d, &init, nullptr, 2);
-      for (int s = 0; s < r->n_steps; ++s) {
-        nfvm_step_stats ss{};
-        nfvm_status one = NFVM_OK;
-        g->step(1, &ss, &one);
-        r->last = ss;
-        if (one == NFVM_OK && r->t[2] < 0) {
-          std::lock_guard<std::mutex> lk(mu);
-          r->t[2] = now_since(t0);
-        }
-        if (one == NFVM_E_DIVERGED) {
-          st = one;
-          break;
-        }
-        if (one != NFVM_OK && st == NFVM_OK) st = one;
+    // tiles: the autotuner's cached choices, never a tuning run on the
+    // request's critical path
+    return make_grid(d, &init, s, 2);
+  }
+
+  void finish(Active& a, nfvm_status st, const std::string& err) {
+    Request* r = a.r;
+    for (const nfvm_step_stats& x : a.stats)  // the last step that ran
+      if (x.status != NFVM_PENDING) r->last = x;
+    if (a.g && st != NFVM_E_DIVERGED) {
+      try {
+        nfvm_fields out;
+        double** dst[7] = {&out.u, &out.v, &out.w, &out.p, &out.T, &out.k, &out.omega};
+        for (int f = 0; f < 7; ++f) *dst[f] = r->f[f].data();
+        a.g->get_fields(&out);
+      } catch (const Error& e) {
+        st = e.st;
+        r->err = e.msg;
       }
-      if (st != NFVM_E_DIVERGED) g->get_fields(&init);
-    } catch (const Error& e) {
-      st = e.st;
-      r->err = e.msg;
-    } catch (const std::exception& e) {
-      st = NFVM_E_DEVICE;
-      r->err = e.what();
     }
+    a.g.reset();
     std::lock_guard<std::mutex> lk(mu);
     r->status = st;
+    if (!err.empty()) r->err = err;
     r->state = Q_DONE;
     r->t[3] = now_since(t0);
     used -= r->footprint;
@@ -119,28 +122,82 @@ struct nfvm_server {
     cv.notify_all();
   }
 
-  void worker() {
+  // one lane: up to cap grids advanced together on the lane's stream
+  void worker(int cap) {
     (void)hipSetDevice(device);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    std::vector<Active> act;
+    std::unique_ptr<BatchRunner> br(new BatchRunner(s));
     for (;;) {
-      Request* r = nullptr;
+      std::vector<Request*> admit;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv.wait(lk, [&] {
-          if (stop) return true;
-          for (uint64_t id : queue)
-            if (used + reqs[id]->footprint <= budget) return true;
-          return false;
-        });
-        if (stop) return;
-        r = take_admissible();
-        if (!r) continue;
-        used += r->footprint;
-        ++running;
-        r->state = Q_RUNNING;
-        r->t[1] = now_since(t0);
+        if (act.empty())
+          cv.wait(lk, [&] {
+            if (stop) return true;
+            if (running >= slots) return false;
+            for (uint64_t id : queue)
+              if (used + reqs[id]->footprint <= budget) return true;
+            return false;
+          });
+        if (stop && act.empty()) break;
+        while ((int)(act.size() + admit.size()) < cap && running < slots) {
+          Request* r = take_admissible();
+          if (!r) break;
+          used += r->footprint;
+          ++running;
+          r->state = Q_RUNNING;
+          r->t[1] = now_since(t0);
+          admit.push_back(r);
+        }
       }
-      run(r);
+      for (Request* r : admit) {
+        Active a{r, nullptr, std::vector<nfvm_step_stats>(r->n_steps)};
+        for (nfvm_step_stats& x : a.stats) x.status = NFVM_PENDING;
+        try {
+          if (!s) throw Error{NFVM_E_DEVICE, "stream creation failed"};
+          a.g = make(r, s);
+          br->add(a.g.get(), r->n_steps, a.stats.data());
+          act.push_back(std::move(a));
+        } catch (const Error& e) {
+          finish(a, e.st, e.msg);
+        } catch (const std::exception& e) {
+          finish(a, NFVM_E_DEVICE, e.what());
+        }
+      }
+      if (act.empty()) continue;
+      std::vector<GridBase*> over;
+      try {
+        over = br->advance();
+      } catch (const Error& e) {
+        // a device error ends every running request
+        for (Active& a : act) finish(a, e.st, e.msg);
+        act.clear();
+        br.reset(new BatchRunner(s));
+        continue;
+      } catch (const std::exception& e) {
+        for (Active& a : act) finish(a, NFVM_E_DEVICE, e.what());
+        act.clear();
+        br.reset(new BatchRunner(s));
+        continue;
+      }
+      for (auto it = act.begin(); it != act.end();) {
+        Active& a = *it;
+        if (a.r->t[2] < 0 && a.g->run_converged() > 0) {
+          std::lock_guard<std::mutex> lk(mu);
+          a.r->t[2] = now_since(t0);
+        }
+        if (std::find(over.begin(), over.end(), a.g.get()) != over.end()) {
+          finish(a, a.g->run_status(), "");
+          it = act.erase(it);
+        } else {
+          ++it;
+        }
+      }
     }
+    br.reset();
+    if (s) (void)hipStreamDestroy(s);
   }
 };
 
@@ -168,7 +225,9 @@ nfvm_status nfvm_server_create(double hbm_budget_bytes, int32_t max_slots, nfvm_
     s->budget = (size_t)(0.9 * (double)fr);
   }
   s->slots = max_slots;
-  for (int i = 0; i < max_slots; ++i) s->workers.emplace_back([s] { s->worker(); });
+  const int lanes = std::min(max_slots, 3);
+  const int cap = (max_slots + lanes - 1) / lanes;
+  for (int i = 0; i < lanes; ++i) s->workers.emplace_back([s, cap] { s->worker(cap); });
   *out = s;
   return NFVM_OK;
 }

@@ -22,7 +22,8 @@ NFVM_FP64, NFVM_FP32, NFVM_MIXED = 0, 1, 2
 _dp = C.POINTER(C.c_double)
 
 EXPORTS = (
-    "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_mg_solve", "nfvm_mg_solve_device",
+    "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_step_batch", "nfvm_mg_solve",
+    "nfvm_mg_solve_device",
     "nfvm_get_fields", "nfvm_set_fields", "nfvm_grid_footprint", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
     "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_set_option", "nfvm_tuning_table",
@@ -82,6 +83,8 @@ def lib():
         L.nfvm_init_grid.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(nfvm_fields), C.c_void_p,
                                      C.POINTER(C.c_void_p)]
         L.nfvm_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(nfvm_step_stats)]
+        L.nfvm_step_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_int32,
+                                      C.POINTER(nfvm_step_stats), C.POINTER(C.c_int32)]
         L.nfvm_mg_solve.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int32, C.c_int32,
                                     C.POINTER(nfvm_step_stats)]
         L.nfvm_mg_solve_device.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
@@ -190,6 +193,18 @@ def nfvm_step(grid, n_steps: int, allow=(NFVM_OK,)):
     st = (nfvm_step_stats * max(1, n_steps))()
     s = _check(lib().nfvm_step(grid, n_steps, st), allow)
     return s, [st[i].as_dict() for i in range(n_steps)]
+
+
+def nfvm_step_batch(grids, n_steps: int, allow=(NFVM_OK,)):
+    """n_steps time steps of several grids in batched launches; returns the
+    call's status, each grid's status and each grid's per-step stats."""
+    n = len(grids)
+    hs = (C.c_void_p * n)(*[g.value if isinstance(g, C.c_void_p) else g for g in grids])
+    st = (nfvm_step_stats * max(1, n * n_steps))()
+    sts = (C.c_int32 * n)()
+    s = _check(lib().nfvm_step_batch(hs, n, n_steps, st, sts), allow)
+    stats = [[st[i * n_steps + j].as_dict() for j in range(n_steps)] for i in range(n)]
+    return s, list(sts), stats
 
 
 def nfvm_mg_solve(grid, b: np.ndarray, x0: Optional[np.ndarray] = None, tol: float = 1e-10,
