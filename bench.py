@@ -162,6 +162,36 @@ def run_serve(n_req: int, slots: int, seed: int = 0):
             "mean_cells": int(sum(c.ncells for c in cases) / n_req)}
 
 
+def run_batch(n_grids: int = 8, edge: int = 64, steps: int = 10):
+    """Batched stepping (one launch per multigrid kernel and level over all
+    grids) against the same grids stepped one after the other: n_grids
+    mixed-precision channels of edge^3 cells from the serving recipe."""
+    from paper_2603_21869_amd import cases as C, nfvm
+    import torch
+    cases = [C.serve_case(dict(n=(edge, edge, edge), geometry="channel", seed=900 + i,
+                               n_steps=steps)) for i in range(n_grids)]
+    cells = sum(c.ncells for c in cases)
+    out = {"grids": n_grids, "cells_per_grid": cases[0].ncells, "steps": steps}
+    for mode in ("sequential", "batched"):
+        gs = [nfvm.Grid(c) for c in cases]
+        if mode == "batched":
+            nfvm.nfvm_step_batch([g.h for g in gs], 2)
+            t0 = time.perf_counter()
+            nfvm.nfvm_step_batch([g.h for g in gs], steps)
+        else:
+            for g in gs:
+                g.step(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for g in gs:
+                g.step(steps)
+        torch.cuda.synchronize()
+        out[mode + "_mcell_steps_s"] = round(cells * steps / (time.perf_counter() - t0) / 1e6, 2)
+        for g in gs:
+            g.close()
+    return out
+
+
 def cpu_baseline(case, budget_s: float = 20.0):
     """The serial FP64 oracle on a bounded number of steps of the same workload."""
     from oracle import oracle as O
@@ -195,7 +225,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--serve", type=int, default=24,
                     help="requests of the serving trace to replay (0: skip)")
-    ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--serve-slots", type=int, default=9)
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (for "
                          "scaling hardware byte counters) and exit")
@@ -290,6 +321,8 @@ def main():
         "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
                          "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",
     }
+    if not args.no_batch:
+        out["batching"] = run_batch()
     if args.serve:
         out["serving"] = run_serve(args.serve, args.serve_slots)
     if not args.no_cpu:
