@@ -159,8 +159,9 @@ nfvm_status nfvm_step_batch(nfvm_grid_t* grids, int32_t n_grids, int32_t n_steps
  * seven/five-point -laplacian, zero-gradient walls, inlets and solids, zero
  * value at outlets) by the multigrid-preconditioned iteration.  b, x: host
  * FP64 [nz][ny][nx]; x is the initial guess on entry and the solution on exit;
- * solid cells are ignored on entry and 0 on exit.  forced_cycles >= 0 runs
- * exactly that many cycles (tol ignored).  stats may be NULL. */
+ * solid cells are ignored on entry and 0 on exit; b = 0 gives x = 0.
+ * forced_cycles >= 0 runs exactly that many cycles (tol ignored).  stats may
+ * be NULL. */
 nfvm_status nfvm_mg_solve(nfvm_grid_t grid, const double* b, double* x, double tol,
                           int32_t max_cycles, int32_t forced_cycles, nfvm_step_stats* stats);
 
@@ -243,16 +244,33 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
  *                     nfvm_profile timing is on.
  *   NFVM_OPT_PREDICT  CG iterations enqueued before the first convergence
  *                     check (default: the count of the previous solve).
- *   NFVM_OPT_BOTTOM   1 (default): the coarse levels whose iterates fit in
- *                     64 KiB of LDS run as one workgroup in one launch;
- *                     0: one launch per operator and level.
+ *   NFVM_OPT_BOTTOM   1 (default): the coarse levels whose arrays fit in the
+ *                     LDS of one workgroup (160 KiB on MI355X) run as one
+ *                     workgroup in one launch; 0: one launch per operator
+ *                     and level.
  *   NFVM_OPT_AUTOTUNE 1 (default, applied in nfvm_init_grid): the tile shape
  *                     (workgroups per launch, planes per thread) of every hot
  *                     kernel is chosen per level by timing candidates on the
  *                     grid; results are cached per shape and precision for
  *                     the process.  0: fixed default tiles.
+ *   NFVM_OPT_WARM_START 1 (default): each step's pressure solve starts from
+ *                     the previous step's increment phi = p^{n+1} - p^n
+ *                     (zero after nfvm_init_grid, nfvm_set_fields and
+ *                     nfvm_mg_solve; Algorithm 1 likewise starts from the
+ *                     state it is given).  The increment is not part of the
+ *                     fields, so a run restarted through nfvm_get_fields /
+ *                     nfvm_set_fields starts its first solve from zero and
+ *                     agrees with the uninterrupted run to the solver
+ *                     tolerance, not bitwise; 0: every solve starts from
+ *                     zero, and restarts are bitwise.
  * Errors: NFVM_E_INVAL for an unknown option. */
-enum { NFVM_OPT_GRAPHS = 0, NFVM_OPT_PREDICT = 1, NFVM_OPT_BOTTOM = 2, NFVM_OPT_AUTOTUNE = 3 };
+enum {
+  NFVM_OPT_GRAPHS = 0,
+  NFVM_OPT_PREDICT = 1,
+  NFVM_OPT_BOTTOM = 2,
+  NFVM_OPT_AUTOTUNE = 3,
+  NFVM_OPT_WARM_START = 4
+};
 
 /* The autotuner's choices so far: up to max entries of {kernel id, nx, ny,
  * nz, dim, precision, tile target}; *count receives the number written. */

@@ -830,6 +830,8 @@ int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int m
   double* pv = (double*)calloc(N, sizeof(double));
   double* q = (double*)calloc(N, sizeof(double));
   double bn = sqrt(dot_active(l, b, b));
+  /* A x = 0 has the solution 0, whatever the initial guess */
+  if (bn == 0.0) memset(x, 0, sizeof(double) * N);
   orc_mg_apply(mg, 0, x, r);
   for (int P = 0; P < N; ++P) r[P] = l->act[P] ? b[P] - r[P] : 0.0;
   int status = ORC_OK, cyc = 0;
@@ -874,7 +876,7 @@ int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int m
  * second half-step destruction.  The flow chart of the paper is missing; this
  * order is the reading recorded in the design notes. */
 int orc_step(const orc_case* c, orc_fields* s, int n_steps, const int* forced,
-             orc_stats* stats) {
+             orc_stats* stats, int warm) {
   int N = ncells(c);
   orc_mg* mg = orc_mg_create(c);
   if (!mg) return ORC_E_INVAL;
@@ -897,7 +899,10 @@ int orc_step(const orc_case* c, orc_fields* s, int n_steps, const int* forced,
     }
     orc_explicit(c, s, &t);
     orc_rhs_b(c, t.u, t.v, t.w, b);
-    memset(phi, 0, sizeof(double) * N);
+    /* initial guess: the previous step's increment phi = p^{n} - p^{n-1}
+     * (Algorithm 1 iterates from the state it is given; with the
+     * incremental pressure the state is the last increment), else zero */
+    if (!warm) memset(phi, 0, sizeof(double) * N);
     int cyc = 0;
     double rel = 0.0, mdiv = 0.0;
     int ms = orc_mg_solve(mg, b, phi, c->tol, c->max_cycles, forced ? forced[st] : -1, &cyc, &rel);

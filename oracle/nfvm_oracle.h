@@ -84,8 +84,10 @@ void orc_mg_vcycle(const orc_mg* mg, double* x, const double* b);
 int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int max_cycles,
                  int forced_cycles, int* cycles, double* rel_residual);
 
+/* warm != 0: each step's pressure solve starts from the previous step's
+ * increment (zero at the first step of the call), else from zero. */
 int orc_step(const orc_case* c, orc_fields* s, int n_steps, const int* forced_cycles,
-             orc_stats* stats);
+             orc_stats* stats, int warm);
 
 #ifdef __cplusplus
 }

@@ -163,8 +163,10 @@ def _fresh(case) -> Dict[str, np.ndarray]:
 
 
 def step(case, n_steps: Optional[int] = None, forced_cycles: Optional[Sequence[int]] = None,
-         fields: Optional[Dict[str, np.ndarray]] = None):
+         fields: Optional[Dict[str, np.ndarray]] = None, warm: bool = True):
     """Run n_steps time steps from the case's initial fields (or ``fields``).
+    With ``warm`` each pressure solve starts from the previous step's
+    increment (zero at the first step), else from zero.
 
     Returns (fields, stats list, status)."""
     L = lib()
@@ -178,7 +180,7 @@ def step(case, n_steps: Optional[int] = None, forced_cycles: Optional[Sequence[i
         fcp = C.cast(fc, C.POINTER(C.c_int))
     else:
         fcp = C.POINTER(C.c_int)()
-    status = L.orc_step(oc.ref, C.byref(fs), n_steps, fcp, st)
+    status = L.orc_step(oc.ref, C.byref(fs), n_steps, fcp, st, 1 if warm else 0)
     stats = [dict(cycles=st[i].cycles, status=st[i].status, rel_residual=st[i].rel_residual,
                   max_face_div=st[i].max_face_div, min_k=st[i].min_k, min_omega=st[i].min_omega)
              for i in range(n_steps)]

@@ -391,8 +391,15 @@ class GridT : public GridBase {
 
     for (int t = 0; t < TP_COUNT; ++t) tp[t] = TILE_DEFAULT;
     if (use_autotune) autotune();
+    clear_increment();
     if (init) set_fields(init);
     NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  // The pressure increment of the last step, the initial guess of the next
+  // step's solve; cleared whenever it no longer belongs to the stored fields.
+  void clear_increment() {
+    NFVM_CK(hipMemsetAsync(phi, 0, (size_t)g.total * sizeof(O), stream));
   }
 
   // ---- autotuner: for every tunable kernel and level, time a few tile
@@ -543,6 +550,7 @@ class GridT : public GridBase {
     NFVM_CK(hipMemcpyAsync(stage, src[6], bytes, hipMemcpyHostToDevice, stream));
     launch_pack<P>(g, stage, p, 0.0, stream);
     if (ph.komega) launch_set_omega_wall<F>(g, ph, patches, type, scur(5), stream);
+    clear_increment();
     NFVM_CK(hipGetLastError());
     NFVM_CK(hipStreamSynchronize(stream));
   }
@@ -823,6 +831,11 @@ class GridT : public GridBase {
     NFVM_CK(hipEventRecord(ev1, stream));
     NFVM_CK(hipStreamSynchronize(stream));
     prof_collect();
+    // b = 0: the solution is 0 whatever the initial guess
+    if (hs[S_BB] == 0.0)
+      NFVM_CK(hipMemsetAsync(x_dev, 0, (size_t)ncells * sizeof(double), stream));
+    clear_increment();
+    NFVM_CK(hipStreamSynchronize(stream));
     float ms = 0;
     NFVM_CK(hipEventElapsedTime(&ms, ev0, ev1));
     if (stt) {
@@ -859,8 +872,9 @@ class GridT : public GridBase {
     launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red,
                        tp[TP_RHS], stream);
     prof_end(NFVM_K_RHS);
-    launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, false, tol, max_cycles, -1, stream,
-                            true, zero0(), wj);
+    // initial guess: the previous step's increment (warm start), else zero
+    launch_fcg_start<O, S0>(lv[0], bvec, use_warm ? phi : x0, r, phi, red, use_warm, tol,
+                            max_cycles, -1, stream, true, zero0(), wj);
   }
 
   // projection, destruction over dt/2 (with the min k / omega reduction)
@@ -1089,9 +1103,14 @@ class GridT : public GridBase {
         for (int t = 0; t < TP_COUNT; ++t) tp[t] = TILE_DEFAULT;
       } else {
         autotune();
+        clear_increment();
       }
       NFVM_CK(hipStreamSynchronize(stream));
       drop_graphs();
+    } else if (opt == NFVM_OPT_WARM_START) {
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
+      use_warm = v != 0.0;
     } else if (opt == NFVM_OPT_BOTTOM) {
       NFVM_CK(hipStreamSynchronize(stream));
       drop_graphs();

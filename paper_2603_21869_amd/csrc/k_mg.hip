@@ -402,13 +402,18 @@ void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool 
 }
 
 // ---- residual and restriction: b_c = mean over the 2^dim children of (b - A x)
-// One thread per fine column (64 x 4 fine columns = 32 x 2 coarse columns per
-// workgroup), walking fine planes in pairs; the 2 x 2 in-plane sum uses a
-// lane exchange (x) and LDS (y).  Tiles count coarse planes along z.
+// One thread per fine column i and coarse row J: it walks the two fine rows
+// 2J, 2J + 1 plane by plane (the z neighbours of both rows stay in
+// registers) and sums each row over the two fine planes of a coarse plane;
+// the x pair is summed by a lane exchange, so no workgroup barrier is
+// needed.  A workgroup covers 64 fine columns by 4 coarse rows; tiles count
+// coarse rows along y and coarse planes along z.  Sum order per coarse cell:
+// ((row 2J over planes) + (x partner's)) + ((row 2J + 1 over planes) + (x
+// partner's)).
 template <class S, class C, class SC>
 struct RestrictArgs {
   LevelView F;
-  Tiles T;  // fine columns, coarse planes
+  Tiles T;  // fine columns, coarse rows, coarse planes
   const S* x;
   const S* b;
   LevelView Cl;
@@ -418,67 +423,79 @@ struct RestrictArgs {
   const double* ctl;
 };
 
+// b - A x at fine cell P (0 for inactive cells), z neighbours given.
+template <class S, class C>
+__device__ __forceinline__ C resid_at(const LevelView& F, const S* __restrict__ x,
+                                      const S* __restrict__ b, int P, C xc, C xm, C xp) {
+  C Ax, D;
+  if (F.code) {
+    const uint32_t cd = F.code[P];
+    const C bP = St<S, C>::ld(b + P);
+    apply_code<S, C>(F.g, cd, x, P, xc, xm, xp, Ax, D);
+    return cd != FACE_CODE_INACTIVE ? bP - Ax : (C)0;
+  }
+  const uint8_t cl = F.cls[P];
+  if (cl == MG_INACTIVE) return (C)0;
+  apply_z<S, C>(F, cl, x, P, xc, xm, xp, Ax, D);
+  return St<S, C>::ld(b + P) - Ax;
+}
+
 template <class S, class C, class SC>
 __device__ __forceinline__ void restrict_body(const RestrictArgs<S, C, SC>& a, const TileCtx& c,
                                               bool) {
   if (a.ctl[S_DONE] != 0.0) return;  // uniform over the workgroup
-  __shared__ C sh[MBY][MBX];
   const LevelView& F = a.F;
   const LevelView& Cl = a.Cl;
   const S* __restrict__ x = a.x;
   const S* __restrict__ b = a.b;
   const Geom& g = F.g;
-  const int lx = threadIdx.x, ly = threadIdx.y;
-  const int i = c.tx * MBX + lx, j = c.ty * MBY + ly;
-  const bool in = i < g.nx && j < g.ny;
+  const int lx = threadIdx.x;
+  const int i = c.tx * MBX + lx, J = c.ty * MBY + threadIdx.y;
+  // lanes past the box still take part in the lane exchange
+  const bool in = i < g.nx && J < Cl.g.ny;
   const bool d3 = g.dim == 3;
   const int K0 = c.tz * a.T.cz, K1 = min(Cl.g.nz, K0 + a.T.cz);
   const int kz = d3 ? 2 : 1;
-  int P = in ? g.idx(i, j, kz * K0) : 0;
-  C xm = 0, xc = 0;
+  int P0 = in ? g.idx(i, 2 * J, kz * K0) : 0, P1 = P0 + g.sx;
+  C xm0 = 0, xc0 = 0, xm1 = 0, xc1 = 0;
   if (in) {
-    xc = St<S, C>::ld(x + P);
-    if (d3) xm = St<S, C>::ld(x + P - g.sxy);
+    xc0 = St<S, C>::ld(x + P0);
+    xc1 = St<S, C>::ld(x + P1);
+    if (d3) {
+      xm0 = St<S, C>::ld(x + P0 - g.sxy);
+      xm1 = St<S, C>::ld(x + P1 - g.sxy);
+    }
   }
   for (int K = K0; K < K1; ++K) {
-    C r = 0;
-    for (int cc = 0; cc < kz; ++cc, P += g.sxy) {
-      C xp = 0;
+    C r0 = 0, r1 = 0;
+    for (int cc = 0; cc < kz; ++cc, P0 += g.sxy, P1 += g.sxy) {
       if (in) {
-        if (d3) xp = St<S, C>::ld(x + P + g.sxy);
-        if (F.code) {
-          const uint32_t cd = F.code[P];
-          const C bP = St<S, C>::ld(b + P);
-          C Ax, D;
-          apply_code<S, C>(g, cd, x, P, xc, xm, xp, Ax, D);
-          if (cd != FACE_CODE_INACTIVE) r += bP - Ax;
-        } else {
-          const uint8_t cl = F.cls[P];
-          if (cl != MG_INACTIVE) {
-            C Ax, D;
-            apply_z<S, C>(F, cl, x, P, xc, xm, xp, Ax, D);
-            r += St<S, C>::ld(b + P) - Ax;
-          }
+        C xp0 = 0, xp1 = 0;
+        if (d3) {
+          xp0 = St<S, C>::ld(x + P0 + g.sxy);
+          xp1 = St<S, C>::ld(x + P1 + g.sxy);
         }
+        r0 += resid_at<S, C>(F, x, b, P0, xc0, xm0, xp0);
+        r1 += resid_at<S, C>(F, x, b, P1, xc1, xm1, xp1);
+        xm0 = xc0;
+        xc0 = xp0;
+        xm1 = xc1;
+        xc1 = xp1;
       }
-      xm = xc;
-      xc = xp;
     }
-    r += __shfl_xor(r, 1);
-    sh[ly][lx] = r;
-    __syncthreads();
-    if (in && !(lx & 1) && !(ly & 1)) {
-      const int PC = Cl.g.idx(i >> 1, j >> 1, K);
+    r0 += __shfl_xor(r0, 1);
+    r1 += __shfl_xor(r1, 1);
+    if (in && !(lx & 1)) {
+      const int PC = Cl.g.idx(i >> 1, J, K);
       const uint8_t ccl = Cl.cls[PC];
       if (ccl != MG_INACTIVE) {
         SC* dst = a.bc + PC;
-        St<SC, C>::st(dst, (sh[ly][lx] + sh[ly + 1][lx]) * (C)(d3 ? 0.125 : 0.25));
+        St<SC, C>::st(dst, (r0 + r1) * (C)(d3 ? 0.125 : 0.25));
         // first pre-smoothing sweep (from zero) of the coarse level
         if (a.zc)
           St<SC, C>::st(a.zc + PC, a.wj * St<SC, C>::ld(dst) / diag_at<C>(Cl, ccl, PC));
       }
     }
-    __syncthreads();
   }
 }
 NFVM_TILE_KERNELS(k_resid_restrict, restrict_body, RestrictArgs, (S, C, SC),
@@ -488,7 +505,7 @@ template <class S, class C, class SC>
 RestrictArgs<S, C, SC> restrict_args(const Level& f, const Level& c, const double* ctl, void* zc,
                                      double wj) {
   return RestrictArgs<S, C, SC>{view(f),
-                                make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_RESTRICT]),
+                                make_tiles(f.g.nx, c.g.ny, c.g.nz, f.tt[TK_RESTRICT]),
                                 (const S*)f.x[f.cur],
                                 (const S*)f.b,
                                 view(c),
@@ -510,73 +527,56 @@ void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hi
 // and 1/4.  A neighbour outside the box contributes the boundary ghost
 // (1 - c_f) e (c_f = 0: zero gradient, 2: zero value); an inactive neighbour
 // is replaced by the cell it is interpolated from.
-template <class SC, class C>
-__device__ __forceinline__ bool act_at(const LevelView& L, int i, int j, int k) {
-  if (i < 0 || j < 0 || k < 0 || i >= L.g.nx || j >= L.g.ny || k >= L.g.nz) return false;
-  return L.cls[L.g.idx(i, j, k)] != MG_INACTIVE;
-}
-
-// Correction at fine cell (i, j, k) with every boundary and mask check.
-// Every value the rules may need is loaded up front (the indices lie in the
-// padded arrays: one ghost layer around the box) and the rules then select
-// among them, so a wave pays one round of loads instead of a chain of
-// dependent ones; the arithmetic is the same, term for term.
+//
+// For a fine column (i, j) the x and y steps on one coarse plane involve the
+// coarse cells (I, J), (I + sx, J), (I, J + sy), (I + sx, J + sy) of that
+// plane (sx, sy: side of the fine cell within its parent); they give the
+// plane value Y and whether the plane's cell (I, J) takes part (active and
+// inside the box).  The z step then combines the planes K and K +- 1.
 template <class C, class SC>
-__device__ C prolong_checked(const LevelView& Cl, const SC* __restrict__ e, int i, int j, int k) {
-  const Geom& cg = Cl.g;
-  const bool d3 = cg.dim == 3;
-  const int I = i >> 1, J = j >> 1, K = d3 ? (k >> 1) : 0;
-  const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
-  const int oy = sy * cg.sx, oz = sz * cg.sxy;
+__device__ __forceinline__ void plane_rules(const LevelView& Cl, const SC* __restrict__ e, int Q,
+                                            int sx, int oy, bool in_plane, bool inx, bool iny,
+                                            C& Y, bool& act) {
   const C w3 = (C)0.75, w1 = (C)0.25;
-  const bool inx = (unsigned)(I + sx) < (unsigned)cg.nx;
-  const bool iny = (unsigned)(J + sy) < (unsigned)cg.ny;
-  const bool inz = d3 && (unsigned)(K + sz) < (unsigned)cg.nz;
-  const int nq = d3 ? 4 : 2;
-  // q = 0: (J, K), 1: (J + sy, K), 2: (J, K + sz), 3: (J + sy, K + sz)
-  const int Q0 = cg.idx(I, J, K);
-  int Q[4] = {Q0, Q0 + oy, Q0, Q0};
-  if (d3) {
-    Q[2] = Q0 + oz;
-    Q[3] = Q0 + oz + oy;
-  }
-  C ev[4] = {0, 0, 0, 0}, en[4] = {0, 0, 0, 0}, cfx[4] = {0, 0, 0, 0};
-  bool ac[4] = {false, false, false, false}, an[4] = {false, false, false, false};
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q >= nq) break;
-    ev[q] = St<SC, C>::ld(e + Q[q]);
-    en[q] = St<SC, C>::ld(e + Q[q] + sx);
-    ac[q] = Cl.cls[Q[q]] != MG_INACTIVE;
-    an[q] = Cl.cls[Q[q] + sx] != MG_INACTIVE;
-    cfx[q] = (C)Cl.cf0[sx > 0 ? Q[q] + 1 : Q[q]];
-  }
-  const C cfy0 = (C)Cl.cf1[sy > 0 ? Q[0] + cg.sx : Q[0]];
-  const C cfy1 = d3 ? (C)Cl.cf1[sy > 0 ? Q[2] + cg.sx : Q[2]] : (C)0;
-  const C cfz = d3 ? (C)Cl.cf2[sz > 0 ? Q0 + cg.sxy : Q0] : (C)0;
-  const bool act[4] = {ac[0], iny && ac[1], inz && ac[2], iny && inz && ac[3]};
-  C X[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const C nb = inx ? (an[q] ? en[q] : ev[q]) : ((C)1 - cfx[q]) * ev[q];
-    X[q] = act[q] ? w3 * ev[q] + w1 * nb : (C)0;
-  }
-  const C yn0 = iny ? (act[1] ? X[1] : X[0]) : ((C)1 - cfy0) * X[0];
-  const C Y0 = act[0] ? w3 * X[0] + w1 * yn0 : (C)0;
-  if (!d3) return Y0;
-  const C yn1 = iny ? (act[3] ? X[3] : X[2]) : ((C)1 - cfy1) * X[2];
-  const C Y1 = act[2] ? w3 * X[2] + w1 * yn1 : (C)0;
-  const C zn = inz ? (act[2] ? Y1 : Y0) : ((C)1 - cfz) * Y0;
-  return w3 * Y0 + w1 * zn;
+  // every index lies in the padded array (one ghost layer around the box)
+  const C e00 = St<SC, C>::ld(e + Q), e10 = St<SC, C>::ld(e + Q + sx);
+  const C e01 = St<SC, C>::ld(e + Q + oy), e11 = St<SC, C>::ld(e + Q + oy + sx);
+  const bool a00 = in_plane && Cl.cls[Q] != MG_INACTIVE;
+  const bool a10 = Cl.cls[Q + sx] != MG_INACTIVE;
+  const bool a01 = iny && in_plane && Cl.cls[Q + oy] != MG_INACTIVE;
+  const bool a11 = Cl.cls[Q + oy + sx] != MG_INACTIVE;
+  const C cfx0 = (C)Cl.cf0[sx > 0 ? Q + 1 : Q];
+  const C cfx1 = (C)Cl.cf0[sx > 0 ? Q + oy + 1 : Q + oy];
+  const C cfy = (C)Cl.cf1[oy > 0 ? Q + oy : Q];
+  const C nb0 = inx ? (a10 ? e10 : e00) : ((C)1 - cfx0) * e00;
+  const C X0 = a00 ? w3 * e00 + w1 * nb0 : (C)0;
+  const C nb1 = inx ? (a11 ? e11 : e01) : ((C)1 - cfx1) * e01;
+  const C X1 = a01 ? w3 * e01 + w1 * nb1 : (C)0;
+  const C yn = iny ? (a01 ? X1 : X0) : ((C)1 - cfy) * X0;
+  Y = a00 ? w3 * X0 + w1 * yn : (C)0;
+  act = a00;
 }
 
-// One thread per fine column (i, j) walking the coarse planes K of its tile.
-// The x-then-y interpolated coarse value of planes K-1, K and K+1 stays in
-// registers, so the two fine cells 2K and 2K+1 under a coarse cell whose 26
-// neighbours are all active cost four coarse loads between them; other cells
-// take the checked path.  Planes K-1 and K+1 are read unchecked: they lie in
-// the padded array (one ghost layer) and hold finite values (ghost and
-// inactive cells are 0), and are used only when the cell is marked full.
+// The same plane value when the four cells are active and inside the box.
+template <class C, class SC>
+__device__ __forceinline__ C plane_interior(const SC* __restrict__ e, int Q, int sx, int oy) {
+  const C w3 = (C)0.75, w1 = (C)0.25;
+  const C e00 = St<SC, C>::ld(e + Q), e10 = St<SC, C>::ld(e + Q + sx);
+  const C e01 = St<SC, C>::ld(e + Q + oy), e11 = St<SC, C>::ld(e + Q + oy + sx);
+  const C X0 = w3 * e00 + w1 * e10;
+  const C X1 = w3 * e01 + w1 * e11;
+  return w3 * X0 + w1 * X1;
+}
+
+// One thread per fine column (i, j) walking the coarse planes K of its tile,
+// with the plane values of K - 1, K and K + 1 in registers (two fine cells
+// per coarse plane).  Per plane the wave takes one of two forms: when the
+// coarse cells under all its columns have their 26 neighbours active and
+// inside the box (`full`), the next plane costs four coarse loads and the
+// rules reduce to plain weights; otherwise every lane evaluates all rules
+// from the plane's values, flags and face coefficients.  The choice is
+// uniform over the wave, so no lane waits for another's path, and both forms
+// give the same value where both apply.
 template <class S, class C, class SC>
 struct ProlongArgs {
   LevelView F;
@@ -600,32 +600,61 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs<S, C, SC>& a, con
   const Geom& cg = Cl.g;
   const bool d3 = cg.dim == 3;
   const int K0 = c.tz * a.T.cz, K1 = min(cg.nz, K0 + a.T.cz);
+  const int I = i >> 1, J = j >> 1;
   const int sx = (i & 1) ? 1 : -1, oy = (j & 1) ? cg.sx : -cg.sx;
+  const bool inx = (unsigned)(I + sx) < (unsigned)cg.nx;
+  const bool iny = (unsigned)(J + ((j & 1) ? 1 : -1)) < (unsigned)cg.ny;
   const C w3 = (C)0.75, w1 = (C)0.25;
-  int PC = cg.idx(i >> 1, j >> 1, K0);
-  auto plane = [&](int Q) -> C {
-    const C x0 = w3 * St<SC, C>::ld(e + Q) + w1 * St<SC, C>::ld(e + Q + sx);
-    const C x1 = w3 * St<SC, C>::ld(e + Q + oy) + w1 * St<SC, C>::ld(e + Q + oy + sx);
-    return w3 * x0 + w1 * x1;
-  };
-  C ym = 0, yc = plane(PC);
-  if (d3) ym = plane(PC - cg.sxy);
+  int PC = cg.idx(I, J, K0);
+  C ym = 0, yc;
+  bool am = false, ac;
+  plane_rules<C, SC>(Cl, e, PC, sx, oy, true, inx, iny, yc, ac);
+  if (d3) plane_rules<C, SC>(Cl, e, PC - cg.sxy, sx, oy, K0 > 0, inx, iny, ym, am);
+  int P = F.g.idx(i, j, d3 ? 2 * K0 : 0);
+  bool full = d3 && Cl.full[PC] != 0;
   for (int K = K0; K < K1; ++K, PC += cg.sxy) {
-    const C yp = d3 ? plane(PC + cg.sxy) : (C)0;
-    const bool full = Cl.full[PC] != 0;
-    for (int cc = 0; cc < (d3 ? 2 : 1); ++cc) {
-      const int k = d3 ? 2 * K + cc : 0;
-      const int P = F.g.idx(i, j, k);
-      if (F.cls[P] == MG_INACTIVE) continue;
-      C Z;
-      if (full)
-        Z = d3 ? w3 * yc + w1 * (cc ? yp : ym) : yc;
-      else
-        Z = prolong_checked<C, SC>(Cl, e, i, j, k);
-      St<S, C>::st(x + P, St<S, C>::ld(x + P) + Z);
+    // the fine cells' loads and the next plane's flag go out first: they do
+    // not depend on the coarse values
+    const uint8_t fc0 = F.cls[P];
+    const S x0 = x[P];
+    uint8_t fc1 = MG_INACTIVE;
+    S x1 = x0;
+    bool full_next = false;
+    if (d3) {
+      fc1 = F.cls[P + F.g.sxy];
+      x1 = x[P + F.g.sxy];
+      full_next = K + 1 < K1 && Cl.full[PC + cg.sxy] != 0;
     }
+    C yp = 0, cz_lo = 0, cz_hi = 0;
+    bool ap = false;
+    if (d3) {
+      if (__all(full)) {
+        yp = plane_interior<C, SC>(e, PC + cg.sxy, sx, oy);
+        ap = true;
+      } else {
+        plane_rules<C, SC>(Cl, e, PC + cg.sxy, sx, oy, K + 1 < cg.nz, inx, iny, yp, ap);
+        cz_lo = (C)Cl.cf2[PC];
+        cz_hi = (C)Cl.cf2[PC + cg.sxy];
+      }
+    }
+    if (fc0 != MG_INACTIVE) {
+      C Z = yc;
+      if (d3) {
+        const C zn = K > 0 ? (am ? ym : yc) : ((C)1 - cz_lo) * yc;
+        Z = w3 * yc + w1 * zn;
+      }
+      St<S, C>::st(x + P, St<S, C>::ld(&x0) + Z);
+    }
+    if (d3 && fc1 != MG_INACTIVE) {
+      const C zn = K + 1 < cg.nz ? (ap ? yp : yc) : ((C)1 - cz_hi) * yc;
+      St<S, C>::st(x + P + F.g.sxy, St<S, C>::ld(&x1) + (w3 * yc + w1 * zn));
+    }
+    P += d3 ? 2 * F.g.sxy : 0;
+    full = full_next;
     ym = yc;
+    am = ac;
     yc = yp;
+    ac = ap;
   }
 }
 NFVM_TILE_KERNELS(k_prolong, prolong_body, ProlongArgs, (S, C, SC), (class S, class C, class SC),
@@ -754,7 +783,7 @@ __global__ __launch_bounds__(MBS) void k_fcg_start(LevelView L, Tiles T, const O
           rP = bP - Ax;
         }
         r[P] = rP;
-        x[P] = xP;
+        if (x) x[P] = xP;  // null: x is x0 (warm start in place)
         zero_sweep<O, S>(L, P, cd, rP, b0, z0, wj);
         bb += (double)bP * (double)bP;
         rr += (double)rP * (double)rP;
@@ -823,7 +852,8 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                       bool fin, void* z0, double wj) {
   const Tiles T = lvl_tiles(l0, TK_START);
   hipLaunchKernelGGL((k_fcg_start<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, b, x0,
-                     r, x, (S*)l0.b, (S*)z0, (S)wj, have_x0 ? 1 : 0, red);
+                     r, (have_x0 && x0 == x) ? nullptr : x, (S*)l0.b, (S*)z0, (S)wj,
+                     have_x0 ? 1 : 0, red);
   if (fin)
     hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(FIN), 0, s, red, T.grid, tol * tol,
                        (double)max_cycles, (double)forced);
@@ -1368,8 +1398,9 @@ __device__ __forceinline__ void bottom_body(const Bottom& B, const SC* __restric
       if (fcls[c] == MG_INACTIVE) continue;
       int i, j, k;
       lds_ijk(F, c, i, j, k);
-      // the rules of prolong_checked on the compact arrays: indices outside
-      // the box are clamped to the cell itself and their values masked
+      // the prolongation rules (plane_rules, then the z step) on the compact
+      // arrays: indices outside the box are clamped to the cell itself and
+      // their values masked
       const int I = i >> 1, J = j >> 1, K = d3 ? (k >> 1) : 0;
       const int sx = (i & 1) ? 1 : -1, sy = (j & 1) ? 1 : -1, sz = (k & 1) ? 1 : -1;
       const C w3 = (C)0.75, w1 = (C)0.25;

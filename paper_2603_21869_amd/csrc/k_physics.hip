@@ -470,7 +470,7 @@ template void launch_rhs_b<float, float>(const Geom&, const Phys&, const uint8_t
 template <class F, class P, class O>
 __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                 const DevPatch* __restrict__ pt,
-                                                const O* __restrict__ phi, const F* __restrict__ u,
+                                                O* __restrict__ phi, const F* __restrict__ u,
                                                 const F* __restrict__ v, const F* __restrict__ w,
                                                 F* __restrict__ uo, F* __restrict__ vo,
                                                 F* __restrict__ wo, P* __restrict__ p,
@@ -480,6 +480,9 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
   const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
   const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
   double mdiv = 0.0;
+  // b = 0: the increment is 0 whatever the solve started from; it is taken
+  // as 0 here and cleared, so the next step does not start from it
+  const bool zero_inc = red.out[S_BB] == 0.0;
   if (tile && i < g.nx && j < g.ny)
   for (int k = kb; k < ke; ++k) {
     const int C0 = g.idx(i, j, k);
@@ -492,7 +495,8 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
       const int st[3] = {1, g.sx, g.sxy};
       const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
       const O dt = (O)ph.dt;
-      const O fP = phi[C0];
+      const O fP = zero_inc ? (O)0 : phi[C0];
+      if (zero_inc) phi[C0] = (O)0;
       O div = 0;
       O unew[3] = {0, 0, 0};
 #pragma unroll
@@ -508,7 +512,7 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
           O vn, fN_ghost, fN_face, c;
           if (is_fluid(tn)) {
             vn = (O)vel[d][N];
-            fN_ghost = phi[N];
+            fN_ghost = zero_inc ? (O)0 : phi[N];
             fN_face = fN_ghost;
             c = 1;
           } else {
@@ -537,7 +541,7 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
 
 template <class F, class P, class O>
 void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                    const O* phi, const F* u, const F* v, const F* w, F* uo, F* vo, F* wo, P* p,
+                    O* phi, const F* u, const F* v, const F* w, F* uo, F* vo, F* wo, P* p,
                     const RedBuf& red, int tt, hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
   NFVM_LAUNCH((k_project<F, P, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
@@ -545,12 +549,12 @@ void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const De
   launch_finalize(1, R_MAX, red, T.grid, S_DIV, S_DIV, s);
 }
 template void launch_project<double, double, double>(const Geom&, const Phys&, const uint8_t*,
-                                                     const DevPatch*, const double*,
+                                                     const DevPatch*, double*,
                                                      const double*, const double*, const double*,
                                                      double*, double*, double*, double*,
                                                      const RedBuf&, int, hipStream_t);
 template void launch_project<float, float, float>(const Geom&, const Phys&, const uint8_t*,
-                                                  const DevPatch*, const float*, const float*,
+                                                  const DevPatch*, float*, const float*,
                                                   const float*, const float*, float*, float*,
                                                   float*, float*, const RedBuf&, int, hipStream_t);
 

@@ -219,10 +219,11 @@ template <class V, class O>
 void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                   const V* u, const V* v, const V* w, O* b, const RedBuf& red, int tt,
                   hipStream_t s);
-// reads u* (u, v, w), writes the corrected velocity to (uo, vo, wo)
+// reads u* (u, v, w), writes the corrected velocity to (uo, vo, wo); when
+// ||b|| = 0 (red.out[S_BB]) the increment phi is taken as 0 and cleared
 template <class V, class P, class O>
 void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
-                    const O* phi, const V* u, const V* v, const V* w, V* uo, V* vo, V* wo, P* p,
+                    O* phi, const V* u, const V* v, const V* w, V* uo, V* vo, V* wo, P* p,
                     const RedBuf& red, int tt, hipStream_t s);
 
 // multigrid (S: storage of the level, C: arithmetic)

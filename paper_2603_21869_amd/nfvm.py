@@ -259,6 +259,7 @@ def nfvm_profile_read(grid, kernel: int):
 
 
 NFVM_OPT_GRAPHS, NFVM_OPT_PREDICT, NFVM_OPT_BOTTOM, NFVM_OPT_AUTOTUNE = 0, 1, 2, 3
+NFVM_OPT_WARM_START = 4
 
 
 def nfvm_tuning_table():

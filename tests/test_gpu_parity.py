@@ -52,6 +52,9 @@ def test_mg_solve_fp64_matches_oracle(nf, oracle, name, case):
     assert not x[~m].any()
     # residual of the GPU answer under the oracle's operator
     assert np.linalg.norm((b - mg.apply(0, x))[m]) <= 2e-10 * np.linalg.norm(b[m])
+    # b = 0 gives x = 0 from any initial guess
+    z, st0, s0 = g.mg_solve(np.zeros_like(b), x0=b, tol=1e-10, max_cycles=60)
+    assert s0 == 0 and st0["cycles"] == 0 and not z.any()
     g.close()
 
 
@@ -102,32 +105,57 @@ def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
 
 
 def test_deterministic_and_restartable(nf):
-    """Two runs give bitwise equal fields; N + N steps with a get/set of the
-    fields in between equal 2N steps bitwise."""
+    """Two runs give bitwise equal fields.  With every solve started from zero,
+    N + N steps with a get/set of the fields in between equal 2N steps
+    bitwise; with the warm start (the default) the restarted run's first solve
+    starts from zero instead of the previous increment, so the two agree to
+    the solver tolerance."""
     case = C.room3d(64, 24, 16, seed=2, n_levels=4, precision=C.PREC_MIXED)
-    a = nf.Grid(case)
-    a.step(4)
-    fa = a.fields()
-    b = nf.Grid(case)
-    b.step(2)
-    mid = b.fields()
-    b.close()
-    c = nf.Grid(case, fields=mid)
-    c.step(2)
-    fc = c.fields()
-    d = nf.Grid(case)
-    d.step(4)
-    fd = d.fields()
+
+    def run(n, warm, fields=None):
+        g = nf.Grid(case, fields=fields)
+        nf.nfvm_set_option(g.h, nf.NFVM_OPT_WARM_START, 1 if warm else 0)
+        g.step(n)
+        f = g.fields()
+        g.close()
+        return f
+
+    fa, fd = run(4, True), run(4, True)
     for k in fa:
         assert np.array_equal(fa[k], fd[k]), k
-    # restart through the FP64 host arrays is exact for every field except T:
-    # the device holds theta = T - T_ref in FP32, and theta + T_ref in FP64
-    # cannot keep every bit of a tiny theta, so T round-trips to ~1e-14 K
-    for k in fa:
-        if k == "T":
-            assert np.abs(fa[k] - fc[k]).max() <= 1e-9, k
-        else:
-            assert np.array_equal(fa[k], fc[k]), k
+    for warm in (False, True):
+        full = run(4, warm)
+        fc = run(2, warm, fields=run(2, warm))
+        for k in full:
+            if not warm and k != "T":
+                assert np.array_equal(full[k], fc[k]), k
+            elif not warm:
+                # the device holds theta = T - T_ref in FP32, and theta + T_ref
+                # in FP64 cannot keep every bit of a tiny theta, so T
+                # round-trips to ~1e-14 K
+                assert np.abs(full[k] - fc[k]).max() <= 1e-9, k
+            else:
+                ref = ("u", "v", "w") if k in ("u", "v", "w") else (k,)
+                scale = max(np.abs(full[r]).max() for r in ref)
+                assert np.abs(full[k] - fc[k]).max() <= 1e-5 * scale, k
+
+
+def test_cold_start_matches_oracle(nf, oracle):
+    """Every solve started from zero (warm start off) against the oracle run
+    the same way."""
+    case = C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3, n_steps=3, tol=1e-9,
+                       precision=C.PREC_FP64)
+    g = nf.Grid(case)
+    nf.nfvm_set_option(g.h, nf.NFVM_OPT_WARM_START, 0)
+    s, stats = g.step(3)
+    out = g.fields()
+    g.close()
+    cyc = [x["cycles"] for x in stats]
+    ref, _, _ = oracle.step(case, 3, forced_cycles=cyc, warm=False)
+    errs = field_errors(case, out, ref)
+    print("   cycles", cyc, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for f in ("vel", "p", "k", "omega", "T"):
+        assert errs[f] <= 1e-10, (f, errs[f])
 
 
 def test_error_paths(nf):

@@ -62,3 +62,18 @@ def test_mirror_symmetry_of_turbulent_channel(oracle):
         scale = np.abs(a).max()
         flip = a[:, ::-1, :] if ax == 1 else a[::-1, :, :]
         assert np.abs(a - sign * flip).max() <= 1e-11 * scale, name
+
+
+def test_warm_and_cold_started_steps_agree_to_tolerance(oracle):
+    """Starting each pressure solve from the previous step's increment changes
+    only where the iteration stops: after several steps both runs agree to the
+    solver tolerance.  (In this start-up transient the increments change a lot
+    from step to step, so the warm start saves no cycles here.)"""
+    c = C.channel2d(64, 16, n_steps=5, tol=1e-9)
+    warm, sw, s1 = oracle.step(c, 5, warm=True)
+    cold, sc, s2 = oracle.step(c, 5, warm=False)
+    assert s1 == 0 and s2 == 0
+    assert sw[0]["cycles"] == sc[0]["cycles"]  # first solve: both from 0
+    for k in ("u", "v", "p"):
+        scale = np.abs(cold[k]).max()
+        assert np.abs(warm[k] - cold[k]).max() <= 1e-6 * scale, k

@@ -164,3 +164,27 @@ def test_projection_identity_and_divergence_free(oracle):
     p, u, v, w, div = oracle.project(c, phi, us, vs, ws, np.zeros(fl.shape))
     assert div < 1e-11 * np.abs(b).max() * c.dt
     assert np.array_equal(p, phi)
+
+
+def test_solve_from_any_initial_guess(oracle):
+    """The solve reaches the dense solution from a nonzero initial guess, and
+    b = 0 gives exactly x = 0 whatever the guess (A is nonsingular with an
+    outlet face, so 0 is the only solution)."""
+    n = (16, 8, 8)
+    pats = [C.Patch(0, (0, 0), (8, 8), kind=C.INLET, U=(1, 0, 0)),
+            C.Patch(1, (0, 0), (8, 8), kind=C.OUTLET)]
+    c = box(n, (0.1, 0.12, 0.09), patches=pats, n_levels=4)
+    mg = oracle.MG(c)
+    act = mg.active(0).astype(bool)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(act.shape) * act
+    x0 = rng.standard_normal(act.shape) * act
+    cold, _, _, st0 = mg.solve(b, tol=1e-13, max_cycles=200)
+    warm, cyc, rel, st1 = mg.solve(b, x0, tol=1e-13, max_cycles=200)
+    assert st0 == 0 and st1 == 0 and cyc > 0
+    assert np.abs(warm - cold).max() <= 1e-10 * np.abs(cold).max()
+    # started at the solution: no cycle is needed and the guess is kept
+    again, cyc2, _, _ = mg.solve(b, cold, tol=1e-10, max_cycles=200)
+    assert cyc2 == 0 and np.array_equal(again, cold)
+    z, cyc3, rel3, st3 = mg.solve(np.zeros_like(b), x0, tol=1e-10, max_cycles=200)
+    assert st3 == 0 and cyc3 == 0 and not z.any()
