@@ -286,17 +286,24 @@ struct SmoothArgs {
 // registers; in-plane neighbours come through the cache.
 template <class S, class C, bool ZERO>
 __device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const TileCtx& c, bool) {
-  if (a.ctl[S_DONE] != 0.0) return;
+  // Coarse levels are small and their launches latency-bound: every load of
+  // a plane (stopping flag, class byte, right-hand side, neighbours, face
+  // coefficients; all indices lie in the padded arrays) goes out at once,
+  // and the flag and the class are tested only before the store.  The
+  // arithmetic is that of apply_z / diag_at, term for term.
   const LevelView& L = a.L;
   const S* __restrict__ xin = a.xin;
   S* __restrict__ xout = a.xout;
   const S* __restrict__ b = a.b;
   const C wj = a.wj;
   const Geom& g = L.g;
+  const bool done = a.ctl[S_DONE] != 0.0;
   const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
   const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
   const bool d3 = g.dim == 3;
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
   int P = g.idx(i, j, k0);
   C xm = 0, xc = 0;
   if (!ZERO) {
@@ -304,16 +311,40 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const Til
     if (d3) xm = St<S, C>::ld(xin + P - g.sxy);
   }
   for (int k = k0; k < k1; ++k, P += g.sxy) {
-    C xp = 0;
-    if (!ZERO && d3) xp = St<S, C>::ld(xin + P + g.sxy);
     const uint8_t cl = L.cls[P];
-    if (cl != MG_INACTIVE) {
-      const C bP = St<S, C>::ld(b + P);
-      C Ax, D;
-      if (ZERO) {
-        St<S, C>::st(xout + P, wj * bP / diag_at<C>(L, cl, P));
+    const C bP = St<S, C>::ld(b + P);
+    const C cxl = (C)L.cf0[P], cxh = (C)L.cf0[P + 1];
+    const C cyl = (C)L.cf1[P], cyh = (C)L.cf1[P + g.sx];
+    const C czl = d3 ? (C)L.cf2[P] : (C)0, czh = d3 ? (C)L.cf2[P + g.sxy] : (C)0;
+    C xp = 0, xl = 0, xh = 0, xs = 0, xn = 0;
+    if (!ZERO) {
+      if (d3) xp = St<S, C>::ld(xin + P + g.sxy);
+      xl = St<S, C>::ld(xin + P - 1);
+      xh = St<S, C>::ld(xin + P + 1);
+      xs = St<S, C>::ld(xin + P - g.sx);
+      xn = St<S, C>::ld(xin + P + g.sx);
+    }
+    if (!done && cl != MG_INACTIVE) {
+      const bool reg = cl == MG_REGULAR;
+      C D;
+      if (reg) {
+        D = (C)2 * (ih2x + ih2y);
+        if (d3) D += (C)2 * ih2z;
       } else {
-        apply_z<S, C>(L, cl, xin, P, xc, xm, xp, Ax, D);
+        D = (cxl + cxh) * ih2x + (cyl + cyh) * ih2y;
+        if (d3) D += (czl + czh) * ih2z;
+      }
+      if (ZERO) {
+        St<S, C>::st(xout + P, wj * bP / D);
+      } else {
+        C Ax;
+        if (reg) {
+          Ax = ((C)2 * xc - xl - xh) * ih2x + ((C)2 * xc - xs - xn) * ih2y;
+          if (d3) Ax += ((C)2 * xc - xm - xp) * ih2z;
+        } else {
+          Ax = (cxl * (xc - xl) + cxh * (xc - xh)) * ih2x + (cyl * (xc - xs) + cyh * (xc - xn)) * ih2y;
+          if (d3) Ax += (czl * (xc - xm) + czh * (xc - xp)) * ih2z;
+        }
         St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
       }
     }
@@ -1252,7 +1283,9 @@ template <class SC, class C>
 __device__ __forceinline__ void bottom_body(const Bottom& B, const SC* __restrict__ btop,
                                             SC* __restrict__ xtop,
                                             const double* __restrict__ ctl) {
-  if (ctl[S_DONE] != 0.0) return;
+  // the stopping flag is read with the image and tested after phase 0,
+  // which writes only LDS
+  const bool done = ctl[S_DONE] != 0.0;
   const int t = threadIdx.x, NT = blockDim.x;
   const int nl = B.nlev;
   const bool pre = B.nu1 > 0;
@@ -1300,6 +1333,7 @@ __device__ __forceinline__ void bottom_body(const Bottom& B, const SC* __restric
   int* cidx = (int*)(bot_lds + B.bcidx);
   const int nco = *B.ncount;
   __syncthreads();
+  if (done) return;  // uniform over the workgroup
   // current iterate buffer of every level, one bit per level (a bit mask
   // rather than an array keeps it in a register); x0 holds the first sweep
   unsigned curm = 0;

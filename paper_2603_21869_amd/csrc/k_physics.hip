@@ -89,14 +89,11 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
           if (d >= g.dim) continue;
           const int N = P + s * st[d];
           const uint8_t tn = type[N];
-          R vn[3], kn_, wn_;
-          if (is_fluid(tn)) {
-            vn[0] = u[N];
-            vn[1] = v[N];
-            vn[2] = w[N];
-            kn_ = kk[N];
-            wn_ = om[N];
-          } else {
+          // loaded whatever the neighbour's kind (every index lies in the
+          // padded arrays), so the loads do not wait for its type byte
+          R vn[3] = {(R)u[N], (R)v[N], (R)w[N]};
+          R kn_ = kk[N], wn_ = om[N];
+          if (!is_fluid(tn)) {
             const DevPatch& pp = pt[tn & 0x7f];
             for (int a = 0; a < 3; ++a) vn[a] = ghost<R>(pp, G_U + a, vel[a], ph.komega);
             kn_ = ghost<R>(pp, G_K, kP, ph.komega);
@@ -278,8 +275,10 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
     // the cell above: loaded once, the next centre
     const int Nz = C0 + g.sxy;
     const uint8_t tz_ = d3 ? type[Nz] : (uint8_t)1;
+    // loaded whatever its kind (every index lies in the padded arrays), so
+    // the loads do not wait for the type byte
     CellVals<R> cU;
-    if (d3 && is_fluid(tz_)) load_cell<V, F, P, R>(in, p, nut, Nz, komega, cU);
+    if (d3) load_cell<V, F, P, R>(in, p, nut, Nz, komega, cU);
     bool next_have = false;
     R Fhi[6], Uhi = 0;
     if (!is_fluid(tp)) {
@@ -308,14 +307,11 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
             CellVals<R> cN;
             const int N = C0 + s * st[d];
             const uint8_t tn = (d == 2 && s > 0) ? tz_ : type[N];
-            if (is_fluid(tn)) {
-              if (d == 2 && s > 0)
-                cN = cU;
-              else
-                load_cell<V, F, P, R>(in, p, nut, N, komega, cN);
-            } else {
-              ghost_cell<R>(pt[tn & 0x7f], cP, komega, cN);
-            }
+            if (d == 2 && s > 0)
+              cN = cU;
+            else
+              load_cell<V, F, P, R>(in, p, nut, N, komega, cN);
+            if (!is_fluid(tn)) ghost_cell<R>(pt[tn & 0x7f], cP, komega, cN);
             face_flux<R>(ph, cP, cN, d, s, ih[d], Ff, Uf);
             for (int a = 0; a < 3; ++a) vN[a] = cN.v[a];
             if (d == 2 && s > 0 && is_fluid(tn)) {
@@ -432,7 +428,8 @@ __global__ __launch_bounds__(BS) void k_rhs_b(Geom g, Phys ph, const uint8_t* __
         for (int s = -1; s <= 1; s += 2) {
           const int N = C0 + s * st[d];
           const uint8_t tn = type[N];
-          const O vn = is_fluid(tn) ? (O)vel[d][N] : ghost<O>(pt[tn & 0x7f], G_U + d, vp, ph.komega);
+          const O vf = (O)vel[d][N];  // loaded whatever the neighbour's kind
+          const O vn = is_fluid(tn) ? vf : ghost<O>(pt[tn & 0x7f], G_U + d, vp, ph.komega);
           fl[s > 0] = (O)0.5 * (vp + vn);
         }
         div += (fl[1] - fl[0]) * ih[d];
@@ -509,10 +506,12 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
         for (int s = -1; s <= 1; s += 2) {
           const int N = C0 + s * st[d];
           const uint8_t tn = type[N];
+          // loaded whatever the neighbour's kind
+          const O vf = (O)vel[d][N], ff = zero_inc ? (O)0 : phi[N];
           O vn, fN_ghost, fN_face, c;
           if (is_fluid(tn)) {
-            vn = (O)vel[d][N];
-            fN_ghost = zero_inc ? (O)0 : phi[N];
+            vn = vf;
+            fN_ghost = ff;
             fN_face = fN_ghost;
             c = 1;
           } else {

@@ -61,18 +61,32 @@ __device__ __forceinline__ double rid() {
   return OP == R_SUM ? 0.0 : (OP == R_MAX ? -INFINITY : INFINITY);
 }
 
-// Fixed-order tree reduction of NV values over a block of BS threads.
+// Fixed-order reduction of NV values over a block of BS threads (BS a
+// multiple of 64): a butterfly over the 64 lanes of each wave (lane l takes
+// l ^ 32, then l ^ 16, ..., l ^ 1; every lane ends with the same value, as
+// both operands of each step are the same pair), then every thread combines
+// the waves' results in wave order.  One barrier; every thread returns the
+// result.
 template <int NV, int OP, int BS>
 __device__ __forceinline__ void block_tree(double (&v)[NV], double (*sh)[BS]) {
+  static_assert(BS % 64 == 0, "block size must be whole waves");
+  constexpr int NW = BS / 64;
   const int t = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-  for (int q = 0; q < NV; ++q) sh[q][t] = v[q];
-  __syncthreads();
-  for (int s = BS / 2; s > 0; s >>= 1) {
-    if (t < s)
-      for (int q = 0; q < NV; ++q) sh[q][t] = rop<OP>(sh[q][t], sh[q][t + s]);
-    __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[q] = rop<OP>(v[q], __shfl_xor(v[q], off));
   }
-  for (int q = 0; q < NV; ++q) v[q] = sh[q][0];
+  if ((t & 63) == 0)
+    for (int q = 0; q < NV; ++q) sh[q][t >> 6] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double acc = sh[q][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) acc = rop<OP>(acc, sh[q][w]);
+    v[q] = acc;
+  }
 }
 
 // Every block stores its partial in red.partial[block * NV + q]; a separate
