@@ -219,42 +219,74 @@ __device__ __forceinline__ bool pack_entry(const Pack<A>& p, int& g, int& t) {
     if (v || PAD) BODY<NFVM_PASS TPLA>(a, c, v);                                              \
   }
 
-// A x and the diagonal at cell P, z neighbours given (the walking kernels
-// keep them in registers).
+// Coarse-level operator from class bytes and face coefficients.  The
+// neighbourhood of cell P is loaded in one go, before its class byte is
+// tested (coarse launches are small and latency-bound; every index lies in
+// the padded arrays); the z neighbours come from the walking kernels'
+// registers.
+template <class C>
+struct Nbhd {
+  C xl, xh, xs, xn;              // x neighbours: -x, +x, -y, +y
+  C cxl, cxh, cyl, cyh, czl, czh;  // face coefficients
+};
+
+// (x null: only the coefficients, for the diagonal)
 template <class S, class C>
-__device__ __forceinline__ void apply_z(const LevelView& L, uint8_t cl, const S* __restrict__ x,
-                                        int P, C xP, C xm, C xp, C& Ax, C& D) {
+__device__ __forceinline__ void load_nbhd(const LevelView& L, const S* __restrict__ x, int P,
+                                          Nbhd<C>& n) {
   const Geom& g = L.g;
-  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
-          ih2z = (C)(1.0 / (g.hz * g.hz));
-  const bool d3 = g.dim == 3;
-  if (cl == MG_REGULAR) {
-    C s = ((C)2 * xP - St<S, C>::ld(x + P - 1) - St<S, C>::ld(x + P + 1)) * ih2x +
-          ((C)2 * xP - St<S, C>::ld(x + P - g.sx) - St<S, C>::ld(x + P + g.sx)) * ih2y;
-    C d = (C)2 * (ih2x + ih2y);
-    if (d3) {
-      s += ((C)2 * xP - xm - xp) * ih2z;
-      d += (C)2 * ih2z;
-    }
-    Ax = s;
-    D = d;
-    return;
+  n.xl = n.xh = n.xs = n.xn = (C)0;
+  if (x) {
+    n.xl = St<S, C>::ld(x + P - 1);
+    n.xh = St<S, C>::ld(x + P + 1);
+    n.xs = St<S, C>::ld(x + P - g.sx);
+    n.xn = St<S, C>::ld(x + P + g.sx);
   }
-  const C cxl = (C)L.cf0[P], cxh = (C)L.cf0[P + 1];
-  const C cyl = (C)L.cf1[P], cyh = (C)L.cf1[P + g.sx];
-  C s = (cxl * (xP - St<S, C>::ld(x + P - 1)) + cxh * (xP - St<S, C>::ld(x + P + 1))) * ih2x +
-        (cyl * (xP - St<S, C>::ld(x + P - g.sx)) + cyh * (xP - St<S, C>::ld(x + P + g.sx))) * ih2y;
-  C d = (cxl + cxh) * ih2x + (cyl + cyh) * ih2y;
-  if (d3) {
-    const C czl = (C)L.cf2[P], czh = (C)L.cf2[P + g.sxy];
-    s += (czl * (xP - xm) + czh * (xP - xp)) * ih2z;
-    d += (czl + czh) * ih2z;
-  }
-  Ax = s;
-  D = d;
+  n.cxl = (C)L.cf0[P];
+  n.cxh = (C)L.cf0[P + 1];
+  n.cyl = (C)L.cf1[P];
+  n.cyh = (C)L.cf1[P + g.sx];
+  n.czl = g.dim == 3 ? (C)L.cf2[P] : (C)0;
+  n.czh = g.dim == 3 ? (C)L.cf2[P + g.sxy] : (C)0;
 }
 
-// Diagonal of A at cell P (active), formed as apply_z forms it.
+// A x at an active cell: regular cells (every face coefficient 1) take the
+// plain form, others the coefficient form.
+template <class C>
+__device__ __forceinline__ C apply_cls(const Geom& g, bool regular, const Nbhd<C>& n, C xP, C xm,
+                                       C xp) {
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
+  C s;
+  if (regular) {
+    s = ((C)2 * xP - n.xl - n.xh) * ih2x + ((C)2 * xP - n.xs - n.xn) * ih2y;
+    if (g.dim == 3) s += ((C)2 * xP - xm - xp) * ih2z;
+  } else {
+    s = (n.cxl * (xP - n.xl) + n.cxh * (xP - n.xh)) * ih2x +
+        (n.cyl * (xP - n.xs) + n.cyh * (xP - n.xn)) * ih2y;
+    if (g.dim == 3) s += (n.czl * (xP - xm) + n.czh * (xP - xp)) * ih2z;
+  }
+  return s;
+}
+
+// Diagonal of A at an active cell, formed as apply_cls forms it.
+template <class C>
+__device__ __forceinline__ C diag_cls(const Geom& g, bool regular, const Nbhd<C>& n) {
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
+  C d;
+  if (regular) {
+    d = (C)2 * (ih2x + ih2y);
+    if (g.dim == 3) d += (C)2 * ih2z;
+  } else {
+    d = (n.cxl + n.cxh) * ih2x + (n.cyl + n.cyh) * ih2y;
+    if (g.dim == 3) d += (n.czl + n.czh) * ih2z;
+  }
+  return d;
+}
+
+// Diagonal of A at cell P (active), formed as diag_cls forms it, with the
+// coefficients loaded here.
 template <class C>
 __device__ __forceinline__ C diag_at(const LevelView& L, uint8_t cl, int P) {
   const Geom& g = L.g;
@@ -287,10 +319,9 @@ struct SmoothArgs {
 template <class S, class C, bool ZERO>
 __device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const TileCtx& c, bool) {
   // Coarse levels are small and their launches latency-bound: every load of
-  // a plane (stopping flag, class byte, right-hand side, neighbours, face
-  // coefficients; all indices lie in the padded arrays) goes out at once,
-  // and the flag and the class are tested only before the store.  The
-  // arithmetic is that of apply_z / diag_at, term for term.
+  // a plane (stopping flag, class byte, right-hand side, neighbourhood) goes
+  // out at once, and the flag and the class are tested only before the
+  // store.
   const LevelView& L = a.L;
   const S* __restrict__ xin = a.xin;
   S* __restrict__ xout = a.xout;
@@ -302,8 +333,6 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const Til
   if (i >= g.nx || j >= g.ny) return;
   const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
   const bool d3 = g.dim == 3;
-  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
-          ih2z = (C)(1.0 / (g.hz * g.hz));
   int P = g.idx(i, j, k0);
   C xm = 0, xc = 0;
   if (!ZERO) {
@@ -313,40 +342,17 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const Til
   for (int k = k0; k < k1; ++k, P += g.sxy) {
     const uint8_t cl = L.cls[P];
     const C bP = St<S, C>::ld(b + P);
-    const C cxl = (C)L.cf0[P], cxh = (C)L.cf0[P + 1];
-    const C cyl = (C)L.cf1[P], cyh = (C)L.cf1[P + g.sx];
-    const C czl = d3 ? (C)L.cf2[P] : (C)0, czh = d3 ? (C)L.cf2[P + g.sxy] : (C)0;
-    C xp = 0, xl = 0, xh = 0, xs = 0, xn = 0;
-    if (!ZERO) {
-      if (d3) xp = St<S, C>::ld(xin + P + g.sxy);
-      xl = St<S, C>::ld(xin + P - 1);
-      xh = St<S, C>::ld(xin + P + 1);
-      xs = St<S, C>::ld(xin + P - g.sx);
-      xn = St<S, C>::ld(xin + P + g.sx);
-    }
+    Nbhd<C> n;
+    load_nbhd<S, C>(L, ZERO ? nullptr : xin, P, n);
+    C xp = 0;
+    if (!ZERO && d3) xp = St<S, C>::ld(xin + P + g.sxy);
     if (!done && cl != MG_INACTIVE) {
       const bool reg = cl == MG_REGULAR;
-      C D;
-      if (reg) {
-        D = (C)2 * (ih2x + ih2y);
-        if (d3) D += (C)2 * ih2z;
-      } else {
-        D = (cxl + cxh) * ih2x + (cyl + cyh) * ih2y;
-        if (d3) D += (czl + czh) * ih2z;
-      }
-      if (ZERO) {
+      const C D = diag_cls<C>(g, reg, n);
+      if (ZERO)
         St<S, C>::st(xout + P, wj * bP / D);
-      } else {
-        C Ax;
-        if (reg) {
-          Ax = ((C)2 * xc - xl - xh) * ih2x + ((C)2 * xc - xs - xn) * ih2y;
-          if (d3) Ax += ((C)2 * xc - xm - xp) * ih2z;
-        } else {
-          Ax = (cxl * (xc - xl) + cxh * (xc - xh)) * ih2x + (cyl * (xc - xs) + cyh * (xc - xn)) * ih2y;
-          if (d3) Ax += (czl * (xc - xm) + czh * (xc - xp)) * ih2z;
-        }
-        St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
-      }
+      else
+        St<S, C>::st(xout + P, xc + wj * (bP - apply_cls<C>(g, reg, n, xc, xm, xp)) / D);
     }
     xm = xc;
     xc = xp;
@@ -360,7 +366,9 @@ NFVM_TILE_KERNELS(k_smooth, smooth_body, SmoothArgs, (S, C), (class S, class C, 
 template <class S, class C, bool ZERO>
 __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, const TileCtx& c,
                                                  bool) {
-  if (a.ctl[S_DONE] != 0.0) return;
+  // the stopping flag is read with the first plane's loads and tested
+  // before the first store (no barrier in this kernel)
+  const bool done = a.ctl[S_DONE] != 0.0;
   const LevelView& L = a.L;
   const S* __restrict__ xin = a.xin;
   S* __restrict__ xout = a.xout;
@@ -376,6 +384,7 @@ __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, cons
     for (int k = k0; k < k1; ++k, P += g.sxy) {
       const uint32_t cd = L.code[P];
       const C bP = St<S, C>::ld(b + P);
+      if (done) return;
       if (cd != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, wj * bP / diag_code<C>(g, cd));
     }
     return;
@@ -391,6 +400,7 @@ __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, cons
     C A0, D0, A1, D1;
     apply_code<S, C>(g, c0, xin, P, xc, xm, xp, A0, D0);
     apply_code<S, C>(g, c1, xin, Q, xp, xc, xpp, A1, D1);
+    if (done) return;
     if (c0 != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, xc + wj * (b0 - A0) / D0);
     if (c1 != FACE_CODE_INACTIVE) St<S, C>::st(xout + Q, xp + wj * (b1 - A1) / D1);
     xm = xp;
@@ -402,6 +412,7 @@ __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, cons
     const C xp = d3 ? St<S, C>::ld(xin + P + g.sxy) : (C)0;
     C Ax, D;
     apply_code<S, C>(g, cd, xin, P, xc, xm, xp, Ax, D);
+    if (done) return;
     if (cd != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
   }
 }
@@ -465,16 +476,22 @@ __device__ __forceinline__ C resid_at(const LevelView& F, const S* __restrict__ 
     apply_code<S, C>(F.g, cd, x, P, xc, xm, xp, Ax, D);
     return cd != FACE_CODE_INACTIVE ? bP - Ax : (C)0;
   }
+  // coarse levels: every load goes out before the class byte is tested
   const uint8_t cl = F.cls[P];
+  const C bP = St<S, C>::ld(b + P);
+  Nbhd<C> n;
+  load_nbhd<S, C>(F, x, P, n);
   if (cl == MG_INACTIVE) return (C)0;
-  apply_z<S, C>(F, cl, x, P, xc, xm, xp, Ax, D);
-  return St<S, C>::ld(b + P) - Ax;
+  (void)D;
+  return bP - apply_cls<C>(F.g, cl == MG_REGULAR, n, xc, xm, xp);
 }
 
 template <class S, class C, class SC>
 __device__ __forceinline__ void restrict_body(const RestrictArgs<S, C, SC>& a, const TileCtx& c,
                                               bool) {
-  if (a.ctl[S_DONE] != 0.0) return;  // uniform over the workgroup
+  // the stopping flag (uniform over the workgroup) is read with the first
+  // loads and tested before the first store; no barrier in this kernel
+  const bool done = a.ctl[S_DONE] != 0.0;
   const LevelView& F = a.F;
   const LevelView& Cl = a.Cl;
   const S* __restrict__ x = a.x;
@@ -516,6 +533,7 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs<S, C, SC>& a, c
     }
     r0 += __shfl_xor(r0, 1);
     r1 += __shfl_xor(r1, 1);
+    if (done) return;
     if (in && !(lx & 1)) {
       const int PC = Cl.g.idx(i >> 1, J, K);
       const uint8_t ccl = Cl.cls[PC];
@@ -621,7 +639,9 @@ struct ProlongArgs {
 template <class S, class C, class SC>
 __device__ __forceinline__ void prolong_body(const ProlongArgs<S, C, SC>& a, const TileCtx& c,
                                              bool) {
-  if (a.ctl[S_DONE] != 0.0) return;
+  // the stopping flag is read with the first loads and tested before the
+  // first store (no barrier in this kernel)
+  const bool done = a.ctl[S_DONE] != 0.0;
   const LevelView& F = a.F;
   const LevelView& Cl = a.Cl;
   S* __restrict__ x = a.x;
@@ -668,6 +688,7 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs<S, C, SC>& a, con
         cz_hi = (C)Cl.cf2[PC + cg.sxy];
       }
     }
+    if (done) return;
     if (fc0 != MG_INACTIVE) {
       C Z = yc;
       if (d3) {
