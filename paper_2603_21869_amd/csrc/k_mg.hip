@@ -230,24 +230,38 @@ struct Nbhd {
   C cxl, cxh, cyl, cyh, czl, czh;  // face coefficients
 };
 
-// (x null: only the coefficients, for the diagonal)
-template <class S, class C>
-__device__ __forceinline__ void load_nbhd(const LevelView& L, const S* __restrict__ x, int P,
-                                          Nbhd<C>& n) {
+// Levels up to this many cells load the face coefficients of every cell up
+// front (latency-bound launches); larger ones only for irregular cells,
+// after the class byte (12 extra bytes per cell would cost bandwidth).
+constexpr long long NBHD_EAGER_CELLS = 1 << 20;
+
+template <class C>
+__device__ __forceinline__ void load_coef(const LevelView& L, int P, Nbhd<C>& n) {
   const Geom& g = L.g;
-  n.xl = n.xh = n.xs = n.xn = (C)0;
-  if (x) {
-    n.xl = St<S, C>::ld(x + P - 1);
-    n.xh = St<S, C>::ld(x + P + 1);
-    n.xs = St<S, C>::ld(x + P - g.sx);
-    n.xn = St<S, C>::ld(x + P + g.sx);
-  }
   n.cxl = (C)L.cf0[P];
   n.cxh = (C)L.cf0[P + 1];
   n.cyl = (C)L.cf1[P];
   n.cyh = (C)L.cf1[P + g.sx];
   n.czl = g.dim == 3 ? (C)L.cf2[P] : (C)0;
   n.czh = g.dim == 3 ? (C)L.cf2[P + g.sxy] : (C)0;
+}
+
+// Neighbour values (x null: none, for the diagonal alone) and, with eager,
+// the face coefficients.  Without eager the caller loads the coefficients
+// of irregular cells (load_coef) once the class byte is known.
+template <class S, class C>
+__device__ __forceinline__ void load_nbhd(const LevelView& L, const S* __restrict__ x, int P,
+                                          bool eager, Nbhd<C>& n) {
+  const Geom& g = L.g;
+  n.xl = n.xh = n.xs = n.xn = (C)0;
+  n.cxl = n.cxh = n.cyl = n.cyh = n.czl = n.czh = (C)0;
+  if (x) {
+    n.xl = St<S, C>::ld(x + P - 1);
+    n.xh = St<S, C>::ld(x + P + 1);
+    n.xs = St<S, C>::ld(x + P - g.sx);
+    n.xn = St<S, C>::ld(x + P + g.sx);
+  }
+  if (eager) load_coef<C>(L, P, n);
 }
 
 // A x at an active cell: regular cells (every face coefficient 1) take the
@@ -333,6 +347,7 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const Til
   if (i >= g.nx || j >= g.ny) return;
   const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
   const bool d3 = g.dim == 3;
+  const bool eager = g.cells() <= NBHD_EAGER_CELLS;
   int P = g.idx(i, j, k0);
   C xm = 0, xc = 0;
   if (!ZERO) {
@@ -343,9 +358,10 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs<S, C>& a, const Til
     const uint8_t cl = L.cls[P];
     const C bP = St<S, C>::ld(b + P);
     Nbhd<C> n;
-    load_nbhd<S, C>(L, ZERO ? nullptr : xin, P, n);
+    load_nbhd<S, C>(L, ZERO ? nullptr : xin, P, eager, n);
     C xp = 0;
     if (!ZERO && d3) xp = St<S, C>::ld(xin + P + g.sxy);
+    if (!eager && cl == MG_IRREGULAR) load_coef<C>(L, P, n);
     if (!done && cl != MG_INACTIVE) {
       const bool reg = cl == MG_REGULAR;
       const C D = diag_cls<C>(g, reg, n);
@@ -479,8 +495,10 @@ __device__ __forceinline__ C resid_at(const LevelView& F, const S* __restrict__ 
   // coarse levels: every load goes out before the class byte is tested
   const uint8_t cl = F.cls[P];
   const C bP = St<S, C>::ld(b + P);
+  const bool eager = F.g.cells() <= NBHD_EAGER_CELLS;
   Nbhd<C> n;
-  load_nbhd<S, C>(F, x, P, n);
+  load_nbhd<S, C>(F, x, P, eager, n);
+  if (!eager && cl == MG_IRREGULAR) load_coef<C>(F, P, n);
   if (cl == MG_INACTIVE) return (C)0;
   (void)D;
   return bP - apply_cls<C>(F.g, cl == MG_REGULAR, n, xc, xm, xp);
