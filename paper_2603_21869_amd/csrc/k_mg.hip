@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "nfvm_device.hpp"
@@ -52,17 +53,16 @@ __device__ __forceinline__ C face_c(uint32_t cd, int f) {
   return (C)(int)((cd >> (2 * f)) & 3u);
 }
 
-// A x and the diagonal at cell P from its face code, z neighbours given:
-// sum over faces of c_f (x_P - x_N) / h^2.
-template <class S, class C>
-__device__ __forceinline__ void apply_code(const Geom& g, uint32_t cd, const S* __restrict__ x,
-                                           int P, C xP, C xm, C xp, C& Ax, C& D) {
+// A x and the diagonal at a cell from its face code and the six neighbour
+// values (-x, +x, -y, +y, -z, +z): sum over faces of c_f (x_P - x_N) / h^2.
+template <class C>
+__device__ __forceinline__ void apply_code_v(const Geom& g, uint32_t cd, C xP, C xl, C xh, C xs,
+                                             C xn, C xm, C xp, C& Ax, C& D) {
   const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
           ih2z = (C)(1.0 / (g.hz * g.hz));
   const C cxl = face_c<C>(cd, 0), cxh = face_c<C>(cd, 1);
   const C cyl = face_c<C>(cd, 2), cyh = face_c<C>(cd, 3);
-  C s = (cxl * (xP - St<S, C>::ld(x + P - 1)) + cxh * (xP - St<S, C>::ld(x + P + 1))) * ih2x +
-        (cyl * (xP - St<S, C>::ld(x + P - g.sx)) + cyh * (xP - St<S, C>::ld(x + P + g.sx))) * ih2y;
+  C s = (cxl * (xP - xl) + cxh * (xP - xh)) * ih2x + (cyl * (xP - xs) + cyh * (xP - xn)) * ih2y;
   C d = (cxl + cxh) * ih2x + (cyl + cyh) * ih2y;
   if (g.dim == 3) {
     const C czl = face_c<C>(cd, 4), czh = face_c<C>(cd, 5);
@@ -71,6 +71,15 @@ __device__ __forceinline__ void apply_code(const Geom& g, uint32_t cd, const S* 
   }
   Ax = s;
   D = d;
+}
+
+// ... at cell P, the x and y neighbours loaded here, the z neighbours given
+// (the walking kernels keep them in registers).
+template <class S, class C>
+__device__ __forceinline__ void apply_code(const Geom& g, uint32_t cd, const S* __restrict__ x,
+                                           int P, C xP, C xm, C xp, C& Ax, C& D) {
+  apply_code_v<C>(g, cd, xP, St<S, C>::ld(x + P - 1), St<S, C>::ld(x + P + 1),
+                  St<S, C>::ld(x + P - g.sx), St<S, C>::ld(x + P + g.sx), xm, xp, Ax, D);
 }
 
 // Diagonal of A from a face code.
@@ -435,11 +444,76 @@ __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, cons
 NFVM_TILE_KERNELS(k_smooth_code, smooth_code_body, SmoothArgs, (S, C),
                   (class S, class C, bool ZERO), (S, C, ZERO), MBS, false)
 
+// Level-0 sweep over four consecutive x cells per thread (nx a multiple of
+// 4): one aligned 4-wide load per row (the centre row, the rows at y +- 1 and
+// the plane above), the two x neighbours past the ends, the four face codes
+// in one 8-byte load; a wave covers 256 cells of a row.  Inactive cells are
+// written as 0 (the value they always hold).  Per cell the arithmetic is
+// apply_code's.
+template <class S>
+struct Quad {
+  typedef S V __attribute__((ext_vector_type(4)));
+};
+// level-0 storage types (coarse-only BF16 has no four-wide form)
+template <class S>
+constexpr bool has_quad = !std::is_same<S, bf16>::value;
+
+template <class S, class C>
+__device__ __forceinline__ void smooth_code4_body(const SmoothArgs<S, C>& a, const TileCtx& c,
+                                                  bool) {
+  typedef typename Quad<S>::V V4;
+  const bool done = a.ctl[S_DONE] != 0.0;
+  const LevelView& L = a.L;
+  const S* __restrict__ xin = a.xin;
+  S* __restrict__ xout = a.xout;
+  const S* __restrict__ b = a.b;
+  const C wj = a.wj;
+  const Geom& g = L.g;
+  const int i0 = 4 * (c.tx * MBX + threadIdx.x), j = c.ty * MBY + threadIdx.y;
+  if (i0 >= g.nx || j >= g.ny) return;
+  const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
+  const bool d3 = g.dim == 3;
+  int P = g.idx(i0, j, k0);
+  V4 xc = *(const V4*)(xin + P);
+  V4 xm = d3 ? *(const V4*)(xin + P - g.sxy) : V4(0);
+  for (int k = k0; k < k1; ++k, P += g.sxy) {
+    const V4 xp = d3 ? *(const V4*)(xin + P + g.sxy) : V4(0);
+    const V4 xs = *(const V4*)(xin + P - g.sx), xn = *(const V4*)(xin + P + g.sx);
+    const V4 bb = *(const V4*)(b + P);
+    const C xl = St<S, C>::ld(xin + P - 1), xr = St<S, C>::ld(xin + P + 4);
+    const uint2 cw = *(const uint2*)(L.code + P);
+    if (done) return;
+    const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
+    const C xv[6] = {xl, (C)xc[0], (C)xc[1], (C)xc[2], (C)xc[3], xr};
+    V4 out;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      C A, D;
+      apply_code_v<C>(g, cd[q], xv[q + 1], xv[q], xv[q + 2], (C)xs[q], (C)xn[q], (C)xm[q],
+                      (C)xp[q], A, D);
+      out[q] = cd[q] != FACE_CODE_INACTIVE ? (S)(xv[q + 1] + wj * ((C)bb[q] - A) / D) : (S)0;
+    }
+    *(V4*)(xout + P) = out;
+    xm = xc;
+    xc = xp;
+  }
+}
+NFVM_TILE_KERNELS(k_smooth_code4, smooth_code4_body, SmoothArgs, (S, C), (class S, class C),
+                  (S, C), MBS, false)
+
+// Whether a level-0 sweep takes the four-cells-per-thread kernel.
+__host__ inline bool sweep_quad(const Level& l, bool from_zero) {
+  return l.code && !from_zero && l.g.nx % 4 == 0;
+}
+
 template <class S, class C>
 SmoothArgs<S, C> smooth_args(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                              const double* ctl) {
-  return SmoothArgs<S, C>{view(l),      lvl_tiles(l, from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH),
-                          (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl};
+  const int tk = from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH;
+  const Tiles T = sweep_quad(l, from_zero)
+                      ? make_tiles(l.g.nx / 4, l.g.ny, l.g.nz, l.tt[tk])
+                      : lvl_tiles(l, tk);
+  return SmoothArgs<S, C>{view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl};
 }
 
 template <class S, class C>
@@ -450,8 +524,11 @@ void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool 
   if (l.code) {
     if (from_zero)
       NFVM_LAUNCH((k_smooth_code<S, C, true>), G, B, 0, s, a);
-    else
+    else if (sweep_quad(l, false)) {
+      if constexpr (has_quad<S>) NFVM_LAUNCH((k_smooth_code4<S, C>), G, B, 0, s, a);
+    } else {
       NFVM_LAUNCH((k_smooth_code<S, C, false>), G, B, 0, s, a);
+    }
   } else if (from_zero) {
     NFVM_LAUNCH((k_smooth<S, C, true>), G, B, 0, s, a);
   } else {
@@ -1665,17 +1742,21 @@ void emit_blocks(BatchOps& o, const std::vector<A>& args, K kern, int threads, s
 // zero or not.
 template <class S, class C>
 struct SweepGroups {
-  Group<SmoothArgs<S, C>> g[2][2];  // [code][zero]
+  // [class bytes, face codes, face codes four cells per thread][from zero]
+  Group<SmoothArgs<S, C>> g[3][2];
   void add(const Level& l, double wj, bool zero, const double* ctl) {
     const void* xin = zero ? nullptr : l.x[l.cur];
     void* xout = zero ? l.x[0] : l.x[l.cur ^ 1];
-    g[l.code != nullptr][zero].push_back(smooth_args<S, C>(l, xin, xout, wj, zero, ctl));
+    const int kind = sweep_quad(l, zero) ? 2 : (l.code != nullptr ? 1 : 0);
+    g[kind][zero].push_back(smooth_args<S, C>(l, xin, xout, wj, zero, ctl));
   }
   void emit(BatchOps& o) const {
     emit_tiles(o, g[0][0], k_smooth<S, C, false>, k_smooth_batch<S, C, false>, false);
     emit_tiles(o, g[0][1], k_smooth<S, C, true>, k_smooth_batch<S, C, true>, false);
     emit_tiles(o, g[1][0], k_smooth_code<S, C, false>, k_smooth_code_batch<S, C, false>, false);
     emit_tiles(o, g[1][1], k_smooth_code<S, C, true>, k_smooth_code_batch<S, C, true>, false);
+    if constexpr (has_quad<S>)
+      emit_tiles(o, g[2][0], k_smooth_code4<S, C>, k_smooth_code4_batch<S, C>, false);
   }
 };
 

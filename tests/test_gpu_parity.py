@@ -28,8 +28,11 @@ def nf():
 
 
 def small_cases():
+    # nx = 90 is not a multiple of 4: the level-0 sweep takes its one-cell
+    # form there (the others take the four-cell form)
     return [
         ("ch2d", C.channel2d(96, 18, L=4.0, H=1.0, n_levels=2, n_steps=3)),
+        ("ch2d_nx90", C.channel2d(90, 18, L=4.0, H=1.0, n_levels=2, n_steps=3)),
         ("ch3d", C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3, n_steps=3, tol=1e-8)),
         ("room", C.room3d(64, 24, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4, n_steps=2)),
     ]
