@@ -212,6 +212,7 @@ class GridT : public GridBase {
   int* ncount = nullptr;
   double* work = nullptr;
   double* hs = nullptr;  // host-coherent mirror of the scalars (written by the device)
+  double* tune_out = nullptr;  // scratch scalars of the autotuner's CG launches
   hipEvent_t ev_step[2][2] = {};  // start / end of the last two steps
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
@@ -387,6 +388,13 @@ class GridT : public GridBase {
     red.partial = alloc<double>((size_t)red.max_blocks * 3);
     red.counter = alloc<unsigned>(16);
     red.out = alloc<double>(S_COUNT);
+    {
+      double init[S_COUNT] = {};
+      init[S_FORCED] = 1e30;
+      tune_out = alloc<double>(S_COUNT);
+      NFVM_CK(hipMemcpyAsync(tune_out, init, sizeof init, hipMemcpyHostToDevice, stream));
+      NFVM_CK(hipStreamSynchronize(stream));
+    }
     NFVM_CK(hipHostGetDevicePointer((void**)&red.mirror, hs, 0));
 
     for (int t = 0; t < TP_COUNT; ++t) tp[t] = TILE_DEFAULT;
@@ -487,13 +495,19 @@ class GridT : public GridBase {
           launch_fcg_start<O, S0>(v, bvec, x0, r, phi, red, false, 1.0, 1, -1, stream, false,
                                   zero0(), wj);
         });
+        // the CG passes are timed with their finalising kernels (the block
+        // count they sum grows with the tile count), on scratch scalars whose
+        // stopping rule never fires (forced count 1e30)
+        RedBuf tr = red;
+        tr.out = tune_out;
+        tr.mirror = nullptr;
         v.tt[TK_APPLY] = tune_one(TK_APPLY, v.g, [&](int tt) {
           v.tt[TK_APPLY] = tt;
-          launch_fcg_apply<O, S0>(v, r, q, wv, red, stream, false);
+          launch_fcg_apply<O, S0>(v, r, q, wv, tr, stream, true);
         });
         v.tt[TK_UPDATE] = tune_one(TK_UPDATE, v.g, [&](int tt) {
           v.tt[TK_UPDATE] = tt;
-          launch_fcg_update<O, S0>(v, phi, r, pv, q, wv, red, stream, false, zero0(), wj);
+          launch_fcg_update<O, S0>(v, phi, r, pv, q, wv, tr, stream, true, zero0(), wj);
         });
       } else {
         v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + 1000, v.g, [&](int tt) {

@@ -1063,6 +1063,67 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<O, S>& a, const TileC
 NFVM_TILE_KERNELS(k_fcg_apply, apply_body, ApplyArgs, (O, S), (class O, class S), (O, S), MBS,
                   true)
 
+// The same over four consecutive x cells per thread (nx a multiple of 4),
+// with four-wide loads and stores as in k_smooth_code4; inactive cells get
+// w = 0 (never read).
+template <class O, class S>
+__device__ __forceinline__ void apply4_body(const ApplyArgs<O, S>& a, const TileCtx& c,
+                                            bool valid) {
+  typedef typename Quad<S>::V S4;
+  typedef typename Quad<O>::V O4;
+  const RedBuf& red = a.red;
+  if (red.out[S_DONE] != 0.0) return;
+  const LevelView& L = a.L;
+  const S* __restrict__ z = a.z;
+  const O* __restrict__ r = a.r;
+  const O* __restrict__ q = a.q;
+  O* __restrict__ w = a.w;
+  double zr = 0.0, zq = 0.0, zw = 0.0;
+  if (valid) {
+    const Geom& g = L.g;
+    const int i0 = 4 * (c.tx * MBX + threadIdx.x), j = c.ty * MBY + threadIdx.y;
+    if (i0 < g.nx && j < g.ny) {
+      const bool d3 = g.dim == 3;
+      const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
+      int P = g.idx(i0, j, k0);
+      S4 zc = *(const S4*)(z + P);
+      S4 zm = d3 ? *(const S4*)(z + P - g.sxy) : S4(0);
+      for (int k = k0; k < k1; ++k, P += g.sxy) {
+        const S4 zp = d3 ? *(const S4*)(z + P + g.sxy) : S4(0);
+        const S4 zs = *(const S4*)(z + P - g.sx), zn = *(const S4*)(z + P + g.sx);
+        const O zl = St<S, O>::ld(z + P - 1), zh = St<S, O>::ld(z + P + 4);
+        const uint2 cw = *(const uint2*)(L.code + P);
+        const O4 rv = *(const O4*)(r + P), qv = *(const O4*)(q + P);
+        const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
+        const O zv[6] = {zl, (O)zc[0], (O)zc[1], (O)zc[2], (O)zc[3], zh};
+        O4 wv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          O Az = 0, D;
+          if (cd[e] != FACE_CODE_INACTIVE) {
+            apply_code_v<O>(g, cd[e], zv[e + 1], zv[e], zv[e + 2], (O)zs[e], (O)zn[e], (O)zm[e],
+                            (O)zp[e], Az, D);
+            zr += (double)zv[e + 1] * (double)rv[e];
+            zq += (double)zv[e + 1] * (double)qv[e];
+            zw += (double)zv[e + 1] * (double)Az;
+          }
+          wv[e] = Az;
+        }
+        *(O4*)(w + P) = wv;
+        zm = zc;
+        zc = zp;
+      }
+    }
+  }
+  double vv[3] = {zr, zq, zw};
+  block_partial<3, R_SUM, MBS>(vv, red, c.pb);
+}
+NFVM_TILE_KERNELS(k_fcg_apply4, apply4_body, ApplyArgs, (O, S), (class O, class S), (O, S), MBS,
+                  true)
+
+// Whether the level-0 CG passes take their four-cells-per-thread kernels.
+__host__ inline bool cg_quad(const Level& l0) { return l0.code && l0.g.nx % 4 == 0; }
+
 constexpr int FIN_NV3 = 3;
 
 // Arguments of the one-workgroup finalising kernels (one workgroup per grid
@@ -1099,14 +1160,19 @@ __global__ __launch_bounds__(FIN) void k_fin_apply_batch(Pack<FinArgs> f) {
 
 template <class O, class S>
 ApplyArgs<O, S> apply_args(const Level& l0, const O* r, const O* q, O* w, const RedBuf& red) {
-  return ApplyArgs<O, S>{view(l0), lvl_tiles(l0, TK_APPLY), (const S*)l0.x[l0.cur], r, q, w, red};
+  const Tiles T = cg_quad(l0) ? make_tiles(l0.g.nx / 4, l0.g.ny, l0.g.nz, l0.tt[TK_APPLY])
+                              : lvl_tiles(l0, TK_APPLY);
+  return ApplyArgs<O, S>{view(l0), T, (const S*)l0.x[l0.cur], r, q, w, red};
 }
 
 template <class O, class S>
 void launch_fcg_apply(const Level& l0, const O* r, const O* q, O* w, const RedBuf& red,
                       hipStream_t s, bool fin) {
   const ApplyArgs<O, S> a = apply_args<O, S>(l0, r, q, w, red);
-  NFVM_LAUNCH((k_fcg_apply<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  if (cg_quad(l0))
+    NFVM_LAUNCH((k_fcg_apply4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  else
+    NFVM_LAUNCH((k_fcg_apply<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   if (fin) hipLaunchKernelGGL(k_fin_apply, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
 
@@ -1171,6 +1237,72 @@ __device__ __forceinline__ void update_body(const UpdateArgs<O, S>& A, const Til
 NFVM_TILE_KERNELS(k_fcg_update, update_body, UpdateArgs, (O, S), (class O, class S), (O, S), MBS,
                   true)
 
+// The same over four consecutive x cells per thread (nx a multiple of 4);
+// inactive cells keep their values (p, q, x, r written back as read; the
+// right-hand side and first sweep written as 0, the value they hold).
+template <class O, class S>
+__device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const TileCtx& c,
+                                             bool valid) {
+  typedef typename Quad<S>::V S4;
+  typedef typename Quad<O>::V O4;
+  const RedBuf& red = A.red;
+  if (red.out[S_DONE] != 0.0) return;
+  const LevelView& L = A.L;
+  O* __restrict__ x = A.x;
+  O* __restrict__ r = A.r;
+  O* __restrict__ p = A.p;
+  O* __restrict__ q = A.q;
+  const O* __restrict__ w = A.w;
+  const S* __restrict__ z = A.z;
+  const bool first = red.out[S_ITER] == 0.0;
+  const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA];
+  double rr = 0.0;
+  if (valid) {
+    const Geom& g = L.g;
+    const int i0 = 4 * (c.tx * MBX + threadIdx.x), j = c.ty * MBY + threadIdx.y;
+    if (i0 < g.nx && j < g.ny) {
+      const int k0 = c.tz * A.T.cz, k1 = min(g.nz, k0 + A.T.cz);
+      for (int k = k0; k < k1; ++k) {
+        const int P = g.idx(i0, j, k);
+        const uint2 cw = *(const uint2*)(L.code + P);
+        const S4 zv = *(const S4*)(z + P);
+        O4 pv = *(const O4*)(p + P), qv = *(const O4*)(q + P);
+        O4 xv = *(const O4*)(x + P), rv = *(const O4*)(r + P);
+        const O4 wv = *(const O4*)(w + P);
+        const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
+        S4 b0v = S4(0), z0v = S4(0);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (cd[e] == FACE_CODE_INACTIVE) continue;
+          const O zP = (O)zv[e];  // S is FP32 or FP64 on level 0
+          const O pP = first ? zP : zP + be * pv[e];
+          const O qP = first ? wv[e] : wv[e] + be * qv[e];
+          pv[e] = pP;
+          qv[e] = qP;
+          xv[e] += a * pP;
+          const O rP = rv[e] - a * qP;
+          rv[e] = rP;
+          S bs;
+          St<S, O>::st(&bs, rP);
+          b0v[e] = bs;
+          if (A.z0) z0v[e] = A.wj * bs / diag_code<S>(g, cd[e]);
+          rr += (double)rP * (double)rP;
+        }
+        *(O4*)(p + P) = pv;
+        *(O4*)(q + P) = qv;
+        *(O4*)(x + P) = xv;
+        *(O4*)(r + P) = rv;
+        *(S4*)(A.b0 + P) = b0v;
+        if (A.z0) *(S4*)(A.z0 + P) = z0v;
+      }
+    }
+  }
+  double vv[1] = {rr};
+  block_partial<1, R_SUM, MBS>(vv, red, c.pb);
+}
+NFVM_TILE_KERNELS(k_fcg_update4, update4_body, UpdateArgs, (O, S), (class O, class S), (O, S),
+                  MBS, true)
+
 // ||r||^2, one more iteration done, stopping rule
 __device__ __forceinline__ void fin_update_body(const FinArgs& f) {
   const RedBuf& red = f.red;
@@ -1192,15 +1324,20 @@ __global__ __launch_bounds__(FIN) void k_fin_update_batch(Pack<FinArgs> f) {
 template <class O, class S>
 UpdateArgs<O, S> update_args(const Level& l0, O* x, O* r, O* p, O* q, const O* w,
                              const RedBuf& red, void* z0, double wj) {
-  return UpdateArgs<O, S>{view(l0), lvl_tiles(l0, TK_UPDATE), x, r, p, q, w,
-                          (const S*)l0.x[l0.cur], (S*)l0.b, (S*)z0, (S)wj, red};
+  const Tiles T = cg_quad(l0) ? make_tiles(l0.g.nx / 4, l0.g.ny, l0.g.nz, l0.tt[TK_UPDATE])
+                              : lvl_tiles(l0, TK_UPDATE);
+  return UpdateArgs<O, S>{view(l0), T, x, r, p, q, w, (const S*)l0.x[l0.cur], (S*)l0.b, (S*)z0,
+                          (S)wj, red};
 }
 
 template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const O* w, const RedBuf& red,
                        hipStream_t s, bool fin, void* z0, double wj) {
   const UpdateArgs<O, S> a = update_args<O, S>(l0, x, r, p, q, w, red, z0, wj);
-  NFVM_LAUNCH((k_fcg_update<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  if (cg_quad(l0))
+    NFVM_LAUNCH((k_fcg_update4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  else
+    NFVM_LAUNCH((k_fcg_update<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   if (fin) hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
 
@@ -1910,30 +2047,32 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
     }
   }
   // CG: w = A z with its dot products, then the vector update
-  Group<ApplyArgs<O, S0>> ap;
-  Group<UpdateArgs<O, S0>> up;
+  Group<ApplyArgs<O, S0>> ap[2];  // [one cell, four cells per thread]
+  Group<UpdateArgs<O, S0>> up[2];
   Group<FinArgs> fa, fu;
   for (int i = 0; i < n; ++i) {
     MgGridDesc& d = G[i];
     const auto a = apply_args<O, S0>(d.lv[0], (const O*)d.r, (const O*)d.q, (O*)d.w, d.red);
-    ap.push_back(a);
+    ap[cg_quad(d.lv[0])].push_back(a);
     fa.push_back(FinArgs{d.red, a.T.grid});
   }
   for (int i = 0; i < n; ++i) {
     MgGridDesc& d = G[i];
     const auto a = update_args<O, S0>(d.lv[0], (O*)d.x, (O*)d.r, (O*)d.p, (O*)d.q,
                                       (const O*)d.w, d.red, d.zero[0], d.wj);
-    up.push_back(a);
+    up[cg_quad(d.lv[0])].push_back(a);
     fu.push_back(FinArgs{d.red, a.T.grid});
   }
-  emit_tiles(o, ap, k_fcg_apply<O, S0>, k_fcg_apply_batch<O, S0>, true);
+  emit_tiles(o, ap[0], k_fcg_apply<O, S0>, k_fcg_apply_batch<O, S0>, true);
+  emit_tiles(o, ap[1], k_fcg_apply4<O, S0>, k_fcg_apply4_batch<O, S0>, true);
   if (n == 1)
     o.ops.push_back([f = fa[0]](const unsigned char*, hipStream_t s) {
       hipLaunchKernelGGL(k_fin_apply, dim3(1), dim3(FIN), 0, s, f);
     });
   else
     emit_packed_blocks(o, fa, k_fin_apply_batch, FIN);
-  emit_tiles(o, up, k_fcg_update<O, S0>, k_fcg_update_batch<O, S0>, true);
+  emit_tiles(o, up[0], k_fcg_update<O, S0>, k_fcg_update_batch<O, S0>, true);
+  emit_tiles(o, up[1], k_fcg_update4<O, S0>, k_fcg_update4_batch<O, S0>, true);
   if (n == 1)
     o.ops.push_back([f = fu[0]](const unsigned char*, hipStream_t s) {
       hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, f);
