@@ -87,11 +87,13 @@ def make_case(name: str, precision: int, tol: float):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(case, steps: int, warmup: int, profile: bool, stream: int, graphs: bool = True):
+def run_gpu(case, steps: int, warmup: int, profile: bool, stream: int, graphs: bool = True,
+            warm_start: bool = False):
     import torch
     from paper_2603_21869_amd import nfvm
     g = nfvm.Grid(case, stream=stream)
     nfvm.nfvm_set_option(g.h, nfvm.NFVM_OPT_GRAPHS, 1.0 if graphs else 0.0)
+    nfvm.nfvm_set_option(g.h, nfvm.NFVM_OPT_WARM_START, 1.0 if warm_start else 0.0)
     if warmup:
         g.step(warmup, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
     torch.cuda.synchronize()
@@ -277,6 +279,12 @@ def main():
 
     variants = {}
     if not args.no_variants:
+        # the same workload with each solve started from the previous step's
+        # increment (NFVM_OPT_WARM_START; the default starts from zero)
+        sw, stw, _, _ = run_gpu(case, args.steps, args.warmup, False, stream, warm_start=True)
+        variants[args.precision + "_warm_start"] = dict(
+            value=case.ncells * args.steps / sw / 1e6, ms_per_step=sw / args.steps * 1e3,
+            mean_cycles=sum(x["cycles"] for x in stw) / len(stw))
         for pname, pv in (("fp64", C.PREC_FP64), ("fp32", C.PREC_FP32), ("mixed", C.PREC_MIXED)):
             if pv == prec:
                 continue

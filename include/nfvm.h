@@ -253,16 +253,15 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
  *                     kernel is chosen per level by timing candidates on the
  *                     grid; results are cached per shape and precision for
  *                     the process.  0: fixed default tiles.
- *   NFVM_OPT_WARM_START 1 (default): each step's pressure solve starts from
- *                     the previous step's increment phi = p^{n+1} - p^n
+ *   NFVM_OPT_WARM_START 0 (default): every step's pressure solve starts
+ *                     from phi = 0, and restarts through nfvm_get_fields /
+ *                     nfvm_set_fields are bitwise.  1: each solve starts
+ *                     from the previous step's increment phi = p^{n+1} - p^n
  *                     (zero after nfvm_init_grid, nfvm_set_fields and
- *                     nfvm_mg_solve; Algorithm 1 likewise starts from the
- *                     state it is given).  The increment is not part of the
- *                     fields, so a run restarted through nfvm_get_fields /
- *                     nfvm_set_fields starts its first solve from zero and
- *                     agrees with the uninterrupted run to the solver
- *                     tolerance, not bitwise; 0: every solve starts from
- *                     zero, and restarts are bitwise.
+ *                     nfvm_mg_solve), which saves cycles in a slowly
+ *                     varying flow; the increment is not part of the
+ *                     fields, so a restarted run then agrees with the
+ *                     uninterrupted one to the solver tolerance only.
  * Errors: NFVM_E_INVAL for an unknown option. */
 enum {
   NFVM_OPT_GRAPHS = 0,

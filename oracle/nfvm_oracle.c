@@ -899,9 +899,8 @@ int orc_step(const orc_case* c, orc_fields* s, int n_steps, const int* forced,
     }
     orc_explicit(c, s, &t);
     orc_rhs_b(c, t.u, t.v, t.w, b);
-    /* initial guess: the previous step's increment phi = p^{n} - p^{n-1}
-     * (Algorithm 1 iterates from the state it is given; with the
-     * incremental pressure the state is the last increment), else zero */
+    /* initial guess: zero, or with warm the previous step's increment
+     * phi = p^{n} - p^{n-1} */
     if (!warm) memset(phi, 0, sizeof(double) * N);
     int cyc = 0;
     double rel = 0.0, mdiv = 0.0;

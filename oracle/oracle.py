@@ -163,10 +163,10 @@ def _fresh(case) -> Dict[str, np.ndarray]:
 
 
 def step(case, n_steps: Optional[int] = None, forced_cycles: Optional[Sequence[int]] = None,
-         fields: Optional[Dict[str, np.ndarray]] = None, warm: bool = True):
+         fields: Optional[Dict[str, np.ndarray]] = None, warm: bool = False):
     """Run n_steps time steps from the case's initial fields (or ``fields``).
-    With ``warm`` each pressure solve starts from the previous step's
-    increment (zero at the first step), else from zero.
+    Each pressure solve starts from zero; with ``warm`` from the previous
+    step's increment instead (zero at the first step).
 
     Returns (fields, stats list, status)."""
     L = lib()

@@ -116,7 +116,7 @@ class GridBase {
   virtual void set_option(int opt, double v) = 0;
   bool use_graphs = true;
   bool use_bottom = true;
-  bool use_warm = true;
+  bool use_warm = false;
   bool use_autotune = true;
   // kernel timing (nfvm_profile)
   struct ProfRec {

@@ -108,9 +108,9 @@ def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
 
 
 def test_deterministic_and_restartable(nf):
-    """Two runs give bitwise equal fields.  With every solve started from zero,
-    N + N steps with a get/set of the fields in between equal 2N steps
-    bitwise; with the warm start (the default) the restarted run's first solve
+    """Two runs give bitwise equal fields.  With every solve started from zero
+    (the default), N + N steps with a get/set of the fields in between equal
+    2N steps bitwise; with the warm start the restarted run's first solve
     starts from zero instead of the previous increment, so the two agree to
     the solver tolerance."""
     case = C.room3d(64, 24, 16, seed=2, n_levels=4, precision=C.PREC_MIXED)
@@ -123,7 +123,7 @@ def test_deterministic_and_restartable(nf):
         g.close()
         return f
 
-    fa, fd = run(4, True), run(4, True)
+    fa, fd = run(4, False), run(4, False)
     for k in fa:
         assert np.array_equal(fa[k], fd[k]), k
     for warm in (False, True):
@@ -143,18 +143,18 @@ def test_deterministic_and_restartable(nf):
                 assert np.abs(full[k] - fc[k]).max() <= 1e-5 * scale, k
 
 
-def test_cold_start_matches_oracle(nf, oracle):
-    """Every solve started from zero (warm start off) against the oracle run
-    the same way."""
+def test_warm_start_matches_oracle(nf, oracle):
+    """Every solve started from the previous step's increment (warm start
+    on) against the oracle run the same way."""
     case = C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3, n_steps=3, tol=1e-9,
                        precision=C.PREC_FP64)
     g = nf.Grid(case)
-    nf.nfvm_set_option(g.h, nf.NFVM_OPT_WARM_START, 0)
+    nf.nfvm_set_option(g.h, nf.NFVM_OPT_WARM_START, 1)
     s, stats = g.step(3)
     out = g.fields()
     g.close()
     cyc = [x["cycles"] for x in stats]
-    ref, _, _ = oracle.step(case, 3, forced_cycles=cyc, warm=False)
+    ref, _, _ = oracle.step(case, 3, forced_cycles=cyc, warm=True)
     errs = field_errors(case, out, ref)
     print("   cycles", cyc, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for f in ("vel", "p", "k", "omega", "T"):
