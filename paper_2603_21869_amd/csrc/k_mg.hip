@@ -645,11 +645,88 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs<S, C, SC>& a, c
 NFVM_TILE_KERNELS(k_resid_restrict, restrict_body, RestrictArgs, (S, C, SC),
                   (class S, class C, class SC), (S, C, SC), MBS, false)
 
+// Level 0 with nx a multiple of 4: one thread per four fine columns (two
+// coarse cells) and coarse row J, with four-wide loads of the rows 2J - 1 ..
+// 2J + 2, the right-hand sides and the face codes.  The sums are formed in
+// the order of restrict_body, so the results are the same.
+template <class S, class C, class SC>
+__device__ __forceinline__ void restrict4_body(const RestrictArgs<S, C, SC>& a, const TileCtx& c,
+                                               bool) {
+  typedef typename Quad<S>::V V4;
+  const bool done = a.ctl[S_DONE] != 0.0;
+  const LevelView& F = a.F;
+  const LevelView& Cl = a.Cl;
+  const S* __restrict__ x = a.x;
+  const S* __restrict__ b = a.b;
+  const Geom& g = F.g;
+  const int i0 = 4 * (c.tx * MBX + threadIdx.x), J = c.ty * MBY + threadIdx.y;
+  if (i0 >= g.nx || J >= Cl.g.ny) return;
+  const bool d3 = g.dim == 3;
+  const int K0 = c.tz * a.T.cz, K1 = min(Cl.g.nz, K0 + a.T.cz);
+  const int kz = d3 ? 2 : 1;
+  int P0 = g.idx(i0, 2 * J, kz * K0);  // row 2J; row 2J + 1 is P0 + sx
+  // centre and lower plane of both rows
+  V4 xc0 = *(const V4*)(x + P0), xc1 = *(const V4*)(x + P0 + g.sx);
+  V4 xm0 = d3 ? *(const V4*)(x + P0 - g.sxy) : V4(0);
+  V4 xm1 = d3 ? *(const V4*)(x + P0 + g.sx - g.sxy) : V4(0);
+  for (int K = K0; K < K1; ++K) {
+    C r[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    for (int cc = 0; cc < kz; ++cc, P0 += g.sxy) {
+      const int P1 = P0 + g.sx;
+      const V4 xp0 = d3 ? *(const V4*)(x + P0 + g.sxy) : V4(0);
+      const V4 xp1 = d3 ? *(const V4*)(x + P1 + g.sxy) : V4(0);
+      const V4 ys = *(const V4*)(x + P0 - g.sx), yn = *(const V4*)(x + P1 + g.sx);
+      const V4 b0 = *(const V4*)(b + P0), b1 = *(const V4*)(b + P1);
+      const uint2 w0 = *(const uint2*)(F.code + P0), w1 = *(const uint2*)(F.code + P1);
+      const C l0 = St<S, C>::ld(x + P0 - 1), h0 = St<S, C>::ld(x + P0 + 4);
+      const C l1 = St<S, C>::ld(x + P1 - 1), h1 = St<S, C>::ld(x + P1 + 4);
+      const uint32_t cd0[4] = {w0.x & 0xFFFFu, w0.x >> 16, w0.y & 0xFFFFu, w0.y >> 16};
+      const uint32_t cd1[4] = {w1.x & 0xFFFFu, w1.x >> 16, w1.y & 0xFFFFu, w1.y >> 16};
+      const C v0[6] = {l0, (C)xc0[0], (C)xc0[1], (C)xc0[2], (C)xc0[3], h0};
+      const C v1[6] = {l1, (C)xc1[0], (C)xc1[1], (C)xc1[2], (C)xc1[3], h1};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        C A, D;
+        // row 2J: y neighbours are row 2J - 1 and row 2J + 1
+        apply_code_v<C>(g, cd0[e], v0[e + 1], v0[e], v0[e + 2], (C)ys[e], (C)xc1[e], (C)xm0[e],
+                        (C)xp0[e], A, D);
+        r[0][e] += cd0[e] != FACE_CODE_INACTIVE ? (C)b0[e] - A : (C)0;
+        // row 2J + 1: y neighbours are row 2J and row 2J + 2
+        apply_code_v<C>(g, cd1[e], v1[e + 1], v1[e], v1[e + 2], (C)xc0[e], (C)yn[e], (C)xm1[e],
+                        (C)xp1[e], A, D);
+        r[1][e] += cd1[e] != FACE_CODE_INACTIVE ? (C)b1[e] - A : (C)0;
+      }
+      xm0 = xc0;
+      xc0 = xp0;
+      xm1 = xc1;
+      xc1 = xp1;
+    }
+    if (done) return;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int PC = Cl.g.idx((i0 >> 1) + h, J, K);
+      const uint8_t ccl = Cl.cls[PC];
+      if (ccl == MG_INACTIVE) continue;
+      const C s0 = r[0][2 * h] + r[0][2 * h + 1], s1 = r[1][2 * h] + r[1][2 * h + 1];
+      SC* dst = a.bc + PC;
+      St<SC, C>::st(dst, (s0 + s1) * (C)(d3 ? 0.125 : 0.25));
+      // first pre-smoothing sweep (from zero) of the coarse level
+      if (a.zc) St<SC, C>::st(a.zc + PC, a.wj * St<SC, C>::ld(dst) / diag_at<C>(Cl, ccl, PC));
+    }
+  }
+}
+NFVM_TILE_KERNELS(k_resid_restrict4, restrict4_body, RestrictArgs, (S, C, SC),
+                  (class S, class C, class SC), (S, C, SC), MBS, false)
+
+// Whether the restriction from fine level f takes the four-column kernel.
+__host__ inline bool restrict_quad(const Level& f) { return f.code && f.g.nx % 4 == 0; }
+
 template <class S, class C, class SC>
 RestrictArgs<S, C, SC> restrict_args(const Level& f, const Level& c, const double* ctl, void* zc,
                                      double wj) {
   return RestrictArgs<S, C, SC>{view(f),
-                                make_tiles(f.g.nx, c.g.ny, c.g.nz, f.tt[TK_RESTRICT]),
+                                make_tiles(restrict_quad(f) ? f.g.nx / 4 : f.g.nx, c.g.ny,
+                                           c.g.nz, f.tt[TK_RESTRICT]),
                                 (const S*)f.x[f.cur],
                                 (const S*)f.b,
                                 view(c),
@@ -663,7 +740,12 @@ template <class S, class C, class SC>
 void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s,
                            void* zc, double wj) {
   const RestrictArgs<S, C, SC> a = restrict_args<S, C, SC>(f, c, ctl, zc, wj);
-  NFVM_LAUNCH((k_resid_restrict<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  if (restrict_quad(f)) {
+    if constexpr (has_quad<S>)
+      NFVM_LAUNCH((k_resid_restrict4<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  } else {
+    NFVM_LAUNCH((k_resid_restrict<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  }
 }
 
 // ---- prolongation and correction: x_f += PROL(e_c) ------------------------------
@@ -1968,19 +2050,23 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
       g0.emit(o);
       gc.emit(o);
     }
-    Group<RestrictArgs<S0, C, SC>> r0;
+    Group<RestrictArgs<S0, C, SC>> r0, r0q;
     Group<RestrictArgs<SC, C, SC>> rc;
     for (int i = 0; i < n; ++i) {
       MgGridDesc& d = G[i];
       if (l >= stop_level(d)) continue;
       if (l == 0) {
-        r0.push_back(restrict_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out, d.zero[1], d.wj));
+        (restrict_quad(d.lv[0]) ? r0q : r0)
+            .push_back(restrict_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out, d.zero[1], d.wj));
       } else {
         rc.push_back(
             restrict_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out, d.zero[l + 1], d.wj));
       }
     }
     emit_tiles(o, r0, k_resid_restrict<S0, C, SC>, k_resid_restrict_batch<S0, C, SC>, false);
+    if constexpr (has_quad<S0>)
+      emit_tiles(o, r0q, k_resid_restrict4<S0, C, SC>, k_resid_restrict4_batch<S0, C, SC>,
+                 false);
     emit_tiles(o, rc, k_resid_restrict<SC, C, SC>, k_resid_restrict_batch<SC, C, SC>, false);
   }
   // bottom solver or coarsest solve of every grid
