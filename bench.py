@@ -33,7 +33,15 @@ WORKLOADS = {
     "channel2d": "2D turbulent channel 256x64, 6 levels",
     "room": "3D ventilated room 512x256x128 with seeded blocks, 8 levels",
     "bigroom": "3D ventilated room 1024x512x256 with seeded blocks, 9 levels",
+    "open_channel_128": "open channel at 5 mm, 128x128x128 (L = 0.64 m), 8 levels",
+    "open_channel_512": "open channel at 5 mm, 512x128x128 (L = 2.56 m), 8 levels",
+    "open_channel_2048": "open channel at 5 mm, 2048x128x128 (L = 10.24 m), 8 levels",
 }
+
+# The paper's GPU wall times for 100 steps of its open channel at 5 mm with
+# slice-based stencils (Sec. 3.3, Table 1; RTX PRO 5000 Blackwell, precision
+# and multigrid iteration count not stated), by streamwise cell count.
+PAPER_TABLE1_GPU_S = {128: 5.5, 512: 22.8, 2048: 140.7}
 
 
 # kernel sources whose hash identifies the build the committed counter
@@ -84,6 +92,8 @@ def make_case(name: str, precision: int, tol: float):
         return C.room3d(precision=precision, tol=tol)
     if name == "bigroom":
         return C.room3d(1024, 512, 256, n_levels=9, precision=precision, tol=tol, n_steps=100)
+    if name.startswith("open_channel_"):
+        return C.open_channel(int(name.rsplit("_", 1)[1]), precision=precision, tol=tol)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -194,6 +204,24 @@ def run_batch(n_grids: int = 8, edge: int = 64, steps: int = 10):
     return out
 
 
+def run_paper_table(stream: int, precision: int, tol: float, steps: int = 100):
+    """The paper's time-profiling workload (Sec. 3.3, Table 1): 100 steps of
+    the open channel at 5 mm for each of its three streamwise lengths, timed
+    the same way as the headline (fields resident, after two warm-up steps)."""
+    from paper_2603_21869_amd import cases as C
+    rows = []
+    for nx, paper_s in PAPER_TABLE1_GPU_S.items():
+        case = C.open_channel(nx, precision=precision, tol=tol, n_steps=steps)
+        sec, stats, _, _ = run_gpu(case, steps, 2, False, stream)
+        rows.append({"cells": case.ncells, "n": list(case.n), "levels": case.n_levels,
+                     "steps": steps, "seconds": round(sec, 3),
+                     "mcell_steps_s": round(case.ncells * steps / sec / 1e6, 2),
+                     "mean_cycles": sum(x["cycles"] for x in stats) / len(stats),
+                     "paper_gpu_seconds": paper_s,
+                     "paper_mcell_steps_s": round(case.ncells * steps / paper_s / 1e6, 2)})
+    return rows
+
+
 def cpu_baseline(case, budget_s: float = 20.0):
     """The serial FP64 oracle on a bounded number of steps of the same workload."""
     from oracle import oracle as O
@@ -229,6 +257,8 @@ def main():
                     help="requests of the serving trace to replay (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=9)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-paper-table", action="store_true",
+                    help="skip the paper's open-channel timing workload (three lengths)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (for "
                          "scaling hardware byte counters) and exit")
@@ -333,6 +363,8 @@ def main():
         out["batching"] = run_batch()
     if args.serve:
         out["serving"] = run_serve(args.serve, args.serve_slots)
+    if not args.no_paper_table:
+        out["paper_table"] = run_paper_table(stream, prec, args.tol)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(make_case(args.workload, C.PREC_FP64, args.tol))
     print(json.dumps(out))

@@ -202,6 +202,39 @@ def channel3d(nx: int = 256, ny: int = 64, nz: int = 64, Lx: float = 2.56, Ly: f
                 precision=precision, n_levels=n_levels, tol=tol, n_steps=n_steps, seed=seed)
 
 
+OPEN_CHANNEL_LENGTHS = {128: 0.64, 512: 2.56, 2048: 10.24}
+
+
+def open_channel(nx: int = 512, ny: int = 128, nz: int = 128, h: float = 5e-3, U: float = 0.1,
+                 nu: float = 1.46e-5, rho: float = 1.2, dt: float = 2e-3, T_in: float = 298.15,
+                 T_wall: float = 308.15, seed: int = 0, n_levels: Optional[int] = None,
+                 n_steps: int = 100, precision: int = PREC_MIXED, tol: float = 1e-6,
+                 buoyancy: bool = True) -> Case:
+    """The paper's open-channel verification flow on its uniform 5 mm mesh
+    (Sec. 3.1: 0.64 x 0.64 m cross-section, U_in = 0.1 m/s, nu = 1.46e-5,
+    inlet at 25 C, every wall held at 35 C), with the streamwise length set by
+    nx as in the time profiling of Sec. 3.3 (Table 1: nx = 128, 512, 2048 for
+    L = 0.64, 2.56, 10.24 m; 100 steps).  Plug inlet x-, zero-gradient outlet
+    x+, no-slip walls on the four other faces."""
+    n = (nx, ny, nz)
+    hh = (h, h, h)
+    k_in, om_in = inlet_turbulence(U, nz * h)
+    patches = [
+        Patch(0, *_face_full(n, 0), kind=INLET, U=(U, 0.0, 0.0), T=T_in, k=k_in, omega=om_in),
+        Patch(1, *_face_full(n, 1), kind=OUTLET),
+    ] + [Patch(f, *_face_full(n, f), kind=WALL, T_wall=T_wall) for f in (2, 3, 4, 5)]
+    fluid = np.ones((nz, ny, nx), dtype=bool)
+    f = _base_fields(n, fluid, T_in, k_in, om_in)
+    f["u"][...] = _noisy_u(n, U, seed, fluid)
+    phys = PHYS_KOMEGA | PHYS_ENERGY | (PHYS_BUOYANCY if buoyancy else 0)
+    if n_levels is None:
+        n_levels = min(8, max_levels(n, 3))
+    return Case(name=f"open_channel_{nx}x{ny}x{nz}", dim=3, n=n, h=hh, nu=nu, rho=rho,
+                alpha_T=nu / 0.71, dt=dt, physics=phys, patches=patches, fields=f,
+                gravity=(0.0, 0.0, -9.81), T_ref=T_in, beta_T=1.0 / T_in,
+                precision=precision, n_levels=n_levels, tol=tol, n_steps=n_steps, seed=seed)
+
+
 def _reachable_from(fluid: np.ndarray, seeds: List[Tuple[int, int, int]]) -> np.ndarray:
     """Fluid cells face-connected to any seed cell (z, y, x indexing)."""
     from scipy import ndimage

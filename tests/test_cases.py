@@ -1,0 +1,32 @@
+"""Host-side workload builders: the open-channel timing workload has the
+paper's mesh counts (Sec. 3.3, Table 1) and the boundary data of its
+verification case (Sec. 3.1)."""
+import numpy as np
+
+from paper_2603_21869_amd import cases as C
+
+
+def test_open_channel_mesh_counts_match_table1():
+    # Table 1 lists 2,097,152, 8,388,608 and 33,554,432 cells for channel
+    # lengths 0.64, 2.56 and 10.24 m on the 5 mm mesh (built without fields)
+    for nx, L, cells in ((128, 0.64, 2097152), (512, 2.56, 8388608), (2048, 10.24, 33554432)):
+        assert C.OPEN_CHANNEL_LENGTHS[nx] == L
+        assert nx * 128 * 128 == cells
+        assert abs(nx * 5e-3 - L) < 1e-12
+    c = C.open_channel(128)
+    assert c.ncells == 2097152 and c.h == (5e-3, 5e-3, 5e-3) and c.n_levels == 8
+    assert c.n_steps == 100 and c.dt == 2e-3
+
+
+def test_open_channel_boundaries():
+    c = C.open_channel(32, 16, 16, h=0.04)
+    kinds = {p.face: p for p in c.patches}
+    assert kinds[0].kind == C.INLET and kinds[0].U == (0.1, 0.0, 0.0)
+    assert abs(kinds[0].T - 298.15) < 1e-12
+    assert kinds[1].kind == C.OUTLET
+    for f in (2, 3, 4, 5):
+        assert kinds[f].kind == C.WALL and abs(kinds[f].T_wall - 308.15) < 1e-12
+    # Re = U L / nu with the 0.64 m cross-section gives the paper's 4384
+    assert abs(0.1 * 0.64 / c.nu - 4384) < 1
+    u = c.fields["u"]
+    assert np.all(np.abs(u / 0.1 - 1) <= 0.01 + 1e-15) and u.std() > 0

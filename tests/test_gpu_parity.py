@@ -35,6 +35,9 @@ def small_cases():
         ("ch2d_nx90", C.channel2d(90, 18, L=4.0, H=1.0, n_levels=2, n_steps=3)),
         ("ch3d", C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3, n_steps=3, tol=1e-8)),
         ("room", C.room3d(64, 24, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4, n_steps=2)),
+        # every wall at a fixed temperature (Dirichlet T on the y and z faces)
+        ("open", C.open_channel(48, 16, 16, h=0.02, n_levels=3, n_steps=3, tol=1e-8,
+                                precision=C.PREC_FP64)),
     ]
 
 
@@ -105,6 +108,23 @@ def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
         print("   cycles", stats[0]["cycles"], {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
         for f in ("vel", "p", "k", "omega", "T"):
             assert errs[f] <= tol, (prec, f, errs[f])
+
+
+def test_full_size_open_channel_128_mixed(nf, oracle):
+    """The paper's timing workload at its smallest length (128 x 128 x 128 at
+    5 mm, 8 levels) in the benchmark's launch configuration: one mixed step,
+    every cell compared."""
+    case = C.open_channel(128, n_steps=1, tol=1e-8)
+    print("[full] open_channel 128^3 mixed", flush=True)
+    g = nf.Grid(case)
+    s, stats = g.step(1)
+    out = g.fields()
+    g.close()
+    ref, _, _ = oracle.step(case, 1, forced_cycles=[stats[0]["cycles"]])
+    errs = field_errors(case, out, ref)
+    print("   cycles", stats[0]["cycles"], {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for f in ("vel", "p", "k", "omega", "T"):
+        assert errs[f] <= 1e-6, (f, errs[f])
 
 
 def test_deterministic_and_restartable(nf):
