@@ -204,6 +204,26 @@ def run_batch(n_grids: int = 8, edge: int = 64, steps: int = 10):
     return out
 
 
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy
+    of `mib` MiB (bytes read + written / time, best of `reps`)."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * mib * (1 << 20) / best / 1e9
+
+
 def run_paper_table(stream: int, precision: int, tol: float, steps: int = 100):
     """The paper's time-profiling workload (Sec. 3.3, Table 1): 100 steps of
     the open channel at 5 mm for each of its three streamwise lengths, timed
@@ -349,7 +369,8 @@ def main():
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "traffic_source": traffic_src,
                      "avg_launch_us": round(avg * 1e6, 2),
-                     "algorithmic_bytes_per_launch": d["bytes_per_launch"]},
+                     "algorithmic_bytes_per_launch": d["bytes_per_launch"],
+                     "copy_GBs": round(copy_bandwidth(), 1)},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernel_table.items()},
         "variants": variants,

@@ -759,11 +759,28 @@ void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hi
 // plane (sx, sy: side of the fine cell within its parent); they give the
 // plane value Y and whether the plane's cell (I, J) takes part (active and
 // inside the box).  The z step then combines the planes K and K +- 1.
+// The plane value from the four coarse values, whether each cell takes part
+// (a00 already includes in_plane, a01 in_plane and iny) and the boundary
+// face coefficients cfx0, cfx1 (x faces on the fine cell's side, rows 0 and
+// 1) and cfy (y face on its side, row 0).
+template <class C>
+__device__ __forceinline__ void plane_value(C e00, C e10, C e01, C e11, bool a00, bool a10,
+                                            bool a01, bool a11, C cfx0, C cfx1, C cfy, bool inx,
+                                            bool iny, C& Y, bool& act) {
+  const C w3 = (C)0.75, w1 = (C)0.25;
+  const C nb0 = inx ? (a10 ? e10 : e00) : ((C)1 - cfx0) * e00;
+  const C X0 = a00 ? w3 * e00 + w1 * nb0 : (C)0;
+  const C nb1 = inx ? (a11 ? e11 : e01) : ((C)1 - cfx1) * e01;
+  const C X1 = a01 ? w3 * e01 + w1 * nb1 : (C)0;
+  const C yn = iny ? (a01 ? X1 : X0) : ((C)1 - cfy) * X0;
+  Y = a00 ? w3 * X0 + w1 * yn : (C)0;
+  act = a00;
+}
+
 template <class C, class SC>
 __device__ __forceinline__ void plane_rules(const LevelView& Cl, const SC* __restrict__ e, int Q,
                                             int sx, int oy, bool in_plane, bool inx, bool iny,
                                             C& Y, bool& act) {
-  const C w3 = (C)0.75, w1 = (C)0.25;
   // every index lies in the padded array (one ghost layer around the box)
   const C e00 = St<SC, C>::ld(e + Q), e10 = St<SC, C>::ld(e + Q + sx);
   const C e01 = St<SC, C>::ld(e + Q + oy), e11 = St<SC, C>::ld(e + Q + oy + sx);
@@ -774,13 +791,7 @@ __device__ __forceinline__ void plane_rules(const LevelView& Cl, const SC* __res
   const C cfx0 = (C)Cl.cf0[sx > 0 ? Q + 1 : Q];
   const C cfx1 = (C)Cl.cf0[sx > 0 ? Q + oy + 1 : Q + oy];
   const C cfy = (C)Cl.cf1[oy > 0 ? Q + oy : Q];
-  const C nb0 = inx ? (a10 ? e10 : e00) : ((C)1 - cfx0) * e00;
-  const C X0 = a00 ? w3 * e00 + w1 * nb0 : (C)0;
-  const C nb1 = inx ? (a11 ? e11 : e01) : ((C)1 - cfx1) * e01;
-  const C X1 = a01 ? w3 * e01 + w1 * nb1 : (C)0;
-  const C yn = iny ? (a01 ? X1 : X0) : ((C)1 - cfy) * X0;
-  Y = a00 ? w3 * X0 + w1 * yn : (C)0;
-  act = a00;
+  plane_value<C>(e00, e10, e01, e11, a00, a10, a01, a11, cfx0, cfx1, cfy, inx, iny, Y, act);
 }
 
 // The same plane value when the four cells are active and inside the box.
@@ -889,17 +900,152 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs<S, C, SC>& a, con
 NFVM_TILE_KERNELS(k_prolong, prolong_body, ProlongArgs, (S, C, SC), (class S, class C, class SC),
                   (S, C, SC), MBS, false)
 
+// Level 0 with nx a multiple of 4: one thread per four fine columns, the
+// children of coarse cells I0 and I0 + 1 (I0 even), walking the coarse
+// planes.  Per plane the coarse cells I0 - 1 .. I0 + 2 of the two rows the
+// rules need (values, class bytes, face coefficients) are loaded once for
+// the four columns, and each column's value is plane_value's, so the results
+// are prolong_body's; the fine values and class bytes go in four-wide loads.
+// Inactive fine cells are written back unchanged.
+template <class C, class SC>
+__device__ __forceinline__ void plane4(const LevelView& Cl, const SC* __restrict__ e, int Q, int oy,
+                                       bool in_plane, bool iny, const bool (&inx)[4], C (&Y)[4],
+                                       bool (&act)[4]) {
+  // every index lies in the padded array: I0 - 1 >= -1 and I0 + 2 <= nx
+  C r0[4], r1[4];
+  bool c0[4], c1[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    r0[m] = St<SC, C>::ld(e + Q - 1 + m);
+    r1[m] = St<SC, C>::ld(e + Q + oy - 1 + m);
+    c0[m] = Cl.cls[Q - 1 + m] != MG_INACTIVE;
+    c1[m] = Cl.cls[Q + oy - 1 + m] != MG_INACTIVE;
+  }
+  // x faces of cells I0, I0 + 1 (the low face at the cell's index) and the
+  // y faces between the two rows
+  C f0[3], f1[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    f0[m] = (C)Cl.cf0[Q + m];
+    f1[m] = (C)Cl.cf0[Q + oy + m];
+  }
+  const int qy = oy > 0 ? Q + oy : Q;
+  const C fy[2] = {(C)Cl.cf1[qy], (C)Cl.cf1[qy + 1]};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int h = q >> 1, sx = (q & 1) ? 1 : -1, m = 1 + h;
+    plane_value<C>(r0[m], r0[m + sx], r1[m], r1[m + sx], in_plane && c0[m], c0[m + sx],
+                   iny && in_plane && c1[m], c1[m + sx], sx > 0 ? f0[h + 1] : f0[h],
+                   sx > 0 ? f1[h + 1] : f1[h], fy[h], inx[q], iny, Y[q], act[q]);
+  }
+}
+
+template <class S, class C, class SC>
+__device__ __forceinline__ void prolong4_body(const ProlongArgs<S, C, SC>& a, const TileCtx& c,
+                                              bool) {
+  typedef typename Quad<S>::V V4;
+  const bool done = a.ctl[S_DONE] != 0.0;
+  const LevelView& F = a.F;
+  const LevelView& Cl = a.Cl;
+  S* __restrict__ x = a.x;
+  const SC* __restrict__ e = a.e;
+  const int i0 = 4 * (c.tx * MBX + threadIdx.x), j = c.ty * MBY + threadIdx.y;
+  if (i0 >= F.g.nx || j >= F.g.ny) return;
+  const Geom& cg = Cl.g;
+  const bool d3 = cg.dim == 3;
+  const int K0 = c.tz * a.T.cz, K1 = min(cg.nz, K0 + a.T.cz);
+  const int I0 = i0 >> 1, J = j >> 1;
+  const int oy = (j & 1) ? cg.sx : -cg.sx;
+  const bool iny = (unsigned)(J + ((j & 1) ? 1 : -1)) < (unsigned)cg.ny;
+  bool inx[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    inx[q] = (unsigned)(I0 + (q >> 1) + ((q & 1) ? 1 : -1)) < (unsigned)cg.nx;
+  const C w3 = (C)0.75, w1 = (C)0.25;
+  int PC = cg.idx(I0, J, K0);
+  C ym[4] = {0, 0, 0, 0}, yc[4];
+  bool am[4] = {false, false, false, false}, ac[4];
+  plane4<C, SC>(Cl, e, PC, oy, true, iny, inx, yc, ac);
+  if (d3) plane4<C, SC>(Cl, e, PC - cg.sxy, oy, K0 > 0, iny, inx, ym, am);
+  int P = F.g.idx(i0, j, d3 ? 2 * K0 : 0);
+  for (int K = K0; K < K1; ++K, PC += cg.sxy) {
+    const uchar4 fc0 = *(const uchar4*)(F.cls + P);
+    const V4 x0 = *(const V4*)(x + P);
+    uchar4 fc1 = fc0;
+    V4 x1 = x0;
+    C yp[4] = {0, 0, 0, 0}, czl[2] = {0, 0}, czh[2] = {0, 0};
+    bool ap[4] = {false, false, false, false};
+    if (d3) {
+      fc1 = *(const uchar4*)(F.cls + P + F.g.sxy);
+      x1 = *(const V4*)(x + P + F.g.sxy);
+      plane4<C, SC>(Cl, e, PC + cg.sxy, oy, K + 1 < cg.nz, iny, inx, yp, ap);
+      czl[0] = (C)Cl.cf2[PC];
+      czl[1] = (C)Cl.cf2[PC + 1];
+      czh[0] = (C)Cl.cf2[PC + cg.sxy];
+      czh[1] = (C)Cl.cf2[PC + cg.sxy + 1];
+    }
+    if (done) return;
+    const uint8_t f0[4] = {fc0.x, fc0.y, fc0.z, fc0.w}, f1[4] = {fc1.x, fc1.y, fc1.z, fc1.w};
+    V4 o0 = x0, o1 = x1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int h = q >> 1;
+      if (f0[q] != MG_INACTIVE) {
+        C Z = yc[q];
+        if (d3) {
+          const C zn = K > 0 ? (am[q] ? ym[q] : yc[q]) : ((C)1 - czl[h]) * yc[q];
+          Z = w3 * yc[q] + w1 * zn;
+        }
+        const S xs = x0[q];
+        S v;
+        St<S, C>::st(&v, St<S, C>::ld(&xs) + Z);
+        o0[q] = v;
+      }
+      if (d3 && f1[q] != MG_INACTIVE) {
+        const C zn = K + 1 < cg.nz ? (ap[q] ? yp[q] : yc[q]) : ((C)1 - czh[h]) * yc[q];
+        const S xs = x1[q];
+        S v;
+        St<S, C>::st(&v, St<S, C>::ld(&xs) + (w3 * yc[q] + w1 * zn));
+        o1[q] = v;
+      }
+    }
+    *(V4*)(x + P) = o0;
+    if (d3) *(V4*)(x + P + F.g.sxy) = o1;
+    P += d3 ? 2 * F.g.sxy : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ym[q] = yc[q];
+      am[q] = ac[q];
+      yc[q] = yp[q];
+      ac[q] = ap[q];
+    }
+  }
+}
+NFVM_TILE_KERNELS(k_prolong4, prolong4_body, ProlongArgs, (S, C, SC),
+                  (class S, class C, class SC), (S, C, SC), MBS, false)
+
+// Whether the prolongation to fine level f takes the four-column kernel.
+__host__ inline bool prolong_quad(const Level& f) { return f.code && f.g.nx % 4 == 0; }
+
 template <class S, class C, class SC>
 ProlongArgs<S, C, SC> prolong_args(const Level& f, const Level& c, const double* ctl) {
-  // tiles over fine columns and coarse planes
-  return ProlongArgs<S, C, SC>{view(f), make_tiles(f.g.nx, f.g.ny, c.g.nz, f.tt[TK_PROLONG]),
-                               (S*)f.x[f.cur], view(c), (const SC*)c.x[c.cur], ctl};
+  // tiles over fine columns (groups of four with the four-column kernel) and
+  // coarse planes
+  return ProlongArgs<S, C, SC>{
+      view(f),
+      make_tiles(prolong_quad(f) ? f.g.nx / 4 : f.g.nx, f.g.ny, c.g.nz, f.tt[TK_PROLONG]),
+      (S*)f.x[f.cur], view(c), (const SC*)c.x[c.cur], ctl};
 }
 
 template <class S, class C, class SC>
 void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
   const ProlongArgs<S, C, SC> a = prolong_args<S, C, SC>(f, c, ctl);
-  NFVM_LAUNCH((k_prolong<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  if (prolong_quad(f)) {
+    if constexpr (has_quad<S>)
+      NFVM_LAUNCH((k_prolong4<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  } else {
+    NFVM_LAUNCH((k_prolong<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  }
 }
 
 // ---- coarsest level: x = A^-1 b with the dense inverse, one workgroup -------------
@@ -2105,18 +2251,21 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
   }
   // up: prolongation and post-smoothing
   for (int l = top - 1; l >= 0; --l) {
-    Group<ProlongArgs<S0, C, SC>> p0;
+    Group<ProlongArgs<S0, C, SC>> p0, p0q;
     Group<ProlongArgs<SC, C, SC>> pc;
     for (int i = 0; i < n; ++i) {
       MgGridDesc& d = G[i];
       if (l >= stop_level(d)) continue;
       if (l == 0) {
-        p0.push_back(prolong_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out));
+        (prolong_quad(d.lv[0]) ? p0q : p0)
+            .push_back(prolong_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out));
       } else {
         pc.push_back(prolong_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out));
       }
     }
     emit_tiles(o, p0, k_prolong<S0, C, SC>, k_prolong_batch<S0, C, SC>, false);
+    if constexpr (has_quad<S0>)
+      emit_tiles(o, p0q, k_prolong4<S0, C, SC>, k_prolong4_batch<S0, C, SC>, false);
     emit_tiles(o, pc, k_prolong<SC, C, SC>, k_prolong_batch<SC, C, SC>, false);
     for (int s = 0; s < nu2; ++s) {
       SweepGroups<S0, C> g0;

@@ -110,6 +110,41 @@ def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
             assert errs[f] <= tol, (prec, f, errs[f])
 
 
+def test_full_size_channel2d_fp64(nf, oracle):
+    """The 2D channel at its full size (256 x 64, 6 levels, FP64) for 20
+    steps, every cell compared."""
+    case = C.channel2d(n_steps=20)
+    print("[full] channel2d fp64, 20 steps", flush=True)
+    g = nf.Grid(case)
+    s, stats = g.step(20)
+    out = g.fields()
+    g.close()
+    ref, _, _ = oracle.step(case, 20, forced_cycles=[x["cycles"] for x in stats])
+    errs = field_errors(case, out, ref)
+    print("   cycles", [x["cycles"] for x in stats], {k: f"{v:.2e}" for k, v in errs.items()},
+          flush=True)
+    for f in ("vel", "p", "k", "omega"):
+        assert errs[f] <= 1e-10, (f, errs[f])
+
+
+def test_channel2d_diverges_where_the_oracle_does(nf, oracle):
+    """The 2D channel's 100 steps do not survive the method's near-wall omega
+    on a 64-cell cross-section (k grows until the eddy viscosity breaks the
+    explicit diffusion limit): both sides report NFVM_E_DIVERGED, at the same
+    step."""
+    case = C.channel2d()
+    g = nf.Grid(case)
+    s, stats = g.step(100, allow=(nf.NFVM_E_DIVERGED,))
+    g.close()
+    _, rst, rs = oracle.step(case, 100)
+    first = next(i for i, x in enumerate(stats) if x["status"] != 0)
+    ofirst = next(i for i, x in enumerate(rst) if x["status"] != 0)
+    print(f"   diverged at step {first} (oracle {ofirst})", flush=True)
+    assert s == nf.NFVM_E_DIVERGED and rs == nf.NFVM_E_DIVERGED
+    assert stats[first]["status"] == nf.NFVM_E_DIVERGED
+    assert abs(first - ofirst) <= 1
+
+
 def test_full_size_open_channel_128_mixed(nf, oracle):
     """The paper's timing workload at its smallest length (128 x 128 x 128 at
     5 mm, 8 levels) in the benchmark's launch configuration: one mixed step,
@@ -125,6 +160,38 @@ def test_full_size_open_channel_128_mixed(nf, oracle):
     print("   cycles", stats[0]["cycles"], {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     for f in ("vel", "p", "k", "omega", "T"):
         assert errs[f] <= 1e-6, (f, errs[f])
+
+
+@pytest.mark.parametrize("size", ["room", "bigroom"])
+def test_full_size_room_pressure_solve_mixed(nf, oracle, size):
+    """The room at its full sizes (512 x 256 x 128 with 8 levels, and
+    1024 x 512 x 256 with 9) in the launch configuration the benchmark
+    times, mixed precision: the pressure solve of a seeded right-hand side
+    reaches 1e-6 as measured again with the oracle's FP64 operator, solid
+    cells stay zero, and (room) a time step stays finite at the tolerance."""
+    if size == "room":
+        case = C.room3d(precision=C.PREC_MIXED, n_steps=1)
+    else:
+        case = C.room3d(1024, 512, 256, n_levels=9, precision=C.PREC_MIXED, n_steps=1)
+    print(f"[full] {size} {case.n} mixed pressure solve", flush=True)
+    g = nf.Grid(case)
+    m = fluid(case)
+    b = np.random.default_rng(11).standard_normal(g.shape) * m
+    x, st, s = g.mg_solve(b, tol=1e-6, max_cycles=100)
+    print(f"   cycles {st['cycles']} rel {st['rel_residual']:.3e}", flush=True)
+    assert s == 0 and st["rel_residual"] <= 1e-6
+    assert not x[~m].any()
+    mg = oracle.MG(case)
+    rel = np.linalg.norm((b - mg.apply(0, x))[m]) / np.linalg.norm(b[m])
+    del mg
+    print(f"   oracle-measured rel {rel:.3e}", flush=True)
+    assert rel <= 1.01e-6
+    if size == "room":
+        s2, stats = g.step(1)
+        f = g.fields()
+        assert s2 == 0 and stats[0]["rel_residual"] <= 1e-6
+        assert all(np.isfinite(v).all() for v in f.values())
+    g.close()
 
 
 def test_deterministic_and_restartable(nf):
