@@ -94,7 +94,7 @@ size_t footprint_bytes(const nfvm_grid_desc& d) {
   const size_t T = (size_t)g.total, N = (size_t)g.cells();
   size_t b = 0;
   b += 6 * T * V + 7 * T * F + T * P + T;           // fields (ping-pong), nu_t, pressure, types
-  b += 6 * T * O;                                   // b, phi, r, p (x2), q
+  b += 5 * T * O;                                   // b, phi, r, p, q
   b += T * O;                                       // initial guess of the solve call
   b += 8 * N + (d.solid_mask ? N : 0);              // dense staging, mask
   for (int l = 0; l < d.n_levels; ++l) {
@@ -204,8 +204,7 @@ class GridT : public GridBase {
   P* p = nullptr;
   F* nut = nullptr;  // eddy viscosity of the stored k, omega (written by the first half step)
   std::vector<Level> lv;
-  O *bvec = nullptr, *phi = nullptr, *r = nullptr, *pv = nullptr, *q = nullptr, *wv = nullptr,
-    *x0 = nullptr;
+  O *bvec = nullptr, *phi = nullptr, *r = nullptr, *pv = nullptr, *q = nullptr, *x0 = nullptr;
   double* stage = nullptr;
   RedBuf red{};
   int* cmap = nullptr;
@@ -269,6 +268,9 @@ class GridT : public GridBase {
       const double nc = L > 1 ? (double)level_geom(d, 1).cells() : 0.0;
       // level 0 reads a 2-byte face code per cell; the restriction also
       // writes the coarse level's first sweep, the CG update the level-0 one
+      // (V-cycles with nu1 + nu2 even); the CG passes read z, r, q (apply)
+      // and z, p, q, x, r (update, which forms A z again instead of reading
+      // a stored one)
       prof_bytes[NFVM_K_SMOOTH0] = N * (3 * s0 + 2);
       prof_bytes[NFVM_K_SMOOTH0_ZERO] = N * (2 * s0 + 2);
       prof_bytes[NFVM_K_RESTRICT0] = N * (2 * s0 + 2) + nc * (2 * scs + 1);
@@ -277,8 +279,8 @@ class GridT : public GridBase {
       prof_bytes[NFVM_K_DESTROY] = N * (3 * sv + 5 * sf + 1);  // (the first half step)
       prof_bytes[NFVM_K_RHS] = N * (3 * sv + so + 1);
       prof_bytes[NFVM_K_PROJECT] = N * (6 * sv + 2 * sp + so + 1);
-      prof_bytes[NFVM_K_FCG_APPLY] = N * (s0 + 3 * so + 2);
-      prof_bytes[NFVM_K_FCG_UPDATE] = N * (3 * s0 + 9 * so + 2);
+      prof_bytes[NFVM_K_FCG_APPLY] = N * (s0 + 2 * so + 2);
+      prof_bytes[NFVM_K_FCG_UPDATE] = N * (3 * s0 + 8 * so + 2);
     }
     NFVM_CK(hipEventCreate(&ev0));
     NFVM_CK(hipEventCreate(&ev1));
@@ -381,7 +383,6 @@ class GridT : public GridBase {
     phi = alloc<O>(g.total);
     r = alloc<O>(g.total);
     pv = alloc<O>(g.total);
-    wv = alloc<O>(g.total);
     q = alloc<O>(g.total);
     x0 = alloc<O>(g.total);
     red.max_blocks = max_blocks_of(g);
@@ -503,11 +504,11 @@ class GridT : public GridBase {
         tr.mirror = nullptr;
         v.tt[TK_APPLY] = tune_one(TK_APPLY, v.g, [&](int tt) {
           v.tt[TK_APPLY] = tt;
-          launch_fcg_apply<O, S0>(v, r, q, wv, tr, stream, true);
+          launch_fcg_apply<O, S0>(v, r, q, tr, stream, true);
         });
         v.tt[TK_UPDATE] = tune_one(TK_UPDATE, v.g, [&](int tt) {
           v.tt[TK_UPDATE] = tt;
-          launch_fcg_update<O, S0>(v, phi, r, pv, q, wv, tr, stream, true, zero0(), wj);
+          launch_fcg_update<O, S0>(v, phi, r, pv, q, tr, stream, true, zero0(), wj);
         });
       } else {
         v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + 1000, v.g, [&](int tt) {
@@ -532,7 +533,7 @@ class GridT : public GridBase {
     NFVM_CK(hipGetLastError());
     // leave every buffer the tuning touched as a fresh grid has it
     const size_t ob = (size_t)g.total * sizeof(O);
-    for (O* bufp : {bvec, phi, r, pv, q, wv, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
+    for (O* bufp : {bvec, phi, r, pv, q, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
     for (int l = 0; l < L; ++l) {
       const size_t es = (size_t)lv[l].g.total * (l == 0 ? sizeof(S0) : sizeof(SC));
       for (int c = 0; c < 2; ++c) NFVM_CK(hipMemsetAsync(lv[l].x[c], 0, es, stream));
@@ -692,8 +693,13 @@ class GridT : public GridBase {
   // Whether level l gets its first pre-smoothing sweep from the kernel that
   // writes its right-hand side (CG start / update for level 0, the
   // restriction from level l - 1 otherwise): levels that run a regular
-  // V-cycle step with pre-smoothing.
-  bool fused_zero(int l) const { return nu1 > 0 && l != bottom_top && l < L - 1; }
+  // V-cycle step with pre-smoothing.  The CG update reads the V-cycle's
+  // result z around every cell while it writes level 0's fused sweep; with
+  // nu1 + nu2 odd the sweeps leave z in the buffer that sweep goes to, so
+  // level 0 then sweeps from zero itself.
+  bool fused_zero(int l) const {
+    return nu1 > 0 && l != bottom_top && l < L - 1 && (l > 0 || (nu1 + nu2) % 2 == 0);
+  }
   void* zero_of(int l) const { return fused_zero(l) ? lv[l].x[0] : nullptr; }
 
   void vcycle(int l) {
@@ -746,10 +752,10 @@ class GridT : public GridBase {
   void fcg_iteration() {
     vcycle(0);
     prof_begin(NFVM_K_FCG_APPLY);
-    launch_fcg_apply<O, S0>(lv[0], r, q, wv, red, stream);
+    launch_fcg_apply<O, S0>(lv[0], r, q, red, stream);
     prof_end(NFVM_K_FCG_APPLY);
     prof_begin(NFVM_K_FCG_UPDATE);
-    launch_fcg_update<O, S0>(lv[0], phi, r, pv, q, wv, red, stream, true, zero0(), wj);
+    launch_fcg_update<O, S0>(lv[0], phi, r, pv, q, red, stream, true, zero0(), wj);
     prof_end(NFVM_K_FCG_UPDATE);
   }
 
@@ -1078,7 +1084,6 @@ class GridT : public GridBase {
     d.r = r;
     d.p = pv;
     d.q = q;
-    d.w = wv;
   }
 
   std::unique_ptr<IterPlan> make_plan(const std::vector<GridBase*>& same) override {
