@@ -1234,11 +1234,12 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                        (double)max_cycles, (double)forced);
 }
 
-// w = A z and the dot products (z, r), (z, q_prev), (z, w).  With
-// beta = -(z, q_prev) / (p_prev, q_prev), the new direction p = z + beta p_prev
-// has A p = w + beta q_prev and (p, A p) = (z, w) + 2 beta (z, q_prev) +
-// beta^2 (p_prev, q_prev), so one stencil pass per iteration serves both the
-// direction and the step length.
+// The dot products (z, r), (z, q_prev), (z, w) with w = A z (not stored).
+// With beta = -(z, q_prev) / (p_prev, q_prev), the new direction
+// p = z + beta p_prev has A p = w + beta q_prev and (p, A p) = (z, w) +
+// 2 beta (z, q_prev) + beta^2 (p_prev, q_prev), so the operator applied to
+// z (here, and again in the update pass) serves both the direction and the
+// step length.
 template <class O, class S>
 struct ApplyArgs {
   LevelView L;
@@ -2291,7 +2292,7 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
       gc.emit(o);
     }
   }
-  // CG: w = A z with its dot products, then the vector update
+  // CG: the dot products with w = A z, then the vector update
   Group<ApplyArgs<O, S0>> ap[2];  // [one cell, four cells per thread]
   Group<UpdateArgs<O, S0>> up[2];
   Group<FinArgs> fa, fu;
