@@ -111,32 +111,39 @@ enum { G_U = 0, G_V = 1, G_W = 2, G_P = 3, G_T = 4, G_K = 5, G_OM = 6, G_NUT = 7
 __device__ __forceinline__ bool is_fluid(uint8_t t) { return (t & 0x7f) == 0; }
 
 // Value standing in for a non-fluid neighbour across a face: a Dirichlet
-// value b on the face gives 2b - vP, a zero gradient gives vP.
+// value b on the face gives 2b - vP, a zero gradient gives vP.  The patch
+// values are read whatever the patch kind and the rule is chosen by
+// selects, so a wave whose lanes see different kinds takes no branches.
 template <class R>
 __device__ __forceinline__ R ghost(const DevPatch& p, int fld, R vP, int komega) {
   const int kind = p.kind;
+  const bool in = kind == K_INLET, out = kind == K_OUTLET;
   switch (fld) {
     case G_U:
     case G_V:
-    case G_W:
-      if (kind == K_INLET) return (R)(2.0 * p.U[fld]) - vP;
-      if (kind == K_OUTLET) return vP;
-      return -vP;
+    case G_W: {
+      const R b = (R)(2.0 * p.U[fld]) - vP;
+      return in ? b : (out ? vP : -vP);
+    }
     case G_P:
-      return kind == K_OUTLET ? -vP : vP;
-    case G_T:
-      if (kind == K_INLET) return (R)(2.0 * p.T) - vP;
-      if (kind == K_WALL && p.T_dirichlet) return (R)(2.0 * p.T_wall) - vP;
-      return vP;
-    case G_K:
-      return kind == K_INLET ? (R)(2.0 * p.k) - vP : vP;
-    case G_OM:
-      return kind == K_INLET ? (R)(2.0 * p.omega) - vP : vP;
-    default:  // G_NUT
+      return out ? -vP : vP;
+    case G_T: {
+      const R bi = (R)(2.0 * p.T) - vP, bw = (R)(2.0 * p.T_wall) - vP;
+      return in ? bi : ((kind == K_WALL && p.T_dirichlet) ? bw : vP);
+    }
+    case G_K: {
+      const R b = (R)(2.0 * p.k) - vP;
+      return in ? b : vP;
+    }
+    case G_OM: {
+      const R b = (R)(2.0 * p.omega) - vP;
+      return in ? b : vP;
+    }
+    default: {  // G_NUT
+      const R b = (R)(2.0 * p.nut) - vP;
       if (!komega) return (R)0;
-      if (kind == K_INLET) return (R)(2.0 * p.nut) - vP;
-      if (kind == K_OUTLET) return vP;
-      return -vP;
+      return in ? b : (out ? vP : -vP);
+    }
   }
 }
 
