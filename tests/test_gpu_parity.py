@@ -221,6 +221,52 @@ def test_odd_and_one_sided_smoothing_matches_oracle(nf, oracle, nu):
     g2.close()
 
 
+@pytest.mark.parametrize("prec", [C.PREC_FP64, C.PREC_MIXED], ids=["fp64", "mixed"])
+def test_fluid_at_rest_stays_at_rest(nf, prec):
+    """Degenerate input: a closed box of fluid at rest.  The Poisson
+    right-hand side is exactly zero, so every solve takes no iteration and
+    returns zero, and the fields stay exactly as they are; zero steps change
+    nothing either."""
+    from tests.boxcase import box
+    case = box(n=(16, 16, 16), h=(0.1, 0.1, 0.1), physics=0, n_levels=3, precision=prec,
+               tol=1e-9, n_steps=3)
+    g = nf.Grid(case)
+    f0 = g.fields()
+    s0, st0 = g.step(0)
+    assert s0 == nf.NFVM_OK and st0 == []
+    s, stats = g.step(3)
+    out = g.fields()
+    g.close()
+    assert s == nf.NFVM_OK and [x["cycles"] for x in stats] == [0, 0, 0]
+    for k in f0:
+        assert np.array_equal(f0[k], out[k]), k
+    for k in ("u", "v", "w", "p"):
+        assert not out[k].any(), k
+
+
+def test_closed_box_in_motion_reports_a_failed_solve(nf, oracle):
+    """A domain without a pressure boundary makes the pressure operator
+    singular (its constant mode): once the flow moves (here k - omega with a
+    fixed wall omega drives it), the coarsest-level inverse is meaningless
+    and neither side converges at the first step: the oracle's elimination
+    meets a zero pivot and reports NFVM_E_DIVERGED, the HIP path's stays
+    finite and reports NFVM_E_NOTCONV at its cycle budget; neither returns
+    NFVM_OK."""
+    from tests.boxcase import box
+    case = box(n=(16, 16, 16), h=(0.1, 0.1, 0.1), physics=C.PHYS_KOMEGA, n_levels=3,
+               precision=C.PREC_FP64, tol=1e-9, n_steps=1)
+    case.fields["k"][...] = 1e-3
+    case.fields["omega"][...] = 5.0
+    fail = (nf.NFVM_E_DIVERGED, nf.NFVM_E_NOTCONV)
+    _, rst, rs = oracle.step(case, 1)
+    g = nf.Grid(case, max_cycles=40)
+    s, stats = g.step(1, allow=fail)
+    g.close()
+    print(f"   oracle {rs}, HIP path {s} after {stats[0]['cycles']} cycles", flush=True)
+    assert rs in fail and rst[0]["status"] in fail
+    assert s in fail and stats[0]["status"] in fail
+
+
 def test_deterministic_and_restartable(nf):
     """Two runs give bitwise equal fields.  With every solve started from zero
     (the default), N + N steps with a get/set of the fields in between equal
