@@ -1182,7 +1182,7 @@ __device__ __forceinline__ void publish(const RedBuf& red, int s0, int s1 = -1, 
 }
 
 // Stopping rule, evaluated by one thread after ||r||^2 is known.
-__device__ __forceinline__ void fcg_judge(double* ctl) {
+__device__ __forceinline__ void fcg_stop_rule(double* ctl) {
   const double bb = ctl[S_BB], rr = ctl[S_RR], it = ctl[S_ITER];
   bool done;
   if (!isfinite(rr) || !isfinite(bb))
@@ -1216,7 +1216,7 @@ __global__ __launch_bounds__(FIN) void k_fin_start(RedBuf red, int nb, double to
     red.out[S_TOL2] = tol2;
     red.out[S_MAXIT] = maxit;
     red.out[S_FORCED] = forced;
-    fcg_judge(red.out);
+    fcg_stop_rule(red.out);
     publish(red, S_BB, S_RR, S_ITER, S_DONE);
   }
 }
@@ -1551,7 +1551,7 @@ __device__ __forceinline__ void fin_update_body(const FinArgs& f) {
   if (threadIdx.x == 0) {
     red.out[S_RR] = acc[0];
     red.out[S_ITER] += 1.0;
-    fcg_judge(red.out);
+    fcg_stop_rule(red.out);
     publish(red, S_RR, S_ITER, S_DONE);
   }
 }
