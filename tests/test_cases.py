@@ -1,6 +1,6 @@
-"""Host-side workload builders: the open-channel timing workload has the
-paper's mesh counts (Sec. 3.3, Table 1) and the boundary data of its
-verification case (Sec. 3.1)."""
+"""Host-side logic: the open-channel timing workload has the paper's mesh
+counts (Sec. 3.3, Table 1) and the boundary data of its verification case
+(Sec. 3.1); the benchmark refuses more than one GPU."""
 import numpy as np
 
 from paper_2603_21869_amd import cases as C
@@ -30,3 +30,17 @@ def test_open_channel_boundaries():
     assert abs(0.1 * 0.64 / c.nu - 4384) < 1
     u = c.fields["u"]
     assert np.all(np.abs(u / 0.1 - 1) <= 0.01 + 1e-15) and u.std() > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asking for more exits with a message
+    before any GPU work."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
