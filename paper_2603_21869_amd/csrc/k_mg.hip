@@ -325,6 +325,31 @@ __device__ __forceinline__ C diag_at(const LevelView& L, uint8_t cl, int P) {
   return d;
 }
 
+// The same diagonal with the coefficients loaded whatever the class, so the
+// loads need not wait for the class byte (small, latency-bound levels).
+template <class C>
+__device__ __forceinline__ C diag_eager(const LevelView& L, uint8_t cl, int P) {
+  const Geom& g = L.g;
+  const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
+          ih2z = (C)(1.0 / (g.hz * g.hz));
+  const C fx0 = (C)L.cf0[P], fx1 = (C)L.cf0[P + 1], fy0 = (C)L.cf1[P], fy1 = (C)L.cf1[P + g.sx];
+  const C fz0 = g.dim == 3 ? (C)L.cf2[P] : (C)0, fz1 = g.dim == 3 ? (C)L.cf2[P + g.sxy] : (C)0;
+  C dr = (C)2 * (ih2x + ih2y);
+  if (g.dim == 3) dr += (C)2 * ih2z;
+  C di = (fx0 + fx1) * ih2x + (fy0 + fy1) * ih2y;
+  if (g.dim == 3) di += (fz0 + fz1) * ih2z;
+  return cl == MG_REGULAR ? dr : di;
+}
+
+// The first sweep from zero of a coarse cell whose right-hand side has just
+// been formed: w bc / D with bc rounded to storage as the store rounds it.
+template <class SC, class C>
+__device__ __forceinline__ C zero_sweep_of(C bc, C wj, C D) {
+  SC s;
+  St<SC, C>::st(&s, bc);
+  return wj * St<SC, C>::ld(&s) / D;
+}
+
 // ---- damped Jacobi sweep: x_out = x_in + w (b - A x_in) / D -------------------
 template <class S, class C>
 struct SmoothArgs {
@@ -609,36 +634,47 @@ __device__ __forceinline__ void restrict_body(const RestrictArgs<S, C, SC>& a, c
       xm1 = St<S, C>::ld(x + P1 - g.sxy);
     }
   }
+  const bool lead = in && !(lx & 1);  // the lane that stores the coarse cell
+  const bool ceager = Cl.g.cells() <= NBHD_EAGER_CELLS;
+  const int dz = d3 ? g.sxy : 0;  // (2D: the one plane read twice, counted once)
   for (int K = K0; K < K1; ++K) {
+    // the coarse cell's class byte and diagonal go out with the fine loads
+    const int PC = lead ? Cl.g.idx(i >> 1, J, K) : 0;
+    const uint8_t ccl = lead ? Cl.cls[PC] : (uint8_t)MG_INACTIVE;
+    const C dge = (lead && ceager) ? diag_eager<C>(Cl, ccl, PC) : (C)1;
     C r0 = 0, r1 = 0;
-    for (int cc = 0; cc < kz; ++cc, P0 += g.sxy, P1 += g.sxy) {
-      if (in) {
-        C xp0 = 0, xp1 = 0;
-        if (d3) {
-          xp0 = St<S, C>::ld(x + P0 + g.sxy);
-          xp1 = St<S, C>::ld(x + P1 + g.sxy);
-        }
-        r0 += resid_at<S, C>(F, x, b, P0, xc0, xm0, xp0);
-        r1 += resid_at<S, C>(F, x, b, P1, xc1, xm1, xp1);
-        xm0 = xc0;
-        xc0 = xp0;
-        xm1 = xc1;
-        xc1 = xp1;
+    if (in) {
+      // both fine planes of the coarse plane: every load of the four cells
+      // before their arithmetic
+      const C xp0 = St<S, C>::ld(x + P0 + dz), xp1 = St<S, C>::ld(x + P1 + dz);
+      const C xq0 = St<S, C>::ld(x + P0 + 2 * dz), xq1 = St<S, C>::ld(x + P1 + 2 * dz);
+      const C a0 = resid_at<S, C>(F, x, b, P0, xc0, xm0, xp0);
+      const C a1 = resid_at<S, C>(F, x, b, P1, xc1, xm1, xp1);
+      const C c0 = resid_at<S, C>(F, x, b, P0 + dz, xp0, xc0, xq0);
+      const C c1 = resid_at<S, C>(F, x, b, P1 + dz, xp1, xc1, xq1);
+      r0 += a0;
+      r1 += a1;
+      if (d3) {
+        r0 += c0;
+        r1 += c1;
       }
+      xm0 = xp0;
+      xc0 = xq0;
+      xm1 = xp1;
+      xc1 = xq1;
+      P0 += kz * g.sxy;
+      P1 += kz * g.sxy;
     }
     r0 += __shfl_xor(r0, 1);
     r1 += __shfl_xor(r1, 1);
     if (done) return;
-    if (in && !(lx & 1)) {
-      const int PC = Cl.g.idx(i >> 1, J, K);
-      const uint8_t ccl = Cl.cls[PC];
-      if (ccl != MG_INACTIVE) {
-        SC* dst = a.bc + PC;
-        St<SC, C>::st(dst, (r0 + r1) * (C)(d3 ? 0.125 : 0.25));
-        // first pre-smoothing sweep (from zero) of the coarse level
-        if (a.zc)
-          St<SC, C>::st(a.zc + PC, a.wj * St<SC, C>::ld(dst) / diag_at<C>(Cl, ccl, PC));
-      }
+    if (lead && ccl != MG_INACTIVE) {
+      const C bc = (r0 + r1) * (C)(d3 ? 0.125 : 0.25);
+      St<SC, C>::st(a.bc + PC, bc);
+      // first pre-smoothing sweep (from zero) of the coarse level
+      if (a.zc)
+        St<SC, C>::st(a.zc + PC, zero_sweep_of<SC, C>(bc, a.wj,
+                                                      ceager ? dge : diag_at<C>(Cl, ccl, PC)));
     }
   }
 }
@@ -669,7 +705,17 @@ __device__ __forceinline__ void restrict4_body(const RestrictArgs<S, C, SC>& a, 
   V4 xc0 = *(const V4*)(x + P0), xc1 = *(const V4*)(x + P0 + g.sx);
   V4 xm0 = d3 ? *(const V4*)(x + P0 - g.sxy) : V4(0);
   V4 xm1 = d3 ? *(const V4*)(x + P0 + g.sx - g.sxy) : V4(0);
+  const bool ceager = Cl.g.cells() <= NBHD_EAGER_CELLS;
   for (int K = K0; K < K1; ++K) {
+    // the coarse cells' class bytes (and, on small levels, diagonals) go out
+    // with the fine loads
+    const int PC0 = Cl.g.idx(i0 >> 1, J, K);
+    const uint8_t ccl[2] = {Cl.cls[PC0], Cl.cls[PC0 + 1]};
+    C dge[2] = {(C)1, (C)1};
+    if (ceager) {
+      dge[0] = diag_eager<C>(Cl, ccl[0], PC0);
+      dge[1] = diag_eager<C>(Cl, ccl[1], PC0 + 1);
+    }
     C r[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
     for (int cc = 0; cc < kz; ++cc, P0 += g.sxy) {
       const int P1 = P0 + g.sx;
@@ -704,14 +750,15 @@ __device__ __forceinline__ void restrict4_body(const RestrictArgs<S, C, SC>& a, 
     if (done) return;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int PC = Cl.g.idx((i0 >> 1) + h, J, K);
-      const uint8_t ccl = Cl.cls[PC];
-      if (ccl == MG_INACTIVE) continue;
+      if (ccl[h] == MG_INACTIVE) continue;
+      const int PC = PC0 + h;
       const C s0 = r[0][2 * h] + r[0][2 * h + 1], s1 = r[1][2 * h] + r[1][2 * h + 1];
-      SC* dst = a.bc + PC;
-      St<SC, C>::st(dst, (s0 + s1) * (C)(d3 ? 0.125 : 0.25));
+      const C bc = (s0 + s1) * (C)(d3 ? 0.125 : 0.25);
+      St<SC, C>::st(a.bc + PC, bc);
       // first pre-smoothing sweep (from zero) of the coarse level
-      if (a.zc) St<SC, C>::st(a.zc + PC, a.wj * St<SC, C>::ld(dst) / diag_at<C>(Cl, ccl, PC));
+      if (a.zc)
+        St<SC, C>::st(a.zc + PC, zero_sweep_of<SC, C>(
+                                     bc, a.wj, ceager ? dge[h] : diag_at<C>(Cl, ccl[h], PC)));
     }
   }
 }
