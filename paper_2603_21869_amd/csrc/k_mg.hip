@@ -897,7 +897,11 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs<S, C, SC>& a, con
   plane_rules<C, SC>(Cl, e, PC, sx, oy, true, inx, iny, yc, ac);
   if (d3) plane_rules<C, SC>(Cl, e, PC - cg.sxy, sx, oy, K0 > 0, inx, iny, ym, am);
   int P = F.g.idx(i, j, d3 ? 2 * K0 : 0);
-  bool full = d3 && Cl.full[PC] != 0;
+  // small coarse levels take the full rule set on every plane, with all its
+  // loads issued at once (one memory round per plane); larger ones take the
+  // interior form where the whole wave can (fewer loads)
+  const bool ceager = cg.cells() <= NBHD_EAGER_CELLS;
+  bool full = d3 && !ceager && Cl.full[PC] != 0;
   for (int K = K0; K < K1; ++K, PC += cg.sxy) {
     // the fine cells' loads and the next plane's flag go out first: they do
     // not depend on the coarse values
@@ -909,12 +913,16 @@ __device__ __forceinline__ void prolong_body(const ProlongArgs<S, C, SC>& a, con
     if (d3) {
       fc1 = F.cls[P + F.g.sxy];
       x1 = x[P + F.g.sxy];
-      full_next = K + 1 < K1 && Cl.full[PC + cg.sxy] != 0;
+      full_next = !ceager && K + 1 < K1 && Cl.full[PC + cg.sxy] != 0;
     }
     C yp = 0, cz_lo = 0, cz_hi = 0;
     bool ap = false;
     if (d3) {
-      if (__all(full)) {
+      if (ceager) {
+        plane_rules<C, SC>(Cl, e, PC + cg.sxy, sx, oy, K + 1 < cg.nz, inx, iny, yp, ap);
+        cz_lo = (C)Cl.cf2[PC];
+        cz_hi = (C)Cl.cf2[PC + cg.sxy];
+      } else if (__all(full)) {
         yp = plane_interior<C, SC>(e, PC + cg.sxy, sx, oy);
         ap = true;
       } else {
