@@ -161,7 +161,8 @@ nfvm_status nfvm_step_batch(nfvm_grid_t* grids, int32_t n_grids, int32_t n_steps
  * FP64 [nz][ny][nx]; x is the initial guess on entry and the solution on exit;
  * solid cells are ignored on entry and 0 on exit; b = 0 gives x = 0.
  * forced_cycles >= 0 runs exactly that many cycles (tol ignored).  stats may
- * be NULL. */
+ * be NULL.  A domain with no outlet has a singular operator (constant mode):
+ * a non-zero b then ends in NFVM_E_NOTCONV or NFVM_E_DIVERGED. */
 nfvm_status nfvm_mg_solve(nfvm_grid_t grid, const double* b, double* x, double tol,
                           int32_t max_cycles, int32_t forced_cycles, nfvm_step_stats* stats);
 
