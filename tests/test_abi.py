@@ -45,3 +45,18 @@ def test_footprint_and_validation_without_gpu():
     with pytest.raises(nfvm.NfvmError) as e:
         nfvm.nfvm_grid_footprint(bad)
     assert e.value.status == nfvm.NFVM_E_INVAL
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the binding raises instead of falling
+    back to anything (run in a fresh interpreter so the loaded library of
+    this process is not reused)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2603_21869_amd import nfvm\n"
+            "nfvm.LIB_PATH = '/nonexistent/libnfvm.so'\n"
+            "try:\n    nfvm.lib()\nexcept OSError as e:\n    print('raised', e)\n    sys.exit(0)\n"
+            "sys.exit(1)\n") % ROOT
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and "raised" in r.stdout, r.stdout + r.stderr
