@@ -452,7 +452,7 @@ typedef struct {
 } orc_level;
 
 struct orc_mg {
-  int dim, L, nu1, nu2;
+  int dim, L, nu1, nu2, prolong;
   double wj;
   orc_level lv[24];
   int nc;        /* active cells on the coarsest level */
@@ -560,11 +560,24 @@ static int in_box(const orc_level* l, const int q[3]) {
 
 /* Prolongation (PROL, eq. prolongation): cell-centred linear interpolation
  * applied axis by axis (x, then y, then z) with weights 3/4 (parent side)
- * and 1/4 (neighbour side); the correction is added to active fine cells. */
+ * and 1/4 (neighbour side); the correction is added to active fine cells.
+ * With prolong = 1 the upsampling of Algorithm 1 is read as nearest
+ * (piecewise-constant) instead. */
 void orc_mg_prolong_add(const orc_mg* mg, int li, const double* e, double* x) {
   const orc_level* f = &mg->lv[li];
   const orc_level* c = &mg->lv[li + 1];
   int dim = mg->dim;
+  if (mg->prolong == 1) {
+    /* nearest upsampling: an active fine cell takes its parent's value (the
+     * parent of an active cell is active) */
+    for (int k = 0; k < f->n[2]; ++k)
+      for (int j = 0; j < f->n[1]; ++j)
+        for (int i = 0; i < f->n[0]; ++i) {
+          int P = lidx(f, i, j, k);
+          if (f->act[P]) x[P] += e[lidx(c, i / 2, j / 2, dim == 3 ? k / 2 : 0)];
+        }
+    return;
+  }
   for (int k = 0; k < f->n[2]; ++k)
     for (int j = 0; j < f->n[1]; ++j)
       for (int i = 0; i < f->n[0]; ++i) {
@@ -695,6 +708,7 @@ orc_mg* orc_mg_create(const orc_case* c) {
   mg->dim = c->dim;
   mg->L = c->n_levels;
   mg->nu1 = c->nu1;
+  mg->prolong = c->prolong;
   mg->nu2 = c->nu2;
   mg->wj = c->omega_jacobi > 0 ? c->omega_jacobi : (c->dim == 3 ? 6.0 / 7.0 : 4.0 / 5.0);
   /* level 0 from the cell classification */

@@ -45,6 +45,9 @@ typedef struct {
   double omega_jacobi; /* 0 = 4/5 in 2D, 6/7 in 3D */
   double tol;
   int max_cycles;
+  int prolong;         /* 0: linear interpolation (eq. prolongation); 1: nearest
+                          (piecewise constant), the plainest reading of the
+                          upsampling in Algorithm 1 */
 } orc_case;
 
 typedef struct { double *u, *v, *w, *p, *T, *k, *omega; } orc_fields;

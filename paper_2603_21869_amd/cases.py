@@ -26,6 +26,7 @@ WALL, INLET, OUTLET = 0, 1, 2
 KIND_NAMES = {WALL: "wall", INLET: "inlet", OUTLET: "outlet"}
 
 PREC_FP64, PREC_FP32, PREC_MIXED = 0, 1, 2
+PROL_LINEAR, PROL_NEAREST = 0, 1
 
 PHYS_KOMEGA, PHYS_ENERGY, PHYS_BUOYANCY = 1, 2, 4
 
@@ -97,6 +98,9 @@ class Case:
     omega_jacobi: float = 0.0  # 0: method default for the dimension
     tol: float = 1e-6
     max_cycles: int = 100
+    # multigrid prolongation: PROL_LINEAR (eq. prolongation) or PROL_NEAREST
+    # (piecewise constant, the plainest reading of Algorithm 1's upsampling)
+    prolong: int = 0
     n_steps: int = 1
     seed: int = 0
 

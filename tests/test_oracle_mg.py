@@ -145,6 +145,88 @@ def test_transfer_operators(oracle):
     assert mg.restrict(0, f).sum() * 8 == pytest.approx(f.sum(), rel=1e-12)
 
 
+def _vented_box(n_levels, **kw):
+    n = (16, 8, 8)
+    solid = np.zeros((8, 8, 16), dtype=np.uint8)
+    solid[0:4, 2:5, 5:9] = 1
+    pats = [C.Patch(0, (2, 5), (5, 8), kind=C.INLET, U=(1, 0, 0)),
+            C.Patch(1, (3, 0), (6, 2), kind=C.OUTLET)]
+    return box(n, (0.1, 0.12, 0.09), patches=pats, solid=solid, n_levels=n_levels, **kw)
+
+
+def test_nearest_prolongation_is_scaled_transpose_of_restriction(oracle):
+    """Nearest upsampling (the plainest reading of Algorithm 1's upsampling)
+    and mean-of-children restriction are adjoint up to the factor 2^d on the
+    active cells: <R r, e>_coarse * 2^d = <r, P e>_fine for every r, e.  A
+    block-constant field over fully active blocks survives R then P.  The
+    linear prolongation fails the adjoint identity, so the option changes
+    the operator."""
+    for dim in (3, 2):
+        if dim == 3:
+            c = _vented_box(3, prolong=C.PROL_NEAREST)
+            lin = oracle.MG(_vented_box(3))
+        else:
+            c = box((16, 12, 1), (0.1, 0.1, 1.0), dim=2, kinds=[C.WALL, C.OUTLET, C.WALL, C.WALL],
+                    n_levels=3, prolong=C.PROL_NEAREST)
+            lin = oracle.MG(box((16, 12, 1), (0.1, 0.1, 1.0), dim=2,
+                                kinds=[C.WALL, C.OUTLET, C.WALL, C.WALL], n_levels=3))
+        mg = oracle.MG(c)
+        rng = np.random.default_rng(11 + dim)
+        for l in (0, 1):
+            fa, ca = mg.active(l).astype(bool), mg.active(l + 1).astype(bool)
+            r = rng.standard_normal(fa.shape) * fa
+            e = rng.standard_normal(ca.shape) * ca
+            Pe = mg.prolong_add(l, e, np.zeros(fa.shape))
+            assert not Pe[~fa].any()
+            lhs = (mg.restrict(l, r) * e).sum() * 2 ** dim
+            assert lhs == pytest.approx((r * Pe).sum(), rel=1e-12)
+            Pl = lin.prolong_add(l, e, np.zeros(fa.shape))
+            assert abs(lhs - (r * Pl).sum()) > 1e-3 * abs(lhs)
+            # block-constant over blocks whose children are all active
+            f = np.repeat(np.repeat(e, 2, axis=-1), 2, axis=-2)
+            if dim == 3:
+                f = np.repeat(f, 2, axis=0)
+            blocks = np.repeat(np.repeat(ca, 2, axis=-1), 2, axis=-2)
+            if dim == 3:
+                blocks = np.repeat(blocks, 2, axis=0)
+            full = fa.copy()
+            for idx in np.argwhere(blocks & ~fa):
+                I = tuple(i // 2 for i in idx) if dim == 3 else (0, idx[1] // 2, idx[2] // 2)
+                sl = tuple(slice(2 * i, 2 * i + 2) for i in I) if dim == 3 else \
+                    (slice(0, 1), slice(2 * I[1], 2 * I[1] + 2), slice(2 * I[2], 2 * I[2] + 2))
+                full[sl] = False
+            back = mg.prolong_add(l, mg.restrict(l, f * fa), np.zeros(fa.shape))
+            assert np.allclose(back[full], f[full], rtol=1e-14, atol=0)
+
+
+def test_nearest_cycles_reach_the_dense_solution(oracle):
+    """Brute force: with nearest prolongation, as V(2,2) and as Algorithm 1's
+    V(0,1) shape, the preconditioned solve reaches the dense solution of the
+    assembled operator (the preconditioner changes the path, not the answer),
+    and the linear prolongation needs fewer cycles."""
+    lin = _vented_box(4)
+    mg0 = oracle.MG(lin)
+    act = mg0.active(0).astype(bool)
+    ids = np.flatnonzero(act)
+    A = np.zeros((ids.size, ids.size))
+    for col, q in enumerate(ids):
+        e = np.zeros(act.size)
+        e[q] = 1.0
+        A[:, col] = mg0.apply(0, e.reshape(act.shape)).ravel()[ids]
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(act.shape) * act
+    want = np.linalg.solve(A, b.ravel()[ids])
+    _, cyc_lin, _, st = mg0.solve(b, tol=1e-12, max_cycles=200)
+    assert st == 0
+    for nu1, nu2 in ((2, 2), (0, 1)):
+        mg = oracle.MG(_vented_box(4, prolong=C.PROL_NEAREST, nu1=nu1, nu2=nu2))
+        sol, cyc, rel, st = mg.solve(b, tol=1e-12, max_cycles=400)
+        assert st == 0 and rel <= 1e-12
+        assert np.abs(sol.ravel()[ids] - want).max() <= 1e-9 * np.abs(want).max()
+        assert not sol[~act].any()
+        assert cyc > cyc_lin
+
+
 def test_projection_identity_and_divergence_free(oracle):
     """Face fluxes after projection satisfy sum_d D_d F_d = -dt (b - A phi) per
     cell for any phi; with a converged phi the face divergence is round-off
