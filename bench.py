@@ -335,6 +335,17 @@ def main():
         variants[args.precision + "_warm_start"] = dict(
             value=case.ncells * args.steps / sw / 1e6, ms_per_step=sw / args.steps * 1e3,
             mean_cycles=sum(x["cycles"] for x in stw) / len(stw))
+        # Algorithm 1's upsampling read as nearest (piecewise constant), in
+        # the V(2,2) cycle and in Algorithm 1's own V(0,1) shape
+        for vname, kw in (("nearest_prolongation", dict(prolong=C.PROL_NEAREST)),
+                          ("alg1_v01_nearest", dict(prolong=C.PROL_NEAREST, nu1=0, nu2=1))):
+            c2 = make_case(args.workload, prec, args.tol).copy(**kw)
+            k2 = max(5, args.steps // 2)
+            s2, st2, _, _ = run_gpu(c2, k2, args.warmup, False, stream)
+            variants[args.precision + "_" + vname] = dict(
+                value=c2.ncells * k2 / s2 / 1e6, ms_per_step=s2 / k2 * 1e3,
+                mean_cycles=sum(x["cycles"] for x in st2) / len(st2),
+                statuses=sorted({x["status"] for x in st2}))
         for pname, pv in (("fp64", C.PREC_FP64), ("fp32", C.PREC_FP32), ("mixed", C.PREC_MIXED)):
             if pv == prec:
                 continue

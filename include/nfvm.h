@@ -263,13 +263,23 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
  *                     varying flow; the increment is not part of the
  *                     fields, so a restarted run then agrees with the
  *                     uninterrupted one to the solver tolerance only.
+ *   NFVM_OPT_PROLONG  0 (default): the multigrid correction is prolongated
+ *                     by cell-centred linear interpolation (Sec. 2.4, eq.
+ *                     prolongation).  1: nearest (piecewise-constant)
+ *                     upsampling, the plainest reading of the upsampling in
+ *                     Algorithm 1; the coarse levels then run one launch per
+ *                     operator and level (the LDS-resident bottom solver
+ *                     interpolates linearly).  Grids batch together only
+ *                     with grids of the same setting.  Other values:
+ *                     NFVM_E_INVAL.
  * Errors: NFVM_E_INVAL for an unknown option. */
 enum {
   NFVM_OPT_GRAPHS = 0,
   NFVM_OPT_PREDICT = 1,
   NFVM_OPT_BOTTOM = 2,
   NFVM_OPT_AUTOTUNE = 3,
-  NFVM_OPT_WARM_START = 4
+  NFVM_OPT_WARM_START = 4,
+  NFVM_OPT_PROLONG = 5
 };
 
 /* The autotuner's choices so far: up to max entries of {kernel id, nx, ny,

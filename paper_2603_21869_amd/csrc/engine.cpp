@@ -605,6 +605,9 @@ class GridT : public GridBase {
 
   // levels bottom_top .. L-1 run in one LDS-resident workgroup
   int bottom_top = -1;
+  // nearest (piecewise-constant) prolongation on every level; the bottom
+  // solver's prolongation is linear, so it is not used then
+  bool nearest = false;
   Bottom bot{};
 
   // LDS layout of the bottom solver: iterates and right-hand sides of every
@@ -623,7 +626,7 @@ class GridT : public GridBase {
 
   void setup_bottom() {
     bottom_top = -1;
-    if (!use_bottom || L < 3) return;
+    if (!use_bottom || nearest || L < 3) return;
     const size_t limit = bottom_lds_limit<SC, C>();
     size_t bytes = al16(COARSE_MAX * sizeof(int));
     int top = L;
@@ -1063,7 +1066,8 @@ class GridT : public GridBase {
   }
 
   // ---- batched iterations ----
-  int type_id() const override { return desc.precision; }
+  // grids batch together when they share precision and prolongation
+  int type_id() const override { return desc.precision + (nearest ? 16 : 0); }
 
   void mg_desc(MgGridDesc& d) {
     memset(&d, 0, sizeof d);
@@ -1134,6 +1138,14 @@ class GridT : public GridBase {
       NFVM_CK(hipStreamSynchronize(stream));
       drop_graphs();
       use_bottom = v != 0.0;
+      setup_bottom();
+    } else if (opt == NFVM_OPT_PROLONG) {
+      if (v != 0.0 && v != 1.0)
+        throw Error{NFVM_E_INVAL, "prolongation must be 0 (linear) or 1 (nearest)"};
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
+      nearest = v != 0.0;
+      for (int l = 0; l + 1 < L; ++l) lv[l].nearest = nearest;
       setup_bottom();
     } else {
       throw Error{NFVM_E_INVAL, "unknown option"};

@@ -1079,8 +1079,47 @@ __device__ __forceinline__ void prolong4_body(const ProlongArgs<S, C, SC>& a, co
 NFVM_TILE_KERNELS(k_prolong4, prolong4_body, ProlongArgs, (S, C, SC),
                   (class S, class C, class SC), (S, C, SC), MBS, false)
 
+// Nearest (piecewise-constant) upsampling, the plainest reading of
+// Algorithm 1's upsampling: every active fine cell adds its parent's
+// correction (the parent of an active cell is active).  One thread per fine
+// column walking the coarse planes of its tile, two fine cells per plane in
+// 3D; the same tiles as the linear kernel.
+template <class S, class C, class SC>
+__device__ __forceinline__ void prolong_nearest_body(const ProlongArgs<S, C, SC>& a,
+                                                     const TileCtx& c, bool) {
+  const bool done = a.ctl[S_DONE] != 0.0;
+  const LevelView& F = a.F;
+  const Geom& cg = a.Cl.g;
+  S* __restrict__ x = a.x;
+  const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
+  if (i >= F.g.nx || j >= F.g.ny) return;
+  const bool d3 = cg.dim == 3;
+  const int K0 = c.tz * a.T.cz, K1 = min(cg.nz, K0 + a.T.cz);
+  int PC = cg.idx(i >> 1, j >> 1, K0);
+  int P = F.g.idx(i, j, d3 ? 2 * K0 : 0);
+  for (int K = K0; K < K1; ++K, PC += cg.sxy) {
+    const C e = St<SC, C>::ld(a.e + PC);
+    const uint8_t fc0 = F.cls[P];
+    const S x0 = x[P];
+    uint8_t fc1 = MG_INACTIVE;
+    S x1 = x0;
+    if (d3) {
+      fc1 = F.cls[P + F.g.sxy];
+      x1 = x[P + F.g.sxy];
+    }
+    if (done) return;
+    if (fc0 != MG_INACTIVE) St<S, C>::st(x + P, St<S, C>::ld(&x0) + e);
+    if (d3 && fc1 != MG_INACTIVE) St<S, C>::st(x + P + F.g.sxy, St<S, C>::ld(&x1) + e);
+    P += d3 ? 2 * F.g.sxy : 0;
+  }
+}
+NFVM_TILE_KERNELS(k_prolong_nearest, prolong_nearest_body, ProlongArgs, (S, C, SC),
+                  (class S, class C, class SC), (S, C, SC), MBS, false)
+
 // Whether the prolongation to fine level f takes the four-column kernel.
-__host__ inline bool prolong_quad(const Level& f) { return f.code && f.g.nx % 4 == 0; }
+__host__ inline bool prolong_quad(const Level& f) {
+  return f.code && f.g.nx % 4 == 0 && !f.nearest;
+}
 
 template <class S, class C, class SC>
 ProlongArgs<S, C, SC> prolong_args(const Level& f, const Level& c, const double* ctl) {
@@ -1095,7 +1134,9 @@ ProlongArgs<S, C, SC> prolong_args(const Level& f, const Level& c, const double*
 template <class S, class C, class SC>
 void launch_prolong(const Level& f, const Level& c, const double* ctl, hipStream_t s) {
   const ProlongArgs<S, C, SC> a = prolong_args<S, C, SC>(f, c, ctl);
-  if (prolong_quad(f)) {
+  if (f.nearest) {
+    NFVM_LAUNCH((k_prolong_nearest<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
+  } else if (prolong_quad(f)) {
     if constexpr (has_quad<S>)
       NFVM_LAUNCH((k_prolong4<S, C, SC>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   } else {
@@ -2317,22 +2358,25 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
   }
   // up: prolongation and post-smoothing
   for (int l = top - 1; l >= 0; --l) {
-    Group<ProlongArgs<S0, C, SC>> p0, p0q;
-    Group<ProlongArgs<SC, C, SC>> pc;
+    Group<ProlongArgs<S0, C, SC>> p0, p0q, p0n;
+    Group<ProlongArgs<SC, C, SC>> pc, pcn;
     for (int i = 0; i < n; ++i) {
       MgGridDesc& d = G[i];
       if (l >= stop_level(d)) continue;
       if (l == 0) {
-        (prolong_quad(d.lv[0]) ? p0q : p0)
+        (d.lv[0].nearest ? p0n : prolong_quad(d.lv[0]) ? p0q : p0)
             .push_back(prolong_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out));
       } else {
-        pc.push_back(prolong_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out));
+        (d.lv[l].nearest ? pcn : pc)
+            .push_back(prolong_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out));
       }
     }
     emit_tiles(o, p0, k_prolong<S0, C, SC>, k_prolong_batch<S0, C, SC>, false);
     if constexpr (has_quad<S0>)
       emit_tiles(o, p0q, k_prolong4<S0, C, SC>, k_prolong4_batch<S0, C, SC>, false);
+    emit_tiles(o, p0n, k_prolong_nearest<S0, C, SC>, k_prolong_nearest_batch<S0, C, SC>, false);
     emit_tiles(o, pc, k_prolong<SC, C, SC>, k_prolong_batch<SC, C, SC>, false);
+    emit_tiles(o, pcn, k_prolong_nearest<SC, C, SC>, k_prolong_nearest_batch<SC, C, SC>, false);
     for (int s = 0; s < nu2; ++s) {
       SweepGroups<S0, C> g0;
       SweepGroups<SC, C> gc;

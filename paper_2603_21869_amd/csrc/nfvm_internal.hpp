@@ -132,6 +132,8 @@ struct Level {
   void* b;                      // right-hand side
   int cur;                      // which x is current
   uint16_t* code;               // level 0 only: face codes (else null)
+  bool nearest = false;         // correction from the next coarser level taken
+                                // as nearest (piecewise constant), not linear
 };
 
 // Level-0 face code of a cell: 2 bits per face (x-, x+, y-, y+, z-, z+ from

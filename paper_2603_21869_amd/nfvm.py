@@ -260,6 +260,7 @@ def nfvm_profile_read(grid, kernel: int):
 
 NFVM_OPT_GRAPHS, NFVM_OPT_PREDICT, NFVM_OPT_BOTTOM, NFVM_OPT_AUTOTUNE = 0, 1, 2, 3
 NFVM_OPT_WARM_START = 4
+NFVM_OPT_PROLONG = 5
 
 
 def nfvm_tuning_table():
@@ -321,6 +322,8 @@ class Grid:
         self.desc = Desc(case, precision, tol, max_cycles)
         self.shape = (case.n[2], case.n[1], case.n[0])
         self.h = nfvm_init_grid(self.desc, case.fields if fields is None else fields, stream)
+        if getattr(case, "prolong", 0):
+            nfvm_set_option(self.h, NFVM_OPT_PROLONG, float(case.prolong))
 
     def step(self, n: int, allow=(NFVM_OK,)):
         return nfvm_step(self.h, n, allow)

@@ -221,6 +221,80 @@ def test_odd_and_one_sided_smoothing_matches_oracle(nf, oracle, nu):
     g2.close()
 
 
+def _nearest_cases():
+    return [
+        ("ch2d", C.channel2d(96, 18, L=4.0, H=1.0, n_levels=2, n_steps=2)),
+        ("ch3d", C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3, n_steps=2, tol=1e-9)),
+        ("room", C.room3d(64, 24, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4, n_steps=2,
+                          tol=1e-9)),
+        ("open", C.open_channel(48, 16, 16, h=0.02, n_levels=3, n_steps=2, tol=1e-9,
+                                precision=C.PREC_FP64)),
+    ]
+
+
+@pytest.mark.parametrize("name,case", _nearest_cases(), ids=[c[0] for c in _nearest_cases()])
+def test_nearest_prolongation_matches_oracle(nf, oracle, name, case):
+    """NFVM_OPT_PROLONG = 1 (nearest upsampling): the pressure solve and the
+    time step match the oracle run with the same prolongation, as V(2,2) and
+    as Algorithm 1's V(0,1) shape, in FP64 and in mixed precision."""
+    case = case.copy(prolong=C.PROL_NEAREST, precision=C.PREC_FP64)
+    m = fluid(case)
+    g = nf.Grid(case)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(g.shape) * m
+    x, st, s = g.mg_solve(b, tol=1e-10, max_cycles=80)
+    assert s == 0 and st["rel_residual"] <= 1e-10
+    xr, _, _, _ = oracle.MG(case).solve(b, forced=st["cycles"])
+    err = np.linalg.norm((x - xr)[m]) / np.linalg.norm(xr[m])
+    print(f"[nearest] {name} mg_solve cycles={st['cycles']} err={err:.2e}", flush=True)
+    assert err < 1e-12 and not x[~m].any()
+    g.close()
+    for nu in ((2, 2), (0, 1)):
+        for prec in (C.PREC_FP64, C.PREC_MIXED):
+            # solved to 1e-10 so that the mixed comparison measures the
+            # arithmetic, not how far each side stopped short of the answer
+            c2 = case.copy(nu1=nu[0], nu2=nu[1], precision=prec, tol=1e-10)
+            g = nf.Grid(c2)
+            s, stats = g.step(c2.n_steps, allow=(0, nf.NFVM_E_NOTCONV))
+            out = g.fields()
+            g.close()
+            cyc = [x["cycles"] for x in stats]
+            ref, _, _ = oracle.step(c2, c2.n_steps, forced_cycles=cyc)
+            errs = field_errors(c2, out, ref)
+            print(f"   nu={nu} prec={prec} cycles={cyc}", {k: f"{v:.2e}" for k, v in errs.items()},
+                  flush=True)
+            for f in ("vel", "p", "k", "omega"):
+                assert errs[f] <= TOL[prec], (f, errs[f])
+
+
+def test_nearest_prolongation_batches_apart(nf):
+    """Grids with nearest and with linear prolongation stepped in one batch
+    keep their own V-cycles: each ends bitwise equal to its run alone."""
+    base = C.channel3d(64, 16, 16, Lx=1.28, Ly=0.32, Lz=0.32, n_levels=3, n_steps=2, tol=1e-9)
+    cases = [base.copy(prolong=C.PROL_NEAREST), base,
+             base.copy(prolong=C.PROL_NEAREST, precision=C.PREC_MIXED),
+             base.copy(prolong=C.PROL_NEAREST, nu1=0, nu2=1)]
+    alone = []
+    for c in cases:
+        g = nf.Grid(c)
+        g.step(2, allow=(0, nf.NFVM_E_NOTCONV))
+        alone.append(g.fields())
+        g.close()
+    gs = [nf.Grid(c) for c in cases]
+    nf.nfvm_step_batch([g.h for g in gs], 2)
+    for i, g in enumerate(gs):
+        f = g.fields()
+        for k in f:
+            assert np.array_equal(f[k], alone[i][k]), (i, k)
+        g.close()
+    # linear and nearest differ (the option reaches the kernels)
+    assert not np.array_equal(alone[0]["p"], alone[1]["p"])
+    g = nf.Grid(base)
+    with pytest.raises(nf.NfvmError):
+        nf.nfvm_set_option(g.h, nf.NFVM_OPT_PROLONG, 2.0)
+    g.close()
+
+
 @pytest.mark.parametrize("prec", [C.PREC_FP64, C.PREC_MIXED], ids=["fp64", "mixed"])
 def test_fluid_at_rest_stays_at_rest(nf, prec):
     """Degenerate input: a closed box of fluid at rest.  The Poisson
