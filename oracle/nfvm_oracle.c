@@ -288,7 +288,7 @@ void orc_explicit_rhs(const orc_case* c, const orc_fields* s, orc_fields* r) {
  * Runge-Kutta of unstated order, read as first order), with k and omega
  * clamped to stay positive (appendix, explicit time stepping); solid cells and
  * wall-fixed omega cells keep their values. */
-void orc_explicit(const orc_case* c, const orc_fields* s, orc_fields* o) {
+static void explicit_euler(const orc_case* c, const orc_fields* s, orc_fields* o) {
   int N = ncells(c);
   orc_fields r;
   double* buf = (double*)malloc(sizeof(double) * 7 * N);
@@ -316,6 +316,30 @@ void orc_explicit(const orc_case* c, const orc_fields* s, orc_fields* o) {
           }
         }
       }
+  free(buf);
+}
+
+/* The explicit stage (Algorithms 2 and 4): one forward-Euler step, or with
+ * rk_order = 2 Heun's method written as the average of the start and a
+ * second Euler step taken from the first one (nu_t of the second from the
+ * first stage's k and omega; each stage clamps k and omega). */
+void orc_explicit(const orc_case* c, const orc_fields* s, orc_fields* o) {
+  explicit_euler(c, s, o);
+  if (c->rk_order != 2) return;
+  int N = ncells(c);
+  double* buf = (double*)malloc(sizeof(double) * 7 * N);
+  orc_fields t;
+  t.u = buf; t.v = buf + N; t.w = buf + 2 * N; t.p = buf + 3 * N;
+  t.T = buf + 4 * N; t.k = buf + 5 * N; t.omega = buf + 6 * N;
+  explicit_euler(c, o, &t);
+  for (int P = 0; P < N; ++P) {
+    o->u[P] = 0.5 * (s->u[P] + t.u[P]);
+    o->v[P] = 0.5 * (s->v[P] + t.v[P]);
+    o->w[P] = 0.5 * (s->w[P] + t.w[P]);
+    o->T[P] = 0.5 * (s->T[P] + t.T[P]);
+    o->k[P] = 0.5 * (s->k[P] + t.k[P]);
+    o->omega[P] = 0.5 * (s->omega[P] + t.omega[P]);
+  }
   free(buf);
 }
 

@@ -48,6 +48,9 @@ typedef struct {
   int prolong;         /* 0: linear interpolation (eq. prolongation); 1: nearest
                           (piecewise constant), the plainest reading of the
                           upsampling in Algorithm 1 */
+  int rk_order;        /* explicit stage: 1 forward Euler; 2 Heun's method in
+                          its strong-stability-preserving form (Sec. 2.6 leaves
+                          the Runge-Kutta scheme open) */
 } orc_case;
 
 typedef struct { double *u, *v, *w, *p, *T, *k, *omega; } orc_fields;

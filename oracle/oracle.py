@@ -36,7 +36,8 @@ class _Case(C.Structure):
                 ("T_solid", C.c_double), ("n_patches", C.c_int), ("patches", C.POINTER(_Patch)),
                 ("solid", C.POINTER(C.c_ubyte)), ("n_levels", C.c_int), ("nu1", C.c_int),
                 ("nu2", C.c_int), ("omega_jacobi", C.c_double), ("tol", C.c_double),
-                ("max_cycles", C.c_int), ("prolong", C.c_int)]
+                ("max_cycles", C.c_int), ("prolong", C.c_int),
+                ("rk_order", C.c_int)]
 
 
 class _Fields(C.Structure):
@@ -140,6 +141,7 @@ class OracleCase:
         c.tol = case.tol
         c.max_cycles = case.max_cycles
         c.prolong = case.prolong
+        c.rk_order = case.rk_order
         self.c = c
 
     @property

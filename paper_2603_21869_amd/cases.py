@@ -101,6 +101,9 @@ class Case:
     # multigrid prolongation: PROL_LINEAR (eq. prolongation) or PROL_NEAREST
     # (piecewise constant, the plainest reading of Algorithm 1's upsampling)
     prolong: int = 0
+    # explicit stage: 1 forward Euler, 2 Heun's method (SSP form); the paper
+    # names explicit Runge-Kutta schemes without fixing one (Sec. 2.6)
+    rk_order: int = 1
     n_steps: int = 1
     seed: int = 0
 

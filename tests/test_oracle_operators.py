@@ -103,6 +103,29 @@ def test_diffusion_of_cosine_mode_decays_by_closed_form(oracle):
             assert np.allclose(out, g * f["T"], rtol=0, atol=1e-13)
 
 
+def test_heun_stage_of_cosine_mode_is_second_order_polynomial(oracle):
+    """With rk_order = 2 the explicit stage is Heun's method: a cosine mode of
+    pure diffusion between adiabatic walls is multiplied by 1 - z + z^2/2,
+    z = 4 a dt/h^2 sin^2(pi m/(2n)), the second-order Taylor polynomial of
+    exp(-z) (the forward-Euler factor is 1 - z)."""
+    a, dt = 0.05, 0.01
+    for axis, (n, h) in enumerate(((16, 0.1), (12, 0.07), (10, 0.09))):
+        nn = [4, 4, 4]
+        nn[axis] = n
+        hh = [0.1, 0.1, 0.1]
+        hh[axis] = h
+        c = box(tuple(nn), tuple(hh), physics=C.PHYS_ENERGY, alpha_T=a, dt=dt, rk_order=2)
+        coord = centres(c)[axis]
+        L = n * h
+        for m in (1, 3, 7):
+            f = dict(c.fields)
+            f["T"] = np.cos(math.pi * m * coord / L)
+            out = oracle.explicit(c, f)["T"]
+            z = 4 * a * dt / h ** 2 * math.sin(math.pi * m / (2 * n)) ** 2
+            assert np.allclose(out, (1 - z + z * z / 2) * f["T"], rtol=0, atol=1e-13)
+            assert not np.allclose(out, (1 - z) * f["T"], rtol=0, atol=1e-6)
+
+
 def test_buoyancy_and_pressure_free_rest_state(oracle):
     """Fluid at rest with uniform T: the only momentum source is the Boussinesq
     term -beta_T (T - T_ref) g (vertical component)."""
