@@ -337,8 +337,10 @@ def main():
             mean_cycles=sum(x["cycles"] for x in stw) / len(stw))
         # Algorithm 1's upsampling read as nearest (piecewise constant), in
         # the V(2,2) cycle and in Algorithm 1's own V(0,1) shape
+        # and the explicit stage as Heun's second-order Runge-Kutta method
         for vname, kw in (("nearest_prolongation", dict(prolong=C.PROL_NEAREST)),
-                          ("alg1_v01_nearest", dict(prolong=C.PROL_NEAREST, nu1=0, nu2=1))):
+                          ("alg1_v01_nearest", dict(prolong=C.PROL_NEAREST, nu1=0, nu2=1)),
+                          ("heun_rk2", dict(rk_order=2))):
             c2 = make_case(args.workload, prec, args.tol).copy(**kw)
             k2 = max(5, args.steps // 2)
             s2, st2, _, _ = run_gpu(c2, k2, args.warmup, False, stream)

@@ -272,6 +272,16 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
  *                     interpolates linearly).  Grids batch together only
  *                     with grids of the same setting.  Other values:
  *                     NFVM_E_INVAL.
+ *   NFVM_OPT_RK_ORDER 1 (default): the explicit stage is one forward-Euler
+ *                     step.  2: Heun's second-order Runge-Kutta method
+ *                     (Sec. 2.6 leaves the explicit scheme open), as the
+ *                     average of the start and a second Euler step taken
+ *                     from the first, whose nu_t comes from the first
+ *                     stage's k and omega.  The first call with 2 allocates
+ *                     one more set of the six transported fields (three
+ *                     velocity and three scalar arrays, padded; not counted
+ *                     by nfvm_grid_footprint); NFVM_E_NOMEM if that fails.
+ *                     Other values: NFVM_E_INVAL.
  * Errors: NFVM_E_INVAL for an unknown option. */
 enum {
   NFVM_OPT_GRAPHS = 0,
@@ -279,7 +289,8 @@ enum {
   NFVM_OPT_BOTTOM = 2,
   NFVM_OPT_AUTOTUNE = 3,
   NFVM_OPT_WARM_START = 4,
-  NFVM_OPT_PROLONG = 5
+  NFVM_OPT_PROLONG = 5,
+  NFVM_OPT_RK_ORDER = 6
 };
 
 /* The autotuner's choices so far: up to max entries of {kernel id, nx, ny,

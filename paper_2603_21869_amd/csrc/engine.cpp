@@ -608,6 +608,9 @@ class GridT : public GridBase {
   // nearest (piecewise-constant) prolongation on every level; the bottom
   // solver's prolongation is linear, so it is not used then
   bool nearest = false;
+  // explicit stage: 1 forward Euler, 2 Heun (second stage written to rk2)
+  int rk_order = 1;
+  FieldSet<V, F> rk2{};
   Bottom bot{};
 
   // LDS layout of the bottom solver: iterates and right-hand sides of every
@@ -889,6 +892,12 @@ class GridT : public GridBase {
     FieldSet<V, F> out{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
     prof_begin(NFVM_K_EXPLICIT);
     launch_explicit<V, F, P>(g, ph, type, patches, in, p, nut, out, tp[TP_EXPLICIT], stream);
+    if (rk_order == 2) {
+      // Heun: a second Euler step from the first stage, averaged with the start
+      if (ph.komega) launch_nut<V, F>(g, ph, type, out.k, out.om, nut, stream);
+      launch_explicit<V, F, P>(g, ph, type, patches, out, p, nut, rk2, tp[TP_EXPLICIT], stream);
+      launch_rk2_average<V, F>(g, in, rk2, out, stream);
+    }
     prof_end(NFVM_K_EXPLICIT);
     for (int f = 0; f < 6; ++f) swap(f);
     prof_begin(NFVM_K_RHS);
@@ -1139,6 +1148,20 @@ class GridT : public GridBase {
       drop_graphs();
       use_bottom = v != 0.0;
       setup_bottom();
+    } else if (opt == NFVM_OPT_RK_ORDER) {
+      if (v != 1.0 && v != 2.0) throw Error{NFVM_E_INVAL, "Runge-Kutta order must be 1 or 2"};
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
+      if (v == 2.0 && !rk2.om) {  // allocated last: a failed set is made again
+        rk2.u = alloc<V>(g.total);
+        rk2.v = alloc<V>(g.total);
+        rk2.w = alloc<V>(g.total);
+        rk2.T = alloc<F>(g.total);
+        rk2.k = alloc<F>(g.total);
+        rk2.om = alloc<F>(g.total);
+        NFVM_CK(hipStreamSynchronize(stream));
+      }
+      rk_order = (int)v;
     } else if (opt == NFVM_OPT_PROLONG) {
       if (v != 0.0 && v != 1.0)
         throw Error{NFVM_E_INVAL, "prolongation must be 0 (linear) or 1 (nearest)"};

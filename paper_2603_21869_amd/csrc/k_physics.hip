@@ -400,6 +400,70 @@ INST_EXPLICIT(double, double, double)
 INST_EXPLICIT(float, float, float)
 INST_EXPLICIT(double, float, double)
 
+// ---- second-order explicit stage (option): Heun's method in its
+// strong-stability-preserving form, U* = (U + E(E(U))) / 2 with E the Euler
+// step above; the second step takes nu_t from the first stage's k and omega
+template <class V, class F>
+__global__ __launch_bounds__(BS) void k_nut(Geom g, Phys ph, const uint8_t* __restrict__ type,
+                                            const F* __restrict__ kk, const F* __restrict__ om,
+                                            F* __restrict__ nut, Tiles T) {
+  typedef V R;
+  int tx = 0, ty = 0, tz = 0;
+  const bool tile = tile_of(T, tx, ty, tz);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
+  if (!tile || i >= g.nx || j >= g.ny) return;
+  for (int k = kb; k < ke; ++k) {
+    const int P = g.idx(i, j, k);
+    if (is_fluid(type[P])) nut[P] = (F)eddy_visc<R>((R)ph.nu, (R)kk[P], (R)om[P]);
+  }
+}
+
+// out = (a + c) / 2 on every cell of the box (cells the Euler step leaves
+// alone hold the same value in a and c, which the average keeps exactly)
+template <class V, class F>
+__global__ __launch_bounds__(BS) void k_rk2_average(Geom g, FieldSet<V, F> a, FieldSet<V, F> c,
+                                                    FieldSet<V, F> out, Tiles T) {
+  typedef V R;
+  int tx = 0, ty = 0, tz = 0;
+  const bool tile = tile_of(T, tx, ty, tz);
+  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
+  if (!tile || i >= g.nx || j >= g.ny) return;
+  const R h = (R)0.5;
+  for (int k = kb; k < ke; ++k) {
+    const int P = g.idx(i, j, k);
+    out.u[P] = (V)(((R)a.u[P] + (R)c.u[P]) * h);
+    out.v[P] = (V)(((R)a.v[P] + (R)c.v[P]) * h);
+    out.w[P] = (V)(((R)a.w[P] + (R)c.w[P]) * h);
+    out.T[P] = (F)(((R)a.T[P] + (R)c.T[P]) * h);
+    out.k[P] = (F)(((R)a.k[P] + (R)c.k[P]) * h);
+    out.om[P] = (F)(((R)a.om[P] + (R)c.om[P]) * h);
+  }
+}
+
+template <class V, class F>
+void launch_nut(const Geom& g, const Phys& ph, const uint8_t* type, const F* k, const F* om,
+                F* nut, hipStream_t s) {
+  const Tiles T = cell_tiles(g, TILE_DEFAULT);
+  NFVM_LAUNCH((k_nut<V, F>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, k, om, nut, T);
+}
+
+template <class V, class F>
+void launch_rk2_average(const Geom& g, FieldSet<V, F> a, FieldSet<V, F> c, FieldSet<V, F> out,
+                        hipStream_t s) {
+  const Tiles T = cell_tiles(g, TILE_DEFAULT);
+  NFVM_LAUNCH((k_rk2_average<V, F>), dim3(T.grid), dim3(BX, BY), 0, s, g, a, c, out, T);
+}
+#define INST_RK2(V, F)                                                                        \
+  template void launch_nut<V, F>(const Geom&, const Phys&, const uint8_t*, const F*, const F*, \
+                                 F*, hipStream_t);                                            \
+  template void launch_rk2_average<V, F>(const Geom&, FieldSet<V, F>, FieldSet<V, F>,          \
+                                         FieldSet<V, F>, hipStream_t);
+INST_RK2(double, double)
+INST_RK2(float, float)
+INST_RK2(double, float)
+
 // ---- Poisson right-hand side: b = -(1/dt) sum_d D_d L_d BC_d(u*_d) ------------
 template <class F, class O>
 __global__ __launch_bounds__(BS) void k_rhs_b(Geom g, Phys ph, const uint8_t* __restrict__ type,

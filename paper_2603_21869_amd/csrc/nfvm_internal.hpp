@@ -207,6 +207,15 @@ struct FieldSet {
   F *T, *k, *om;
 };
 
+// second-order explicit stage (option): nu_t from k and omega on fluid
+// cells, and out = (a + c) / 2 over the box
+template <class V, class F>
+void launch_nut(const Geom& g, const Phys& ph, const uint8_t* type, const F* k, const F* om,
+                F* nut, hipStream_t s);
+template <class V, class F>
+void launch_rk2_average(const Geom& g, FieldSet<V, F> a, FieldSet<V, F> c, FieldSet<V, F> out,
+                        hipStream_t s);
+
 template <class V, class F>
 void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
                     const V* u, const V* v, const V* w, const F* k, const F* om, double tau,

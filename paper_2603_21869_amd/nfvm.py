@@ -261,6 +261,7 @@ def nfvm_profile_read(grid, kernel: int):
 NFVM_OPT_GRAPHS, NFVM_OPT_PREDICT, NFVM_OPT_BOTTOM, NFVM_OPT_AUTOTUNE = 0, 1, 2, 3
 NFVM_OPT_WARM_START = 4
 NFVM_OPT_PROLONG = 5
+NFVM_OPT_RK_ORDER = 6
 
 
 def nfvm_tuning_table():
@@ -324,6 +325,8 @@ class Grid:
         self.h = nfvm_init_grid(self.desc, case.fields if fields is None else fields, stream)
         if getattr(case, "prolong", 0):
             nfvm_set_option(self.h, NFVM_OPT_PROLONG, float(case.prolong))
+        if getattr(case, "rk_order", 1) != 1:
+            nfvm_set_option(self.h, NFVM_OPT_RK_ORDER, float(case.rk_order))
 
     def step(self, n: int, allow=(NFVM_OK,)):
         return nfvm_step(self.h, n, allow)

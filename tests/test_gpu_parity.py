@@ -295,6 +295,66 @@ def test_nearest_prolongation_batches_apart(nf):
     g.close()
 
 
+@pytest.mark.parametrize("name,case", _nearest_cases(), ids=[c[0] for c in _nearest_cases()])
+def test_heun_stage_matches_oracle(nf, oracle, name, case):
+    """NFVM_OPT_RK_ORDER = 2 (Heun's method for the explicit stage) matches
+    the oracle run with the same stage, in FP64 and in mixed precision, and
+    differs from the forward-Euler step."""
+    euler = None
+    for prec in (C.PREC_FP64, C.PREC_MIXED):
+        c2 = case.copy(rk_order=2, precision=prec, tol=1e-10)
+        g = nf.Grid(c2)
+        s, stats = g.step(c2.n_steps, allow=(0, nf.NFVM_E_NOTCONV))
+        out = g.fields()
+        g.close()
+        cyc = [x["cycles"] for x in stats]
+        ref, _, _ = oracle.step(c2, c2.n_steps, forced_cycles=cyc)
+        errs = field_errors(c2, out, ref)
+        print(f"[heun] {name} prec={prec} cycles={cyc}", {k: f"{v:.2e}" for k, v in errs.items()},
+              flush=True)
+        for f in ("vel", "p", "k", "omega"):
+            assert errs[f] <= TOL[prec], (f, errs[f])
+        if c2.physics & C.PHYS_ENERGY:
+            assert errs["T"] <= TOL[prec], ("T", errs["T"])
+        if prec == C.PREC_FP64:
+            g = nf.Grid(c2.copy(rk_order=1))
+            g.step(c2.n_steps, allow=(0, nf.NFVM_E_NOTCONV))
+            euler = g.fields()
+            g.close()
+            assert np.abs(euler["u"] - out["u"]).max() > 1e-12
+
+
+def test_heun_stage_in_a_batch_and_errors(nf):
+    """A Heun grid stepped in a batch with forward-Euler grids ends bitwise
+    equal to its run alone; switching back to order 1 restores the Euler
+    result; orders other than 1 and 2 are rejected."""
+    base = C.channel3d(64, 16, 16, Lx=1.28, Ly=0.32, Lz=0.32, n_levels=3, n_steps=2, tol=1e-9)
+    cases = [base.copy(rk_order=2), base, base.copy(rk_order=2, precision=C.PREC_MIXED)]
+    alone = []
+    for c in cases:
+        g = nf.Grid(c)
+        g.step(2, allow=(0, nf.NFVM_E_NOTCONV))
+        alone.append(g.fields())
+        g.close()
+    gs = [nf.Grid(c) for c in cases]
+    nf.nfvm_step_batch([g.h for g in gs], 2)
+    for i, g in enumerate(gs):
+        f = g.fields()
+        for k in f:
+            assert np.array_equal(f[k], alone[i][k]), (i, k)
+        g.close()
+    g = nf.Grid(cases[0])
+    nf.nfvm_set_option(g.h, nf.NFVM_OPT_RK_ORDER, 1.0)
+    g.step(2, allow=(0, nf.NFVM_E_NOTCONV))
+    f = g.fields()
+    for k in f:
+        assert np.array_equal(f[k], alone[1][k]), k
+    for bad in (0.0, 3.0, 1.5):
+        with pytest.raises(nf.NfvmError):
+            nf.nfvm_set_option(g.h, nf.NFVM_OPT_RK_ORDER, bad)
+    g.close()
+
+
 @pytest.mark.parametrize("prec", [C.PREC_FP64, C.PREC_MIXED], ids=["fp64", "mixed"])
 def test_fluid_at_rest_stays_at_rest(nf, prec):
     """Degenerate input: a closed box of fluid at rest.  The Poisson
