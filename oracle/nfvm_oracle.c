@@ -199,6 +199,23 @@ static void velgrad(const orc_case* c, const double* u, const double* v, const d
       G[a][b] = (a < c->dim) ? cgrad(c, vel[a], F_U + a, i, j, k, b) : 0.0;
 }
 
+/* Velocity gradient of every cell, G[a][b] = d u_a / d x_b as nine values
+ * per cell (row-major), with the central gradient and boundary ghosts of
+ * Algorithm 3; zero on non-fluid cells.  Post-processing input: the lambda2
+ * vortex criterion of Sec. 3.2 is formed from it. */
+void orc_velocity_gradient(const orc_case* c, const double* u, const double* v,
+                           const double* w, double* G9) {
+  for (int k = 0; k < c->n[2]; ++k)
+    for (int j = 0; j < c->n[1]; ++j)
+      for (int i = 0; i < c->n[0]; ++i) {
+        int P = cidx(c, i, j, k);
+        double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        if (is_fluid(c, P)) velgrad(c, u, v, w, i, j, k, G);
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) G9[9 * (size_t)P + 3 * a + b] = G[a][b];
+      }
+}
+
 /* S^2 = 2 S_ij S_ij (eqs. strain_rate_magnitude, strain_rate) */
 static double strain2(double G[3][3]) {
   double s = 0.0;

@@ -77,6 +77,11 @@ void orc_project(const orc_case* c, const double* phi, const double* us, const d
                  const double* ws, double* p, double* u, double* v, double* w,
                  double* max_face_div);
 
+/* d u_a / d x_b per cell, nine values per cell (row-major); zero on
+ * non-fluid cells (post-processing, Sec. 3.2). */
+void orc_velocity_gradient(const orc_case* c, const double* u, const double* v,
+                           const double* w, double* G9);
+
 orc_mg* orc_mg_create(const orc_case* c);
 void orc_mg_free(orc_mg* mg);
 int orc_mg_levels(const orc_mg* mg);

@@ -77,3 +77,27 @@ def test_warm_and_cold_started_steps_agree_to_tolerance(oracle):
     for k in ("u", "v", "p"):
         scale = np.abs(cold[k]).max()
         assert np.abs(warm[k] - cold[k]).max() <= 1e-6 * scale, k
+
+
+def test_lambda2_closed_forms(oracle):
+    """The lambda2 criterion (Sec. 3.2) on linear velocity fields, where the
+    central gradient is exact away from the walls: solid-body rotation gives
+    -Omega^2, plane shear 0, axisymmetric strain a^2/4, and rotation plus
+    axial strain a^2/4 - Omega^2 (negative, a vortex, only when the
+    rotation wins); non-fluid cells hold 0."""
+    from tests.boxcase import box, centres
+    solid = np.zeros((8, 10, 12), dtype=np.uint8)
+    solid[0, 0, 0] = 1
+    c = box((12, 10, 8), (0.1, 0.12, 0.09), kinds=[C.WALL] * 6, solid=solid)
+    x, y, z = centres(c)
+    x, y, z = x - x.mean(), y - y.mean(), z - z.mean()
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    Om, a, gam = 1.7, 0.9, 2.3
+    cases = [((-Om * y, Om * x, 0 * z), -Om ** 2),
+             ((gam * y, 0 * x, 0 * z), 0.0),
+             ((-a * x / 2, -a * y / 2, a * z), a * a / 4),
+             ((-a * x / 2 - Om * y, -a * y / 2 + Om * x, a * z), a * a / 4 - Om ** 2)]
+    for (u, v, w), want in cases:
+        l2 = oracle.lambda2(c, u, v, w)
+        assert np.allclose(l2[inner], want, rtol=0, atol=1e-12)
+        assert l2[0, 0, 0] == 0.0
