@@ -277,6 +277,8 @@ def main():
                     help="requests of the serving trace to replay (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=9)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--lambda2", type=int, default=3,
+                    help="lambda2 post-processing calls timed after the run (0: skip)")
     ap.add_argument("--no-paper-table", action="store_true",
                     help="skip the paper's open-channel timing workload (three lengths)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -359,6 +361,21 @@ def main():
                                    mean_cycles=sum(x["cycles"] for x in st2) / len(st2))
 
     pcie = run_pcie(case, args.steps, stream)
+    post = None
+    if args.lambda2 > 0:
+        # the lambda2 vortex criterion of the stepped velocity, handed back
+        # in host memory (device kernel plus the FP64 copy over PCIe)
+        from paper_2603_21869_amd import nfvm
+        g = nfvm.Grid(case, stream=stream)
+        g.step(1, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+        g.lambda2()
+        t0 = time.perf_counter()
+        for _ in range(args.lambda2):
+            l2 = g.lambda2()
+        sec = (time.perf_counter() - t0) / args.lambda2
+        g.close()
+        post = dict(lambda2_ms_host=round(sec * 1e3, 3), calls=args.lambda2,
+                    vortex_cells=int((l2 < 0).sum()))
     traffic, traffic_src = measured_traffic(args.workload, args.precision, dom)
     out = {
         "metric": "Mcell-steps/s at 1e-6 residual",
@@ -389,6 +406,7 @@ def main():
         "variants": variants,
         "stream_launch_ms_per_step": round(psec / args.steps * 1e3, 4),
         "pcie_inclusive_mcell_steps_s": round(pcie, 2),
+        "postprocess": post,
         "tuning": [list(t) for t in nfvm.nfvm_tuning_table()],
         "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
                          "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",

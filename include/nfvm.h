@@ -173,6 +173,17 @@ nfvm_status nfvm_mg_solve_device(nfvm_grid_t grid, const double* b_dev, double* 
 
 /* Copy the fields to / from host FP64 arrays (all seven pointers required). */
 nfvm_status nfvm_get_fields(nfvm_grid_t grid, nfvm_fields* out);
+
+/* Vortex criterion of Sec. 3.2 (lambda2 of Jeong and Hussain) for the
+ * grid's current velocity: per cell the middle eigenvalue of S^2 + W^2,
+ * with S and W the symmetric and antisymmetric parts of the velocity
+ * gradient (central differences with the boundary ghosts, as in the
+ * destruction step of Algorithm 3); negative values mark vortex cores.
+ * Non-fluid cells receive 0.  lambda2: host array of n[0]*n[1]*n[2] FP64
+ * values, C order [nz][ny][nx], written before return (the call waits for
+ * the grid's stream).  Computed on the device in the velocity's precision.
+ * Errors: NFVM_E_INVAL for a null argument. */
+nfvm_status nfvm_lambda2(nfvm_grid_t grid, double* lambda2);
 nfvm_status nfvm_set_fields(nfvm_grid_t grid, const nfvm_fields* in);
 
 /* Bytes of device memory a grid with this descriptor allocates. */

@@ -236,16 +236,23 @@ def destroy(case, u, v, w, k, omega, tau):
     return ko, oo
 
 
+def velocity_gradient(case, u, v, w):
+    """G[..., a, b] = d u_a / d x_b per cell (central, with boundary ghosts);
+    zero on non-fluid cells."""
+    oc = OracleCase(case)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (u, v, w)]
+    G = np.zeros(oc.shape + (3, 3))
+    lib().orc_velocity_gradient(oc.ref, *[_ptr(x) for x in a], _ptr(G))
+    return G
+
+
 def lambda2(case, u, v, w):
     """Vortex criterion of Sec. 3.2 (Jeong and Hussain): the middle
     eigenvalue of S^2 + W^2, S and W the symmetric and antisymmetric parts of
     the velocity gradient (the oracle's central gradient with boundary
     ghosts); zero on non-fluid cells.  The eigenvalues come from numpy's
     symmetric eigensolver."""
-    oc = OracleCase(case)
-    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (u, v, w)]
-    G = np.zeros(oc.shape + (3, 3))
-    lib().orc_velocity_gradient(oc.ref, *[_ptr(x) for x in a], _ptr(G))
+    G = velocity_gradient(case, u, v, w)
     S = 0.5 * (G + np.swapaxes(G, -1, -2))
     W = 0.5 * (G - np.swapaxes(G, -1, -2))
     M = S @ S + W @ W

@@ -172,6 +172,14 @@ nfvm_status nfvm_get_fields(nfvm_grid_t grid, nfvm_fields* out) {
   });
 }
 
+nfvm_status nfvm_lambda2(nfvm_grid_t grid, double* lambda2) {
+  if (!grid || !lambda2) return fail(NFVM_E_INVAL, "grid and lambda2 are required");
+  return guard([&] {
+    grid->g->lambda2(lambda2);
+    return NFVM_OK;
+  });
+}
+
 nfvm_status nfvm_set_fields(nfvm_grid_t grid, const nfvm_fields* in) {
   if (!grid || !in) return fail(NFVM_E_INVAL, "grid and fields are required");
   return guard([&] {

@@ -2,6 +2,7 @@
 // order of kernels in a time step (Sec. 2.6: destruction over dt/2, explicit
 // step, projection, destruction over dt/2) and in the pressure solve.
 #include "engine.hpp"
+#include "post.hpp"
 
 #include <math.h>
 #include <string.h>
@@ -585,6 +586,15 @@ class GridT : public GridBase {
       NFVM_CK(hipMemcpyAsync(dst[f], stage, bytes, hipMemcpyDeviceToHost, stream));
       NFVM_CK(hipStreamSynchronize(stream));
     }
+  }
+
+  void lambda2(double* out) override {
+    if (!out) throw Error{NFVM_E_INVAL, "an output array is required"};
+    launch_lambda2<V>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), stage, stream);
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipMemcpyAsync(out, stage, (size_t)ncells * sizeof(double), hipMemcpyDeviceToHost,
+                           stream));
+    NFVM_CK(hipStreamSynchronize(stream));
   }
 
   // ---- multigrid ------------------------------------------------------------------

@@ -112,6 +112,7 @@ class GridBase {
   virtual void mg_solve(const double* b_dev, double* x_dev, double tol, int max_cycles, int forced,
                         nfvm_step_stats* st, nfvm_status* status) = 0;
   virtual void get_fields(nfvm_fields* out) = 0;
+  virtual void lambda2(double* out) = 0;
   virtual void set_fields(const nfvm_fields* in) = 0;
   virtual void set_option(int opt, double v) = 0;
   bool use_graphs = true;

@@ -24,7 +24,7 @@ _dp = C.POINTER(C.c_double)
 EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_step_batch", "nfvm_mg_solve",
     "nfvm_mg_solve_device",
-    "nfvm_get_fields", "nfvm_set_fields", "nfvm_grid_footprint", "nfvm_free_grid",
+    "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_grid_footprint", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
     "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_set_option", "nfvm_tuning_table",
     "nfvm_last_error",
@@ -90,6 +90,7 @@ def lib():
         L.nfvm_mg_solve_device.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                            C.c_int32, C.c_int32, C.POINTER(nfvm_step_stats)]
         L.nfvm_get_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
+        L.nfvm_lambda2.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.nfvm_set_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
         L.nfvm_grid_footprint.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(C.c_size_t)]
         L.nfvm_free_grid.argtypes = [C.c_void_p]
@@ -225,6 +226,13 @@ def nfvm_mg_solve_device(grid, b_ptr: int, x_ptr: int, tol: float = 1e-10, max_c
     return st.as_dict(), s
 
 
+def nfvm_lambda2(grid, shape) -> np.ndarray:
+    """The lambda2 vortex criterion of the grid's current velocity, [nz][ny][nx]."""
+    out = np.zeros(shape)
+    _check(lib().nfvm_lambda2(grid, out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
 def nfvm_get_fields(grid, shape) -> Dict[str, np.ndarray]:
     out = {n: np.zeros(shape) for n in FIELD_ORDER}
     _check(lib().nfvm_get_fields(grid, C.byref(_fields_struct(out))))
@@ -333,6 +341,9 @@ class Grid:
 
     def fields(self):
         return nfvm_get_fields(self.h, self.shape)
+
+    def lambda2(self):
+        return nfvm_lambda2(self.h, self.shape)
 
     def set_fields(self, f):
         nfvm_set_fields(self.h, f)

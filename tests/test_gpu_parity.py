@@ -355,6 +355,40 @@ def test_heun_stage_in_a_batch_and_errors(nf):
     g.close()
 
 
+@pytest.mark.parametrize("name,case", _nearest_cases(), ids=[c[0] for c in _nearest_cases()])
+def test_lambda2_matches_oracle(nf, oracle, name, case):
+    """nfvm_lambda2 after two steps matches the oracle's lambda2 of the
+    GPU's own velocity field to 1e-12 (FP64 velocity: FP64 and mixed grids)
+    or 1e-5 (FP32 grid) of the largest |grad u|^2, the scale of S^2 and W^2
+    (in shear flow lambda2 is their near-cancelling sum, so rounding is
+    measured against the terms, not the result); non-fluid cells hold 0.  A
+    rotating field gives the oracle's value, -Omega^2 in the interior."""
+    m = fluid(case)
+    for prec, tol in ((C.PREC_FP64, 1e-12), (C.PREC_MIXED, 1e-12), (C.PREC_FP32, 1e-5)):
+        g = nf.Grid(case.copy(precision=prec))
+        g.step(2, allow=(0, nf.NFVM_E_NOTCONV))
+        f = g.fields()
+        l2 = g.lambda2()
+        g.close()
+        ref = oracle.lambda2(case, f["u"], f["v"], f["w"])
+        scale = (oracle.velocity_gradient(case, f["u"], f["v"], f["w"]) ** 2).sum((-2, -1)).max()
+        err = np.abs(l2 - ref)[m].max() / scale
+        print(f"[lambda2] {name} prec={prec} max|ref|={scale:.3e} err={err:.2e}", flush=True)
+        assert err <= tol and not l2[~m].any()
+    if case.dim == 3:
+        from tests.boxcase import centres
+        x, y, z = centres(case)
+        rot = case.copy(precision=C.PREC_FP64)
+        rot.fields["u"] = -2.0 * (y - y.mean()) * m
+        rot.fields["v"] = 2.0 * (x - x.mean()) * m
+        rot.fields["w"] = np.zeros_like(x)
+        g = nf.Grid(rot)
+        l2 = g.lambda2()
+        g.close()
+        ref = oracle.lambda2(rot, rot.fields["u"], rot.fields["v"], rot.fields["w"])
+        assert np.abs(l2 - ref)[m].max() <= 1e-12 * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("prec", [C.PREC_FP64, C.PREC_MIXED], ids=["fp64", "mixed"])
 def test_fluid_at_rest_stays_at_rest(nf, prec):
     """Degenerate input: a closed box of fluid at rest.  The Poisson
