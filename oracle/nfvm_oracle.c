@@ -860,6 +860,9 @@ static void vcycle(const orc_mg* mg, int li, double* x, const double* b) {
 
 void orc_mg_vcycle(const orc_mg* mg, double* x, const double* b) { vcycle(mg, 0, x, b); }
 
+/* Smallest (p, A p) / (z, A z) kept before the direction restarts. */
+#define CG_RESTART 1e-12
+
 static double dot_active(const orc_level* l, const double* a, const double* b) {
   int N = lcells(l);
   double s = 0.0;
@@ -875,7 +878,9 @@ static double dot_active(const orc_level* l, const double* a, const double* b) {
  * iteration (Polak-Ribiere form), stopped when ||r|| <= tol ||b|| or after
  * forced_cycles preconditioner applications when forced_cycles >= 0:
  *   z = V(r);  beta = (z, r - r_prev) / (z_prev, r_prev) = -alpha_prev (z, q_prev) / (z_prev, r_prev)
- *   p = z + beta p;  q = A p;  alpha = (z, r) / (p, q);  x += alpha p;  r -= alpha q. */
+ *   p = z + beta p;  q = A p;  alpha = (z, r) / (p, q);  x += alpha p;  r -= alpha q.
+ * At a breakdown ((p, q) a vanishing fraction of (z, A z)) the direction
+ * restarts as p = z, and a zero (p, q) (z = 0) takes no step. */
 int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int max_cycles,
                  int forced, int* cycles, double* relres) {
   const orc_level* l = &mg->lv[0];
@@ -890,7 +895,7 @@ int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int m
   orc_mg_apply(mg, 0, x, r);
   for (int P = 0; P < N; ++P) r[P] = l->act[P] ? b[P] - r[P] : 0.0;
   int status = ORC_OK, cyc = 0;
-  double rel = 0.0, zr_prev = 0.0, alpha_prev = 0.0;
+  double rel = 0.0, zr_prev = 0.0, alpha_prev = 0.0, pq_prev = 0.0;
   for (;;) {
     double rn = sqrt(dot_active(l, r, r));
     rel = bn > 0.0 ? rn / bn : 0.0;
@@ -904,20 +909,34 @@ int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int m
     memset(z, 0, sizeof(double) * N);
     vcycle(mg, 0, z, r);
     double zr = dot_active(l, z, r);
+    double pq;
     if (cyc == 0) {
       memcpy(pv, z, sizeof(double) * N);
+      orc_mg_apply(mg, 0, pv, q);
+      pq = dot_active(l, pv, q);
     } else {
       double beta = -alpha_prev * dot_active(l, z, q) / zr_prev;
       for (int P = 0; P < N; ++P) pv[P] = z[P] + beta * pv[P];
+      orc_mg_apply(mg, 0, pv, q);
+      pq = dot_active(l, pv, q);
+      /* Breakdown: p A-orthogonal to p_prev gives (z, A z) = (p, A p) +
+       * beta^2 (p_prev, A p_prev); when (p, A p) is a vanishing part of it,
+       * z and p_prev are A-parallel and the direction restarts from z. */
+      if (!(pq > CG_RESTART * (pq + beta * beta * pq_prev))) {
+        memcpy(pv, z, sizeof(double) * N);
+        orc_mg_apply(mg, 0, pv, q);
+        pq = dot_active(l, pv, q);
+      }
     }
-    orc_mg_apply(mg, 0, pv, q);
-    double alpha = zr / dot_active(l, pv, q);
+    /* z = 0 (an exactly solved system): no step */
+    double alpha = pq > 0.0 ? zr / pq : 0.0;
     for (int P = 0; P < N; ++P) {
       x[P] += alpha * pv[P];
       r[P] -= alpha * q[P];
     }
     zr_prev = zr;
     alpha_prev = alpha;
+    pq_prev = pq;
     ++cyc;
   }
   free(r); free(z); free(pv); free(q);

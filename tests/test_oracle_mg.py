@@ -270,3 +270,20 @@ def test_solve_from_any_initial_guess(oracle):
     assert cyc2 == 0 and np.array_equal(again, cold)
     z, cyc3, rel3, st3 = mg.solve(np.zeros_like(b), x0, tol=1e-10, max_cycles=200)
     assert st3 == 0 and cyc3 == 0 and not z.any()
+
+
+def test_exact_first_cycle_then_breakdown_takes_no_step(oracle):
+    """Closed form: a single cell with one zero-value face (A = 2/h^2 = 2 at
+    h = 1) and a one-level hierarchy (the coarsest dense inverse, exact in
+    binary) solves A x = 1 in one preconditioned iteration: x = 1/2 and r = 0
+    exactly.  Forced further iterations then meet z = 0, where (p, A p) = 0
+    and the plain step length would be 0/0; the restart takes no step, so x
+    stays 1/2 exactly (a missing guard turns x into NaN)."""
+    c = box((1, 1, 1), (1.0, 1.0, 1.0), dim=2, kinds=[C.OUTLET, C.WALL, C.WALL, C.WALL])
+    mg = oracle.MG(c)
+    b = np.ones((1, 1, 1))
+    assert mg.apply(0, np.ones((1, 1, 1)))[0, 0, 0] == 2.0
+    x, cyc, rel, st = mg.solve(b, forced=4)
+    assert cyc == 4 and st == 0
+    assert x[0, 0, 0] == 0.5 and rel == 0.0
+
