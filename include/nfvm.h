@@ -171,7 +171,10 @@ nfvm_status nfvm_mg_solve_device(nfvm_grid_t grid, const double* b_dev, double* 
                                  double tol, int32_t max_cycles, int32_t forced_cycles,
                                  nfvm_step_stats* stats);
 
-/* Copy the fields to / from host FP64 arrays (all seven pointers required). */
+/* Copy the cell-centred fields u, v, w, p, T, k, omega (the tensors of
+ * Sec. 2.2, one value per cell) to host FP64 arrays, [nz][ny][nx] (all seven
+ * pointers required; waits for the grid's stream).  Errors: NFVM_E_INVAL for
+ * a null pointer. */
 nfvm_status nfvm_get_fields(nfvm_grid_t grid, nfvm_fields* out);
 
 /* Vortex criterion of Sec. 3.2 (lambda2 of Jeong and Hussain) for the
@@ -184,11 +187,29 @@ nfvm_status nfvm_get_fields(nfvm_grid_t grid, nfvm_fields* out);
  * the grid's stream).  Computed on the device in the velocity's precision.
  * Errors: NFVM_E_INVAL for a null argument. */
 nfvm_status nfvm_lambda2(nfvm_grid_t grid, double* lambda2);
+
+/* Replace the grid's fields (Sec. 2.2 tensors) from host FP64 arrays,
+ * [nz][ny][nx], all seven required; values in solid cells are kept as given
+ * and never updated; omega in wall-adjacent cells is reset to the wall value
+ * (Sec. 2.7); the pressure solve's initial guess is cleared.  Errors:
+ * NFVM_E_INVAL for a null pointer. */
 nfvm_status nfvm_set_fields(nfvm_grid_t grid, const nfvm_fields* in);
 
 /* Bytes of device memory a grid with this descriptor allocates. */
 nfvm_status nfvm_grid_footprint(const nfvm_grid_desc* desc, size_t* bytes);
 
+/* Host-side check of the reduction scratch (no device work): *needed is the
+ * largest number of workgroups any reducing level-0 kernel launches for this
+ * descriptor under any tile choice the autotuner can make (each workgroup
+ * stores up to three FP64 partials); *capacity is how many workgroups the
+ * grid's partial buffer holds.  Every reducing launch also checks this
+ * itself and fails with NFVM_E_DEVICE instead of writing past the buffer.
+ * Errors: NFVM_E_INVAL (descriptor or null pointer). */
+nfvm_status nfvm_reduction_blocks(const nfvm_grid_desc* desc, int32_t* needed,
+                                  int32_t* capacity);
+
+/* Release the grid's device memory, stream (if the library created it) and
+ * graphs; waits for the grid's pending work.  The handle is invalid after. */
 nfvm_status nfvm_free_grid(nfvm_grid_t grid);
 
 /* Serving: at most max_slots solves run at once; queued solves are admitted

@@ -223,6 +223,18 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
   return NFVM_OK;
 }
 
+nfvm_status nfvm_reduction_blocks(const nfvm_grid_desc* desc, int32_t* needed,
+                                  int32_t* capacity) {
+  if (!desc || !needed || !capacity) return fail(NFVM_E_INVAL, "desc, needed and capacity are required");
+  return guard([&] {
+    int n = 0, c = 0;
+    reduction_blocks(*desc, &n, &c);
+    *needed = n;
+    *capacity = c;
+    return NFVM_OK;
+  });
+}
+
 nfvm_status nfvm_set_option(nfvm_grid_t grid, int32_t option, double value) {
   if (!grid) return fail(NFVM_E_INVAL, "grid is NULL");
   return guard([&] {

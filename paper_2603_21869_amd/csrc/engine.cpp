@@ -84,8 +84,38 @@ static void sizes_of(int prec, size_t& V, size_t& F, size_t& P, size_t& O, size_
   else { V = 8; F = 4; P = 8; O = 8; S0 = 4; SC = 2; }
 }
 
+// Blocks of the largest launch of any reducing kernel on a level-0 grid:
+// make_tiles covers at most ceil(nx / 64) x ceil(ny / 4) columns (fewer for
+// the four-cells-per-thread kernels) times nz planes and rounds the block
+// count up to a multiple of 8, and every block, padding ones included,
+// stores its partial.
 static int max_blocks_of(const Geom& g) {
-  return ((g.nx + 63) / 64) * ((g.ny + 3) / 4) * g.nz;
+  const long long t = (long long)((g.nx + 63) / 64) * ((g.ny + 3) / 4) * g.nz;
+  return (int)((t + 7) / 8 * 8);
+}
+
+// Tile targets (blocks per launch) the autotuner times for each kernel.
+static const int TILE_CANDIDATES[] = {512, 2048, 8192, 1 << 30};
+static constexpr int N_TILE_CANDIDATES = 4;
+
+void reduction_blocks(const nfvm_grid_desc& d, int* needed, int* capacity) {
+  validate_desc(d);
+  const Geom g = level_geom(d, 0);
+  int need = 0;
+  for (int ci = 0; ci <= N_TILE_CANDIDATES; ++ci) {
+    const int t = ci < N_TILE_CANDIDATES ? TILE_CANDIDATES[ci] : TILE_DEFAULT;
+    // cell tiles (physics kernels, one-cell CG passes) and four-cell tiles
+    need = std::max(need, make_tiles(g.nx, g.ny, g.nz, t).grid);
+    if (g.nx % 4 == 0) need = std::max(need, make_tiles(g.nx / 4, g.ny, g.nz, t).grid);
+  }
+  *needed = need;
+  *capacity = max_blocks_of(g);
+}
+
+void fail_partials(int nblocks, int nv, int max_blocks) {
+  throw Error{NFVM_E_DEVICE, "reduction of " + std::to_string(nblocks) + " blocks x " +
+                                 std::to_string(nv) + " values exceeds the partial buffer (" +
+                                 std::to_string(max_blocks) + " blocks)"};
 }
 
 size_t footprint_bytes(const nfvm_grid_desc& d) {
@@ -104,7 +134,7 @@ size_t footprint_bytes(const nfvm_grid_desc& d) {
     b += l == 0 ? (size_t)gl.total * 2 : (size_t)gl.total;  // face codes / full flags
   }
   b += 160 * 1024;                                  // bottom solver's LDS image
-  b += (size_t)max_blocks_of(g) * 3 * 8 + 4096;     // reduction partials
+  b += (size_t)max_blocks_of(g) * RED_MAX_NV * 8 + 4096;  // reduction partials
   b += (size_t)2 * COARSE_MAX * COARSE_MAX * 8 + COARSE_MAX * 4;  // dense coarse inverse
   b += MAX_PATCHES * sizeof(DevPatch) + 5 * 4 * MAX_PATCHES;
   return b;
@@ -387,7 +417,7 @@ class GridT : public GridBase {
     q = alloc<O>(g.total);
     x0 = alloc<O>(g.total);
     red.max_blocks = max_blocks_of(g);
-    red.partial = alloc<double>((size_t)red.max_blocks * 3);
+    red.partial = alloc<double>((size_t)red.max_blocks * RED_MAX_NV);
     red.counter = alloc<unsigned>(16);
     red.out = alloc<double>(S_COUNT);
     {
@@ -433,14 +463,15 @@ class GridT : public GridBase {
 
   template <class Fn>
   int tune_one(int kid, const Geom& gg, Fn&& launch) {
-    const int cand[] = {512, 2048, 8192, 1 << 30};
+    const int* cand = TILE_CANDIDATES;
     TuneKey key{kid, gg.nx, gg.ny, gg.nz, desc.dim, desc.precision};
     int cached;
     if (tune_lookup(key, &cached)) return cached;
     if (tune_cached_only) return TILE_DEFAULT;
     int best = TILE_DEFAULT;
     float bt = 1e30f;
-    for (int c : cand) {
+    for (int ci = 0; ci < N_TILE_CANDIDATES; ++ci) {
+      const int c = cand[ci];
       const float t = time_it([&] { launch(c); });
       if (t < bt) {
         bt = t;
@@ -541,6 +572,8 @@ class GridT : public GridBase {
       NFVM_CK(hipMemsetAsync(lv[l].b, 0, es, stream));
     }
     NFVM_CK(hipMemsetAsync(red.out, 0, S_COUNT * sizeof(double), stream));
+    NFVM_CK(hipMemsetAsync(red.partial, 0, (size_t)red.max_blocks * RED_MAX_NV * sizeof(double),
+                           stream));
     NFVM_CK(hipStreamSynchronize(stream));
   }
 
@@ -792,7 +825,14 @@ class GridT : public GridBase {
     hipGraph_t gr = nullptr;
     NFVM_CK(hipStreamSynchronize(stream));  // capture starts on an idle stream
     NFVM_CK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-    fn();
+    try {
+      fn();
+    } catch (...) {
+      // leave the stream out of capture mode before the error goes up
+      (void)hipStreamEndCapture(stream, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      throw;
+    }
     NFVM_CK(hipStreamEndCapture(stream, &gr));
     hipGraphExec_t ex = nullptr;
     NFVM_CK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));

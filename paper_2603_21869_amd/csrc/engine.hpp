@@ -57,6 +57,9 @@ struct DevBuf {
 };
 
 size_t footprint_bytes(const nfvm_grid_desc& d);
+// Largest block count of a reducing level-0 launch over every tile target
+// the autotuner may pick, and the block capacity of the grid's partials.
+void reduction_blocks(const nfvm_grid_desc& d, int* needed, int* capacity);
 
 // autotuner results, per kernel, level shape, dimension and precision
 struct TuneKey {

@@ -1322,6 +1322,7 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                       bool have_x0, double tol, int max_cycles, int forced, hipStream_t s,
                       bool fin, void* z0, double wj) {
   const Tiles T = lvl_tiles(l0, TK_START);
+  check_partials(red, T.grid, 2);
   hipLaunchKernelGGL((k_fcg_start<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, b, x0,
                      r, (have_x0 && x0 == x) ? nullptr : x, (S*)l0.b, (S*)z0, (S)wj,
                      have_x0 ? 1 : 0, red);
@@ -1443,6 +1444,9 @@ __host__ inline bool cg_quad(const Level& l0) { return l0.code && l0.g.nx % 4 ==
 
 constexpr int FIN_NV3 = 3;
 
+// Smallest (p, A p) / (z, A z) kept before the CG direction restarts.
+constexpr double CG_RESTART = 1e-12;
+
 // Arguments of the one-workgroup finalising kernels (one workgroup per grid
 // in a batched launch).
 struct FinArgs {
@@ -1460,14 +1464,21 @@ __device__ __forceinline__ void fin_apply_body(const FinArgs& f) {
     const double zr = acc[0], zq = acc[1], zw = acc[2];
     const bool first = red.out[S_ITER] == 0.0;
     const double pq_prev = red.out[S_PQ];
-    const double beta = first ? 0.0 : -zq / pq_prev;
-    const double pq = first ? zw : zw + 2.0 * beta * zq + beta * beta * pq_prev;
+    double beta = first ? 0.0 : -zq / pq_prev;
+    double pq = first ? zw : zw + 2.0 * beta * zq + beta * beta * pq_prev;
+    // (p, A p) = (z, A z) sin^2 of the A-angle between z and p_prev: when the
+    // two are (nearly) A-parallel it cancels to rounding noise, so the
+    // direction restarts from z (beta = 0); z = 0 takes no step
+    if (!first && !(pq > CG_RESTART * zw)) {
+      beta = 0.0;
+      pq = zw;
+    }
     red.out[S_ZR] = zr;
     red.out[S_ZQ] = zq;
     red.out[S_ZW] = zw;
     red.out[S_BETA] = beta;
     red.out[S_PQ] = pq;
-    red.out[S_ALPHA] = zr / pq;
+    red.out[S_ALPHA] = pq > 0.0 ? zr / pq : 0.0;
   }
 }
 __global__ __launch_bounds__(FIN) void k_fin_apply(FinArgs f) { fin_apply_body(f); }
@@ -1486,6 +1497,7 @@ template <class O, class S>
 void launch_fcg_apply(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
                       bool fin) {
   const ApplyArgs<O, S> a = apply_args<O, S>(l0, r, q, red);
+  check_partials(red, a.T.grid, 3);
   if (cg_quad(l0))
     NFVM_LAUNCH((k_fcg_apply4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   else
@@ -1669,6 +1681,7 @@ template <class O, class S>
 void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const RedBuf& red, hipStream_t s,
                        bool fin, void* z0, double wj) {
   const UpdateArgs<O, S> a = update_args<O, S>(l0, x, r, p, q, red, z0, wj);
+  check_partials(red, a.T.grid, 1);
   if (cg_quad(l0))
     NFVM_LAUNCH((k_fcg_update4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   else
@@ -2398,6 +2411,7 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
   for (int i = 0; i < n; ++i) {
     MgGridDesc& d = G[i];
     const auto a = apply_args<O, S0>(d.lv[0], (const O*)d.r, (const O*)d.q, d.red);
+    check_partials(d.red, a.T.grid, 3);
     ap[cg_quad(d.lv[0])].push_back(a);
     fa.push_back(FinArgs{d.red, a.T.grid});
   }
@@ -2405,6 +2419,7 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
     MgGridDesc& d = G[i];
     const auto a = update_args<O, S0>(d.lv[0], (O*)d.x, (O*)d.r, (O*)d.p, (O*)d.q, d.red,
                                       d.zero[0], d.wj);
+    check_partials(d.red, a.T.grid, 1);
     up[cg_quad(d.lv[0])].push_back(a);
     fu.push_back(FinArgs{d.red, a.T.grid});
   }

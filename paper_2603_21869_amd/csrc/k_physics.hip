@@ -154,6 +154,7 @@ void launch_destroy(const Geom& g, const Phys& ph, const uint8_t* type, const De
                     F* k_out, F* om_out, F* nut_out, const RedBuf* red, int tt, hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
   if (red) {
+    check_partials(*red, T.grid, 2);
     NFVM_LAUNCH((k_destroy<V, F, true>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt,
                        u, v, w, k, om, (V)tau, k_out, om_out, nut_out, *red, T);
     launch_finalize(2, R_MIN, *red, T.grid, S_MINK, S_MINW, s);
@@ -512,6 +513,7 @@ void launch_rhs_b(const Geom& g, const Phys& ph, const uint8_t* type, const DevP
                   const F* u, const F* v, const F* w, O* b, const RedBuf& red, int tt,
                   hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
+  check_partials(red, T.grid, 1);
   NFVM_LAUNCH((k_rhs_b<F, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, u, v, w,
                      b, red, T);
   launch_finalize(1, R_SUM, red, T.grid, S_BB, S_BB, s);
@@ -607,6 +609,7 @@ void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const De
                     O* phi, const F* u, const F* v, const F* w, F* uo, F* vo, F* wo, P* p,
                     const RedBuf& red, int tt, hipStream_t s) {
   const Tiles T = cell_tiles(g, tt);
+  check_partials(red, T.grid, 1);
   NFVM_LAUNCH((k_project<F, P, O>), dim3(T.grid), dim3(BX, BY), 0, s, g, ph, type, pt, phi,
                      u, v, w, uo, vo, wo, p, red, T);
   launch_finalize(1, R_MAX, red, T.grid, S_DIV, S_DIV, s);

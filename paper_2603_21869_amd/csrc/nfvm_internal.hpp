@@ -149,7 +149,7 @@ struct RedBuf {
   double* partial;
   unsigned* counter;
   double* out;
-  int max_blocks;
+  int max_blocks;  // partial holds max_blocks * RED_MAX_NV values
   // host-coherent copy of the scalars the host reads (stopping state,
   // norms, step statistics), written by the finalising kernels; may be null
   double* mirror;
@@ -175,6 +175,17 @@ enum {
   S_BETA = 15,     // direction coefficient of the current iteration
   S_COUNT = 16
 };
+
+// Most values one block of a reducing kernel stores in red.partial.
+constexpr int RED_MAX_NV = 3;
+
+// Host-side check before a reducing launch: nblocks blocks storing nv
+// partials each must fit red.partial (throws the library's error otherwise;
+// defined in engine.cpp).
+[[noreturn]] void fail_partials(int nblocks, int nv, int max_blocks);
+inline void check_partials(const RedBuf& red, int nblocks, int nv) {
+  if (nv > RED_MAX_NV || nblocks > red.max_blocks) fail_partials(nblocks, nv, red.max_blocks);
+}
 
 // ---- launchers (defined in the .hip files) --------------------------------
 // Reduce nblocks partials of nv values (op 0 sum, 1 max, 2 min) into

@@ -24,7 +24,8 @@ _dp = C.POINTER(C.c_double)
 EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_step_batch", "nfvm_mg_solve",
     "nfvm_mg_solve_device",
-    "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_grid_footprint", "nfvm_free_grid",
+    "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_grid_footprint",
+    "nfvm_reduction_blocks", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
     "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_set_option", "nfvm_tuning_table",
     "nfvm_last_error",
@@ -93,6 +94,8 @@ def lib():
         L.nfvm_lambda2.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.nfvm_set_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
         L.nfvm_grid_footprint.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(C.c_size_t)]
+        L.nfvm_reduction_blocks.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(C.c_int32),
+                                            C.POINTER(C.c_int32)]
         L.nfvm_free_grid.argtypes = [C.c_void_p]
         L.nfvm_server_create.argtypes = [C.c_double, C.c_int32, C.POINTER(C.c_void_p)]
         L.nfvm_submit.argtypes = [C.c_void_p, C.POINTER(nfvm_grid_desc), C.POINTER(nfvm_fields),
@@ -248,6 +251,15 @@ def nfvm_grid_footprint(desc: Desc) -> int:
     b = C.c_size_t(0)
     _check(lib().nfvm_grid_footprint(C.byref(desc.d), C.byref(b)))
     return b.value
+
+
+def nfvm_reduction_blocks(desc: Desc):
+    """(needed, capacity): the largest reducing launch in workgroups over
+    every tile choice, and the workgroups the partial buffer holds."""
+    n = C.c_int32(0)
+    c = C.c_int32(0)
+    _check(lib().nfvm_reduction_blocks(C.byref(desc.d), C.byref(n), C.byref(c)))
+    return n.value, c.value
 
 
 def nfvm_free_grid(grid):

@@ -60,3 +60,30 @@ def test_missing_library_fails_loudly():
             "sys.exit(1)\n") % ROOT
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0 and "raised" in r.stdout, r.stdout + r.stderr
+
+
+def test_reduction_scratch_covers_every_tiling_of_odd_shapes():
+    """The partial buffer of the device reductions holds the largest launch
+    any tile choice can make: tile counts are rounded up to a multiple of 8
+    workgroups, every one of which stores its partial, so shapes whose column
+    and plane counts multiply to a non-multiple of 8 need the rounded count
+    (host code, no device work)."""
+    from paper_2603_21869_amd import cases as C, nfvm
+    if not os.path.exists(nfvm.LIB_PATH):
+        pytest.skip("libnfvm.so not built")
+    shapes2 = [(90, 18), (64, 2), (66, 6), (130, 34), (8, 8), (256, 64), (4, 4)]
+    shapes3 = [(64, 32, 32), (96, 32, 32), (66, 6, 3), (130, 10, 7), (200, 12, 5), (8, 8, 1),
+               (1024, 512, 256)]
+    seen_round = False
+    for nx, ny in shapes2:
+        c = C.channel2d(nx, ny, n_levels=1, n_steps=1)
+        need, cap = nfvm.nfvm_reduction_blocks(nfvm.Desc(c))
+        assert 0 < need <= cap, (nx, ny, need, cap)
+        cols = -(-nx // 64) * -(-ny // 4)
+        seen_round |= need > cols
+    for nx, ny, nz in shapes3:
+        c = C.channel3d(nx, ny, nz, n_levels=1, n_steps=1)
+        need, cap = nfvm.nfvm_reduction_blocks(nfvm.Desc(c))
+        assert 0 < need <= cap, (nx, ny, nz, need, cap)
+        assert need % 8 == 0 and cap % 8 == 0
+    assert seen_round  # some 2D shape needs more workgroups than it has columns

@@ -91,6 +91,26 @@ def test_step_matches_oracle(nf, oracle, name, case, prec):
     g.close()
 
 
+def test_exactly_solved_system_takes_no_further_step(nf, oracle):
+    """A single cell with one zero-value face (A = 2 at h = 1) and a
+    one-level hierarchy: the first preconditioned iteration solves A x = 1
+    exactly (x = 1/2, r = 0); further forced iterations meet z = 0 and
+    (p, A p) = 0, where the step length would be 0/0.  Every precision keeps
+    x = 1/2 exactly, as the oracle does."""
+    from tests.boxcase import box
+    case = box((1, 1, 1), (1.0, 1.0, 1.0), dim=2, kinds=[C.OUTLET, C.WALL, C.WALL, C.WALL])
+    b = np.ones((1, 1, 1))
+    xr, cyc, rel, st = oracle.MG(case).solve(b, forced=4)
+    assert xr[0, 0, 0] == 0.5
+    for prec in (nf.NFVM_FP64, nf.NFVM_FP32, nf.NFVM_MIXED):
+        g = nf.Grid(case, precision=prec)
+        x, stt, s = g.mg_solve(b, forced_cycles=4)
+        g.close()
+        print(f"   prec={prec} x={x.ravel()} cycles={stt['cycles']} rel={stt['rel_residual']}",
+              flush=True)
+        assert s == 0 and stt["cycles"] == 4 and x[0, 0, 0] == 0.5
+
+
 def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
     """The 3D heated channel at its full size (256 x 64 x 64, 7 levels, tol
     1e-8) in the launch configuration the benchmark times: one step, every
