@@ -248,11 +248,13 @@ nfvm_status nfvm_server_destroy(nfvm_server_t server);
 
 /* Kernel timing.  nfvm_profile(grid, mask) times every later launch of the
  * kernels whose bit (1 << id) is set with HIP events on the grid's stream and
- * resets the totals (mask 0: off).  nfvm_profile_read returns, per kernel,
- * the number of timed launches, their summed device time and the
- * algorithmic bytes one launch moves (the minimum traffic of its operands:
- * each input read once, each output written once, at the storage precision;
- * on level 0 of the multigrid hierarchy). */
+ * resets the totals (mask 0: off); every kernel of a time step belongs to one
+ * id.  nfvm_profile_read returns, per id, the number of timed launches, their
+ * summed device time and the mean algorithmic bytes of one launch (the
+ * minimum traffic of its operands: each input read once, each output written
+ * once, at the storage precision; 0 for the finalisers, whose few KB of
+ * partials are latency, not bandwidth).  Ids 10 to 12 gather the per-level
+ * kernels of every coarse level, so their bytes vary from launch to launch. */
 enum {
   NFVM_K_SMOOTH0 = 0,      /* damped-Jacobi sweep on level 0 */
   NFVM_K_SMOOTH0_ZERO = 1, /* first sweep from a zero iterate */
@@ -264,7 +266,13 @@ enum {
   NFVM_K_PROJECT = 7,      /* projection */
   NFVM_K_FCG_APPLY = 8,    /* w = A z and (z, r), (z, q), (z, w) */
   NFVM_K_FCG_UPDATE = 9,   /* p, q, x, r update and ||r|| */
-  NFVM_K_COUNT = 10
+  NFVM_K_SMOOTH_C = 10,    /* damped-Jacobi sweeps on the coarse levels */
+  NFVM_K_RESTRICT_C = 11,  /* residual + restriction between coarse levels */
+  NFVM_K_PROLONG_C = 12,   /* prolongation + correction between coarse levels */
+  NFVM_K_BOTTOM = 13,      /* LDS bottom solver, or the coarsest dense solve */
+  NFVM_K_FCG_START = 14,   /* r = b - A x0, ||b||, ||r|| and level 0's first sweep */
+  NFVM_K_FINALIZE = 15,    /* one-workgroup finalisers of the reductions */
+  NFVM_K_COUNT = 16
 };
 nfvm_status nfvm_profile(nfvm_grid_t grid, uint32_t kernel_mask);
 nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launches,

@@ -61,7 +61,9 @@ nfvm_status nfvm_step(nfvm_grid_t grid, int32_t n_steps, nfvm_step_stats* stats)
   return guard([&] {
     nfvm_status st = NFVM_OK;
     grid->g->step(n_steps, stats, &st);
-    if (st == NFVM_E_DIVERGED) set_error("non-finite residual or field");
+    if (st == NFVM_E_DIVERGED)
+      set_error("non-finite residual or field" +
+                (grid->g->last_diag.empty() ? std::string() : "; " + grid->g->last_diag));
     if (st == NFVM_E_NOTCONV) set_error("pressure solve reached max_cycles");
     return st;
   });
@@ -219,7 +221,10 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
     return fail(NFVM_E_INVAL, "bad grid or kernel id");
   if (launches) *launches = grid->g->prof_launches[kernel];
   if (seconds) *seconds = grid->g->prof_seconds[kernel];
-  if (bytes_per_launch) *bytes_per_launch = grid->g->prof_bytes[kernel];
+  if (bytes_per_launch) {
+    const long long n = grid->g->prof_launches[kernel];
+    *bytes_per_launch = n ? grid->g->prof_bytes_sum[kernel] / (double)n : grid->g->prof_bytes[kernel];
+  }
   return NFVM_OK;
 }
 

@@ -5,6 +5,7 @@
 #include "post.hpp"
 
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -175,20 +176,36 @@ hipEvent_t GridBase::next_event() {
 thread_local LaunchEvents t_launch_ev;
 
 // The main kernel launched between prof_begin and prof_end records the pair
-// of events at its own start and end.
-void GridBase::prof_begin(int kid) {
-  if (!(prof_mask & (1u << kid))) return;
-  ProfRec r{kid, next_event(), next_event()};
-  t_launch_ev = LaunchEvents{r.a, r.b};
-  prof_pending.push_back(r);
+// of events at its own start and end, and its finaliser (if any) a pair of
+// its own.
+void GridBase::prof_begin(int kid, double bytes) {
+  LaunchEvents e{};
+  if (prof_mask & (1u << kid)) {
+    ProfRec r{kid, next_event(), next_event(), bytes < 0 ? prof_bytes[kid] : bytes};
+    e.start = r.a;
+    e.stop = r.b;
+    prof_pending.push_back(r);
+  }
+  if (prof_mask & (1u << NFVM_K_FINALIZE)) {
+    ProfRec r{NFVM_K_FINALIZE, next_event(), next_event(), 0.0};
+    e.fstart = r.a;
+    e.fstop = r.b;
+    prof_pending.push_back(r);
+  }
+  t_launch_ev = e;
 }
 
-void GridBase::prof_end(int kid) {
-  if (!(prof_mask & (1u << kid))) return;
-  if (t_launch_ev.start) {  // nothing was launched: drop the record
-    t_launch_ev = LaunchEvents{};
-    prof_pending.pop_back();
+void GridBase::prof_end(int) {
+  // records of launches that did not happen are dropped
+  for (hipEvent_t unused : {t_launch_ev.start, t_launch_ev.fstart}) {
+    if (!unused) continue;
+    for (size_t i = prof_pending.size(); i-- > 0;)
+      if (prof_pending[i].a == unused) {
+        prof_pending.erase(prof_pending.begin() + i);
+        break;
+      }
   }
+  t_launch_ev = LaunchEvents{};
 }
 
 void GridBase::prof_collect() {
@@ -197,6 +214,7 @@ void GridBase::prof_collect() {
     NFVM_CK(hipEventElapsedTime(&ms, r.a, r.b));
     prof_launches[r.kid] += 1;
     prof_seconds[r.kid] += ms * 1e-3;
+    prof_bytes_sum[r.kid] += r.bytes;
   }
   prof_pending.clear();
   ev_used = 0;
@@ -210,6 +228,7 @@ void GridBase::prof_reset(uint32_t mask) {
   for (int k = 0; k < NFVM_K_COUNT; ++k) {
     prof_launches[k] = 0;
     prof_seconds[k] = 0;
+    prof_bytes_sum[k] = 0;
   }
 }
 
@@ -407,6 +426,7 @@ class GridT : public GridBase {
     if (nc > COARSE_MAX)
       throw Error{NFVM_E_INVAL, "coarsest level has " + std::to_string(nc) +
                                     " fluid cells; at most 512 (add levels)"};
+    n_coarse = nc;
 
     setup_bottom();
 
@@ -418,7 +438,6 @@ class GridT : public GridBase {
     x0 = alloc<O>(g.total);
     red.max_blocks = max_blocks_of(g);
     red.partial = alloc<double>((size_t)red.max_blocks * RED_MAX_NV);
-    red.counter = alloc<unsigned>(16);
     red.out = alloc<double>(S_COUNT);
     {
       double init[S_COUNT] = {};
@@ -641,10 +660,46 @@ class GridT : public GridBase {
       launch_smooth<S0, C>(v, xin, xout, wj, zero, red.out, stream);
       prof_end(kid);
     } else {
+      // x in, b, x out and the class byte (from zero: no x in)
+      const double nc = (double)v.g.cells(), sc = sizeof(SC);
+      prof_begin(NFVM_K_SMOOTH_C, nc * ((zero ? 2 : 3) * sc + 1));
       launch_smooth<SC, C>(v, xin, xout, wj, zero, red.out, stream);
+      prof_end(NFVM_K_SMOOTH_C);
     }
     v.cur = zero ? 0 : (v.cur ^ 1);
   }
+
+  // Algorithmic bytes of the coarse-level transfers between levels l and
+  // l + 1 (the fine side: x, b and class byte read, or x read and written
+  // with the class byte; the coarse side: b and the fused first sweep
+  // written with the class byte, or the correction read with it).
+  double restrict_bytes(int l, bool fused) const {
+    const double nf = (double)lv[l].g.cells(), nc = (double)lv[l + 1].g.cells();
+    const double sc = sizeof(SC);
+    return nf * (2 * sc + 1) + nc * ((fused ? 2 : 1) * sc + 1);
+  }
+  double prolong_bytes(int l) const {
+    const double nf = (double)lv[l].g.cells(), nc = (double)lv[l + 1].g.cells();
+    const double sc = sizeof(SC);
+    return nf * (2 * sc + 1) + nc * (sc + 1);
+  }
+  // the bottom solver: its top level's b read and x written, the constant
+  // LDS image read; the coarsest dense solve: the inverse and its vectors
+  double bottom_bytes_moved() const {
+    const double nt = (double)lv[bottom_top].g.cells(), sc = sizeof(SC);
+    return nt * 2 * sc + (double)(bot.lds_bytes - bot.zero_bytes);
+  }
+  double coarse_bytes_moved() const {
+    const double n = (double)n_coarse, sc = L == 1 ? sizeof(S0) : sizeof(SC);
+    return n * n * 8 + n * (2 * sc + 4);
+  }
+  // CG start: b read, r and x written, the level-0 right-hand side and (fused)
+  // first sweep written, the face code; with an initial guess it is read too
+  double start_bytes(bool have_x0) const {
+    const double N = (double)ncells, so = sizeof(O), s0 = sizeof(S0);
+    return N * ((have_x0 ? 4 : 3) * so + 2 + (zero0() ? 2 : 1) * s0);
+  }
+  int n_coarse = 0;  // active cells of the coarsest level
 
   // levels bottom_top .. L-1 run in one LDS-resident workgroup
   int bottom_top = -1;
@@ -755,15 +810,19 @@ class GridT : public GridBase {
     Level& v = lv[l];
     if (l == bottom_top) {
       v.cur = 0;
+      prof_begin(NFVM_K_BOTTOM, bottom_bytes_moved());
       launch_bottom<SC, C>(bot, v.b, v.x[0], red.out, stream);
+      prof_end(NFVM_K_BOTTOM);
       return;
     }
     if (l == L - 1) {
       v.cur = 0;
+      prof_begin(NFVM_K_BOTTOM, coarse_bytes_moved());
       if (l == 0)
         launch_coarse_solve<S0, C>(v, cmap, ncount, work, COARSE_MAX, red.out, stream);
       else
         launch_coarse_solve<SC, C>(v, cmap, ncount, work, COARSE_MAX, red.out, stream);
+      prof_end(NFVM_K_BOTTOM);
       return;
     }
     if (nu1 > 0) {
@@ -775,24 +834,36 @@ class GridT : public GridBase {
       for (int s = 1; s < nu1; ++s) smooth(l, false);
     } else {
       v.cur = 0;
-      if (l == 0)
+      // (no pre-smoothing: the iterate is zeroed, one store per cell)
+      if (l == 0) {
+        prof_begin(NFVM_K_SMOOTH0_ZERO, (double)v.g.cells() * sizeof(S0));
         launch_fill_zero<S0>(v, v.x[0], red.out, stream);
-      else
+        prof_end(NFVM_K_SMOOTH0_ZERO);
+      } else {
+        prof_begin(NFVM_K_SMOOTH_C, (double)v.g.cells() * sizeof(SC));
         launch_fill_zero<SC>(v, v.x[0], red.out, stream);
+        prof_end(NFVM_K_SMOOTH_C);
+      }
     }
     if (l == 0) {
       prof_begin(NFVM_K_RESTRICT0);
       launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream, zero_of(1), wj);
       prof_end(NFVM_K_RESTRICT0);
-    } else
+    } else {
+      prof_begin(NFVM_K_RESTRICT_C, restrict_bytes(l, zero_of(l + 1) != nullptr));
       launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream, zero_of(l + 1), wj);
+      prof_end(NFVM_K_RESTRICT_C);
+    }
     vcycle(l + 1);
     if (l == 0) {
       prof_begin(NFVM_K_PROLONG0);
       launch_prolong<S0, C, SC>(lv[0], lv[1], red.out, stream);
       prof_end(NFVM_K_PROLONG0);
-    } else
+    } else {
+      prof_begin(NFVM_K_PROLONG_C, prolong_bytes(l));
       launch_prolong<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
+      prof_end(NFVM_K_PROLONG_C);
+    }
     for (int s = 0; s < nu2; ++s) smooth(l, false);
   }
 
@@ -864,9 +935,12 @@ class GridT : public GridBase {
   // Flexible CG preconditioned by one V-cycle; b in bvec, result in phi.
   nfvm_status solve(bool have_x0, double tol_, int maxc, int forced, int* cycles, double* rel,
                     bool started = false) {
-    if (!started)
+    if (!started) {
+      prof_begin(NFVM_K_FCG_START, start_bytes(have_x0));
       launch_fcg_start<O, S0>(lv[0], bvec, x0, r, phi, red, have_x0, tol_, maxc, forced, stream,
                               true, zero0(), wj);
+      prof_end(NFVM_K_FCG_START);
+    }
     int ahead = forced >= 0 ? forced : std::min(predicted, maxc);
     for (int i = 0; i < ahead; ++i) run_iteration();
     NFVM_CK(hipGetLastError());
@@ -881,6 +955,72 @@ class GridT : public GridBase {
       NFVM_CK(hipGetLastError());
     }
     return solve_result(forced, tol_, cycles, rel);
+  }
+
+  // Post-mortem of a solve that ended with a non-finite residual: the
+  // solver's scalars and every device array that holds a non-finite value
+  // (count and first padded index), read back to the host.
+  std::string diagnose() {
+    static const char* SN[S_COUNT] = {"bb", "rr", "zr", "zq", "pq", "zw", "alpha", "div",
+                                      "mink", "minw", "done", "iter", "tol2", "maxit",
+                                      "forced", "beta"};
+    std::string m = "scalars:";
+    double sc[S_COUNT];
+    NFVM_CK(hipMemcpyAsync(sc, red.out, sizeof sc, hipMemcpyDeviceToHost, stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+    char buf[96];
+    for (int i = 0; i < S_COUNT; ++i) {
+      snprintf(buf, sizeof buf, " %s=%.6g", SN[i], sc[i]);
+      m += buf;
+    }
+    std::string bad;
+    std::vector<unsigned char> h;
+    auto scan = [&](const std::string& name, const void* p, size_t n, int es) {
+      if (!p || !n) return;
+      h.resize(n * es);
+      NFVM_CK(hipMemcpyAsync(h.data(), p, n * es, hipMemcpyDeviceToHost, stream));
+      NFVM_CK(hipStreamSynchronize(stream));
+      size_t cnt = 0, first = 0;
+      for (size_t i = 0; i < n; ++i) {
+        bool fin;
+        if (es == 8) {
+          double v;
+          memcpy(&v, &h[i * 8], 8);
+          fin = isfinite(v);
+        } else if (es == 4) {
+          float v;
+          memcpy(&v, &h[i * 4], 4);
+          fin = isfinite(v);
+        } else {
+          uint16_t v;
+          memcpy(&v, &h[i * 2], 2);
+          fin = (v & 0x7F80u) != 0x7F80u;  // bf16: exponent all ones is inf or NaN
+        }
+        if (!fin && cnt++ == 0) first = i;
+      }
+      if (cnt) {
+        snprintf(buf, sizeof buf, " %s[%zu non-finite, first at %zu]", name.c_str(), cnt, first);
+        bad += buf;
+      }
+    };
+    const size_t T = (size_t)g.total;
+    scan("b", bvec, T, sizeof(O));
+    scan("phi", phi, T, sizeof(O));
+    scan("r", r, T, sizeof(O));
+    scan("p", pv, T, sizeof(O));
+    scan("q", q, T, sizeof(O));
+    for (int l = 0; l < L; ++l) {
+      const int es = l == 0 ? (int)sizeof(S0) : (int)sizeof(SC);
+      const size_t n = (size_t)lv[l].g.total;
+      scan("L" + std::to_string(l) + ".x0", lv[l].x[0], n, es);
+      scan("L" + std::to_string(l) + ".x1", lv[l].x[1], n, es);
+      scan("L" + std::to_string(l) + ".b", lv[l].b, n, es);
+    }
+    scan("pressure", p, T, sizeof(P));
+    for (int f = 0; f < 3; ++f) scan("vel" + std::to_string(f), vcur(f), T, sizeof(V));
+    for (int f = 3; f < 6; ++f) scan("scalar" + std::to_string(f), scur(f), T, sizeof(F));
+    scan("nut", nut, T, sizeof(F));
+    return m + (bad.empty() ? " arrays: all finite" : " non-finite arrays:" + bad);
   }
 
   // Outcome of a finished solve from the mirrored scalars.
@@ -902,7 +1042,9 @@ class GridT : public GridBase {
     launch_pack<O>(g, x_dev, x0, 0.0, stream);
     int cyc = 0;
     double rel = 0;
+    last_diag.clear();
     nfvm_status st = solve(true, tol_, maxc, forced, &cyc, &rel);
+    if (st == NFVM_E_DIVERGED) last_diag = diagnose();
     launch_unpack<O>(g, phi, x_dev, 0.0, stream);
     NFVM_CK(hipEventRecord(ev1, stream));
     NFVM_CK(hipStreamSynchronize(stream));
@@ -955,8 +1097,10 @@ class GridT : public GridBase {
                        tp[TP_RHS], stream);
     prof_end(NFVM_K_RHS);
     // initial guess: the previous step's increment (warm start), else zero
+    prof_begin(NFVM_K_FCG_START, start_bytes(use_warm));
     launch_fcg_start<O, S0>(lv[0], bvec, use_warm ? phi : x0, r, phi, red, use_warm, tol,
                             max_cycles, -1, stream, true, zero0(), wj);
+    prof_end(NFVM_K_FCG_START);
   }
 
   // projection, destruction over dt/2 (with the min k / omega reduction)
@@ -1024,6 +1168,7 @@ class GridT : public GridBase {
 
   void run_begin(int n, nfvm_step_stats* stt) override {
     run = Run{};
+    last_diag.clear();
     run.n = n;
     run.stt = stt;
     if (n > 0) run_start_step();
@@ -1081,6 +1226,7 @@ class GridT : public GridBase {
       double rel = 0;
       const nfvm_status st = solve_result(-1, tol, &cyc, &rel);
       if (st == NFVM_E_DIVERGED) {
+        last_diag = "step " + std::to_string(run.s) + ": " + diagnose();
         if (run.stt) {
           memset(&run.stt[run.s], 0, sizeof run.stt[run.s]);
           run.stt[run.s].status = st;

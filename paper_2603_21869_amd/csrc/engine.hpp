@@ -126,6 +126,7 @@ class GridBase {
   struct ProfRec {
     int kid;
     hipEvent_t a, b;
+    double bytes;  // algorithmic bytes of the launch
   };
   uint32_t prof_mask = 0;
   std::vector<hipEvent_t> ev_pool;
@@ -133,15 +134,20 @@ class GridBase {
   std::vector<ProfRec> prof_pending;
   long long prof_launches[NFVM_K_COUNT] = {};
   double prof_seconds[NFVM_K_COUNT] = {};
-  double prof_bytes[NFVM_K_COUNT] = {};
-  int prof_open = -1;
+  double prof_bytes[NFVM_K_COUNT] = {};      // per launch, for the level-0 and physics kernels
+  double prof_bytes_sum[NFVM_K_COUNT] = {};  // summed over the timed launches
   hipEvent_t next_event();
-  void prof_begin(int kid);
+  // time the next kernel launched (and, with NFVM_K_FINALIZE in the mask,
+  // its finaliser) as kernel kid moving `bytes` (< 0: prof_bytes[kid])
+  void prof_begin(int kid, double bytes = -1.0);
   void prof_end(int kid);
   void prof_collect();  // after a stream synchronisation
   void prof_reset(uint32_t mask);
   void prof_release();
 
+  // what the last failed solve left on the device (solver scalars, arrays
+  // holding non-finite values); empty after a good one
+  std::string last_diag;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   long long ncells = 0;

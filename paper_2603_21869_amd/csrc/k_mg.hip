@@ -1189,7 +1189,7 @@ CoarseArgs<SC, C> coarse_args(const Level& c, const int* cmap, const int* ncount
 template <class SC, class C>
 void launch_coarse_solve(const Level& c, const int* cmap, const int* ncount, const double* ainv,
                          int max_n, const double* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_solve<SC, C>), dim3(1), dim3(256), 0, s,
+  NFVM_LAUNCH((k_coarse_solve<SC, C>), dim3(1), dim3(256), 0, s,
                      coarse_args<SC, C>(c, cmap, ncount, ainv, max_n, ctl));
 }
 
@@ -1204,7 +1204,7 @@ __global__ void k_fill_zero(Geom g, S* x, const double* __restrict__ ctl) {
 }
 template <class S>
 void launch_fill_zero(const Level& l, void* x, const double* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_zero<S>, lvl_grid(l.g), dim3(MBX, MBY), 0, s, l.g, (S*)x, ctl);
+  NFVM_LAUNCH(k_fill_zero<S>, lvl_grid(l.g), dim3(MBX, MBY), 0, s, l.g, (S*)x, ctl);
 }
 
 // ---- flexible conjugate gradient on level 0 ---------------------------------------
@@ -1323,11 +1323,11 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                       bool fin, void* z0, double wj) {
   const Tiles T = lvl_tiles(l0, TK_START);
   check_partials(red, T.grid, 2);
-  hipLaunchKernelGGL((k_fcg_start<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, b, x0,
+  NFVM_LAUNCH((k_fcg_start<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, b, x0,
                      r, (have_x0 && x0 == x) ? nullptr : x, (S*)l0.b, (S*)z0, (S)wj,
                      have_x0 ? 1 : 0, red);
   if (fin)
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(FIN), 0, s, red, T.grid, tol * tol,
+    NFVM_LAUNCH_FIN(k_fin_start, dim3(1), dim3(FIN), 0, s, red, T.grid, tol * tol,
                        (double)max_cycles, (double)forced);
 }
 
@@ -1502,7 +1502,7 @@ void launch_fcg_apply(const Level& l0, const O* r, const O* q, const RedBuf& red
     NFVM_LAUNCH((k_fcg_apply4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   else
     NFVM_LAUNCH((k_fcg_apply<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
-  if (fin) hipLaunchKernelGGL(k_fin_apply, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
+  if (fin) NFVM_LAUNCH_FIN(k_fin_apply, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
 
 // p = z + beta p, q = w + beta q, x += alpha p, r -= alpha q, ||r||^2, the
@@ -1686,7 +1686,7 @@ void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const RedBuf& re
     NFVM_LAUNCH((k_fcg_update4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   else
     NFVM_LAUNCH((k_fcg_update<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
-  if (fin) hipLaunchKernelGGL(k_fin_update, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
+  if (fin) NFVM_LAUNCH_FIN(k_fin_update, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
 
 // ---- deterministic finalisation of block partials ---------------------------------
@@ -1708,13 +1708,13 @@ __global__ __launch_bounds__(256) void k_finalize(RedBuf red, int nb, int s0, in
 void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, int slot1,
                      hipStream_t s) {
   if (nv == 1 && op == R_SUM)
-    hipLaunchKernelGGL((k_finalize<1, R_SUM>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    NFVM_LAUNCH_FIN((k_finalize<1, R_SUM>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
   else if (nv == 1 && op == R_MAX)
-    hipLaunchKernelGGL((k_finalize<1, R_MAX>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    NFVM_LAUNCH_FIN((k_finalize<1, R_MAX>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
   else if (nv == 2 && op == R_SUM)
-    hipLaunchKernelGGL((k_finalize<2, R_SUM>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    NFVM_LAUNCH_FIN((k_finalize<2, R_SUM>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
   else
-    hipLaunchKernelGGL((k_finalize<2, R_MIN>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    NFVM_LAUNCH_FIN((k_finalize<2, R_MIN>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
 }
 
 // ---- LDS bottom solver ----------------------------------------------------------------
@@ -2140,7 +2140,7 @@ template size_t bottom_lds_limit<bf16, float>();
 template <class SC, class C>
 void launch_bottom(const Bottom& B, const void* btop, void* xtop, const double* ctl,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_bottom<SC, C>), dim3(1), dim3(1024), B.lds_bytes, s, B, (const SC*)btop,
+  NFVM_LAUNCH((k_bottom<SC, C>), dim3(1), dim3(1024), B.lds_bytes, s, B, (const SC*)btop,
                      (SC*)xtop, ctl);
 }
 template void launch_bottom<double, double>(const Bottom&, const void*, void*, const double*,

@@ -17,7 +17,8 @@ namespace nfvm {
 // the interval is the kernel's own run time, and clears them, so the
 // finalising kernels that follow are not timed.
 struct LaunchEvents {
-  hipEvent_t start = nullptr, stop = nullptr;
+  hipEvent_t start = nullptr, stop = nullptr;    // the main kernel
+  hipEvent_t fstart = nullptr, fstop = nullptr;  // its finaliser (NFVM_LAUNCH_FIN)
 };
 extern thread_local LaunchEvents t_launch_ev;
 
@@ -26,7 +27,19 @@ extern thread_local LaunchEvents t_launch_ev;
     if (::nfvm::t_launch_ev.start) {                                                         \
       hipExtLaunchKernelGGL(K, G, B, SH, S, ::nfvm::t_launch_ev.start,                       \
                             ::nfvm::t_launch_ev.stop, 0, __VA_ARGS__);                       \
-      ::nfvm::t_launch_ev = ::nfvm::LaunchEvents{};                                          \
+      ::nfvm::t_launch_ev.start = ::nfvm::t_launch_ev.stop = nullptr;                        \
+    } else {                                                                                 \
+      hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                       \
+    }                                                                                        \
+  } while (0)
+
+// The same for a finalising kernel (its own pair of events).
+#define NFVM_LAUNCH_FIN(K, G, B, SH, S, ...)                                                 \
+  do {                                                                                       \
+    if (::nfvm::t_launch_ev.fstart) {                                                        \
+      hipExtLaunchKernelGGL(K, G, B, SH, S, ::nfvm::t_launch_ev.fstart,                      \
+                            ::nfvm::t_launch_ev.fstop, 0, __VA_ARGS__);                      \
+      ::nfvm::t_launch_ev.fstart = ::nfvm::t_launch_ev.fstop = nullptr;                      \
     } else {                                                                                 \
       hipLaunchKernelGGL(K, G, B, SH, S, __VA_ARGS__);                                       \
     }                                                                                        \
@@ -143,11 +156,9 @@ constexpr uint32_t FACE_CODE_INACTIVE = 0xFFFFu;
 void launch_face_codes(const Geom& g, const uint8_t* cls, const float* cx, const float* cy,
                        const float* cz, uint16_t* code, hipStream_t s);
 
-// Device-wide reduction scratch: per-block partials, a completion counter and
-// the reduced scalars.
+// Device-wide reduction scratch: per-block partials and the reduced scalars.
 struct RedBuf {
   double* partial;
-  unsigned* counter;
   double* out;
   int max_blocks;  // partial holds max_blocks * RED_MAX_NV values
   // host-coherent copy of the scalars the host reads (stopping state,

@@ -32,7 +32,8 @@ EXPORTS = (
 )
 
 KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "explicit", "destroy", "rhs",
-           "project", "fcg_apply", "fcg_update")
+           "project", "fcg_apply", "fcg_update", "smooth_coarse", "restrict_coarse",
+           "prolong_coarse", "bottom", "fcg_start", "finalize")
 
 
 class nfvm_patch(C.Structure):

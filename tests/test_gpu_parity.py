@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2603_21869_amd import cases as C
-from tests.parity import field_errors, fluid
+from tests.parity import check_fields, field_errors, field_max_errors, fluid
 
 pytestmark = pytest.mark.gpu
 
@@ -77,15 +77,8 @@ def test_step_matches_oracle(nf, oracle, name, case, prec):
     out = g.fields()
     cyc = [x["cycles"] for x in stats]
     ref, rst, status = oracle.step(case, n, forced_cycles=cyc)
-    errs = field_errors(case, out, ref)
-    print("   cycles", cyc, "errors", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    tol = TOL[prec]
-    for f in ("vel", "k", "omega"):
-        assert errs[f] <= tol, (f, errs[f])
-    tol_pT = FP32_FLOOR if prec == C.PREC_FP32 else tol
-    assert errs["p"] <= tol_pT, ("p", errs["p"])
-    if case.physics & C.PHYS_ENERGY:
-        assert errs["T"] <= tol_pT, ("T", errs["T"])
+    floors = {"p": FP32_FLOOR, "T": FP32_FLOOR} if prec == C.PREC_FP32 else None
+    check_fields(case, out, ref, TOL[prec], floors=floors, tag=f"cycles {cyc}")
     for a, b in zip(stats, rst):
         assert abs(a["min_k"] - b["min_k"]) <= 1e-6 * b["min_k"] + 1e-30
     g.close()
@@ -111,6 +104,44 @@ def test_exactly_solved_system_takes_no_further_step(nf, oracle):
         assert s == 0 and stt["cycles"] == 4 and x[0, 0, 0] == 0.5
 
 
+def test_operating_point_batched_mixed_vs_converged_oracle(nf, oracle):
+    """The setting the benchmark times: mixed precision, grids stepped
+    together in batched launches, every pressure solve stopped by its own
+    rule ||r|| <= tol ||b|| (no forced count), against the FP64 oracle solved
+    to 1e-12.  At tol = 1e-6 velocity, k, omega and T are within 1e-6 (L2 and
+    max norm).  The pressure is not, in any precision: a solve stopped at a
+    relative residual of 1e-6 leaves p up to ~3e-5 from the converged one (the
+    oracle's own FP64 solve stopped at the same rule does), so there the mixed
+    p is held to the FP64 solve's stopping error (within 5x of it: the mixed
+    preconditioner stops at a different iterate).  At tol = 1e-9 every field,
+    p included, is within 1e-6 (the BF16 coarse correction leaves more of
+    the residual in smooth modes, which A^-1 amplifies most, so the mixed
+    solve needs a tighter stop than FP64 for the same pressure error: at
+    1e-8 the room's p is still 1.05e-6 away in L2)."""
+    cases = [c.copy(precision=C.PREC_MIXED, n_steps=3) for _, c in small_cases()]
+    conv = [oracle.step(c.copy(precision=C.PREC_FP64, tol=1e-12, max_cycles=400), 3)[0]
+            for c in cases]
+    for tol in (1e-6, 1e-9):
+        gs = [nf.Grid(c.copy(tol=tol)) for c in cases]
+        s, sts, stats = nf.nfvm_step_batch([g.h for g in gs], 3)
+        assert s == nf.NFVM_OK and all(x == nf.NFVM_OK for x in sts)
+        outs = [g.fields() for g in gs]
+        for g in gs:
+            g.close()
+        for c, out, ref, st in zip(cases, outs, conv, stats):
+            tag = f"{c.name} tol={tol} cycles={[x['cycles'] for x in st]}"
+            if tol == 1e-9:
+                check_fields(c, out, ref, 1e-6, tag=tag)
+                continue
+            check_fields(c, out, ref, 1e-6, fields=("vel", "k", "omega", "T"), tag=tag)
+            o64 = oracle.step(c.copy(precision=C.PREC_FP64, tol=tol), 3)[0]
+            l2g, mxg = field_errors(c, out, ref)["p"], field_max_errors(c, out, ref)["p"]
+            l2o, mxo = field_errors(c, o64, ref)["p"], field_max_errors(c, o64, ref)["p"]
+            print(f"   p: mixed L2 {l2g:.2e} max {mxg:.2e}; FP64 at the same rule "
+                  f"L2 {l2o:.2e} max {mxo:.2e}", flush=True)
+            assert l2g <= 5 * l2o + 1e-9 and mxg <= 5 * mxo + 1e-9
+
+
 def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
     """The 3D heated channel at its full size (256 x 64 x 64, 7 levels, tol
     1e-8) in the launch configuration the benchmark times: one step, every
@@ -124,10 +155,7 @@ def test_full_size_channel3d_fp64_and_mixed(nf, oracle):
         out = g.fields()
         g.close()
         ref, rst, st = oracle.step(case, 1, forced_cycles=[stats[0]["cycles"]])
-        errs = field_errors(case, out, ref)
-        print("   cycles", stats[0]["cycles"], {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-        for f in ("vel", "p", "k", "omega", "T"):
-            assert errs[f] <= tol, (prec, f, errs[f])
+        check_fields(case, out, ref, tol, tag=f"prec {prec} cycles {stats[0]['cycles']}")
 
 
 def test_full_size_channel2d_fp64(nf, oracle):
@@ -140,11 +168,7 @@ def test_full_size_channel2d_fp64(nf, oracle):
     out = g.fields()
     g.close()
     ref, _, _ = oracle.step(case, 20, forced_cycles=[x["cycles"] for x in stats])
-    errs = field_errors(case, out, ref)
-    print("   cycles", [x["cycles"] for x in stats], {k: f"{v:.2e}" for k, v in errs.items()},
-          flush=True)
-    for f in ("vel", "p", "k", "omega"):
-        assert errs[f] <= 1e-10, (f, errs[f])
+    check_fields(case, out, ref, 1e-10, tag=f"cycles {[x['cycles'] for x in stats]}")
 
 
 def test_channel2d_diverges_where_the_oracle_does(nf, oracle):
@@ -176,10 +200,7 @@ def test_full_size_open_channel_128_mixed(nf, oracle):
     out = g.fields()
     g.close()
     ref, _, _ = oracle.step(case, 1, forced_cycles=[stats[0]["cycles"]])
-    errs = field_errors(case, out, ref)
-    print("   cycles", stats[0]["cycles"], {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for f in ("vel", "p", "k", "omega", "T"):
-        assert errs[f] <= 1e-6, (f, errs[f])
+    check_fields(case, out, ref, 1e-6, tag=f"cycles {stats[0]['cycles']}")
 
 
 @pytest.mark.parametrize("size", ["room", "bigroom"])
@@ -214,6 +235,43 @@ def test_full_size_room_pressure_solve_mixed(nf, oracle, size):
     g.close()
 
 
+def test_full_size_room_forced_cycles_element_wise(nf, oracle):
+    """The room at full size (512 x 256 x 128, 8 levels), where levels above
+    1M cells take the class-byte load path: two forced preconditioned
+    iterations of the pressure solve, and a time step whose solve is held to
+    two iterations, element by element against the oracle in FP64 (a wrong
+    preconditioner changes these iterates; a converged solve would hide it).
+    The mixed-precision kernels are the same templates on FP32 / BF16
+    storage; their iterates differ from FP64 by the weaker BF16 coarse
+    correction itself (two iterations reach a residual of 0.12 against
+    FP64's 0.08), so the mixed solve at this size is checked by its converged
+    residual (test_full_size_room_pressure_solve_mixed)."""
+    case = C.room3d(precision=C.PREC_FP64, n_steps=1)
+    m = fluid(case)
+    b = np.random.default_rng(11).standard_normal((case.n[2], case.n[1], case.n[0])) * m
+    print("[full] room 512x256x128 forced 2 iterations", flush=True)
+    mg = oracle.MG(case)
+    xr, _, rel_o, _ = mg.solve(b, forced=2)
+    del mg
+    for prec, bar in ((C.PREC_FP64, 1e-12),):
+        g = nf.Grid(case, precision=prec)
+        x, st, s = g.mg_solve(b, forced_cycles=2, allow=(0, nf.NFVM_E_NOTCONV))
+        g.close()
+        err = np.linalg.norm((x - xr)[m]) / np.linalg.norm(xr[m])
+        emax = np.abs(x - xr)[m].max() / np.abs(xr[m]).max()
+        print(f"   prec={prec} rel {st['rel_residual']:.4e} (oracle {rel_o:.4e}) "
+              f"L2 {err:.2e} max {emax:.2e}", flush=True)
+        assert st["cycles"] == 2 and err <= bar and emax <= bar
+        assert not x[~m].any()
+    g = nf.Grid(case, max_cycles=2)
+    s, stats = g.step(1, allow=(0, nf.NFVM_E_NOTCONV))
+    out = g.fields()
+    g.close()
+    assert stats[0]["cycles"] == 2
+    ref, _, _ = oracle.step(case, 1, forced_cycles=[2])
+    check_fields(case, out, ref, 1e-10, tag="room step, 2 iterations")
+
+
 @pytest.mark.parametrize("nu", [(2, 1), (1, 2), (1, 0)], ids=["nu2_1", "nu1_1", "nu2_0"])
 def test_odd_and_one_sided_smoothing_matches_oracle(nf, oracle, nu):
     """V(nu1, nu2) cycles other than V(2, 2): with nu1 + nu2 odd the V-cycle's
@@ -227,11 +285,7 @@ def test_odd_and_one_sided_smoothing_matches_oracle(nf, oracle, nu):
     out = g.fields()
     g.close()
     ref, _, _ = oracle.step(case, 2, forced_cycles=[x["cycles"] for x in stats])
-    errs = field_errors(case, out, ref)
-    print("   nu", nu, "cycles", [x["cycles"] for x in stats],
-          {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for f in ("vel", "p", "k", "omega"):
-        assert errs[f] <= 1e-10, (f, errs[f])
+    check_fields(case, out, ref, 1e-10, tag=f"nu {nu} cycles {[x['cycles'] for x in stats]}")
     g1, g2 = nf.Grid(case), nf.Grid(case.copy(precision=C.PREC_MIXED))
     nf.nfvm_step_batch([g1.h, g2.h], 2)
     f1 = g1.fields()
@@ -280,11 +334,7 @@ def test_nearest_prolongation_matches_oracle(nf, oracle, name, case):
             g.close()
             cyc = [x["cycles"] for x in stats]
             ref, _, _ = oracle.step(c2, c2.n_steps, forced_cycles=cyc)
-            errs = field_errors(c2, out, ref)
-            print(f"   nu={nu} prec={prec} cycles={cyc}", {k: f"{v:.2e}" for k, v in errs.items()},
-                  flush=True)
-            for f in ("vel", "p", "k", "omega"):
-                assert errs[f] <= TOL[prec], (f, errs[f])
+            check_fields(c2, out, ref, TOL[prec], tag=f"nu={nu} prec={prec} cycles={cyc}")
 
 
 def test_nearest_prolongation_batches_apart(nf):
@@ -329,13 +379,7 @@ def test_heun_stage_matches_oracle(nf, oracle, name, case):
         g.close()
         cyc = [x["cycles"] for x in stats]
         ref, _, _ = oracle.step(c2, c2.n_steps, forced_cycles=cyc)
-        errs = field_errors(c2, out, ref)
-        print(f"[heun] {name} prec={prec} cycles={cyc}", {k: f"{v:.2e}" for k, v in errs.items()},
-              flush=True)
-        for f in ("vel", "p", "k", "omega"):
-            assert errs[f] <= TOL[prec], (f, errs[f])
-        if c2.physics & C.PHYS_ENERGY:
-            assert errs["T"] <= TOL[prec], ("T", errs["T"])
+        check_fields(c2, out, ref, TOL[prec], tag=f"[heun] {name} prec={prec} cycles={cyc}")
         if prec == C.PREC_FP64:
             g = nf.Grid(c2.copy(rk_order=1))
             g.step(c2.n_steps, allow=(0, nf.NFVM_E_NOTCONV))
@@ -503,10 +547,7 @@ def test_warm_start_matches_oracle(nf, oracle):
     g.close()
     cyc = [x["cycles"] for x in stats]
     ref, _, _ = oracle.step(case, 3, forced_cycles=cyc, warm=True)
-    errs = field_errors(case, out, ref)
-    print("   cycles", cyc, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for f in ("vel", "p", "k", "omega", "T"):
-        assert errs[f] <= 1e-10, (f, errs[f])
+    check_fields(case, out, ref, 1e-10, tag=f"cycles {cyc}")
 
 
 def test_error_paths(nf):
@@ -545,7 +586,4 @@ def test_bottom_solver_and_graphs_match_plain_launches(nf, oracle):
         g.close()
     for (out, cyc) in outs:
         ref, _, _ = oracle.step(case, 3, forced_cycles=cyc)
-        errs = field_errors(case, out, ref)
-        print("   cycles", cyc, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-        for f in ("vel", "p", "k", "omega", "T"):
-            assert errs[f] <= 1e-10, (f, errs[f])
+        check_fields(case, out, ref, 1e-10, tag=f"cycles {cyc}")

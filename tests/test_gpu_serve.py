@@ -42,11 +42,12 @@ def test_alone_equals_in_mix(nf):
               flush=True)
         g = nf.Grid(c)
         s, stats = g.step(c.n_steps, allow=(nf.NFVM_OK, nf.NFVM_E_DIVERGED, nf.NFVM_E_NOTCONV))
+        why = nf.nfvm_last_error() if s != nf.NFVM_OK else ""
         out = g.fields()
         g.close()
         bad = [(i, st) for i, st in enumerate(stats) if st["status"] != nf.NFVM_OK]
         nonfinite = [k for k, v in out.items() if not np.isfinite(v).all()]
-        assert s == nf.NFVM_OK, (c.name, s, bad[:1], stats, nonfinite)
+        assert s == nf.NFVM_OK, (c.name, s, why, bad[:1], stats, nonfinite)
         alone.append(out)
     srv = nf.nfvm_server_create(0.0, 3)
     tickets = []
