@@ -493,7 +493,7 @@ typedef struct {
 } orc_level;
 
 struct orc_mg {
-  int dim, L, nu1, nu2, prolong;
+  int dim, L, nu1, nu2, prolong, literal;
   double wj;
   orc_level lv[24];
   int nc;        /* active cells on the coarsest level */
@@ -526,6 +526,12 @@ static double lface(const orc_level* l, int d, int side, int i, int j, int k, in
 static double ldiag(const orc_mg* mg, const orc_level* l, int i, int j, int k) {
   double D = 0.0;
   int nidx;
+  if (mg->literal) {
+    /* eq. jacobi_pc: D replaced by the scalar 6/dx^2 (2 sum_d 1/h_d^2 with
+     * unequal spacings), whatever the cell's faces */
+    for (int d = 0; d < mg->dim; ++d) D += 2.0 / (l->h[d] * l->h[d]);
+    return D;
+  }
   for (int d = 0; d < mg->dim; ++d)
     for (int s = -1; s <= 1; s += 2) D += lface(l, d, s, i, j, k, &nidx) / (l->h[d] * l->h[d]);
   return D;
@@ -752,6 +758,15 @@ orc_mg* orc_mg_create(const orc_case* c) {
   mg->prolong = c->prolong;
   mg->nu2 = c->nu2;
   mg->wj = c->omega_jacobi > 0 ? c->omega_jacobi : (c->dim == 3 ? 6.0 / 7.0 : 4.0 / 5.0);
+  mg->literal = c->literal;
+  if (mg->literal) {
+    /* Algorithm 1: no pre-smoothing, one sweep per level on the way up,
+     * undamped, nearest upsampling */
+    mg->nu1 = 0;
+    mg->nu2 = 1;
+    mg->wj = 1.0;
+    mg->prolong = 1;
+  }
   /* level 0 from the cell classification */
   orc_level* l0 = &mg->lv[0];
   for (int d = 0; d < 3; ++d) { l0->n[d] = c->n[d]; l0->h[d] = c->h[d]; }
@@ -842,7 +857,16 @@ void orc_mg_level_active(const orc_mg* mg, int l, unsigned char* act) {
 
 static void vcycle(const orc_mg* mg, int li, double* x, const double* b) {
   const orc_level* l = &mg->lv[li];
-  if (li == mg->L - 1) { coarse_solve(mg, x, b); return; }
+  if (li == mg->L - 1) {
+    if (mg->literal) {
+      /* Algorithm 1's coarsest level: one Jacobi sweep from w = 0 */
+      memset(x, 0, sizeof(double) * lcells(l));
+      orc_mg_smooth(mg, li, x, b, 1);
+    } else {
+      coarse_solve(mg, x, b);
+    }
+    return;
+  }
   int N = lcells(l);
   orc_mg_smooth(mg, li, x, b, mg->nu1);
   double* r = (double*)malloc(sizeof(double) * N);
@@ -908,6 +932,16 @@ int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int m
     }
     memset(z, 0, sizeof(double) * N);
     vcycle(mg, 0, z, r);
+    if (mg->literal) {
+      /* Algorithm 1's outer loop: p <- p - w with w the cycle's answer for
+       * A w = A p - b (here x += z with z for A z = b - A x), then the
+       * residual again (read as recomputed every iteration) */
+      for (int P = 0; P < N; ++P) x[P] += z[P];
+      orc_mg_apply(mg, 0, x, r);
+      for (int P = 0; P < N; ++P) r[P] = l->act[P] ? b[P] - r[P] : 0.0;
+      ++cyc;
+      continue;
+    }
     double zr = dot_active(l, z, r);
     double pq;
     if (cyc == 0) {

@@ -51,6 +51,13 @@ typedef struct {
   int rk_order;        /* explicit stage: 1 forward Euler; 2 Heun's method in
                           its strong-stability-preserving form (Sec. 2.6 leaves
                           the Runge-Kutta scheme open) */
+  int literal;         /* 1: Algorithm 1 as printed: the residual restricted to
+                          every level, one undamped Jacobi sweep per level on the
+                          way up with the scalar diagonal 2 sum_d 1/h_d^2 of eq.
+                          jacobi_pc (one sweep from zero on the coarsest level),
+                          nearest upsampling, one fine sweep, repeated as a plain
+                          iteration (no Krylov wrapper); nu1, nu2, omega_jacobi
+                          and prolong are then ignored */
 } orc_case;
 
 typedef struct { double *u, *v, *w, *p, *T, *k, *omega; } orc_fields;

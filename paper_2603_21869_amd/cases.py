@@ -104,6 +104,10 @@ class Case:
     # explicit stage: 1 forward Euler, 2 Heun's method (SSP form); the paper
     # names explicit Runge-Kutta schemes without fixing one (Sec. 2.6)
     rk_order: int = 1
+    # 1: the pressure solve as Algorithm 1 prints it (undamped Jacobi with the
+    # scalar diagonal, V(0,1) with nearest upsampling and one coarsest sweep,
+    # a plain iteration without a Krylov wrapper)
+    literal: int = 0
     n_steps: int = 1
     seed: int = 0
 

@@ -287,3 +287,98 @@ def test_exact_first_cycle_then_breakdown_takes_no_step(oracle):
     assert cyc == 4 and st == 0
     assert x[0, 0, 0] == 0.5 and rel == 0.0
 
+
+
+def test_literal_jacobi_sweep_is_undamped_with_scalar_diagonal(oracle):
+    """Algorithm 1 read literally (eq. jacobi_pc): one Jacobi sweep with the
+    scalar D = 2 sum_d 1/h_d^2 (6/dx^2 at equal spacing) and no damping
+    multiplies every eigenmode of A by exactly 1 - lambda/D, boundary cells
+    included (a per-cell diagonal would not keep the sine modes)."""
+    n = (8, 6, 5)
+    h = (0.1, 0.13, 0.07)
+    c = box(n, h, kinds=[C.OUTLET] * 6).copy(literal=1)
+    mg = oracle.MG(c)
+    Ds = sum(2 / hd ** 2 for hd in h)
+    idx = np.meshgrid(np.arange(5), np.arange(6), np.arange(8), indexing="ij")
+    for m in ((1, 1, 1), (3, 2, 4), (8, 6, 5)):
+        v = np.ones((5, 6, 8))
+        lam = 0.0
+        for d, (ax, nd) in enumerate(((2, 8), (1, 6), (0, 5))):
+            v = v * np.sin(math.pi * m[d] * (idx[ax] + 0.5) / nd)
+            lam += 4 / h[d] ** 2 * math.sin(math.pi * m[d] / (2 * nd)) ** 2
+        out = mg.smooth(0, v, np.zeros_like(v), 1)
+        assert np.allclose(out, v * (1 - lam / Ds), rtol=0, atol=1e-12)
+    # the highest mode grows in magnitude under the undamped sweep: |1 - lambda/D| > 1
+    # is impossible here (lambda < 2 D), but it is barely damped: the smoothing
+    # factor of undamped Jacobi is 1 on the checkerboard mode
+    assert abs(1 - lam / Ds) > 0.9
+
+
+def test_literal_plain_iteration_closed_form(oracle):
+    """One level (the coarsest is the fine level, one sweep from zero): the
+    literal cycle returns r / D, so the plain iteration x <- x + (b - A x)/D on
+    an eigenmode b = v reaches x_k = (1 - (1 - lambda/D)^k) v / lambda."""
+    n = (8, 6)
+    h = (0.1, 0.13)
+    c = box(n, h, dim=2, kinds=[C.OUTLET] * 4).copy(literal=1)
+    mg = oracle.MG(c)
+    Ds = sum(2 / hd ** 2 for hd in h)
+    j, i = np.meshgrid(np.arange(6), np.arange(8), indexing="ij")
+    v = (np.sin(math.pi * 2 * (i + 0.5) / 8) * np.sin(math.pi * (j + 0.5) / 6))[None]
+    lam = 4 / h[0] ** 2 * math.sin(math.pi * 2 / 16) ** 2 + 4 / h[1] ** 2 * math.sin(math.pi / 12) ** 2
+    e = mg.vcycle(np.zeros_like(v), v)
+    assert np.allclose(e, v / Ds, rtol=0, atol=1e-15)
+    for k in (1, 2, 7):
+        x, cyc, rel, st = mg.solve(v, forced=k)
+        want = (1 - (1 - lam / Ds) ** k) * v / lam
+        assert cyc == k and np.allclose(x, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+def test_literal_cycle_matches_algorithm_1_in_matrix_form(oracle):
+    """Brute force: Algorithm 1 written out with assembled matrices (the level
+    operators A_l column by column from the oracle's operator; RES the mean of
+    the children, PROL nearest upsampling, D_l the scalar diagonal), its
+    residual r = A p - b restricted to every level, one sweep per level on the
+    way up with w <- PROL(w), p <- p - w and one fine sweep, gives the
+    oracle's forced iterates."""
+    n = (16, 8)
+    h = (0.05, 0.07)
+    pats = [C.Patch(0, (0, 0), (8, 1), kind=C.INLET), C.Patch(1, (2, 0), (6, 1), kind=C.OUTLET)]
+    c = box(n, h, dim=2, patches=pats, n_levels=3).copy(literal=1)
+    mg = oracle.MG(c)
+    L = 3
+    shapes = [mg.shape(l)[0] for l in range(L)]
+    A = []
+    for l in range(L):
+        N = int(np.prod(shapes[l]))
+        M = np.zeros((N, N))
+        for q in range(N):
+            e = np.zeros(N)
+            e[q] = 1.0
+            M[:, q] = mg.apply(l, e.reshape(shapes[l])).ravel()
+        A.append(M)
+    Ds = [sum(2 / (hd * 2 ** l) ** 2 for hd in h) for l in range(L)]
+
+    def res(r, l):  # level l -> l + 1, mean of the 2 x 2 children
+        f = r.reshape(shapes[l])[0]
+        return (0.25 * (f[0::2, 0::2] + f[1::2, 0::2] + f[0::2, 1::2] + f[1::2, 1::2])).ravel()
+
+    def prol(w, l):  # level l + 1 -> l, nearest
+        cw = w.reshape(shapes[l + 1])[0]
+        return np.repeat(np.repeat(cw, 2, axis=0), 2, axis=1).ravel()
+
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(shapes[0]).ravel()
+    p = np.zeros_like(b)
+    for it in range(1, 5):
+        r = [A[0] @ p - b]
+        for l in range(L - 1):
+            r.append(res(r[-1], l))
+        w = np.zeros_like(r[L - 1])
+        for l in range(L - 1, 0, -1):
+            w = w - (A[l] @ w) / Ds[l] + r[l] / Ds[l]
+            w = prol(w, l - 1)
+        p = p - w
+        p = p - (A[0] @ p) / Ds[0] + b / Ds[0]
+        x, cyc, rel, st = mg.solve(b.reshape(shapes[0]), forced=it)
+        assert np.allclose(x.ravel(), p, rtol=0, atol=1e-12 * np.abs(p).max()), it
