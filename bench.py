@@ -5,11 +5,12 @@ step, explicit update, Poisson right-hand side, multigrid-preconditioned
 pressure solve to the residual target, projection, destruction half step) over
 the whole grid, with all fields resident in device memory.
 
-Default workload: the 3D heated channel, 256 x 64 x 64 cells (2.56 x 0.64 x
-0.64 m, inlet 0.1 m/s, bottom wall 310 K, Boussinesq buoyancy, seeded 1 %
-velocity noise), 7 multigrid levels, mixed precision (FP32 scalars, FP32 /
-BF16 V-cycle, FP64 velocity, pressure, residual and projection), pressure
-solved to a relative residual of 1e-6 every step.
+Default workload: the ventilated room at its largest size, 10 x 4 x 3 m on
+1024 x 512 x 256 cells (134M), 8-24 seeded solid blocks, supply vent under
+the ceiling and exhaust at the floor, 9 multigrid levels, mixed precision
+(FP32 scalars and level-0 sweeps, BF16 coarse levels, FP64 velocity,
+pressure, residual and projection), pressure solved to a relative residual
+of 1e-6 every step.
 
 Prints one JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
 """
@@ -31,8 +32,9 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, vendor figure
 WORKLOADS = {
     "channel3d": "3D heated channel 256x64x64, 7 levels",
     "channel2d": "2D turbulent channel 256x64, 6 levels",
-    "room": "3D ventilated room 512x256x128 with seeded blocks, 8 levels",
-    "bigroom": "3D ventilated room 1024x512x256 with seeded blocks, 9 levels",
+    "room": "3D ventilated room 10x4x3 m on 512x256x128 cells with seeded blocks, 8 levels",
+    "bigroom": "3D ventilated room 10x4x3 m on 1024x512x256 cells (134M) with seeded blocks, "
+               "9 levels",
     "open_channel_128": "open channel at 5 mm, 128x128x128 (L = 0.64 m), 8 levels",
     "open_channel_512": "open channel at 5 mm, 512x128x128 (L = 2.56 m), 8 levels",
     "open_channel_2048": "open channel at 5 mm, 2048x128x128 (L = 10.24 m), 8 levels",
@@ -50,7 +52,24 @@ KERNEL_SOURCES = ("k_mg.hip", "k_physics.hip", "nfvm_device.hpp", "nfvm_internal
 PROFILE_FILES = {
     ("channel3d", "mixed"): "kernels_channel3d_256x64x64_mixed.md",
     ("room", "mixed"): "kernels_room_512x256x128_mixed.md",
+    ("bigroom", "mixed"): "kernels_bigroom_1024x512x256_mixed.md",
 }
+
+# Unfused per-operator byte model of one 3D V(2,2) cycle and of the rest of a
+# step, per fine cell: each operand of each operator read once and each
+# result written once at its storage precision.  A cycle moves 18.25 values
+# per fine cell on level 0 (four sweeps of 3, residual 3, restriction 1 1/8,
+# prolongation and correction 2 1/8) and 8/7 of that over all levels; mixed
+# precision stores level 0 in FP32 and the coarse levels in BF16 and adds the
+# FP64 outer residual and update (40 B).  The rest of a step is the explicit
+# update, the two destruction half steps, the right-hand side and the
+# projection.
+MODEL_CYCLE_B = {"fp64": 167.0, "fp32": 83.0, "mixed": 118.0}
+MODEL_STEP_B = {"fp64": 344.0, "fp32": 172.0, "mixed": 190.0}
+# kernels of the pressure solve (the rest of a step is the physics kernels)
+SOLVE_KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "fcg_apply", "fcg_update",
+                 "smooth_coarse", "restrict_coarse", "prolong_coarse", "bottom", "fcg_start",
+                 "finalize")
 
 
 def kernel_source_hash() -> str:
@@ -97,45 +116,52 @@ def make_case(name: str, precision: int, tol: float):
     raise SystemExit(f"unknown workload {name}")
 
 
-def run_gpu(case, steps: int, warmup: int, profile: bool, stream: int, graphs: bool = True,
-            warm_start: bool = False):
+def timed_steps(g, steps: int):
+    """steps time steps of grid g between two device synchronisations."""
     import torch
     from paper_2603_21869_amd import nfvm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s, stats = g.step(steps, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV, nfvm.NFVM_E_DIVERGED))
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats, s
+
+
+def profile_steps(g, steps: int):
+    """The same steps with HIP events around every kernel launch (stream
+    launches: the events would split the graphs).  Returns the summed event
+    time and, per kernel, launches, seconds and mean algorithmic bytes."""
+    from paper_2603_21869_amd import nfvm
+    nfvm.nfvm_profile(g.h, (1 << len(nfvm.KERNELS)) - 1)
+    sec, _, _ = timed_steps(g, steps)
+    prof = {name: nfvm.nfvm_profile_read(g.h, kid) for kid, name in enumerate(nfvm.KERNELS)}
+    nfvm.nfvm_profile(g.h, 0)
+    return sec, prof
+
+
+def run_gpu(case, steps: int, warmup: int, stream: int, warm_start: bool = False):
+    """Throughput of `steps` steps on a fresh grid after `warmup` steps."""
+    from paper_2603_21869_amd import nfvm
     g = nfvm.Grid(case, stream=stream)
-    nfvm.nfvm_set_option(g.h, nfvm.NFVM_OPT_GRAPHS, 1.0 if graphs else 0.0)
     nfvm.nfvm_set_option(g.h, nfvm.NFVM_OPT_WARM_START, 1.0 if warm_start else 0.0)
     if warmup:
-        g.step(warmup, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
-    torch.cuda.synchronize()
-    if profile:
-        nfvm.nfvm_profile(g.h, (1 << len(nfvm.KERNELS)) - 1)
-    t0 = time.perf_counter()
-    s, stats = g.step(steps, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = {}
-    if profile:
-        for kid, name in enumerate(nfvm.KERNELS):
-            prof[name] = nfvm.nfvm_profile_read(g.h, kid)
+        g.step(warmup, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV, nfvm.NFVM_E_DIVERGED))
+    sec, stats, s = timed_steps(g, steps)
     g.close()
-    return t1 - t0, stats, prof, s
+    return sec, stats, s
 
 
-def run_pcie(case, steps: int, stream: int):
+def run_pcie(g, case, steps: int):
     """Throughput with the fields handed over in host memory: upload, the
-    steps, download (the grid and its tile choices exist already)."""
+    steps, download (on a grid whose tile choices exist already)."""
     import torch
-    from paper_2603_21869_amd import nfvm
-    g = nfvm.Grid(case, stream=stream)
-    g.step(1, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.set_fields(case.fields)
-    g.step(steps, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+    g.step(steps, allow=(0, -5))
     g.fields()
     torch.cuda.synchronize()
     sec = time.perf_counter() - t0
-    g.close()
     return case.ncells * steps / sec / 1e6
 
 
@@ -232,7 +258,7 @@ def run_paper_table(stream: int, precision: int, tol: float, steps: int = 100):
     rows = []
     for nx, paper_s in PAPER_TABLE1_GPU_S.items():
         case = C.open_channel(nx, precision=precision, tol=tol, n_steps=steps)
-        sec, stats, _, _ = run_gpu(case, steps, 2, False, stream)
+        sec, stats, _ = run_gpu(case, steps, 2, stream)
         rows.append({"cells": case.ncells, "n": list(case.n), "levels": case.n_levels,
                      "steps": steps, "seconds": round(sec, 3),
                      "mcell_steps_s": round(case.ncells * steps / sec / 1e6, 2),
@@ -242,49 +268,88 @@ def run_paper_table(stream: int, precision: int, tol: float, steps: int = 100):
     return rows
 
 
-def cpu_baseline(case, budget_s: float = 20.0):
-    """The serial FP64 oracle on a bounded number of steps of the same workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload: str, tol: float, budget_s: float = 20.0):
+    """The serial FP64 oracle, pinned to one host core, on a bounded sample of
+    the workload.  The large room is sampled as the same room (same blocks in
+    metres, vents, physics and tolerance) on a 256 x 128 x 64 grid, one step;
+    the other workloads as up to four steps of the workload itself."""
+    from paper_2603_21869_amd import cases as C
     from oracle import oracle as O
     O.build()
-    t0 = time.perf_counter()
-    f, st, status = O.step(case, 1)
-    t1 = time.perf_counter()
-    n = 1
-    per = t1 - t0
-    extra = int(max(0, min(3, budget_s / per - 1)))
-    if extra:
-        t2 = time.perf_counter()
-        O.step(case, extra, fields=f)
-        t3 = time.perf_counter()
-        per = (t1 - t0 + t3 - t2) / (1 + extra)
-        n += extra
-    return dict(value=case.ncells / per / 1e6, unit="Mcell-steps/s", cores=1, kind="oracle",
-                sample=f"{n} step(s) of the same workload from its initial state, serial FP64 "
-                       f"oracle, {per:.2f} s/step")
+    if workload == "bigroom":
+        case = C.room3d(256, 128, 64, n_levels=7, precision=C.PREC_FP64, tol=tol, n_steps=1)
+        what = ("one time step of the same room (same blocks, vents, physics, tol) on a "
+                "256x128x64 grid (1/64 of the cells), 7 levels")
+    else:
+        case = make_case(workload, C.PREC_FP64, tol)
+        what = "time steps of the same workload from its initial state"
+    try:
+        old_aff = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {min(old_aff)})
+    except (AttributeError, OSError):
+        old_aff = None
+    try:
+        t0 = time.perf_counter()
+        f, st, status = O.step(case, 1)
+        per = time.perf_counter() - t0
+        n = 1
+        if workload != "bigroom":
+            extra = int(max(0, min(3, budget_s / per - 1)))
+            if extra:
+                t2 = time.perf_counter()
+                O.step(case, extra, fields=f)
+                per = (per + time.perf_counter() - t2) / (1 + extra)
+                n += extra
+    finally:
+        if old_aff is not None:
+            os.sched_setaffinity(0, old_aff)
+    return dict(value=round(case.ncells / per / 1e6, 4), unit="Mcell-steps/s", cores=1,
+                kind="oracle",
+                sample=f"{n} {what}; serial FP64 oracle pinned to one core ({cpu_model()}), "
+                       f"{per:.2f} s/step, {st[0]['cycles']} V-cycles in its first step")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="channel3d", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="bigroom", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other precisions and tolerances of the same workload")
+    ap.add_argument("--all-variants", action="store_true",
+                    help="also Algorithm 1's cycle, nearest upsampling, Heun stage, FP32")
     ap.add_argument("--serve", type=int, default=24,
                     help="requests of the serving trace to replay (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=9)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--lambda2", type=int, default=3,
+    ap.add_argument("--lambda2", type=int, default=1,
                     help="lambda2 post-processing calls timed after the run (0: skip)")
     ap.add_argument("--no-paper-table", action="store_true",
                     help="skip the paper's open-channel timing workload (three lengths)")
+    ap.add_argument("--only-steps", action="store_true",
+                    help="only the timed steps of the workload (for profiler runs)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (for "
                          "scaling hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
     if args.copy_calibration_mb:
         import torch
         n = args.copy_calibration_mb * (1 << 20) // 4
@@ -295,9 +360,6 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "repeats": 5}))
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
 
     import torch
     from paper_2603_21869_amd import cases as C, nfvm
@@ -306,79 +368,113 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     prec = {"fp64": C.PREC_FP64, "fp32": C.PREC_FP32, "mixed": C.PREC_MIXED}[args.precision]
     case = make_case(args.workload, prec, args.tol)
+    print(f"[bench] {args.workload} {case.n} {args.precision} tol={args.tol}", file=sys.stderr,
+          flush=True)
 
     # timed run: graphs on, no per-kernel events (they would split the graphs)
-    sec, stats, _, status = run_gpu(case, args.steps, args.warmup, False, stream, graphs=True)
+    g = nfvm.Grid(case, stream=stream)
+    if args.warmup:
+        g.step(args.warmup, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+    sec, stats, status = timed_steps(g, args.steps)
     ms_per_step = sec / args.steps * 1e3
     value = case.ncells * args.steps / sec / 1e6
     cycles = [s["cycles"] for s in stats]
+    mean_cycles = sum(cycles) / len(cycles)
     rel = [s["rel_residual"] for s in stats]
-    # kernel timing: the same workload and step count with HIP events around
-    # every hot kernel launch (stream launches)
-    psec, _, prof, _ = run_gpu(case, args.steps, args.warmup, True, stream, graphs=False)
+    if args.only_steps:
+        g.close()
+        print(json.dumps({"workload": args.workload, "value": round(value, 3),
+                          "ms_per_step": round(ms_per_step, 4), "mean_cycles": mean_cycles}))
+        return
+    print(f"[bench] {value:.1f} Mcell-steps/s, {mean_cycles:.2f} cycles", file=sys.stderr,
+          flush=True)
 
-    # dominant kernel: largest summed device time in the timed region
+    # the same steps again with HIP events around every kernel launch
+    psec, prof = profile_steps(g, args.steps)
+    kernel_table = {}
+    for k, v in prof.items():
+        if not v["launches"]:
+            continue
+        avg = v["seconds"] / v["launches"]
+        kernel_table[k] = dict(launches=v["launches"], avg_us=round(avg * 1e6, 3),
+                               bytes_per_launch=round(v["bytes_per_launch"]),
+                               GBs=round(v["bytes_per_launch"] / avg / 1e9, 1) if avg > 0 else 0.0,
+                               share=round(v["seconds"] / psec, 4))
+    # dominant kernel: the largest summed device time over every kernel
     dom = max(prof, key=lambda k: prof[k]["seconds"])
     d = prof[dom]
     avg = d["seconds"] / max(1, d["launches"])
     achieved = d["bytes_per_launch"] / avg / 1e9 if avg > 0 else 0.0
-    kernel_table = {k: dict(launches=v["launches"], avg_us=(v["seconds"] / v["launches"] * 1e6)
-                            if v["launches"] else 0.0,
-                            GBs=(v["bytes_per_launch"] / (v["seconds"] / v["launches"]) / 1e9)
-                            if v["launches"] and v["seconds"] > 0 else 0.0,
-                            share=v["seconds"] / psec)
-                    for k, v in prof.items() if v["launches"]}
-
-    variants = {}
-    if not args.no_variants:
-        # the same workload with each solve started from the previous step's
-        # increment (NFVM_OPT_WARM_START; the default starts from zero)
-        sw, stw, _, _ = run_gpu(case, args.steps, args.warmup, False, stream, warm_start=True)
-        variants[args.precision + "_warm_start"] = dict(
-            value=case.ncells * args.steps / sw / 1e6, ms_per_step=sw / args.steps * 1e3,
-            mean_cycles=sum(x["cycles"] for x in stw) / len(stw))
-        # Algorithm 1's upsampling read as nearest (piecewise constant), in
-        # the V(2,2) cycle and in Algorithm 1's own V(0,1) shape
-        # and the explicit stage as Heun's second-order Runge-Kutta method
-        for vname, kw in (("nearest_prolongation", dict(prolong=C.PROL_NEAREST)),
-                          ("alg1_v01_nearest", dict(prolong=C.PROL_NEAREST, nu1=0, nu2=1)),
-                          ("heun_rk2", dict(rk_order=2))):
-            c2 = make_case(args.workload, prec, args.tol).copy(**kw)
-            k2 = max(5, args.steps // 2)
-            s2, st2, _, _ = run_gpu(c2, k2, args.warmup, False, stream)
-            variants[args.precision + "_" + vname] = dict(
-                value=c2.ncells * k2 / s2 / 1e6, ms_per_step=s2 / k2 * 1e3,
-                mean_cycles=sum(x["cycles"] for x in st2) / len(st2),
-                statuses=sorted({x["status"] for x in st2}))
-        for pname, pv in (("fp64", C.PREC_FP64), ("fp32", C.PREC_FP32), ("mixed", C.PREC_MIXED)):
-            if pv == prec:
-                continue
-            c2 = make_case(args.workload, pv, args.tol)
-            k2 = max(5, args.steps // 2)
-            s2, st2, _, _ = run_gpu(c2, k2, args.warmup, False, stream)
-            variants[pname] = dict(value=c2.ncells * k2 / s2 / 1e6,
-                                   ms_per_step=s2 / k2 * 1e3,
-                                   mean_cycles=sum(x["cycles"] for x in st2) / len(st2))
-
-    pcie = run_pcie(case, args.steps, stream)
+    # the pressure solve as a whole: its kernels' summed device time per step,
+    # their algorithmic bytes, and the unfused byte model of a V(2,2) cycle
+    t_solve = sum(prof[k]["seconds"] for k in SOLVE_KERNELS) / args.steps
+    b_solve = sum(prof[k]["bytes_per_launch"] * prof[k]["launches"] for k in SOLVE_KERNELS) \
+        / args.steps
+    t_phys = sum(v["seconds"] for k, v in prof.items() if k not in SOLVE_KERNELS) / args.steps
+    model_solve = MODEL_CYCLE_B[args.precision] * case.ncells * mean_cycles
+    model_step = model_solve + MODEL_STEP_B[args.precision] * case.ncells
+    solve = {
+        "kernel_ms_per_step": round(t_solve * 1e3, 4),
+        "physics_kernel_ms_per_step": round(t_phys * 1e3, 4),
+        "algorithmic_GBs": round(b_solve / t_solve / 1e9, 1),
+        "model_bytes_per_cell_cycle": MODEL_CYCLE_B[args.precision],
+        "model_GBs": round(model_solve / t_solve / 1e9, 1),
+        "model_frac": round(model_solve / t_solve / 1e9 / PEAK_HBM_GBS, 4),
+        "step_model_GBs": round(model_step / (ms_per_step * 1e-3) / 1e9, 1),
+        "step_model_frac": round(model_step / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+    }
+    pcie = run_pcie(g, case, max(2, args.steps // 2))
     post = None
     if args.lambda2 > 0:
         # the lambda2 vortex criterion of the stepped velocity, handed back
         # in host memory (device kernel plus the FP64 copy over PCIe)
-        from paper_2603_21869_amd import nfvm
-        g = nfvm.Grid(case, stream=stream)
-        g.step(1, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
         g.lambda2()
         t0 = time.perf_counter()
         for _ in range(args.lambda2):
             l2 = g.lambda2()
-        sec = (time.perf_counter() - t0) / args.lambda2
-        g.close()
-        post = dict(lambda2_ms_host=round(sec * 1e3, 3), calls=args.lambda2,
+        lsec = (time.perf_counter() - t0) / args.lambda2
+        post = dict(lambda2_ms_host=round(lsec * 1e3, 3), calls=args.lambda2,
                     vortex_cells=int((l2 < 0).sum()))
+        del l2
+    g.close()
+    copy_GBs = round(copy_bandwidth(), 1)
+
+    variants = {}
+    if not args.no_variants:
+        k2 = max(3, args.steps // 2)
+        runs = [("fp64", C.PREC_FP64, args.tol, {}, False)]
+        if args.tol > 1e-9:
+            # the tolerances at which every field meets 1e-6 of the converged
+            # FP64 solution on the small rooms (mixed: 1e-9, FP64: 1e-8)
+            runs += [("mixed_tol_1e-9", C.PREC_MIXED, 1e-9, {}, False),
+                     ("fp64_tol_1e-8", C.PREC_FP64, 1e-8, {}, False)]
+        runs += [(args.precision + "_warm_start", prec, args.tol, {}, True),
+                 # Algorithm 1 as printed (undamped scalar-diagonal Jacobi,
+                 # V(0,1), nearest upsampling, plain iteration): its
+                 # convergence or divergence on this workload
+                 (args.precision + "_alg1_literal", prec, args.tol, dict(literal=1), False)]
+        if args.all_variants:
+            runs += [("fp32", C.PREC_FP32, args.tol, {}, False),
+                     (args.precision + "_nearest_prolongation", prec, args.tol,
+                      dict(prolong=C.PROL_NEAREST), False),
+                     (args.precision + "_alg1_v01_nearest", prec, args.tol,
+                      dict(prolong=C.PROL_NEAREST, nu1=0, nu2=1), False),
+                     (args.precision + "_heun_rk2", prec, args.tol, dict(rk_order=2), False)]
+        for vname, pv, tv, kw, warm in runs:
+            if vname.split("_")[0] == args.precision and tv == args.tol and not kw and not warm:
+                continue
+            c2 = make_case(args.workload, pv, tv).copy(**kw)
+            print(f"[bench] variant {vname}", file=sys.stderr, flush=True)
+            s2, st2, _ = run_gpu(c2, k2, 1, stream, warm_start=warm)
+            variants[vname] = dict(value=round(c2.ncells * k2 / s2 / 1e6, 2),
+                                   ms_per_step=round(s2 / k2 * 1e3, 3), tol=tv,
+                                   mean_cycles=sum(x["cycles"] for x in st2) / len(st2),
+                                   statuses=sorted({x["status"] for x in st2}),
+                                   last_rel_residual=st2[-1]["rel_residual"])
+            del c2
     traffic, traffic_src = measured_traffic(args.workload, args.precision, dom)
     out = {
-        "metric": "Mcell-steps/s at 1e-6 residual",
+        "metric": "Mcell-steps/s at 1e-6 residual, % HBM peak; p50/p99 latency, batched solves",
         "value": round(value, 3),
         "unit": "Mcell-steps/s",
         "n_gpus": 1,
@@ -394,31 +490,35 @@ def main():
                    "precision": args.precision, "tol": args.tol, "dt": case.dt,
                    "levels": case.n_levels, "smoothing": "V(2,2) damped Jacobi",
                    "parallelism": "single GPU"},
-        "solver": {"mean_cycles": sum(cycles) / len(cycles), "max_rel_residual": max(rel)},
+        "solver": {"mean_cycles": mean_cycles, "max_rel_residual": max(rel),
+                   "statuses": sorted({x["status"] for x in stats})},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": traffic, "traffic_source": traffic_src,
                      "avg_launch_us": round(avg * 1e6, 2),
                      "algorithmic_bytes_per_launch": d["bytes_per_launch"],
-                     "copy_GBs": round(copy_bandwidth(), 1)},
-        "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                    for k, v in kernel_table.items()},
+                     "copy_GBs": copy_GBs, "solve": solve},
+        "kernels": kernel_table,
         "variants": variants,
-        "stream_launch_ms_per_step": round(psec / args.steps * 1e3, 4),
+        "event_timed_ms_per_step": round(psec / args.steps * 1e3, 4),
         "pcie_inclusive_mcell_steps_s": round(pcie, 2),
         "postprocess": post,
-        "tuning": [list(t) for t in nfvm.nfvm_tuning_table()],
+        "tuning_entries": len(nfvm.nfvm_tuning_table()),
         "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
                          "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",
     }
     if not args.no_batch:
+        print("[bench] batching", file=sys.stderr, flush=True)
         out["batching"] = run_batch()
     if args.serve:
+        print("[bench] serving", file=sys.stderr, flush=True)
         out["serving"] = run_serve(args.serve, args.serve_slots)
     if not args.no_paper_table:
+        print("[bench] paper table", file=sys.stderr, flush=True)
         out["paper_table"] = run_paper_table(stream, prec, args.tol)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(make_case(args.workload, C.PREC_FP64, args.tol))
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)
     print(json.dumps(out))
 
 

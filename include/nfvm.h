@@ -209,7 +209,10 @@ nfvm_status nfvm_reduction_blocks(const nfvm_grid_desc* desc, int32_t* needed,
                                   int32_t* capacity);
 
 /* Release the grid's device memory, stream (if the library created it) and
- * graphs; waits for the grid's pending work.  The handle is invalid after. */
+ * graphs; waits for the grid's pending work.  The handle is invalid after.
+ * The grid's buffers come from one allocation with a zeroed guard zone after
+ * each; NFVM_E_DEVICE (the grid is released all the same) if a guard zone
+ * holds a non-zero byte, naming the buffer an out-of-bounds store ran past. */
 nfvm_status nfvm_free_grid(nfvm_grid_t grid);
 
 /* Serving: at most max_slots solves run at once; queued solves are admitted
@@ -322,6 +325,19 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
  *                     velocity and three scalar arrays, padded; not counted
  *                     by nfvm_grid_footprint); NFVM_E_NOMEM if that fails.
  *                     Other values: NFVM_E_INVAL.
+ *   NFVM_OPT_LITERAL  0 (default).  1: the pressure solve exactly as
+ *                     Algorithm 1 prints it (Sec. 2.4): the residual
+ *                     restricted to every level, on the way up one undamped
+ *                     Jacobi sweep per level with the scalar diagonal of eq.
+ *                     jacobi_pc (6/dx^2, 2 sum_d 1/h_d^2 for unequal spacings;
+ *                     one sweep from zero on the coarsest level) and nearest
+ *                     upsampling, then one fine sweep, repeated as a plain
+ *                     iteration p <- p + V(b - A p) without the conjugate-
+ *                     gradient wrapper, to tol or max_cycles (forced counts as
+ *                     usual).  nu1, nu2 and omega_jacobi of the descriptor
+ *                     are set aside while it is on.  Such grids are stepped
+ *                     alone: nfvm_step_batch refuses them (NFVM_E_INVAL).
+ *                     Other values: NFVM_E_INVAL.
  * Errors: NFVM_E_INVAL for an unknown option. */
 enum {
   NFVM_OPT_GRAPHS = 0,
@@ -330,7 +346,8 @@ enum {
   NFVM_OPT_AUTOTUNE = 3,
   NFVM_OPT_WARM_START = 4,
   NFVM_OPT_PROLONG = 5,
-  NFVM_OPT_RK_ORDER = 6
+  NFVM_OPT_RK_ORDER = 6,
+  NFVM_OPT_LITERAL = 7
 };
 
 /* The autotuner's choices so far: up to max entries of {kernel id, nx, ny,

@@ -21,6 +21,9 @@ static nfvm_status guard(Fn&& fn) {
     return fn();
   } catch (const Error& e) {
     set_error(e.msg);
+    // a failed HIP call leaves its code as this thread's last error: clear
+    // it, so that the next call's launch check does not report it again
+    (void)hipGetLastError();
     return e.st;
   } catch (const std::bad_alloc&) {
     set_error("host allocation failed");
@@ -202,7 +205,16 @@ nfvm_status nfvm_grid_footprint(const nfvm_grid_desc* desc, size_t* bytes) {
 nfvm_status nfvm_free_grid(nfvm_grid_t grid) {
   if (!grid) return fail(NFVM_E_INVAL, "grid is NULL");
   return guard([&] {
+    std::string bad;
+    try {
+      bad = grid->g->check_guards();
+    } catch (...) {
+      delete grid;
+      throw;
+    }
     delete grid;
+    if (!bad.empty())
+      throw Error{NFVM_E_DEVICE, "out-of-bounds device store past: " + bad};
     return NFVM_OK;
   });
 }

@@ -265,11 +265,50 @@ class GridT : public GridBase {
   hipEvent_t ev_step[2][2] = {};  // start / end of the last two steps
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
+  // Device memory of the grid: while the grid is set up, every buffer is
+  // carved from one allocation (the arena, sized by the footprint model),
+  // 256-byte aligned and followed by a zeroed guard zone that no kernel
+  // writes; buffers created later (options) get allocations of their own.
+  static constexpr size_t GUARD = 4096;
+  DevBuf arena;
+  size_t arena_off = 0;
+  bool arena_open = false;
+  std::vector<std::pair<size_t, std::string>> guards;  // guard offset, buffer before it
+
   template <class T>
-  T* alloc(size_t count) {
+  T* alloc(size_t count, const char* what = "buffer") {
+    const size_t bytes = count * sizeof(T);
+    if (arena_open) {
+      const size_t off = (arena_off + 255) & ~(size_t)255;
+      if (off + bytes + GUARD > arena.bytes)
+        throw Error{NFVM_E_NOMEM, std::string("grid memory model too small at ") + what};
+      arena_off = off + bytes;
+      guards.emplace_back(arena_off, what);
+      arena_off += GUARD;
+      return (T*)((unsigned char*)arena.p + off);
+    }
     pool.emplace_back(new DevBuf());
-    pool.back()->alloc(count * sizeof(T), stream);
+    pool.back()->alloc(bytes, stream);
     return pool.back()->template as<T>();
+  }
+
+  // Names of the buffers whose guard zone holds a non-zero byte (an
+  // out-of-bounds store past the buffer); empty when all are intact.
+  std::string check_guards() override {
+    std::string bad;
+    if (!arena.p || guards.empty()) return bad;
+    NFVM_CK(hipStreamSynchronize(stream));
+    std::vector<unsigned char> h(GUARD);
+    for (const auto& gr : guards) {
+      NFVM_CK(hipMemcpy(h.data(), (unsigned char*)arena.p + gr.first, GUARD,
+                        hipMemcpyDeviceToHost));
+      for (unsigned char c : h)
+        if (c) {
+          bad += (bad.empty() ? "" : ", ") + gr.second;
+          break;
+        }
+    }
+    return bad;
   }
 
   ~GridT() override {
@@ -277,6 +316,7 @@ class GridT : public GridBase {
     drop_graphs();
     prof_release();
     pool.clear();
+    arena.release();
     if (hs) (void)hipHostFree(hs);
     for (auto& pr : ev_step)
       for (hipEvent_t e : pr)
@@ -287,6 +327,10 @@ class GridT : public GridBase {
   }
 
   void init(const nfvm_grid_desc& d, const nfvm_fields* init) {
+    // one allocation for every buffer of the set-up (the footprint model
+    // bounds them; 2 MiB more covers alignment and guard zones)
+    arena.alloc(footprint_bytes(d) + ((size_t)2 << 20), stream);
+    arena_open = true;
     desc = d;
     desc.patches = nullptr;
     desc.solid_mask = nullptr;
@@ -364,30 +408,30 @@ class GridT : public GridBase {
       rect[5 * qi + 3] = s.hi[0];
       rect[5 * qi + 4] = s.hi[1];
     }
-    patches = alloc<DevPatch>(MAX_PATCHES);
+    patches = alloc<DevPatch>(MAX_PATCHES, "patch table");
     NFVM_CK(hipMemcpyAsync(patches, tab.data(), tab.size() * sizeof(DevPatch),
                            hipMemcpyHostToDevice, stream));
-    int* rect_d = alloc<int>(rect.size());
+    int* rect_d = alloc<int>(rect.size(), "patch rectangles");
     NFVM_CK(hipMemcpyAsync(rect_d, rect.data(), rect.size() * sizeof(int), hipMemcpyHostToDevice,
                            stream));
     uint8_t* solid_d = nullptr;
     if (d.solid_mask) {
-      solid_d = alloc<uint8_t>((size_t)ncells);
+      solid_d = alloc<uint8_t>((size_t)ncells, "solid mask");
       NFVM_CK(hipMemcpyAsync(solid_d, d.solid_mask, (size_t)ncells, hipMemcpyHostToDevice,
                              stream));
     }
-    type = alloc<uint8_t>(g.total);
+    type = alloc<uint8_t>(g.total, "cell types");
     launch_classify(g, solid_d, rect_d, d.n_patches, patches, d.nu, ph.komega, type, stream);
     if (ph.komega) launch_fix_omega(g, patches, type, stream);
 
     for (int f = 0; f < 3; ++f)
       for (int c = 0; c < 2; ++c) {
-        vel[f][c] = alloc<V>(g.total);
-        sca[f][c] = alloc<F>(g.total);
+        vel[f][c] = alloc<V>(g.total, "velocity");
+        sca[f][c] = alloc<F>(g.total, "T/k/omega");
       }
-    p = alloc<P>(g.total);
-    nut = alloc<F>(g.total);
-    stage = alloc<double>((size_t)ncells);
+    p = alloc<P>(g.total, "pressure");
+    nut = alloc<F>(g.total, "eddy viscosity");
+    stage = alloc<double>((size_t)ncells, "host staging");
 
     // multigrid hierarchy
     lv.resize(L);
@@ -395,28 +439,28 @@ class GridT : public GridBase {
     for (int l = 0; l < L; ++l) {
       Level& v = lv[l];
       v.g = level_geom(d, l);
-      v.cls = alloc<uint8_t>(v.g.total);
-      v.full = l > 0 ? alloc<uint8_t>(v.g.total) : nullptr;
-      for (int a = 0; a < 3; ++a) v.cf[a] = a < d.dim ? alloc<float>(v.g.total) : nullptr;
+      v.cls = alloc<uint8_t>(v.g.total, "level classes");
+      v.full = l > 0 ? alloc<uint8_t>(v.g.total, "level full flags") : nullptr;
+      for (int a = 0; a < 3; ++a) v.cf[a] = a < d.dim ? alloc<float>(v.g.total, "level face coefficients") : nullptr;
       const size_t es = l == 0 ? s0 : sc;
-      for (int c = 0; c < 2; ++c) v.x[c] = alloc<uint8_t>(v.g.total * es);
-      v.b = alloc<uint8_t>(v.g.total * es);
+      for (int c = 0; c < 2; ++c) v.x[c] = alloc<uint8_t>(v.g.total * es, "level iterate");
+      v.b = alloc<uint8_t>(v.g.total * es, "level right-hand side");
       v.cur = 0;
       v.code = nullptr;
       for (int t = 0; t < TK_LEVEL_COUNT; ++t) v.tt[t] = TILE_DEFAULT;
       if (l == 0) {
         launch_level0(v.g, type, patches, v.cls, v.cf[0], v.cf[1], d.dim == 3 ? v.cf[2] : v.cf[0],
                       stream);
-        v.code = alloc<uint16_t>(v.g.total);
+        v.code = alloc<uint16_t>(v.g.total, "face codes");
         launch_face_codes(v.g, v.cls, v.cf[0], v.cf[1], d.dim == 3 ? v.cf[2] : v.cf[0], v.code,
                           stream);
       } else
         launch_coarsen(lv[l - 1].g, lv[l - 1].cls, lv[l - 1].cf, v.g, v.cls, v.cf, stream);
       if (l > 0) launch_mark_full(v, stream);
     }
-    cmap = alloc<int>(COARSE_MAX);
-    ncount = alloc<int>(1);
-    work = alloc<double>((size_t)2 * COARSE_MAX * COARSE_MAX);
+    cmap = alloc<int>(COARSE_MAX, "coarsest map");
+    ncount = alloc<int>(1, "coarsest count");
+    work = alloc<double>((size_t)2 * COARSE_MAX * COARSE_MAX, "coarsest inverse");
     launch_coarse_factor(lv[L - 1].g, lv[L - 1].cls, lv[L - 1].cf, cmap, ncount, work, COARSE_MAX,
                          stream);
     NFVM_CK(hipGetLastError());
@@ -430,24 +474,25 @@ class GridT : public GridBase {
 
     setup_bottom();
 
-    bvec = alloc<O>(g.total);
-    phi = alloc<O>(g.total);
-    r = alloc<O>(g.total);
-    pv = alloc<O>(g.total);
-    q = alloc<O>(g.total);
-    x0 = alloc<O>(g.total);
+    bvec = alloc<O>(g.total, "Poisson b");
+    phi = alloc<O>(g.total, "CG x");
+    r = alloc<O>(g.total, "CG r");
+    pv = alloc<O>(g.total, "CG p");
+    q = alloc<O>(g.total, "CG q");
+    x0 = alloc<O>(g.total, "initial guess");
     red.max_blocks = max_blocks_of(g);
-    red.partial = alloc<double>((size_t)red.max_blocks * RED_MAX_NV);
-    red.out = alloc<double>(S_COUNT);
+    red.partial = alloc<double>((size_t)red.max_blocks * RED_MAX_NV, "reduction partials");
+    red.out = alloc<double>(S_COUNT, "solver scalars");
     {
       double init[S_COUNT] = {};
       init[S_FORCED] = 1e30;
-      tune_out = alloc<double>(S_COUNT);
+      tune_out = alloc<double>(S_COUNT, "tuning scalars");
       NFVM_CK(hipMemcpyAsync(tune_out, init, sizeof init, hipMemcpyHostToDevice, stream));
       NFVM_CK(hipStreamSynchronize(stream));
     }
     NFVM_CK(hipHostGetDevicePointer((void**)&red.mirror, hs, 0));
 
+    arena_open = false;
     for (int t = 0; t < TP_COUNT; ++t) tp[t] = TILE_DEFAULT;
     if (use_autotune) autotune();
     clear_increment();
@@ -708,6 +753,9 @@ class GridT : public GridBase {
   bool nearest = false;
   // explicit stage: 1 forward Euler, 2 Heun (second stage written to rk2)
   int rk_order = 1;
+  // Algorithm 1 as printed: V(0,1) cycle of undamped sweeps with the scalar
+  // diagonal, nearest upsampling, one coarsest sweep, plain outer iteration
+  bool literal = false;
   FieldSet<V, F> rk2{};
   Bottom bot{};
 
@@ -727,7 +775,7 @@ class GridT : public GridBase {
 
   void setup_bottom() {
     bottom_top = -1;
-    if (!use_bottom || nearest || L < 3) return;
+    if (!use_bottom || nearest || literal || L < 3) return;
     const size_t limit = bottom_lds_limit<SC, C>();
     size_t bytes = al16(COARSE_MAX * sizeof(int));
     int top = L;
@@ -781,7 +829,7 @@ class GridT : public GridBase {
     bot.lds_bytes = off;
     if (off - bot.zero_bytes > bot_img_bytes) {
       bot_img_bytes = off - bot.zero_bytes;
-      bot_img = alloc<unsigned char>(bot_img_bytes);
+      bot_img = alloc<unsigned char>(bot_img_bytes, "bottom LDS image");
     }
     bot.img = bot_img;
     launch_bottom_image<C>(bot, bot_img, stream);
@@ -813,6 +861,10 @@ class GridT : public GridBase {
       prof_begin(NFVM_K_BOTTOM, bottom_bytes_moved());
       launch_bottom<SC, C>(bot, v.b, v.x[0], red.out, stream);
       prof_end(NFVM_K_BOTTOM);
+      return;
+    }
+    if (l == L - 1 && literal) {
+      smooth(l, true);  // Algorithm 1's coarsest level: one sweep from zero
       return;
     }
     if (l == L - 1) {
@@ -870,6 +922,15 @@ class GridT : public GridBase {
   // One preconditioned flexible-CG iteration (all kernels are no-ops once
   // the device-side stopping rule has fired).
   void fcg_iteration() {
+    if (literal) {
+      // Algorithm 1's outer loop: the cycle's correction added, the residual
+      // formed again
+      vcycle(0);
+      prof_begin(NFVM_K_FCG_UPDATE, (double)ncells * (2 * sizeof(O) + sizeof(S0) + 2));
+      launch_plain_update<O, S0>(lv[0], phi, bvec, red, stream);
+      prof_end(NFVM_K_FCG_UPDATE);
+      return;
+    }
     vcycle(0);
     prof_begin(NFVM_K_FCG_APPLY);
     launch_fcg_apply<O, S0>(lv[0], r, q, red, stream);
@@ -1020,6 +1081,8 @@ class GridT : public GridBase {
     for (int f = 0; f < 3; ++f) scan("vel" + std::to_string(f), vcur(f), T, sizeof(V));
     for (int f = 3; f < 6; ++f) scan("scalar" + std::to_string(f), scur(f), T, sizeof(F));
     scan("nut", nut, T, sizeof(F));
+    const std::string gb = check_guards();
+    if (!gb.empty()) m += " out-of-bounds store past: " + gb + ";";
     return m + (bad.empty() ? " arrays: all finite" : " non-finite arrays:" + bad);
   }
 
@@ -1272,7 +1335,7 @@ class GridT : public GridBase {
 
   // ---- batched iterations ----
   // grids batch together when they share precision and prolongation
-  int type_id() const override { return desc.precision + (nearest ? 16 : 0); }
+  int type_id() const override { return desc.precision + (nearest ? 16 : 0) + (literal ? 32 : 0); }
 
   void mg_desc(MgGridDesc& d) {
     memset(&d, 0, sizeof d);
@@ -1296,6 +1359,8 @@ class GridT : public GridBase {
   }
 
   std::unique_ptr<IterPlan> make_plan(const std::vector<GridBase*>& same) override {
+    if (literal)
+      throw Error{NFVM_E_INVAL, "grids in Algorithm 1's literal mode are stepped alone, not batched"};
     std::vector<MgGridDesc> ds(same.size());
     for (size_t i = 0; i < same.size(); ++i) {
       if (same[i]->type_id() != type_id() || same[i]->stream != stream)
@@ -1358,13 +1423,35 @@ class GridT : public GridBase {
         NFVM_CK(hipStreamSynchronize(stream));
       }
       rk_order = (int)v;
+    } else if (opt == NFVM_OPT_LITERAL) {
+      if (v != 0.0 && v != 1.0) throw Error{NFVM_E_INVAL, "literal mode must be 0 or 1"};
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
+      literal = v != 0.0;
+      if (literal) {
+        nu1 = 0;
+        nu2 = 1;
+        wj = 1.0;
+      } else {
+        nu1 = desc.nu1;
+        nu2 = desc.nu2;
+        wj = desc.omega_jacobi > 0 ? desc.omega_jacobi : (desc.dim == 3 ? 6.0 / 7.0 : 4.0 / 5.0);
+      }
+      for (int l = 0; l < L; ++l) {
+        Geom& gl = lv[l].g;
+        gl.sd = literal ? 2.0 / (gl.hx * gl.hx) + 2.0 / (gl.hy * gl.hy) +
+                              (desc.dim == 3 ? 2.0 / (gl.hz * gl.hz) : 0.0)
+                        : 0.0;
+        if (l + 1 < L) lv[l].nearest = nearest || literal;
+      }
+      setup_bottom();
     } else if (opt == NFVM_OPT_PROLONG) {
       if (v != 0.0 && v != 1.0)
         throw Error{NFVM_E_INVAL, "prolongation must be 0 (linear) or 1 (nearest)"};
       NFVM_CK(hipStreamSynchronize(stream));
       drop_graphs();
       nearest = v != 0.0;
-      for (int l = 0; l + 1 < L; ++l) lv[l].nearest = nearest;
+      for (int l = 0; l + 1 < L; ++l) lv[l].nearest = nearest || literal;
       setup_bottom();
     } else {
       throw Error{NFVM_E_INVAL, "unknown option"};

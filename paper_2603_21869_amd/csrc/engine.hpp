@@ -118,6 +118,8 @@ class GridBase {
   virtual void lambda2(double* out) = 0;
   virtual void set_fields(const nfvm_fields* in) = 0;
   virtual void set_option(int opt, double v) = 0;
+  // buffers whose guard zone an out-of-bounds store has written (empty: none)
+  virtual std::string check_guards() = 0;
   bool use_graphs = true;
   bool use_bottom = true;
   bool use_warm = false;

@@ -70,7 +70,7 @@ __device__ __forceinline__ void apply_code_v(const Geom& g, uint32_t cd, C xP, C
     d += (czl + czh) * ih2z;
   }
   Ax = s;
-  D = d;
+  D = g.sd > 0.0 ? (C)g.sd : d;
 }
 
 // ... at cell P, the x and y neighbours loaded here, the z neighbours given
@@ -89,7 +89,7 @@ __device__ __forceinline__ C diag_code(const Geom& g, uint32_t cd) {
           ih2z = (C)(1.0 / (g.hz * g.hz));
   C d = (face_c<C>(cd, 0) + face_c<C>(cd, 1)) * ih2x + (face_c<C>(cd, 2) + face_c<C>(cd, 3)) * ih2y;
   if (g.dim == 3) d += (face_c<C>(cd, 4) + face_c<C>(cd, 5)) * ih2z;
-  return d;
+  return g.sd > 0.0 ? (C)g.sd : d;
 }
 
 // Coarse cells whose 26 neighbours are all active and inside the box: the
@@ -130,7 +130,7 @@ __device__ __forceinline__ void apply_at(const LevelView& L, uint8_t cl, const S
       d += (C)2 * ih2z;
     }
     Ax = s;
-    D = d;
+    D = g.sd > 0.0 ? (C)g.sd : d;
     return;
   }
   const C cxl = (C)L.cf0[P], cxh = (C)L.cf0[P + 1];
@@ -144,7 +144,7 @@ __device__ __forceinline__ void apply_at(const LevelView& L, uint8_t cl, const S
     d += (czl + czh) * ih2z;
   }
   Ax = s;
-  D = d;
+  D = g.sd > 0.0 ? (C)g.sd : d;
 }
 
 // Tiles of a level for the column-walking kernels below.
@@ -305,7 +305,7 @@ __device__ __forceinline__ C diag_cls(const Geom& g, bool regular, const Nbhd<C>
     d = (n.cxl + n.cxh) * ih2x + (n.cyl + n.cyh) * ih2y;
     if (g.dim == 3) d += (n.czl + n.czh) * ih2z;
   }
-  return d;
+  return g.sd > 0.0 ? (C)g.sd : d;
 }
 
 // Diagonal of A at cell P (active), formed as diag_cls forms it, with the
@@ -315,6 +315,7 @@ __device__ __forceinline__ C diag_at(const LevelView& L, uint8_t cl, int P) {
   const Geom& g = L.g;
   const C ih2x = (C)(1.0 / (g.hx * g.hx)), ih2y = (C)(1.0 / (g.hy * g.hy)),
           ih2z = (C)(1.0 / (g.hz * g.hz));
+  if (g.sd > 0.0) return (C)g.sd;
   if (cl == MG_REGULAR) {
     C d = (C)2 * (ih2x + ih2y);
     if (g.dim == 3) d += (C)2 * ih2z;
@@ -338,7 +339,7 @@ __device__ __forceinline__ C diag_eager(const LevelView& L, uint8_t cl, int P) {
   if (g.dim == 3) dr += (C)2 * ih2z;
   C di = (fx0 + fx1) * ih2x + (fy0 + fy1) * ih2y;
   if (g.dim == 3) di += (fz0 + fz1) * ih2z;
-  return cl == MG_REGULAR ? dr : di;
+  return g.sd > 0.0 ? (C)g.sd : (cl == MG_REGULAR ? dr : di);
 }
 
 // The first sweep from zero of a coarse cell whose right-hand side has just
@@ -1688,6 +1689,73 @@ void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const RedBuf& re
     NFVM_LAUNCH((k_fcg_update<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
   if (fin) NFVM_LAUNCH_FIN(k_fin_update, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
+
+// ---- Algorithm 1's plain iteration: x += z, then r = b - A x --------------------
+// (the outer loop of the literal mode; the residual is formed again every
+// iteration, and its norm goes through the CG update's finaliser, which
+// counts the iteration and applies the stopping rule)
+template <class O, class S>
+__global__ __launch_bounds__(MBS) void k_plain_correct(Geom g, Tiles T, const uint16_t* __restrict__ code,
+                                                       O* __restrict__ x, const S* __restrict__ z,
+                                                       const double* __restrict__ ctl) {
+  if (ctl[S_DONE] != 0.0) return;
+  int tx, ty, tz;
+  if (!tile_of(T, tx, ty, tz)) return;
+  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+  for (int k = k0; k < k1; ++k) {
+    const int P = g.idx(i, j, k);
+    if (code[P] != FACE_CODE_INACTIVE) x[P] += St<S, O>::ld(z + P);
+  }
+}
+
+template <class O, class S>
+__global__ __launch_bounds__(MBS) void k_plain_residual(LevelView L, Tiles T, const O* __restrict__ x,
+                                                        const O* __restrict__ b, S* __restrict__ b0,
+                                                        RedBuf red) {
+  if (red.out[S_DONE] != 0.0) return;  // (uniform: the finaliser returns too)
+  int tx, ty, tz;
+  double rr = 0.0;
+  if (tile_of(T, tx, ty, tz)) {
+    const Geom& g = L.g;
+    const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+    if (i < g.nx && j < g.ny) {
+      const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+      for (int k = k0; k < k1; ++k) {
+        const int P = g.idx(i, j, k);
+        const uint32_t cd = L.code[P];
+        if (cd == FACE_CODE_INACTIVE) continue;
+        const O xP = x[P];
+        const O xm = g.dim == 3 ? x[P - g.sxy] : (O)0, xp = g.dim == 3 ? x[P + g.sxy] : (O)0;
+        O Ax, D;
+        apply_code<O, O>(g, cd, x, P, xP, xm, xp, Ax, D);
+        const O rP = b[P] - Ax;
+        St<S, O>::st(b0 + P, rP);
+        rr += (double)rP * (double)rP;
+      }
+    }
+  }
+  double vv[1] = {rr};
+  block_partial<1, R_SUM, MBS>(vv, red);
+}
+
+template <class O, class S>
+void launch_plain_update(const Level& l0, O* x, const O* b, const RedBuf& red, hipStream_t s) {
+  const Tiles T = lvl_tiles(l0, TK_UPDATE);
+  check_partials(red, T.grid, 1);
+  NFVM_LAUNCH((k_plain_correct<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, l0.g, T, l0.code, x,
+              (const S*)l0.x[l0.cur], red.out);
+  hipLaunchKernelGGL((k_plain_residual<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, view(l0), T, x,
+                     b, (S*)l0.b, red);
+  NFVM_LAUNCH_FIN(k_fin_update, dim3(1), dim3(FIN), 0, s, FinArgs{red, T.grid});
+}
+template void launch_plain_update<double, double>(const Level&, double*, const double*,
+                                                  const RedBuf&, hipStream_t);
+template void launch_plain_update<float, float>(const Level&, float*, const float*, const RedBuf&,
+                                                hipStream_t);
+template void launch_plain_update<double, float>(const Level&, double*, const double*,
+                                                 const RedBuf&, hipStream_t);
 
 // ---- deterministic finalisation of block partials ---------------------------------
 template <int NV, int OP>

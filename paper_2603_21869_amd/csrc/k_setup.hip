@@ -23,6 +23,7 @@ Geom make_geom(int dim, int nx, int ny, int nz, double hx, double hy, double hz)
   g.hx = hx;
   g.hy = hy;
   g.hz = hz;
+  g.sd = 0.0;
   return g;
 }
 

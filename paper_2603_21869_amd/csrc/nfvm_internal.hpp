@@ -84,6 +84,9 @@ struct Geom {
   int sx, sxy, gz;
   int off, total;
   double hx, hy, hz;
+  // > 0: the Jacobi sweeps of this multigrid level divide by this scalar
+  // (Algorithm 1's reading of eq. jacobi_pc) instead of the cell's diagonal
+  double sd;
   __host__ __device__ inline int idx(int i, int j, int k) const {
     return off + k * sxy + j * sx + i;
   }
@@ -203,6 +206,12 @@ inline void check_partials(const RedBuf& red, int nblocks, int nv) {
 // red.out[slot0] (and red.out[slot1] when nv == 2).
 void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, int slot1,
                      hipStream_t s);
+// Algorithm 1's outer iteration on level 0: x += z (z the level's current
+// iterate), then r = b - A x rounded into the level's right-hand side, with
+// ||r||^2 through the CG update's finaliser (iteration count, stopping rule).
+template <class O, class S>
+void launch_plain_update(const Level& l0, O* x, const O* b, const RedBuf& red, hipStream_t s);
+
 void launch_classify(const Geom& g, const uint8_t* solid_dense, const int* patch_rect,
                      int n_patches_user, DevPatch* patches, double nu, int komega,
                      uint8_t* type, hipStream_t s);

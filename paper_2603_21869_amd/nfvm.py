@@ -283,6 +283,7 @@ NFVM_OPT_GRAPHS, NFVM_OPT_PREDICT, NFVM_OPT_BOTTOM, NFVM_OPT_AUTOTUNE = 0, 1, 2,
 NFVM_OPT_WARM_START = 4
 NFVM_OPT_PROLONG = 5
 NFVM_OPT_RK_ORDER = 6
+NFVM_OPT_LITERAL = 7
 
 
 def nfvm_tuning_table():
@@ -348,6 +349,8 @@ class Grid:
             nfvm_set_option(self.h, NFVM_OPT_PROLONG, float(case.prolong))
         if getattr(case, "rk_order", 1) != 1:
             nfvm_set_option(self.h, NFVM_OPT_RK_ORDER, float(case.rk_order))
+        if getattr(case, "literal", 0):
+            nfvm_set_option(self.h, NFVM_OPT_LITERAL, 1.0)
 
     def step(self, n: int, allow=(NFVM_OK,)):
         return nfvm_step(self.h, n, allow)

@@ -337,6 +337,43 @@ def test_nearest_prolongation_matches_oracle(nf, oracle, name, case):
             check_fields(c2, out, ref, TOL[prec], tag=f"nu={nu} prec={prec} cycles={cyc}")
 
 
+@pytest.mark.parametrize("name,case", _nearest_cases(), ids=[c[0] for c in _nearest_cases()])
+def test_literal_algorithm_1_matches_oracle(nf, oracle, name, case):
+    """NFVM_OPT_LITERAL = 1 (Algorithm 1 as printed: V(0,1) of undamped
+    sweeps with the scalar diagonal, nearest upsampling, one coarsest sweep,
+    plain outer iteration): forced iterations of the pressure solve and a time
+    step held to them match the oracle's literal mode in FP64.  Whether the
+    plain iteration converges is the method's own behaviour: both sides
+    report the same residual after the same iterations."""
+    case = case.copy(literal=1, precision=C.PREC_FP64)
+    m = fluid(case)
+    g = nf.Grid(case)
+    b = np.random.default_rng(3).standard_normal(g.shape) * m
+    x, st, s = g.mg_solve(b, forced_cycles=6, allow=(0, nf.NFVM_E_NOTCONV, nf.NFVM_E_DIVERGED))
+    g.close()
+    xr, cyc, rel, sr = oracle.MG(case).solve(b, forced=6)
+    err = np.abs(x - xr)[m].max() / np.abs(xr[m]).max()
+    print(f"[literal] {name} 6 iterations: rel residual {st['rel_residual']:.4e} "
+          f"(oracle {rel:.4e}) max err {err:.2e}", flush=True)
+    assert st["cycles"] == 6 and err <= 1e-12
+    assert st["rel_residual"] == pytest.approx(rel, rel=1e-9)
+    g = nf.Grid(case, max_cycles=3)
+    s, stats = g.step(2, allow=(0, nf.NFVM_E_NOTCONV))
+    out = g.fields()
+    with pytest.raises(nf.NfvmError) as e:  # such grids step alone
+        g2 = nf.Grid(case.copy(literal=0))
+        try:
+            nf.nfvm_step_batch([g.h, g2.h], 1)
+        finally:
+            g2.close()
+    assert e.value.status == nf.NFVM_E_INVAL
+    g.close()
+    cyc = [x["cycles"] for x in stats]
+    assert cyc == [3, 3]
+    ref, _, _ = oracle.step(case, 2, forced_cycles=cyc)
+    check_fields(case, out, ref, 1e-10, tag=f"[literal] {name} step")
+
+
 def test_nearest_prolongation_batches_apart(nf):
     """Grids with nearest and with linear prolongation stepped in one batch
     keep their own V-cycles: each ends bitwise equal to its run alone."""
