@@ -171,6 +171,23 @@ nfvm_status nfvm_mg_solve_device(nfvm_grid_t grid, const double* b_dev, double* 
                                  double tol, int32_t max_cycles, int32_t forced_cycles,
                                  nfvm_step_stats* stats);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: tight serving loops, harnesses that forbid allocation):
+ * nfvm_mg_solve_device without any device allocation.  The solve's
+ * reduction partials and scalars live in a fixed 2 MiB device array of the
+ * library (one copy per device, held until the process ends) instead of the
+ * grid's own buffers; the kernels and their order are nfvm_mg_solve_device's,
+ * so the results are the same.  Arguments, layout and errors as
+ * nfvm_mg_solve_device; NFVM_E_INVAL if the grid's reductions need more
+ * partials than the array holds (about 87,000 workgroups; grids up to the
+ * 1024 x 512 x 256 room with autotuned tiles fit).  Every call on a device
+ * shares its array: calls that overlap on one device (two host threads, or
+ * two streams in flight) race and must not be made.  The call waits for the
+ * grid's stream (it cannot be captured into a graph). */
+nfvm_status nfvm_mg_solve_device_noalloc(nfvm_grid_t grid, const double* b_dev, double* x_dev,
+                                         double tol, int32_t max_cycles, int32_t forced_cycles,
+                                         nfvm_step_stats* stats);
+
 /* Copy the cell-centred fields u, v, w, p, T, k, omega (the tensors of
  * Sec. 2.2, one value per cell) to host FP64 arrays, [nz][ny][nx] (all seven
  * pointers required; waits for the grid's stream).  Errors: NFVM_E_INVAL for

@@ -1130,6 +1130,38 @@ class GridT : public GridBase {
     *status = st;
   }
 
+  void mg_solve_scratch(const double* b_dev, double* x_dev, double tol_, int maxc, int forced,
+                        nfvm_step_stats* stt, nfvm_status* status, double* scratch,
+                        size_t n_doubles) override {
+    // scalars first (32 doubles keep the partials 256-byte aligned)
+    const size_t head = 32;
+    const size_t cap = n_doubles > head ? (n_doubles - head) / RED_MAX_NV : 0;
+    const int need = fcg_max_blocks(lv[0]);
+    if ((size_t)need > cap)
+      throw Error{NFVM_E_INVAL, "the solve's reductions need " + std::to_string(need) +
+                                    " workgroups of partials; the scratch holds " +
+                                    std::to_string(cap)};
+    RedBuf s = red;
+    s.out = scratch;
+    s.partial = scratch + head;
+    s.max_blocks = (int)std::min<size_t>(cap, 1u << 30);
+    launch_fill_f64(s.out, (int)head, 0.0, stream);
+    NFVM_CK(hipGetLastError());
+    const RedBuf own = red;
+    const bool graphs = use_graphs;
+    red = s;
+    use_graphs = false;  // the captured iteration refers to the grid's own buffers
+    try {
+      mg_solve(b_dev, x_dev, tol_, maxc, forced, stt, status);
+    } catch (...) {
+      red = own;
+      use_graphs = graphs;
+      throw;
+    }
+    red = own;
+    use_graphs = graphs;
+  }
+
   void swap(int f) { fcur[f] ^= 1; }
 
   // destruction over dt/2, explicit step, Poisson right-hand side, CG start

@@ -114,6 +114,12 @@ class GridBase {
 
   virtual void mg_solve(const double* b_dev, double* x_dev, double tol, int max_cycles, int forced,
                         nfvm_step_stats* st, nfvm_status* status) = 0;
+  // The same solve with its reduction partials and scalars in the n_doubles
+  // doubles of device memory at scratch (256-byte aligned) instead of the
+  // grid's own, launched without the captured graphs; allocates nothing.
+  virtual void mg_solve_scratch(const double* b_dev, double* x_dev, double tol, int max_cycles,
+                                int forced, nfvm_step_stats* st, nfvm_status* status,
+                                double* scratch, size_t n_doubles) = 0;
   virtual void get_fields(nfvm_fields* out) = 0;
   virtual void lambda2(double* out) = 0;
   virtual void set_fields(const nfvm_fields* in) = 0;

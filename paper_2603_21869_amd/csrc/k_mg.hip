@@ -1757,6 +1757,25 @@ template void launch_plain_update<float, float>(const Level&, float*, const floa
 template void launch_plain_update<double, float>(const Level&, double*, const double*,
                                                  const RedBuf&, hipStream_t);
 
+int fcg_max_blocks(const Level& l0) {
+  const Tiles ts = lvl_tiles(l0, TK_START);
+  const Tiles ta = cg_quad(l0) ? make_tiles(l0.g.nx / 4, l0.g.ny, l0.g.nz, l0.tt[TK_APPLY])
+                               : lvl_tiles(l0, TK_APPLY);
+  const Tiles tu = cg_quad(l0) ? make_tiles(l0.g.nx / 4, l0.g.ny, l0.g.nz, l0.tt[TK_UPDATE])
+                               : lvl_tiles(l0, TK_UPDATE);
+  return std::max(ts.grid, std::max(ta.grid, tu.grid));
+}
+
+__global__ void k_fill_f64(double* __restrict__ x, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+void launch_fill_f64(double* x, int n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3((n + 255) / 256), dim3(256), 0, s, x, n, v);
+}
+
 // ---- deterministic finalisation of block partials ---------------------------------
 template <int NV, int OP>
 __global__ __launch_bounds__(256) void k_finalize(RedBuf red, int nb, int s0, int s1) {

@@ -212,6 +212,12 @@ void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, 
 template <class O, class S>
 void launch_plain_update(const Level& l0, O* x, const O* b, const RedBuf& red, hipStream_t s);
 
+// Workgroups of the largest reducing launch of one pressure solve on level
+// 0 (CG start, apply and update with the level's current tiles).
+int fcg_max_blocks(const Level& l0);
+// x[0 .. n) = v on stream s (a kernel, so that it may be captured).
+void launch_fill_f64(double* x, int n, double v, hipStream_t s);
+
 void launch_classify(const Geom& g, const uint8_t* solid_dense, const int* patch_rect,
                      int n_patches_user, DevPatch* patches, double nu, int komega,
                      uint8_t* type, hipStream_t s);
