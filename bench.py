@@ -466,11 +466,18 @@ def main():
             c2 = make_case(args.workload, pv, tv).copy(**kw)
             print(f"[bench] variant {vname}", file=sys.stderr, flush=True)
             s2, st2, _ = run_gpu(c2, k2, 1, stream, warm_start=warm)
-            variants[vname] = dict(value=round(c2.ncells * k2 / s2 / 1e6, 2),
-                                   ms_per_step=round(s2 / k2 * 1e3, 3), tol=tv,
-                                   mean_cycles=sum(x["cycles"] for x in st2) / len(st2),
-                                   statuses=sorted({x["status"] for x in st2}),
-                                   last_rel_residual=st2[-1]["rel_residual"])
+            bad = [i for i, x in enumerate(st2) if x["status"] != 0]
+            if bad:
+                # a failed solve ends the run: no throughput, where and how
+                x = st2[bad[0]]
+                variants[vname] = dict(value=None, tol=tv, failed_at_step=bad[0] + 1,
+                                       status=x["status"], cycles=x["cycles"],
+                                       rel_residual=x["rel_residual"])
+            else:
+                variants[vname] = dict(value=round(c2.ncells * k2 / s2 / 1e6, 2),
+                                       ms_per_step=round(s2 / k2 * 1e3, 3), tol=tv,
+                                       mean_cycles=sum(x["cycles"] for x in st2) / len(st2),
+                                       last_rel_residual=st2[-1]["rel_residual"])
             del c2
     traffic, traffic_src = measured_traffic(args.workload, args.precision, dom)
     out = {

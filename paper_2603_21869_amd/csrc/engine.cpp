@@ -126,7 +126,7 @@ size_t footprint_bytes(const nfvm_grid_desc& d) {
   const size_t T = (size_t)g.total, N = (size_t)g.cells();
   size_t b = 0;
   b += 6 * T * V + 7 * T * F + T * P + T;           // fields (ping-pong), nu_t, pressure, types
-  b += 5 * T * O;                                   // b, phi, r, p, q
+  b += 3 * T * O + 2 * T * S0;                      // b, phi, r; two directions
   b += T * O;                                       // initial guess of the solve call
   b += 8 * N + (d.solid_mask ? N : 0);              // dense staging, mask
   for (int l = 0; l < d.n_levels; ++l) {
@@ -254,7 +254,10 @@ class GridT : public GridBase {
   P* p = nullptr;
   F* nut = nullptr;  // eddy viscosity of the stored k, omega (written by the first half step)
   std::vector<Level> lv;
-  O *bvec = nullptr, *phi = nullptr, *r = nullptr, *pv = nullptr, *q = nullptr, *x0 = nullptr;
+  O *bvec = nullptr, *phi = nullptr, *r = nullptr, *x0 = nullptr;
+  // the two buffers of the CG search direction (level-0 storage type), which
+  // alternate between iterations
+  void* dir[2] = {nullptr, nullptr};
   double* stage = nullptr;
   RedBuf red{};
   int* cmap = nullptr;
@@ -300,8 +303,11 @@ class GridT : public GridBase {
     NFVM_CK(hipStreamSynchronize(stream));
     std::vector<unsigned char> h(GUARD);
     for (const auto& gr : guards) {
-      NFVM_CK(hipMemcpy(h.data(), (unsigned char*)arena.p + gr.first, GUARD,
-                        hipMemcpyDeviceToHost));
+      // (on the grid's stream: a copy on the legacy stream is refused while
+      // another thread, a serving lane, captures a graph)
+      NFVM_CK(hipMemcpyAsync(h.data(), (unsigned char*)arena.p + gr.first, GUARD,
+                             hipMemcpyDeviceToHost, stream));
+      NFVM_CK(hipStreamSynchronize(stream));
       for (unsigned char c : h)
         if (c) {
           bad += (bad.empty() ? "" : ", ") + gr.second;
@@ -362,9 +368,10 @@ class GridT : public GridBase {
       const double nc = L > 1 ? (double)level_geom(d, 1).cells() : 0.0;
       // level 0 reads a 2-byte face code per cell; the restriction also
       // writes the coarse level's first sweep, the CG update the level-0 one
-      // (V-cycles with nu1 + nu2 even); the CG passes read z, r, q (apply)
-      // and z, p, q, x, r (update, which forms A z again instead of reading
-      // a stored one)
+      // (V-cycles with nu1 + nu2 even); the CG passes read z, r and the
+      // previous direction (apply), and z, the previous direction, x, r
+      // (update, which writes the new direction and forms its image A p
+      // from it instead of storing one)
       prof_bytes[NFVM_K_SMOOTH0] = N * (3 * s0 + 2);
       prof_bytes[NFVM_K_SMOOTH0_ZERO] = N * (2 * s0 + 2);
       prof_bytes[NFVM_K_RESTRICT0] = N * (2 * s0 + 2) + nc * (2 * scs + 1);
@@ -373,8 +380,8 @@ class GridT : public GridBase {
       prof_bytes[NFVM_K_DESTROY] = N * (3 * sv + 5 * sf + 1);  // (the first half step)
       prof_bytes[NFVM_K_RHS] = N * (3 * sv + so + 1);
       prof_bytes[NFVM_K_PROJECT] = N * (6 * sv + 2 * sp + so + 1);
-      prof_bytes[NFVM_K_FCG_APPLY] = N * (s0 + 2 * so + 2);
-      prof_bytes[NFVM_K_FCG_UPDATE] = N * (3 * s0 + 8 * so + 2);
+      prof_bytes[NFVM_K_FCG_APPLY] = N * (2 * s0 + so + 2);
+      prof_bytes[NFVM_K_FCG_UPDATE] = N * (5 * s0 + 4 * so + 2);
     }
     NFVM_CK(hipEventCreate(&ev0));
     NFVM_CK(hipEventCreate(&ev1));
@@ -477,8 +484,8 @@ class GridT : public GridBase {
     bvec = alloc<O>(g.total, "Poisson b");
     phi = alloc<O>(g.total, "CG x");
     r = alloc<O>(g.total, "CG r");
-    pv = alloc<O>(g.total, "CG p");
-    q = alloc<O>(g.total, "CG q");
+    dir[0] = alloc<S0>(g.total, "CG direction (even iterations)");
+    dir[1] = alloc<S0>(g.total, "CG direction (odd iterations)");
     x0 = alloc<O>(g.total, "initial guess");
     red.max_blocks = max_blocks_of(g);
     red.partial = alloc<double>((size_t)red.max_blocks * RED_MAX_NV, "reduction partials");
@@ -600,11 +607,11 @@ class GridT : public GridBase {
         tr.mirror = nullptr;
         v.tt[TK_APPLY] = tune_one(TK_APPLY, v.g, [&](int tt) {
           v.tt[TK_APPLY] = tt;
-          launch_fcg_apply<O, S0>(v, r, q, tr, stream, true);
+          launch_fcg_apply<O, S0>(v, r, dir, tr, stream, true);
         });
         v.tt[TK_UPDATE] = tune_one(TK_UPDATE, v.g, [&](int tt) {
           v.tt[TK_UPDATE] = tt;
-          launch_fcg_update<O, S0>(v, phi, r, pv, q, tr, stream, true, zero0(), wj);
+          launch_fcg_update<O, S0>(v, phi, r, dir, tr, stream, true, zero0(), wj);
         });
       } else {
         v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + 1000, v.g, [&](int tt) {
@@ -629,7 +636,8 @@ class GridT : public GridBase {
     NFVM_CK(hipGetLastError());
     // leave every buffer the tuning touched as a fresh grid has it
     const size_t ob = (size_t)g.total * sizeof(O);
-    for (O* bufp : {bvec, phi, r, pv, q, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
+    for (O* bufp : {bvec, phi, r, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
+    for (void* d : dir) NFVM_CK(hipMemsetAsync(d, 0, (size_t)g.total * sizeof(S0), stream));
     for (int l = 0; l < L; ++l) {
       const size_t es = (size_t)lv[l].g.total * (l == 0 ? sizeof(S0) : sizeof(SC));
       for (int c = 0; c < 2; ++c) NFVM_CK(hipMemsetAsync(lv[l].x[c], 0, es, stream));
@@ -933,10 +941,10 @@ class GridT : public GridBase {
     }
     vcycle(0);
     prof_begin(NFVM_K_FCG_APPLY);
-    launch_fcg_apply<O, S0>(lv[0], r, q, red, stream);
+    launch_fcg_apply<O, S0>(lv[0], r, dir, red, stream);
     prof_end(NFVM_K_FCG_APPLY);
     prof_begin(NFVM_K_FCG_UPDATE);
-    launch_fcg_update<O, S0>(lv[0], phi, r, pv, q, red, stream, true, zero0(), wj);
+    launch_fcg_update<O, S0>(lv[0], phi, r, dir, red, stream, true, zero0(), wj);
     prof_end(NFVM_K_FCG_UPDATE);
   }
 
@@ -1068,8 +1076,8 @@ class GridT : public GridBase {
     scan("b", bvec, T, sizeof(O));
     scan("phi", phi, T, sizeof(O));
     scan("r", r, T, sizeof(O));
-    scan("p", pv, T, sizeof(O));
-    scan("q", q, T, sizeof(O));
+    scan("p (even)", dir[0], T, sizeof(S0));
+    scan("p (odd)", dir[1], T, sizeof(S0));
     for (int l = 0; l < L; ++l) {
       const int es = l == 0 ? (int)sizeof(S0) : (int)sizeof(SC);
       const size_t n = (size_t)lv[l].g.total;
@@ -1386,8 +1394,8 @@ class GridT : public GridBase {
     d.red = red;
     d.x = phi;
     d.r = r;
-    d.p = pv;
-    d.q = q;
+    d.dir[0] = dir[0];
+    d.dir[1] = dir[1];
   }
 
   std::unique_ptr<IterPlan> make_plan(const std::vector<GridBase*>& same) override {

@@ -1332,19 +1332,45 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                        (double)max_cycles, (double)forced);
 }
 
-// The dot products (z, r), (z, q_prev), (z, w) with w = A z (not stored).
+// The search directions live in the level-0 storage type S, in two buffers
+// that alternate between iterations: iteration it (the count of finished
+// iterations, S_ITER) reads the previous direction from p[it & 1] and writes
+// its own to p[(it + 1) & 1], so the update pass can read the previous
+// direction at a cell's neighbours while other workgroups write the new one.
+// The parity comes from the device-side count, so a captured iteration and a
+// batch whose grids are at different iterations need no host bookkeeping.
+template <class S>
+__device__ __forceinline__ const S* dir_prev(S* const (&p)[2], const double* ctl) {
+  return p[(int)ctl[S_ITER] & 1];
+}
+template <class S>
+__device__ __forceinline__ S* dir_next(S* const (&p)[2], const double* ctl) {
+  return p[((int)ctl[S_ITER] + 1) & 1];
+}
+
+// The new direction at one cell, p = z + beta p_prev rounded to the storage
+// type (as one fused multiply-add, so that every thread that forms it, the
+// cell's own and its neighbours', gets the same stored value).
+template <class O, class S>
+__device__ __forceinline__ S dir_at(S z, S pprev, O be) {
+  S v;
+  St<S, O>::st(&v, fma(be, St<S, O>::ld(&pprev), St<S, O>::ld(&z)));
+  return v;
+}
+
+// The dot products (z, r), (w, p_prev), (z, w) with w = A z (not stored).
+// A is symmetric, so (w, p_prev) = (z, A p_prev) = (z, q_prev) with q_prev
+// the previous direction's image, which is therefore not stored either.
 // With beta = -(z, q_prev) / (p_prev, q_prev), the new direction
-// p = z + beta p_prev has A p = w + beta q_prev and (p, A p) = (z, w) +
-// 2 beta (z, q_prev) + beta^2 (p_prev, q_prev), so the operator applied to
-// z (here, and again in the update pass) serves both the direction and the
-// step length.
+// p = z + beta p_prev has (p, A p) = (z, w) + 2 beta (z, q_prev) +
+// beta^2 (p_prev, q_prev): the step length follows without A p.
 template <class O, class S>
 struct ApplyArgs {
   LevelView L;
   Tiles T;
   const S* z;
   const O* r;
-  const O* q;
+  S* p[2];
   RedBuf red;
 };
 
@@ -1356,7 +1382,8 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<O, S>& a, const TileC
   const LevelView& L = a.L;
   const S* __restrict__ z = a.z;
   const O* __restrict__ r = a.r;
-  const O* __restrict__ q = a.q;
+  const bool first = red.out[S_ITER] == 0.0;
+  const S* __restrict__ pp = dir_prev<S>(a.p, red.out);
   double zr = 0.0, zq = 0.0, zw = 0.0;
   if (valid) {
     const Geom& g = L.g;
@@ -1373,7 +1400,7 @@ __device__ __forceinline__ void apply_body(const ApplyArgs<O, S>& a, const TileC
           O Az, D;
           apply_code<S, O>(g, cd, z, P, zc, zm, zp, Az, D);
           zr += (double)zc * (double)r[P];
-          zq += (double)zc * (double)q[P];
+          if (!first) zq += (double)Az * (double)St<S, O>::ld(pp + P);
           zw += (double)zc * (double)Az;
         }
         zm = zc;
@@ -1399,7 +1426,8 @@ __device__ __forceinline__ void apply4_body(const ApplyArgs<O, S>& a, const Tile
   const LevelView& L = a.L;
   const S* __restrict__ z = a.z;
   const O* __restrict__ r = a.r;
-  const O* __restrict__ q = a.q;
+  const bool first = red.out[S_ITER] == 0.0;
+  const S* __restrict__ pp = dir_prev<S>(a.p, red.out);
   double zr = 0.0, zq = 0.0, zw = 0.0;
   if (valid) {
     const Geom& g = L.g;
@@ -1415,7 +1443,8 @@ __device__ __forceinline__ void apply4_body(const ApplyArgs<O, S>& a, const Tile
         const S4 zs = *(const S4*)(z + P - g.sx), zn = *(const S4*)(z + P + g.sx);
         const O zl = St<S, O>::ld(z + P - 1), zh = St<S, O>::ld(z + P + 4);
         const uint2 cw = *(const uint2*)(L.code + P);
-        const O4 rv = *(const O4*)(r + P), qv = *(const O4*)(q + P);
+        const O4 rv = *(const O4*)(r + P);
+        const S4 pv = first ? S4(0) : *(const S4*)(pp + P);
         const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
         const O zv[6] = {zl, (O)zc[0], (O)zc[1], (O)zc[2], (O)zc[3], zh};
 #pragma unroll
@@ -1425,7 +1454,7 @@ __device__ __forceinline__ void apply4_body(const ApplyArgs<O, S>& a, const Tile
             apply_code_v<O>(g, cd[e], zv[e + 1], zv[e], zv[e + 2], (O)zs[e], (O)zn[e], (O)zm[e],
                             (O)zp[e], Az, D);
             zr += (double)zv[e + 1] * (double)rv[e];
-            zq += (double)zv[e + 1] * (double)qv[e];
+            zq += (double)Az * (double)(O)pv[e];
             zw += (double)zv[e + 1] * (double)Az;
           }
         }
@@ -1488,16 +1517,16 @@ __global__ __launch_bounds__(FIN) void k_fin_apply_batch(Pack<FinArgs> f) {
 }
 
 template <class O, class S>
-ApplyArgs<O, S> apply_args(const Level& l0, const O* r, const O* q, const RedBuf& red) {
+ApplyArgs<O, S> apply_args(const Level& l0, const O* r, void* const* dir, const RedBuf& red) {
   const Tiles T = cg_quad(l0) ? make_tiles(l0.g.nx / 4, l0.g.ny, l0.g.nz, l0.tt[TK_APPLY])
                               : lvl_tiles(l0, TK_APPLY);
-  return ApplyArgs<O, S>{view(l0), T, (const S*)l0.x[l0.cur], r, q, red};
+  return ApplyArgs<O, S>{view(l0), T, (const S*)l0.x[l0.cur], r, {(S*)dir[0], (S*)dir[1]}, red};
 }
 
 template <class O, class S>
-void launch_fcg_apply(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
-                      bool fin) {
-  const ApplyArgs<O, S> a = apply_args<O, S>(l0, r, q, red);
+void launch_fcg_apply(const Level& l0, const O* r, void* const* dir, const RedBuf& red,
+                      hipStream_t s, bool fin) {
+  const ApplyArgs<O, S> a = apply_args<O, S>(l0, r, dir, red);
   check_partials(red, a.T.grid, 3);
   if (cg_quad(l0))
     NFVM_LAUNCH((k_fcg_apply4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
@@ -1506,19 +1535,19 @@ void launch_fcg_apply(const Level& l0, const O* r, const O* q, const RedBuf& red
   if (fin) NFVM_LAUNCH_FIN(k_fin_apply, dim3(1), dim3(FIN), 0, s, FinArgs{red, a.T.grid});
 }
 
-// p = z + beta p, q = w + beta q, x += alpha p, r -= alpha q, ||r||^2, the
-// next V-cycle's right-hand side (and first level-0 sweep).  w = A z is
-// formed again from z with the apply pass's operator (the same arithmetic on
-// the same values, so the same w) instead of being stored there and read
-// here: 16 bytes per cell less traffic for a few cached neighbour loads.
+// p = z + beta p_prev (stored in S), x += alpha p, r -= alpha A p, ||r||^2,
+// the next V-cycle's right-hand side (and first level-0 sweep).  A p is
+// formed from the stored p, which every thread forms at a cell's neighbours
+// as the cell's own thread does (dir_at), so x and r take the same direction
+// and r stays b - A x up to the FP64 rounding of the updates whatever the
+// storage type of p.  No image q = A p is stored or read.
 template <class O, class S>
 struct UpdateArgs {
   LevelView L;
   Tiles T;
   O* x;
   O* r;
-  O* p;
-  O* q;
+  S* p[2];
   const S* z;
   S* b0;
   S* z0;
@@ -1534,12 +1563,14 @@ __device__ __forceinline__ void update_body(const UpdateArgs<O, S>& A, const Til
   const LevelView& L = A.L;
   O* __restrict__ x = A.x;
   O* __restrict__ r = A.r;
-  O* __restrict__ p = A.p;
-  O* __restrict__ q = A.q;
+  const S* __restrict__ pp = dir_prev<S>(A.p, red.out);
+  S* __restrict__ pn = dir_next<S>(A.p, red.out);
   const S* __restrict__ z = A.z;
   const bool first = red.out[S_ITER] == 0.0;
   const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA];
   double rr = 0.0;
+  // the new direction at padded index Q
+  auto dir = [&](int Q) -> S { return first ? z[Q] : dir_at<O, S>(z[Q], pp[Q], be); };
   if (valid) {
     const Geom& g = L.g;
     const int i = c.tx * MBX + threadIdx.x, j = c.ty * MBY + threadIdx.y;
@@ -1547,22 +1578,20 @@ __device__ __forceinline__ void update_body(const UpdateArgs<O, S>& A, const Til
       const bool d3 = g.dim == 3;
       const int k0 = c.tz * A.T.cz, k1 = min(g.nz, k0 + A.T.cz);
       int P = g.idx(i, j, k0);
-      O zm = d3 ? St<S, O>::ld(z + P - g.sxy) : (O)0, zc = St<S, O>::ld(z + P);
+      S qm = d3 ? dir(P - g.sxy) : S(0), qc = dir(P);
       for (int k = k0; k < k1; ++k, P += g.sxy) {
-        const O zp = d3 ? St<S, O>::ld(z + P + g.sxy) : (O)0;
+        const S qp = d3 ? dir(P + g.sxy) : S(0);
         const uint32_t cd = L.code[P];
-        const O zP = zc, zB = zm;
-        zm = zc;
-        zc = zp;
+        const S qP = qc, qB = qm;
+        qm = qc;
+        qc = qp;
+        pn[P] = qP;
         if (cd == FACE_CODE_INACTIVE) continue;
-        O wP, D;
-        apply_code<S, O>(g, cd, z, P, zP, zB, zp, wP, D);
-        const O pP = first ? zP : zP + be * p[P];
-        const O qP = first ? wP : wP + be * q[P];
-        p[P] = pP;
-        q[P] = qP;
-        x[P] += a * pP;
-        const O rP = r[P] - a * qP;
+        O Ap, D;
+        apply_code_v<O>(g, cd, (O)qP, (O)dir(P - 1), (O)dir(P + 1), (O)dir(P - g.sx),
+                        (O)dir(P + g.sx), (O)qB, (O)qp, Ap, D);
+        x[P] += a * (O)qP;
+        const O rP = r[P] - a * Ap;
         r[P] = rP;
         zero_sweep<O, S>(L, P, cd, rP, A.b0, A.z0, A.wj);
         rr += (double)rP * (double)rP;
@@ -1576,8 +1605,9 @@ NFVM_TILE_KERNELS(k_fcg_update, update_body, UpdateArgs, (O, S), (class O, class
                   true)
 
 // The same over four consecutive x cells per thread (nx a multiple of 4);
-// inactive cells keep their values (p, q, x, r written back as read; the
-// right-hand side and first sweep written as 0, the value they hold).
+// inactive cells keep x and r (written back as read), their direction is
+// stored as formed (z and the previous direction are 0 there) and the
+// right-hand side and first sweep written as 0, the value they hold.
 template <class O, class S>
 __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const TileCtx& c,
                                              bool valid) {
@@ -1588,12 +1618,25 @@ __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const Ti
   const LevelView& L = A.L;
   O* __restrict__ x = A.x;
   O* __restrict__ r = A.r;
-  O* __restrict__ p = A.p;
-  O* __restrict__ q = A.q;
+  const S* __restrict__ pp = dir_prev<S>(A.p, red.out);
+  S* __restrict__ pn = dir_next<S>(A.p, red.out);
   const S* __restrict__ z = A.z;
   const bool first = red.out[S_ITER] == 0.0;
   const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA];
   double rr = 0.0;
+  // the new direction of four cells from index Q, and of one cell
+  auto dir4 = [&](int Q) -> S4 {
+    const S4 zq = *(const S4*)(z + Q);
+    if (first) return zq;
+    const S4 pq = *(const S4*)(pp + Q);
+    S4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = dir_at<O, S>(zq[e], pq[e], be);
+    return v;
+  };
+  auto dir1 = [&](int Q) -> O {
+    return (O)(first ? z[Q] : dir_at<O, S>(z[Q], pp[Q], be));
+  };
   if (valid) {
     const Geom& g = L.g;
     const int i0 = 4 * (c.tx * MBX + threadIdx.x), j = c.ty * MBY + threadIdx.y;
@@ -1601,32 +1644,26 @@ __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const Ti
       const bool d3 = g.dim == 3;
       const int k0 = c.tz * A.T.cz, k1 = min(g.nz, k0 + A.T.cz);
       int P = g.idx(i0, j, k0);
-      S4 zc = *(const S4*)(z + P);
-      S4 zm = d3 ? *(const S4*)(z + P - g.sxy) : S4(0);
+      S4 qc = dir4(P);
+      S4 qm = d3 ? dir4(P - g.sxy) : S4(0);
       for (int k = k0; k < k1; ++k, P += g.sxy) {
-        // the loads and operator of apply4_body
-        const S4 zp = d3 ? *(const S4*)(z + P + g.sxy) : S4(0);
-        const S4 zs = *(const S4*)(z + P - g.sx), zn = *(const S4*)(z + P + g.sx);
-        const O zl = St<S, O>::ld(z + P - 1), zh = St<S, O>::ld(z + P + 4);
+        // the operator of apply4_body, on the new direction
+        const S4 qp = d3 ? dir4(P + g.sxy) : S4(0);
+        const S4 qs = dir4(P - g.sx), qn = dir4(P + g.sx);
+        const O ql = dir1(P - 1), qh = dir1(P + 4);
         const uint2 cw = *(const uint2*)(L.code + P);
-        O4 pv = *(const O4*)(p + P), qv = *(const O4*)(q + P);
         O4 xv = *(const O4*)(x + P), rv = *(const O4*)(r + P);
         const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
-        const O zv[6] = {zl, (O)zc[0], (O)zc[1], (O)zc[2], (O)zc[3], zh};
+        const O qv[6] = {ql, (O)qc[0], (O)qc[1], (O)qc[2], (O)qc[3], qh};
         S4 b0v = S4(0), z0v = S4(0);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           if (cd[e] == FACE_CODE_INACTIVE) continue;
-          O wP, D;
-          apply_code_v<O>(g, cd[e], zv[e + 1], zv[e], zv[e + 2], (O)zs[e], (O)zn[e], (O)zm[e],
-                          (O)zp[e], wP, D);
-          const O zP = zv[e + 1];
-          const O pP = first ? zP : zP + be * pv[e];
-          const O qP = first ? wP : wP + be * qv[e];
-          pv[e] = pP;
-          qv[e] = qP;
-          xv[e] += a * pP;
-          const O rP = rv[e] - a * qP;
+          O Ap, D;
+          apply_code_v<O>(g, cd[e], qv[e + 1], qv[e], qv[e + 2], (O)qs[e], (O)qn[e], (O)qm[e],
+                          (O)qp[e], Ap, D);
+          xv[e] += a * qv[e + 1];
+          const O rP = rv[e] - a * Ap;
           rv[e] = rP;
           S bs;
           St<S, O>::st(&bs, rP);
@@ -1634,14 +1671,13 @@ __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const Ti
           if (A.z0) z0v[e] = A.wj * bs / diag_code<S>(g, cd[e]);
           rr += (double)rP * (double)rP;
         }
-        *(O4*)(p + P) = pv;
-        *(O4*)(q + P) = qv;
+        *(S4*)(pn + P) = qc;
         *(O4*)(x + P) = xv;
         *(O4*)(r + P) = rv;
         *(S4*)(A.b0 + P) = b0v;
         if (A.z0) *(S4*)(A.z0 + P) = z0v;
-        zm = zc;
-        zc = zp;
+        qm = qc;
+        qc = qp;
       }
     }
   }
@@ -1670,18 +1706,18 @@ __global__ __launch_bounds__(FIN) void k_fin_update_batch(Pack<FinArgs> f) {
 }
 
 template <class O, class S>
-UpdateArgs<O, S> update_args(const Level& l0, O* x, O* r, O* p, O* q, const RedBuf& red,
+UpdateArgs<O, S> update_args(const Level& l0, O* x, O* r, void* const* dir, const RedBuf& red,
                              void* z0, double wj) {
   const Tiles T = cg_quad(l0) ? make_tiles(l0.g.nx / 4, l0.g.ny, l0.g.nz, l0.tt[TK_UPDATE])
                               : lvl_tiles(l0, TK_UPDATE);
-  return UpdateArgs<O, S>{view(l0), T, x, r, p, q, (const S*)l0.x[l0.cur], (S*)l0.b, (S*)z0,
-                          (S)wj, red};
+  return UpdateArgs<O, S>{view(l0), T, x, r, {(S*)dir[0], (S*)dir[1]}, (const S*)l0.x[l0.cur],
+                          (S*)l0.b, (S*)z0, (S)wj, red};
 }
 
 template <class O, class S>
-void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const RedBuf& red, hipStream_t s,
-                       bool fin, void* z0, double wj) {
-  const UpdateArgs<O, S> a = update_args<O, S>(l0, x, r, p, q, red, z0, wj);
+void launch_fcg_update(const Level& l0, O* x, O* r, void* const* dir, const RedBuf& red,
+                       hipStream_t s, bool fin, void* z0, double wj) {
+  const UpdateArgs<O, S> a = update_args<O, S>(l0, x, r, dir, red, z0, wj);
   check_partials(red, a.T.grid, 1);
   if (cg_quad(l0))
     NFVM_LAUNCH((k_fcg_update4<O, S>), dim3(a.T.grid), dim3(MBX, MBY), 0, s, a);
@@ -2497,14 +2533,14 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
   Group<FinArgs> fa, fu;
   for (int i = 0; i < n; ++i) {
     MgGridDesc& d = G[i];
-    const auto a = apply_args<O, S0>(d.lv[0], (const O*)d.r, (const O*)d.q, d.red);
+    const auto a = apply_args<O, S0>(d.lv[0], (const O*)d.r, d.dir, d.red);
     check_partials(d.red, a.T.grid, 3);
     ap[cg_quad(d.lv[0])].push_back(a);
     fa.push_back(FinArgs{d.red, a.T.grid});
   }
   for (int i = 0; i < n; ++i) {
     MgGridDesc& d = G[i];
-    const auto a = update_args<O, S0>(d.lv[0], (O*)d.x, (O*)d.r, (O*)d.p, (O*)d.q, d.red,
+    const auto a = update_args<O, S0>(d.lv[0], (O*)d.x, (O*)d.r, d.dir, d.red,
                                       d.zero[0], d.wj);
     check_partials(d.red, a.T.grid, 1);
     up[cg_quad(d.lv[0])].push_back(a);
@@ -2562,9 +2598,9 @@ template void launch_coarse_solve<bf16, float>(const Level&, const int*, const i
 #define INST_FCG(O, S)                                                                          \
   template void launch_fcg_start<O, S>(const Level&, const O*, const O*, O*, O*, const RedBuf&, \
                                        bool, double, int, int, hipStream_t, bool, void*, double); \
-  template void launch_fcg_apply<O, S>(const Level&, const O*, const O*, const RedBuf&,         \
+  template void launch_fcg_apply<O, S>(const Level&, const O*, void* const*, const RedBuf&,     \
                                        hipStream_t, bool);                                      \
-  template void launch_fcg_update<O, S>(const Level&, O*, O*, O*, O*, const RedBuf&,            \
+  template void launch_fcg_update<O, S>(const Level&, O*, O*, void* const*, const RedBuf&,      \
                                         hipStream_t, bool, void*, double);
 INST_FCG(double, double)
 INST_FCG(float, float)

@@ -340,11 +340,11 @@ void launch_fcg_start(const Level& l0, const O* b, const O* x0, O* r, O* x, cons
                       bool have_x0, double tol, int max_cycles, int forced, hipStream_t s,
                       bool fin = true, void* z0 = nullptr, double wj = 0.0);
 template <class O, class S>
-void launch_fcg_apply(const Level& l0, const O* r, const O* q, const RedBuf& red, hipStream_t s,
-                      bool fin = true);
+void launch_fcg_apply(const Level& l0, const O* r, void* const* dir, const RedBuf& red,
+                      hipStream_t s, bool fin = true);
 template <class O, class S>
-void launch_fcg_update(const Level& l0, O* x, O* r, O* p, O* q, const RedBuf& red, hipStream_t s,
-                       bool fin = true, void* z0 = nullptr, double wj = 0.0);
+void launch_fcg_update(const Level& l0, O* x, O* r, void* const* dir, const RedBuf& red,
+                       hipStream_t s, bool fin = true, void* z0 = nullptr, double wj = 0.0);
 
 // ---- batched iterations of several grids ----------------------------------------
 constexpr int MAX_LEVELS = 20;
@@ -362,7 +362,8 @@ struct MgGridDesc {
   int coarse_max;
   void* zero[MAX_LEVELS];  // buffer of level l's fused first sweep, or null
   RedBuf red;
-  void *x, *r, *p, *q;
+  void *x, *r;
+  void* dir[2];  // the two level-0 direction buffers (storage type of level 0)
 };
 
 // One flexible-CG iteration of several grids as a list of launches: per
