@@ -90,7 +90,12 @@ typedef struct {
  *                 the coarsest level holds at most 512 fluid cells
  *   nu1, nu2      pre/post Jacobi sweeps; omega_jacobi (0: 4/5 in 2D, 6/7 in 3D)
  *   tol           relative residual target ||b - A phi|| <= tol ||b||
- *   max_cycles    preconditioner applications per pressure solve */
+ *   max_cycles    preconditioner applications per pressure solve
+ *   nu_coarse     pre and post sweeps on every level below the finest
+ *                 (0: nu1 and nu2 there too).  The V-cycle keeps its shape;
+ *                 more work on the cheap coarse levels makes up for their
+ *                 rediscretised operators, which approximate the fine one
+ *                 less well around solid blocks as the grids coarsen. */
 typedef struct {
   int32_t dim, n[3];
   double h[3];
@@ -104,6 +109,7 @@ typedef struct {
   int32_t n_levels, nu1, nu2;
   double omega_jacobi, tol;
   int32_t max_cycles;
+  int32_t nu_coarse;
 } nfvm_grid_desc;
 
 /* Host FP64 fields, [nz][ny][nx].  p is kinematic pressure (Pa / rho). */

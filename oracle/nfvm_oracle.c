@@ -493,7 +493,7 @@ typedef struct {
 } orc_level;
 
 struct orc_mg {
-  int dim, L, nu1, nu2, prolong, literal;
+  int dim, L, nu1, nu2, nuc, prolong, literal;
   double wj;
   orc_level lv[24];
   int nc;        /* active cells on the coarsest level */
@@ -757,6 +757,7 @@ orc_mg* orc_mg_create(const orc_case* c) {
   mg->nu1 = c->nu1;
   mg->prolong = c->prolong;
   mg->nu2 = c->nu2;
+  mg->nuc = c->nu_coarse;
   mg->wj = c->omega_jacobi > 0 ? c->omega_jacobi : (c->dim == 3 ? 6.0 / 7.0 : 4.0 / 5.0);
   mg->literal = c->literal;
   if (mg->literal) {
@@ -764,6 +765,7 @@ orc_mg* orc_mg_create(const orc_case* c) {
      * undamped, nearest upsampling */
     mg->nu1 = 0;
     mg->nu2 = 1;
+    mg->nuc = 0;
     mg->wj = 1.0;
     mg->prolong = 1;
   }
@@ -868,7 +870,10 @@ static void vcycle(const orc_mg* mg, int li, double* x, const double* b) {
     return;
   }
   int N = lcells(l);
-  orc_mg_smooth(mg, li, x, b, mg->nu1);
+  /* sweeps of this level: nu1 / nu2 on the finest, nu_coarse below it when set */
+  const int pre = li > 0 && mg->nuc > 0 ? mg->nuc : mg->nu1;
+  const int post = li > 0 && mg->nuc > 0 ? mg->nuc : mg->nu2;
+  orc_mg_smooth(mg, li, x, b, pre);
   double* r = (double*)malloc(sizeof(double) * N);
   orc_mg_apply(mg, li, x, r);
   for (int P = 0; P < N; ++P) r[P] = l->act[P] ? b[P] - r[P] : 0.0;
@@ -878,7 +883,7 @@ static void vcycle(const orc_mg* mg, int li, double* x, const double* b) {
   orc_mg_restrict(mg, li, r, bc);
   vcycle(mg, li + 1, ec, bc);
   orc_mg_prolong_add(mg, li, ec, x);
-  orc_mg_smooth(mg, li, x, b, mg->nu2);
+  orc_mg_smooth(mg, li, x, b, post);
   free(r); free(bc); free(ec);
 }
 

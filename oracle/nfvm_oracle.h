@@ -58,6 +58,10 @@ typedef struct {
                           nearest upsampling, one fine sweep, repeated as a plain
                           iteration (no Krylov wrapper); nu1, nu2, omega_jacobi
                           and prolong are then ignored */
+  int nu_coarse;       /* pre and post sweeps on the levels below the finest
+                          (0: nu1 and nu2 there too); the cycle keeps the
+                          V shape of Algorithm 1 (the paper fixes no sweep
+                          count) */
 } orc_case;
 
 typedef struct { double *u, *v, *w, *p, *T, *k, *omega; } orc_fields;

@@ -37,7 +37,7 @@ class _Case(C.Structure):
                 ("solid", C.POINTER(C.c_ubyte)), ("n_levels", C.c_int), ("nu1", C.c_int),
                 ("nu2", C.c_int), ("omega_jacobi", C.c_double), ("tol", C.c_double),
                 ("max_cycles", C.c_int), ("prolong", C.c_int),
-                ("rk_order", C.c_int), ("literal", C.c_int)]
+                ("rk_order", C.c_int), ("literal", C.c_int), ("nu_coarse", C.c_int)]
 
 
 class _Fields(C.Structure):
@@ -143,6 +143,7 @@ class OracleCase:
         c.prolong = case.prolong
         c.rk_order = case.rk_order
         c.literal = getattr(case, "literal", 0)
+        c.nu_coarse = getattr(case, "nu_coarse", 0)
         self.c = c
 
     @property

@@ -95,6 +95,8 @@ class Case:
     n_levels: int = 1
     nu1: int = 2
     nu2: int = 2
+    # pre and post sweeps on the levels below the finest (0: nu1, nu2)
+    nu_coarse: int = 0
     omega_jacobi: float = 0.0  # 0: method default for the dimension
     tol: float = 1e-6
     max_cycles: int = 100

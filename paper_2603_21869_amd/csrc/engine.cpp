@@ -62,6 +62,7 @@ void validate_desc(const nfvm_grid_desc& d) {
   for (int a = 0; a < d.dim; ++a)
     if (d.n[a] % (1 << (d.n_levels - 1))) bad("every axis must halve exactly n_levels-1 times");
   if (d.nu1 < 0 || d.nu2 < 0 || d.nu1 + d.nu2 < 1) bad("need at least one smoothing sweep");
+  if (d.nu_coarse < 0 || d.nu_coarse > 64) bad("nu_coarse must be in 0 .. 64");
   if (d.n_patches < 0 || d.n_patches > MAX_PATCHES - PID_USER) bad("too many patches");
   if (d.n_patches > 0 && !d.patches) bad("patches pointer is NULL");
   for (int q = 0; q < d.n_patches; ++q) {
@@ -244,6 +245,9 @@ class GridT : public GridBase {
   Geom g{};
   Phys ph{};
   int L = 1, nu1 = 2, nu2 = 2;
+  int nuc = 0;  // sweeps on the levels below the finest (0: nu1, nu2)
+  int pre_of(int l) const { return l > 0 && nuc > 0 ? nuc : nu1; }
+  int post_of(int l) const { return l > 0 && nuc > 0 ? nuc : nu2; }
   double wj = 0.8;
   std::vector<std::unique_ptr<DevBuf>> pool;
   uint8_t* type = nullptr;
@@ -347,6 +351,7 @@ class GridT : public GridBase {
     L = d.n_levels;
     nu1 = d.nu1;
     nu2 = d.nu2;
+    nuc = d.nu_coarse;
     wj = d.omega_jacobi > 0 ? d.omega_jacobi : (d.dim == 3 ? 6.0 / 7.0 : 4.0 / 5.0);
     ph.nu = d.nu;
     ph.alpha_T = d.alpha_T;
@@ -796,8 +801,8 @@ class GridT : public GridBase {
     if (top > L - 2) return;  // fewer than two levels would fit
     bottom_top = top;
     bot.nlev = L - top;
-    bot.nu1 = nu1;
-    bot.nu2 = nu2;
+    bot.nu1 = pre_of(top);  // (every level of the bottom solver is a coarse one)
+    bot.nu2 = post_of(top);
     bot.wj = wj;
     size_t off = 0;
     for (int l = top; l < L; ++l) {
@@ -858,7 +863,7 @@ class GridT : public GridBase {
   // nu1 + nu2 odd the sweeps leave z in the buffer that sweep goes to, so
   // level 0 then sweeps from zero itself.
   bool fused_zero(int l) const {
-    return nu1 > 0 && l != bottom_top && l < L - 1 && (l > 0 || (nu1 + nu2) % 2 == 0);
+    return pre_of(l) > 0 && l != bottom_top && l < L - 1 && (l > 0 || (nu1 + nu2) % 2 == 0);
   }
   void* zero_of(int l) const { return fused_zero(l) ? lv[l].x[0] : nullptr; }
 
@@ -885,13 +890,13 @@ class GridT : public GridBase {
       prof_end(NFVM_K_BOTTOM);
       return;
     }
-    if (nu1 > 0) {
+    if (pre_of(l) > 0) {
       if (fused_zero(l)) {
         v.cur = 0;  // first sweep from zero done by the kernel that wrote v.b
       } else {
         smooth(l, true);
       }
-      for (int s = 1; s < nu1; ++s) smooth(l, false);
+      for (int s = 1; s < pre_of(l); ++s) smooth(l, false);
     } else {
       v.cur = 0;
       // (no pre-smoothing: the iterate is zeroed, one store per cell)
@@ -924,7 +929,7 @@ class GridT : public GridBase {
       launch_prolong<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
       prof_end(NFVM_K_PROLONG_C);
     }
-    for (int s = 0; s < nu2; ++s) smooth(l, false);
+    for (int s = 0; s < post_of(l); ++s) smooth(l, false);
   }
 
   // One preconditioned flexible-CG iteration (all kernels are no-ops once
@@ -1384,6 +1389,8 @@ class GridT : public GridBase {
     d.bottom_top = bottom_top;
     d.nu1 = nu1;
     d.nu2 = nu2;
+    d.nu1c = pre_of(1);
+    d.nu2c = post_of(1);
     d.wj = wj;
     d.bot = &bot;
     d.cmap = cmap;
@@ -1471,10 +1478,12 @@ class GridT : public GridBase {
       if (literal) {
         nu1 = 0;
         nu2 = 1;
+        nuc = 0;
         wj = 1.0;
       } else {
         nu1 = desc.nu1;
         nu2 = desc.nu2;
+        nuc = desc.nu_coarse;
         wj = desc.omega_jacobi > 0 ? desc.omega_jacobi : (desc.dim == 3 ? 6.0 / 7.0 : 4.0 / 5.0);
       }
       for (int l = 0; l < L; ++l) {

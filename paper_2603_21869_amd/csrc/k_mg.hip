@@ -1814,12 +1814,13 @@ void launch_fill_f64(double* x, int n, double v, hipStream_t s) {
 
 // ---- deterministic finalisation of block partials ---------------------------------
 template <int NV, int OP>
-__global__ __launch_bounds__(256) void k_finalize(RedBuf red, int nb, int s0, int s1) {
+__global__ __launch_bounds__(256) void k_finalize(RedBuf red, const double* __restrict__ part,
+                                                  int nb, int s0, int s1) {
   __shared__ double sh[NV][256];
   double acc[NV];
   for (int q = 0; q < NV; ++q) acc[q] = rid<OP>();
   for (int i = threadIdx.x; i < nb; i += 256)
-    for (int q = 0; q < NV; ++q) acc[q] = rop<OP>(acc[q], red.partial[(size_t)i * NV + q]);
+    for (int q = 0; q < NV; ++q) acc[q] = rop<OP>(acc[q], part[(size_t)i * NV + q]);
   block_tree<NV, OP, 256>(acc, sh);
   if (threadIdx.x == 0) {
     red.out[s0] = acc[0];
@@ -1828,16 +1829,61 @@ __global__ __launch_bounds__(256) void k_finalize(RedBuf red, int nb, int s0, in
   }
 }
 
+// Partials one folding workgroup reduces.  A launch over a large grid leaves
+// hundreds of thousands of partials, which one workgroup reads at the rate
+// of one compute unit; folding them first in fixed chunks over many
+// workgroups keeps the order fixed and the finaliser short.
+constexpr int FOLD = 1024;
+
+template <int NV, int OP>
+__global__ __launch_bounds__(256) void k_fold(const double* __restrict__ part, int nb,
+                                              double* __restrict__ out) {
+  __shared__ double sh[NV][256];
+  double acc[NV];
+  for (int q = 0; q < NV; ++q) acc[q] = rid<OP>();
+  const int base = blockIdx.x * FOLD;
+  for (int i = threadIdx.x; i < FOLD; i += 256) {
+    const int b = base + i;
+    if (b < nb)
+      for (int q = 0; q < NV; ++q) acc[q] = rop<OP>(acc[q], part[(size_t)b * NV + q]);
+  }
+  block_tree<NV, OP, 256>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < NV; ++q) out[(size_t)blockIdx.x * NV + q] = acc[q];
+}
+
+template <int NV, int OP>
+void finalize_as(const RedBuf& red, int nb, int slot0, int slot1, hipStream_t s) {
+  const int nf = (nb + FOLD - 1) / FOLD;
+  // the folded values go after the partials, in the same buffer
+  const bool fold = nb > 2 * FOLD && (size_t)(nb + nf) * NV <= (size_t)red.max_blocks * RED_MAX_NV;
+  if (!fold) {
+    NFVM_LAUNCH_FIN((k_finalize<NV, OP>), dim3(1), dim3(256), 0, s, red, red.partial, nb, slot0,
+                    slot1);
+    return;
+  }
+  double* folded = red.partial + (size_t)nb * NV;
+  // (timed as one finaliser: both launches between the pair of events; a
+  // failed record shows when the profiler reads the pair)
+  hipEvent_t e0 = t_launch_ev.fstart, e1 = t_launch_ev.fstop;
+  t_launch_ev.fstart = t_launch_ev.fstop = nullptr;
+  if (e0) (void)hipEventRecord(e0, s);
+  hipLaunchKernelGGL((k_fold<NV, OP>), dim3(nf), dim3(256), 0, s, red.partial, nb, folded);
+  hipLaunchKernelGGL((k_finalize<NV, OP>), dim3(1), dim3(256), 0, s, red, folded, nf, slot0,
+                     slot1);
+  if (e1) (void)hipEventRecord(e1, s);
+}
+
 void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, int slot1,
                      hipStream_t s) {
   if (nv == 1 && op == R_SUM)
-    NFVM_LAUNCH_FIN((k_finalize<1, R_SUM>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    finalize_as<1, R_SUM>(red, nblocks, slot0, slot1, s);
   else if (nv == 1 && op == R_MAX)
-    NFVM_LAUNCH_FIN((k_finalize<1, R_MAX>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    finalize_as<1, R_MAX>(red, nblocks, slot0, slot1, s);
   else if (nv == 2 && op == R_SUM)
-    NFVM_LAUNCH_FIN((k_finalize<2, R_SUM>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    finalize_as<2, R_SUM>(red, nblocks, slot0, slot1, s);
   else
-    NFVM_LAUNCH_FIN((k_finalize<2, R_MIN>), dim3(1), dim3(256), 0, s, red, nblocks, slot0, slot1);
+    finalize_as<2, R_MIN>(red, nblocks, slot0, slot1, s);
 }
 
 // ---- LDS bottom solver ----------------------------------------------------------------
@@ -2372,6 +2418,10 @@ struct SweepGroups {
 // bottom solver's or the coarsest solve's).
 int stop_level(const MgGridDesc& d) { return d.bottom_top >= 0 ? d.bottom_top : d.L - 1; }
 
+// Pre- and post-smoothing sweeps of grid d on level l.
+int pre_of(const MgGridDesc& d, int l) { return l > 0 ? d.nu1c : d.nu1; }
+int post_of(const MgGridDesc& d, int l) { return l > 0 ? d.nu2c : d.nu2; }
+
 // Sweep number s on level l of grid d (the same order as one grid's
 // recursive V-cycle): pre-smoothing when `pre`.
 template <class S, class C>
@@ -2379,7 +2429,7 @@ void add_sweep(SweepGroups<S, C>& sg, MgGridDesc& d, int l, int s, bool pre) {
   Level& v = d.lv[l];
   const double* ctl = d.red.out;
   if (pre) {
-    if (d.nu1 == 0) return;
+    if (pre_of(d, l) == 0) return;
     if (s == 0) {
       if (d.zero[l]) {
         v.cur = 0;  // written by the kernel that formed this level's right-hand side
@@ -2389,8 +2439,8 @@ void add_sweep(SweepGroups<S, C>& sg, MgGridDesc& d, int l, int s, bool pre) {
       }
       return;
     }
-    if (s >= d.nu1) return;
-  } else if (s >= d.nu2) {
+    if (s >= pre_of(d, l)) return;
+  } else if (s >= post_of(d, l)) {
     return;
   }
   sg.add(v, d.wj, false, ctl);
@@ -2401,12 +2451,19 @@ void add_sweep(SweepGroups<S, C>& sg, MgGridDesc& d, int l, int s, bool pre) {
 
 template <class O, class S0, class SC, class C>
 void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
-  int top = 0, nu1 = 0, nu2 = 0;
-  for (int i = 0; i < n; ++i) {
-    top = std::max(top, stop_level(G[i]));
-    nu1 = std::max(nu1, G[i].nu1);
-    nu2 = std::max(nu2, G[i].nu2);
-  }
+  int top = 0;
+  for (int i = 0; i < n; ++i) top = std::max(top, stop_level(G[i]));
+  // the most sweeps any grid takes on level l
+  auto max_pre = [&](int l) {
+    int m = 0;
+    for (int i = 0; i < n; ++i) m = std::max(m, pre_of(G[i], l));
+    return m;
+  };
+  auto max_post = [&](int l) {
+    int m = 0;
+    for (int i = 0; i < n; ++i) m = std::max(m, post_of(G[i], l));
+    return m;
+  };
   // zero-filled levels (no pre-smoothing): one launch per grid, not batched
   auto fill = [&](MgGridDesc& d, int l) {
     Level& v = d.lv[l];
@@ -2422,12 +2479,12 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
   };
   // down: pre-smoothing and restriction, level by level
   for (int l = 0; l < top; ++l) {
-    for (int s = 0; s < std::max(nu1, 1); ++s) {
+    for (int s = 0; s < std::max(max_pre(l), 1); ++s) {
       SweepGroups<S0, C> g0;
       SweepGroups<SC, C> gc;
       for (int i = 0; i < n; ++i) {
         if (l >= stop_level(G[i])) continue;
-        if (G[i].nu1 == 0) {
+        if (pre_of(G[i], l) == 0) {
           if (s == 0) fill(G[i], l);
           continue;
         }
@@ -2513,7 +2570,7 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
     emit_tiles(o, p0n, k_prolong_nearest<S0, C, SC>, k_prolong_nearest_batch<S0, C, SC>, false);
     emit_tiles(o, pc, k_prolong<SC, C, SC>, k_prolong_batch<SC, C, SC>, false);
     emit_tiles(o, pcn, k_prolong_nearest<SC, C, SC>, k_prolong_nearest_batch<SC, C, SC>, false);
-    for (int s = 0; s < nu2; ++s) {
+    for (int s = 0; s < max_post(l); ++s) {
       SweepGroups<S0, C> g0;
       SweepGroups<SC, C> gc;
       for (int i = 0; i < n; ++i) {

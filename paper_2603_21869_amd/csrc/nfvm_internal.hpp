@@ -354,6 +354,7 @@ constexpr int MAX_LEVELS = 20;
 struct MgGridDesc {
   Level* lv;  // levels 0 .. L-1; cur is advanced as the iteration is laid out
   int L, bottom_top, nu1, nu2;
+  int nu1c, nu2c;  // sweeps on the levels below the finest
   double wj;
   const Bottom* bot;  // when bottom_top >= 0
   const int* cmap;

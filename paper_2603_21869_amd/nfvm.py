@@ -51,7 +51,8 @@ class nfvm_grid_desc(C.Structure):
                 ("n_patches", C.c_int32), ("patches", C.POINTER(nfvm_patch)),
                 ("solid_mask", C.POINTER(C.c_uint8)), ("precision", C.c_int32),
                 ("n_levels", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
-                ("omega_jacobi", C.c_double), ("tol", C.c_double), ("max_cycles", C.c_int32)]
+                ("omega_jacobi", C.c_double), ("tol", C.c_double), ("max_cycles", C.c_int32),
+                ("nu_coarse", C.c_int32)]
 
 
 class nfvm_fields(C.Structure):
@@ -174,6 +175,7 @@ class Desc:
         d.omega_jacobi = case.omega_jacobi
         d.tol = case.tol if tol is None else tol
         d.max_cycles = case.max_cycles if max_cycles is None else max_cycles
+        d.nu_coarse = case.nu_coarse
         self.d = d
 
 

@@ -382,3 +382,62 @@ def test_literal_cycle_matches_algorithm_1_in_matrix_form(oracle):
         p = p - (A[0] @ p) / Ds[0] + b / Ds[0]
         x, cyc, rel, st = mg.solve(b.reshape(shapes[0]), forced=it)
         assert np.allclose(x.ravel(), p, rtol=0, atol=1e-12 * np.abs(p).max()), it
+
+
+def test_coarse_sweep_count_schedule(oracle):
+    """nu_coarse: the cycle written out from the level operators (damped
+    Jacobi sweeps, mean-of-children restriction, interpolation, a dense
+    solve on the coarsest level) with nu1 = 2 pre and nu2 = 1 post sweeps
+    on the finest level and nu_coarse pre and post sweeps on every level
+    below gives the oracle's cycle; nu_coarse = 0 keeps nu1, nu2 there."""
+    for nuc in (0, 3):
+        c = _vented_box(3).copy(nu1=2, nu2=1, nu_coarse=nuc)
+        mg = oracle.MG(c)
+        L = mg.L
+        act = [mg.active(l).astype(bool) for l in range(L)]
+        sh = mg.shape(L - 1)[0]
+        ids = np.flatnonzero(act[L - 1])
+        A = np.zeros((ids.size, ids.size))
+        for q, i in enumerate(ids):
+            e = np.zeros(act[L - 1].size)
+            e[i] = 1.0
+            A[:, q] = mg.apply(L - 1, e.reshape(sh)).ravel()[ids]
+
+        def cycle(l, b):
+            if l == L - 1:
+                x = np.zeros(act[l].size)
+                x[ids] = np.linalg.solve(A, b.ravel()[ids])
+                return x.reshape(b.shape)
+            pre, post = (2, 1) if l == 0 or nuc == 0 else (nuc, nuc)
+            x = mg.smooth(l, np.zeros_like(b), b, pre)
+            r = (b - mg.apply(l, x)) * act[l]
+            x = mg.prolong_add(l, cycle(l + 1, mg.restrict(l, r)), x)
+            return mg.smooth(l, x, b, post)
+
+        b = np.random.default_rng(3).standard_normal(act[0].shape) * act[0]
+        want = cycle(0, b)
+        got = mg.vcycle(np.zeros_like(b), b)
+        assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max()), nuc
+    plain = oracle.MG(_vented_box(3).copy(nu1=2, nu2=1)).vcycle(np.zeros_like(b), b)
+    assert not np.allclose(plain, got)
+
+
+def test_coarse_sweeps_help_around_solid_blocks(oracle):
+    """On a room with seeded solid blocks the rediscretised coarse operators
+    approximate the fine one less well as the levels coarsen, and the
+    preconditioned solve needs more iterations than on the empty room;
+    more sweeps on the coarse levels (nu_coarse = 8) win most of them back,
+    with the V shape of the cycle unchanged."""
+    base = C.room3d(128, 64, 32, size=(10.0, 4.0, 3.0), seed=0, n_levels=6, precision=C.PREC_FP64)
+    m = base.solid == 0
+    # a smooth right-hand side (as the divergence of a developed flow is),
+    # which leaves the most work to the coarse levels
+    z, y, x = np.meshgrid(*(np.linspace(0, 1, k) for k in m.shape), indexing="ij")
+    b = (np.sin(3.1 * x + 0.3) * np.cos(2.2 * y) + 0.5 * np.sin(5 * z) + 0.2) * m
+    its = {}
+    for nuc in (0, 8):
+        xs, cyc, rel, st = oracle.MG(base.copy(nu_coarse=nuc)).solve(b, tol=1e-6, max_cycles=200)
+        assert st == 0 and rel <= 1e-6
+        its[nuc] = cyc
+    print("iterations", its)
+    assert its[8] <= 0.8 * its[0]
