@@ -95,7 +95,15 @@ typedef struct {
  *                 (0: nu1 and nu2 there too).  The V-cycle keeps its shape;
  *                 more work on the cheap coarse levels makes up for their
  *                 rediscretised operators, which approximate the fine one
- *                 less well around solid blocks as the grids coarsen. */
+ *                 less well around solid blocks as the grids coarsen.
+ *   coarse_fp32_cells  NFVM_MIXED only: coarse levels with at least this many
+ *                 cells are stored in FP32 like the finest level, smaller
+ *                 ones in BF16 (0: 131072).  BF16 rounding of a large coarse
+ *                 level's iterate puts noise on the cycle's correction at
+ *                 that level's scale, where the operator weighs it most, and
+ *                 costs iterations that grow with the grid; on the small
+ *                 levels it is harmless.  A value above every level's cell
+ *                 count keeps all coarse levels in BF16. */
 typedef struct {
   int32_t dim, n[3];
   double h[3];
@@ -110,6 +118,7 @@ typedef struct {
   double omega_jacobi, tol;
   int32_t max_cycles;
   int32_t nu_coarse;
+  int32_t coarse_fp32_cells;
 } nfvm_grid_desc;
 
 /* Host FP64 fields, [nz][ny][nx].  p is kinematic pressure (Pa / rho). */

@@ -97,6 +97,9 @@ class Case:
     nu2: int = 2
     # pre and post sweeps on the levels below the finest (0: nu1, nu2)
     nu_coarse: int = 0
+    # mixed precision: coarse levels with at least this many cells in FP32,
+    # the others in BF16 (0: the library's default; 2**31 - 1: all BF16)
+    coarse_fp32_cells: int = 0
     omega_jacobi: float = 0.0  # 0: method default for the dimension
     tol: float = 1e-6
     max_cycles: int = 100

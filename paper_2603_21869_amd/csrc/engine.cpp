@@ -63,6 +63,7 @@ void validate_desc(const nfvm_grid_desc& d) {
     if (d.n[a] % (1 << (d.n_levels - 1))) bad("every axis must halve exactly n_levels-1 times");
   if (d.nu1 < 0 || d.nu2 < 0 || d.nu1 + d.nu2 < 1) bad("need at least one smoothing sweep");
   if (d.nu_coarse < 0 || d.nu_coarse > 64) bad("nu_coarse must be in 0 .. 64");
+  if (d.coarse_fp32_cells < 0) bad("coarse_fp32_cells must not be negative");
   if (d.n_patches < 0 || d.n_patches > MAX_PATCHES - PID_USER) bad("too many patches");
   if (d.n_patches > 0 && !d.patches) bad("patches pointer is NULL");
   for (int q = 0; q < d.n_patches; ++q) {
@@ -120,6 +121,18 @@ void fail_partials(int nblocks, int nv, int max_blocks) {
                                  std::to_string(max_blocks) + " blocks)"};
 }
 
+// Mixed precision: coarse levels with at least this many cells are held in
+// FP32, the level-0 storage type, unless the descriptor sets another bound.
+constexpr long long COARSE_FP32_CELLS = 131072;
+
+// Whether coarse level l of a grid is stored in the level-0 type rather than
+// the coarse one (only mixed precision has two).
+static bool wide_level(const nfvm_grid_desc& d, int l) {
+  if (d.precision != NFVM_MIXED || l == 0) return false;
+  const long long lim = d.coarse_fp32_cells > 0 ? d.coarse_fp32_cells : COARSE_FP32_CELLS;
+  return (long long)level_geom(d, l).cells() >= lim;
+}
+
 size_t footprint_bytes(const nfvm_grid_desc& d) {
   size_t V, F, P, O, S0, SC;
   sizes_of(d.precision, V, F, P, O, S0, SC);
@@ -132,7 +145,7 @@ size_t footprint_bytes(const nfvm_grid_desc& d) {
   b += 8 * N + (d.solid_mask ? N : 0);              // dense staging, mask
   for (int l = 0; l < d.n_levels; ++l) {
     const Geom gl = level_geom(d, l);
-    b += (size_t)gl.total * (1 + 4 * d.dim + 3 * (l == 0 ? S0 : SC));
+    b += (size_t)gl.total * (1 + 4 * d.dim + 3 * (l == 0 || wide_level(d, l) ? S0 : SC));
     b += l == 0 ? (size_t)gl.total * 2 : (size_t)gl.total;  // face codes / full flags
   }
   b += 160 * 1024;                                  // bottom solver's LDS image
@@ -369,7 +382,8 @@ class GridT : public GridBase {
     {
       // algorithmic bytes per launch: operands read once, results written once
       const double N = (double)ncells, sv = sizeof(V), sf = sizeof(F), sp = sizeof(P),
-                   so = sizeof(O), s0 = sizeof(S0), scs = sizeof(SC);
+                   so = sizeof(O), s0 = sizeof(S0);
+      const double scs = wide_level(d, 1) ? sizeof(S0) : sizeof(SC);  // level 1
       const double nc = L > 1 ? (double)level_geom(d, 1).cells() : 0.0;
       // level 0 reads a 2-byte face code per cell; the restriction also
       // writes the coarse level's first sweep, the CG update the level-0 one
@@ -454,7 +468,8 @@ class GridT : public GridBase {
       v.cls = alloc<uint8_t>(v.g.total, "level classes");
       v.full = l > 0 ? alloc<uint8_t>(v.g.total, "level full flags") : nullptr;
       for (int a = 0; a < 3; ++a) v.cf[a] = a < d.dim ? alloc<float>(v.g.total, "level face coefficients") : nullptr;
-      const size_t es = l == 0 ? s0 : sc;
+      v.wide = wide_level(d, l);
+      const size_t es = l == 0 || v.wide ? s0 : sc;
       for (int c = 0; c < 2; ++c) v.x[c] = alloc<uint8_t>(v.g.total * es, "level iterate");
       v.b = alloc<uint8_t>(v.g.total * es, "level right-hand side");
       v.cur = 0;
@@ -591,13 +606,13 @@ class GridT : public GridBase {
           v.tt[TK_SMOOTH_ZERO] = tt;
           launch_smooth<S0, C>(v, nullptr, v.x[0], wj, true, red.out, stream);
         });
-        v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT, v.g, [&](int tt) {
+        v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT + (lv[1].wide ? 4000 : 0), v.g, [&](int tt) {
           v.tt[TK_RESTRICT] = tt;
-          launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream, zero_of(1), wj);
+          restrict_as(0);
         });
-        v.tt[TK_PROLONG] = tune_one(TK_PROLONG, v.g, [&](int tt) {
+        v.tt[TK_PROLONG] = tune_one(TK_PROLONG + (lv[1].wide ? 4000 : 0), v.g, [&](int tt) {
           v.tt[TK_PROLONG] = tt;
-          launch_prolong<S0, C, SC>(lv[0], lv[1], red.out, stream);
+          prolong_as(0);
         });
         v.tt[TK_START] = tune_one(TK_START, v.g, [&](int tt) {
           v.tt[TK_START] = tt;
@@ -619,22 +634,23 @@ class GridT : public GridBase {
           launch_fcg_update<O, S0>(v, phi, r, dir, tr, stream, true, zero0(), wj);
         });
       } else {
-        v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + 1000, v.g, [&](int tt) {
+        // (the tuning key tells the storage types of the level and the next)
+        const int tk = 1000 + (v.wide ? 2000 : 0) + (lv[l + 1].wide ? 4000 : 0);
+        v.tt[TK_SMOOTH] = tune_one(TK_SMOOTH + tk, v.g, [&](int tt) {
           v.tt[TK_SMOOTH] = tt;
-          launch_smooth<SC, C>(v, v.x[0], v.x[1], wj, false, red.out, stream);
+          smooth_as(l, v.x[0], v.x[1], false);
         });
-        v.tt[TK_SMOOTH_ZERO] = tune_one(TK_SMOOTH_ZERO + 1000, v.g, [&](int tt) {
+        v.tt[TK_SMOOTH_ZERO] = tune_one(TK_SMOOTH_ZERO + tk, v.g, [&](int tt) {
           v.tt[TK_SMOOTH_ZERO] = tt;
-          launch_smooth<SC, C>(v, nullptr, v.x[0], wj, true, red.out, stream);
+          smooth_as(l, nullptr, v.x[0], true);
         });
-        v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT + 1000, v.g, [&](int tt) {
+        v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT + tk, v.g, [&](int tt) {
           v.tt[TK_RESTRICT] = tt;
-          launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream, zero_of(l + 1),
-                                           wj);
+          restrict_as(l);
         });
-        v.tt[TK_PROLONG] = tune_one(TK_PROLONG + 1000, v.g, [&](int tt) {
+        v.tt[TK_PROLONG] = tune_one(TK_PROLONG + tk, v.g, [&](int tt) {
           v.tt[TK_PROLONG] = tt;
-          launch_prolong<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
+          prolong_as(l);
         });
       }
     }
@@ -644,7 +660,7 @@ class GridT : public GridBase {
     for (O* bufp : {bvec, phi, r, x0}) NFVM_CK(hipMemsetAsync(bufp, 0, ob, stream));
     for (void* d : dir) NFVM_CK(hipMemsetAsync(d, 0, (size_t)g.total * sizeof(S0), stream));
     for (int l = 0; l < L; ++l) {
-      const size_t es = (size_t)lv[l].g.total * (l == 0 ? sizeof(S0) : sizeof(SC));
+      const size_t es = (size_t)lv[l].g.total * elem_size(l);
       for (int c = 0; c < 2; ++c) NFVM_CK(hipMemsetAsync(lv[l].x[c], 0, es, stream));
       NFVM_CK(hipMemsetAsync(lv[l].b, 0, es, stream));
     }
@@ -708,6 +724,39 @@ class GridT : public GridBase {
   }
 
   // ---- multigrid ------------------------------------------------------------------
+  // Storage type of level l: the level-0 type on level 0 and on wide coarse
+  // levels, the coarse type elsewhere.  fn is called with a value of it.
+  template <class Fn>
+  void as_level(int l, Fn&& fn) const {
+    if (l == 0 || lv[l].wide)
+      fn(S0{});
+    else
+      fn(SC{});
+  }
+  size_t elem_size(int l) const { return l == 0 || lv[l].wide ? sizeof(S0) : sizeof(SC); }
+  // sweep on level l >= 1, residual and restriction from level l to l + 1,
+  // prolongation and correction from level l + 1 to l, in the levels' types
+  void smooth_as(int l, const void* xin, void* xout, bool zero) {
+    as_level(l, [&](auto t) {
+      launch_smooth<decltype(t), C>(lv[l], xin, xout, wj, zero, red.out, stream);
+    });
+  }
+  void restrict_as(int l) {
+    as_level(l, [&](auto f) {
+      as_level(l + 1, [&](auto c) {
+        launch_resid_restrict<decltype(f), C, decltype(c)>(lv[l], lv[l + 1], red.out, stream,
+                                                           zero_of(l + 1), wj);
+      });
+    });
+  }
+  void prolong_as(int l) {
+    as_level(l, [&](auto f) {
+      as_level(l + 1, [&](auto c) {
+        launch_prolong<decltype(f), C, decltype(c)>(lv[l], lv[l + 1], red.out, stream);
+      });
+    });
+  }
+
   void smooth(int l, bool zero) {
     Level& v = lv[l];
     const void* xin = zero ? nullptr : v.x[v.cur];
@@ -719,9 +768,9 @@ class GridT : public GridBase {
       prof_end(kid);
     } else {
       // x in, b, x out and the class byte (from zero: no x in)
-      const double nc = (double)v.g.cells(), sc = sizeof(SC);
+      const double nc = (double)v.g.cells(), sc = elem_size(l);
       prof_begin(NFVM_K_SMOOTH_C, nc * ((zero ? 2 : 3) * sc + 1));
-      launch_smooth<SC, C>(v, xin, xout, wj, zero, red.out, stream);
+      smooth_as(l, xin, xout, zero);
       prof_end(NFVM_K_SMOOTH_C);
     }
     v.cur = zero ? 0 : (v.cur ^ 1);
@@ -733,22 +782,22 @@ class GridT : public GridBase {
   // written with the class byte, or the correction read with it).
   double restrict_bytes(int l, bool fused) const {
     const double nf = (double)lv[l].g.cells(), nc = (double)lv[l + 1].g.cells();
-    const double sc = sizeof(SC);
-    return nf * (2 * sc + 1) + nc * ((fused ? 2 : 1) * sc + 1);
+    const double sf = elem_size(l), sc = elem_size(l + 1);
+    return nf * (2 * sf + 1) + nc * ((fused ? 2 : 1) * sc + 1);
   }
   double prolong_bytes(int l) const {
     const double nf = (double)lv[l].g.cells(), nc = (double)lv[l + 1].g.cells();
-    const double sc = sizeof(SC);
-    return nf * (2 * sc + 1) + nc * (sc + 1);
+    const double sf = elem_size(l), sc = elem_size(l + 1);
+    return nf * (2 * sf + 1) + nc * (sc + 1);
   }
   // the bottom solver: its top level's b read and x written, the constant
   // LDS image read; the coarsest dense solve: the inverse and its vectors
   double bottom_bytes_moved() const {
-    const double nt = (double)lv[bottom_top].g.cells(), sc = sizeof(SC);
+    const double nt = (double)lv[bottom_top].g.cells(), sc = elem_size(bottom_top);
     return nt * 2 * sc + (double)(bot.lds_bytes - bot.zero_bytes);
   }
   double coarse_bytes_moved() const {
-    const double n = (double)n_coarse, sc = L == 1 ? sizeof(S0) : sizeof(SC);
+    const double n = (double)n_coarse, sc = elem_size(L - 1);
     return n * n * 8 + n * (2 * sc + 4);
   }
   // CG start: b read, r and x written, the level-0 right-hand side and (fused)
@@ -789,7 +838,9 @@ class GridT : public GridBase {
   void setup_bottom() {
     bottom_top = -1;
     if (!use_bottom || nearest || literal || L < 3) return;
-    const size_t limit = bottom_lds_limit<SC, C>();
+    // (the top level in global memory is held in either storage type; both
+    // kernels get the same LDS limit)
+    const size_t limit = std::min(bottom_lds_limit<SC, C>(), bottom_lds_limit<S0, C>());
     size_t bytes = al16(COARSE_MAX * sizeof(int));
     int top = L;
     for (int l = L - 1; l >= 1; --l) {
@@ -872,7 +923,7 @@ class GridT : public GridBase {
     if (l == bottom_top) {
       v.cur = 0;
       prof_begin(NFVM_K_BOTTOM, bottom_bytes_moved());
-      launch_bottom<SC, C>(bot, v.b, v.x[0], red.out, stream);
+      as_level(l, [&](auto t) { launch_bottom<decltype(t), C>(bot, v.b, v.x[0], red.out, stream); });
       prof_end(NFVM_K_BOTTOM);
       return;
     }
@@ -883,10 +934,9 @@ class GridT : public GridBase {
     if (l == L - 1) {
       v.cur = 0;
       prof_begin(NFVM_K_BOTTOM, coarse_bytes_moved());
-      if (l == 0)
-        launch_coarse_solve<S0, C>(v, cmap, ncount, work, COARSE_MAX, red.out, stream);
-      else
-        launch_coarse_solve<SC, C>(v, cmap, ncount, work, COARSE_MAX, red.out, stream);
+      as_level(l, [&](auto t) {
+        launch_coarse_solve<decltype(t), C>(v, cmap, ncount, work, COARSE_MAX, red.out, stream);
+      });
       prof_end(NFVM_K_BOTTOM);
       return;
     }
@@ -905,28 +955,28 @@ class GridT : public GridBase {
         launch_fill_zero<S0>(v, v.x[0], red.out, stream);
         prof_end(NFVM_K_SMOOTH0_ZERO);
       } else {
-        prof_begin(NFVM_K_SMOOTH_C, (double)v.g.cells() * sizeof(SC));
-        launch_fill_zero<SC>(v, v.x[0], red.out, stream);
+        prof_begin(NFVM_K_SMOOTH_C, (double)v.g.cells() * elem_size(l));
+        as_level(l, [&](auto t) { launch_fill_zero<decltype(t)>(v, v.x[0], red.out, stream); });
         prof_end(NFVM_K_SMOOTH_C);
       }
     }
     if (l == 0) {
       prof_begin(NFVM_K_RESTRICT0);
-      launch_resid_restrict<S0, C, SC>(lv[0], lv[1], red.out, stream, zero_of(1), wj);
+      restrict_as(0);
       prof_end(NFVM_K_RESTRICT0);
     } else {
       prof_begin(NFVM_K_RESTRICT_C, restrict_bytes(l, zero_of(l + 1) != nullptr));
-      launch_resid_restrict<SC, C, SC>(lv[l], lv[l + 1], red.out, stream, zero_of(l + 1), wj);
+      restrict_as(l);
       prof_end(NFVM_K_RESTRICT_C);
     }
     vcycle(l + 1);
     if (l == 0) {
       prof_begin(NFVM_K_PROLONG0);
-      launch_prolong<S0, C, SC>(lv[0], lv[1], red.out, stream);
+      prolong_as(0);
       prof_end(NFVM_K_PROLONG0);
     } else {
       prof_begin(NFVM_K_PROLONG_C, prolong_bytes(l));
-      launch_prolong<SC, C, SC>(lv[l], lv[l + 1], red.out, stream);
+      prolong_as(l);
       prof_end(NFVM_K_PROLONG_C);
     }
     for (int s = 0; s < post_of(l); ++s) smooth(l, false);
@@ -1084,7 +1134,7 @@ class GridT : public GridBase {
     scan("p (even)", dir[0], T, sizeof(S0));
     scan("p (odd)", dir[1], T, sizeof(S0));
     for (int l = 0; l < L; ++l) {
-      const int es = l == 0 ? (int)sizeof(S0) : (int)sizeof(SC);
+      const int es = (int)elem_size(l);
       const size_t n = (size_t)lv[l].g.total;
       scan("L" + std::to_string(l) + ".x0", lv[l].x[0], n, es);
       scan("L" + std::to_string(l) + ".x1", lv[l].x[1], n, es);

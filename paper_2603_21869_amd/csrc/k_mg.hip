@@ -2447,6 +2447,82 @@ void add_sweep(SweepGroups<S, C>& sg, MgGridDesc& d, int l, int s, bool pre) {
   v.cur ^= 1;
 }
 
+// Whether level l of grid d is held in the level-0 storage type.
+bool wide_of(const MgGridDesc& d, int l) { return l == 0 || d.lv[l].wide; }
+
+// The bottom solves of grids whose bottom solver's top level is held in type
+// T: the single kernel for one grid, else one workgroup per grid.
+template <class T, class C>
+void emit_bottoms(BatchOps& o, const std::vector<BottomArgsBase>& bo, size_t lds) {
+  if (bo.size() == 1) {
+    const BottomArgsBase e = bo[0];
+    o.ops.push_back([=](const unsigned char*, hipStream_t s) {
+      hipLaunchKernelGGL((k_bottom<T, C>), dim3(1), dim3(1024), e.B.lds_bytes, s, e.B,
+                         (const T*)e.btop, (T*)e.xtop, e.ctl);
+    });
+  } else {
+    emit_blocks(o, bo, k_bottom_batch<T, C>, 1024, lds);
+  }
+}
+
+// Restrictions from a level of type A to one of type B, by kernel.
+template <class A, class B, class C>
+struct RestrictSet {
+  Group<RestrictArgs<A, C, B>> plain, quad;
+  void add(const MgGridDesc& d, int l) {
+    (restrict_quad(d.lv[l]) ? quad : plain)
+        .push_back(restrict_args<A, C, B>(d.lv[l], d.lv[l + 1], d.red.out, d.zero[l + 1], d.wj));
+  }
+  void emit(BatchOps& o) const {
+    emit_tiles(o, plain, k_resid_restrict<A, C, B>, k_resid_restrict_batch<A, C, B>, false);
+    if constexpr (has_quad<A>)
+      emit_tiles(o, quad, k_resid_restrict4<A, C, B>, k_resid_restrict4_batch<A, C, B>, false);
+  }
+};
+
+// Prolongations to a level of type A from one of type B, by kernel.
+template <class A, class B, class C>
+struct ProlongSet {
+  Group<ProlongArgs<A, C, B>> plain, quad, nearest;
+  void add(const MgGridDesc& d, int l) {
+    (d.lv[l].nearest ? nearest : prolong_quad(d.lv[l]) ? quad : plain)
+        .push_back(prolong_args<A, C, B>(d.lv[l], d.lv[l + 1], d.red.out));
+  }
+  void emit(BatchOps& o) const {
+    emit_tiles(o, plain, k_prolong<A, C, B>, k_prolong_batch<A, C, B>, false);
+    if constexpr (has_quad<A>)
+      emit_tiles(o, quad, k_prolong4<A, C, B>, k_prolong4_batch<A, C, B>, false);
+    emit_tiles(o, nearest, k_prolong_nearest<A, C, B>, k_prolong_nearest_batch<A, C, B>, false);
+  }
+};
+
+// The four pairings of the two storage types (wide = the level-0 type W,
+// narrow = the coarse type N) between a level and the next coarser one.
+template <template <class, class, class> class Set, class W, class N, class C>
+struct TypePairs {
+  Set<W, W, C> ww;
+  Set<W, N, C> wn;
+  Set<N, N, C> nn;
+  Set<N, W, C> nw;
+  void add(const MgGridDesc& d, int l) {
+    const bool a = wide_of(d, l), b = wide_of(d, l + 1);
+    if (a && b)
+      ww.add(d, l);
+    else if (a)
+      wn.add(d, l);
+    else if (b)
+      nw.add(d, l);
+    else
+      nn.add(d, l);
+  }
+  void emit(BatchOps& o) const {
+    ww.emit(o);
+    wn.emit(o);
+    nn.emit(o);
+    nw.emit(o);
+  }
+};
+
 }  // namespace
 
 template <class O, class S0, class SC, class C>
@@ -2471,7 +2547,7 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
     const Level lv = v;
     const double* ctl = d.red.out;
     o.ops.push_back([=](const unsigned char*, hipStream_t s) {
-      if (l == 0)
+      if (l == 0 || lv.wide)
         launch_fill_zero<S0>(lv, lv.x[0], ctl, s);
       else
         launch_fill_zero<SC>(lv, lv.x[0], ctl, s);
@@ -2488,7 +2564,7 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
           if (s == 0) fill(G[i], l);
           continue;
         }
-        if (l == 0)
+        if (wide_of(G[i], l))
           add_sweep(g0, G[i], l, s, true);
         else
           add_sweep(gc, G[i], l, s, true);
@@ -2496,86 +2572,52 @@ void plan_fcg_iteration(MgGridDesc* G, int n, BatchOps& o) {
       g0.emit(o);
       gc.emit(o);
     }
-    Group<RestrictArgs<S0, C, SC>> r0, r0q;
-    Group<RestrictArgs<SC, C, SC>> rc;
-    for (int i = 0; i < n; ++i) {
-      MgGridDesc& d = G[i];
-      if (l >= stop_level(d)) continue;
-      if (l == 0) {
-        (restrict_quad(d.lv[0]) ? r0q : r0)
-            .push_back(restrict_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out, d.zero[1], d.wj));
-      } else {
-        rc.push_back(
-            restrict_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out, d.zero[l + 1], d.wj));
-      }
-    }
-    emit_tiles(o, r0, k_resid_restrict<S0, C, SC>, k_resid_restrict_batch<S0, C, SC>, false);
-    if constexpr (has_quad<S0>)
-      emit_tiles(o, r0q, k_resid_restrict4<S0, C, SC>, k_resid_restrict4_batch<S0, C, SC>,
-                 false);
-    emit_tiles(o, rc, k_resid_restrict<SC, C, SC>, k_resid_restrict_batch<SC, C, SC>, false);
+    TypePairs<RestrictSet, S0, SC, C> rs;
+    for (int i = 0; i < n; ++i)
+      if (l < stop_level(G[i])) rs.add(G[i], l);
+    rs.emit(o);
   }
   // bottom solver or coarsest solve of every grid
   {
-    std::vector<BottomArgsBase> bo;
+    // [bottom top level held in the coarse type, in the level-0 type]
+    std::vector<BottomArgsBase> bo[2];
+    size_t lds[2] = {0, 0};
     Group<CoarseArgs<S0, C>> c0;
     Group<CoarseArgs<SC, C>> cc;
-    size_t lds = 0;
     for (int i = 0; i < n; ++i) {
       MgGridDesc& d = G[i];
       if (d.bottom_top >= 0) {
         Level& v = d.lv[d.bottom_top];
         v.cur = 0;
-        bo.push_back(BottomArgsBase{*d.bot, v.b, v.x[0], d.red.out});
-        lds = std::max(lds, d.bot->lds_bytes);
+        const int w = wide_of(d, d.bottom_top) ? 1 : 0;
+        bo[w].push_back(BottomArgsBase{*d.bot, v.b, v.x[0], d.red.out});
+        lds[w] = std::max(lds[w], d.bot->lds_bytes);
       } else {
         Level& v = d.lv[d.L - 1];
         v.cur = 0;
-        if (d.L == 1)
+        if (wide_of(d, d.L - 1))
           c0.push_back(coarse_args<S0, C>(v, d.cmap, d.ncount, d.ainv, d.coarse_max, d.red.out));
         else
           cc.push_back(coarse_args<SC, C>(v, d.cmap, d.ncount, d.ainv, d.coarse_max, d.red.out));
       }
     }
-    if (bo.size() == 1) {
-      const BottomArgsBase e = bo[0];
-      o.ops.push_back([=](const unsigned char*, hipStream_t s) {
-        hipLaunchKernelGGL((k_bottom<SC, C>), dim3(1), dim3(1024), e.B.lds_bytes, s, e.B,
-                           (const SC*)e.btop, (SC*)e.xtop, e.ctl);
-      });
-    } else {
-      emit_blocks(o, bo, k_bottom_batch<SC, C>, 1024, lds);
-    }
+    emit_bottoms<SC, C>(o, bo[0], lds[0]);
+    emit_bottoms<S0, C>(o, bo[1], lds[1]);
     emit_packed_blocks(o, c0, k_coarse_solve_batch<S0, C>, 256);
     emit_packed_blocks(o, cc, k_coarse_solve_batch<SC, C>, 256);
   }
   // up: prolongation and post-smoothing
   for (int l = top - 1; l >= 0; --l) {
-    Group<ProlongArgs<S0, C, SC>> p0, p0q, p0n;
-    Group<ProlongArgs<SC, C, SC>> pc, pcn;
-    for (int i = 0; i < n; ++i) {
-      MgGridDesc& d = G[i];
-      if (l >= stop_level(d)) continue;
-      if (l == 0) {
-        (d.lv[0].nearest ? p0n : prolong_quad(d.lv[0]) ? p0q : p0)
-            .push_back(prolong_args<S0, C, SC>(d.lv[0], d.lv[1], d.red.out));
-      } else {
-        (d.lv[l].nearest ? pcn : pc)
-            .push_back(prolong_args<SC, C, SC>(d.lv[l], d.lv[l + 1], d.red.out));
-      }
-    }
-    emit_tiles(o, p0, k_prolong<S0, C, SC>, k_prolong_batch<S0, C, SC>, false);
-    if constexpr (has_quad<S0>)
-      emit_tiles(o, p0q, k_prolong4<S0, C, SC>, k_prolong4_batch<S0, C, SC>, false);
-    emit_tiles(o, p0n, k_prolong_nearest<S0, C, SC>, k_prolong_nearest_batch<S0, C, SC>, false);
-    emit_tiles(o, pc, k_prolong<SC, C, SC>, k_prolong_batch<SC, C, SC>, false);
-    emit_tiles(o, pcn, k_prolong_nearest<SC, C, SC>, k_prolong_nearest_batch<SC, C, SC>, false);
+    TypePairs<ProlongSet, S0, SC, C> ps;
+    for (int i = 0; i < n; ++i)
+      if (l < stop_level(G[i])) ps.add(G[i], l);
+    ps.emit(o);
     for (int s = 0; s < max_post(l); ++s) {
       SweepGroups<S0, C> g0;
       SweepGroups<SC, C> gc;
       for (int i = 0; i < n; ++i) {
         if (l >= stop_level(G[i])) continue;
-        if (l == 0)
+        if (wide_of(G[i], l))
           add_sweep(g0, G[i], l, s, false);
         else
           add_sweep(gc, G[i], l, s, false);
@@ -2644,6 +2686,7 @@ INST_PAIR(double, double, double)
 INST_PAIR(float, float, float)
 INST_PAIR(float, float, bf16)
 INST_PAIR(bf16, float, bf16)
+INST_PAIR(bf16, float, float)
 
 template void launch_coarse_solve<double, double>(const Level&, const int*, const int*,
                                                   const double*, int, const double*, hipStream_t);

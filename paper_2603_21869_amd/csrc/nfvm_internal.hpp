@@ -150,6 +150,8 @@ struct Level {
   uint16_t* code;               // level 0 only: face codes (else null)
   bool nearest = false;         // correction from the next coarser level taken
                                 // as nearest (piecewise constant), not linear
+  bool wide = false;            // coarse level stored in the level-0 type (mixed
+                                // precision: FP32 instead of BF16)
 };
 
 // Level-0 face code of a cell: 2 bits per face (x-, x+, y-, y+, z-, z+ from

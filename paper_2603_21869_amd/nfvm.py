@@ -52,7 +52,7 @@ class nfvm_grid_desc(C.Structure):
                 ("solid_mask", C.POINTER(C.c_uint8)), ("precision", C.c_int32),
                 ("n_levels", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("omega_jacobi", C.c_double), ("tol", C.c_double), ("max_cycles", C.c_int32),
-                ("nu_coarse", C.c_int32)]
+                ("nu_coarse", C.c_int32), ("coarse_fp32_cells", C.c_int32)]
 
 
 class nfvm_fields(C.Structure):
@@ -176,6 +176,7 @@ class Desc:
         d.tol = case.tol if tol is None else tol
         d.max_cycles = case.max_cycles if max_cycles is None else max_cycles
         d.nu_coarse = case.nu_coarse
+        d.coarse_fp32_cells = case.coarse_fp32_cells
         self.d = d
 
 

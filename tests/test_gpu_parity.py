@@ -328,6 +328,41 @@ def test_coarse_sweeps_match_oracle(nf, oracle, nuc):
         g.close()
 
 
+@pytest.mark.parametrize("lim", [1, 4096, 2**31 - 1], ids=["all_fp32", "split", "all_bf16"])
+def test_mixed_coarse_storage_matches_oracle(nf, oracle, lim):
+    """Mixed precision with the coarse levels held in FP32 down to a cell
+    count and in BF16 below it (every coarse level FP32, a split hierarchy,
+    every coarse level BF16): the time step matches the FP64 oracle to 1e-6
+    with the LDS bottom solver and without it, and a batch of grids with
+    different splits gives each grid's fields bitwise as stepped alone."""
+    case = C.room3d(64, 32, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4, n_steps=2,
+                    tol=1e-9, precision=C.PREC_MIXED).copy(coarse_fp32_cells=lim)
+    for bottom in (1.0, 0.0):
+        g = nf.Grid(case)
+        nf.nfvm_set_option(g.h, nf.NFVM_OPT_BOTTOM, bottom)
+        s, stats = g.step(2)
+        out = g.fields()
+        g.close()
+        cyc = [x["cycles"] for x in stats]
+        ref, _, _ = oracle.step(case.copy(precision=C.PREC_FP64), 2, forced_cycles=cyc)
+        check_fields(case, out, ref, 1e-6, tag=f"coarse fp32 from {lim} cells, bottom {bottom}, "
+                                              f"cycles {cyc}")
+    variants = (lim, 1, 2**31 - 1, 4096)
+    alone = []
+    for v in variants:
+        g = nf.Grid(case.copy(coarse_fp32_cells=v))
+        g.step(2)
+        alone.append(g.fields())
+        g.close()
+    gs = [nf.Grid(case.copy(coarse_fp32_cells=v)) for v in variants]
+    nf.nfvm_step_batch([g.h for g in gs], 2)
+    for v, g, a in zip(variants, gs, alone):
+        f = g.fields()
+        for k in f:
+            assert np.array_equal(f[k], a[k]), (v, k)
+        g.close()
+
+
 def _nearest_cases():
     return [
         ("ch2d", C.channel2d(96, 18, L=4.0, H=1.0, n_levels=2, n_steps=2)),
