@@ -55,16 +55,10 @@ PROFILE_FILES = {
     ("bigroom", "mixed"): "kernels_bigroom_1024x512x256_mixed.md",
 }
 
-# Unfused per-operator byte model of one 3D V(2,2) cycle and of the rest of a
-# step, per fine cell: each operand of each operator read once and each
-# result written once at its storage precision.  A cycle moves 18.25 values
-# per fine cell on level 0 (four sweeps of 3, residual 3, restriction 1 1/8,
-# prolongation and correction 2 1/8) and 8/7 of that over all levels; mixed
-# precision stores level 0 in FP32 and the coarse levels in BF16 and adds the
-# FP64 outer residual and update (40 B).  The rest of a step is the explicit
-# update, the two destruction half steps, the right-hand side and the
-# projection.
-MODEL_CYCLE_B = {"fp64": 167.0, "fp32": 83.0, "mixed": 118.0}
+# Unfused per-operator byte model of the rest of a step, per cell (each
+# operand read once and each result written once at its storage precision):
+# the explicit update, the two destruction half steps, the right-hand side
+# and the projection.  The cycle's model is model_cycle_bytes below.
 MODEL_STEP_B = {"fp64": 344.0, "fp32": 172.0, "mixed": 190.0}
 # kernels of the pressure solve (the rest of a step is the physics kernels)
 SOLVE_KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "fcg_apply", "fcg_update",
@@ -101,6 +95,59 @@ def measured_traffic(workload: str, precision: str, kernel: str):
     return traffic.get(kernel), name
 
 
+# V-cycle shape of the room workloads: three pre- and post-sweeps on the
+# finest level and six on every coarser one (the solid blocks make the
+# rediscretised coarse operators the weak part of the cycle; measured on the
+# 1024x512x256 room in mixed precision: V(2,2) 13.8 iterations and 81 ms per
+# step, V(3,3) with 4 coarse sweeps 10.1 / 76.5 ms, with 6 9.1 / 74.2 ms,
+# V(4,4) with 6 8.5 / 77.6 ms)
+ROOM_CYCLE = dict(nu1=3, nu2=3, nu_coarse=6)
+
+
+def smoothing_of(case) -> str:
+    """The V-cycle shape of a case in words."""
+    s = f"V({case.nu1},{case.nu2}) damped Jacobi"
+    if case.nu_coarse:
+        s += f", {case.nu_coarse}+{case.nu_coarse} sweeps on the coarse levels"
+    return s
+
+
+def coarse_storage_of(case) -> str:
+    from paper_2603_21869_amd import cases as C
+    if case.precision != C.PREC_MIXED:
+        return "as level 0"
+    lim = case.coarse_fp32_cells or 131072
+    if lim >= 2**31 - 1:
+        return "BF16 on every coarse level"
+    return f"FP32 on coarse levels of >= {lim} cells, BF16 below (LDS bottom levels in FP32)"
+
+
+def model_cycle_bytes(case) -> float:
+    """Unfused per-operator byte model of one preconditioned iteration of a
+    case, in bytes per fine cell: on a level with nu sweeps per side each
+    sweep moves 3 values per cell (x, b read, x written), the residual 3, the
+    restriction 1 1/8 and the prolongation and correction 2 1/8 (values per
+    cell of that level, at its storage size: the level-0 type on level 0 and
+    on coarse levels of at least coarse_fp32_cells cells in mixed precision,
+    the coarse type below); the coarsest solve is left out; the outer
+    iteration moves 5 values per fine cell (z read, p, x and r updated) in
+    the outer type."""
+    from paper_2603_21869_amd import cases as C
+    s0, sc, so = {C.PREC_FP64: (8, 8, 8), C.PREC_FP32: (4, 4, 4),
+                  C.PREC_MIXED: (4, 2, 8)}[case.precision]
+    lim = case.coarse_fp32_cells or 131072
+    n = list(case.n)
+    total = 0.0
+    N0 = float(case.ncells)
+    for l in range(case.n_levels - 1):
+        cells = float(n[0] * n[1] * n[2])
+        nu = case.nu1 + case.nu2 if l == 0 or not case.nu_coarse else 2 * case.nu_coarse
+        size = s0 if l == 0 or (case.precision == C.PREC_MIXED and cells >= lim) else sc
+        total += (3 * nu + 6.25) * size * cells / N0
+        n = [max(1, k // 2) if a < case.dim else k for a, k in enumerate(n)]
+    return total + 5 * so
+
+
 def make_case(name: str, precision: int, tol: float):
     from paper_2603_21869_amd import cases as C
     if name == "channel3d":
@@ -108,9 +155,10 @@ def make_case(name: str, precision: int, tol: float):
     if name == "channel2d":
         return C.channel2d(precision=precision, tol=tol)
     if name == "room":
-        return C.room3d(precision=precision, tol=tol)
+        return C.room3d(precision=precision, tol=tol).copy(**ROOM_CYCLE)
     if name == "bigroom":
-        return C.room3d(1024, 512, 256, n_levels=9, precision=precision, tol=tol, n_steps=100)
+        return C.room3d(1024, 512, 256, n_levels=9, precision=precision, tol=tol,
+                        n_steps=100).copy(**ROOM_CYCLE)
     if name.startswith("open_channel_"):
         return C.open_channel(int(name.rsplit("_", 1)[1]), precision=precision, tol=tol)
     raise SystemExit(f"unknown workload {name}")
@@ -288,9 +336,10 @@ def cpu_baseline(workload: str, tol: float, budget_s: float = 20.0):
     from oracle import oracle as O
     O.build()
     if workload == "bigroom":
-        case = C.room3d(256, 128, 64, n_levels=7, precision=C.PREC_FP64, tol=tol, n_steps=1)
-        what = ("one time step of the same room (same blocks, vents, physics, tol) on a "
-                "256x128x64 grid (1/64 of the cells), 7 levels")
+        case = C.room3d(256, 128, 64, n_levels=7, precision=C.PREC_FP64, tol=tol,
+                        n_steps=1).copy(**ROOM_CYCLE)
+        what = ("one time step of the same room (same blocks, vents, physics, tol, cycle "
+                "shape) on a 256x128x64 grid (1/64 of the cells), 7 levels")
     else:
         case = make_case(workload, C.PREC_FP64, tol)
         what = "time steps of the same workload from its initial state"
@@ -411,13 +460,14 @@ def main():
     b_solve = sum(prof[k]["bytes_per_launch"] * prof[k]["launches"] for k in SOLVE_KERNELS) \
         / args.steps
     t_phys = sum(v["seconds"] for k, v in prof.items() if k not in SOLVE_KERNELS) / args.steps
-    model_solve = MODEL_CYCLE_B[args.precision] * case.ncells * mean_cycles
+    model_cycle = model_cycle_bytes(case)
+    model_solve = model_cycle * case.ncells * mean_cycles
     model_step = model_solve + MODEL_STEP_B[args.precision] * case.ncells
     solve = {
         "kernel_ms_per_step": round(t_solve * 1e3, 4),
         "physics_kernel_ms_per_step": round(t_phys * 1e3, 4),
         "algorithmic_GBs": round(b_solve / t_solve / 1e9, 1),
-        "model_bytes_per_cell_cycle": MODEL_CYCLE_B[args.precision],
+        "model_bytes_per_cell_cycle": round(model_cycle, 1),
         "model_GBs": round(model_solve / t_solve / 1e9, 1),
         "model_frac": round(model_solve / t_solve / 1e9 / PEAK_HBM_GBS, 4),
         "step_model_GBs": round(model_step / (ms_per_step * 1e-3) / 1e9, 1),
@@ -452,7 +502,14 @@ def main():
                  # Algorithm 1 as printed (undamped scalar-diagonal Jacobi,
                  # V(0,1), nearest upsampling, plain iteration): its
                  # convergence or divergence on this workload
-                 (args.precision + "_alg1_literal", prec, args.tol, dict(literal=1), False)]
+                 (args.precision + "_alg1_literal", prec, args.tol, dict(literal=1), False),
+                 # the plain V(2,2) cycle of the channel workloads
+                 (args.precision + "_v22", prec, args.tol, dict(nu1=2, nu2=2, nu_coarse=0),
+                  False)]
+        if args.precision == "mixed":
+            # every coarse level in BF16
+            runs += [("mixed_all_coarse_bf16", prec, args.tol,
+                      dict(coarse_fp32_cells=2**31 - 1), False)]
         if args.all_variants:
             runs += [("fp32", C.PREC_FP32, args.tol, {}, False),
                      (args.precision + "_nearest_prolongation", prec, args.tol,
@@ -495,7 +552,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "cells": case.ncells,
                    "precision": args.precision, "tol": args.tol, "dt": case.dt,
-                   "levels": case.n_levels, "smoothing": "V(2,2) damped Jacobi",
+                   "levels": case.n_levels, "smoothing": smoothing_of(case),
+                   "coarse_storage": coarse_storage_of(case),
                    "parallelism": "single GPU"},
         "solver": {"mean_cycles": mean_cycles, "max_rel_residual": max(rel),
                    "statuses": sorted({x["status"] for x in stats})},
