@@ -474,6 +474,72 @@ void orc_project(const orc_case* c, const double* phi, const double* us, const d
   if (max_face_div) *max_face_div = mdiv;
 }
 
+/* Slope of a ghost rule: the ghost value is affine in the cell's own value,
+ * ghost = s phi_P + const, and s = ghost(1) - ghost(0). */
+static double ghost_slope(const orc_case* c, const nbinfo* nb, int fld) {
+  return ghost(c, nb, fld, 1.0) - ghost(c, nb, fld, 0.0);
+}
+
+/* Reverse mode of the pressure step: each forward formula of orc_rhs_b and
+ * orc_project is taken term by term and its partial derivative scattered
+ * onto the value it reads (a fluid neighbour, or the cell itself through the
+ * slope of a ghost rule). */
+static int pressure_adjoint_with(const orc_case* c, const orc_mg* mg, const double* ubar,
+                                 const double* vbar, const double* wbar, const double* pbar,
+                                 double tol, int max_cycles, int forced, double* usbar,
+                                 double* vsbar, double* wsbar, double* phibar_out,
+                                 double* lambda_out, int* cycles, double* rel) {
+  const int N = ncells(c);
+  const double* ub[3] = {ubar, vbar, wbar};
+  double* usb[3] = {usbar, vsbar, wsbar};
+  double* phib = (double*)calloc(N, sizeof(double));
+  double* lam = (double*)calloc(N, sizeof(double));
+  /* u_d = u*_d - dt (phi~_+ - phi~_-) / (2 h_d) on fluid cells, p += phi:
+   * phibar = pbar + d/dphi of the velocity outputs */
+  for (int k = 0; k < c->n[2]; ++k)
+    for (int j = 0; j < c->n[1]; ++j)
+      for (int i = 0; i < c->n[0]; ++i) {
+        int P = cidx(c, i, j, k);
+        if (!is_fluid(c, P)) continue;
+        phib[P] += pbar[P];
+        for (int d = 0; d < c->dim; ++d) {
+          double g = -c->dt * ub[d][P] / (2.0 * c->h[d]);
+          nbinfo hi = neighbour(c, i, j, k, 2 * d + 1), lo = neighbour(c, i, j, k, 2 * d);
+          if (hi.fluid) phib[hi.idx] += g;
+          else phib[P] += g * ghost_slope(c, &hi, F_P);
+          if (lo.fluid) phib[lo.idx] -= g;
+          else phib[P] -= g * ghost_slope(c, &lo, F_P);
+        }
+      }
+  /* lambda = A^-T phibar = A^-1 phibar (A symmetric) */
+  int st = orc_mg_solve(mg, phib, lam, tol, max_cycles, forced, cycles, rel);
+  /* b_P = -(1/dt) sum_d (uf_+ - uf_-) / h_d, uf = (u*_P + u~_N) / 2:
+   * usbar = ubar (u = u* + correction) + d/du* of b, weighted by lambda */
+  for (int d = 0; d < 3; ++d)
+    for (int P = 0; P < N; ++P) usb[d][P] = ub[d][P];
+  for (int k = 0; k < c->n[2]; ++k)
+    for (int j = 0; j < c->n[1]; ++j)
+      for (int i = 0; i < c->n[0]; ++i) {
+        int P = cidx(c, i, j, k);
+        if (!is_fluid(c, P)) continue;
+        for (int d = 0; d < c->dim; ++d) {
+          double s = -lam[P] / (c->dt * c->h[d]);
+          for (int side = -1; side <= 1; side += 2) {
+            nbinfo nb = neighbour(c, i, j, k, 2 * d + (side > 0));
+            double gf = side * 0.5 * s; /* d b_P / d uf of this face, times 1/2 */
+            usb[d][P] += gf;
+            if (nb.fluid) usb[d][nb.idx] += gf;
+            else usb[d][P] += gf * ghost_slope(c, &nb, F_U + d);
+          }
+        }
+      }
+  if (phibar_out) memcpy(phibar_out, phib, sizeof(double) * N);
+  if (lambda_out) memcpy(lambda_out, lam, sizeof(double) * N);
+  free(phib);
+  free(lam);
+  return st;
+}
+
 /* ===========================================================================
  * Geometric multigrid for A phi = b (Sec. 2.4, Algorithm 1).
  *
@@ -888,6 +954,18 @@ static void vcycle(const orc_mg* mg, int li, double* x, const double* b) {
 }
 
 void orc_mg_vcycle(const orc_mg* mg, double* x, const double* b) { vcycle(mg, 0, x, b); }
+
+int orc_pressure_adjoint(const orc_case* c, const double* ubar, const double* vbar,
+                         const double* wbar, const double* pbar, double tol, int max_cycles,
+                         int forced_cycles, double* usbar, double* vsbar, double* wsbar,
+                         double* phibar, double* lambda, int* cycles, double* rel_residual) {
+  orc_mg* mg = orc_mg_create(c);
+  if (!mg) return -1;
+  int st = pressure_adjoint_with(c, mg, ubar, vbar, wbar, pbar, tol, max_cycles, forced_cycles,
+                                 usbar, vsbar, wsbar, phibar, lambda, cycles, rel_residual);
+  orc_mg_free(mg);
+  return st;
+}
 
 /* Smallest (p, A p) / (z, A z) kept before the direction restarts. */
 #define CG_RESTART 1e-12

@@ -106,6 +106,19 @@ void orc_mg_vcycle(const orc_mg* mg, double* x, const double* b);
 int orc_mg_solve(const orc_mg* mg, const double* b, double* x, double tol, int max_cycles,
                  int forced_cycles, int* cycles, double* rel_residual);
 
+/* Reverse mode of the pressure step (Sec. 2.4): the map from (u*, p^n) to
+ * (u^{n+1}, p^{n+1}) through b = rhs_b(u*), phi = A^-1 b, u = u* - dt
+ * grad(phi), p = p^n + phi is affine in u*; its transposed Jacobian applied to
+ * the adjoints (ubar, vbar, wbar, pbar) of the outputs gives the adjoint of
+ * u* in (usbar, vsbar, wsbar) (that of p^n is pbar itself).  A is symmetric,
+ * so A^-T is a second solve with the same multigrid (to tol, or forced
+ * cycles); phibar receives A's right-hand side of that solve and lambda its
+ * solution when not NULL.  Returns the solve's status. */
+int orc_pressure_adjoint(const orc_case* c, const double* ubar, const double* vbar,
+                         const double* wbar, const double* pbar, double tol, int max_cycles,
+                         int forced_cycles, double* usbar, double* vsbar, double* wsbar,
+                         double* phibar, double* lambda, int* cycles, double* rel_residual);
+
 /* warm != 0: each step's pressure solve starts from the previous step's
  * increment (zero at the first step of the call), else from zero. */
 int orc_step(const orc_case* c, orc_fields* s, int n_steps, const int* forced_cycles,

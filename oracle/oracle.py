@@ -85,6 +85,9 @@ def lib():
         L.orc_mg_level_shape.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), _dp]
         L.orc_mg_level_active.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_ubyte)]
         L.orc_closure_point.argtypes = [C.c_double, C.c_double, C.c_double, _dp]
+        L.orc_pressure_adjoint.argtypes = [C.POINTER(_Case), _dp, _dp, _dp, _dp, C.c_double,
+                                           C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp,
+                                           C.POINTER(C.c_int), _dp]
         _lib = L
     return _lib
 
@@ -267,6 +270,23 @@ def rhs_b(case, us, vs, ws):
     a = [np.ascontiguousarray(x, dtype=np.float64) for x in (us, vs, ws)]
     lib().orc_rhs_b(oc.ref, *[_ptr(x) for x in a], _ptr(b))
     return b
+
+
+def pressure_adjoint(case, ubar, vbar, wbar, pbar, tol: float = 1e-12, max_cycles: int = 200,
+                     forced: int = -1):
+    """Reverse mode of the pressure step (rhs_b, the solve, project): the
+    adjoints of u*, v*, w* for the adjoints (ubar, vbar, wbar, pbar) of the
+    step's velocity and pressure (the adjoint of p^n is pbar).  Returns
+    (usbar, vsbar, wsbar, phibar, lambda, cycles, rel_residual, status):
+    phibar is the right-hand side of the second solve, lambda its solution."""
+    oc = OracleCase(case)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (ubar, vbar, wbar, pbar)]
+    out = [np.zeros(oc.shape) for _ in range(5)]
+    cyc = C.c_int(0)
+    rel = C.c_double(0.0)
+    st = lib().orc_pressure_adjoint(oc.ref, *[_ptr(x) for x in a], tol, max_cycles, forced,
+                                    *[_ptr(x) for x in out], C.byref(cyc), C.byref(rel))
+    return out[0], out[1], out[2], out[3], out[4], cyc.value, rel.value, st
 
 
 def project(case, phi, us, vs, ws, p):
