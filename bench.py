@@ -63,7 +63,7 @@ MODEL_STEP_B = {"fp64": 344.0, "fp32": 172.0, "mixed": 190.0}
 # kernels of the pressure solve (the rest of a step is the physics kernels)
 SOLVE_KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "fcg_apply", "fcg_update",
                  "smooth_coarse", "restrict_coarse", "prolong_coarse", "bottom", "fcg_start",
-                 "finalize")
+                 "finalize", "smooth0_pair")
 
 
 def kernel_source_hash() -> str:

@@ -307,7 +307,8 @@ enum {
   NFVM_K_BOTTOM = 13,      /* LDS bottom solver, or the coarsest dense solve */
   NFVM_K_FCG_START = 14,   /* r = b - A x0, ||b||, ||r|| and level 0's first sweep */
   NFVM_K_FINALIZE = 15,    /* one-workgroup finalisers of the reductions */
-  NFVM_K_COUNT = 16
+  NFVM_K_SMOOTH0_PAIR = 16, /* two damped-Jacobi sweeps in one pass on level 0 */
+  NFVM_K_COUNT = 17
 };
 nfvm_status nfvm_profile(nfvm_grid_t grid, uint32_t kernel_mask);
 nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launches,
@@ -370,6 +371,15 @@ nfvm_status nfvm_profile_read(nfvm_grid_t grid, int32_t kernel, int64_t* launche
  *                     are set aside while it is on.  Such grids are stepped
  *                     alone: nfvm_step_batch refuses them (NFVM_E_INVAL).
  *                     Other values: NFVM_E_INVAL.
+ *   NFVM_OPT_SWEEP_PAIRS  1 (default): consecutive damped-Jacobi sweeps on
+ *                     the finest level run two per pass (x, b and the face
+ *                     codes read once for both) where its rows are a
+ *                     multiple of 4 cells, as many as keep the V-cycle's
+ *                     result out of the buffer the next cycle's first sweep
+ *                     is fused into; the fields are bitwise those of single
+ *                     sweeps.  0: one sweep per pass.  Batched iterations
+ *                     (nfvm_step_batch, serving) take single sweeps.
+ *                     Other values: NFVM_E_INVAL.
  * Errors: NFVM_E_INVAL for an unknown option. */
 enum {
   NFVM_OPT_GRAPHS = 0,
@@ -379,7 +389,8 @@ enum {
   NFVM_OPT_WARM_START = 4,
   NFVM_OPT_PROLONG = 5,
   NFVM_OPT_RK_ORDER = 6,
-  NFVM_OPT_LITERAL = 7
+  NFVM_OPT_LITERAL = 7,
+  NFVM_OPT_SWEEP_PAIRS = 8
 };
 
 /* The autotuner's choices so far: up to max entries of {kernel id, nx, ny,

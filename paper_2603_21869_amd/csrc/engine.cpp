@@ -392,6 +392,7 @@ class GridT : public GridBase {
       // (update, which writes the new direction and forms its image A p
       // from it instead of storing one)
       prof_bytes[NFVM_K_SMOOTH0] = N * (3 * s0 + 2);
+      prof_bytes[NFVM_K_SMOOTH0_PAIR] = N * (3 * s0 + 2);  // (two sweeps, one pass)
       prof_bytes[NFVM_K_SMOOTH0_ZERO] = N * (2 * s0 + 2);
       prof_bytes[NFVM_K_RESTRICT0] = N * (2 * s0 + 2) + nc * (2 * scs + 1);
       prof_bytes[NFVM_K_PROLONG0] = N * (2 * s0 + 1) + nc * (scs + 1);
@@ -606,6 +607,11 @@ class GridT : public GridBase {
           v.tt[TK_SMOOTH_ZERO] = tt;
           launch_smooth<S0, C>(v, nullptr, v.x[0], wj, true, red.out, stream);
         });
+        if (sweep_pair(v))
+          v.tt[TK_SMOOTH2] = tune_one(TK_SMOOTH2, v.g, [&](int tt) {
+            v.tt[TK_SMOOTH2] = tt;
+            launch_smooth2<S0, C>(v, v.x[0], v.x[1], wj, red.out, stream);
+          });
         v.tt[TK_RESTRICT] = tune_one(TK_RESTRICT + (lv[1].wide ? 4000 : 0), v.g, [&](int tt) {
           v.tt[TK_RESTRICT] = tt;
           restrict_as(0);
@@ -818,6 +824,7 @@ class GridT : public GridBase {
   // Algorithm 1 as printed: V(0,1) cycle of undamped sweeps with the scalar
   // diagonal, nearest upsampling, one coarsest sweep, plain outer iteration
   bool literal = false;
+  bool use_pairs = true;  // two level-0 sweeps per pass where the level takes them
   FieldSet<V, F> rk2{};
   Bottom bot{};
 
@@ -946,7 +953,7 @@ class GridT : public GridBase {
       } else {
         smooth(l, true);
       }
-      for (int s = 1; s < pre_of(l); ++s) smooth(l, false);
+      sweeps(l, pre_of(l) - 1, true);
     } else {
       v.cur = 0;
       // (no pre-smoothing: the iterate is zeroed, one store per cell)
@@ -979,7 +986,42 @@ class GridT : public GridBase {
       prolong_as(l);
       prof_end(NFVM_K_PROLONG_C);
     }
-    for (int s = 0; s < post_of(l); ++s) smooth(l, false);
+    sweeps(l, post_of(l), false);
+  }
+
+  // Two-sweep passes on level 0 in this V-cycle: before and after the coarse
+  // correction.  Each pass flips the level's iterate buffer once where two
+  // sweeps flip it twice, and with a fused first sweep the cycle's result must
+  // end in the buffer that sweep does not write (an odd number of flips, as
+  // with nu1 + nu2 even and single sweeps): pairs are dropped, the pre-
+  // smoothing's last, until the number of pairs is even.
+  void sweep_pairs(int& pre, int& post) const {
+    pre = post = 0;
+    if (!use_pairs || literal || !sweep_pair(lv[0]) || L < 2) return;
+    const int m1 = pre_of(0) > 0 ? pre_of(0) - 1 : 0;  // (the first sweep is apart)
+    pre = m1 / 2;
+    post = post_of(0) / 2;
+    if (fused_zero(0) && (pre + post) % 2 == 1) {
+      if (pre > 0)
+        --pre;
+      else
+        --post;
+    }
+  }
+  // n sweeps on level l after its first (pre: before the coarse correction)
+  void sweeps(int l, int n, bool pre) {
+    if (l == 0) {
+      int pp, pq;
+      sweep_pairs(pp, pq);
+      for (int k = pre ? pp : pq; k > 0 && n >= 2; --k, n -= 2) {
+        Level& v = lv[0];
+        prof_begin(NFVM_K_SMOOTH0_PAIR);
+        launch_smooth2<S0, C>(v, v.x[v.cur], v.x[v.cur ^ 1], wj, red.out, stream);
+        prof_end(NFVM_K_SMOOTH0_PAIR);
+        v.cur ^= 1;
+      }
+    }
+    for (; n > 0; --n) smooth(l, false);
   }
 
   // One preconditioned flexible-CG iteration (all kernels are no-ops once
@@ -1520,6 +1562,11 @@ class GridT : public GridBase {
         NFVM_CK(hipStreamSynchronize(stream));
       }
       rk_order = (int)v;
+    } else if (opt == NFVM_OPT_SWEEP_PAIRS) {
+      if (v != 0.0 && v != 1.0) throw Error{NFVM_E_INVAL, "sweep pairs must be 0 or 1"};
+      NFVM_CK(hipStreamSynchronize(stream));
+      drop_graphs();
+      use_pairs = v != 0.0;
     } else if (opt == NFVM_OPT_LITERAL) {
       if (v != 0.0 && v != 1.0) throw Error{NFVM_E_INVAL, "literal mode must be 0 or 1"};
       NFVM_CK(hipStreamSynchronize(stream));

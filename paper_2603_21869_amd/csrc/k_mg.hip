@@ -562,6 +562,210 @@ void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool 
   }
 }
 
+// ---- two level-0 sweeps in one pass ------------------------------------------------
+// x2 = S(S(x0)), S(x) = x + wj (b - A x) / D, four cells per thread as in
+// k_smooth_code4: half the HBM bytes of two single sweeps (x0, b and the
+// face code read once, x2 written once).  Each thread owns two rows of four
+// columns and walks the planes of its column tile: per plane it forms the
+// first sweep one plane ahead for its rows (registers) and puts it in LDS;
+// the first and last waves of the workgroup also form it for the row past
+// their side of the tile.  A wave's first and last lanes are halo lanes:
+// they form the first sweep of the four columns past each side of the tile
+// and write no result, so a tile is 62 four-cell columns wide and every lane
+// runs the same instructions.  After one barrier per plane the second sweep
+// reads its in-plane neighbours from LDS and its z neighbours from
+// registers.  Both sweeps take
+// k_smooth_code4's arithmetic on the same values and the first is rounded to
+// the storage type before the second reads it, so the result is bitwise that
+// of two single sweeps.  The first sweep is 0 outside the box and on
+// inactive cells, as a single sweep leaves them.  LDS holds three planes, so
+// one barrier per plane suffices: a wave that writes plane k + 1 has passed
+// the barrier of plane k - 1, which every wave reaches only after reading
+// plane k - 2, the buffer plane k + 1 reuses.
+constexpr int S2_ROW = 4 * MBX;          // the cells of a wave's 64 four-cell columns
+constexpr int S2_ROWS = 2 * MBY;         // rows of a workgroup (two per thread)
+constexpr int S2_QX = MBX - 2;           // four-cell columns a tile writes
+
+template <class S, class C>
+__device__ __forceinline__ typename Quad<S>::V sweep_quad_at(const Geom& g, uint2 cw,
+                                                             typename Quad<S>::V xc, C xl, C xr,
+                                                             typename Quad<S>::V xs,
+                                                             typename Quad<S>::V xn,
+                                                             typename Quad<S>::V xm,
+                                                             typename Quad<S>::V xp,
+                                                             typename Quad<S>::V bb, C wj) {
+  typedef typename Quad<S>::V V4;
+  const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
+  const C xv[6] = {xl, (C)xc[0], (C)xc[1], (C)xc[2], (C)xc[3], xr};
+  V4 out;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    C A, D;
+    apply_code_v<C>(g, cd[q], xv[q + 1], xv[q], xv[q + 2], (C)xs[q], (C)xn[q], (C)xm[q],
+                    (C)xp[q], A, D);
+    out[q] = cd[q] != FACE_CODE_INACTIVE ? (S)(xv[q + 1] + wj * ((C)bb[q] - A) / D) : (S)0;
+  }
+  return out;
+}
+
+// The first sweep of a row's quad at one plane, with the plane's right-hand
+// side and face codes (kept for the second sweep there).
+template <class S>
+struct FirstQuad {
+  typename Quad<S>::V x1, bb;
+  uint2 cw;
+};
+
+template <class S, class C>
+__device__ __forceinline__ void smooth2_body(const SmoothArgs<S, C>& a, const TileCtx& c, bool) {
+  typedef typename Quad<S>::V V4;
+  __shared__ S lx[3][S2_ROWS + 2][S2_ROW];
+  if (a.ctl[S_DONE] != 0.0) return;  // (uniform: every thread reads the same flag)
+  const LevelView& L = a.L;
+  const S* __restrict__ x = a.xin;
+  S* __restrict__ xout = a.xout;
+  const S* __restrict__ b = a.b;
+  const C wj = a.wj;
+  const Geom& g = L.g;
+  const bool d3 = g.dim == 3;
+  const int lane = threadIdx.x, wy = threadIdx.y;
+  const int i0 = 4 * (c.tx * S2_QX + lane - 1);  // (lane 0: the halo left of the tile)
+  const int jt = S2_ROWS * c.ty;  // first row of the workgroup
+  const int j0 = jt + 2 * wy;     // this thread's rows j0, j0 + 1
+  const bool col = i0 >= 0 && i0 < g.nx;
+  const bool halo = lane == 0 || lane == MBX - 1;  // no result of its own
+  const bool live[2] = {col && j0 < g.ny, col && j0 + 1 < g.ny};
+  const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
+  // the row past the workgroup's side of the tile (first wave: above the
+  // first row, last wave: below the last), 0 outside the box
+  const int jx = wy == 0 ? jt - 1 : jt + S2_ROWS;
+  const bool xrow = (wy == 0 || wy == MBY - 1) && col && jx >= 0 && jx < g.ny;
+  auto first4 = [&](int r, int m) -> FirstQuad<S> {
+    const int P = g.idx(i0, r, m);
+    const V4 xc = *(const V4*)(x + P);
+    const V4 xm = d3 ? *(const V4*)(x + P - g.sxy) : V4(0);
+    const V4 xp = d3 ? *(const V4*)(x + P + g.sxy) : V4(0);
+    const V4 xs = *(const V4*)(x + P - g.sx), xn = *(const V4*)(x + P + g.sx);
+    const C xl = St<S, C>::ld(x + P - 1), xr = St<S, C>::ld(x + P + 4);
+    FirstQuad<S> f;
+    f.bb = *(const V4*)(b + P);
+    f.cw = *(const uint2*)(L.code + P);
+    f.x1 = sweep_quad_at<S, C>(g, f.cw, xc, xl, xr, xs, xn, xm, xp, f.bb, wj);
+    return f;
+  };
+  // x0 of this thread's rows as the walk carries it: planes m - 1 and m of
+  // the next plane m whose first sweep is formed (each plane loaded once;
+  // the rows' in-plane neighbours j0 + 1 and j0 are each other's centres)
+  auto ldp = [&](int r, int m) -> V4 {
+    return (m >= -1 && m <= g.nz && (d3 || m == 0)) ? *(const V4*)(x + g.idx(i0, r, m)) : V4(0);
+  };
+  V4 xa[2], xb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    xa[h] = live[h] ? ldp(j0 + h, k0 - 2) : V4(0);
+    xb[h] = live[h] ? ldp(j0 + h, k0 - 1) : V4(0);
+  }
+  // the first sweep of this thread's rows at plane m (0 outside the box);
+  // advances the carried planes by one
+  auto own2 = [&](int m, FirstQuad<S> (&f)[2]) {
+    V4 xn[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) xn[h] = live[h] ? ldp(j0 + h, m + 1) : V4(0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (live[h] && m >= 0 && m < g.nz) {
+        const int P = g.idx(i0, j0 + h, m);
+        const V4 ys = h == 0 ? *(const V4*)(x + P - g.sx) : xb[0];
+        const V4 yn = h == 1 ? *(const V4*)(x + P + g.sx) : xb[1];
+        const C xl = St<S, C>::ld(x + P - 1), xr = St<S, C>::ld(x + P + 4);
+        f[h].bb = *(const V4*)(b + P);
+        f[h].cw = *(const uint2*)(L.code + P);
+        f[h].x1 = sweep_quad_at<S, C>(g, f[h].cw, xb[h], xl, xr, ys, yn, xa[h], xn[h], f[h].bb,
+                                      wj);
+      } else {
+        f[h].x1 = f[h].bb = V4(0);
+        f[h].cw = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      xa[h] = xb[h];
+      xb[h] = xn[h];
+    }
+  };
+  // plane m of the first sweep into LDS buffer m % 3 (the own quads given)
+  auto to_lds = [&](int m, const V4& q0, const V4& q1) {
+    S(*row)[S2_ROW] = lx[m % 3];
+    *(V4*)&row[2 * wy + 1][4 * lane] = q0;
+    *(V4*)&row[2 * wy + 2][4 * lane] = q1;
+    if (wy == 0 || wy == MBY - 1) {
+      const V4 e = xrow ? first4(jx, m).x1 : V4(0);
+      *(V4*)&row[wy == 0 ? 0 : S2_ROWS + 1][4 * lane] = e;
+    }
+  };
+  // prologue: planes k0 - 1 (registers) and k0 (registers and LDS)
+  V4 ym[2], yc[2];
+  V4 bc[2];
+  uint2 cc[2];
+  {
+    FirstQuad<S> f[2];
+    own2(k0 - 1, f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) ym[h] = f[h].x1;
+    own2(k0, f);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      yc[h] = f[h].x1;
+      bc[h] = f[h].bb;
+      cc[h] = f[h].cw;
+    }
+  }
+  to_lds(k0, yc[0], yc[1]);
+  for (int k = k0; k < k1; ++k) {
+    // the first sweep one plane ahead (LDS only if a later plane of this
+    // tile reads it in-plane)
+    FirstQuad<S> fp[2];
+    own2(k + 1, fp);
+    if (k + 1 < k1) to_lds(k + 1, fp[0].x1, fp[1].x1);
+    __syncthreads();
+    S(*row)[S2_ROW] = lx[k % 3];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (live[h] && !halo) {
+        const int lr = 2 * wy + 1 + h;  // this row's LDS row
+        const V4 ys = *(const V4*)&row[lr - 1][4 * lane];
+        const V4 yn = *(const V4*)&row[lr + 1][4 * lane];
+        const C yl = (C)row[lr][4 * lane - 1];
+        const C yr = (C)row[lr][4 * lane + 4];
+        *(V4*)(xout + g.idx(i0, j0 + h, k)) =
+            sweep_quad_at<S, C>(g, cc[h], yc[h], yl, yr, ys, yn, ym[h], fp[h].x1, bc[h], wj);
+      }
+      ym[h] = yc[h];
+      yc[h] = fp[h].x1;
+      bc[h] = fp[h].bb;
+      cc[h] = fp[h].cw;
+    }
+  }
+}
+NFVM_TILE_KERNELS(k_smooth2_code4, smooth2_body, SmoothArgs, (S, C), (class S, class C),
+                  (S, C), MBS, false)
+
+// Whether level l takes two-sweep passes (level 0 with four-cell rows).
+bool sweep_pair(const Level& l) { return l.code && l.g.nx % 4 == 0; }
+
+template <class S, class C>
+void launch_smooth2(const Level& l, const void* xin, void* xout, double wj, const double* ctl,
+                    hipStream_t s) {
+  if constexpr (has_quad<S>) {
+    // tiles of 62 four-cell columns (make_tiles counts 64 per tile) by 8
+    // rows (two per thread)
+    const int nq = l.g.nx / 4, ntx = (nq + S2_QX - 1) / S2_QX;
+    const Tiles T = make_tiles(ntx * MBX, (l.g.ny + 1) / 2, l.g.nz, l.tt[TK_SMOOTH2]);
+    const SmoothArgs<S, C> a{view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl};
+    NFVM_LAUNCH((k_smooth2_code4<S, C>), dim3(T.grid), dim3(MBX, MBY), 0, s, a);
+  }
+}
+
 // ---- residual and restriction: b_c = mean over the 2^dim children of (b - A x)
 // One thread per fine column i and coarse row J: it walks the two fine rows
 // 2J, 2J + 1 plane by plane (the z neighbours of both rows stay in
@@ -2676,6 +2880,10 @@ INST_LEVEL(float, float)
 template void launch_smooth<bf16, float>(const Level&, const void*, void*, double, bool,
                                          const double*, hipStream_t);
 template void launch_fill_zero<bf16>(const Level&, void*, const double*, hipStream_t);
+template void launch_smooth2<double, double>(const Level&, const void*, void*, double,
+                                             const double*, hipStream_t);
+template void launch_smooth2<float, float>(const Level&, const void*, void*, double,
+                                           const double*, hipStream_t);
 
 #define INST_PAIR(S, C, SC)                                                                 \
   template void launch_resid_restrict<S, C, SC>(const Level&, const Level&, const double*,   \

@@ -624,4 +624,121 @@ template void launch_project<float, float, float>(const Geom&, const Phys&, cons
                                                   const float*, const float*, float*, float*,
                                                   float*, float*, const RedBuf&, int, hipStream_t);
 
+// ---- reverse mode of the pressure step ------------------------------------------
+// The step (Sec. 2.4) maps u* to u = u* - dt G(phi), p = p^n + phi with
+// phi = A^-1 b and b = -(1/dt) sum_d D_d L_d BC_d(u*_d) (eq. pc_residual);
+// it is affine in u*.  Its transposed Jacobian, written as gathers over the
+// cells whose forward formulas read a cell: each fluid cell's face average and
+// central difference read its fluid neighbours directly and its own value
+// through the slope of a ghost rule (ghost = s v_P + const, s = ghost(1) -
+// ghost(0)).  Inputs and outputs are dense FP64 [nz][ny][nx]; the solve's
+// right-hand side and solution are the grid's padded vectors.
+__device__ __forceinline__ double ghost_slope(const DevPatch& pp, int fld, int komega) {
+  return ghost<double>(pp, fld, 1.0, komega) - ghost<double>(pp, fld, 0.0, komega);
+}
+
+// phibar = pbar - dt G^T ubar on fluid cells (0 elsewhere), into the solve's
+// right-hand side
+template <class O>
+__global__ __launch_bounds__(BS) void k_adj_phibar(Geom g, Phys ph, const uint8_t* __restrict__ type,
+                                                   const DevPatch* __restrict__ pt,
+                                                   const double* __restrict__ ub,
+                                                   const double* __restrict__ vb,
+                                                   const double* __restrict__ wb,
+                                                   const double* __restrict__ pb,
+                                                   O* __restrict__ rhs) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int C0 = g.idx(i, j, k);
+  const long long n = ((long long)k * g.ny + j) * g.nx + i;
+  if (!is_fluid(type[C0])) {
+    rhs[C0] = (O)0;
+    return;
+  }
+  const double* bar[3] = {ub, vb, wb};
+  const int st[3] = {1, g.sx, g.sxy};
+  const long long sd[3] = {1, g.nx, (long long)g.nx * g.ny};
+  const double h[3] = {g.hx, g.hy, g.hz};
+  double acc = pb[n];
+  for (int d = 0; d < g.dim; ++d) {
+    const double f = ph.dt / (2.0 * h[d]);
+    const uint8_t tl = type[C0 - st[d]], th = type[C0 + st[d]];
+    const double uP = bar[d][n];
+    if (is_fluid(tl))
+      acc -= f * bar[d][n - sd[d]];
+    else
+      acc += f * uP * ghost_slope(pt[tl & 0x7f], G_P, ph.komega);
+    if (is_fluid(th))
+      acc += f * bar[d][n + sd[d]];
+    else
+      acc -= f * uP * ghost_slope(pt[th & 0x7f], G_P, ph.komega);
+  }
+  rhs[C0] = (O)acc;
+}
+
+// usbar = ubar + (d b / d u*)^T lambda (fluid cells; ubar elsewhere)
+template <class O>
+__global__ __launch_bounds__(BS) void k_adj_velocity(Geom g, Phys ph, const uint8_t* __restrict__ type,
+                                                     const DevPatch* __restrict__ pt,
+                                                     const O* __restrict__ lam,
+                                                     const double* __restrict__ ub,
+                                                     const double* __restrict__ vb,
+                                                     const double* __restrict__ wb,
+                                                     double* __restrict__ usb,
+                                                     double* __restrict__ vsb,
+                                                     double* __restrict__ wsb) {
+  const int i = blockIdx.x * BX + threadIdx.x, j = blockIdx.y * BY + threadIdx.y, k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int C0 = g.idx(i, j, k);
+  const long long n = ((long long)k * g.ny + j) * g.nx + i;
+  const double* bar[3] = {ub, vb, wb};
+  double* out[3] = {usb, vsb, wsb};
+  const bool fl = is_fluid(type[C0]);
+  const int st[3] = {1, g.sx, g.sxy};
+  const double h[3] = {g.hx, g.hy, g.hz};
+  for (int d = 0; d < 3; ++d) {
+    double acc = bar[d][n];
+    if (fl && d < g.dim) {
+      // s_Y = -lambda_Y / (dt h_d): d b_Y / d (face average) of a face of Y
+      const double c = -1.0 / (ph.dt * h[d]);
+      const double sP = c * (double)lam[C0];
+      const uint8_t tl = type[C0 - st[d]], th = type[C0 + st[d]];
+      if (is_fluid(tl))
+        acc += 0.5 * c * (double)lam[C0 - st[d]];
+      else
+        acc -= 0.5 * sP * ghost_slope(pt[tl & 0x7f], G_U + d, ph.komega);
+      if (is_fluid(th))
+        acc -= 0.5 * c * (double)lam[C0 + st[d]];
+      else
+        acc += 0.5 * sP * ghost_slope(pt[th & 0x7f], G_U + d, ph.komega);
+    }
+    out[d][n] = acc;
+  }
+}
+
+template <class O>
+void launch_adj_phibar(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                       const double* ub, const double* vb, const double* wb, const double* pb,
+                       O* rhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_phibar<O>, cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, ub, vb,
+                     wb, pb, rhs);
+}
+template <class O>
+void launch_adj_velocity(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                         const O* lam, const double* ub, const double* vb, const double* wb,
+                         double* usb, double* vsb, double* wsb, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_velocity<O>, cell_grid(g), dim3(BX, BY), 0, s, g, ph, type, pt, lam,
+                     ub, vb, wb, usb, vsb, wsb);
+}
+#define INST_ADJ(O)                                                                             \
+  template void launch_adj_phibar<O>(const Geom&, const Phys&, const uint8_t*, const DevPatch*, \
+                                     const double*, const double*, const double*, const double*, \
+                                     O*, hipStream_t);                                          \
+  template void launch_adj_velocity<O>(const Geom&, const Phys&, const uint8_t*,                \
+                                       const DevPatch*, const O*, const double*, const double*, \
+                                       const double*, double*, double*, double*, hipStream_t);
+INST_ADJ(double)
+INST_ADJ(float)
+
 }  // namespace nfvm
+

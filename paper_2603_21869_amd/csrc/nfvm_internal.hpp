@@ -132,6 +132,7 @@ enum {
   TK_START,
   TK_APPLY,
   TK_UPDATE,
+  TK_SMOOTH2,   // two level-0 sweeps in one pass
   TK_LEVEL_COUNT
 };
 enum { TP_EXPLICIT = 0, TP_DESTROY, TP_RHS, TP_PROJECT, TP_COUNT };
@@ -281,6 +282,12 @@ void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const De
 template <class S, class C>
 void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                    const double* ctl, hipStream_t s);
+// Two sweeps in one pass on a level that takes them (sweep_pair: level 0
+// with nx a multiple of 4); bitwise the result of two launch_smooth calls.
+bool sweep_pair(const Level& l);
+template <class S, class C>
+void launch_smooth2(const Level& l, const void* xin, void* xout, double wj, const double* ctl,
+                    hipStream_t s);
 template <class S, class C, class SC>
 void launch_resid_restrict(const Level& f, const Level& c, const double* ctl, hipStream_t s,
                            void* zc = nullptr, double wj = 0.0);

@@ -33,7 +33,7 @@ EXPORTS = (
 
 KERNELS = ("smooth0", "smooth0_zero", "restrict0", "prolong0", "explicit", "destroy", "rhs",
            "project", "fcg_apply", "fcg_update", "smooth_coarse", "restrict_coarse",
-           "prolong_coarse", "bottom", "fcg_start", "finalize")
+           "prolong_coarse", "bottom", "fcg_start", "finalize", "smooth0_pair")
 
 
 class nfvm_patch(C.Structure):
@@ -301,6 +301,7 @@ NFVM_OPT_WARM_START = 4
 NFVM_OPT_PROLONG = 5
 NFVM_OPT_RK_ORDER = 6
 NFVM_OPT_LITERAL = 7
+NFVM_OPT_SWEEP_PAIRS = 8
 
 
 def nfvm_tuning_table():

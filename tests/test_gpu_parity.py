@@ -363,6 +363,40 @@ def test_mixed_coarse_storage_matches_oracle(nf, oracle, lim):
         g.close()
 
 
+@pytest.mark.parametrize("nu", [(3, 3), (4, 4), (2, 3), (3, 2), (2, 2)],
+                         ids=["nu33", "nu44", "nu23", "nu32", "nu22"])
+def test_sweep_pairs_equal_single_sweeps(nf, nu):
+    """Two level-0 sweeps per pass (NFVM_OPT_SWEEP_PAIRS, the default) give
+    bitwise the fields, cycle counts and residuals of one sweep per pass, in
+    FP64 and mixed precision, on a channel and on a room with solid blocks
+    (rows a multiple of 4 cells, several z tiles), with the pair kernel
+    launched wherever the schedule allows pairs."""
+    cases = [C.channel3d(64, 16, 16, Lx=1.28, Ly=0.32, Lz=0.32, n_levels=3, n_steps=2),
+             C.room3d(64, 32, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4, n_steps=2)]
+    for base in cases:
+        for prec in (C.PREC_FP64, C.PREC_MIXED):
+            case = base.copy(precision=prec, tol=1e-9, nu1=nu[0], nu2=nu[1])
+            out, stats = {}, {}
+            for pairs in (0.0, 1.0):
+                g = nf.Grid(case)
+                nf.nfvm_set_option(g.h, nf.NFVM_OPT_SWEEP_PAIRS, pairs)
+                nf.nfvm_profile(g.h, 1 << nf.KERNELS.index("smooth0_pair"))
+                s, st = g.step(2)
+                used = nf.nfvm_profile_read(g.h, nf.KERNELS.index("smooth0_pair"))["launches"]
+                out[pairs], stats[pairs] = g.fields(), st
+                g.close()
+                print(f"   {case.name} prec={prec} nu={nu} pairs={pairs}: "
+                      f"{[x['cycles'] for x in st]} cycles, {used} pair launches", flush=True)
+                if pairs == 0.0:
+                    assert used == 0
+                elif nu != (2, 2):
+                    assert used > 0
+            for k in out[0.0]:
+                assert np.array_equal(out[0.0][k], out[1.0][k]), (case.name, prec, k)
+            for a, b in zip(stats[0.0], stats[1.0]):
+                assert a["cycles"] == b["cycles"] and a["rel_residual"] == b["rel_residual"]
+
+
 def _nearest_cases():
     return [
         ("ch2d", C.channel2d(96, 18, L=4.0, H=1.0, n_levels=2, n_steps=2)),
