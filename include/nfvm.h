@@ -186,6 +186,39 @@ nfvm_status nfvm_mg_solve_device(nfvm_grid_t grid, const double* b_dev, double* 
                                  double tol, int32_t max_cycles, int32_t forced_cycles,
                                  nfvm_step_stats* stats);
 
+/* Reverse mode of the pressure solve (the paper's solver is differentiable,
+ * Sec. 1 and 4): for the adjoint xbar of the solution of A x = b, the adjoint
+ * of the right-hand side is bbar = A^-T xbar, and A (eq. pc_discretized) is
+ * symmetric, so this is the same multigrid solve with xbar on the right.  The
+ * solution is differentiated as the exact A^-1 b (implicit differentiation),
+ * not through the iterations that approximate it.  xbar_dev, bbar_dev: device
+ * FP64 [nz][ny][nx]; bbar_dev holds the initial guess on entry (zeros for
+ * none) and bbar on exit.  Tolerance, forced cycles, stats and errors as
+ * nfvm_mg_solve_device. */
+nfvm_status nfvm_mg_solve_adjoint_device(nfvm_grid_t grid, const double* xbar_dev,
+                                         double* bbar_dev, double tol, int32_t max_cycles,
+                                         int32_t forced_cycles, nfvm_step_stats* stats);
+
+/* Reverse mode of the pressure step (Sec. 2.4): the map from the explicit
+ * step's velocity u* and the pressure p^n to u = u* - dt G(phi) and
+ * p = p^n + phi, where phi = A^-1 b and b = -(1/dt) sum_d D_d L_d BC_d(u*_d)
+ * (eq. pc_residual), with the boundary ghosts of Sec. 2.7, is affine in u*.
+ * For the adjoints ubar, vbar, wbar, pbar of u, v, w and p it writes the
+ * adjoints of u*, v*, w* into usbar, vsbar, wsbar (that of p^n is pbar
+ * itself): usbar = ubar + (dB/du*)^T lambda with lambda = A^-T (pbar -
+ * dt G^T ubar), one multigrid solve (to tol, or forced_cycles; the solve is
+ * differentiated as the exact one).  All arrays device FP64 [nz][ny][nx],
+ * all seven required (in 2D w is passed through: wsbar = wbar); outputs may
+ * not alias inputs.  Runs on the grid's stream and waits for it; the grid's
+ * fields are not touched.  stats: NULL or one entry (the solve's cycles,
+ * status, relative residual and time).  Errors as nfvm_mg_solve_device;
+ * NFVM_E_INVAL for a null pointer. */
+nfvm_status nfvm_pressure_adjoint_device(nfvm_grid_t grid, const double* ubar,
+                                         const double* vbar, const double* wbar,
+                                         const double* pbar, double* usbar, double* vsbar,
+                                         double* wsbar, double tol, int32_t max_cycles,
+                                         int32_t forced_cycles, nfvm_step_stats* stats);
+
 /* For callers that cannot allocate device memory (code that must not call
  * hipMalloc: tight serving loops, harnesses that forbid allocation):
  * nfvm_mg_solve_device without any device allocation.  The solve's

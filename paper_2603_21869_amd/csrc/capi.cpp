@@ -147,6 +147,30 @@ nfvm_status nfvm_mg_solve_device(nfvm_grid_t grid, const double* b_dev, double* 
   });
 }
 
+nfvm_status nfvm_mg_solve_adjoint_device(nfvm_grid_t grid, const double* xbar_dev,
+                                         double* bbar_dev, double tol, int32_t max_cycles,
+                                         int32_t forced_cycles, nfvm_step_stats* stats) {
+  // A is symmetric: the adjoint solve is the solve with xbar on the right
+  return nfvm_mg_solve_device(grid, xbar_dev, bbar_dev, tol, max_cycles, forced_cycles, stats);
+}
+
+nfvm_status nfvm_pressure_adjoint_device(nfvm_grid_t grid, const double* ubar,
+                                         const double* vbar, const double* wbar,
+                                         const double* pbar, double* usbar, double* vsbar,
+                                         double* wsbar, double tol, int32_t max_cycles,
+                                         int32_t forced_cycles, nfvm_step_stats* stats) {
+  if (!grid || !ubar || !vbar || !wbar || !pbar || !usbar || !vsbar || !wsbar)
+    return fail(NFVM_E_INVAL, "grid and all seven arrays are required");
+  return guard([&] {
+    nfvm_status st = NFVM_OK;
+    grid->g->pressure_adjoint(ubar, vbar, wbar, pbar, usbar, vsbar, wsbar, tol, max_cycles,
+                              forced_cycles, stats, &st);
+    if (st == NFVM_E_NOTCONV) set_error("adjoint pressure solve reached max_cycles");
+    if (st == NFVM_E_DIVERGED) set_error("non-finite residual");
+    return st;
+  });
+}
+
 nfvm_status nfvm_mg_solve(nfvm_grid_t grid, const double* b, double* x, double tol,
                           int32_t max_cycles, int32_t forced_cycles, nfvm_step_stats* stats) {
   if (!grid || !b || !x) return fail(NFVM_E_INVAL, "grid, b and x are required");

@@ -1235,6 +1235,38 @@ class GridT : public GridBase {
     *status = st;
   }
 
+  void pressure_adjoint(const double* ub, const double* vb, const double* wb, const double* pb,
+                        double* usb, double* vsb, double* wsb, double tol_, int maxc, int forced,
+                        nfvm_step_stats* stt, nfvm_status* status) override {
+    NFVM_CK(hipEventRecord(ev0, stream));
+    // lambda = A^-1 (pbar - dt G^T ubar), then usbar = ubar + (dB/du*)^T lambda
+    launch_adj_phibar<O>(g, ph, type, patches, ub, vb, wb, pb, bvec, stream);
+    NFVM_CK(hipGetLastError());
+    int cyc = 0;
+    double rel = 0;
+    last_diag.clear();
+    nfvm_status st = solve(false, tol_, maxc, forced, &cyc, &rel);
+    if (st == NFVM_E_DIVERGED) last_diag = diagnose();
+    launch_adj_velocity<O>(g, ph, type, patches, phi, ub, vb, wb, usb, vsb, wsb, stream);
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipEventRecord(ev1, stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+    prof_collect();
+    clear_increment();  // (phi held lambda; it is not the step's increment)
+    NFVM_CK(hipStreamSynchronize(stream));
+    float ms = 0;
+    NFVM_CK(hipEventElapsedTime(&ms, ev0, ev1));
+    if (stt) {
+      memset(stt, 0, sizeof *stt);
+      stt->cycles = cyc;
+      stt->status = st;
+      stt->rel_residual = rel;
+      stt->seconds = ms * 1e-3;
+      stt->min_k = stt->min_omega = NAN;
+    }
+    *status = st;
+  }
+
   void mg_solve_scratch(const double* b_dev, double* x_dev, double tol_, int maxc, int forced,
                         nfvm_step_stats* stt, nfvm_status* status, double* scratch,
                         size_t n_doubles) override {

@@ -114,6 +114,12 @@ class GridBase {
 
   virtual void mg_solve(const double* b_dev, double* x_dev, double tol, int max_cycles, int forced,
                         nfvm_step_stats* st, nfvm_status* status) = 0;
+  // Reverse mode of the pressure step: the adjoints of u*, v*, w* (dense
+  // device FP64) for those of the step's velocity and pressure.
+  virtual void pressure_adjoint(const double* ub, const double* vb, const double* wb,
+                                const double* pb, double* usb, double* vsb, double* wsb,
+                                double tol, int max_cycles, int forced, nfvm_step_stats* st,
+                                nfvm_status* status) = 0;
   // The same solve with its reduction partials and scalars in the n_doubles
   // doubles of device memory at scratch (256-byte aligned) instead of the
   // grid's own, launched without the captured graphs; allocates nothing.

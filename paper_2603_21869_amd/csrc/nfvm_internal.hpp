@@ -282,6 +282,16 @@ void launch_project(const Geom& g, const Phys& ph, const uint8_t* type, const De
 template <class S, class C>
 void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                    const double* ctl, hipStream_t s);
+// Reverse mode of the pressure step (dense FP64 adjoints; rhs and lam are the
+// solve's padded right-hand side and solution in the outer type O).
+template <class O>
+void launch_adj_phibar(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                       const double* ub, const double* vb, const double* wb, const double* pb,
+                       O* rhs, hipStream_t s);
+template <class O>
+void launch_adj_velocity(const Geom& g, const Phys& ph, const uint8_t* type, const DevPatch* pt,
+                         const O* lam, const double* ub, const double* vb, const double* wb,
+                         double* usb, double* vsb, double* wsb, hipStream_t s);
 // Two sweeps in one pass on a level that takes them (sweep_pair: level 0
 // with nx a multiple of 4); bitwise the result of two launch_smooth calls.
 bool sweep_pair(const Level& l);

@@ -23,7 +23,8 @@ _dp = C.POINTER(C.c_double)
 
 EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_step_batch", "nfvm_mg_solve",
-    "nfvm_mg_solve_device", "nfvm_mg_solve_device_noalloc",
+    "nfvm_mg_solve_device", "nfvm_mg_solve_device_noalloc", "nfvm_mg_solve_adjoint_device",
+    "nfvm_pressure_adjoint_device",
     "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_grid_footprint",
     "nfvm_reduction_blocks", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
@@ -95,6 +96,11 @@ def lib():
         L.nfvm_mg_solve_device_noalloc.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p,
                                                    C.c_double, C.c_int32, C.c_int32,
                                                    C.POINTER(nfvm_step_stats)]
+        L.nfvm_mg_solve_adjoint_device.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p,
+                                                   C.c_double, C.c_int32, C.c_int32,
+                                                   C.POINTER(nfvm_step_stats)]
+        L.nfvm_pressure_adjoint_device.argtypes = [C.c_void_p] + [C.c_void_p] * 7 + [
+            C.c_double, C.c_int32, C.c_int32, C.POINTER(nfvm_step_stats)]
         L.nfvm_get_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
         L.nfvm_lambda2.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
         L.nfvm_set_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
@@ -233,6 +239,28 @@ def nfvm_mg_solve_device(grid, b_ptr: int, x_ptr: int, tol: float = 1e-10, max_c
     st = nfvm_step_stats()
     s = _check(lib().nfvm_mg_solve_device(grid, C.c_void_p(b_ptr), C.c_void_p(x_ptr), tol,
                                           max_cycles, forced_cycles, C.byref(st)), allow)
+    return st.as_dict(), s
+
+
+def nfvm_mg_solve_adjoint_device(grid, xbar_ptr: int, bbar_ptr: int, tol: float = 1e-10,
+                                 max_cycles: int = 100, forced_cycles: int = -1,
+                                 allow=(NFVM_OK,)):
+    """bbar = A^-T xbar on device FP64 arrays (bbar: initial guess in, result out)."""
+    st = nfvm_step_stats()
+    s = _check(lib().nfvm_mg_solve_adjoint_device(grid, C.c_void_p(xbar_ptr),
+                                                  C.c_void_p(bbar_ptr), tol, max_cycles,
+                                                  forced_cycles, C.byref(st)), allow)
+    return st.as_dict(), s
+
+
+def nfvm_pressure_adjoint_device(grid, bars, outs, tol: float = 1e-10, max_cycles: int = 100,
+                                 forced_cycles: int = -1, allow=(NFVM_OK,)):
+    """Reverse mode of the pressure step on device FP64 arrays: bars = device
+    pointers of (ubar, vbar, wbar, pbar), outs = those of (usbar, vsbar, wsbar)."""
+    st = nfvm_step_stats()
+    s = _check(lib().nfvm_pressure_adjoint_device(grid, *[C.c_void_p(p) for p in bars],
+                                                  *[C.c_void_p(p) for p in outs], tol,
+                                                  max_cycles, forced_cycles, C.byref(st)), allow)
     return st.as_dict(), s
 
 

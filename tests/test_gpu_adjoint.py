@@ -1,0 +1,99 @@
+"""Reverse mode of the pressure solve and of the pressure step on the GPU
+(through the C ABI) against the oracle's reverse mode, which is pinned by
+its assembled Jacobian and a dot-product test (tests/test_oracle_adjoint.py).
+Bars as for the forward parity tests: FP64 1e-10 with the oracle running the
+GPU's cycle count, mixed 1e-6 with both solves stopped at 1e-9."""
+import numpy as np
+import pytest
+
+from paper_2603_21869_amd import cases as C
+from tests.parity import fluid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2603_21869_amd import nfvm
+    nfvm.lib()
+    return nfvm
+
+
+def _cases():
+    return [
+        ("ch2d", C.channel2d(96, 18, L=4.0, H=1.0, n_levels=2)),
+        ("ch3d", C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3)),
+        ("room", C.room3d(64, 24, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4)),
+        ("open", C.open_channel(48, 16, 16, h=0.02, n_levels=3, precision=C.PREC_FP64)),
+    ]
+
+
+def _rel(a, b, m):
+    d = (a - b)[m]
+    return (float(np.linalg.norm(d) / max(np.linalg.norm(b[m]), 1e-300)),
+            float(np.abs(d).max() / max(np.abs(b[m]).max(), 1e-300)))
+
+
+def test_mg_solve_adjoint_is_the_transposed_solve(nf, oracle):
+    """<A^-1 b, c> = <b, A^-T c> with both solves on the GPU, and A^-T c
+    against the oracle's solve run the GPU's cycle count."""
+    import torch
+    case = C.room3d(64, 32, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4,
+                    precision=C.PREC_FP64)
+    g = nf.Grid(case)
+    m = fluid(case)
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(g.shape) * m
+    c = rng.standard_normal(g.shape) * m
+    bd, cd = torch.from_numpy(b).cuda(), torch.from_numpy(c).cuda()
+    x, y = torch.zeros_like(bd), torch.zeros_like(cd)
+    s1, _ = nf.nfvm_mg_solve_device(g.h, bd.data_ptr(), x.data_ptr(), tol=1e-13, max_cycles=200)
+    s2, _ = nf.nfvm_mg_solve_adjoint_device(g.h, cd.data_ptr(), y.data_ptr(), tol=1e-13,
+                                            max_cycles=200)
+    torch.cuda.synchronize()
+    x, y = x.cpu().numpy(), y.cpu().numpy()
+    g.close()
+    lhs, rhs = float(np.sum(x * c)), float(np.sum(b * y))
+    print(f"   <A^-1 b, c> = {lhs:.15e}, <b, A^-T c> = {rhs:.15e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+    yr, cyc, rel, st = oracle.MG(case).solve(c, forced=s2["cycles"])
+    assert max(_rel(y, yr, m)) <= 1e-10
+
+
+@pytest.mark.parametrize("prec", [C.PREC_FP64, C.PREC_MIXED], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("name,case", _cases(), ids=[c[0] for c in _cases()])
+def test_pressure_adjoint_matches_oracle(nf, oracle, name, case, prec):
+    import torch
+    case = case.copy(precision=prec)
+    g = nf.Grid(case)
+    sh = g.shape
+    rng = np.random.default_rng(17)
+    bars = [rng.standard_normal(sh) for _ in range(4)]
+    if case.dim == 2:
+        bars[2][:] = 0.0
+    dev = [torch.from_numpy(a).cuda() for a in bars]
+    outs = [torch.zeros_like(dev[0]) for _ in range(3)]
+    tol = 1e-12 if prec == C.PREC_FP64 else 1e-9
+    st, s = nf.nfvm_pressure_adjoint_device(g.h, [a.data_ptr() for a in dev],
+                                            [o.data_ptr() for o in outs], tol=tol,
+                                            max_cycles=200)
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o in outs]
+    g.close()
+    forced = st["cycles"] if prec == C.PREC_FP64 else -1
+    ref = oracle.pressure_adjoint(case.copy(precision=C.PREC_FP64), *bars,
+                                  tol=1e-12 if forced < 0 else 1e-30, max_cycles=400,
+                                  forced=forced)
+    bar = 1e-10 if prec == C.PREC_FP64 else 1e-6
+    everywhere = np.ones(sh, bool)
+    for d in range(3):
+        err = _rel(got[d], ref[d], everywhere)
+        print(f"   {name} prec={prec} cycles={st['cycles']} component {d}: L2 {err[0]:.2e} "
+              f"max {err[1]:.2e}", flush=True)
+        assert max(err) <= bar, (d, err)
+    # non-fluid cells pass their adjoint through unchanged
+    m = fluid(case)
+    for d in range(3):
+        assert np.array_equal(got[d][~m], bars[d][~m])
