@@ -426,6 +426,14 @@ enum {
   NFVM_OPT_SWEEP_PAIRS = 8
 };
 
+/* Tune the tile shapes of a grid shape and precision ahead of serving:
+ * creates a grid of the descriptor with the autotuner on, on a stream of its
+ * own, and frees it; the choices stay in the process-wide table.  Served
+ * grids never tune: a shape that is in the table takes its choices, another
+ * takes those of the tuned shape of the same dimension and precision nearest
+ * in cell count (log scale), else the defaults.  Errors as nfvm_init_grid. */
+nfvm_status nfvm_tune(const nfvm_grid_desc* desc);
+
 /* The autotuner's choices so far: up to max entries of {kernel id, nx, ny,
  * nz, dim, precision, tile target}; *count receives the number written. */
 nfvm_status nfvm_tuning_table(int32_t* entries, int32_t max, int32_t* count);

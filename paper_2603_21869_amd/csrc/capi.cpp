@@ -284,6 +284,16 @@ nfvm_status nfvm_set_option(nfvm_grid_t grid, int32_t option, double value) {
   });
 }
 
+nfvm_status nfvm_tune(const nfvm_grid_desc* desc) {
+  if (!desc) return fail(NFVM_E_INVAL, "desc is required");
+  return guard([&] {
+    auto g = make_grid(*desc, nullptr, nullptr, 1);
+    NFVM_CK(hipStreamSynchronize(g->stream));
+    g.reset();
+    return NFVM_OK;
+  });
+}
+
 nfvm_status nfvm_tuning_table(int32_t* entries, int32_t max, int32_t* count) {
   if (!count || (max > 0 && !entries)) return fail(NFVM_E_INVAL, "count and entries are required");
   auto all = tune_entries();

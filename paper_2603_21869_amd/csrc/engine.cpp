@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <mutex>
 
@@ -165,6 +166,26 @@ bool tune_lookup(const TuneKey& k, int* v) {
   if (it == g_tune.end()) return false;
   *v = it->second;
   return true;
+}
+
+bool tune_lookup_near(const TuneKey& k, int* v) {
+  // the entry of the same kernel, dimension and precision whose shape has
+  // the closest cell count (log scale; ties to the smaller shape)
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const double want = std::log((double)k.nx * k.ny * k.nz);
+  double best = 1e300;
+  bool found = false;
+  for (const auto& kv : g_tune) {
+    const TuneKey& e = kv.first;
+    if (e.kid != k.kid || e.dim != k.dim || e.prec != k.prec) continue;
+    const double d = std::fabs(std::log((double)e.nx * e.ny * e.nz) - want);
+    if (d < best) {
+      best = d;
+      *v = kv.second;
+      found = true;
+    }
+  }
+  return found;
 }
 
 void tune_store(const TuneKey& k, int v) {
@@ -559,7 +580,9 @@ class GridT : public GridBase {
     TuneKey key{kid, gg.nx, gg.ny, gg.nz, desc.dim, desc.precision};
     int cached;
     if (tune_lookup(key, &cached)) return cached;
-    if (tune_cached_only) return TILE_DEFAULT;
+    // served grids never tune: the choice of the tuned shape nearest in
+    // size, else the default
+    if (tune_cached_only) return tune_lookup_near(key, &cached) ? cached : TILE_DEFAULT;
     int best = TILE_DEFAULT;
     float bt = 1e30f;
     for (int ci = 0; ci < N_TILE_CANDIDATES; ++ci) {

@@ -69,6 +69,9 @@ struct TuneKey {
   }
 };
 bool tune_lookup(const TuneKey& k, int* v);
+// The cached choice of the same kernel, dimension and precision at the shape
+// nearest in cell count (false: none cached yet).
+bool tune_lookup_near(const TuneKey& k, int* v);
 void tune_store(const TuneKey& k, int v);
 std::vector<std::pair<TuneKey, int>> tune_entries();
 void validate_desc(const nfvm_grid_desc& d);

@@ -24,7 +24,7 @@ _dp = C.POINTER(C.c_double)
 EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_step_batch", "nfvm_mg_solve",
     "nfvm_mg_solve_device", "nfvm_mg_solve_device_noalloc", "nfvm_mg_solve_adjoint_device",
-    "nfvm_pressure_adjoint_device",
+    "nfvm_pressure_adjoint_device", "nfvm_tune",
     "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_grid_footprint",
     "nfvm_reduction_blocks", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
@@ -121,6 +121,7 @@ def lib():
                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.nfvm_set_option.argtypes = [C.c_void_p, C.c_int32, C.c_double]
         L.nfvm_tuning_table.argtypes = [C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int32)]
+        L.nfvm_tune.argtypes = [C.POINTER(nfvm_grid_desc)]
         L.nfvm_last_error.restype = C.c_char_p
         for name in EXPORTS:
             if name != "nfvm_last_error":
@@ -330,6 +331,11 @@ NFVM_OPT_PROLONG = 5
 NFVM_OPT_RK_ORDER = 6
 NFVM_OPT_LITERAL = 7
 NFVM_OPT_SWEEP_PAIRS = 8
+
+
+def nfvm_tune(desc: Desc):
+    """Tune the tile shapes of a descriptor's shape and precision (no grid kept)."""
+    _check(lib().nfvm_tune(C.byref(desc.d)))
 
 
 def nfvm_tuning_table():

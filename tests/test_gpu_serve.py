@@ -103,3 +103,16 @@ def test_failed_request_does_not_disturb_others(nf):
     s, out, st = nf.nfvm_poll(srv, tg, (reqs[1].n[2], reqs[1].n[1], reqs[1].n[0]))
     assert s == nf.NFVM_OK and np.isfinite(out["u"]).all()
     nf.nfvm_server_destroy(srv)
+
+
+def test_tune_fills_the_table(nf):
+    """nfvm_tune records the tile choices of a shape before any grid of it is
+    kept; a second call for the same shape adds nothing."""
+    case = C.serve_case(dict(n=(64, 32, 32), geometry="channel", seed=3, n_steps=1))
+    before = len(nf.nfvm_tuning_table())
+    nf.nfvm_tune(nf.Desc(case))
+    after = len(nf.nfvm_tuning_table())
+    nf.nfvm_tune(nf.Desc(case))
+    assert after >= before and len(nf.nfvm_tuning_table()) == after
+    shapes = {(e[1], e[2], e[3]) for e in nf.nfvm_tuning_table()}
+    assert (64, 32, 32) in shapes
