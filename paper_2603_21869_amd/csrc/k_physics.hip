@@ -55,6 +55,20 @@ template void launch_unpack<float>(const Geom&, const float*, double*, double, h
 // f_beta omega) with cell-centred central gradients (face derivative D, then
 // average L) feeding chi_k and chi_omega; every right-hand side uses the
 // input k and omega.  Fixed wall cells keep omega.
+// The values a cell's gradients read from one neighbour (loaded whatever the
+// neighbour's kind; every index lies in the padded arrays).
+template <class R>
+struct DestroyNb {
+  uint8_t t;
+  R u[3], k, w;
+};
+
+// Each thread walks the planes of its column: the cells below and above stay
+// in registers (the cell above becomes the next centre), so a plane loads
+// its own cell's row neighbours and the cell above once.  The vortex
+// stretching Omega_ij Omega_jk S_ki is tr(W W S) with W the antisymmetric
+// part of the gradient; for W = [a]x (the cross-product matrix of a),
+// W W = a a^T - |a|^2 I, so it is a^T S a - |a|^2 tr S.
 template <class V, class F, bool RED>
 __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                 const DevPatch* __restrict__ pt,
@@ -68,79 +82,90 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
   const bool tile = tile_of(T, tx, ty, tz);
   const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
   const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
+  const bool d3 = g.dim == 3;
   double mk = INFINITY, mw = INFINITY;
-  if (tile && i < g.nx && j < g.ny)
-  for (int k = kb; k < ke; ++k) {
-    const int P = g.idx(i, j, k);
-    const uint8_t tp = type[P];
-    const R kP = kk[P], wP = om[P];
-    R kn = kP, wn = wP;
-    if (is_fluid(tp)) {
-      const R vel[3] = {u[P], v[P], w[P]};
-      R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      R gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
-      const int st[3] = {1, g.sx, g.sxy};
-      const R ih2[3] = {(R)(0.5 / g.hx), (R)(0.5 / g.hy), (R)(0.5 / g.hz)};
-      // constant trip counts keep G, gk and gw in registers
+  auto load = [&](int N) {
+    DestroyNb<R> c;
+    c.t = type[N];
+    c.u[0] = u[N];
+    c.u[1] = v[N];
+    c.u[2] = w[N];
+    c.k = kk[N];
+    c.w = om[N];
+    return c;
+  };
+  const R inu = (R)(1.0 / ph.nu);
+  if (tile && i < g.nx && j < g.ny) {
+    int P = g.idx(i, j, kb);
+    DestroyNb<R> cm, cc = load(P);
+    if (d3) cm = load(P - g.sxy);
+    for (int k = kb; k < ke; ++k, P += g.sxy) {
+      DestroyNb<R> cp;
+      if (d3) cp = load(P + g.sxy);
+      const uint8_t tp = cc.t;
+      const R kP = cc.k, wP = cc.w;
+      R kn = kP, wn = wP;
+      if (is_fluid(tp)) {
+        R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        R gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+        const int st[2] = {1, g.sx};
+        const R ih2[3] = {(R)(0.5 / g.hx), (R)(0.5 / g.hy), (R)(0.5 / g.hz)};
+        // constant trip counts keep G, gk and gw in registers
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
+        for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int s = -1; s <= 1; s += 2) {
-          if (d >= g.dim) continue;
-          const int N = P + s * st[d];
-          const uint8_t tn = type[N];
-          // loaded whatever the neighbour's kind (every index lies in the
-          // padded arrays), so the loads do not wait for its type byte
-          R vn[3] = {(R)u[N], (R)v[N], (R)w[N]};
-          R kn_ = kk[N], wn_ = om[N];
-          if (!is_fluid(tn)) {
-            const DevPatch& pp = pt[tn & 0x7f];
-            for (int a = 0; a < 3; ++a) vn[a] = ghost<R>(pp, G_U + a, vel[a], ph.komega);
-            kn_ = ghost<R>(pp, G_K, kP, ph.komega);
-            wn_ = ghost<R>(pp, G_OM, wP, ph.komega);
+          for (int s = -1; s <= 1; s += 2) {
+            if (d >= g.dim) continue;
+            DestroyNb<R> n = d == 2 ? (s < 0 ? cm : cp) : load(P + s * st[d]);
+            if (!is_fluid(n.t)) {
+              const DevPatch& pp = pt[n.t & 0x7f];
+              for (int a = 0; a < 3; ++a) n.u[a] = ghost<R>(pp, G_U + a, cc.u[a], ph.komega);
+              n.k = ghost<R>(pp, G_K, kP, ph.komega);
+              n.w = ghost<R>(pp, G_OM, wP, ph.komega);
+            }
+            const R sc = (R)s * ih2[d];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+              if (a < g.dim) G[a][d] += sc * n.u[a];
+            gk[d] += sc * n.k;
+            gw[d] += sc * n.w;
           }
-          const R sc = (R)s * ih2[d];
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-            if (a < g.dim) G[a][d] += sc * vn[a];
-          gk[d] += sc * kn_;
-          gw[d] += sc * wn_;
+        const R oh = omhat(wP);
+        const R ioh = (R)1 / oh;
+        const R ioh3 = ioh * ioh * ioh;
+        const R dkdw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
+        const R chik = dkdw * ioh3;
+        const R fbs = chik <= (R)0 ? (R)1
+                                   : ((R)1 + (R)680 * chik * chik) / ((R)1 + (R)400 * chik * chik);
+        const R ret = kP * ioh * inu;
+        const R x = ret * (R)(1.0 / C_R_BETA);
+        const R x2 = x * x;
+        const R x4 = x2 * x2;
+        // 0.09 (4/15 + x^4)/(1 + x^4), written so that x^4 = inf gives 0.09
+        const R bst = (R)C_BSTAR * ((R)1 - (R)(11.0 / 15.0) / ((R)1 + x4));
+        kn = kP / ((R)1 + tau * bst * fbs * wP);
+        if (!(tp & FIXED_BIT)) {
+          const R a0 = (R)0.5 * (G[2][1] - G[1][2]), a1 = (R)0.5 * (G[0][2] - G[2][0]),
+                  a2 = (R)0.5 * (G[1][0] - G[0][1]);
+          const R s01 = (R)0.5 * (G[0][1] + G[1][0]), s02 = (R)0.5 * (G[0][2] + G[2][0]),
+                  s12 = (R)0.5 * (G[1][2] + G[2][1]);
+          const R aSa = a0 * a0 * G[0][0] + a1 * a1 * G[1][1] + a2 * a2 * G[2][2] +
+                        (R)2 * (a0 * a1 * s01 + a0 * a2 * s02 + a1 * a2 * s12);
+          const R X = aSa - (a0 * a0 + a1 * a1 + a2 * a2) * (G[0][0] + G[1][1] + G[2][2]);
+          const R chiw = fabs(X) * ioh3 * (R)(1.0 / (C_BSTAR * C_BSTAR * C_BSTAR));
+          const R fb = ((R)1 + (R)70 * chiw) / ((R)1 + (R)80 * chiw);
+          wn = wP / ((R)1 + tau * (R)C_BETA_I * fb * wP);
         }
-      const R oh = omhat(wP);
-      const R dkdw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
-      const R chik = dkdw / (oh * oh * oh);
-      const R fbs = chik <= (R)0 ? (R)1
-                                 : ((R)1 + (R)680 * chik * chik) / ((R)1 + (R)400 * chik * chik);
-      const R ret = kP / ((R)ph.nu * oh);
-      const R x = ret * (R)(1.0 / C_R_BETA);
-      const R x2 = x * x;
-      const R x4 = x2 * x2;
-      // 0.09 (4/15 + x^4)/(1 + x^4), written so that x^4 = inf gives 0.09
-      const R bst = (R)C_BSTAR * ((R)1 - (R)(11.0 / 15.0) / ((R)1 + x4));
-      kn = kP / ((R)1 + tau * bst * fbs * wP);
-      if (!(tp & FIXED_BIT)) {
-        R S[3][3], W[3][3];
-        for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b) {
-            S[a][b] = (R)0.5 * (G[a][b] + G[b][a]);
-            W[a][b] = (R)0.5 * (G[a][b] - G[b][a]);
-          }
-        R X = 0;
-        for (int a = 0; a < 3; ++a)
-          for (int b = 0; b < 3; ++b)
-            for (int e = 0; e < 3; ++e) X += W[a][b] * W[b][e] * S[e][a];
-        const R den = (R)C_BSTAR * oh;
-        const R chiw = fabs(X) / (den * den * den);
-        const R fb = ((R)1 + (R)70 * chiw) / ((R)1 + (R)80 * chiw);
-        wn = wP / ((R)1 + tau * (R)C_BETA_I * fb * wP);
+        mk = fmin(mk, (double)kn);
+        mw = fmin(mw, (double)wn);
+        // eddy viscosity of the stored k, omega, for the explicit step
+        if (nut_out) nut_out[P] = (F)eddy_visc<R>((R)ph.nu, (R)(F)kn, (R)(F)wn);
       }
-      mk = fmin(mk, (double)kn);
-      mw = fmin(mw, (double)wn);
-      // eddy viscosity of the stored k, omega, for the explicit step
-      if (nut_out) nut_out[P] = (F)eddy_visc<R>((R)ph.nu, (R)(F)kn, (R)(F)wn);
+      k_out[P] = (F)kn;
+      om_out[P] = (F)wn;
+      cm = cc;
+      cc = cp;
     }
-    k_out[P] = (F)kn;
-    om_out[P] = (F)wn;
   }
   if (RED) {
     double vv[2] = {mk, mw};
