@@ -422,7 +422,8 @@ class GridT : public GridBase {
       prof_bytes[NFVM_K_RHS] = N * (3 * sv + so + 1);
       prof_bytes[NFVM_K_PROJECT] = N * (6 * sv + 2 * sp + so + 1);
       prof_bytes[NFVM_K_FCG_APPLY] = N * (2 * s0 + so + 2);
-      prof_bytes[NFVM_K_FCG_UPDATE] = N * (5 * s0 + 4 * so + 2);
+      // (x is read and written every other iteration)
+      prof_bytes[NFVM_K_FCG_UPDATE] = N * (5 * s0 + 3 * so + 2);
     }
     NFVM_CK(hipEventCreate(&ev0));
     NFVM_CK(hipEventCreate(&ev1));
@@ -1152,7 +1153,7 @@ class GridT : public GridBase {
   std::string diagnose() {
     static const char* SN[S_COUNT] = {"bb", "rr", "zr", "zq", "pq", "zw", "alpha", "div",
                                       "mink", "minw", "done", "iter", "tol2", "maxit",
-                                      "forced", "beta"};
+                                      "forced", "beta", "aprev"};
     std::string m = "scalars:";
     double sc[S_COUNT];
     NFVM_CK(hipMemcpyAsync(sc, red.out, sizeof sc, hipMemcpyDeviceToHost, stream));
@@ -1236,6 +1237,7 @@ class GridT : public GridBase {
     last_diag.clear();
     nfvm_status st = solve(true, tol_, maxc, forced, &cyc, &rel);
     if (st == NFVM_E_DIVERGED) last_diag = diagnose();
+    flush_x();
     launch_unpack<O>(g, phi, x_dev, 0.0, stream);
     NFVM_CK(hipEventRecord(ev1, stream));
     NFVM_CK(hipStreamSynchronize(stream));
@@ -1270,6 +1272,7 @@ class GridT : public GridBase {
     last_diag.clear();
     nfvm_status st = solve(false, tol_, maxc, forced, &cyc, &rel);
     if (st == NFVM_E_DIVERGED) last_diag = diagnose();
+    flush_x();
     launch_adj_velocity<O>(g, ph, type, patches, phi, ub, vb, wb, usb, vsb, wsb, stream);
     NFVM_CK(hipGetLastError());
     NFVM_CK(hipEventRecord(ev1, stream));
@@ -1358,9 +1361,16 @@ class GridT : public GridBase {
     prof_end(NFVM_K_FCG_START);
   }
 
+  // the CG x update the solve's last iteration deferred (none in Algorithm
+  // 1's plain iteration, which updates x every time)
+  void flush_x() {
+    if (!literal) launch_fcg_flush<O, S0>(lv[0], phi, dir, red.out, stream);
+  }
+
   // projection, destruction over dt/2 (with the min k / omega reduction)
   void step_suffix() {
     const double half = 0.5 * ph.dt;
+    flush_x();
     prof_begin(NFVM_K_PROJECT);
     launch_project<V, P, O>(g, ph, type, patches, phi, vcur(0), vcur(1), vcur(2), valt(0),
                             valt(1), valt(2), p, red, tp[TP_PROJECT], stream);

@@ -1712,6 +1712,7 @@ __device__ __forceinline__ void fin_apply_body(const FinArgs& f) {
     red.out[S_ZW] = zw;
     red.out[S_BETA] = beta;
     red.out[S_PQ] = pq;
+    red.out[S_APREV] = first ? 0.0 : red.out[S_ALPHA];
     red.out[S_ALPHA] = pq > 0.0 ? zr / pq : 0.0;
   }
 }
@@ -1744,7 +1745,12 @@ void launch_fcg_apply(const Level& l0, const O* r, void* const* dir, const RedBu
 // formed from the stored p, which every thread forms at a cell's neighbours
 // as the cell's own thread does (dir_at), so x and r take the same direction
 // and r stays b - A x up to the FP64 rounding of the updates whatever the
-// storage type of p.  No image q = A p is stored or read.
+// storage type of p.  No image q = A p is stored or read.  Nothing in the
+// iteration reads x, so an iteration with an even index leaves its x update
+// to the next one, which adds alpha_prev p_prev (the direction it reads
+// anyway) and then its own alpha p, the same two updates in the same order:
+// x is read and written every other iteration (launch_fcg_flush adds an
+// update left pending when the solve stops).
 template <class O, class S>
 struct UpdateArgs {
   LevelView L;
@@ -1771,7 +1777,8 @@ __device__ __forceinline__ void update_body(const UpdateArgs<O, S>& A, const Til
   S* __restrict__ pn = dir_next<S>(A.p, red.out);
   const S* __restrict__ z = A.z;
   const bool first = red.out[S_ITER] == 0.0;
-  const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA];
+  const bool xnow = ((int)red.out[S_ITER] & 1) != 0;  // x updated for this and the previous
+  const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA], ap = (O)red.out[S_APREV];
   double rr = 0.0;
   // the new direction at padded index Q
   auto dir = [&](int Q) -> S { return first ? z[Q] : dir_at<O, S>(z[Q], pp[Q], be); };
@@ -1794,7 +1801,12 @@ __device__ __forceinline__ void update_body(const UpdateArgs<O, S>& A, const Til
         O Ap, D;
         apply_code_v<O>(g, cd, (O)qP, (O)dir(P - 1), (O)dir(P + 1), (O)dir(P - g.sx),
                         (O)dir(P + g.sx), (O)qB, (O)qp, Ap, D);
-        x[P] += a * (O)qP;
+        if (xnow) {
+          O xP = x[P];
+          xP += ap * St<S, O>::ld(pp + P);
+          xP += a * (O)qP;
+          x[P] = xP;
+        }
         const O rP = r[P] - a * Ap;
         r[P] = rP;
         zero_sweep<O, S>(L, P, cd, rP, A.b0, A.z0, A.wj);
@@ -1826,7 +1838,8 @@ __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const Ti
   S* __restrict__ pn = dir_next<S>(A.p, red.out);
   const S* __restrict__ z = A.z;
   const bool first = red.out[S_ITER] == 0.0;
-  const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA];
+  const bool xnow = ((int)red.out[S_ITER] & 1) != 0;  // x updated for this and the previous
+  const O a = (O)red.out[S_ALPHA], be = (O)red.out[S_BETA], ap = (O)red.out[S_APREV];
   double rr = 0.0;
   // the new direction of four cells from index Q, and of one cell
   auto dir4 = [&](int Q) -> S4 {
@@ -1856,7 +1869,9 @@ __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const Ti
         const S4 qs = dir4(P - g.sx), qn = dir4(P + g.sx);
         const O ql = dir1(P - 1), qh = dir1(P + 4);
         const uint2 cw = *(const uint2*)(L.code + P);
-        O4 xv = *(const O4*)(x + P), rv = *(const O4*)(r + P);
+        O4 xv = xnow ? *(const O4*)(x + P) : O4(0);
+        const S4 pv = xnow ? *(const S4*)(pp + P) : S4(0);
+        O4 rv = *(const O4*)(r + P);
         const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
         const O qv[6] = {ql, (O)qc[0], (O)qc[1], (O)qc[2], (O)qc[3], qh};
         S4 b0v = S4(0), z0v = S4(0);
@@ -1866,6 +1881,7 @@ __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const Ti
           O Ap, D;
           apply_code_v<O>(g, cd[e], qv[e + 1], qv[e], qv[e + 2], (O)qs[e], (O)qn[e], (O)qm[e],
                           (O)qp[e], Ap, D);
+          xv[e] += ap * (O)pv[e];
           xv[e] += a * qv[e + 1];
           const O rP = rv[e] - a * Ap;
           rv[e] = rP;
@@ -1876,7 +1892,7 @@ __device__ __forceinline__ void update4_body(const UpdateArgs<O, S>& A, const Ti
           rr += (double)rP * (double)rP;
         }
         *(S4*)(pn + P) = qc;
-        *(O4*)(x + P) = xv;
+        if (xnow) *(O4*)(x + P) = xv;
         *(O4*)(r + P) = rv;
         *(S4*)(A.b0 + P) = b0v;
         if (A.z0) *(S4*)(A.z0 + P) = z0v;
@@ -1996,6 +2012,41 @@ template void launch_plain_update<float, float>(const Level&, float*, const floa
                                                 hipStream_t);
 template void launch_plain_update<double, float>(const Level&, double*, const double*,
                                                  const RedBuf&, hipStream_t);
+
+// The x update a solve's last iteration left pending.  After an odd count of
+// iterations the last one had an even index and deferred x += alpha p; its
+// direction sits in p[1] (iteration it writes p[(it + 1) & 1]) and its step
+// length in S_ALPHA.  After an even count (zero included) x is complete.
+template <class O, class S>
+__global__ __launch_bounds__(MBS) void k_fcg_flush(Geom g, Tiles T, const uint16_t* __restrict__ code,
+                                                   O* __restrict__ x, const S* __restrict__ p,
+                                                   const double* __restrict__ ctl) {
+  if (((int)ctl[S_ITER] & 1) == 0) return;
+  int tx, ty, tz;
+  if (!tile_of(T, tx, ty, tz)) return;
+  const int i = tx * MBX + threadIdx.x, j = ty * MBY + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const O a = (O)ctl[S_ALPHA];
+  const int k0 = tz * T.cz, k1 = min(g.nz, k0 + T.cz);
+  for (int k = k0; k < k1; ++k) {
+    const int P = g.idx(i, j, k);
+    if (code[P] != FACE_CODE_INACTIVE) x[P] += a * St<S, O>::ld(p + P);
+  }
+}
+
+template <class O, class S>
+void launch_fcg_flush(const Level& l0, O* x, void* const* dir, const double* ctl,
+                      hipStream_t s) {
+  const Tiles T = lvl_tiles(l0, TK_UPDATE);
+  NFVM_LAUNCH((k_fcg_flush<O, S>), dim3(T.grid), dim3(MBX, MBY), 0, s, l0.g, T, l0.code, x,
+              (const S*)dir[1], ctl);
+}
+template void launch_fcg_flush<double, double>(const Level&, double*, void* const*,
+                                               const double*, hipStream_t);
+template void launch_fcg_flush<float, float>(const Level&, float*, void* const*, const double*,
+                                             hipStream_t);
+template void launch_fcg_flush<double, float>(const Level&, double*, void* const*,
+                                              const double*, hipStream_t);
 
 int fcg_max_blocks(const Level& l0) {
   const Tiles ts = lvl_tiles(l0, TK_START);

@@ -190,7 +190,8 @@ enum {
   S_MAXIT = 13,
   S_FORCED = 14,   // < 0: stop on tol
   S_BETA = 15,     // direction coefficient of the current iteration
-  S_COUNT = 16
+  S_APREV = 16,    // step length of the previous iteration (its x update is deferred)
+  S_COUNT = 17
 };
 
 // Most values one block of a reducing kernel stores in red.partial.
@@ -214,6 +215,13 @@ void launch_finalize(int nv, int op, const RedBuf& red, int nblocks, int slot0, 
 // ||r||^2 through the CG update's finaliser (iteration count, stopping rule).
 template <class O, class S>
 void launch_plain_update(const Level& l0, O* x, const O* b, const RedBuf& red, hipStream_t s);
+
+// The x update the last CG iteration of a solve deferred (iterations with an
+// even index leave x += alpha p to the next one): to be launched once the
+// solve has stopped, before anything reads x; no-op when nothing is pending.
+template <class O, class S>
+void launch_fcg_flush(const Level& l0, O* x, void* const* dir, const double* ctl,
+                      hipStream_t s);
 
 // Workgroups of the largest reducing launch of one pressure solve on level
 // 0 (CG start, apply and update with the level's current tiles).
