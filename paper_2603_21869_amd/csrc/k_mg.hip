@@ -532,11 +532,75 @@ __host__ inline bool sweep_quad(const Level& l, bool from_zero) {
   return l.code && !from_zero && l.g.nx % 4 == 0;
 }
 
+// Coarse-level sweep over four consecutive x cells per thread, for the large
+// coarse levels (bandwidth-bound, unlike the small ones smooth_body serves):
+// one 4-wide load per row (centre, y +- 1, the plane above) and of the
+// right-hand side, the four class bytes in one 4-byte load, the two x
+// neighbours past the ends; irregular cells load their face coefficients
+// after the class test, as smooth_body does for levels of this size.  Per
+// cell the arithmetic is smooth_body's; inactive cells are written as 0, the
+// value they hold.
+template <class S, class C>
+__device__ __forceinline__ void smooth4_body(const SmoothArgs<S, C>& a, const TileCtx& c, bool) {
+  typedef typename Quad<S>::V V4;
+  const bool done = a.ctl[S_DONE] != 0.0;
+  const LevelView& L = a.L;
+  const S* __restrict__ xin = a.xin;
+  S* __restrict__ xout = a.xout;
+  const S* __restrict__ b = a.b;
+  const C wj = a.wj;
+  const Geom& g = L.g;
+  const int i0 = 4 * (c.tx * MBX + threadIdx.x), j = c.ty * MBY + threadIdx.y;
+  if (i0 >= g.nx || j >= g.ny) return;
+  const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
+  const bool d3 = g.dim == 3;
+  int P = g.idx(i0, j, k0);
+  V4 xc = *(const V4*)(xin + P);
+  V4 xm = d3 ? *(const V4*)(xin + P - g.sxy) : V4(0);
+  for (int k = k0; k < k1; ++k, P += g.sxy) {
+    const V4 xp = d3 ? *(const V4*)(xin + P + g.sxy) : V4(0);
+    const V4 xs = *(const V4*)(xin + P - g.sx), xn = *(const V4*)(xin + P + g.sx);
+    const V4 bb = *(const V4*)(b + P);
+    const C xl = St<S, C>::ld(xin + P - 1), xr = St<S, C>::ld(xin + P + 4);
+    const uint32_t cw = *(const uint32_t*)(L.cls + P);
+    if (done) return;
+    const C xv[6] = {xl, (C)xc[0], (C)xc[1], (C)xc[2], (C)xc[3], xr};
+    V4 out;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint8_t cl = (uint8_t)(cw >> (8 * q));
+      Nbhd<C> n;
+      n.xl = xv[q];
+      n.xh = xv[q + 2];
+      n.xs = (C)xs[q];
+      n.xn = (C)xn[q];
+      n.cxl = n.cxh = n.cyl = n.cyh = n.czl = n.czh = (C)0;
+      if (cl == MG_IRREGULAR) load_coef<C>(L, P + q, n);
+      const bool reg = cl == MG_REGULAR;
+      const C D = diag_cls<C>(g, reg, n);
+      const C Ax = apply_cls<C>(g, reg, n, xv[q + 1], (C)xm[q], (C)xp[q]);
+      out[q] = cl != MG_INACTIVE ? (S)(xv[q + 1] + wj * ((C)bb[q] - Ax) / D) : (S)0;
+    }
+    *(V4*)(xout + P) = out;
+    xm = xc;
+    xc = xp;
+  }
+}
+NFVM_TILE_KERNELS(k_smooth4, smooth4_body, SmoothArgs, (S, C), (class S, class C), (S, C), MBS,
+                  false)
+
+// Whether a coarse-level sweep takes k_smooth4.
+template <class S>
+__host__ inline bool coarse_quad(const Level& l, bool from_zero) {
+  return has_quad<S> && !l.code && !from_zero && l.g.nx % 4 == 0 &&
+         l.g.cells() > NBHD_EAGER_CELLS;
+}
+
 template <class S, class C>
 SmoothArgs<S, C> smooth_args(const Level& l, const void* xin, void* xout, double wj, bool from_zero,
                              const double* ctl) {
   const int tk = from_zero ? TK_SMOOTH_ZERO : TK_SMOOTH;
-  const Tiles T = sweep_quad(l, from_zero)
+  const Tiles T = sweep_quad(l, from_zero) || coarse_quad<S>(l, from_zero)
                       ? make_tiles(l.g.nx / 4, l.g.ny, l.g.nz, l.tt[tk])
                       : lvl_tiles(l, tk);
   return SmoothArgs<S, C>{view(l), T, (const S*)xin, (S*)xout, (const S*)l.b, (C)wj, ctl};
@@ -557,6 +621,8 @@ void launch_smooth(const Level& l, const void* xin, void* xout, double wj, bool 
     }
   } else if (from_zero) {
     NFVM_LAUNCH((k_smooth<S, C, true>), G, B, 0, s, a);
+  } else if (coarse_quad<S>(l, false)) {
+    if constexpr (has_quad<S>) NFVM_LAUNCH((k_smooth4<S, C>), G, B, 0, s, a);
   } else {
     NFVM_LAUNCH((k_smooth<S, C, false>), G, B, 0, s, a);
   }
@@ -2651,12 +2717,16 @@ void emit_blocks(BatchOps& o, const std::vector<A>& args, K kern, int threads, s
 // zero or not.
 template <class S, class C>
 struct SweepGroups {
-  // [class bytes, face codes, face codes four cells per thread][from zero]
-  Group<SmoothArgs<S, C>> g[3][2];
+  // [class bytes, face codes, face codes four cells per thread, class bytes
+  // four cells per thread][from zero]
+  Group<SmoothArgs<S, C>> g[4][2];
   void add(const Level& l, double wj, bool zero, const double* ctl) {
     const void* xin = zero ? nullptr : l.x[l.cur];
     void* xout = zero ? l.x[0] : l.x[l.cur ^ 1];
-    const int kind = sweep_quad(l, zero) ? 2 : (l.code != nullptr ? 1 : 0);
+    const int kind = sweep_quad(l, zero)         ? 2
+                     : coarse_quad<S>(l, zero) ? 3
+                     : l.code != nullptr       ? 1
+                                               : 0;
     g[kind][zero].push_back(smooth_args<S, C>(l, xin, xout, wj, zero, ctl));
   }
   void emit(BatchOps& o) const {
@@ -2664,8 +2734,10 @@ struct SweepGroups {
     emit_tiles(o, g[0][1], k_smooth<S, C, true>, k_smooth_batch<S, C, true>, false);
     emit_tiles(o, g[1][0], k_smooth_code<S, C, false>, k_smooth_code_batch<S, C, false>, false);
     emit_tiles(o, g[1][1], k_smooth_code<S, C, true>, k_smooth_code_batch<S, C, true>, false);
-    if constexpr (has_quad<S>)
+    if constexpr (has_quad<S>) {
       emit_tiles(o, g[2][0], k_smooth_code4<S, C>, k_smooth_code4_batch<S, C>, false);
+      emit_tiles(o, g[3][0], k_smooth4<S, C>, k_smooth4_batch<S, C>, false);
+    }
   }
 };
 
