@@ -264,11 +264,24 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const CellVals<R>& P,
   }
 }
 
-// Each thread walks cz planes of one column.  The cell above becomes the
-// next centre and the flux through the face between them is kept, so a cell
-// loads only its four in-plane neighbours and the cell above, and computes
-// five face fluxes instead of six; the sums are formed in the same order as
-// face by face.
+// Each workgroup walks cz planes of a 64 x 4 column tile, one cell per
+// thread.  A plane's values (u, v, w, T, k, omega, p, nu_t at the arithmetic
+// type) and kind bytes go to LDS for the tile and its one-cell rim on the
+// four sides, so a cell takes its four in-plane neighbours from LDS instead
+// of loading them (the rim is loaded by the threads of the edge rows and 2 x 4
+// threads of the second row).  The cell above is loaded by the cell's own
+// thread with the next plane's rim while the plane is computed, and becomes
+// the next centre; the flux through the face between them is kept, so a cell
+// computes five face fluxes instead of six.  Two LDS planes alternate, so one
+// barrier per plane suffices: a wave that writes plane k + 1 has passed the
+// barrier of plane k, which every wave reaches only after computing plane
+// k - 1, the last reader of that buffer.  The sums are formed in the same
+// order as face by face.
+constexpr int EX_W = BX + 2, EX_N = EX_W * (BY + 2);  // plane slots with the rim
+
+// slot of tile cell (a, b), a in [-1, BX], b in [-1, BY]
+__device__ __forceinline__ int ex_slot(int a, int b) { return (b + 1) * EX_W + a + 1; }
+
 template <class V, class F, class P>
 __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                  const DevPatch* __restrict__ pt,
@@ -276,45 +289,94 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
                                                  const F* __restrict__ nut, FieldSet<V, F> out,
                                                  Tiles T) {
   typedef V R;
+  __shared__ R lv[2][8][EX_N];
+  __shared__ uint8_t lt[2][EX_N];
   int tx = 0, ty = 0, tz = 0;
-  const bool tile = tile_of(T, tx, ty, tz);
-  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
+  if (!tile_of(T, tx, ty, tz)) return;  // (whole workgroup)
+  const int a = threadIdx.x, b = threadIdx.y;
+  const int i0 = tx * BX, j0 = ty * BY;
+  const int i = i0 + a, j = j0 + b;
   const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
-  if (!tile || i >= g.nx || j >= g.ny) return;
+  const bool valid = i < g.nx && j < g.ny;
   const R nu = (R)ph.nu;
   const int komega = ph.komega;
   const bool d3 = g.dim == 3;
   const int st[3] = {1, g.sx, g.sxy};
   const R ih[3] = {(R)(1.0 / g.hx), (R)(1.0 / g.hy), (R)(1.0 / g.hz)};
   const R dt = (R)ph.dt;
-  int C0 = g.idx(i, j, kb);
-  // centre of the first plane
-  uint8_t tp = type[C0];
-  CellVals<R> cP;
-  load_cell<V, F, P, R>(in, p, nut, C0, komega, cP);
+  // the cell this thread stages (its own, when it lies in the padded plane)
+  // and its rim cell, if any
+  const bool own = i <= g.nx && j <= g.ny;
+  int ha = 0, hb = 0;
+  bool rim = false;
+  if (b == 0) {
+    ha = a, hb = -1;
+    rim = i <= g.nx;
+  } else if (b == BY - 1) {
+    ha = a, hb = BY;
+    rim = i <= g.nx && j0 + BY <= g.ny;
+  } else if (b == 1 && a < 2 * BY) {
+    ha = a < BY ? -1 : BX;
+    hb = a < BY ? a : a - BY;
+    rim = i0 + ha <= g.nx && j0 + hb <= g.ny;
+  }
+  const int so = ex_slot(a, b), sh = ex_slot(ha, hb);
+  int C0 = g.idx(i, j, kb), H0 = g.idx(i0 + ha, j0 + hb, kb);
+  CellVals<R> cP, cH;
+  uint8_t tp = 0, th = 0;
+  if (own) {
+    tp = type[C0];
+    load_cell<V, F, P, R>(in, p, nut, C0, komega, cP);
+  }
+  if (rim) {
+    th = type[H0];
+    load_cell<V, F, P, R>(in, p, nut, H0, komega, cH);
+  }
   // the face below the centre: its flux when the cell below was a fluid
   // centre of this walk
   bool have_lo = false;
   R Flo[6], Ulo = 0;
   R vlo[3] = {0, 0, 0};  // velocities of the fluid cell below
-  for (int k = kb; k < ke; ++k, C0 += g.sxy) {
-    // the cell above: loaded once, the next centre
+  for (int k = kb, buf = 0; k < ke; ++k, C0 += g.sxy, H0 += g.sxy, buf ^= 1) {
+    R(*L)[EX_N] = lv[buf];
+    if (own) {
+#pragma unroll
+      for (int f = 0; f < 6; ++f) L[f][so] = cP.v[f];
+      L[6][so] = cP.p;
+      L[7][so] = cP.nut;
+      lt[buf][so] = tp;
+    }
+    if (rim) {
+#pragma unroll
+      for (int f = 0; f < 6; ++f) L[f][sh] = cH.v[f];
+      L[6][sh] = cH.p;
+      L[7][sh] = cH.nut;
+      lt[buf][sh] = th;
+    }
+    // the cell above (loaded whatever its kind: every index lies in the
+    // padded arrays) and the next plane's rim cell
     const int Nz = C0 + g.sxy;
-    const uint8_t tz_ = d3 ? type[Nz] : (uint8_t)1;
-    // loaded whatever its kind (every index lies in the padded arrays), so
-    // the loads do not wait for the type byte
+    uint8_t tz_ = 1;
     CellVals<R> cU;
-    if (d3) load_cell<V, F, P, R>(in, p, nut, Nz, komega, cU);
+    if (d3 && own) {
+      tz_ = type[Nz];
+      load_cell<V, F, P, R>(in, p, nut, Nz, komega, cU);
+    }
+    if (rim && k + 1 < ke) {
+      th = type[H0 + g.sxy];
+      load_cell<V, F, P, R>(in, p, nut, H0 + g.sxy, komega, cH);
+    }
+    __syncthreads();
     bool next_have = false;
     R Fhi[6], Uhi = 0;
-    if (!is_fluid(tp)) {
-      out.u[C0] = in.u[C0];
-      out.v[C0] = in.v[C0];
-      out.w[C0] = in.w[C0];
-      out.T[C0] = in.T[C0];
-      out.k[C0] = in.k[C0];
-      out.om[C0] = in.om[C0];
-    } else {
+    if (valid && !is_fluid(tp)) {
+      out.u[C0] = (V)cP.v[0];
+      out.v[C0] = (V)cP.v[1];
+      out.w[C0] = (V)cP.v[2];
+      out.T[C0] = (F)cP.v[3];
+      out.k[C0] = (F)cP.v[4];
+      out.om[C0] = (F)cP.v[5];
+    } else if (valid) {
       R rhs[6] = {0, 0, 0, 0, 0, 0};
       R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
       R divU = 0;
@@ -328,18 +390,29 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
           if (d == 2 && s < 0 && have_lo) {
             for (int f = 0; f < 6; ++f) Ff[f] = Flo[f];
             Uf = Ulo;
-            for (int a = 0; a < 3; ++a) vN[a] = vlo[a];
+            for (int a2 = 0; a2 < 3; ++a2) vN[a2] = vlo[a2];
           } else {
             CellVals<R> cN;
-            const int N = C0 + s * st[d];
-            const uint8_t tn = (d == 2 && s > 0) ? tz_ : type[N];
-            if (d == 2 && s > 0)
-              cN = cU;
-            else
-              load_cell<V, F, P, R>(in, p, nut, N, komega, cN);
+            uint8_t tn;
+            if (d == 2) {
+              if (s > 0) {
+                cN = cU;
+                tn = tz_;
+              } else {  // the first plane of the walk, or below a non-fluid cell
+                tn = type[C0 - g.sxy];
+                load_cell<V, F, P, R>(in, p, nut, C0 - g.sxy, komega, cN);
+              }
+            } else {
+              const int sl = d == 0 ? ex_slot(a + s, b) : ex_slot(a, b + s);
+              tn = lt[buf][sl];
+#pragma unroll
+              for (int f = 0; f < 6; ++f) cN.v[f] = L[f][sl];
+              cN.p = L[6][sl];
+              cN.nut = L[7][sl];
+            }
             if (!is_fluid(tn)) ghost_cell<R>(pt[tn & 0x7f], cP, komega, cN);
             face_flux<R>(ph, cP, cN, d, s, ih[d], Ff, Uf);
-            for (int a = 0; a < 3; ++a) vN[a] = cN.v[a];
+            for (int a2 = 0; a2 < 3; ++a2) vN[a2] = cN.v[a2];
             if (d == 2 && s > 0 && is_fluid(tn)) {
               next_have = true;
               for (int f = 0; f < 6; ++f) Fhi[f] = Ff[f];
@@ -350,8 +423,8 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
           divU += sc * Uf;
           const R hg = (R)s * (R)0.5 * ih[d];
 #pragma unroll
-          for (int a = 0; a < 3; ++a)
-            if (a < g.dim) G[a][d] += hg * vN[a];
+          for (int a2 = 0; a2 < 3; ++a2)
+            if (a2 < g.dim) G[a2][d] += hg * vN[a2];
 #pragma unroll
           for (int f = 0; f < 6; ++f) rhs[f] += sc * Ff[f];
         }
@@ -362,10 +435,10 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
       rhs[3] -= (R)ph.T_ref * divU;
       R o[6];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
+      for (int a2 = 0; a2 < 3; ++a2) {
         R src = 0;
-        if (ph.buoyancy) src = -(R)ph.beta_T * cP.v[3] * (R)ph.g[a];
-        o[a] = a < g.dim ? cP.v[a] + dt * (rhs[a] + src) : cP.v[a];
+        if (ph.buoyancy) src = -(R)ph.beta_T * cP.v[3] * (R)ph.g[a2];
+        o[a2] = a2 < g.dim ? cP.v[a2] + dt * (rhs[a2] + src) : cP.v[a2];
       }
       o[3] = ph.energy ? cP.v[3] + dt * rhs[3] : cP.v[3];
       o[4] = cP.v[4];
@@ -373,10 +446,10 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
       if (komega) {
         R S2 = 0;
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int a2 = 0; a2 < 3; ++a2)
 #pragma unroll
           for (int b2 = 0; b2 < 3; ++b2) {
-            const R sab = (R)0.5 * (G[a][b2] + G[b2][a]);
+            const R sab = (R)0.5 * (G[a2][b2] + G[b2][a2]);
             S2 += sab * sab;
           }
         S2 *= (R)2;
@@ -403,10 +476,12 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
     if (next_have) {
       for (int f = 0; f < 6; ++f) Flo[f] = Fhi[f];
       Ulo = Uhi;
-      for (int a = 0; a < 3; ++a) vlo[a] = cP.v[a];
+      for (int a2 = 0; a2 < 3; ++a2) vlo[a2] = cP.v[a2];
     }
-    tp = tz_;
-    if (d3 && is_fluid(tz_)) cP = cU;  // (a non-fluid centre only copies its values)
+    if (d3) {
+      tp = tz_;
+      cP = cU;
+    }
   }
 }
 
