@@ -73,6 +73,44 @@ __device__ __forceinline__ void apply_code_v(const Geom& g, uint32_t cd, C xP, C
   D = g.sd > 0.0 ? (C)g.sd : d;
 }
 
+// One damped Jacobi update at a cell from its face code and neighbours,
+// x + wj (b - A x) / D.  Cells whose faces all have coefficient 1 (the
+// regular interior: code 0x555 in 3D, 0x55 in 2D) take the plain stencil
+// and the constant wj / D of the level, formed once per thread, in place of
+// the coefficient form and a division per cell; every level-0 sweep kernel
+// takes this function, so a cell gets the same value from each of them.
+template <class C>
+struct JacobiConst {
+  C ih2x, ih2y, ih2z, wj, wjd;
+  uint32_t reg;
+};
+template <class C>
+__device__ __forceinline__ JacobiConst<C> jacobi_const(const Geom& g, C wj) {
+  JacobiConst<C> k;
+  k.ih2x = (C)(1.0 / (g.hx * g.hx));
+  k.ih2y = (C)(1.0 / (g.hy * g.hy));
+  k.ih2z = (C)(1.0 / (g.hz * g.hz));
+  C d = (C)2 * k.ih2x + (C)2 * k.ih2y;
+  if (g.dim == 3) d += (C)2 * k.ih2z;
+  if (g.sd > 0.0) d = (C)g.sd;
+  k.wj = wj;
+  k.wjd = wj / d;
+  k.reg = g.dim == 3 ? 0x555u : 0x55u;
+  return k;
+}
+template <class C>
+__device__ __forceinline__ C jacobi_code(const Geom& g, const JacobiConst<C>& k, uint32_t cd,
+                                         C xP, C xl, C xh, C xs, C xn, C xm, C xp, C bP) {
+  if (cd == k.reg) {
+    C s = ((xP - xl) + (xP - xh)) * k.ih2x + ((xP - xs) + (xP - xn)) * k.ih2y;
+    if (g.dim == 3) s += ((xP - xm) + (xP - xp)) * k.ih2z;
+    return xP + (bP - s) * k.wjd;
+  }
+  C A, D;
+  apply_code_v<C>(g, cd, xP, xl, xh, xs, xn, xm, xp, A, D);
+  return xP + k.wj * (bP - A) / D;
+}
+
 // ... at cell P, the x and y neighbours loaded here, the z neighbours given
 // (the walking kernels keep them in registers).
 template <class S, class C>
@@ -440,6 +478,8 @@ __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, cons
     }
     return;
   }
+  const JacobiConst<C> jk = jacobi_const<C>(g, wj);
+  auto ld = [&](int Q) { return St<S, C>::ld(xin + Q); };
   C xc = St<S, C>::ld(xin + P);
   C xm = d3 ? St<S, C>::ld(xin + P - g.sxy) : (C)0;
   int k = k0;
@@ -448,12 +488,13 @@ __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, cons
     const uint32_t c0 = L.code[P], c1 = L.code[Q];
     const C b0 = St<S, C>::ld(b + P), b1 = St<S, C>::ld(b + Q);
     const C xp = St<S, C>::ld(xin + Q), xpp = St<S, C>::ld(xin + Q + g.sxy);
-    C A0, D0, A1, D1;
-    apply_code<S, C>(g, c0, xin, P, xc, xm, xp, A0, D0);
-    apply_code<S, C>(g, c1, xin, Q, xp, xc, xpp, A1, D1);
+    const C y0 = jacobi_code<C>(g, jk, c0, xc, ld(P - 1), ld(P + 1), ld(P - g.sx), ld(P + g.sx),
+                                xm, xp, b0);
+    const C y1 = jacobi_code<C>(g, jk, c1, xp, ld(Q - 1), ld(Q + 1), ld(Q - g.sx), ld(Q + g.sx),
+                                xc, xpp, b1);
     if (done) return;
-    if (c0 != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, xc + wj * (b0 - A0) / D0);
-    if (c1 != FACE_CODE_INACTIVE) St<S, C>::st(xout + Q, xp + wj * (b1 - A1) / D1);
+    if (c0 != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, y0);
+    if (c1 != FACE_CODE_INACTIVE) St<S, C>::st(xout + Q, y1);
     xm = xp;
     xc = xpp;
   }
@@ -461,10 +502,10 @@ __device__ __forceinline__ void smooth_code_body(const SmoothArgs<S, C>& a, cons
     const uint32_t cd = L.code[P];
     const C bP = St<S, C>::ld(b + P);
     const C xp = d3 ? St<S, C>::ld(xin + P + g.sxy) : (C)0;
-    C Ax, D;
-    apply_code<S, C>(g, cd, xin, P, xc, xm, xp, Ax, D);
+    const C y = jacobi_code<C>(g, jk, cd, xc, ld(P - 1), ld(P + 1), ld(P - g.sx), ld(P + g.sx),
+                               xm, xp, bP);
     if (done) return;
-    if (cd != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, xc + wj * (bP - Ax) / D);
+    if (cd != FACE_CODE_INACTIVE) St<S, C>::st(xout + P, y);
   }
 }
 NFVM_TILE_KERNELS(k_smooth_code, smooth_code_body, SmoothArgs, (S, C),
@@ -484,6 +525,30 @@ struct Quad {
 template <class S>
 constexpr bool has_quad = !std::is_same<S, bf16>::value;
 
+// One sweep of four consecutive cells (k_smooth_code4's arithmetic; inactive
+// cells are 0).
+template <class S, class C>
+__device__ __forceinline__ typename Quad<S>::V sweep_quad_at(const Geom& g,
+                                                             const JacobiConst<C>& jk, uint2 cw,
+                                                             typename Quad<S>::V xc, C xl, C xr,
+                                                             typename Quad<S>::V xs,
+                                                             typename Quad<S>::V xn,
+                                                             typename Quad<S>::V xm,
+                                                             typename Quad<S>::V xp,
+                                                             typename Quad<S>::V bb) {
+  typedef typename Quad<S>::V V4;
+  const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
+  const C xv[6] = {xl, (C)xc[0], (C)xc[1], (C)xc[2], (C)xc[3], xr};
+  V4 out;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const C y = jacobi_code<C>(g, jk, cd[q], xv[q + 1], xv[q], xv[q + 2], (C)xs[q], (C)xn[q],
+                               (C)xm[q], (C)xp[q], (C)bb[q]);
+    out[q] = cd[q] != FACE_CODE_INACTIVE ? (S)y : (S)0;
+  }
+  return out;
+}
+
 template <class S, class C>
 __device__ __forceinline__ void smooth_code4_body(const SmoothArgs<S, C>& a, const TileCtx& c,
                                                   bool) {
@@ -500,6 +565,7 @@ __device__ __forceinline__ void smooth_code4_body(const SmoothArgs<S, C>& a, con
   const int k0 = c.tz * a.T.cz, k1 = min(g.nz, k0 + a.T.cz);
   const bool d3 = g.dim == 3;
   int P = g.idx(i0, j, k0);
+  const JacobiConst<C> jk = jacobi_const<C>(g, wj);
   V4 xc = *(const V4*)(xin + P);
   V4 xm = d3 ? *(const V4*)(xin + P - g.sxy) : V4(0);
   for (int k = k0; k < k1; ++k, P += g.sxy) {
@@ -509,17 +575,7 @@ __device__ __forceinline__ void smooth_code4_body(const SmoothArgs<S, C>& a, con
     const C xl = St<S, C>::ld(xin + P - 1), xr = St<S, C>::ld(xin + P + 4);
     const uint2 cw = *(const uint2*)(L.code + P);
     if (done) return;
-    const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
-    const C xv[6] = {xl, (C)xc[0], (C)xc[1], (C)xc[2], (C)xc[3], xr};
-    V4 out;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      C A, D;
-      apply_code_v<C>(g, cd[q], xv[q + 1], xv[q], xv[q + 2], (C)xs[q], (C)xn[q], (C)xm[q],
-                      (C)xp[q], A, D);
-      out[q] = cd[q] != FACE_CODE_INACTIVE ? (S)(xv[q + 1] + wj * ((C)bb[q] - A) / D) : (S)0;
-    }
-    *(V4*)(xout + P) = out;
+    *(V4*)(xout + P) = sweep_quad_at<S, C>(g, jk, cw, xc, xl, xr, xs, xn, xm, xp, bb);
     xm = xc;
     xc = xp;
   }
@@ -652,28 +708,6 @@ constexpr int S2_ROW = 4 * MBX;          // the cells of a wave's 64 four-cell c
 constexpr int S2_ROWS = 2 * MBY;         // rows of a workgroup (two per thread)
 constexpr int S2_QX = MBX - 2;           // four-cell columns a tile writes
 
-template <class S, class C>
-__device__ __forceinline__ typename Quad<S>::V sweep_quad_at(const Geom& g, uint2 cw,
-                                                             typename Quad<S>::V xc, C xl, C xr,
-                                                             typename Quad<S>::V xs,
-                                                             typename Quad<S>::V xn,
-                                                             typename Quad<S>::V xm,
-                                                             typename Quad<S>::V xp,
-                                                             typename Quad<S>::V bb, C wj) {
-  typedef typename Quad<S>::V V4;
-  const uint32_t cd[4] = {cw.x & 0xFFFFu, cw.x >> 16, cw.y & 0xFFFFu, cw.y >> 16};
-  const C xv[6] = {xl, (C)xc[0], (C)xc[1], (C)xc[2], (C)xc[3], xr};
-  V4 out;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    C A, D;
-    apply_code_v<C>(g, cd[q], xv[q + 1], xv[q], xv[q + 2], (C)xs[q], (C)xn[q], (C)xm[q],
-                    (C)xp[q], A, D);
-    out[q] = cd[q] != FACE_CODE_INACTIVE ? (S)(xv[q + 1] + wj * ((C)bb[q] - A) / D) : (S)0;
-  }
-  return out;
-}
-
 // The first sweep of a row's quad at one plane, with the plane's right-hand
 // side and face codes (kept for the second sweep there).
 template <class S>
@@ -691,8 +725,8 @@ __device__ __forceinline__ void smooth2_body(const SmoothArgs<S, C>& a, const Ti
   const S* __restrict__ x = a.xin;
   S* __restrict__ xout = a.xout;
   const S* __restrict__ b = a.b;
-  const C wj = a.wj;
   const Geom& g = L.g;
+  const JacobiConst<C> jk = jacobi_const<C>(g, a.wj);
   const bool d3 = g.dim == 3;
   const int lane = threadIdx.x, wy = threadIdx.y;
   const int i0 = 4 * (c.tx * S2_QX + lane - 1);  // (lane 0: the halo left of the tile)
@@ -716,7 +750,7 @@ __device__ __forceinline__ void smooth2_body(const SmoothArgs<S, C>& a, const Ti
     FirstQuad<S> f;
     f.bb = *(const V4*)(b + P);
     f.cw = *(const uint2*)(L.code + P);
-    f.x1 = sweep_quad_at<S, C>(g, f.cw, xc, xl, xr, xs, xn, xm, xp, f.bb, wj);
+    f.x1 = sweep_quad_at<S, C>(g, jk, f.cw, xc, xl, xr, xs, xn, xm, xp, f.bb);
     return f;
   };
   // x0 of this thread's rows as the walk carries it: planes m - 1 and m of
@@ -746,8 +780,8 @@ __device__ __forceinline__ void smooth2_body(const SmoothArgs<S, C>& a, const Ti
         const C xl = St<S, C>::ld(x + P - 1), xr = St<S, C>::ld(x + P + 4);
         f[h].bb = *(const V4*)(b + P);
         f[h].cw = *(const uint2*)(L.code + P);
-        f[h].x1 = sweep_quad_at<S, C>(g, f[h].cw, xb[h], xl, xr, ys, yn, xa[h], xn[h], f[h].bb,
-                                      wj);
+        f[h].x1 = sweep_quad_at<S, C>(g, jk, f[h].cw, xb[h], xl, xr, ys, yn, xa[h], xn[h],
+                                      f[h].bb);
       } else {
         f[h].x1 = f[h].bb = V4(0);
         f[h].cw = make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu);
@@ -804,7 +838,7 @@ __device__ __forceinline__ void smooth2_body(const SmoothArgs<S, C>& a, const Ti
         const C yl = (C)row[lr][4 * lane - 1];
         const C yr = (C)row[lr][4 * lane + 4];
         *(V4*)(xout + g.idx(i0, j0 + h, k)) =
-            sweep_quad_at<S, C>(g, cc[h], yc[h], yl, yr, ys, yn, ym[h], fp[h].x1, bc[h], wj);
+            sweep_quad_at<S, C>(g, jk, cc[h], yc[h], yl, yr, ys, yn, ym[h], fp[h].x1, bc[h]);
       }
       ym[h] = yc[h];
       yc[h] = fp[h].x1;
