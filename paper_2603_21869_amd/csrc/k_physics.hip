@@ -23,6 +23,31 @@ __host__ inline dim3 cell_grid(const Geom& g) {
 // walking a chunk of planes
 __host__ inline Tiles cell_tiles(const Geom& g, int tt) { return make_tiles(g.nx, g.ny, g.nz, tt); }
 
+// LDS planes of the stencil kernels that stage a tile: the 64 x 4 cells and
+// their one-cell rim on the four sides (corners unused).  The rim is loaded
+// by the threads of the first and last rows (the rows outside) and by 2 x 4
+// threads of the second row (the columns outside).
+constexpr int PL_W = BX + 2, PL_N = PL_W * (BY + 2);
+
+// slot of tile cell (a, b), a in [-1, BX], b in [-1, BY]
+__device__ __forceinline__ int pl_slot(int a, int b) { return (b + 1) * PL_W + a + 1; }
+
+// The rim cell (a, b) relative to the tile that thread (x, y) stages, if any.
+__device__ __forceinline__ bool pl_rim(int x, int y, int& a, int& b) {
+  if (y == 0) {
+    a = x, b = -1;
+  } else if (y == BY - 1) {
+    a = x, b = BY;
+  } else if (y == 1 && x < 2 * BY) {
+    a = x < BY ? -1 : BX;
+    b = x < BY ? x : x - BY;
+  } else {
+    a = b = 0;
+    return false;
+  }
+  return true;
+}
+
 // ---- dense <-> padded copies ------------------------------------------------
 // padded = dense - offset (rounded to F) and back
 template <class F>
@@ -63,12 +88,16 @@ struct DestroyNb {
   R u[3], k, w;
 };
 
-// Each thread walks the planes of its column: the cells below and above stay
-// in registers (the cell above becomes the next centre), so a plane loads
-// its own cell's row neighbours and the cell above once.  The vortex
-// stretching Omega_ij Omega_jk S_ki is tr(W W S) with W the antisymmetric
-// part of the gradient; for W = [a]x (the cross-product matrix of a),
-// W W = a a^T - |a|^2 I, so it is a^T S a - |a|^2 tr S.
+// Each workgroup walks the planes of a 64 x 4 column tile, one cell per
+// thread.  A plane's values (u, v, w, k, omega at the arithmetic type) and
+// kind bytes go to LDS for the tile and its rim, so a cell takes its four
+// in-plane neighbours from there; the cells below and above stay in the
+// thread's registers (the cell above, loaded with the next plane's rim while
+// the plane is computed, becomes the next centre).  Two LDS planes
+// alternate, so one barrier per plane suffices.  The vortex stretching
+// Omega_ij Omega_jk S_ki is tr(W W S) with W the antisymmetric part of the
+// gradient; for W = [a]x (the cross-product matrix of a), W W = a a^T -
+// |a|^2 I, so it is a^T S a - |a|^2 tr S.
 template <class V, class F, bool RED>
 __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                 const DevPatch* __restrict__ pt,
@@ -78,11 +107,16 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
                                                 F* __restrict__ k_out, F* __restrict__ om_out,
                                                 F* __restrict__ nut_out, RedBuf red, Tiles T) {
   typedef V R;
+  __shared__ R lv[2][5][PL_N];
+  __shared__ uint8_t lt[2][PL_N];
   int tx = 0, ty = 0, tz = 0;
-  const bool tile = tile_of(T, tx, ty, tz);
-  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
-  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
+  const bool tile = tile_of(T, tx, ty, tz);  // (whole workgroup)
+  const int a = threadIdx.x, b = threadIdx.y;
+  const int i0 = tx * BX, j0 = ty * BY;
+  const int i = i0 + a, j = j0 + b;
+  const int kb = tz * T.cz, ke = tile ? min(g.nz, kb + T.cz) : kb;
   const bool d3 = g.dim == 3;
+  const bool valid = i < g.nx && j < g.ny;
   double mk = INFINITY, mw = INFINITY;
   auto load = [&](int N) {
     DestroyNb<R> c;
@@ -94,78 +128,109 @@ __global__ __launch_bounds__(BS) void k_destroy(Geom g, Phys ph, const uint8_t* 
     c.w = om[N];
     return c;
   };
+  auto stage = [&](R (*L)[PL_N], uint8_t* T8, int sl, const DestroyNb<R>& c) {
+    L[0][sl] = c.u[0];
+    L[1][sl] = c.u[1];
+    L[2][sl] = c.u[2];
+    L[3][sl] = c.k;
+    L[4][sl] = c.w;
+    T8[sl] = c.t;
+  };
   const R inu = (R)(1.0 / ph.nu);
-  if (tile && i < g.nx && j < g.ny) {
-    int P = g.idx(i, j, kb);
-    DestroyNb<R> cm, cc = load(P);
+  const bool own = i <= g.nx && j <= g.ny;
+  int ha, hb;
+  const bool rim = pl_rim(a, b, ha, hb) && i0 + ha <= g.nx && j0 + hb <= g.ny;
+  const int so = pl_slot(a, b), sh = pl_slot(ha, hb);
+  int P = g.idx(i, j, kb), H = g.idx(i0 + ha, j0 + hb, kb);
+  DestroyNb<R> cm, cc, ch;
+  if (tile && own) {
+    cc = load(P);
     if (d3) cm = load(P - g.sxy);
-    for (int k = kb; k < ke; ++k, P += g.sxy) {
-      DestroyNb<R> cp;
-      if (d3) cp = load(P + g.sxy);
-      const uint8_t tp = cc.t;
-      const R kP = cc.k, wP = cc.w;
-      R kn = kP, wn = wP;
-      if (is_fluid(tp)) {
-        R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        R gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
-        const int st[2] = {1, g.sx};
-        const R ih2[3] = {(R)(0.5 / g.hx), (R)(0.5 / g.hy), (R)(0.5 / g.hz)};
-        // constant trip counts keep G, gk and gw in registers
+  }
+  if (tile && rim) ch = load(H);
+  for (int k = kb, buf = 0; k < ke; ++k, P += g.sxy, H += g.sxy, buf ^= 1) {
+    R(*L)[PL_N] = lv[buf];
+    if (own) stage(L, lt[buf], so, cc);
+    if (rim) stage(L, lt[buf], sh, ch);
+    DestroyNb<R> cp;
+    if (d3 && own) cp = load(P + g.sxy);
+    if (rim && k + 1 < ke) ch = load(H + g.sxy);
+    __syncthreads();
+    const uint8_t tp = cc.t;
+    const R kP = cc.k, wP = cc.w;
+    R kn = kP, wn = wP;
+    if (valid && is_fluid(tp)) {
+      R G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      R gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+      const R ih2[3] = {(R)(0.5 / g.hx), (R)(0.5 / g.hy), (R)(0.5 / g.hz)};
+      // constant trip counts keep G, gk and gw in registers
 #pragma unroll
-        for (int d = 0; d < 3; ++d)
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-          for (int s = -1; s <= 1; s += 2) {
-            if (d >= g.dim) continue;
-            DestroyNb<R> n = d == 2 ? (s < 0 ? cm : cp) : load(P + s * st[d]);
-            if (!is_fluid(n.t)) {
-              const DevPatch& pp = pt[n.t & 0x7f];
-              for (int a = 0; a < 3; ++a) n.u[a] = ghost<R>(pp, G_U + a, cc.u[a], ph.komega);
-              n.k = ghost<R>(pp, G_K, kP, ph.komega);
-              n.w = ghost<R>(pp, G_OM, wP, ph.komega);
-            }
-            const R sc = (R)s * ih2[d];
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-              if (a < g.dim) G[a][d] += sc * n.u[a];
-            gk[d] += sc * n.k;
-            gw[d] += sc * n.w;
+        for (int s = -1; s <= 1; s += 2) {
+          if (d >= g.dim) continue;
+          DestroyNb<R> n;
+          if (d == 2) {
+            n = s < 0 ? cm : cp;
+          } else {
+            const int sl = d == 0 ? pl_slot(a + s, b) : pl_slot(a, b + s);
+            n.u[0] = L[0][sl];
+            n.u[1] = L[1][sl];
+            n.u[2] = L[2][sl];
+            n.k = L[3][sl];
+            n.w = L[4][sl];
+            n.t = lt[buf][sl];
           }
-        const R oh = omhat(wP);
-        const R ioh = (R)1 / oh;
-        const R ioh3 = ioh * ioh * ioh;
-        const R dkdw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
-        const R chik = dkdw * ioh3;
-        const R fbs = chik <= (R)0 ? (R)1
-                                   : ((R)1 + (R)680 * chik * chik) / ((R)1 + (R)400 * chik * chik);
-        const R ret = kP * ioh * inu;
-        const R x = ret * (R)(1.0 / C_R_BETA);
-        const R x2 = x * x;
-        const R x4 = x2 * x2;
-        // 0.09 (4/15 + x^4)/(1 + x^4), written so that x^4 = inf gives 0.09
-        const R bst = (R)C_BSTAR * ((R)1 - (R)(11.0 / 15.0) / ((R)1 + x4));
-        kn = kP / ((R)1 + tau * bst * fbs * wP);
-        if (!(tp & FIXED_BIT)) {
-          const R a0 = (R)0.5 * (G[2][1] - G[1][2]), a1 = (R)0.5 * (G[0][2] - G[2][0]),
-                  a2 = (R)0.5 * (G[1][0] - G[0][1]);
-          const R s01 = (R)0.5 * (G[0][1] + G[1][0]), s02 = (R)0.5 * (G[0][2] + G[2][0]),
-                  s12 = (R)0.5 * (G[1][2] + G[2][1]);
-          const R aSa = a0 * a0 * G[0][0] + a1 * a1 * G[1][1] + a2 * a2 * G[2][2] +
-                        (R)2 * (a0 * a1 * s01 + a0 * a2 * s02 + a1 * a2 * s12);
-          const R X = aSa - (a0 * a0 + a1 * a1 + a2 * a2) * (G[0][0] + G[1][1] + G[2][2]);
-          const R chiw = fabs(X) * ioh3 * (R)(1.0 / (C_BSTAR * C_BSTAR * C_BSTAR));
-          const R fb = ((R)1 + (R)70 * chiw) / ((R)1 + (R)80 * chiw);
-          wn = wP / ((R)1 + tau * (R)C_BETA_I * fb * wP);
+          if (!is_fluid(n.t)) {
+            const DevPatch& pp = pt[n.t & 0x7f];
+            for (int c = 0; c < 3; ++c) n.u[c] = ghost<R>(pp, G_U + c, cc.u[c], ph.komega);
+            n.k = ghost<R>(pp, G_K, kP, ph.komega);
+            n.w = ghost<R>(pp, G_OM, wP, ph.komega);
+          }
+          const R sc = (R)s * ih2[d];
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (c < g.dim) G[c][d] += sc * n.u[c];
+          gk[d] += sc * n.k;
+          gw[d] += sc * n.w;
         }
-        mk = fmin(mk, (double)kn);
-        mw = fmin(mw, (double)wn);
-        // eddy viscosity of the stored k, omega, for the explicit step
-        if (nut_out) nut_out[P] = (F)eddy_visc<R>((R)ph.nu, (R)(F)kn, (R)(F)wn);
+      const R oh = omhat(wP);
+      const R ioh = (R)1 / oh;
+      const R ioh3 = ioh * ioh * ioh;
+      const R dkdw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
+      const R chik = dkdw * ioh3;
+      const R fbs = chik <= (R)0 ? (R)1
+                                 : ((R)1 + (R)680 * chik * chik) / ((R)1 + (R)400 * chik * chik);
+      const R ret = kP * ioh * inu;
+      const R x = ret * (R)(1.0 / C_R_BETA);
+      const R x2 = x * x;
+      const R x4 = x2 * x2;
+      // 0.09 (4/15 + x^4)/(1 + x^4), written so that x^4 = inf gives 0.09
+      const R bst = (R)C_BSTAR * ((R)1 - (R)(11.0 / 15.0) / ((R)1 + x4));
+      kn = kP / ((R)1 + tau * bst * fbs * wP);
+      if (!(tp & FIXED_BIT)) {
+        const R a0 = (R)0.5 * (G[2][1] - G[1][2]), a1 = (R)0.5 * (G[0][2] - G[2][0]),
+                a2 = (R)0.5 * (G[1][0] - G[0][1]);
+        const R s01 = (R)0.5 * (G[0][1] + G[1][0]), s02 = (R)0.5 * (G[0][2] + G[2][0]),
+                s12 = (R)0.5 * (G[1][2] + G[2][1]);
+        const R aSa = a0 * a0 * G[0][0] + a1 * a1 * G[1][1] + a2 * a2 * G[2][2] +
+                      (R)2 * (a0 * a1 * s01 + a0 * a2 * s02 + a1 * a2 * s12);
+        const R X = aSa - (a0 * a0 + a1 * a1 + a2 * a2) * (G[0][0] + G[1][1] + G[2][2]);
+        const R chiw = fabs(X) * ioh3 * (R)(1.0 / (C_BSTAR * C_BSTAR * C_BSTAR));
+        const R fb = ((R)1 + (R)70 * chiw) / ((R)1 + (R)80 * chiw);
+        wn = wP / ((R)1 + tau * (R)C_BETA_I * fb * wP);
       }
+      mk = fmin(mk, (double)kn);
+      mw = fmin(mw, (double)wn);
+      // eddy viscosity of the stored k, omega, for the explicit step
+      if (nut_out) nut_out[P] = (F)eddy_visc<R>((R)ph.nu, (R)(F)kn, (R)(F)wn);
+    }
+    if (valid) {
       k_out[P] = (F)kn;
       om_out[P] = (F)wn;
-      cm = cc;
-      cc = cp;
     }
+    cm = cc;
+    cc = cp;
   }
   if (RED) {
     double vv[2] = {mk, mw};
@@ -277,11 +342,6 @@ __device__ __forceinline__ void face_flux(const Phys& ph, const CellVals<R>& P,
 // barrier of plane k, which every wave reaches only after computing plane
 // k - 1, the last reader of that buffer.  The sums are formed in the same
 // order as face by face.
-constexpr int EX_W = BX + 2, EX_N = EX_W * (BY + 2);  // plane slots with the rim
-
-// slot of tile cell (a, b), a in [-1, BX], b in [-1, BY]
-__device__ __forceinline__ int ex_slot(int a, int b) { return (b + 1) * EX_W + a + 1; }
-
 template <class V, class F, class P>
 __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                  const DevPatch* __restrict__ pt,
@@ -289,8 +349,8 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
                                                  const F* __restrict__ nut, FieldSet<V, F> out,
                                                  Tiles T) {
   typedef V R;
-  __shared__ R lv[2][8][EX_N];
-  __shared__ uint8_t lt[2][EX_N];
+  __shared__ R lv[2][8][PL_N];
+  __shared__ uint8_t lt[2][PL_N];
   int tx = 0, ty = 0, tz = 0;
   if (!tile_of(T, tx, ty, tz)) return;  // (whole workgroup)
   const int a = threadIdx.x, b = threadIdx.y;
@@ -301,26 +361,14 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
   const R nu = (R)ph.nu;
   const int komega = ph.komega;
   const bool d3 = g.dim == 3;
-  const int st[3] = {1, g.sx, g.sxy};
   const R ih[3] = {(R)(1.0 / g.hx), (R)(1.0 / g.hy), (R)(1.0 / g.hz)};
   const R dt = (R)ph.dt;
   // the cell this thread stages (its own, when it lies in the padded plane)
   // and its rim cell, if any
   const bool own = i <= g.nx && j <= g.ny;
-  int ha = 0, hb = 0;
-  bool rim = false;
-  if (b == 0) {
-    ha = a, hb = -1;
-    rim = i <= g.nx;
-  } else if (b == BY - 1) {
-    ha = a, hb = BY;
-    rim = i <= g.nx && j0 + BY <= g.ny;
-  } else if (b == 1 && a < 2 * BY) {
-    ha = a < BY ? -1 : BX;
-    hb = a < BY ? a : a - BY;
-    rim = i0 + ha <= g.nx && j0 + hb <= g.ny;
-  }
-  const int so = ex_slot(a, b), sh = ex_slot(ha, hb);
+  int ha, hb;
+  const bool rim = pl_rim(a, b, ha, hb) && i0 + ha <= g.nx && j0 + hb <= g.ny;
+  const int so = pl_slot(a, b), sh = pl_slot(ha, hb);
   int C0 = g.idx(i, j, kb), H0 = g.idx(i0 + ha, j0 + hb, kb);
   CellVals<R> cP, cH;
   uint8_t tp = 0, th = 0;
@@ -338,7 +386,7 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
   R Flo[6], Ulo = 0;
   R vlo[3] = {0, 0, 0};  // velocities of the fluid cell below
   for (int k = kb, buf = 0; k < ke; ++k, C0 += g.sxy, H0 += g.sxy, buf ^= 1) {
-    R(*L)[EX_N] = lv[buf];
+    R(*L)[PL_N] = lv[buf];
     if (own) {
 #pragma unroll
       for (int f = 0; f < 6; ++f) L[f][so] = cP.v[f];
@@ -403,7 +451,7 @@ __global__ __launch_bounds__(BS, 3) void k_explicit(Geom g, Phys ph, const uint8
                 load_cell<V, F, P, R>(in, p, nut, C0 - g.sxy, komega, cN);
               }
             } else {
-              const int sl = d == 0 ? ex_slot(a + s, b) : ex_slot(a, b + s);
+              const int sl = d == 0 ? pl_slot(a + s, b) : pl_slot(a, b + s);
               tn = lt[buf][sl];
 #pragma unroll
               for (int f = 0; f < 6; ++f) cN.v[f] = L[f][sl];
