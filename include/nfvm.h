@@ -253,6 +253,59 @@ nfvm_status nfvm_get_fields(nfvm_grid_t grid, nfvm_fields* out);
  * Errors: NFVM_E_INVAL for a null argument. */
 nfvm_status nfvm_lambda2(nfvm_grid_t grid, double* lambda2);
 
+/* Reverse mode of the explicit stage (Sec. 2.3, Algorithms 2 and 4, eqs.
+ * ko_mom, ko_temp, ko_k, ko_o; the solver is differentiable, Sec. 1 and 4):
+ * the forward-Euler step E of the rest terms maps the fields (u, v, w, p, T,
+ * k, omega) to (u, v, w, T, k, omega), with nu_t the closure of the input k
+ * and omega (eqs. a_star, ko_turb_diff), the boundary ghosts of Sec. 2.7,
+ * k and omega clamped at 1e-10 and omega held on wall-adjacent cells.  For
+ * the adjoints `bar` of its six outputs (bar->p is not read and may be
+ * NULL) this writes the adjoints J^T bar of its seven inputs into `out`,
+ * J the Jacobian of E at the input state `state` (upwind selections and
+ * clamps as the forward step takes them there).  All arrays device FP64
+ * [nz][ny][nx], T absolute; outputs may not alias inputs.  Arithmetic in
+ * FP64 whatever the grid's precision; the grid's fields are not touched.
+ * The first call of this or nfvm_destroy_adjoint_device allocates 21 FP64
+ * values per padded cell of scratch, kept until the grid is freed.  Runs on
+ * the grid's stream and waits for it.  Errors: NFVM_E_INVAL for a null
+ * pointer, NFVM_E_NOMEM. */
+nfvm_status nfvm_explicit_adjoint_device(nfvm_grid_t grid, const nfvm_fields* state,
+                                         const nfvm_fields* bar, nfvm_fields* out);
+
+/* Reverse mode of the destruction step (Sec. 2.5, Algorithm 3, eqs.
+ * k_des_step, o_des_step, beta_star, o_des): the step over a time tau maps
+ * (u, v, w, k, omega) to k' = k / (1 + tau beta* f_beta* omega) and omega' =
+ * omega / (1 + tau beta_i f_beta omega), whose coefficients read the central
+ * gradients of k, omega and the velocity (boundary ghosts of Sec. 2.7);
+ * wall-adjacent cells keep omega and non-fluid cells keep both.  For the
+ * adjoints kbar, wbar of k' and omega' this writes the adjoints of the five
+ * inputs (state->u, v, w, k, omega; T and p not read, out->T and out->p not
+ * written) at the input state.  All arrays device FP64 [nz][ny][nx]; outputs
+ * may not alias inputs; FP64 arithmetic; scratch as for
+ * nfvm_explicit_adjoint_device (shared).  Runs on the grid's stream and
+ * waits for it.  Errors: NFVM_E_INVAL for a null pointer or tau < 0,
+ * NFVM_E_NOMEM. */
+nfvm_status nfvm_destroy_adjoint_device(nfvm_grid_t grid, const nfvm_fields* state, double tau,
+                                        const double* kbar, const double* wbar,
+                                        nfvm_fields* out);
+
+/* Line probes of Sec. 3.1 (the velocity magnitude V, the temperature T, k
+ * and omega compared along lines of the channel cases): at n points of the
+ * grid's current fields.  pts: host array of 3*n FP64 coordinates in metres
+ * (x, y, z per point; z is ignored in 2D), the box spanning [0, n_d h_d].
+ * Each field is interpolated trilinearly between the cell centres (the
+ * centre of cell i at (i + 1/2) h), over the fluid cells among the eight
+ * around the point with their weights renormalised to sum to one; a point
+ * is first clamped into the box of cell centres.  V is the magnitude of the
+ * interpolated velocity; T is absolute (T_ref added back).  out: host array
+ * of 4*n FP64 values {V, T, k, omega} per point, written before return (the
+ * call waits for the grid's stream); a point whose eight cells are all
+ * non-fluid receives NaN.  Computed on the device in FP64 from the stored
+ * fields.  Errors: NFVM_E_INVAL for a null grid, n < 0, null arrays with
+ * n > 0, or more than ncells / 7 points (the points and results pass
+ * through the grid's staging buffer). */
+nfvm_status nfvm_line_probe(nfvm_grid_t grid, const double* pts, int32_t n, double* out);
+
 /* Replace the grid's fields (Sec. 2.2 tensors) from host FP64 arrays,
  * [nz][ny][nx], all seven required; values in solid cells are kept as given
  * and never updated; omega in wall-adjacent cells is reset to the wall value

@@ -175,6 +175,39 @@ static int is_fixed(const orc_case* c, int i, int j, int k) {
   return 0;
 }
 
+/* The boundary classification of every fluid cell as tables: per cell P
+ * and face direction dir (0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+),
+ * nidx[6P + dir] is the neighbour's index, or -1 where the face takes a
+ * ghost value, whose rule is affine in the cell's own value: ghost =
+ * a0 + a1 value_P for field fld (F_U .. F_NUT) at a0/a1[8 (6P + dir) + fld];
+ * fixed[P] flags the cells whose omega is held (wall-adjacent).  The
+ * reverse mode of the explicit stage is differentiated through these. */
+void orc_ghost_table(const orc_case* c, int* nidx, double* a0, double* a1,
+                     unsigned char* fixed) {
+  for (int k = 0; k < c->n[2]; ++k)
+    for (int j = 0; j < c->n[1]; ++j)
+      for (int i = 0; i < c->n[0]; ++i) {
+        int P = cidx(c, i, j, k);
+        fixed[P] = is_fluid(c, P) ? (unsigned char)is_fixed(c, i, j, k) : 0;
+        for (int dir = 0; dir < 6; ++dir) {
+          int e = 6 * P + dir;
+          nidx[e] = -1;
+          for (int f = 0; f < 8; ++f) a0[8 * e + f] = a1[8 * e + f] = 0.0;
+          if (!is_fluid(c, P) || dir >= 2 * c->dim) continue;
+          nbinfo nb = neighbour(c, i, j, k, dir);
+          if (nb.fluid) {
+            nidx[e] = nb.idx;
+            continue;
+          }
+          for (int f = 0; f < 8; ++f) {
+            double g0 = ghost(c, &nb, f, 0.0);
+            a0[8 * e + f] = g0;
+            a1[8 * e + f] = ghost(c, &nb, f, 1.0) - g0;
+          }
+        }
+      }
+}
+
 void orc_nut(const orc_case* c, const double* k, const double* om, double* nut) {
   int N = ncells(c);
   for (int P = 0; P < N; ++P)

@@ -93,6 +93,12 @@ void orc_project(const orc_case* c, const double* phi, const double* us, const d
 void orc_velocity_gradient(const orc_case* c, const double* u, const double* v,
                            const double* w, double* G9);
 
+/* Boundary classification as tables (see the definition): neighbour index
+ * or -1 per cell and face direction, the affine ghost rule of each field,
+ * the fixed-omega flag per cell. */
+void orc_ghost_table(const orc_case* c, int* nidx, double* a0, double* a1,
+                     unsigned char* fixed);
+
 orc_mg* orc_mg_create(const orc_case* c);
 void orc_mg_free(orc_mg* mg);
 int orc_mg_levels(const orc_mg* mg);

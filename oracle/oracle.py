@@ -88,6 +88,8 @@ def lib():
         L.orc_pressure_adjoint.argtypes = [C.POINTER(_Case), _dp, _dp, _dp, _dp, C.c_double,
                                            C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp,
                                            C.POINTER(C.c_int), _dp]
+        L.orc_ghost_table.argtypes = [C.POINTER(_Case), C.POINTER(C.c_int), _dp, _dp,
+                                      C.POINTER(C.c_ubyte)]
         _lib = L
     return _lib
 
@@ -262,6 +264,69 @@ def lambda2(case, u, v, w):
     W = 0.5 * (G - np.swapaxes(G, -1, -2))
     M = S @ S + W @ W
     return np.linalg.eigvalsh(M)[..., 1]
+
+
+def line_probe(case, fields: Dict[str, np.ndarray], pts) -> np.ndarray:
+    """Line probes of Sec. 3.1: the velocity magnitude V, the temperature T,
+    k and omega at points (metres, shape (n, 3): x, y, z), as compared with
+    the reference solutions along lines there.  The paper does not say how
+    values between cell centres are formed; this reading interpolates each
+    field trilinearly between the cell centres (centre of cell i at
+    (i + 1/2) h), over the fluid cells among the eight around the point with
+    their weights renormalised to sum to one (NaN where none is fluid), with
+    the point clamped into the box of cell centres; V is the magnitude of the
+    interpolated velocity.  fields are dense [nz][ny][nx] arrays with T
+    absolute.  Returns (n, 4) columns V, T, k, omega.  Plain loops."""
+    n = tuple(case.n)
+    dim = case.dim
+    h = tuple(case.h)
+    fluid = np.ones(n[::-1], dtype=bool) if case.solid is None else case.solid == 0
+    pts = np.asarray(pts, dtype=np.float64).reshape(-1, 3)
+    out = np.full((len(pts), 4), np.nan)
+    names = ("u", "v", "w", "T", "k", "omega")
+    for q, x in enumerate(pts):
+        lo, t = [0, 0, 0], [0.0, 0.0, 0.0]
+        for d in range(dim):
+            f = min(max(x[d] / h[d] - 0.5, 0.0), n[d] - 1.0)
+            i = min(int(math.floor(f)), max(n[d] - 2, 0))
+            lo[d], t[d] = i, f - i
+        acc = np.zeros(6)
+        wsum = 0.0
+        for c in range(8 if dim == 3 else 4):
+            idx, wt = [], 1.0
+            for d in range(3):
+                bit = (c >> d) & 1
+                if d >= dim:
+                    idx.append(0)
+                    continue
+                idx.append(min(lo[d] + bit, n[d] - 1))
+                wt *= t[d] if bit else 1.0 - t[d]
+            i, j, k = idx
+            if not fluid[k, j, i]:
+                continue
+            wsum += wt
+            for a, nm in enumerate(names):
+                acc[a] += wt * fields[nm][k, j, i]
+        if wsum > 0.0:
+            val = acc / wsum
+            out[q] = (math.sqrt(val[0] ** 2 + val[1] ** 2 + val[2] ** 2), val[3], val[4], val[5])
+    return out
+
+
+def ghost_tables(case):
+    """The oracle's boundary classification as arrays over the flattened
+    cells: neighbour index per face direction (-1: ghost), the affine ghost
+    rule a0 + a1 value_P per direction and field (u, v, w, p, T, k, omega,
+    nu_t), and the fixed-omega flag."""
+    oc = OracleCase(case)
+    n = int(np.prod(oc.shape))
+    nidx = np.zeros((n, 6), dtype=np.int32)
+    a0 = np.zeros((n, 6, 8))
+    a1 = np.zeros((n, 6, 8))
+    fixed = np.zeros(n, dtype=np.uint8)
+    lib().orc_ghost_table(oc.ref, nidx.ctypes.data_as(C.POINTER(C.c_int)), _ptr(a0), _ptr(a1),
+                          fixed.ctypes.data_as(C.POINTER(C.c_ubyte)))
+    return nidx, a0, a1, fixed.astype(bool)
 
 
 def rhs_b(case, us, vs, ws):

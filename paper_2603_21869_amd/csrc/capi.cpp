@@ -171,6 +171,25 @@ nfvm_status nfvm_pressure_adjoint_device(nfvm_grid_t grid, const double* ubar,
   });
 }
 
+nfvm_status nfvm_explicit_adjoint_device(nfvm_grid_t grid, const nfvm_fields* state,
+                                         const nfvm_fields* bar, nfvm_fields* out) {
+  if (!grid || !state || !bar || !out) return fail(NFVM_E_INVAL, "grid, state, bar and out are required");
+  return guard([&] {
+    grid->g->explicit_adjoint(*state, *bar, *out);
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_destroy_adjoint_device(nfvm_grid_t grid, const nfvm_fields* state, double tau,
+                                        const double* kbar, const double* wbar,
+                                        nfvm_fields* out) {
+  if (!grid || !state || !out) return fail(NFVM_E_INVAL, "grid, state and out are required");
+  return guard([&] {
+    grid->g->destroy_adjoint(*state, tau, kbar, wbar, *out);
+    return NFVM_OK;
+  });
+}
+
 nfvm_status nfvm_mg_solve(nfvm_grid_t grid, const double* b, double* x, double tol,
                           int32_t max_cycles, int32_t forced_cycles, nfvm_step_stats* stats) {
   if (!grid || !b || !x) return fail(NFVM_E_INVAL, "grid, b and x are required");
@@ -205,6 +224,14 @@ nfvm_status nfvm_lambda2(nfvm_grid_t grid, double* lambda2) {
   if (!grid || !lambda2) return fail(NFVM_E_INVAL, "grid and lambda2 are required");
   return guard([&] {
     grid->g->lambda2(lambda2);
+    return NFVM_OK;
+  });
+}
+
+nfvm_status nfvm_line_probe(nfvm_grid_t grid, const double* pts, int32_t n, double* out) {
+  if (!grid) return fail(NFVM_E_INVAL, "grid is required");
+  return guard([&] {
+    grid->g->probe(pts, n, out);
     return NFVM_OK;
   });
 }

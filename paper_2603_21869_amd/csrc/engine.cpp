@@ -297,6 +297,7 @@ class GridT : public GridBase {
   // alternate between iterations
   void* dir[2] = {nullptr, nullptr};
   double* stage = nullptr;
+  double* adj_scratch = nullptr;  // reverse modes of the explicit and destruction steps
   RedBuf red{};
   int* cmap = nullptr;
   int* ncount = nullptr;
@@ -750,6 +751,76 @@ class GridT : public GridBase {
     NFVM_CK(hipGetLastError());
     NFVM_CK(hipMemcpyAsync(out, stage, (size_t)ncells * sizeof(double), hipMemcpyDeviceToHost,
                            stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  void probe(const double* pts, int n, double* out) override {
+    if (n < 0 || (n > 0 && (!pts || !out)))
+      throw Error{NFVM_E_INVAL, "points and an output array are required"};
+    // points and results pass through the staging buffer
+    if ((long long)7 * n > ncells)
+      throw Error{NFVM_E_INVAL, "at most " + std::to_string(ncells / 7) +
+                                    " probe points per call on this grid"};
+    if (n == 0) return;
+    double* dp = stage;
+    double* dout = stage + 3 * (size_t)n;
+    NFVM_CK(hipMemcpyAsync(dp, pts, 3 * (size_t)n * sizeof(double), hipMemcpyHostToDevice,
+                           stream));
+    launch_probe<V, F>(g, type, vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5), ph.T_ref,
+                       dp, n, dout, stream);
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipMemcpyAsync(out, dout, 4 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                           stream));
+    NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  void explicit_adjoint(const nfvm_fields& st, const nfvm_fields& bar,
+                        const nfvm_fields& out) override {
+    const double* sp[7] = {st.u, st.v, st.w, st.p, st.T, st.k, st.omega};
+    const double* yb[6] = {bar.u, bar.v, bar.w, bar.T, bar.k, bar.omega};
+    double* xb[7] = {out.u, out.v, out.w, out.p, out.T, out.k, out.omega};
+    for (const double* q : sp)
+      if (!q) throw Error{NFVM_E_INVAL, "all seven state arrays are required"};
+    for (const double* q : yb)
+      if (!q) throw Error{NFVM_E_INVAL, "the six output adjoints are required"};
+    for (double* q : xb)
+      if (!q) throw Error{NFVM_E_INVAL, "all seven input adjoint arrays are required"};
+    const size_t T = (size_t)g.total;
+    // (allocated on first use: 21 padded FP64 arrays)
+    if (!adj_scratch) adj_scratch = alloc<double>(21 * T, "adjoint scratch");
+    double* S = adj_scratch;
+    const double* sd[7];
+    for (int f = 0; f < 7; ++f) {
+      launch_pack<double>(g, sp[f], S + f * T, f == 4 ? ph.T_ref : 0.0, stream);
+      sd[f] = S + f * T;
+    }
+    launch_explicit_adjoint(g, ph, type, patches, sd, yb, S + 7 * T, S + 13 * T, S + 15 * T, xb,
+                            stream);
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  void destroy_adjoint(const nfvm_fields& st, double tau, const double* kb, const double* wb,
+                       const nfvm_fields& out) override {
+    const double* sp[5] = {st.u, st.v, st.w, st.k, st.omega};
+    double* xb[5] = {out.u, out.v, out.w, out.k, out.omega};
+    for (const double* q : sp)
+      if (!q) throw Error{NFVM_E_INVAL, "the state's u, v, w, k and omega are required"};
+    for (double* q : xb)
+      if (!q) throw Error{NFVM_E_INVAL, "the adjoints of u, v, w, k and omega are required"};
+    if (!kb || !wb) throw Error{NFVM_E_INVAL, "the adjoints of k and omega are required"};
+    if (!(tau >= 0.0)) throw Error{NFVM_E_INVAL, "tau must be >= 0"};
+    const size_t T = (size_t)g.total;
+    if (!adj_scratch) adj_scratch = alloc<double>(21 * T, "adjoint scratch");
+    double* S = adj_scratch;
+    const double* sd[5];
+    for (int f = 0; f < 5; ++f) {
+      launch_pack<double>(g, sp[f], S + f * T, 0.0, stream);
+      sd[f] = S + f * T;
+    }
+    launch_destroy_adjoint(g, ph, type, patches, sd, tau, kb, wb, S + 5 * T, S + 11 * T, xb,
+                           stream);
+    NFVM_CK(hipGetLastError());
     NFVM_CK(hipStreamSynchronize(stream));
   }
 

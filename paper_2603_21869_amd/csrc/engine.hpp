@@ -131,6 +131,12 @@ class GridBase {
                                 double* scratch, size_t n_doubles) = 0;
   virtual void get_fields(nfvm_fields* out) = 0;
   virtual void lambda2(double* out) = 0;
+  virtual void probe(const double* pts, int n, double* out) = 0;
+  // device FP64 dense arrays; see nfvm_explicit_adjoint_device
+  virtual void explicit_adjoint(const nfvm_fields& st, const nfvm_fields& bar,
+                                const nfvm_fields& out) = 0;
+  virtual void destroy_adjoint(const nfvm_fields& st, double tau, const double* kb,
+                               const double* wb, const nfvm_fields& out) = 0;
   virtual void set_fields(const nfvm_fields* in) = 0;
   virtual void set_option(int opt, double v) = 0;
   // buffers whose guard zone an out-of-bounds store has written (empty: none)

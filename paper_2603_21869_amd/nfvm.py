@@ -24,8 +24,10 @@ _dp = C.POINTER(C.c_double)
 EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_step_batch", "nfvm_mg_solve",
     "nfvm_mg_solve_device", "nfvm_mg_solve_device_noalloc", "nfvm_mg_solve_adjoint_device",
-    "nfvm_pressure_adjoint_device", "nfvm_tune",
-    "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_grid_footprint",
+    "nfvm_pressure_adjoint_device", "nfvm_explicit_adjoint_device",
+    "nfvm_destroy_adjoint_device", "nfvm_tune",
+    "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_line_probe",
+    "nfvm_grid_footprint",
     "nfvm_reduction_blocks", "nfvm_free_grid",
     "nfvm_server_create", "nfvm_submit", "nfvm_poll", "nfvm_request_times", "nfvm_server_drain",
     "nfvm_server_destroy", "nfvm_profile", "nfvm_profile_read", "nfvm_set_option", "nfvm_tuning_table",
@@ -103,6 +105,14 @@ def lib():
             C.c_double, C.c_int32, C.c_int32, C.POINTER(nfvm_step_stats)]
         L.nfvm_get_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
         L.nfvm_lambda2.argtypes = [C.c_void_p, C.POINTER(C.c_double)]
+        L.nfvm_explicit_adjoint_device.argtypes = [C.c_void_p, C.POINTER(nfvm_fields),
+                                                   C.POINTER(nfvm_fields),
+                                                   C.POINTER(nfvm_fields)]
+        L.nfvm_destroy_adjoint_device.argtypes = [C.c_void_p, C.POINTER(nfvm_fields), C.c_double,
+                                                  C.c_void_p, C.c_void_p,
+                                                  C.POINTER(nfvm_fields)]
+        L.nfvm_line_probe.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                                      C.POINTER(C.c_double)]
         L.nfvm_set_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
         L.nfvm_grid_footprint.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(C.c_size_t)]
         L.nfvm_reduction_blocks.argtypes = [C.POINTER(nfvm_grid_desc), C.POINTER(C.c_int32),
@@ -265,6 +275,29 @@ def nfvm_pressure_adjoint_device(grid, bars, outs, tol: float = 1e-10, max_cycle
     return st.as_dict(), s
 
 
+def _dev_fields(ptrs) -> nfvm_fields:
+    f = nfvm_fields()
+    for nm in ("u", "v", "w", "p", "T", "k", "omega"):
+        q = ptrs.get(nm)
+        setattr(f, nm, C.cast(C.c_void_p(q), C.POINTER(C.c_double)) if q else None)
+    return f
+
+
+def nfvm_explicit_adjoint_device(grid, state, bars, outs):
+    """Reverse mode of the explicit stage on device FP64 arrays: state, bars
+    and outs map field names (u v w p T k omega) to device pointers."""
+    s, b, o = _dev_fields(state), _dev_fields(bars), _dev_fields(outs)
+    _check(lib().nfvm_explicit_adjoint_device(grid, C.byref(s), C.byref(b), C.byref(o)))
+
+
+def nfvm_destroy_adjoint_device(grid, state, tau: float, kbar: int, wbar: int, outs):
+    """Reverse mode of the destruction step on device FP64 arrays: state and
+    outs map u v w k omega to device pointers; kbar, wbar are pointers."""
+    s, o = _dev_fields(state), _dev_fields(outs)
+    _check(lib().nfvm_destroy_adjoint_device(grid, C.byref(s), tau, C.c_void_p(kbar),
+                                             C.c_void_p(wbar), C.byref(o)))
+
+
 def nfvm_mg_solve_device_noalloc(grid, b_ptr: int, x_ptr: int, tol: float = 1e-10,
                                  max_cycles: int = 100, forced_cycles: int = -1,
                                  allow=(NFVM_OK,)):
@@ -281,6 +314,21 @@ def nfvm_lambda2(grid, shape) -> np.ndarray:
     out = np.zeros(shape)
     _check(lib().nfvm_lambda2(grid, out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
+
+
+def nfvm_line_probe(grid, pts) -> np.ndarray:
+    """{V, T, k, omega} at points (metres, shape (n, 3)) of the grid's fields."""
+    p = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 3))
+    out = np.empty((len(p), 4))
+    _check(lib().nfvm_line_probe(grid, p.ctypes.data_as(C.POINTER(C.c_double)), len(p),
+                                 out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def line(p0, p1, n: int) -> np.ndarray:
+    """n points evenly spaced from p0 to p1 (both included)."""
+    t = np.linspace(0.0, 1.0, n)[:, None]
+    return (1.0 - t) * np.asarray(p0, dtype=np.float64) + t * np.asarray(p1, dtype=np.float64)
 
 
 def nfvm_get_fields(grid, shape) -> Dict[str, np.ndarray]:
@@ -412,6 +460,9 @@ class Grid:
 
     def lambda2(self):
         return nfvm_lambda2(self.h, self.shape)
+
+    def probe(self, pts):
+        return nfvm_line_probe(self.h, pts)
 
     def set_fields(self, f):
         nfvm_set_fields(self.h, f)

@@ -97,3 +97,89 @@ def test_pressure_adjoint_matches_oracle(nf, oracle, name, case, prec):
     m = fluid(case)
     for d in range(3):
         assert np.array_equal(got[d][~m], bars[d][~m])
+
+
+def _ex_state(case, seed):
+    """The case's fields with seeded perturbations that make every term of
+    the explicit stage active (as in the oracle's pins)."""
+    rng = np.random.default_rng(seed)
+    f = {k: np.array(v, dtype=np.float64) for k, v in case.fields.items()}
+    sh = f["u"].shape
+    scale = max(np.abs(f["u"]).max(), 0.1)
+    for nm in ("u", "v", "w"):
+        f[nm] = f[nm] + 0.3 * scale * rng.standard_normal(sh)
+    if case.dim == 2:
+        f["w"][:] = 0.0
+    f["p"] = 0.05 * rng.standard_normal(sh)
+    f["T"] = f["T"] + 2.0 * rng.standard_normal(sh)
+    f["k"] = f["k"] * (1.0 + 0.5 * rng.random(sh)) + 1e-4
+    f["omega"] = f["omega"] * (1.0 + 0.5 * rng.random(sh)) + 1.0
+    return f
+
+
+@pytest.mark.parametrize("name,case", _cases(), ids=[c[0] for c in _cases()])
+def test_explicit_adjoint_matches_autodiff(nf, name, case):
+    """nfvm_explicit_adjoint_device against the autodiff reverse mode of the
+    oracle's explicit stage (pinned by finite differences of the C oracle):
+    every input adjoint over every cell to 1e-10 of its largest value, on
+    grids of each precision (the adjoint's arithmetic is FP64 in all); with
+    a k adjoint on a cell whose k the stage clamps, that cell's k adjoint is
+    the oracle's too."""
+    import torch
+    from oracle import autodiff as AD
+    f = _ex_state(case, 4)
+    rng = np.random.default_rng(9)
+    outs = ("u", "v", "w", "T", "k", "omega")
+    ybar = {nm: rng.standard_normal(f["u"].shape) for nm in outs}
+    ref = AD.explicit_vjp(case, f, ybar)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    st = {nm: dev(f[nm]) for nm in ("u", "v", "w", "p", "T", "k", "omega")}
+    yb = {nm: dev(ybar[nm]) for nm in outs}
+    for prec in (C.PREC_FP64, C.PREC_MIXED):
+        g = nf.Grid(case.copy(precision=prec))
+        xb = {nm: torch.full_like(st["u"], float("nan")) for nm in st}
+        nf.nfvm_explicit_adjoint_device(g.h, {k: v.data_ptr() for k, v in st.items()},
+                                        {k: v.data_ptr() for k, v in yb.items()},
+                                        {k: v.data_ptr() for k, v in xb.items()})
+        torch.cuda.synchronize()
+        g.close()
+        for nm in st:
+            got = xb[nm].cpu().numpy()
+            scale = max(np.abs(ref[nm]).max(), 1e-300)
+            err = np.abs(got - ref[nm]).max() / scale
+            print(f"[ex-adjoint] {name} prec={prec} {nm} max|ref|={scale:.3e} err={err:.2e}",
+                  flush=True)
+            assert np.isfinite(got).all() and err <= 1e-10, (name, prec, nm, err)
+
+
+@pytest.mark.parametrize("name,case", _cases(), ids=[c[0] for c in _cases()])
+def test_destroy_adjoint_matches_autodiff(nf, name, case):
+    """nfvm_destroy_adjoint_device against the autodiff reverse mode of the
+    oracle's destruction step (pinned by finite differences of the C
+    oracle), over half a time step and over a long tau where the limiters
+    vary: the adjoints of u, v, w, k, omega to 1e-10 of their largest value."""
+    import torch
+    from oracle import autodiff as AD
+    f = _ex_state(case, 5)
+    rng = np.random.default_rng(10)
+    kb, wb = rng.standard_normal(f["u"].shape), rng.standard_normal(f["u"].shape)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    names = ("u", "v", "w", "k", "omega")
+    st = {nm: dev(f[nm]) for nm in names}
+    kbd, wbd = dev(kb), dev(wb)
+    g = nf.Grid(case.copy(precision=C.PREC_FP64))
+    for tau in (0.5 * case.dt, 40.0 * case.dt):
+        ref = AD.destroy_vjp(case, f, tau, kb, wb)
+        xb = {nm: torch.full_like(st["u"], float("nan")) for nm in names}
+        nf.nfvm_destroy_adjoint_device(g.h, {k: v.data_ptr() for k, v in st.items()}, tau,
+                                       kbd.data_ptr(), wbd.data_ptr(),
+                                       {k: v.data_ptr() for k, v in xb.items()})
+        torch.cuda.synchronize()
+        for nm in names:
+            got = xb[nm].cpu().numpy()
+            scale = max(np.abs(ref[nm]).max(), 1e-300)
+            err = np.abs(got - ref[nm]).max() / scale
+            print(f"[des-adjoint] {name} tau={tau:.2e} {nm} max|ref|={scale:.3e} err={err:.2e}",
+                  flush=True)
+            assert np.isfinite(got).all() and err <= 1e-10, (name, tau, nm, err)
+    g.close()

@@ -726,3 +726,36 @@ def test_bottom_solver_and_graphs_match_plain_launches(nf, oracle):
     for (out, cyc) in outs:
         ref, _, _ = oracle.step(case, 3, forced_cycles=cyc)
         check_fields(case, out, ref, 1e-10, tag=f"cycles {cyc}")
+
+
+@pytest.mark.parametrize("name,case", _nearest_cases(), ids=[c[0] for c in _nearest_cases()])
+def test_line_probes_match_oracle(nf, oracle, name, case):
+    """nfvm_line_probe (Sec. 3.1) after two steps: V, T, k and omega along
+    the lines the paper compares (three streamwise lines at fractions of the
+    height above the bottom wall's centre line and a vertical line through
+    the outlet's centre), plus random points, some of them outside the box of
+    cell centres or among solid cells, match the oracle's probes of the GPU's
+    own fields to 1e-12 (FP64 arithmetic on the stored values in every
+    precision); NaN exactly where the oracle has it."""
+    L = [case.n[d] * case.h[d] for d in range(3)]
+    zc = 0.5 * L[2] if case.dim == 3 else 0.0
+    lines = [nf.line([0.0, f * L[1], zc], [L[0], f * L[1], zc], 33) for f in (0.27, 0.53, 0.8)]
+    lines.append(nf.line([L[0], 0.0, zc], [L[0], L[1], zc], 17))
+    rng = np.random.default_rng(11)
+    lines.append(np.column_stack([rng.uniform(-0.05 * L[d], 1.05 * L[d], 64) for d in range(3)]))
+    pts = np.vstack(lines)
+    for prec in (C.PREC_FP64, C.PREC_MIXED, C.PREC_FP32):
+        g = nf.Grid(case.copy(precision=prec))
+        g.step(2, allow=(0, nf.NFVM_E_NOTCONV))
+        f = g.fields()
+        got = g.probe(pts)
+        assert g.probe(np.zeros((0, 3))).shape == (0, 4)
+        g.close()
+        ref = oracle.line_probe(case, f, pts)
+        nan = np.isnan(ref)
+        assert np.array_equal(np.isnan(got), nan), (name, prec)
+        scale = np.nanmax(np.abs(ref), axis=0)
+        err = (np.abs(got - ref)[~nan.any(1)] / scale).max()
+        print(f"[probe] {name} prec={prec} points={len(pts)} nan={nan.any(1).sum()} "
+              f"err={err:.2e}", flush=True)
+        assert err <= 1e-12, (name, prec, err)
