@@ -191,7 +191,7 @@ class Stage:
 
 def _tensors(fields, grad: bool):
     return {nm: torch.tensor(np.ascontiguousarray(fields[nm], dtype=np.float64).reshape(-1),
-                             requires_grad=grad) for nm in NAMES}
+                             requires_grad=grad) for nm in NAMES if nm in fields}
 
 
 def explicit_forward(case, fields) -> Dict[str, np.ndarray]:
@@ -247,3 +247,51 @@ def destroy_vjp(case, fields, tau: float, kbar, wbar) -> Dict[str, np.ndarray]:
     shape = tuple(case.n[::-1])
     return {nm: (np.zeros(shape) if gr is None else gr.numpy().reshape(shape))
             for nm, gr in zip(names, grads)}
+
+
+def step_vjp(case, fields, bars, tol: float = 1e-13, max_cycles: int = 200) -> Dict[str, np.ndarray]:
+    """Reverse mode of one whole time step (the oracle's step: omega reset
+    on wall-adjacent cells, destruction over dt/2, the explicit stage, the
+    pressure step, destruction over dt/2; Sec. 2.3 to 2.5) at the state
+    `fields`: the adjoints of the seven input fields from those of the seven
+    output fields.  The forward stages are the C oracle's (the solve to tol),
+    the reverse modes of the destruction and explicit stages this module's,
+    that of the pressure step the C oracle's (an exact second solve).  The
+    solve is differentiated as the exact A^-1 (implicit differentiation)."""
+    c = case
+    komega = c.physics & KOMEGA
+    f0 = {nm: np.array(fields[nm], dtype=np.float64) for nm in NAMES}
+    f0["omega"] = O.fixed_omega(c, f0["omega"])
+    half = 0.5 * c.dt
+    if komega:
+        kd, wd = O.destroy(c, f0["u"], f0["v"], f0["w"], f0["k"], f0["omega"], half)
+    else:
+        kd, wd = f0["k"], f0["omega"]
+    s1 = dict(f0, k=kd, omega=wd)
+    t = O.explicit(c, s1)
+    b = O.rhs_b(c, t["u"], t["v"], t["w"])
+    phi, _, _, _ = O.MG(c).solve(b, tol=tol, max_cycles=max_cycles)
+    _, u1, v1, w1, _ = O.project(c, phi, t["u"], t["v"], t["w"], f0["p"])
+    ub = {nm: np.array(bars[nm], dtype=np.float64) for nm in ("u", "v", "w")}
+    if komega:
+        d2 = destroy_vjp(c, dict(u=u1, v=v1, w=w1, k=t["k"], omega=t["omega"]), half, bars["k"],
+                         bars["omega"])
+        for nm in ub:
+            ub[nm] = ub[nm] + d2[nm]
+        ksb, wsb = d2["k"], d2["omega"]
+    else:
+        ksb, wsb = bars["k"], bars["omega"]
+    usb, vsb, wsb_vel = O.pressure_adjoint(c, ub["u"], ub["v"], ub["w"], bars["p"], tol=tol,
+                                           max_cycles=max_cycles)[:3]
+    ex = explicit_vjp(c, s1, dict(u=usb, v=vsb, w=wsb_vel, T=bars["T"], k=ksb, omega=wsb))
+    out = dict(ex)
+    out["p"] = np.asarray(bars["p"], dtype=np.float64) + ex["p"]
+    if komega:
+        d1 = destroy_vjp(c, f0, half, ex["k"], ex["omega"])
+        for nm in ("u", "v", "w"):
+            out[nm] = ex[nm] + d1[nm]
+        out["k"], out["omega"] = d1["k"], d1["omega"]
+        # the reset holds omega on wall-adjacent cells whatever its input
+        held = O.fixed_omega(c, np.full(f0["omega"].shape, np.nan))
+        out["omega"] = np.where(np.isnan(held), out["omega"], 0.0)
+    return out

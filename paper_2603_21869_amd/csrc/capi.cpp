@@ -190,6 +190,21 @@ nfvm_status nfvm_destroy_adjoint_device(nfvm_grid_t grid, const nfvm_fields* sta
   });
 }
 
+nfvm_status nfvm_step_adjoint_device(nfvm_grid_t grid, const nfvm_fields* state,
+                                     const nfvm_fields* bar, nfvm_fields* out, double tol,
+                                     int32_t max_cycles, int32_t forced_cycles,
+                                     nfvm_step_stats* stats) {
+  if (!grid || !state || !bar || !out)
+    return fail(NFVM_E_INVAL, "grid, state, bar and out are required");
+  return guard([&] {
+    nfvm_status st = NFVM_OK;
+    grid->g->step_adjoint(*state, *bar, *out, tol, max_cycles, forced_cycles, stats, &st);
+    if (st == NFVM_E_NOTCONV) set_error("a pressure solve reached max_cycles");
+    if (st == NFVM_E_DIVERGED) set_error("non-finite residual");
+    return st;
+  });
+}
+
 nfvm_status nfvm_mg_solve(nfvm_grid_t grid, const double* b, double* x, double tol,
                           int32_t max_cycles, int32_t forced_cycles, nfvm_step_stats* stats) {
   if (!grid || !b || !x) return fail(NFVM_E_INVAL, "grid, b and x are required");

@@ -298,6 +298,7 @@ class GridT : public GridBase {
   void* dir[2] = {nullptr, nullptr};
   double* stage = nullptr;
   double* adj_scratch = nullptr;  // reverse modes of the explicit and destruction steps
+  double* adj_dense = nullptr;    // reverse mode of the whole step
   RedBuf red{};
   int* cmap = nullptr;
   int* ncount = nullptr;
@@ -822,6 +823,153 @@ class GridT : public GridBase {
                            stream);
     NFVM_CK(hipGetLastError());
     NFVM_CK(hipStreamSynchronize(stream));
+  }
+
+  // Reverse mode of one whole step at a state: the step is run forward from
+  // the state on the grid's fields (which keep its result), with the stage
+  // inputs the reverse modes need kept as dense copies, then the stages'
+  // reverse modes are applied in reverse order.
+  void step_adjoint(const nfvm_fields& st, const nfvm_fields& bar, const nfvm_fields& out,
+                    double tol_, int maxc, int forced, nfvm_step_stats* stt,
+                    nfvm_status* status) override {
+    if (rk_order != 1)
+      throw Error{NFVM_E_INVAL, "the reverse mode covers the forward-Euler explicit stage"};
+    const double* sp[7] = {st.u, st.v, st.w, st.p, st.T, st.k, st.omega};
+    const double* bp[7] = {bar.u, bar.v, bar.w, bar.p, bar.T, bar.k, bar.omega};
+    double* op[7] = {out.u, out.v, out.w, out.p, out.T, out.k, out.omega};
+    for (int f = 0; f < 7; ++f)
+      if (!sp[f] || !bp[f] || !op[f])
+        throw Error{NFVM_E_INVAL, "all seven state, adjoint and output arrays are required"};
+    const size_t N = (size_t)ncells;
+    // dense scratch: s0 (7), k and omega after the first destruction (2),
+    // the explicit stage's u, v, w, k, omega (5), the projected u, v, w (3),
+    // the adjoint of that velocity (3), a destruction's reverse mode (5),
+    // the pressure step's (3), the explicit stage's (7)
+    if (!adj_dense) adj_dense = alloc<double>(35 * N, "step adjoint scratch");
+    double* D = adj_dense;
+    auto slot = [&](int q) { return D + (size_t)q * N; };
+    NFVM_CK(hipStreamSynchronize(stream));
+    // the state as the grid's fields, omega held on wall-adjacent cells (as
+    // nfvm_set_fields loads fields)
+    for (int f = 0; f < 3; ++f) launch_pack<V>(g, sp[f], vcur(f), 0.0, stream);
+    launch_pack<P>(g, sp[3], p, 0.0, stream);
+    launch_pack<F>(g, sp[4], scur(3), ph.T_ref, stream);
+    launch_pack<F>(g, sp[5], scur(4), 0.0, stream);
+    launch_pack<F>(g, sp[6], scur(5), 0.0, stream);
+    if (ph.komega) launch_set_omega_wall<F>(g, ph, patches, type, scur(5), stream);
+    clear_increment();
+    for (int f = 0; f < 3; ++f) launch_unpack<V>(g, vcur(f), slot(f), 0.0, stream);
+    launch_unpack<P>(g, p, slot(3), 0.0, stream);
+    launch_unpack<F>(g, scur(3), slot(4), ph.T_ref, stream);
+    launch_unpack<F>(g, scur(4), slot(5), 0.0, stream);
+    launch_unpack<F>(g, scur(5), slot(6), 0.0, stream);
+    // forward: destruction over dt/2, explicit stage, pressure step
+    const double half = 0.5 * ph.dt;
+    if (ph.komega) {
+      launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
+                           half, salt(4), salt(5), nut, nullptr, tp[TP_DESTROY], stream);
+      swap(4);
+      swap(5);
+    }
+    launch_unpack<F>(g, scur(4), slot(7), 0.0, stream);
+    launch_unpack<F>(g, scur(5), slot(8), 0.0, stream);
+    {
+      FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
+      FieldSet<V, F> outf{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
+      launch_explicit<V, F, P>(g, ph, type, patches, in, p, nut, outf, tp[TP_EXPLICIT], stream);
+      for (int f = 0; f < 6; ++f) swap(f);
+    }
+    for (int f = 0; f < 3; ++f) launch_unpack<V>(g, vcur(f), slot(9 + f), 0.0, stream);
+    launch_unpack<F>(g, scur(4), slot(12), 0.0, stream);
+    launch_unpack<F>(g, scur(5), slot(13), 0.0, stream);
+    launch_rhs_b<V, O>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), bvec, red, tp[TP_RHS],
+                       stream);
+    int cyc = 0;
+    double rel = 0.0;
+    last_diag.clear();
+    nfvm_status sst = solve(false, tol_, maxc, forced, &cyc, &rel);
+    if (sst == NFVM_E_DIVERGED) {
+      last_diag = diagnose();
+      *status = sst;
+      return;
+    }
+    flush_x();
+    launch_project<V, P, O>(g, ph, type, patches, phi, vcur(0), vcur(1), vcur(2), valt(0),
+                            valt(1), valt(2), p, red, tp[TP_PROJECT], stream);
+    swap(0);
+    swap(1);
+    swap(2);
+    for (int f = 0; f < 3; ++f) launch_unpack<V>(g, vcur(f), slot(14 + f), 0.0, stream);
+    if (ph.komega) {  // (completes the step on the grid's fields)
+      launch_destroy<V, F>(g, ph, type, patches, vcur(0), vcur(1), vcur(2), scur(4), scur(5),
+                           half, salt(4), salt(5), nullptr, nullptr, tp[TP_DESTROY], stream);
+      swap(4);
+      swap(5);
+    }
+    clear_increment();
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipStreamSynchronize(stream));
+    if (stt) {
+      memset(&stt[0], 0, sizeof stt[0]);
+      stt[0].cycles = cyc;
+      stt[0].status = sst;
+      stt[0].rel_residual = rel;
+      stt[0].min_k = stt[0].min_omega = NAN;
+    }
+    // reverse: second destruction (its velocity is the projected one, also a
+    // step output), pressure step, explicit stage, first destruction
+    double* ub1[3] = {slot(17), slot(18), slot(19)};
+    double* d5[5] = {slot(20), slot(21), slot(22), slot(23), slot(24)};
+    const double* ksb = bp[5];
+    const double* wsb = bp[6];
+    if (ph.komega) {
+      const nfvm_fields s2{slot(14), slot(15), slot(16), nullptr, nullptr, slot(12), slot(13)};
+      const nfvm_fields o2{d5[0], d5[1], d5[2], nullptr, nullptr, d5[3], d5[4]};
+      destroy_adjoint(s2, half, bp[5], bp[6], o2);
+      for (int f = 0; f < 3; ++f) launch_dense_add(N, bp[f], d5[f], ub1[f], stream);
+      ksb = d5[3];
+      wsb = d5[4];
+    } else {
+      for (int f = 0; f < 3; ++f)
+        NFVM_CK(hipMemcpyAsync(ub1[f], bp[f], N * sizeof(double), hipMemcpyDeviceToDevice,
+                               stream));
+    }
+    double* usb[3] = {slot(25), slot(26), slot(27)};
+    nfvm_status ast = NFVM_OK;
+    pressure_adjoint(ub1[0], ub1[1], ub1[2], bp[3], usb[0], usb[1], usb[2], tol_, maxc, forced,
+                     stt ? &stt[1] : nullptr, &ast);
+    if (ast == NFVM_E_DIVERGED) {
+      *status = ast;
+      return;
+    }
+    double* xo[7];
+    for (int f = 0; f < 7; ++f) xo[f] = slot(28 + f);
+    {
+      const nfvm_fields s1{slot(0), slot(1), slot(2), slot(3), slot(4), slot(7), slot(8)};
+      const nfvm_fields b1{usb[0], usb[1], usb[2], nullptr, const_cast<double*>(bp[4]),
+                           const_cast<double*>(ksb), const_cast<double*>(wsb)};
+      const nfvm_fields o1{xo[0], xo[1], xo[2], xo[3], xo[4], xo[5], xo[6]};
+      explicit_adjoint(s1, b1, o1);
+    }
+    launch_dense_add(N, bp[3], xo[3], op[3], stream);  // p^n also passes to p
+    NFVM_CK(hipMemcpyAsync(op[4], xo[4], N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    if (ph.komega) {
+      const nfvm_fields s0{slot(0), slot(1), slot(2), nullptr, nullptr, slot(5), slot(6)};
+      const nfvm_fields o0{d5[0], d5[1], d5[2], nullptr, nullptr, d5[3], d5[4]};
+      destroy_adjoint(s0, half, xo[5], xo[6], o0);
+      for (int f = 0; f < 3; ++f) launch_dense_add(N, xo[f], d5[f], op[f], stream);
+      NFVM_CK(hipMemcpyAsync(op[5], d5[3], N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      NFVM_CK(hipMemcpyAsync(op[6], d5[4], N * sizeof(double), hipMemcpyDeviceToDevice, stream));
+      // the load holds omega on wall-adjacent cells whatever its input
+      launch_zero_held(g, type, op[6], stream);
+    } else {
+      for (int f : {0, 1, 2, 5, 6})
+        NFVM_CK(hipMemcpyAsync(op[f], xo[f], N * sizeof(double), hipMemcpyDeviceToDevice,
+                               stream));
+    }
+    NFVM_CK(hipGetLastError());
+    NFVM_CK(hipStreamSynchronize(stream));
+    *status = sst != NFVM_OK ? sst : ast;
   }
 
   // ---- multigrid ------------------------------------------------------------------

@@ -137,6 +137,9 @@ class GridBase {
                                 const nfvm_fields& out) = 0;
   virtual void destroy_adjoint(const nfvm_fields& st, double tau, const double* kb,
                                const double* wb, const nfvm_fields& out) = 0;
+  virtual void step_adjoint(const nfvm_fields& st, const nfvm_fields& bar, const nfvm_fields& out,
+                            double tol, int maxc, int forced, nfvm_step_stats* stt,
+                            nfvm_status* status) = 0;
   virtual void set_fields(const nfvm_fields* in) = 0;
   virtual void set_option(int opt, double v) = 0;
   // buffers whose guard zone an out-of-bounds store has written (empty: none)

@@ -599,4 +599,30 @@ void launch_destroy_adjoint(const Geom& g, const Phys& ph, const uint8_t* type,
                      xb[1], xb[2], xb[3], xb[4]);
 }
 
+// ---- helpers of the whole step's reverse mode ------------------------------------
+__global__ void k_dense_add(size_t n, const double* __restrict__ a, const double* __restrict__ b,
+                            double* __restrict__ out) {
+  const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) out[q] = a[q] + b[q];
+}
+// out = a + b over n dense values
+void launch_dense_add(size_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_dense_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, b,
+                     out);
+}
+
+__global__ void k_zero_held(Geom g, const uint8_t* __restrict__ type, double* __restrict__ a) {
+  const int i = blockIdx.x * ABX + threadIdx.x, j = blockIdx.y * ABY + threadIdx.y,
+            k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const uint8_t t = type[g.idx(i, j, k)];
+  if (is_fluid(t) && (t & FIXED_BIT)) a[((size_t)k * g.ny + j) * g.nx + i] = 0.0;
+}
+// zero the dense adjoint a on the wall-adjacent cells whose omega is held
+void launch_zero_held(const Geom& g, const uint8_t* type, double* a, hipStream_t s) {
+  const dim3 G((g.nx + ABX - 1) / ABX, (g.ny + ABY - 1) / ABY, g.nz), B(ABX, ABY);
+  hipLaunchKernelGGL(k_zero_held, G, B, 0, s, g, type, a);
+}
+
 }  // namespace nfvm

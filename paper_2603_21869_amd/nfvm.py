@@ -25,7 +25,7 @@ EXPORTS = (
     "nfvm_set_allocator", "nfvm_init_grid", "nfvm_step", "nfvm_step_batch", "nfvm_mg_solve",
     "nfvm_mg_solve_device", "nfvm_mg_solve_device_noalloc", "nfvm_mg_solve_adjoint_device",
     "nfvm_pressure_adjoint_device", "nfvm_explicit_adjoint_device",
-    "nfvm_destroy_adjoint_device", "nfvm_tune",
+    "nfvm_destroy_adjoint_device", "nfvm_step_adjoint_device", "nfvm_tune",
     "nfvm_get_fields", "nfvm_set_fields", "nfvm_lambda2", "nfvm_line_probe",
     "nfvm_grid_footprint",
     "nfvm_reduction_blocks", "nfvm_free_grid",
@@ -111,6 +111,10 @@ def lib():
         L.nfvm_destroy_adjoint_device.argtypes = [C.c_void_p, C.POINTER(nfvm_fields), C.c_double,
                                                   C.c_void_p, C.c_void_p,
                                                   C.POINTER(nfvm_fields)]
+        L.nfvm_step_adjoint_device.argtypes = [C.c_void_p, C.POINTER(nfvm_fields),
+                                               C.POINTER(nfvm_fields),
+                                               C.POINTER(nfvm_fields), C.c_double, C.c_int32,
+                                               C.c_int32, C.POINTER(nfvm_step_stats)]
         L.nfvm_line_probe.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                       C.POINTER(C.c_double)]
         L.nfvm_set_fields.argtypes = [C.c_void_p, C.POINTER(nfvm_fields)]
@@ -296,6 +300,18 @@ def nfvm_destroy_adjoint_device(grid, state, tau: float, kbar: int, wbar: int, o
     s, o = _dev_fields(state), _dev_fields(outs)
     _check(lib().nfvm_destroy_adjoint_device(grid, C.byref(s), tau, C.c_void_p(kbar),
                                              C.c_void_p(wbar), C.byref(o)))
+
+
+def nfvm_step_adjoint_device(grid, state, bars, outs, tol: float = 1e-12,
+                             max_cycles: int = 200, forced_cycles: int = -1,
+                             allow=(NFVM_OK,)):
+    """Reverse mode of one whole step on device FP64 arrays (name -> device
+    pointer maps of the seven fields).  Returns the two solves' stats."""
+    s, b, o = _dev_fields(state), _dev_fields(bars), _dev_fields(outs)
+    st = (nfvm_step_stats * 2)()
+    r = _check(lib().nfvm_step_adjoint_device(grid, C.byref(s), C.byref(b), C.byref(o), tol,
+                                              max_cycles, forced_cycles, st), allow)
+    return [st[0].as_dict(), st[1].as_dict()], r
 
 
 def nfvm_mg_solve_device_noalloc(grid, b_ptr: int, x_ptr: int, tol: float = 1e-10,

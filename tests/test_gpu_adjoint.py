@@ -183,3 +183,56 @@ def test_destroy_adjoint_matches_autodiff(nf, name, case):
                   flush=True)
             assert np.isfinite(got).all() and err <= 1e-10, (name, tau, nm, err)
     g.close()
+
+
+def _step_cases():
+    return [
+        ("ch2d", C.channel2d(96, 18, L=4.0, H=1.0, n_levels=2)),
+        ("ch3d", C.channel3d(80, 20, 12, Lx=2.0, Ly=0.5, Lz=0.3, n_levels=3)),
+        ("room", C.room3d(64, 24, 16, size=(10.0, 4.0, 3.0), seed=5, n_levels=4)),
+        ("open", C.open_channel(48, 16, 16, h=0.02, n_levels=3)),
+    ]
+
+
+@pytest.mark.parametrize("name,case", _step_cases(), ids=[c[0] for c in _step_cases()])
+def test_step_adjoint_matches_oracle(nf, name, case):
+    """nfvm_step_adjoint_device on an FP64 grid against the oracle's reverse
+    mode of its time step (the stages' reverse modes composed, pinned by
+    finite differences of the C oracle's step): every input adjoint to 1e-8
+    of its largest value with both pressure solves to 1e-12; the grid holds
+    the forward step's result afterwards, as the oracle's step gives it."""
+    import torch
+    from oracle import autodiff as AD
+    from oracle import oracle as O
+    c = case.copy(precision=C.PREC_FP64, tol=1e-12, max_cycles=200)
+    f = _ex_state(c, 6)
+    rng = np.random.default_rng(13)
+    names = ("u", "v", "w", "p", "T", "k", "omega")
+    bars = {nm: rng.standard_normal(f["u"].shape) for nm in names}
+    if c.dim == 2:
+        bars["w"][:] = 0.0
+    ref = AD.step_vjp(c, f, bars, tol=1e-12)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    st = {nm: dev(f[nm]) for nm in names}
+    bd = {nm: dev(bars[nm]) for nm in names}
+    xb = {nm: torch.full_like(st["u"], float("nan")) for nm in names}
+    g = nf.Grid(c)
+    stats, _ = nf.nfvm_step_adjoint_device(g.h, {k: v.data_ptr() for k, v in st.items()},
+                                           {k: v.data_ptr() for k, v in bd.items()},
+                                           {k: v.data_ptr() for k, v in xb.items()}, tol=1e-12)
+    torch.cuda.synchronize()
+    after = g.fields()
+    g.close()
+    print(f"[step-adjoint] {name} cycles fwd={stats[0]['cycles']} adj={stats[1]['cycles']}",
+          flush=True)
+    for nm in names:
+        got = xb[nm].cpu().numpy()
+        scale = max(np.abs(ref[nm]).max(), 1e-300)
+        err = np.abs(got - ref[nm]).max() / scale
+        print(f"[step-adjoint] {name} {nm} max|ref|={scale:.3e} err={err:.2e}", flush=True)
+        assert np.isfinite(got).all() and err <= 1e-8, (name, nm, err)
+    fwd, _, s = O.step(c, 1, fields=f)
+    assert s == 0
+    for nm in names:
+        scale = max(np.abs(fwd[nm]).max(), 1e-300)
+        assert np.abs(after[nm] - fwd[nm]).max() <= 1e-8 * scale, nm
