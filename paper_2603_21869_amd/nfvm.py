@@ -156,6 +156,36 @@ def _check(st: int, allow=(NFVM_OK,)):
     return st
 
 
+_torch_alloc = None  # the installed callbacks (kept alive while installed)
+
+
+def use_torch_allocator(on: bool = True):
+    """Route the library's later device allocations through PyTorch's
+    caching allocator on the current device (nfvm_set_allocator), or with
+    on=False back to hipMalloc / hipFree.  Grids free their memory only after
+    their stream has drained, so a block returned to the cache is idle."""
+    global _torch_alloc
+    L = lib()
+    if not on:
+        _check(L.nfvm_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        _torch_alloc = None
+        return
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:  # out of memory: the library reports NFVM_E_NOMEM
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cb = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _check(L.nfvm_set_allocator(cb[0], cb[1], None))
+    _torch_alloc = cb
+
+
 def nfvm_last_error() -> str:
     return lib().nfvm_last_error().decode()
 

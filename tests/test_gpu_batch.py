@@ -122,3 +122,35 @@ def test_batch_divergence_is_per_grid(nf):
         assert np.array_equal(f[k], f_ref[k]), k
     gb.close()
     gg.close()
+
+
+def test_torch_caching_allocator_routes_grid_memory(nf):
+    """With PyTorch's caching allocator installed (nfvm_set_allocator), a
+    grid's device memory comes from it (torch's allocated bytes grow by the
+    grid's footprint and fall back when the grid is freed), and the grid
+    steps to bitwise the same fields as one on hipMalloc memory."""
+    import torch
+    case = C.channel3d(64, 16, 16, Lx=1.28, Ly=0.32, Lz=0.32, n_levels=3, n_steps=2)
+    g = nf.Grid(case)
+    g.step(2)
+    ref = g.fields()
+    g.close()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    nf.use_torch_allocator(True)
+    try:
+        g = nf.Grid(case)
+        during = torch.cuda.memory_allocated()
+        g.step(2)
+        got = g.fields()
+        g.close()
+        torch.cuda.synchronize()
+        after = torch.cuda.memory_allocated()
+    finally:
+        nf.use_torch_allocator(False)
+    fp = nf.nfvm_grid_footprint(nf.Desc(case))
+    print(f"[alloc] torch bytes before={before} during={during} after={after} footprint={fp}",
+          flush=True)
+    assert during - before >= fp and after == before
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
