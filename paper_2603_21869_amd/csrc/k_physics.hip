@@ -678,6 +678,10 @@ template void launch_rhs_b<float, float>(const Geom&, const Phys&, const uint8_t
 // p += phi; u_d = u*_d - dt (phi_E - phi_W)/(2 h_d) with pressure ghosts;
 // corrected face fluxes F = L(u*) - dt c_f D(phi) give the cell divergence
 // (max reduced into S_DIV).  Arithmetic in the outer precision O.
+// Each workgroup walks the planes of a 64 x 4 column tile; per plane phi, u,
+// v (the x- and y-face velocities) and the kind bytes of its cells and their
+// rim go to one of two alternating LDS planes (one barrier per plane), and
+// the column's phi, w and kind below and above stay in registers.
 template <class F, class P, class O>
 __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                                 const DevPatch* __restrict__ pt,
@@ -686,67 +690,146 @@ __global__ __launch_bounds__(BS) void k_project(Geom g, Phys ph, const uint8_t* 
                                                 F* __restrict__ uo, F* __restrict__ vo,
                                                 F* __restrict__ wo, P* __restrict__ p,
                                                 RedBuf red, Tiles T) {
+  __shared__ O lphi[2][PL_N], lu[2][PL_N], lv[2][PL_N];
+  __shared__ uint8_t lt[2][PL_N];
   int tx = 0, ty = 0, tz = 0;
-  const bool tile = tile_of(T, tx, ty, tz);
-  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
-  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
+  const bool tile = tile_of(T, tx, ty, tz);  // (whole workgroup)
+  const int a = threadIdx.x, b = threadIdx.y;
+  const int i0 = tx * BX, j0 = ty * BY;
+  const int i = i0 + a, j = j0 + b;
+  const int kb = tz * T.cz, ke = tile ? min(g.nz, kb + T.cz) : kb;
+  const bool valid = i < g.nx && j < g.ny;
+  const bool own = i <= g.nx && j <= g.ny;
+  int ha, hb;
+  const bool rim = pl_rim(a, b, ha, hb) && i0 + ha <= g.nx && j0 + hb <= g.ny;
+  const int so = pl_slot(a, b), sh = pl_slot(ha, hb);
+  const bool d3 = g.dim == 3;
   double mdiv = 0.0;
   // b = 0: the increment is 0 whatever the solve started from; it is taken
   // as 0 here and cleared, so the next step does not start from it
   const bool zero_inc = red.out[S_BB] == 0.0;
-  if (tile && i < g.nx && j < g.ny)
-  for (int k = kb; k < ke; ++k) {
-    const int C0 = g.idx(i, j, k);
-    const uint8_t tp = type[C0];
-    const F* vel[3] = {u, v, w};
-    F* vout[3] = {uo, vo, wo};
-    if (!is_fluid(tp)) {
-      for (int d = 0; d < 3; ++d) vout[d][C0] = vel[d][C0];
-    } else {
-      const int st[3] = {1, g.sx, g.sxy};
-      const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
-      const O dt = (O)ph.dt;
-      const O fP = zero_inc ? (O)0 : phi[C0];
-      if (zero_inc) phi[C0] = (O)0;
-      O div = 0;
-      O unew[3] = {0, 0, 0};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (d >= g.dim) continue;
-        const O vp = (O)vel[d][C0];
-        O grad = 0;
-        O fl[2];
-#pragma unroll
-        for (int s = -1; s <= 1; s += 2) {
-          const int N = C0 + s * st[d];
-          const uint8_t tn = type[N];
-          // loaded whatever the neighbour's kind
-          const O vf = (O)vel[d][N], ff = zero_inc ? (O)0 : phi[N];
-          O vn, fN_ghost, fN_face, c;
-          if (is_fluid(tn)) {
-            vn = vf;
-            fN_ghost = ff;
-            fN_face = fN_ghost;
-            c = 1;
-          } else {
-            const DevPatch& pp = pt[tn & 0x7f];
-            vn = ghost<O>(pp, G_U + d, vp, ph.komega);
-            fN_ghost = ghost<O>(pp, G_P, fP, ph.komega);
-            c = pp.kind == K_OUTLET ? (O)2 : (O)0;
-            fN_face = 0;
-          }
-          grad += (O)s * fN_ghost;
-          const O dphi = s > 0 ? (fN_face - fP) : (fP - fN_face);
-          fl[s > 0] = (O)0.5 * (vp + vn) - dt * c * dphi * ih[d];
-        }
-        unew[d] = vp - dt * grad * (O)0.5 * ih[d];
-        div += (fl[1] - fl[0]) * ih[d];
-      }
-#pragma unroll
-      for (int d = 0; d < 3; ++d) vout[d][C0] = d < g.dim ? (F)unew[d] : vel[d][C0];
-      p[C0] = (P)((O)p[C0] + fP);
-      mdiv = fmax(mdiv, fabs((double)div));
+  auto ldphi = [&](int N) -> O { return zero_inc ? (O)0 : phi[N]; };
+  const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
+  const O dt = (O)ph.dt;
+  int C0 = g.idx(i, j, kb), H0 = g.idx(i0 + ha, j0 + hb, kb);
+  // this column at planes k - 1 (m) and k (c); the rim cell at plane k (h)
+  O fc = 0, uc = 0, vc = 0, wc = 0, fm = 0, wm = 0, fh = 0, uh = 0, vh = 0;
+  uint8_t tc = 0, tm = 0, th = 0;
+  if (tile && own) {
+    fc = ldphi(C0);
+    uc = (O)u[C0];
+    vc = (O)v[C0];
+    wc = (O)w[C0];
+    tc = type[C0];
+    if (d3) {
+      fm = ldphi(C0 - g.sxy);
+      wm = (O)w[C0 - g.sxy];
+      tm = type[C0 - g.sxy];
     }
+  }
+  if (tile && rim) {
+    fh = ldphi(H0);
+    uh = (O)u[H0];
+    vh = (O)v[H0];
+    th = type[H0];
+  }
+  for (int k = kb, buf = 0; k < ke; ++k, C0 += g.sxy, H0 += g.sxy, buf ^= 1) {
+    if (own) {
+      lphi[buf][so] = fc;
+      lu[buf][so] = uc;
+      lv[buf][so] = vc;
+      lt[buf][so] = tc;
+    }
+    if (rim) {
+      lphi[buf][sh] = fh;
+      lu[buf][sh] = uh;
+      lv[buf][sh] = vh;
+      lt[buf][sh] = th;
+    }
+    // the plane above (loaded whatever its kind) and the next rim cell
+    O fp = 0, up_ = 0, vp_ = 0, wp = 0;
+    uint8_t tq = 0;
+    if (d3 && own) {
+      const int N = C0 + g.sxy;
+      fp = ldphi(N);
+      up_ = (O)u[N];
+      vp_ = (O)v[N];
+      wp = (O)w[N];
+      tq = type[N];
+    }
+    if (rim && k + 1 < ke) {
+      fh = ldphi(H0 + g.sxy);
+      uh = (O)u[H0 + g.sxy];
+      vh = (O)v[H0 + g.sxy];
+      th = type[H0 + g.sxy];
+    }
+    __syncthreads();
+    if (valid) {
+      const F* vel[3] = {u, v, w};
+      F* vout[3] = {uo, vo, wo};
+      const O vc3[3] = {uc, vc, wc};
+      if (!is_fluid(tc)) {
+        for (int d = 0; d < 3; ++d) vout[d][C0] = (F)vc3[d];
+      } else {
+        const O fP = fc;
+        if (zero_inc) phi[C0] = (O)0;
+        O div = 0;
+        O unew[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (d >= g.dim) continue;
+          const O vp = vc3[d];
+          O grad = 0;
+          O fl[2];
+#pragma unroll
+          for (int s = -1; s <= 1; s += 2) {
+            O vf, ff;
+            uint8_t tn;
+            if (d == 2) {
+              vf = s < 0 ? wm : wp;
+              ff = s < 0 ? fm : fp;
+              tn = s < 0 ? tm : tq;
+            } else {
+              const int sl = d == 0 ? pl_slot(a + s, b) : pl_slot(a, b + s);
+              vf = d == 0 ? lu[buf][sl] : lv[buf][sl];
+              ff = lphi[buf][sl];
+              tn = lt[buf][sl];
+            }
+            O vn, fN_ghost, fN_face, c;
+            if (is_fluid(tn)) {
+              vn = vf;
+              fN_ghost = ff;
+              fN_face = fN_ghost;
+              c = 1;
+            } else {
+              const DevPatch& pp = pt[tn & 0x7f];
+              vn = ghost<O>(pp, G_U + d, vp, ph.komega);
+              fN_ghost = ghost<O>(pp, G_P, fP, ph.komega);
+              c = pp.kind == K_OUTLET ? (O)2 : (O)0;
+              fN_face = 0;
+            }
+            grad += (O)s * fN_ghost;
+            const O dphi = s > 0 ? (fN_face - fP) : (fP - fN_face);
+            fl[s > 0] = (O)0.5 * (vp + vn) - dt * c * dphi * ih[d];
+          }
+          unew[d] = vp - dt * grad * (O)0.5 * ih[d];
+          div += (fl[1] - fl[0]) * ih[d];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vout[d][C0] = d < g.dim ? (F)unew[d] : vel[d][C0];
+        p[C0] = (P)((O)p[C0] + fP);
+        mdiv = fmax(mdiv, fabs((double)div));
+      }
+    }
+    // shift: the plane above becomes the centre
+    fm = fc;
+    wm = wc;
+    tm = tc;
+    fc = fp;
+    uc = up_;
+    vc = vp_;
+    wc = wp;
+    tc = tq;
   }
   double vv[1] = {mdiv};
   block_partial<1, R_MAX, BS>(vv, red);
