@@ -614,43 +614,111 @@ INST_RK2(float, float)
 INST_RK2(double, float)
 
 // ---- Poisson right-hand side: b = -(1/dt) sum_d D_d L_d BC_d(u*_d) ------------
+// Each workgroup walks the planes of a 64 x 4 column tile; per plane u, v and
+// the kind bytes of its cells and their rim go to one of two alternating LDS
+// planes (one barrier per plane), and the column's w and kind below and
+// above stay in registers.
 template <class F, class O>
 __global__ __launch_bounds__(BS) void k_rhs_b(Geom g, Phys ph, const uint8_t* __restrict__ type,
                                               const DevPatch* __restrict__ pt,
                                               const F* __restrict__ u, const F* __restrict__ v,
                                               const F* __restrict__ w, O* __restrict__ b,
                                               RedBuf red, Tiles T) {
+  __shared__ O lu[2][PL_N], lv[2][PL_N];
+  __shared__ uint8_t lt[2][PL_N];
   int tx = 0, ty = 0, tz = 0;
-  const bool tile = tile_of(T, tx, ty, tz);
-  const int i = tx * BX + threadIdx.x, j = ty * BY + threadIdx.y;
-  const int kb = tz * T.cz, ke = min(g.nz, kb + T.cz);
+  const bool tile = tile_of(T, tx, ty, tz);  // (whole workgroup)
+  const int a = threadIdx.x, bq = threadIdx.y;
+  const int i0 = tx * BX, j0 = ty * BY;
+  const int i = i0 + a, j = j0 + bq;
+  const int kb = tz * T.cz, ke = tile ? min(g.nz, kb + T.cz) : kb;
+  const bool valid = i < g.nx && j < g.ny;
+  const bool own = i <= g.nx && j <= g.ny;
+  int ha, hb;
+  const bool rim = pl_rim(a, bq, ha, hb) && i0 + ha <= g.nx && j0 + hb <= g.ny;
+  const int so = pl_slot(a, bq), sh = pl_slot(ha, hb);
+  const bool d3 = g.dim == 3;
+  const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
   double acc = 0.0;
-  if (tile && i < g.nx && j < g.ny)
-  for (int k = kb; k < ke; ++k) {
-    const int C0 = g.idx(i, j, k);
-    const uint8_t tp = type[C0];
-    O bv = 0;
-    if (is_fluid(tp)) {
-      const F* vel[3] = {u, v, w};
-      const int st[3] = {1, g.sx, g.sxy};
-      const O ih[3] = {(O)(1.0 / g.hx), (O)(1.0 / g.hy), (O)(1.0 / g.hz)};
-      O div = 0;
-      for (int d = 0; d < g.dim; ++d) {
-        const O vp = (O)vel[d][C0];
-        O fl[2];
-        for (int s = -1; s <= 1; s += 2) {
-          const int N = C0 + s * st[d];
-          const uint8_t tn = type[N];
-          const O vf = (O)vel[d][N];  // loaded whatever the neighbour's kind
-          const O vn = is_fluid(tn) ? vf : ghost<O>(pt[tn & 0x7f], G_U + d, vp, ph.komega);
-          fl[s > 0] = (O)0.5 * (vp + vn);
-        }
-        div += (fl[1] - fl[0]) * ih[d];
-      }
-      bv = -div / (O)ph.dt;
+  int C0 = g.idx(i, j, kb), H0 = g.idx(i0 + ha, j0 + hb, kb);
+  O uc = 0, vc = 0, wc = 0, wm = 0, uh = 0, vh = 0;
+  uint8_t tc = 0, tm = 0, th = 0;
+  if (tile && own) {
+    uc = (O)u[C0];
+    vc = (O)v[C0];
+    wc = (O)w[C0];
+    tc = type[C0];
+    if (d3) {
+      wm = (O)w[C0 - g.sxy];
+      tm = type[C0 - g.sxy];
     }
-    b[C0] = bv;
-    acc += (double)bv * (double)bv;
+  }
+  if (tile && rim) {
+    uh = (O)u[H0];
+    vh = (O)v[H0];
+    th = type[H0];
+  }
+  for (int k = kb, buf = 0; k < ke; ++k, C0 += g.sxy, H0 += g.sxy, buf ^= 1) {
+    if (own) {
+      lu[buf][so] = uc;
+      lv[buf][so] = vc;
+      lt[buf][so] = tc;
+    }
+    if (rim) {
+      lu[buf][sh] = uh;
+      lv[buf][sh] = vh;
+      lt[buf][sh] = th;
+    }
+    O up_ = 0, vp_ = 0, wp = 0;
+    uint8_t tq = 0;
+    if (d3 && own) {
+      const int N = C0 + g.sxy;
+      up_ = (O)u[N];
+      vp_ = (O)v[N];
+      wp = (O)w[N];
+      tq = type[N];
+    }
+    if (rim && k + 1 < ke) {
+      uh = (O)u[H0 + g.sxy];
+      vh = (O)v[H0 + g.sxy];
+      th = type[H0 + g.sxy];
+    }
+    __syncthreads();
+    if (valid) {
+      O bv = 0;
+      if (is_fluid(tc)) {
+        const O vc3[3] = {uc, vc, wc};
+        O div = 0;
+        for (int d = 0; d < g.dim; ++d) {
+          const O vp = vc3[d];
+          O fl[2];
+          for (int s = -1; s <= 1; s += 2) {
+            O vf;
+            uint8_t tn;
+            if (d == 2) {
+              vf = s < 0 ? wm : wp;
+              tn = s < 0 ? tm : tq;
+            } else {
+              const int sl = d == 0 ? pl_slot(a + s, bq) : pl_slot(a, bq + s);
+              vf = d == 0 ? lu[buf][sl] : lv[buf][sl];
+              tn = lt[buf][sl];
+            }
+            const O vn = is_fluid(tn) ? vf : ghost<O>(pt[tn & 0x7f], G_U + d, vp, ph.komega);
+            fl[s > 0] = (O)0.5 * (vp + vn);
+          }
+          div += (fl[1] - fl[0]) * ih[d];
+        }
+        bv = -div / (O)ph.dt;
+      }
+      b[C0] = bv;
+      acc += (double)bv * (double)bv;
+    }
+    wm = wc;
+    tm = tc;
+    uc = up_;
+    vc = vp_;
+    wc = wp;
+    tc = tq;
   }
   double vv[1] = {acc};
   block_partial<1, R_SUM, BS>(vv, red);
