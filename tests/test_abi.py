@@ -87,3 +87,29 @@ def test_reduction_scratch_covers_every_tiling_of_odd_shapes():
         assert 0 < need <= cap, (nx, ny, nz, need, cap)
         assert need % 8 == 0 and cap % 8 == 0
     assert seen_round  # some 2D shape needs more workgroups than it has columns
+
+
+def test_null_arguments_are_rejected_without_gpu():
+    """The reverse-mode, probe and tuning entry points reject a null grid or
+    descriptor with NFVM_E_INVAL and a message, before any device work."""
+    from paper_2603_21869_amd import nfvm
+    if not os.path.exists(nfvm.LIB_PATH):
+        pytest.skip("libnfvm.so not built")
+    L = nfvm.lib()
+    f = nfvm.nfvm_fields()
+    st = nfvm.nfvm_step_stats()
+    calls = [
+        lambda: L.nfvm_explicit_adjoint_device(None, ctypes.byref(f), ctypes.byref(f),
+                                               ctypes.byref(f)),
+        lambda: L.nfvm_destroy_adjoint_device(None, ctypes.byref(f), 0.1, None, None,
+                                              ctypes.byref(f)),
+        lambda: L.nfvm_step_adjoint_device(None, ctypes.byref(f), ctypes.byref(f),
+                                           ctypes.byref(f), 1e-10, 10, -1, ctypes.byref(st)),
+        lambda: L.nfvm_pressure_adjoint_device(None, None, None, None, None, None, None, None,
+                                               1e-10, 10, -1, None),
+        lambda: L.nfvm_line_probe(None, None, 0, None),
+        lambda: L.nfvm_tune(None),
+    ]
+    for call in calls:
+        assert call() == nfvm.NFVM_E_INVAL
+        assert nfvm.nfvm_last_error()

@@ -236,3 +236,25 @@ def test_step_adjoint_matches_oracle(nf, name, case):
     for nm in names:
         scale = max(np.abs(fwd[nm]).max(), 1e-300)
         assert np.abs(after[nm] - fwd[nm]).max() <= 1e-8 * scale, nm
+
+
+def test_step_adjoint_rejects_the_heun_stage(nf):
+    """The whole-step reverse mode covers the forward-Euler explicit stage:
+    with NFVM_OPT_RK_ORDER = 2 it returns NFVM_E_INVAL and leaves the
+    output arrays untouched."""
+    import torch
+    case = C.channel3d(32, 8, 8, Lx=0.64, Ly=0.16, Lz=0.16, n_levels=2,
+                       precision=C.PREC_FP64)
+    g = nf.Grid(case)
+    nf.nfvm_set_option(g.h, nf.NFVM_OPT_RK_ORDER, 2.0)
+    names = ("u", "v", "w", "p", "T", "k", "omega")
+    st = {nm: torch.tensor(np.ascontiguousarray(case.fields[nm]), dtype=torch.float64,
+                           device="cuda") for nm in names}
+    xb = {nm: torch.full_like(st["u"], 7.0) for nm in names}
+    with pytest.raises(nf.NfvmError) as e:
+        nf.nfvm_step_adjoint_device(g.h, {k: v.data_ptr() for k, v in st.items()},
+                                    {k: v.data_ptr() for k, v in st.items()},
+                                    {k: v.data_ptr() for k, v in xb.items()})
+    assert e.value.status == nf.NFVM_E_INVAL
+    g.close()
+    assert all(bool((v == 7.0).all()) for v in xb.values())
