@@ -335,14 +335,12 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(workload: str, tol: float, budget_s: float = 20.0):
-    """The serial FP64 oracle, pinned to one host core, on a bounded sample of
-    the workload.  The large room is sampled as the same room (same blocks in
-    metres, vents, physics and tolerance) on a 256 x 128 x 64 grid, one step;
-    the other workloads as up to four steps of the workload itself."""
+def _cpu_sample(workload: str, tol: float):
+    """The bounded sample of a workload that the oracle is timed on: the
+    large room as the same room (same blocks in metres, vents, physics,
+    tolerance and cycle shape) on a 256 x 128 x 64 grid, the other workloads
+    as themselves."""
     from paper_2603_21869_amd import cases as C
-    from oracle import oracle as O
-    O.build()
     if workload == "bigroom":
         case = C.room3d(256, 128, 64, n_levels=7, precision=C.PREC_FP64, tol=tol,
                         n_steps=1).copy(**ROOM_CYCLE)
@@ -351,9 +349,82 @@ def cpu_baseline(workload: str, tol: float, budget_s: float = 20.0):
     else:
         case = make_case(workload, C.PREC_FP64, tol)
         what = "time steps of the same workload from its initial state"
+    return case, what
+
+
+def _pin(core):
+    try:
+        old = os.sched_getaffinity(0)
+        os.sched_setaffinity(0, {core})
+        return old
+    except (AttributeError, OSError):
+        return None
+
+
+def oracle_worker(workload: str, tol: float, core: int) -> None:
+    """One copy of the all-core leg: build the sample, say so, wait for the
+    common start, time one oracle step on its own core, print the seconds."""
+    from oracle import oracle as O
+    _pin(core)
+    case, _ = _cpu_sample(workload, tol)
+    O.lib()
+    print("ready", flush=True)
+    sys.stdin.readline()
+    t0 = time.perf_counter()
+    O.step(case, 1)
+    print(json.dumps({"seconds": time.perf_counter() - t0}), flush=True)
+
+
+def cpu_all_cores(workload: str, tol: float, ncells: int, max_procs: int = 16):
+    """The unchanged serial oracle on every host core at once: one process
+    per core (at most 16), each stepping its own copy of the sample, started
+    together; throughput = copies x cells / the slowest copy's step time."""
+    import subprocess
+    try:
+        cores = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = list(range(os.cpu_count() or 1))
+    cores = cores[:max_procs]
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker",
+                               str(c), "--workload", workload, "--tol", repr(tol)],
+                              stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True)
+             for c in cores]
+    try:
+        for pr in procs:
+            if pr.stdout.readline().strip() != "ready":
+                raise RuntimeError("oracle worker failed to start")
+        for pr in procs:
+            pr.stdin.write("go\n")
+            pr.stdin.flush()
+        secs = []
+        for pr in procs:
+            secs.append(json.loads(pr.stdout.readline())["seconds"])
+            print(f"[bench] oracle copy {len(secs)}/{len(procs)}: {secs[-1]:.2f} s",
+                  file=sys.stderr, flush=True)
+    finally:
+        for pr in procs:
+            pr.stdin.close()
+            pr.wait(timeout=600)
+    slowest = max(secs)
+    return dict(value=round(len(cores) * ncells / slowest / 1e6, 4), unit="Mcell-steps/s",
+                cores=len(cores), kind="oracle",
+                sample=f"{len(cores)} copies of the serial FP64 oracle, one per host core, "
+                       f"each stepping the same sample once, started together; slowest "
+                       f"{slowest:.2f} s, fastest {min(secs):.2f} s")
+
+
+def cpu_baseline(workload: str, tol: float, budget_s: float = 20.0, all_cores: bool = True):
+    """The serial FP64 oracle, pinned to one host core, on a bounded sample of
+    the workload (one step of the large room's sample; up to four steps of
+    the other workloads), and beside it the same oracle on every host core
+    at once (one copy per core)."""
+    from oracle import oracle as O
+    O.build()
+    case, what = _cpu_sample(workload, tol)
+    old_aff = None
     try:
         old_aff = os.sched_getaffinity(0)
-        os.sched_setaffinity(0, {min(old_aff)})
+        _pin(min(old_aff))
     except (AttributeError, OSError):
         old_aff = None
     try:
@@ -371,10 +442,13 @@ def cpu_baseline(workload: str, tol: float, budget_s: float = 20.0):
     finally:
         if old_aff is not None:
             os.sched_setaffinity(0, old_aff)
-    return dict(value=round(case.ncells / per / 1e6, 4), unit="Mcell-steps/s", cores=1,
-                kind="oracle",
-                sample=f"{n} {what}; serial FP64 oracle pinned to one core ({cpu_model()}), "
-                       f"{per:.2f} s/step, {st[0]['cycles']} V-cycles in its first step")
+    out = dict(value=round(case.ncells / per / 1e6, 4), unit="Mcell-steps/s", cores=1,
+               kind="oracle",
+               sample=f"{n} {what}; serial FP64 oracle pinned to one core ({cpu_model()}), "
+                      f"{per:.2f} s/step, {st[0]['cycles']} V-cycles in its first step")
+    if all_cores:
+        out["all_cores"] = cpu_all_cores(workload, tol, case.ncells)
+    return out
 
 
 def main():
@@ -386,6 +460,8 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-all-cores", action="store_true",
+                    help="time the oracle on one core only (not also on every core)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other precisions and tolerances of the same workload")
     ap.add_argument("--all-variants", action="store_true",
@@ -403,7 +479,11 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (for "
                          "scaling hardware byte counters) and exit")
+    ap.add_argument("--oracle-worker", type=int, default=-1, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_worker >= 0:
+        oracle_worker(args.workload, args.tol, args.oracle_worker)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -591,7 +671,8 @@ def main():
         out["paper_table"] = run_paper_table(stream, prec, args.tol)
     if not args.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.tol)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.tol,
+                                           all_cores=not args.no_all_cores)
     print(json.dumps(out))
 
 

@@ -44,3 +44,21 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in json.loads(r.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_bench_all_core_oracle_leg_runs_one_copy_per_core():
+    """The all-core CPU leg starts one copy of the serial oracle per core
+    (here two), each on the same sample, and reports their aggregate rate
+    against the slowest copy; the workers never touch the GPU."""
+    import os
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    from oracle import oracle as O
+    O.build()
+    case, _ = bench._cpu_sample("channel2d", 1e-6)
+    r = bench.cpu_all_cores("channel2d", 1e-6, case.ncells, max_procs=2)
+    ncores = min(2, len(os.sched_getaffinity(0)))
+    assert r["cores"] == ncores and r["kind"] == "oracle" and r["unit"] == "Mcell-steps/s"
+    assert r["value"] > 0 and f"{ncores} copies" in r["sample"]
