@@ -199,6 +199,96 @@ def run_gpu(case, steps: int, warmup: int, stream: int, warm_start: bool = False
     return sec, stats, s
 
 
+# Algorithmic bytes per cell of the reverse-mode calls (FP64 throughout;
+# each operand read once and each result written once): the state packed
+# into the padded layout (read + written), the weights pass (type byte,
+# state, output adjoints in; per-cell weights out) and the gather pass
+# (type byte, state, output adjoints and weights in; input adjoints out).
+#   explicit stage: 7 x 16 + (1 + 56 + 48 + 112) + (1 + 56 + 48 + 112 + 56)
+#   destruction:    5 x 16 + (1 + 40 + 16 + 120) + (1 + 40 + 16 + 120 + 40)
+REVERSE_BYTES_PER_CELL = {"explicit_adjoint": 602, "destroy_adjoint": 474}
+
+
+def run_reverse(g, case, tol: float, repeats: int = 3):
+    """The reverse modes at the grid's current state, adjoints of the
+    outputs seeded N(0, 1): the explicit stage's and the destruction step's
+    (wall time per call, each call waits for its stream; algorithmic bytes
+    per second against the HBM peak) and one whole step's (forward step
+    with its solve, then the stages' reverse modes and the adjoint solve,
+    both solves to `tol`)."""
+    import numpy as np
+    import torch
+    from paper_2603_21869_amd import nfvm
+    names = ("u", "v", "w", "p", "T", "k", "omega")
+    f = g.fields()
+    st = {n: torch.from_numpy(np.ascontiguousarray(f[n], dtype=np.float64)).cuda() for n in names}
+    del f
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    bars = {n: torch.randn(st[n].shape, dtype=torch.float64, device="cuda", generator=gen)
+            for n in names}
+    outs = {n: torch.empty_like(st[n]) for n in names}
+    ptr = lambda d: {n: t.data_ptr() for n, t in d.items()}
+
+    def timed(fn):
+        fn()  # allocates the call's scratch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / repeats
+
+    out = {}
+    t_ex = timed(lambda: nfvm.nfvm_explicit_adjoint_device(g.h, ptr(st), ptr(bars), ptr(outs)))
+    half = 0.5 * case.dt
+    five = {n: outs[n].data_ptr() for n in ("u", "v", "w", "k", "omega")}
+    t_des = timed(lambda: nfvm.nfvm_destroy_adjoint_device(
+        g.h, ptr(st), half, bars["k"].data_ptr(), bars["omega"].data_ptr(), five))
+    for name, t in (("explicit_adjoint", t_ex), ("destroy_adjoint", t_des)):
+        b = REVERSE_BYTES_PER_CELL[name] * case.ncells
+        out[name] = dict(ms=round(t * 1e3, 3), bytes_per_cell=REVERSE_BYTES_PER_CELL[name],
+                         GBs=round(b / t / 1e9, 1), frac=round(b / t / 1e9 / PEAK_HBM_GBS, 4))
+    stats = []
+
+    def step_adj():
+        s, _ = nfvm.nfvm_step_adjoint_device(g.h, ptr(st), ptr(bars), ptr(outs), tol=tol,
+                                             max_cycles=200)
+        stats.append(s)
+
+    t_step = timed(step_adj)
+    out["step_adjoint"] = dict(ms=round(t_step * 1e3, 2),
+                               mcell_steps_s=round(case.ncells / t_step / 1e6, 2), tol=tol,
+                               forward_cycles=stats[-1][0]["cycles"],
+                               adjoint_cycles=stats[-1][1]["cycles"])
+    del st, bars, outs
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_probes(g, case, points: int = 256, repeats: int = 5):
+    """Line probes (Sec. 3.1) along three lines through the middle of the
+    box, one per axis, `points` each: host wall time per call (points up,
+    the device interpolation, results back)."""
+    from paper_2603_21869_amd import nfvm
+    import numpy as np
+    L = [case.n[d] * case.h[d] for d in range(3)]
+    mid = [0.5 * x for x in L]
+    lines = []
+    for d in range(case.dim):
+        a, b = list(mid), list(mid)
+        a[d], b[d] = 0.0, L[d]
+        lines.append(nfvm.line(a, b, points))
+    pts = np.concatenate(lines)
+    g.probe(pts)
+    t0 = time.perf_counter()
+    for _ in range(repeats):
+        v = g.probe(pts)
+    t = (time.perf_counter() - t0) / repeats
+    return dict(probe_ms_host=round(t * 1e3, 3), probe_points=int(len(pts)),
+                probe_nan_points=int(np.isnan(v).any(axis=1).sum()))
+
+
 def run_pcie(g, case, steps: int):
     """Throughput with the fields handed over in host memory: upload, the
     steps, download (on a grid whose tile choices exist already)."""
@@ -476,6 +566,10 @@ def main():
                     help="skip the paper's open-channel timing workload (three lengths)")
     ap.add_argument("--only-steps", action="store_true",
                     help="only the timed steps of the workload (for profiler runs)")
+    ap.add_argument("--no-reverse", action="store_true",
+                    help="skip the reverse-mode timings")
+    ap.add_argument("--only-reverse", action="store_true",
+                    help="only the reverse-mode calls after the warm-up (for profiler runs)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (for "
                          "scaling hardware byte counters) and exit")
@@ -512,6 +606,11 @@ def main():
     g = nfvm.Grid(case, stream=stream)
     if args.warmup:
         g.step(args.warmup, allow=(nfvm.NFVM_OK, nfvm.NFVM_E_NOTCONV))
+    if args.only_reverse:
+        rev = run_reverse(g, case, args.tol)
+        g.close()
+        print(json.dumps({"workload": args.workload, "reverse_mode": rev}))
+        return
     sec, stats, status = timed_steps(g, args.steps)
     ms_per_step = sec / args.steps * 1e3
     value = case.ncells * args.steps / sec / 1e6
@@ -574,6 +673,11 @@ def main():
         post = dict(lambda2_ms_host=round(lsec * 1e3, 3), calls=args.lambda2,
                     vortex_cells=int((l2 < 0).sum()))
         del l2
+        post.update(run_probes(g, case))
+    reverse = None
+    if not args.no_reverse:
+        print("[bench] reverse mode", file=sys.stderr, flush=True)
+        reverse = run_reverse(g, case, args.tol)
     g.close()
     copy_GBs = round(copy_bandwidth(), 1)
 
@@ -656,6 +760,7 @@ def main():
         "event_timed_ms_per_step": round(psec / args.steps * 1e3, 4),
         "pcie_inclusive_mcell_steps_s": round(pcie, 2),
         "postprocess": post,
+        "reverse_mode": reverse,
         "tuning_entries": len(nfvm.nfvm_tuning_table()),
         "paper_context": "paper: 19-46x GPU over 32-core CPU (RTX PRO 5000 Blackwell vs "
                          "Threadripper 9970X); 23.8-38.1 Mcell-steps/s on its open channel",

@@ -125,7 +125,9 @@ __device__ __forceinline__ void field_coef(const Phys& ph, double (&g0)[NF], dou
 __device__ __forceinline__ void adj_gradient(const Geom& g, const AdjCell& P,
                                              const AdjCell (&N)[3][2], double (&G)[3][3]) {
   const double ih2[3] = {0.5 / g.hx, 0.5 / g.hy, 0.5 / g.hz};
+  #pragma unroll
   for (int a = 0; a < 3; ++a)
+    #pragma unroll
     for (int b = 0; b < 3; ++b)
       G[a][b] = (a < g.dim && b < g.dim) ? (N[b][1].v[a] - N[b][0].v[a]) * ih2[b] : 0.0;
 }
@@ -135,7 +137,9 @@ __device__ __forceinline__ void adj_neighbours(const Geom& g, const Phys& ph, co
                                                const uint8_t* type, const DevPatch* pt, int P,
                                                const AdjCell& c, AdjCell (&N)[3][2]) {
   const int st[3] = {1, g.sx, g.sxy};
+  #pragma unroll
   for (int d = 0; d < 3; ++d)
+    #pragma unroll
     for (int s = 0; s < 2; ++s) {
       if (d >= g.dim) {
         N[d][s] = c;
@@ -182,12 +186,16 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_weights(
   field_coef(ph, g0, is);
   const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
   double rk = 0.0, rw = 0.0;
-  for (int d = 0; d < g.dim; ++d)
+  #pragma unroll
+  for (int d = 0; d < 3; ++d)
+    #pragma unroll
     for (int s = 0; s < 2; ++s) {
+      if (d >= g.dim) continue;
       const AdjCell& n = N[d][s];
       const double sg = s ? 1.0 : -1.0;
       const double Uf = 0.5 * (c.v[d] + n.v[d]);
       const double nutf = 0.5 * (c.nu + n.nu);
+      #pragma unroll
       for (int f = 4; f < 6; ++f) {
         const double lower = s ? c.v[f] : n.v[f], upper = s ? n.v[f] : c.v[f];
         const double up = Uf >= 0.0 ? lower : upper;
@@ -252,11 +260,15 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
     const int st[3] = {1, g.sx, g.sxy};
     const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
     double Wc[NF];
+    #pragma unroll
     for (int f = 0; f < NF; ++f) Wc[f] = W[f * T + P];
     const int komega = ph.komega;
     // faces
-    for (int d = 0; d < g.dim; ++d)
+    #pragma unroll
+    for (int d = 0; d < 3; ++d)
+      #pragma unroll
       for (int s = 0; s < 2; ++s) {
+        if (d >= g.dim) continue;
         const AdjCell& n = N[d][s];
         const double sg = s ? 1.0 : -1.0;
         const bool nf = is_fluid(n.t);
@@ -265,12 +277,14 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
         double gs[NF], gp = 0.0, gn = 0.0;
         double wf[NF];
         if (nf) {
+          #pragma unroll
           for (int f = 0; f < NF; ++f) {
             gs[f] = 0.0;
             wf[f] = sg * ih[d] * (Wc[f] - W[f * T + Q]);
           }
         } else {
           const DevPatch& pp = pt[n.t & 0x7f];
+          #pragma unroll
           for (int f = 0; f < NF; ++f) {
             gs[f] = slope(pp, ghost_code(f), komega);
             wf[f] = sg * ih[d] * Wc[f];
@@ -284,6 +298,7 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
         // from it (lower cell for Uf >= 0)
         const bool own_up = (Uf >= 0.0) == (s == 1);
         double dUf = 0.0, dnut = 0.0;
+        #pragma unroll
         for (int f = 0; f < NF; ++f) {
           const double lower = s ? c.v[f] : n.v[f], upper = s ? n.v[f] : c.v[f];
           const double up = Uf >= 0.0 ? lower : upper;
@@ -302,13 +317,17 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
       }
     // buoyancy -beta_T theta g_a
     if (ph.buoyancy)
-      for (int a = 0; a < g.dim; ++a) xb[3] += Wc[a] * -ph.beta_T * ph.g[a];
+      #pragma unroll
+      for (int a = 0; a < 3; ++a)
+        if (a < g.dim) xb[3] += Wc[a] * -ph.beta_T * ph.g[a];
     if (komega) {
       // production nu_t S^2 and alpha S^2 at this cell
       double G[3][3];
       adj_gradient(g, c, N, G);
       double S2 = 0.0;
+      #pragma unroll
       for (int a = 0; a < 3; ++a)
+        #pragma unroll
         for (int b = 0; b < 3; ++b) {
           const double sab = 0.5 * (G[a][b] + G[b][a]);
           S2 += sab * sab;
@@ -323,18 +342,25 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
       // face (its own 4 Lambda S_ab), or this cell's own through a ghost
       const double ih2[3] = {0.5 / g.hx, 0.5 / g.hy, 0.5 / g.hz};
       const int sidx[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-      for (int b = 0; b < g.dim; ++b)
+      #pragma unroll
+      for (int b = 0; b < 3; ++b)
+        #pragma unroll
         for (int s = 0; s < 2; ++s) {
+          if (b >= g.dim) continue;
           const double sg = s ? 1.0 : -1.0;
           const AdjCell& n = N[b][s];
           if (is_fluid(n.t)) {
             const int Q = P + (s ? 1 : -1) * st[b];
             // this cell is the neighbour of Q on Q's side -sg along b
-            for (int a = 0; a < g.dim; ++a) xb[a] += L4S[sidx[a][b] * T + Q] * -sg * ih2[b];
+            #pragma unroll
+            for (int a = 0; a < 3; ++a)
+              if (a < g.dim) xb[a] += L4S[sidx[a][b] * T + Q] * -sg * ih2[b];
           } else {
             const DevPatch& pp = pt[n.t & 0x7f];
-            for (int a = 0; a < g.dim; ++a)
-              xb[a] += L4S[sidx[a][b] * T + P] * sg * ih2[b] * slope(pp, G_U + a, komega);
+            #pragma unroll
+            for (int a = 0; a < 3; ++a)
+              if (a < g.dim)
+                xb[a] += L4S[sidx[a][b] * T + P] * sg * ih2[b] * slope(pp, G_U + a, komega);
           }
         }
       // nu_t is the closure of this cell's k and omega

@@ -238,6 +238,51 @@ def test_step_adjoint_matches_oracle(nf, name, case):
         assert np.abs(after[nm] - fwd[nm]).max() <= 1e-8 * scale, nm
 
 
+@pytest.mark.parametrize("name,case", _step_cases()[1:3], ids=[c[0] for c in _step_cases()[1:3]])
+def test_step_adjoint_on_a_mixed_grid_matches_oracle(nf, name, case):
+    """nfvm_step_adjoint_device on a mixed-precision grid (k, omega and T
+    stored in FP32, velocity and pressure in FP64): with the state's k,
+    omega and T given at FP32 values, so that loading it rounds nothing, the
+    input adjoints match the FP64 oracle's reverse mode to 1e-5 of their
+    largest value (the forward step rounds its intermediate k, omega and T
+    to FP32, which moves the later stages' linearisation points by about
+    1e-7), and the grid holds the forward step to 1e-6."""
+    import torch
+    from oracle import autodiff as AD
+    from oracle import oracle as O
+    c = case.copy(precision=C.PREC_FP64, tol=1e-12, max_cycles=200)
+    f = _ex_state(c, 6)
+    for nm in ("k", "omega"):
+        f[nm] = f[nm].astype(np.float32).astype(np.float64)
+    f["T"] = c.T_ref + (f["T"] - c.T_ref).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(17)
+    names = ("u", "v", "w", "p", "T", "k", "omega")
+    bars = {nm: rng.standard_normal(f["u"].shape) for nm in names}
+    ref = AD.step_vjp(c, f, bars, tol=1e-12)
+    dev = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    st = {nm: dev(f[nm]) for nm in names}
+    bd = {nm: dev(bars[nm]) for nm in names}
+    xb = {nm: torch.full_like(st["u"], float("nan")) for nm in names}
+    g = nf.Grid(c.copy(precision=C.PREC_MIXED))
+    stats, _ = nf.nfvm_step_adjoint_device(g.h, {k: v.data_ptr() for k, v in st.items()},
+                                           {k: v.data_ptr() for k, v in bd.items()},
+                                           {k: v.data_ptr() for k, v in xb.items()}, tol=1e-12)
+    torch.cuda.synchronize()
+    after = g.fields()
+    g.close()
+    for nm in names:
+        got = xb[nm].cpu().numpy()
+        scale = max(np.abs(ref[nm]).max(), 1e-300)
+        err = np.abs(got - ref[nm]).max() / scale
+        print(f"[step-adjoint mixed] {name} {nm} max|ref|={scale:.3e} err={err:.2e}", flush=True)
+        assert np.isfinite(got).all() and err <= 1e-5, (name, nm, err)
+    fwd, _, s = O.step(c, 1, fields=f)
+    assert s == 0
+    for nm in names:
+        scale = max(np.abs(fwd[nm]).max(), 1e-300)
+        assert np.abs(after[nm] - fwd[nm]).max() <= 1e-6 * scale, nm
+
+
 def test_step_adjoint_rejects_the_heun_stage(nf):
     """The whole-step reverse mode covers the forward-Euler explicit stage:
     with NFVM_OPT_RK_ORDER = 2 it returns NFVM_E_INVAL and leaves the
