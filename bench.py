@@ -201,12 +201,16 @@ def run_gpu(case, steps: int, warmup: int, stream: int, warm_start: bool = False
 
 # Algorithmic bytes per cell of the reverse-mode calls (FP64 throughout;
 # each operand read once and each result written once): the state packed
-# into the padded layout (read + written), the weights pass (type byte,
-# state, output adjoints in; per-cell weights out) and the gather pass
-# (type byte, state, output adjoints and weights in; input adjoints out).
-#   explicit stage: 7 x 16 + (1 + 56 + 48 + 112) + (1 + 56 + 48 + 112 + 56)
+# into the padded layout (read + written), for the explicit stage nu_t
+# formed once (type byte, k, omega in; nu_t out), the weights pass (type
+# byte, the state it reads, output adjoints in; per-cell weights out) and
+# the gather pass (type byte, state, output adjoints and weights in; input
+# adjoints out).
+#   explicit stage: 6 x 16 + 25 + (1 + 48 + 48 + 112) + (1 + 56 + 48 + 112 + 56)
+#                   (u v w T k omega packed; weights read u v w k omega nu_t,
+#                   the gather also T)
 #   destruction:    5 x 16 + (1 + 40 + 16 + 120) + (1 + 40 + 16 + 120 + 40)
-REVERSE_BYTES_PER_CELL = {"explicit_adjoint": 602, "destroy_adjoint": 474}
+REVERSE_BYTES_PER_CELL = {"explicit_adjoint": 603, "destroy_adjoint": 474}
 
 
 def run_reverse(g, case, tol: float, repeats: int = 3):

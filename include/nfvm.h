@@ -265,7 +265,7 @@ nfvm_status nfvm_lambda2(nfvm_grid_t grid, double* lambda2);
  * clamps as the forward step takes them there).  All arrays device FP64
  * [nz][ny][nx], T absolute; outputs may not alias inputs.  Arithmetic in
  * FP64 whatever the grid's precision; the grid's fields are not touched.
- * The first call of this or nfvm_destroy_adjoint_device allocates 21 FP64
+ * The first call of this or nfvm_destroy_adjoint_device allocates 22 FP64
  * values per padded cell of scratch, kept until the grid is freed.  Runs on
  * the grid's stream and waits for it.  Errors: NFVM_E_INVAL for a null
  * pointer, NFVM_E_NOMEM. */

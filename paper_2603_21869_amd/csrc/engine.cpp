@@ -787,16 +787,17 @@ class GridT : public GridBase {
     for (double* q : xb)
       if (!q) throw Error{NFVM_E_INVAL, "all seven input adjoint arrays are required"};
     const size_t T = (size_t)g.total;
-    // (allocated on first use: 21 padded FP64 arrays)
-    if (!adj_scratch) adj_scratch = alloc<double>(21 * T, "adjoint scratch");
+    // (allocated on first use: 22 padded FP64 arrays)
+    if (!adj_scratch) adj_scratch = alloc<double>(22 * T, "adjoint scratch");
     double* S = adj_scratch;
+    // (the Jacobian does not depend on p, which is therefore not packed)
     const double* sd[7];
     for (int f = 0; f < 7; ++f) {
-      launch_pack<double>(g, sp[f], S + f * T, f == 4 ? ph.T_ref : 0.0, stream);
-      sd[f] = S + f * T;
+      sd[f] = f == 3 ? nullptr : S + f * T;
+      if (f != 3) launch_pack<double>(g, sp[f], S + f * T, f == 4 ? ph.T_ref : 0.0, stream);
     }
-    launch_explicit_adjoint(g, ph, type, patches, sd, yb, S + 7 * T, S + 13 * T, S + 15 * T, xb,
-                            stream);
+    launch_explicit_adjoint(g, ph, type, patches, sd, yb, S + 7 * T, S + 13 * T, S + 15 * T,
+                            S + 21 * T, xb, stream);
     NFVM_CK(hipGetLastError());
     NFVM_CK(hipStreamSynchronize(stream));
   }
@@ -812,7 +813,7 @@ class GridT : public GridBase {
     if (!kb || !wb) throw Error{NFVM_E_INVAL, "the adjoints of k and omega are required"};
     if (!(tau >= 0.0)) throw Error{NFVM_E_INVAL, "tau must be >= 0"};
     const size_t T = (size_t)g.total;
-    if (!adj_scratch) adj_scratch = alloc<double>(21 * T, "adjoint scratch");
+    if (!adj_scratch) adj_scratch = alloc<double>(22 * T, "adjoint scratch");
     double* S = adj_scratch;
     const double* sd[5];
     for (int f = 0; f < 5; ++f) {

@@ -38,7 +38,7 @@ __device__ __forceinline__ int ghost_code(int f) {
 }
 
 struct AdjCell {
-  double v[NF], p, nu;
+  double v[NF], nu;
   uint8_t t;
 };
 
@@ -72,8 +72,11 @@ __device__ __forceinline__ void alpha_grad(double nu, double k, double w, double
   dw = live ? da * (-ret / oh) : 0.0;
 }
 
+// (the stage's Jacobian does not depend on p: it enters the momentum
+// update linearly, so the state's p is not read)
 struct AdjState {
-  const double *u, *v, *w, *p, *T, *k, *om;  // padded; T as T - T_ref
+  const double *u, *v, *w, *T, *k, *om;  // padded; T as T - T_ref
+  const double* nu;  // nu_t of the fluid cells (k-omega only), padded
 };
 
 __device__ __forceinline__ AdjCell load_adj(const AdjState& S, const uint8_t* type, int N,
@@ -86,12 +89,7 @@ __device__ __forceinline__ AdjCell load_adj(const AdjState& S, const uint8_t* ty
   c.v[3] = S.T[N];
   c.v[4] = S.k[N];
   c.v[5] = S.om[N];
-  c.p = S.p[N];
-  c.nu = 0.0;
-  if (ph.komega && is_fluid(c.t)) {
-    double dk, dw;
-    closure_grad(ph.nu, c.v[4], c.v[5], c.nu, dk, dw);
-  }
+  c.nu = ph.komega && is_fluid(c.t) ? S.nu[N] : 0.0;
   return c;
 }
 
@@ -100,7 +98,6 @@ __device__ __forceinline__ AdjCell ghost_adj(const DevPatch& pp, const AdjCell& 
                                              uint8_t t) {
   AdjCell g;
   for (int f = 0; f < NF; ++f) g.v[f] = ghost<double>(pp, ghost_code(f), P.v[f], komega);
-  g.p = ghost<double>(pp, G_P, P.p, komega);
   g.nu = ghost<double>(pp, G_NUT, P.nu, komega);
   g.t = t;
   return g;
@@ -152,6 +149,22 @@ __device__ __forceinline__ void adj_neighbours(const Geom& g, const Phys& ph, co
 }
 }  // namespace
 
+// nu_t of every fluid cell (the closure of its k and omega), read by both
+// passes at a cell and its six neighbours instead of being formed there.
+__global__ __launch_bounds__(ABX* ABY) void k_adj_nut(Geom g, Phys ph,
+                                                     const uint8_t* __restrict__ type,
+                                                     const double* __restrict__ kk,
+                                                     const double* __restrict__ om,
+                                                     double* __restrict__ nu) {
+  const int i = blockIdx.x * ABX + threadIdx.x, j = blockIdx.y * ABY + threadIdx.y,
+            k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int P = g.idx(i, j, k);
+  double nt = 0.0, dk, dw;
+  if (is_fluid(type[P])) closure_grad(ph.nu, kk[P], om[P], nt, dk, dw);
+  nu[P] = nt;
+}
+
 // Pass 1: weights of each output cell.  W: six padded arrays (u v w theta k
 // omega), pass: two (k, omega), L4S: six (S00 S11 S22 S01 S02 S12 times
 // 4 Lambda).  ybar: dense [nz][ny][nx] adjoints of the six outputs.
@@ -168,67 +181,77 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_weights(
   const size_t D = ((size_t)k * g.ny + j) * g.nx + i;
   const size_t T = (size_t)g.total;
   const uint8_t tp = type[P];
-  for (int f = 0; f < NF; ++f) {
-    W[f * T + P] = 0.0;
-    L4S[f * T + P] = 0.0;
-  }
-  pass[P] = pass[T + P] = 1.0;
-  if (!is_fluid(tp)) return;
-  const double dt = ph.dt;
-  const double yb[NF] = {ybu[D], ybv[D], ybw[D], ybT[D], ybk[D], ybo[D]};
-  for (int a = 0; a < 3; ++a) W[a * T + P] = a < g.dim ? dt * yb[a] : 0.0;
-  W[3 * T + P] = ph.energy ? dt * yb[3] : 0.0;
-  if (!ph.komega) return;
-  const AdjCell c = load_adj(S, type, P, ph);
-  AdjCell N[3][2];
-  adj_neighbours(g, ph, S, type, pt, P, c, N);
-  double g0[NF], is[NF];
-  field_coef(ph, g0, is);
-  const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
-  double rk = 0.0, rw = 0.0;
-  #pragma unroll
-  for (int d = 0; d < 3; ++d)
+  // formed in registers and stored once (zero weights and pass 1 where the
+  // cell is not fluid)
+  double Wv[NF] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, Lv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double ps[2] = {1.0, 1.0};
+  [&]() {
+    if (!is_fluid(tp)) return;
+    const double dt = ph.dt;
+    const double yb[NF] = {ybu[D], ybv[D], ybw[D], ybT[D], ybk[D], ybo[D]};
     #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      if (d >= g.dim) continue;
-      const AdjCell& n = N[d][s];
-      const double sg = s ? 1.0 : -1.0;
-      const double Uf = 0.5 * (c.v[d] + n.v[d]);
-      const double nutf = 0.5 * (c.nu + n.nu);
+    for (int a = 0; a < 3; ++a) Wv[a] = a < g.dim ? dt * yb[a] : 0.0;
+    Wv[3] = ph.energy ? dt * yb[3] : 0.0;
+    if (!ph.komega) return;
+    const AdjCell c = load_adj(S, type, P, ph);
+    AdjCell N[3][2];
+    adj_neighbours(g, ph, S, type, pt, P, c, N);
+    double g0[NF], is[NF];
+    field_coef(ph, g0, is);
+    const double ih[3] = {1.0 / g.hx, 1.0 / g.hy, 1.0 / g.hz};
+    double rk = 0.0, rw = 0.0;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d)
       #pragma unroll
-      for (int f = 4; f < 6; ++f) {
-        const double lower = s ? c.v[f] : n.v[f], upper = s ? n.v[f] : c.v[f];
-        const double up = Uf >= 0.0 ? lower : upper;
-        const double F = -Uf * up + (g0[f] + nutf * is[f]) * (upper - lower) * ih[d];
-        (f == 4 ? rk : rw) += sg * F * ih[d];
+      for (int s = 0; s < 2; ++s) {
+        if (d >= g.dim) continue;
+        const AdjCell& n = N[d][s];
+        const double sg = s ? 1.0 : -1.0;
+        const double Uf = 0.5 * (c.v[d] + n.v[d]);
+        const double nutf = 0.5 * (c.nu + n.nu);
+        #pragma unroll
+        for (int f = 4; f < 6; ++f) {
+          const double lower = s ? c.v[f] : n.v[f], upper = s ? n.v[f] : c.v[f];
+          const double up = Uf >= 0.0 ? lower : upper;
+          const double F = -Uf * up + (g0[f] + nutf * is[f]) * (upper - lower) * ih[d];
+          (f == 4 ? rk : rw) += sg * F * ih[d];
+        }
       }
-    }
-  double G[3][3];
-  adj_gradient(g, c, N, G);
-  double Sab[6];
-  Sab[0] = G[0][0];
-  Sab[1] = G[1][1];
-  Sab[2] = G[2][2];
-  Sab[3] = 0.5 * (G[0][1] + G[1][0]);
-  Sab[4] = 0.5 * (G[0][2] + G[2][0]);
-  Sab[5] = 0.5 * (G[1][2] + G[2][1]);
-  const double S2 = 2.0 * (Sab[0] * Sab[0] + Sab[1] * Sab[1] + Sab[2] * Sab[2] +
-                           2.0 * (Sab[3] * Sab[3] + Sab[4] * Sab[4] + Sab[5] * Sab[5]));
-  double al, dak, daw;
-  alpha_grad(ph.nu, c.v[4], c.v[5], al, dak, daw);
-  const double kn = c.v[4] + dt * (rk + c.nu * S2);
-  const double wn = c.v[5] + dt * (rw + al * S2);
-  const bool pk = kn > C_EPS;
-  const bool fixed = (tp & FIXED_BIT) != 0;
-  const bool pw = fixed || wn > C_EPS;
-  const double Wk = pk ? dt * yb[4] : 0.0;
-  const double Ww = (!fixed && pw) ? dt * yb[5] : 0.0;
-  W[4 * T + P] = Wk;
-  W[5 * T + P] = Ww;
-  pass[P] = pk ? 1.0 : 0.0;
-  pass[T + P] = pw ? 1.0 : 0.0;
-  const double lam4 = 4.0 * (Wk * c.nu + Ww * al);
-  for (int q = 0; q < 6; ++q) L4S[q * T + P] = lam4 * Sab[q];
+    double G[3][3];
+    adj_gradient(g, c, N, G);
+    double Sab[6];
+    Sab[0] = G[0][0];
+    Sab[1] = G[1][1];
+    Sab[2] = G[2][2];
+    Sab[3] = 0.5 * (G[0][1] + G[1][0]);
+    Sab[4] = 0.5 * (G[0][2] + G[2][0]);
+    Sab[5] = 0.5 * (G[1][2] + G[2][1]);
+    const double S2 = 2.0 * (Sab[0] * Sab[0] + Sab[1] * Sab[1] + Sab[2] * Sab[2] +
+                             2.0 * (Sab[3] * Sab[3] + Sab[4] * Sab[4] + Sab[5] * Sab[5]));
+    double al, dak, daw;
+    alpha_grad(ph.nu, c.v[4], c.v[5], al, dak, daw);
+    const double kn = c.v[4] + dt * (rk + c.nu * S2);
+    const double wn = c.v[5] + dt * (rw + al * S2);
+    const bool pk = kn > C_EPS;
+    const bool fixed = (tp & FIXED_BIT) != 0;
+    const bool pw = fixed || wn > C_EPS;
+    const double Wk = pk ? dt * yb[4] : 0.0;
+    const double Ww = (!fixed && pw) ? dt * yb[5] : 0.0;
+    Wv[4] = Wk;
+    Wv[5] = Ww;
+    ps[0] = pk ? 1.0 : 0.0;
+    ps[1] = pw ? 1.0 : 0.0;
+    const double lam4 = 4.0 * (Wk * c.nu + Ww * al);
+    #pragma unroll
+    for (int q = 0; q < 6; ++q) Lv[q] = lam4 * Sab[q];
+  }();
+  #pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    W[f * T + P] = Wv[f];
+    L4S[f * T + P] = Lv[f];
+  }
+  pass[P] = ps[0];
+  pass[T + P] = ps[1];
 }
 
 // Pass 2: the adjoints of the inputs, dense [nz][ny][nx]: xb = {u v w p T k omega}.
@@ -382,9 +405,10 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
 void launch_explicit_adjoint(const Geom& g, const Phys& ph, const uint8_t* type,
                              const DevPatch* pt, const double* const st[7],
                              const double* const yb[6], double* W, double* pass, double* L4S,
-                             double* const xb[7], hipStream_t s) {
-  const AdjState S{st[0], st[1], st[2], st[3], st[4], st[5], st[6]};
+                             double* nu, double* const xb[7], hipStream_t s) {
+  const AdjState S{st[0], st[1], st[2], st[4], st[5], st[6], nu};
   const dim3 G((g.nx + ABX - 1) / ABX, (g.ny + ABY - 1) / ABY, g.nz), B(ABX, ABY);
+  if (ph.komega) hipLaunchKernelGGL(k_adj_nut, G, B, 0, s, g, ph, type, st[5], st[6], nu);
   hipLaunchKernelGGL(k_adj_ex_weights, G, B, 0, s, g, ph, type, pt, S, yb[0], yb[1], yb[2],
                      yb[3], yb[4], yb[5], W, pass, L4S);
   hipLaunchKernelGGL(k_adj_ex_gather, G, B, 0, s, g, ph, type, pt, S, yb[0], yb[1], yb[2],
@@ -542,24 +566,33 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_des_weights(
   const size_t D = ((size_t)k * g.ny + j) * g.nx + i;
   const size_t T = (size_t)g.total;
   const uint8_t tp = type[P];
-  for (int q = 0; q < 6; ++q) E[q * T + P] = 0.0;
-  for (int q = 0; q < 9; ++q) M[q * T + P] = 0.0;
-  if (!is_fluid(tp)) return;
-  double gk[3], gw[3], G[3][3];
-  des_gradients(g, ph, S, type, pt, P, gk, gw, G);
-  const DesLocal r = des_local(ph, tau, S.k[P], S.om[P], gk, gw, G, (tp & FIXED_BIT) != 0);
-  const double lk = kb[D] * r.lam_k;
-  for (int d = 0; d < 3; ++d) {
-    E[d * T + P] = lk * gw[d];
-    E[(3 + d) * T + P] = lk * gk[d];
+  // formed in registers and stored once (zero where the cell is not fluid)
+  double Ev[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double Mv[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (is_fluid(tp)) {
+    double gk[3], gw[3], G[3][3];
+    des_gradients(g, ph, S, type, pt, P, gk, gw, G);
+    const DesLocal r = des_local(ph, tau, S.k[P], S.om[P], gk, gw, G, (tp & FIXED_BIT) != 0);
+    const double lk = kb[D] * r.lam_k;
+    #pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Ev[d] = lk * gw[d];
+      Ev[3 + d] = lk * gk[d];
+    }
+    if (r.lam_w != 0.0) {
+      double dX[3][3];
+      stretch_grad(G, dX);
+      const double lw = wb[D] * r.lam_w;
+      #pragma unroll
+      for (int p = 0; p < 3; ++p)
+        #pragma unroll
+        for (int q = 0; q < 3; ++q) Mv[3 * p + q] = lw * dX[p][q];
+    }
   }
-  if (r.lam_w != 0.0) {
-    double dX[3][3];
-    stretch_grad(G, dX);
-    const double lw = wb[D] * r.lam_w;
-    for (int p = 0; p < 3; ++p)
-      for (int q = 0; q < 3; ++q) M[(3 * p + q) * T + P] = lw * dX[p][q];
-  }
+  #pragma unroll
+  for (int q = 0; q < 6; ++q) E[q * T + P] = Ev[q];
+  #pragma unroll
+  for (int q = 0; q < 9; ++q) M[q * T + P] = Mv[q];
 }
 
 // Pass 2: the adjoints of the inputs u, v, w, k, omega (dense).

@@ -163,14 +163,15 @@ void launch_face_codes(const Geom& g, const uint8_t* cls, const float* cx, const
                        const float* cz, uint16_t* code, hipStream_t s);
 
 // Reverse mode of the explicit stage (forward Euler) at the state st (seven
-// padded FP64 arrays u v w p theta k omega, theta = T - T_ref): from the
+// padded FP64 arrays u v w p theta k omega, theta = T - T_ref; p is not
+// read and may be null): from the
 // dense adjoints yb of the outputs u v w T k omega, the dense adjoints xb of
 // the inputs u v w p T k omega, nu_t being the closure of k and omega.
-// W (6 padded arrays), pass (2) and L4S (6) are scratch.
+// W (6 padded arrays), pass (2), L4S (6) and nu (1, nu_t) are scratch.
 void launch_explicit_adjoint(const Geom& g, const Phys& ph, const uint8_t* type,
                              const DevPatch* pt, const double* const st[7],
                              const double* const yb[6], double* W, double* pass, double* L4S,
-                             double* const xb[7], hipStream_t s);
+                             double* nu, double* const xb[7], hipStream_t s);
 
 // Reverse mode of the destruction step over tau at the state st (five
 // padded FP64 arrays u v w k omega): from the dense adjoints kb, wb of its k
