@@ -37,6 +37,32 @@ __device__ __forceinline__ int ghost_code(int f) {
   return f < 3 ? G_U + f : (f == 3 ? G_T : (f == 4 ? G_K : G_OM));
 }
 
+// The cell of this thread.  The launch is one-dimensional, 8 * per
+// workgroups of ABX x ABY threads over the list of (column tile, plane)
+// entries, planes fastest; workgroup b runs on XCD b % 8 and takes entry
+// (b % 8) * per + b / 8, so the workgroups in flight on one XCD hold
+// consecutive planes of the same column tiles and the planes above and below
+// that each cell reads are in that XCD's L2.
+__device__ __forceinline__ bool adj_cell(const Geom& g, int& i, int& j, int& k) {
+  const int ntx = (g.nx + ABX - 1) / ABX, nty = (g.ny + ABY - 1) / ABY;
+  const long long total = (long long)ntx * nty * g.nz;
+  const long long per = gridDim.x >> 3;
+  const long long t = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (t >= total) return false;
+  k = (int)(t % g.nz);
+  const long long c = t / g.nz;
+  i = (int)(c % ntx) * ABX + threadIdx.x;
+  j = (int)(c / ntx) * ABY + threadIdx.y;
+  return i < g.nx && j < g.ny;
+}
+
+// workgroups of the launches that use adj_cell (a multiple of 8)
+inline dim3 adj_grid(const Geom& g) {
+  const long long total =
+      (long long)((g.nx + ABX - 1) / ABX) * ((g.ny + ABY - 1) / ABY) * g.nz;
+  return dim3((unsigned)(8 * ((total + 7) / 8)));
+}
+
 struct AdjCell {
   double v[NF], nu;
   uint8_t t;
@@ -156,9 +182,8 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_nut(Geom g, Phys ph,
                                                      const double* __restrict__ kk,
                                                      const double* __restrict__ om,
                                                      double* __restrict__ nu) {
-  const int i = blockIdx.x * ABX + threadIdx.x, j = blockIdx.y * ABY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  int i, j, k;
+  if (!adj_cell(g, i, j, k)) return;
   const int P = g.idx(i, j, k);
   double nt = 0.0, dk, dw;
   if (is_fluid(type[P])) closure_grad(ph.nu, kk[P], om[P], nt, dk, dw);
@@ -174,9 +199,8 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_weights(
     const double* __restrict__ ybw, const double* __restrict__ ybT,
     const double* __restrict__ ybk, const double* __restrict__ ybo, double* __restrict__ W,
     double* __restrict__ pass, double* __restrict__ L4S) {
-  const int i = blockIdx.x * ABX + threadIdx.x, j = blockIdx.y * ABY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  int i, j, k;
+  if (!adj_cell(g, i, j, k)) return;
   const int P = g.idx(i, j, k);
   const size_t D = ((size_t)k * g.ny + j) * g.nx + i;
   const size_t T = (size_t)g.total;
@@ -264,9 +288,8 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
     const double* __restrict__ L4S, double* __restrict__ xu, double* __restrict__ xv,
     double* __restrict__ xw, double* __restrict__ xp, double* __restrict__ xT,
     double* __restrict__ xk, double* __restrict__ xo) {
-  const int i = blockIdx.x * ABX + threadIdx.x, j = blockIdx.y * ABY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  int i, j, k;
+  if (!adj_cell(g, i, j, k)) return;
   const int P = g.idx(i, j, k);
   const size_t D = ((size_t)k * g.ny + j) * g.nx + i;
   const size_t T = (size_t)g.total;
@@ -407,7 +430,7 @@ void launch_explicit_adjoint(const Geom& g, const Phys& ph, const uint8_t* type,
                              const double* const yb[6], double* W, double* pass, double* L4S,
                              double* nu, double* const xb[7], hipStream_t s) {
   const AdjState S{st[0], st[1], st[2], st[4], st[5], st[6], nu};
-  const dim3 G((g.nx + ABX - 1) / ABX, (g.ny + ABY - 1) / ABY, g.nz), B(ABX, ABY);
+  const dim3 G = adj_grid(g), B(ABX, ABY);
   if (ph.komega) hipLaunchKernelGGL(k_adj_nut, G, B, 0, s, g, ph, type, st[5], st[6], nu);
   hipLaunchKernelGGL(k_adj_ex_weights, G, B, 0, s, g, ph, type, pt, S, yb[0], yb[1], yb[2],
                      yb[3], yb[4], yb[5], W, pass, L4S);
@@ -559,9 +582,8 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_des_weights(
     Geom g, Phys ph, const uint8_t* __restrict__ type, const DevPatch* __restrict__ pt,
     DesState S, double tau, const double* __restrict__ kb, const double* __restrict__ wb,
     double* __restrict__ E, double* __restrict__ M) {
-  const int i = blockIdx.x * ABX + threadIdx.x, j = blockIdx.y * ABY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  int i, j, k;
+  if (!adj_cell(g, i, j, k)) return;
   const int P = g.idx(i, j, k);
   const size_t D = ((size_t)k * g.ny + j) * g.nx + i;
   const size_t T = (size_t)g.total;
@@ -602,9 +624,8 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_des_gather(
     const double* __restrict__ E, const double* __restrict__ M, double* __restrict__ xu,
     double* __restrict__ xv, double* __restrict__ xw, double* __restrict__ xk,
     double* __restrict__ xo) {
-  const int i = blockIdx.x * ABX + threadIdx.x, j = blockIdx.y * ABY + threadIdx.y,
-            k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
+  int i, j, k;
+  if (!adj_cell(g, i, j, k)) return;
   const int P = g.idx(i, j, k);
   const size_t D = ((size_t)k * g.ny + j) * g.nx + i;
   const size_t T = (size_t)g.total;
@@ -652,7 +673,7 @@ void launch_destroy_adjoint(const Geom& g, const Phys& ph, const uint8_t* type,
                             const double* kb, const double* wb, double* E, double* M,
                             double* const xb[5], hipStream_t s) {
   const DesState S{st[0], st[1], st[2], st[3], st[4]};
-  const dim3 G((g.nx + ABX - 1) / ABX, (g.ny + ABY - 1) / ABY, g.nz), B(ABX, ABY);
+  const dim3 G = adj_grid(g), B(ABX, ABY);
   hipLaunchKernelGGL(k_adj_des_weights, G, B, 0, s, g, ph, type, pt, S, tau, kb, wb, E, M);
   hipLaunchKernelGGL(k_adj_des_gather, G, B, 0, s, g, ph, type, pt, S, tau, kb, wb, E, M, xb[0],
                      xb[1], xb[2], xb[3], xb[4]);
