@@ -189,6 +189,21 @@ class Stage:
         return (torch.where(self.fluid, kn, k), torch.where(self.fluid, wn, om))
 
 
+def _stage_map(st: Stage, x: Dict[str, torch.Tensor]) -> Dict[str, torch.Tensor]:
+    """The explicit stage of the case: one forward-Euler step E, or with
+    rk_order = 2 Heun's method as the average of the start and a second
+    Euler step from the first, (x + E(E(x))) / 2 (Sec. 2.6 names explicit
+    Runge-Kutta schemes without fixing one); the second step takes nu_t from
+    the first stage's k and omega and the same p."""
+    y1 = st.forward(x)
+    if getattr(st.case, "rk_order", 1) != 2:
+        return y1
+    x1 = dict(y1)
+    x1["p"] = x["p"]
+    y2 = st.forward(x1)
+    return {nm: 0.5 * (x[nm] + y2[nm]) for nm in ("u", "v", "w", "T", "k", "omega")}
+
+
 def _tensors(fields, grad: bool):
     return {nm: torch.tensor(np.ascontiguousarray(fields[nm], dtype=np.float64).reshape(-1),
                              requires_grad=grad) for nm in NAMES if nm in fields}
@@ -199,7 +214,7 @@ def explicit_forward(case, fields) -> Dict[str, np.ndarray]:
     fields, by the torch restatement."""
     st = Stage(case)
     with torch.no_grad():
-        out = st.forward(_tensors(fields, False))
+        out = _stage_map(st, _tensors(fields, False))
     shape = tuple(case.n[::-1])
     return {nm: out[nm].numpy().reshape(shape) for nm in out}
 
@@ -208,10 +223,11 @@ def explicit_vjp(case, fields, bars) -> Dict[str, np.ndarray]:
     """Reverse mode of the explicit stage at the state `fields` (dense u, v,
     w, p, T, k, omega): the adjoints of the seven inputs from the adjoints
     `bars` of the six outputs (u, v, w, T, k, omega), nu_t taken as the
-    closure of the input k and omega (so its adjoint is folded into theirs)."""
+    closure of each Euler step's input k and omega (so its adjoint is folded
+    into theirs); Heun's stage when the case's rk_order is 2."""
     st = Stage(case)
     x = _tensors(fields, True)
-    out = st.forward(x)
+    out = _stage_map(st, x)
     ys, gs = [], []
     for nm in ("u", "v", "w", "T", "k", "omega"):
         ys.append(out[nm])

@@ -165,3 +165,70 @@ def test_step_vjp_matches_finite_differences(name, case):
         lhs = sum((bars[nm] * (fp[nm] - fm[nm])).sum() for nm in O.FIELDS) / (2 * e)
         rhs = sum((xbar[nm] * v[nm]).sum() for nm in O.FIELDS)
         assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs), 1e-12), (name, trial, lhs, rhs)
+
+
+def _heun(case):
+    return case.copy(rk_order=2)
+
+
+@pytest.mark.parametrize("name,case", _cases(), ids=[c[0] for c in _cases()])
+def test_heun_autodiff_forward_reproduces_the_oracle(name, case):
+    """Heun's stage, (x + E(E(x))) / 2 with the second Euler step's nu_t from
+    the first stage's k and omega, restated in torch reproduces the C
+    oracle's rk_order = 2 stage, which differs from one Euler step."""
+    from oracle import autodiff as AD
+    c = _heun(case)
+    f = _state(c, 1)
+    ref = O.explicit(c, f)
+    got = AD.explicit_forward(c, f)
+    euler = O.explicit(case, f)
+    moved = 0.0
+    for nm in ("u", "v", "w", "T", "k", "omega"):
+        scale = max(np.abs(ref[nm]).max(), 1e-30)
+        assert np.abs(got[nm] - ref[nm]).max() <= 1e-13 * scale, nm
+        moved = max(moved, np.abs(ref[nm] - euler[nm]).max() / scale)
+    assert moved > 1e-8
+
+
+@pytest.mark.parametrize("name,case", _cases()[1:3], ids=[c[0] for c in _cases()[1:3]])
+def test_heun_vjp_matches_finite_differences(name, case):
+    """The reverse mode of Heun's stage against central differences of the
+    C oracle's rk_order = 2 stage along random directions."""
+    from oracle import autodiff as AD
+    c = _heun(case)
+    rng = np.random.default_rng(21)
+    f = _state(c, 2)
+    outs = ("u", "v", "w", "T", "k", "omega")
+    ybar = {nm: rng.standard_normal(f["u"].shape) for nm in outs}
+    xbar = AD.explicit_vjp(c, f, ybar)
+    for trial in range(2):
+        v = {nm: rng.standard_normal(f["u"].shape) * max(np.abs(f[nm]).max(), 1e-3)
+             for nm in O.FIELDS}
+        e = 1e-6
+        Ep = O.explicit(c, {nm: f[nm] + e * v[nm] for nm in O.FIELDS})
+        Em = O.explicit(c, {nm: f[nm] - e * v[nm] for nm in O.FIELDS})
+        lhs = sum((ybar[nm] * (Ep[nm] - Em[nm])).sum() for nm in outs) / (2 * e)
+        rhs = sum((xbar[nm] * v[nm]).sum() for nm in O.FIELDS)
+        assert abs(lhs - rhs) <= 1e-6 * max(abs(lhs), abs(rhs), 1e-12), (name, trial, lhs, rhs)
+
+
+@pytest.mark.parametrize("name,case", _step_cases()[1:3], ids=[c[0] for c in _step_cases()[1:3]])
+def test_heun_step_vjp_matches_finite_differences(name, case):
+    """The whole step's reverse mode with Heun's explicit stage against
+    central differences of the C oracle's rk_order = 2 time step (pressure
+    solve converged to 1e-13)."""
+    from oracle import autodiff as AD
+    c = _heun(case).copy(tol=1e-13, max_cycles=200)
+    rng = np.random.default_rng(22)
+    f = _state(c, 7)
+    bars = {nm: rng.standard_normal(f["u"].shape) for nm in O.FIELDS}
+    xbar = AD.step_vjp(c, f, bars)
+    v = {nm: rng.standard_normal(f["u"].shape) * max(np.abs(f[nm]).max(), 1e-3)
+         for nm in O.FIELDS}
+    e = 1e-7
+    fp, _, sp = O.step(c, 1, fields={nm: f[nm] + e * v[nm] for nm in O.FIELDS})
+    fm, _, sm = O.step(c, 1, fields={nm: f[nm] - e * v[nm] for nm in O.FIELDS})
+    assert sp == 0 and sm == 0
+    lhs = sum((bars[nm] * (fp[nm] - fm[nm])).sum() for nm in O.FIELDS) / (2 * e)
+    rhs = sum((xbar[nm] * v[nm]).sum() for nm in O.FIELDS)
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs), 1e-12), (name, lhs, rhs)
