@@ -289,23 +289,26 @@ nfvm_status nfvm_destroy_adjoint_device(nfvm_grid_t grid, const nfvm_fields* sta
                                         const double* kbar, const double* wbar,
                                         nfvm_fields* out);
 
-/* Reverse mode of one whole time step (nfvm_step with the forward-Euler
- * explicit stage; the solver is differentiable, Sec. 1 and 4): the step
- * loads the state as nfvm_set_fields does (omega held on wall-adjacent
- * cells), then destruction over dt/2, the explicit stage, the pressure step
- * and destruction over dt/2 (Sec. 2.3 to 2.5).  For the adjoints `bar` of
- * the seven fields after the step it writes those of the seven fields of
+/* Reverse mode of one whole time step (nfvm_step; the solver is
+ * differentiable, Sec. 1 and 4): the step loads the state as
+ * nfvm_set_fields does (omega held on wall-adjacent cells), then
+ * destruction over dt/2, the explicit stage, the pressure step and
+ * destruction over dt/2 (Sec. 2.3 to 2.5).  For the adjoints `bar` of the
+ * seven fields after the step it writes those of the seven fields of
  * `state` into `out`: the step is run forward from `state` on the grid's
  * fields (which hold its result on return), keeping the stage inputs, and
  * the stages' reverse modes (nfvm_destroy_adjoint_device,
  * nfvm_pressure_adjoint_device, nfvm_explicit_adjoint_device) are applied
  * in reverse order; both pressure solves run to tol (or forced_cycles) and
- * the solve is differentiated as the exact A^-1.  All arrays device FP64
- * [nz][ny][nx], T absolute; outputs may not alias inputs.  stats: NULL or
- * two entries, the forward and the adjoint solve.  The first call allocates
- * 35 dense FP64 arrays of scratch (plus the stage reverse modes' scratch),
- * kept until the grid is freed.  Runs on the grid's stream and waits for it.
- * Errors: NFVM_E_INVAL for a null pointer or NFVM_OPT_RK_ORDER 2; solve
+ * the solve is differentiated as the exact A^-1.  With NFVM_OPT_RK_ORDER 2
+ * the explicit stage is Heun's (U + E(E(U))) / 2 and its reverse mode
+ * (b + J1^T J2^T b) / 2, the forward-Euler reverse mode taken at the first
+ * stage's output, then at U.  All arrays device FP64 [nz][ny][nx], T
+ * absolute; outputs may not alias inputs.  stats: NULL or two entries, the
+ * forward and the adjoint solve.  The first call allocates 35 dense FP64
+ * arrays of scratch (20 more with the Heun stage, plus the stage reverse
+ * modes' scratch), kept until the grid is freed.  Runs on the grid's stream
+ * and waits for it.  Errors: NFVM_E_INVAL for a null pointer; solve
  * statuses as nfvm_mg_solve_device (a diverged forward solve leaves `out`
  * unwritten). */
 nfvm_status nfvm_step_adjoint_device(nfvm_grid_t grid, const nfvm_fields* state,

@@ -299,6 +299,7 @@ class GridT : public GridBase {
   double* stage = nullptr;
   double* adj_scratch = nullptr;  // reverse modes of the explicit and destruction steps
   double* adj_dense = nullptr;    // reverse mode of the whole step
+  double* adj_heun = nullptr;     // ... and of its Heun explicit stage
   RedBuf red{};
   int* cmap = nullptr;
   int* ncount = nullptr;
@@ -833,8 +834,6 @@ class GridT : public GridBase {
   void step_adjoint(const nfvm_fields& st, const nfvm_fields& bar, const nfvm_fields& out,
                     double tol_, int maxc, int forced, nfvm_step_stats* stt,
                     nfvm_status* status) override {
-    if (rk_order != 1)
-      throw Error{NFVM_E_INVAL, "the reverse mode covers the forward-Euler explicit stage"};
     const double* sp[7] = {st.u, st.v, st.w, st.p, st.T, st.k, st.omega};
     const double* bp[7] = {bar.u, bar.v, bar.w, bar.p, bar.T, bar.k, bar.omega};
     double* op[7] = {out.u, out.v, out.w, out.p, out.T, out.k, out.omega};
@@ -849,6 +848,10 @@ class GridT : public GridBase {
     if (!adj_dense) adj_dense = alloc<double>(35 * N, "step adjoint scratch");
     double* D = adj_dense;
     auto slot = [&](int q) { return D + (size_t)q * N; };
+    // Heun's stage (U + E(E(U))) / 2: the first stage's u v w T k omega (6),
+    // the second stage's input adjoints (7), the first stage's (7)
+    if (rk_order == 2 && !adj_heun) adj_heun = alloc<double>(20 * N, "Heun step adjoint scratch");
+    auto hslot = [&](int q) { return adj_heun + (size_t)q * N; };
     NFVM_CK(hipStreamSynchronize(stream));
     // the state as the grid's fields, omega held on wall-adjacent cells (as
     // nfvm_set_fields loads fields)
@@ -878,6 +881,20 @@ class GridT : public GridBase {
       FieldSet<V, F> in{vcur(0), vcur(1), vcur(2), scur(3), scur(4), scur(5)};
       FieldSet<V, F> outf{valt(0), valt(1), valt(2), salt(3), salt(4), salt(5)};
       launch_explicit<V, F, P>(g, ph, type, patches, in, p, nut, outf, tp[TP_EXPLICIT], stream);
+      if (rk_order == 2) {
+        // the first stage kept, then the second Euler step from it (nu_t of
+        // its k and omega) averaged with the start, as the step takes it
+        launch_unpack<V>(g, outf.u, hslot(0), 0.0, stream);
+        launch_unpack<V>(g, outf.v, hslot(1), 0.0, stream);
+        launch_unpack<V>(g, outf.w, hslot(2), 0.0, stream);
+        launch_unpack<F>(g, outf.T, hslot(3), ph.T_ref, stream);
+        launch_unpack<F>(g, outf.k, hslot(4), 0.0, stream);
+        launch_unpack<F>(g, outf.om, hslot(5), 0.0, stream);
+        if (ph.komega) launch_nut<V, F>(g, ph, type, outf.k, outf.om, nut, stream);
+        launch_explicit<V, F, P>(g, ph, type, patches, outf, p, nut, rk2, tp[TP_EXPLICIT],
+                                 stream);
+        launch_rk2_average<V, F>(g, in, rk2, outf, stream);
+      }
       for (int f = 0; f < 6; ++f) swap(f);
     }
     for (int f = 0; f < 3; ++f) launch_unpack<V>(g, vcur(f), slot(9 + f), 0.0, stream);
@@ -950,7 +967,26 @@ class GridT : public GridBase {
       const nfvm_fields b1{usb[0], usb[1], usb[2], nullptr, const_cast<double*>(bp[4]),
                            const_cast<double*>(ksb), const_cast<double*>(wsb)};
       const nfvm_fields o1{xo[0], xo[1], xo[2], xo[3], xo[4], xo[5], xo[6]};
-      explicit_adjoint(s1, b1, o1);
+      if (rk_order == 2) {
+        // the adjoint of (U + E(E(U))) / 2 is (b + J1^T J2^T b) / 2, J2 the
+        // Jacobian of the second stage at the first stage's output U1, J1 that
+        // of the first at U (p passes to both stages)
+        const nfvm_fields s2{hslot(0), hslot(1), hslot(2), slot(3), hslot(3), hslot(4), hslot(5)};
+        const nfvm_fields z{hslot(6), hslot(7), hslot(8), hslot(9), hslot(10), hslot(11),
+                            hslot(12)};
+        explicit_adjoint(s2, b1, z);
+        const nfvm_fields zb{z.u, z.v, z.w, nullptr, z.T, z.k, z.omega};
+        const nfvm_fields y{hslot(13), hslot(14), hslot(15), hslot(16), hslot(17), hslot(18),
+                            hslot(19)};
+        explicit_adjoint(s1, zb, y);
+        const double* b6[6] = {usb[0], usb[1], usb[2], bp[4], ksb, wsb};
+        const double* y6[6] = {y.u, y.v, y.w, y.T, y.k, y.omega};
+        double* x6[6] = {xo[0], xo[1], xo[2], xo[4], xo[5], xo[6]};
+        for (int f = 0; f < 6; ++f) launch_dense_add(N, b6[f], y6[f], x6[f], stream, 0.5);
+        launch_dense_add(N, z.p, y.p, xo[3], stream, 0.5);
+      } else {
+        explicit_adjoint(s1, b1, o1);
+      }
     }
     launch_dense_add(N, bp[3], xo[3], op[3], stream);  // p^n also passes to p
     NFVM_CK(hipMemcpyAsync(op[4], xo[4], N * sizeof(double), hipMemcpyDeviceToDevice, stream));

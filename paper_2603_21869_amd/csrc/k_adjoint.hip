@@ -681,15 +681,16 @@ void launch_destroy_adjoint(const Geom& g, const Phys& ph, const uint8_t* type,
 
 // ---- helpers of the whole step's reverse mode ------------------------------------
 __global__ void k_dense_add(size_t n, const double* __restrict__ a, const double* __restrict__ b,
-                            double* __restrict__ out) {
+                            double* __restrict__ out, double scale) {
   const size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) out[q] = a[q] + b[q];
+  if (q < n) out[q] = scale * (a[q] + b[q]);
 }
-// out = a + b over n dense values
-void launch_dense_add(size_t n, const double* a, const double* b, double* out, hipStream_t s) {
+// out = scale (a + b) over n dense values (scale 1 leaves the sum as formed)
+void launch_dense_add(size_t n, const double* a, const double* b, double* out, hipStream_t s,
+                      double scale) {
   if (n == 0) return;
   hipLaunchKernelGGL(k_dense_add, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, a, b,
-                     out);
+                     out, scale);
 }
 
 __global__ void k_zero_held(Geom g, const uint8_t* __restrict__ type, double* __restrict__ a) {

@@ -182,9 +182,10 @@ void launch_destroy_adjoint(const Geom& g, const Phys& ph, const uint8_t* type,
                             const double* kb, const double* wb, double* E, double* M,
                             double* const xb[5], hipStream_t s);
 
-// out = a + b over n dense FP64 values; zeroing of a dense array on the
-// cells whose omega is held (wall-adjacent fluid cells).
-void launch_dense_add(size_t n, const double* a, const double* b, double* out, hipStream_t s);
+// out = scale (a + b) over n dense FP64 values; zeroing of a dense array on
+// the cells whose omega is held (wall-adjacent fluid cells).
+void launch_dense_add(size_t n, const double* a, const double* b, double* out, hipStream_t s,
+                      double scale = 1.0);
 void launch_zero_held(const Geom& g, const uint8_t* type, double* a, hipStream_t s);
 
 // Device-wide reduction scratch: per-block partials and the reduced scalars.
