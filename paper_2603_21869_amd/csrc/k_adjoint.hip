@@ -173,6 +173,46 @@ __device__ __forceinline__ void adj_neighbours(const Geom& g, const Phys& ph, co
       N[d][s] = is_fluid(tq) ? load_adj(S, type, Q, ph) : ghost_adj(pt[tq & 0x7f], c, ph.komega, tq);
     }
 }
+
+// neighbour s (0: -, 1: +) of fluid cell P along d < dim, ghost substituted
+// (one element of adj_neighbours, loaded where it is used)
+__device__ __forceinline__ AdjCell adj_neighbour(const Geom& g, const Phys& ph, const AdjState& S,
+                                                 const uint8_t* type, const DevPatch* pt, int P,
+                                                 const AdjCell& c, int d, int s) {
+  const int Q = P + (s ? 1 : -1) * (d == 0 ? 1 : (d == 1 ? g.sx : g.sxy));
+  const uint8_t tq = type[Q];
+  return is_fluid(tq) ? load_adj(S, type, Q, ph) : ghost_adj(pt[tq & 0x7f], c, ph.komega, tq);
+}
+
+// the central velocity gradient of adj_gradient, from the neighbours'
+// velocities alone
+__device__ __forceinline__ void adj_gradient_at(const Geom& g, const Phys& ph, const AdjState& S,
+                                                const uint8_t* type, const DevPatch* pt, int P,
+                                                const AdjCell& c, double (&G)[3][3]) {
+  const double ih2[3] = {0.5 / g.hx, 0.5 / g.hy, 0.5 / g.hz};
+  const double* vel[3] = {S.u, S.v, S.w};
+  #pragma unroll
+  for (int a = 0; a < 3; ++a)
+    #pragma unroll
+    for (int b = 0; b < 3; ++b) G[a][b] = 0.0;
+  #pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    if (b >= g.dim) continue;
+    double vn[2][3];
+    #pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int Q = P + (s ? 1 : -1) * (b == 0 ? 1 : (b == 1 ? g.sx : g.sxy));
+      const uint8_t tq = type[Q];
+      #pragma unroll
+      for (int a = 0; a < 3; ++a)
+        vn[s][a] = is_fluid(tq) ? vel[a][Q]
+                                : ghost<double>(pt[tq & 0x7f], G_U + a, c.v[a], ph.komega);
+    }
+    #pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (a < g.dim) G[a][b] = (vn[1][a] - vn[0][a]) * ih2[b];
+  }
+}
 }  // namespace
 
 // nu_t of every fluid cell (the closure of its k and omega), read by both
@@ -299,8 +339,6 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
   double pb = 0.0, nb = 0.0;  // adjoints of p and of nu_t at this cell
   if (is_fluid(tp)) {
     const AdjCell c = load_adj(S, type, P, ph);
-    AdjCell N[3][2];
-    adj_neighbours(g, ph, S, type, pt, P, c, N);
     double g0[NF], is[NF];
     field_coef(ph, g0, is);
     const int st[3] = {1, g.sx, g.sxy};
@@ -315,7 +353,7 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
       #pragma unroll
       for (int s = 0; s < 2; ++s) {
         if (d >= g.dim) continue;
-        const AdjCell& n = N[d][s];
+        const AdjCell n = adj_neighbour(g, ph, S, type, pt, P, c, d, s);
         const double sg = s ? 1.0 : -1.0;
         const bool nf = is_fluid(n.t);
         const int Q = P + (s ? 1 : -1) * st[d];
@@ -369,7 +407,7 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
     if (komega) {
       // production nu_t S^2 and alpha S^2 at this cell
       double G[3][3];
-      adj_gradient(g, c, N, G);
+      adj_gradient_at(g, ph, S, type, pt, P, c, G);
       double S2 = 0.0;
       #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -394,15 +432,15 @@ __global__ __launch_bounds__(ABX* ABY) void k_adj_ex_gather(
         for (int s = 0; s < 2; ++s) {
           if (b >= g.dim) continue;
           const double sg = s ? 1.0 : -1.0;
-          const AdjCell& n = N[b][s];
-          if (is_fluid(n.t)) {
-            const int Q = P + (s ? 1 : -1) * st[b];
+          const int Q = P + (s ? 1 : -1) * st[b];
+          const uint8_t tq = type[Q];
+          if (is_fluid(tq)) {
             // this cell is the neighbour of Q on Q's side -sg along b
             #pragma unroll
             for (int a = 0; a < 3; ++a)
               if (a < g.dim) xb[a] += L4S[sidx[a][b] * T + Q] * -sg * ih2[b];
           } else {
-            const DevPatch& pp = pt[n.t & 0x7f];
+            const DevPatch& pp = pt[tq & 0x7f];
             #pragma unroll
             for (int a = 0; a < 3; ++a)
               if (a < g.dim)
