@@ -688,7 +688,10 @@ def main():
     reverse = None
     if not args.no_reverse:
         print("[bench] reverse mode", file=sys.stderr, flush=True)
-        reverse = run_reverse(g, case, args.tol)
+        try:  # reported beside the forward step: a failure does not end the run
+            reverse = run_reverse(g, case, args.tol)
+        except Exception as e:  # noqa: BLE001
+            reverse = {"error": f"{type(e).__name__}: {e}"}
     g.close()
     copy_GBs = round(copy_bandwidth(), 1)
 
