@@ -99,8 +99,8 @@ static int max_blocks_of(const Geom& g) {
 }
 
 // Tile targets (blocks per launch) the autotuner times for each kernel.
-static const int TILE_CANDIDATES[] = {512, 2048, 8192, 1 << 30};
-static constexpr int N_TILE_CANDIDATES = 4;
+static const int TILE_CANDIDATES[] = {512, 2048, 8192, 32768, 1 << 30};
+static constexpr int N_TILE_CANDIDATES = 5;
 
 void reduction_blocks(const nfvm_grid_desc& d, int* needed, int* capacity) {
   validate_desc(d);
